@@ -1,0 +1,139 @@
+/* pcs.h - polymer channel-flow step on one AMD Instinct MI355X (gfx950).
+ *
+ * One semi-implicit pseudo-spectral time step of dilute-polymer plane-channel
+ * flow, as set up in the paper's Section 2: the conformation-tensor equation
+ * (1) (sPTT, Oldroyd-B for eps = 0) with polymer diffusion kappa, the momentum
+ * equation (2) with the polymer-stress divergence, incompressibility (3);
+ * no-slip walls at y = +-1, conformation wall values from (1) with kappa = 0;
+ * Fourier in x and z, Chebyshev (Gauss-Lobatto collocation) in y, fully
+ * dealiased by the 3/2 rule.  Positive-definiteness of c is deliberately not
+ * enforced; the diagnostics report where Tr c drops below 3 and below 0
+ * (Section 3, eqs. (4)-(5) use the midplane counts).  Time integration is
+ * CNAB2 (Crank-Nicolson / 2nd-order Adams-Bashforth; the first step uses
+ * the current explicit terms as history).
+ *
+ * Conventions shared by every call
+ *  - Errors are returned as pcs_status, never thrown; nothing here exits.
+ *  - Device memory: the caller allocates one device workspace of the size
+ *    reported by pcs_workspace_bytes (256-byte aligned) and keeps it alive
+ *    until pcs_destroy.  The library never allocates device memory itself.
+ *  - Streams: every device operation is enqueued on the caller's HIP stream
+ *    (hipStream_t passed as void*; NULL means the default stream).  Calls on
+ *    one handle must not overlap in time from several host threads.
+ *  - The opaque handle belongs to the library and is released by pcs_destroy;
+ *    host buffers passed in always belong to the caller.
+ */
+#ifndef PCS_H
+#define PCS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pcs_status;
+#define PCS_OK 0
+#define PCS_BLOWUP 1        /* warning: a diagnostic record flagged blow-up (sticky) */
+#define PCS_ERR_ARG (-1)    /* null pointer or out-of-range value */
+#define PCS_ERR_UNSUPPORTED (-2) /* size or option not supported (see pcs_grid) */
+#define PCS_ERR_WORKSPACE (-3)   /* workspace too small or misaligned */
+#define PCS_ERR_DEVICE (-4)      /* a HIP call failed */
+#define PCS_ERR_STATE (-5)       /* stepping a run whose blow-up flag is set */
+
+/* Grid.  dim = 2: x-y channel (nz must be 1); dim = 3: x-y-z.
+ *  nx: points of the base grid in x (even, >= 4); kx = 2 pi m / lx for
+ *      m = 0 .. nx/2 - 1 are kept (Nyquist dropped).  3 nx / 2 must factor
+ *      as 2^a 3^b.
+ *  ny: Gauss-Lobatto points in y (odd, >= 9): N = ny - 1, y_j = cos(pi j/N),
+ *      y_0 = +1, y_N = -1, y_{N/2} = 0 (the midplane).
+ *  nz: base points in z (3D: even, >= 4, 3 nz / 2 = 2^a 3^b; the Nyquist
+ *      slot nz/2 is held at zero).
+ *  lx, lz: periods (the paper uses 10; the 3D workloads here use lz = 5). */
+typedef struct {
+  int32_t dim, nx, ny, nz;
+  double lx, lz;
+} pcs_grid;
+
+/* Physical and numerical parameters (paper, Section 2 scalings):
+ *  re, wi, beta, kappa, eps as in eqs. (1)-(2); dt the time step.
+ *  forcing = 0: constant flow rate, sum_j w_j U_j = q_or_dpdx (4/3 is the
+ *               flux of the laminar profile U = 1 - y^2); the drive Pi is
+ *               solved for every step and reported as dpdx.
+ *  forcing = 1: constant drive Pi = q_or_dpdx (2/Re reproduces eq. (2)).
+ *  precision = 0: every stage in FP64.
+ *  precision = 1: mixed: transforms and pointwise products of the
+ *               fluctuation (all modes except kx = kz = 0) in FP32, the
+ *               mean-mode profiles and every boundary-value solve in FP64;
+ *               eps must be 0. */
+typedef struct {
+  double re, wi, beta, kappa, eps, dt;
+  int32_t forcing;
+  double q_or_dpdx;
+  int32_t precision;
+} pcs_params;
+
+/* One record per step, computed on the base grid (nx x ny x nz points):
+ *  min_trc, n_lt3, n_lt0 over the volume; mid_* on the midplane j = N/2;
+ *  counts use strict '<' and ignore non-finite values;
+ *  cfl = dt max(|u|/dx + |v|/dy_j + |w|/dz) with dy_j the local Lobatto
+ *  spacing (y_{j-1} - y_{j+1})/2, one-sided at the walls;
+ *  dpdx = the drive Pi of this step; energy = <|u|^2/2>, mean_trc = <Tr c>
+ *  (Fourier mean in x, z times Clenshaw-Curtis weights / 2 in y);
+ *  blowup = 1 if any value was non-finite or |Tr c| > 1e12. */
+typedef struct {
+  int64_t step;
+  double t, min_trc, mid_min_trc, cfl, dpdx, energy, mean_trc;
+  uint64_t n_lt3, n_lt0, mid_n_lt3, mid_n_lt0;
+  int32_t blowup, reserved;
+} pcs_diag;
+
+struct pcs_sim;
+
+/* Device workspace needed by pcs_init for this grid / parameter set. */
+pcs_status pcs_workspace_bytes(const pcs_grid* grid, const pcs_params* params, size_t* bytes);
+
+/* Builds the operators (host, extended precision), uploads them into the
+ * workspace, sets the initial state: the laminar Poiseuille state of eqs.
+ * (1)-(2) (U = 1 - y^2, c_xy = Wi U', c_yy = c_zz = 1, c_xx = 1 + 2 (Wi U')^2
+ * plus the kappa boundary-layer term) plus a divergence-free perturbation
+ * of amplitude amp drawn from SplitMix64(seed) (amp = 0: laminar), and the
+ * history from the explicit terms of that state.  Synchronises the stream.
+ * workspace: device pointer of at least pcs_workspace_bytes bytes.
+ * stream: hipStream_t or NULL.  *out receives the handle. */
+pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t seed, double amp, void* workspace,
+                    size_t bytes, void* stream, struct pcs_sim** out);
+
+/* Enqueues nsteps time steps (asynchronous).  Returns PCS_ERR_STATE if a
+ * blow-up was seen at the last synchronisation. */
+pcs_status pcs_step(struct pcs_sim* sim, int32_t nsteps);
+
+/* Synchronises the stream and copies the diagnostic records produced since
+ * the previous call (at most max, the oldest first; the device keeps the last
+ * 4096) into out.  Returns PCS_BLOWUP if any record since init flagged it. */
+pcs_status pcs_diagnostics(struct pcs_sim* sim, pcs_diag* out, int32_t max, int32_t* n_out);
+
+/* Number of doubles in the flat state vector of this handle. */
+pcs_status pcs_state_size(struct pcs_sim* sim, size_t* n);
+
+/* Flat FP64 state (host buffer of pcs_state_size doubles), synchronising:
+ *   [step, t, Pi, 0] then each field as [y j = 0..N][kz slot][kx] complex
+ *   (re, im interleaved);
+ *   fields 2D: u v phi cxx cxy cyy | hv Fxx Fxy Fyy
+ *          3D: u v w phi g cxx cxy cxz cyy cyz czz | hv hg Fxx Fxy Fxz Fyy Fyz Fzz
+ *   phi = lap v, g = omega_y; hv, hg, F are the previous step's explicit
+ *   terms (AB2 history); the kx = kz = 0 slot of u and w holds the mean
+ *   profiles U, W, that of hv and hg the mean-flow forcing history.  */
+pcs_status pcs_get_state(struct pcs_sim* sim, double* host, size_t n);
+/* Replaces the state (same layout) and clears the blow-up flag. */
+pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
+
+pcs_status pcs_destroy(struct pcs_sim* sim);
+const char* pcs_status_string(pcs_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PCS_H */

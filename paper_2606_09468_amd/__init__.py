@@ -1,0 +1,169 @@
+"""Python binding of libpcs: one semi-implicit pseudo-spectral step of
+dilute-polymer plane-channel flow on an AMD Instinct MI355X.
+
+Argument marshalling only: every stage of the step runs in the HIP kernels
+of libpcs.so; PyTorch provides the device workspace and the HIP stream.
+The functions mirror the C ABI in include/pcs.h (same names); ``Sim`` wraps
+them for convenience.  Importing works without a GPU; calling anything that
+needs the library raises if libpcs.so has not been built, and there is no
+fallback path.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(HERE, "libpcs.so")
+
+PCS_OK = 0
+PCS_BLOWUP = 1
+PCS_ERR_ARG = -1
+PCS_ERR_UNSUPPORTED = -2
+PCS_ERR_WORKSPACE = -3
+PCS_ERR_DEVICE = -4
+PCS_ERR_STATE = -5
+
+EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pcs_state_size",
+           "pcs_get_state", "pcs_set_state", "pcs_destroy", "pcs_status_string")
+
+
+class pcs_grid(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
+                ("lx", ctypes.c_double), ("lz", ctypes.c_double)]
+
+
+class pcs_params(ctypes.Structure):
+    _fields_ = [("re", ctypes.c_double), ("wi", ctypes.c_double), ("beta", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("eps", ctypes.c_double), ("dt", ctypes.c_double),
+                ("forcing", ctypes.c_int32), ("q_or_dpdx", ctypes.c_double), ("precision", ctypes.c_int32)]
+
+
+class pcs_diag(ctypes.Structure):
+    _fields_ = [("step", ctypes.c_int64), ("t", ctypes.c_double), ("min_trc", ctypes.c_double),
+                ("mid_min_trc", ctypes.c_double), ("cfl", ctypes.c_double), ("dpdx", ctypes.c_double),
+                ("energy", ctypes.c_double), ("mean_trc", ctypes.c_double), ("n_lt3", ctypes.c_uint64),
+                ("n_lt0", ctypes.c_uint64), ("mid_n_lt3", ctypes.c_uint64), ("mid_n_lt0", ctypes.c_uint64),
+                ("blowup", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+
+def lib():
+    """Loads libpcs.so (raises if it is missing: there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIBPATH):
+        raise RuntimeError("libpcs.so is not built (run __graft_entry__.build()); no fallback exists")
+    L = ctypes.CDLL(LIBPATH)
+    vp, sz, st = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int32
+    L.pcs_workspace_bytes.argtypes = [ctypes.POINTER(pcs_grid), ctypes.POINTER(pcs_params), ctypes.POINTER(sz)]
+    L.pcs_init.argtypes = [ctypes.POINTER(pcs_grid), ctypes.POINTER(pcs_params), ctypes.c_uint64, ctypes.c_double,
+                           vp, sz, vp, ctypes.POINTER(vp)]
+    L.pcs_step.argtypes = [vp, ctypes.c_int32]
+    L.pcs_diagnostics.argtypes = [vp, ctypes.POINTER(pcs_diag), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+    L.pcs_state_size.argtypes = [vp, ctypes.POINTER(sz)]
+    L.pcs_get_state.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
+    L.pcs_set_state.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
+    L.pcs_destroy.argtypes = [vp]
+    L.pcs_status_string.argtypes = [st]
+    L.pcs_status_string.restype = ctypes.c_char_p
+    for name in EXPORTS[:-1]:
+        getattr(L, name).restype = st
+    _lib = L
+    return L
+
+
+class PcsError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib().pcs_status_string(status).decode()
+        super().__init__("%s: %s (status %d)" % (where, msg, status))
+        self.status = status
+
+
+def _check(status, where, allow=(PCS_OK,)):
+    if status not in allow:
+        raise PcsError(status, where)
+    return status
+
+
+def make_grid(dim, nx, ny, nz=1, lx=10.0, lz=5.0):
+    return pcs_grid(dim, nx, ny, 1 if dim == 2 else nz, lx, lz)
+
+
+def make_params(re=0.01, wi=20.0, beta=0.8, kappa=5e-5, eps=0.0, dt=1e-3, forcing=0, q_or_dpdx=4.0 / 3.0,
+                precision=0):
+    return pcs_params(re, wi, beta, kappa, eps, dt, forcing, q_or_dpdx, precision)
+
+
+def pcs_workspace_bytes(grid, params):
+    n = ctypes.c_size_t(0)
+    _check(lib().pcs_workspace_bytes(ctypes.byref(grid), ctypes.byref(params), ctypes.byref(n)),
+           "pcs_workspace_bytes")
+    return n.value
+
+
+DIAG_FIELDS = [f[0] for f in pcs_diag._fields_ if f[0] != "reserved"]
+
+
+class Sim:
+    """One channel-flow run: device workspace and stream from PyTorch, all
+    work in libpcs.  Keep the object alive while the run is in use."""
+
+    def __init__(self, grid, params, seed=0, amp=1e-3, device="cuda:0"):
+        import torch
+        self.grid, self.params = grid, params
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        nbytes = pcs_workspace_bytes(grid, params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.handle = ctypes.c_void_p(0)
+        _check(lib().pcs_init(ctypes.byref(grid), ctypes.byref(params), ctypes.c_uint64(seed), float(amp),
+                              ctypes.c_void_p(ptr), nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                              ctypes.byref(self.handle)), "pcs_init")
+        n = ctypes.c_size_t(0)
+        _check(lib().pcs_state_size(self.handle, ctypes.byref(n)), "pcs_state_size")
+        self.state_size = n.value
+        self.workspace_bytes = nbytes
+
+    def step(self, n=1):
+        return _check(lib().pcs_step(self.handle, int(n)), "pcs_step")
+
+    def diagnostics(self, max_records=4096):
+        buf = (pcs_diag * max_records)()
+        n = ctypes.c_int32(0)
+        st = _check(lib().pcs_diagnostics(self.handle, buf, max_records, ctypes.byref(n)), "pcs_diagnostics",
+                    allow=(PCS_OK, PCS_BLOWUP))
+        recs = [{k: getattr(buf[i], k) for k in DIAG_FIELDS} for i in range(n.value)]
+        return recs, st
+
+    def get_state(self):
+        out = np.zeros(self.state_size)
+        _check(lib().pcs_get_state(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), out.size),
+               "pcs_get_state")
+        return out
+
+    def set_state(self, flat):
+        flat = np.ascontiguousarray(flat, dtype=np.float64)
+        if flat.size != self.state_size:
+            raise ValueError("state has %d values, expected %d" % (flat.size, self.state_size))
+        _check(lib().pcs_set_state(self.handle, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), flat.size),
+               "pcs_set_state")
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self.handle:
+            lib().pcs_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,763 @@
+// C ABI of the polymer channel-flow step (declared in include/pcs.h).
+//
+// pcs_init builds the wall-normal operators on the host, carves the caller's
+// device workspace, uploads operators and the initial state, computes the
+// per-mode homogeneous solutions of the influence-matrix method with the
+// same device kernels as the step, evaluates the first explicit terms as
+// history, and captures one step as a HIP graph.  pcs_step replays it.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <complex>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "../../include/pcs.h"
+#include "host_ops.hpp"
+#include "kernels.hpp"
+
+using namespace pcs;
+
+namespace {
+
+constexpr int RING = 4096;
+constexpr size_t ALIGN = 256;
+
+struct Carve {
+  char* base;
+  size_t off = 0;
+  explicit Carve(char* b) : base(b) {}
+  template <typename T>
+  T* take(size_t count) {
+    off = (off + ALIGN - 1) & ~(ALIGN - 1);
+    T* p = base ? reinterpret_cast<T*>(base + off) : nullptr;
+    off += count * sizeof(T);
+    return p;
+  }
+};
+
+struct JobList {
+  std::vector<GemmJob<double>> h;
+  GemmJob<double>* dev = nullptr;
+  int tiles = 0;
+  void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int m, int n, int k,
+           double alpha = 1.0, double beta = 0.0) {
+    GemmJob<double> j{};
+    j.A = A;
+    j.B = B;
+    j.C = C;
+    j.m = m;
+    j.n = n;
+    j.k = k;
+    j.lda = lda;
+    j.ldb = ldb;
+    j.ldc = ldc;
+    j.alpha = alpha;
+    j.beta = beta;
+    h.push_back(j);
+  }
+  int n() const { return (int)h.size(); }
+};
+
+bool valid_fft(int L) {
+  FftPlan p;
+  return make_plan(L, &p);
+}
+
+}  // namespace
+
+struct pcs_sim {
+  pcs_grid g{};
+  pcs_params prm{};
+  Dims d{};
+  Phys p{};
+  hipStream_t s = nullptr;
+  const WallOps* ops = nullptr;
+  FftPlan plx, plz, pbx, pbz;
+  int nq = 0, nh = 0, nyin = 0, nzin = 0, nout = 0, nsolve = 0, nsv = 0;
+  // device buffers (all inside the caller's workspace)
+  double *IMN, *DMN, *D, *D2, *PNM, *V, *Vinv, *DV, *wV, *lam, *d2i0, *d2in, *w, *ydy, *U1, *kx, *kz;
+  double *twx, *twz, *twbx, *twbz;
+  double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *Dc, *D2buf, *sbuf, *hy, *hgn, *Ds, *hvn;
+  double *R, *X, *Xs, *Zphi, *Zv, *ZDv, *flux, *CB, *prep, *zbuf;
+  int *zsrc, *zder;
+  DiagPart* parts;
+  DiagRec* ring;
+  DevScalars* sc;
+  JobList G1, G2, G3, G4, G5, H4, H5;
+  double wU1 = 0;
+  long long drained = 0;
+  int blowup = 0;
+  size_t nstate = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+};
+
+namespace {
+
+// Assigns every device buffer; with base == nullptr only measures.
+size_t carve(pcs_sim* m, char* base) {
+  const Dims& d = m->d;
+  const size_t n1 = d.N + 1, m1 = d.M + 1, ni = d.N - 1, cw = d.cw;
+  Carve c(base);
+  m->IMN = c.take<double>(m1 * n1);
+  m->DMN = c.take<double>(m1 * n1);
+  m->D = c.take<double>(n1 * n1);
+  m->D2 = c.take<double>(n1 * n1);
+  m->PNM = c.take<double>(n1 * m1);
+  m->V = c.take<double>(ni * ni);
+  m->Vinv = c.take<double>(ni * ni);
+  m->DV = c.take<double>(n1 * ni);
+  m->wV = c.take<double>(ni);
+  m->lam = c.take<double>(ni);
+  m->d2i0 = c.take<double>(ni);
+  m->d2in = c.take<double>(ni);
+  m->w = c.take<double>(n1);
+  m->ydy = c.take<double>(n1);
+  m->U1 = c.take<double>(n1);
+  m->kx = c.take<double>(d.nkx);
+  m->kz = c.take<double>(d.nzs);
+  m->twx = c.take<double>(2 * (size_t)d.px);
+  m->twz = c.take<double>(2 * (size_t)d.pz);
+  m->twbx = c.take<double>(2 * (size_t)d.nx);
+  m->twbz = c.take<double>(2 * (size_t)d.nz);
+  m->infl = c.take<double>(6 * n1 * d.nm + 4 * (size_t)d.nm);
+  m->state = c.take<double>((size_t)(m->nq + m->nh) * n1 * cw);
+  m->Yin = c.take<double>((size_t)m->nyin * m1 * cw);
+  const size_t zrow = (size_t)m1 * d.pz * d.nkx * 2;
+  m->Zin = d.dim == 3 ? c.take<double>((size_t)m->nzin * zrow) : nullptr;
+  m->Zout = d.dim == 3 ? c.take<double>((size_t)m->nout * zrow) : nullptr;
+  m->Yout = c.take<double>((size_t)m->nout * m1 * cw);
+  m->S = c.take<double>((size_t)m->nout * n1 * cw);
+  m->Dc = c.take<double>((size_t)(d.dim == 2 ? 2 : 3) * n1 * cw);
+  m->D2buf = c.take<double>((size_t)m->nsolve * n1 * cw + 2 * n1);
+  m->sbuf = c.take<double>(n1 * cw);
+  m->hy = c.take<double>(n1 * cw);
+  m->hgn = c.take<double>(n1 * cw);
+  m->Ds = c.take<double>(n1 * cw);
+  m->hvn = c.take<double>(n1 * cw);
+  m->R = c.take<double>((size_t)m->nsolve * ni * cw);
+  m->X = c.take<double>((size_t)m->nsolve * ni * cw);
+  m->Xs = c.take<double>((size_t)(m->nsolve + 1) * ni * cw);
+  m->Zphi = c.take<double>(ni * cw);
+  m->Zv = c.take<double>(ni * cw);
+  m->ZDv = c.take<double>(n1 * cw);
+  m->flux = c.take<double>(cw);
+  m->CB = c.take<double>((size_t)d.nc * 2 * cw);
+  m->prep = c.take<double>(4 * n1 * cw);
+  m->zbuf = d.dim == 3 ? c.take<double>(4 * n1 * (size_t)d.nz * d.nkx * 2) : nullptr;
+  m->zsrc = c.take<int>(32);
+  m->zder = c.take<int>(32);
+  const size_t zrows = d.dim == 3 ? d.nz : 1;
+  m->parts = c.take<DiagPart>(n1 * zrows);
+  m->ring = c.take<DiagRec>(RING);
+  m->sc = c.take<DevScalars>(1);
+  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5})
+    jl->dev = c.take<GemmJob<double>>(MAX_JOBS);
+  return c.off;
+}
+
+pcs_status setup_dims(pcs_sim* m, const pcs_grid* g, const pcs_params* p) {
+  if (!g || !p) return PCS_ERR_ARG;
+  if (g->dim != 2 && g->dim != 3) return PCS_ERR_ARG;
+  if (g->nx < 4 || (g->nx & 1) || g->ny < 9 || !(g->ny & 1)) return PCS_ERR_UNSUPPORTED;
+  if (g->dim == 2 && g->nz != 1) return PCS_ERR_ARG;
+  if (g->dim == 3 && (g->nz < 4 || (g->nz & 1))) return PCS_ERR_UNSUPPORTED;
+  if (!(g->lx > 0) || (g->dim == 3 && !(g->lz > 0))) return PCS_ERR_ARG;
+  if (!(p->re > 0) || !(p->wi > 0) || !(p->beta >= 0 && p->beta <= 1) || !(p->kappa >= 0) || !(p->dt > 0))
+    return PCS_ERR_ARG;
+  if (p->forcing != 0 && p->forcing != 1) return PCS_ERR_ARG;
+  if (p->precision != 0) return PCS_ERR_UNSUPPORTED;
+  if (!valid_fft(3 * g->nx / 2) || !valid_fft(g->nx)) return PCS_ERR_UNSUPPORTED;
+  if (g->dim == 3 && (!valid_fft(3 * g->nz / 2) || !valid_fft(g->nz))) return PCS_ERR_UNSUPPORTED;
+  m->g = *g;
+  m->prm = *p;
+  Dims& d = m->d;
+  d.dim = g->dim;
+  d.N = g->ny - 1;
+  d.M = 3 * d.N / 2;
+  d.nkx = g->nx / 2;
+  d.nzs = g->dim == 2 ? 1 : g->nz;
+  d.nm = d.nzs * d.nkx;
+  d.cw = 2 * d.nm;
+  d.px = 3 * g->nx / 2;
+  d.pz = g->dim == 2 ? 1 : 3 * g->nz / 2;
+  d.nx = g->nx;
+  d.nz = g->dim == 2 ? 1 : g->nz;
+  d.nc = g->dim == 2 ? 3 : 6;
+  d.lx = g->lx;
+  d.lz = g->dim == 2 ? 1.0 : g->lz;
+  if (xpencil_lds_bytes(d.dim, d.px) > 160 * 1024) return PCS_ERR_UNSUPPORTED;
+  Phys& q = m->p;
+  q.re = p->re;
+  q.wi = p->wi;
+  q.beta = p->beta;
+  q.kappa = p->kappa;
+  q.eps = p->eps;
+  q.dt = p->dt;
+  q.forcing = p->forcing;
+  q.q_or_dpdx = p->q_or_dpdx;
+  q.coef = (1.0 - p->beta) / (p->re * p->wi);
+  q.nu = p->beta / p->re;
+  m->nq = d.dim == 2 ? 6 : 11;
+  m->nh = d.dim == 2 ? 4 : 8;
+  m->nyin = d.dim == 2 ? 9 : 17;
+  m->nzin = 26;
+  m->nout = d.dim == 2 ? 5 : 9;
+  m->nsv = d.dim == 2 ? 1 : 2;
+  m->nsolve = m->nsv + d.nc;
+  m->nstate = 4 + (size_t)(m->nq + m->nh) * (d.N + 1) * d.cw;
+  make_plan(d.px, &m->plx);
+  make_plan(d.nx, &m->pbx);
+  if (d.dim == 3) {
+    make_plan(d.pz, &m->plz);
+    make_plan(d.nz, &m->pbz);
+  }
+  return PCS_OK;
+}
+
+// Initial state: laminar profiles in the mean slot plus the seeded
+// streamfunction perturbation (divergence-free, no-slip), history zero.
+void initial_state(const pcs_sim* m, uint64_t seed, double amp, std::vector<double>& st) {
+  const Dims& d = m->d;
+  const int n1 = d.N + 1;
+  const size_t fs = (size_t)n1 * d.cw;
+  st.assign((size_t)(m->nq + m->nh) * fs, 0.0);
+  const double* y = m->ops->y.data();
+  std::vector<double> U(n1), cxx(n1), cxy(n1), cyy(n1);
+  laminar(y, n1, m->p.wi, m->p.kappa, U.data(), cxx.data(), cxy.data(), cyy.data());
+  const int FC = d.dim == 2 ? 3 : 5;
+  const int iyy = d.dim == 2 ? 2 : 3;
+  for (int j = 0; j < n1; ++j) {
+    const size_t o = (size_t)j * d.cw;
+    st[0 * fs + o] = U[j];
+    st[(FC + 0) * fs + o] = cxx[j];
+    st[(FC + 1) * fs + o] = cxy[j];
+    st[(FC + iyy) * fs + o] = cyy[j];
+    if (d.dim == 3) st[(FC + 5) * fs + o] = cyy[j];
+  }
+  // basis p_n = (1 - y^2)^2 T_n, n = 0..4, and two derivatives
+  std::vector<double> P(5 * n1), P1(5 * n1), P2(5 * n1);
+  for (int j = 0; j < n1; ++j) {
+    const double yy = y[j], q = 1.0 - yy * yy;
+    double T[5], T1[5], T2[5];
+    T[0] = 1;
+    T1[0] = 0;
+    T2[0] = 0;
+    T[1] = yy;
+    T1[1] = 1;
+    T2[1] = 0;
+    for (int n = 1; n < 4; ++n) {
+      T[n + 1] = 2 * yy * T[n] - T[n - 1];
+      T1[n + 1] = 2 * T[n] + 2 * yy * T1[n] - T1[n - 1];
+      T2[n + 1] = 4 * T1[n] + 2 * yy * T2[n] - T2[n - 1];
+    }
+    for (int n = 0; n < 5; ++n) {
+      P[n * n1 + j] = q * q * T[n];
+      P1[n * n1 + j] = -4.0 * yy * q * T[n] + q * q * T1[n];
+      P2[n * n1 + j] = (12.0 * yy * yy - 4.0) * T[n] - 8.0 * yy * q * T1[n] + q * q * T2[n];
+    }
+  }
+  typedef std::complex<double> cx;
+  struct Pot {
+    std::vector<cx> f, f1, f2;
+  };
+  std::map<std::tuple<int, int, int>, Pot> pots;  // (potential, mx, mz)
+  SplitMix64 rng(seed);
+  auto draw = [&](int pot, int mx, int mz) {
+    double th[5];
+    for (int n = 0; n < 5; ++n) th[n] = 2.0 * M_PI * rng.u01();
+    const bool fits = mx < d.nkx && (d.dim == 2 || std::abs(mz) < d.nz / 2);
+    if (!fits) return;
+    Pot p;
+    p.f.assign(n1, 0);
+    p.f1.assign(n1, 0);
+    p.f2.assign(n1, 0);
+    for (int j = 0; j < n1; ++j) {
+      cx a(0), a1(0), a2(0);
+      for (int n = 0; n < 5; ++n) {
+        const cx c(amp * std::cos(th[n]), amp * std::sin(th[n]));
+        a += c * P[n * n1 + j];
+        a1 += c * P1[n * n1 + j];
+        a2 += c * P2[n * n1 + j];
+      }
+      p.f[j] = a;
+      p.f1[j] = a1;
+      p.f2[j] = a2;
+    }
+    pots[std::make_tuple(pot, mx, mz)] = p;
+    if (d.dim == 3 && mx == 0) {
+      Pot q = p;
+      for (int j = 0; j < n1; ++j) {
+        q.f[j] = std::conj(p.f[j]);
+        q.f1[j] = std::conj(p.f1[j]);
+        q.f2[j] = std::conj(p.f2[j]);
+      }
+      pots[std::make_tuple(pot, 0, -mz)] = q;
+    }
+  };
+  if (d.dim == 2) {
+    for (int mx = 1; mx <= 4; ++mx) draw(0, mx, 0);
+  } else {
+    for (int pot = 0; pot < 2; ++pot)
+      for (int mx = 0; mx <= 4; ++mx)
+        for (int mz = -4; mz <= 4; ++mz) {
+          if ((mx == 0 && mz == 0) || (mx == 0 && mz < 0)) continue;
+          draw(pot, mx, mz);
+        }
+  }
+  const int FPHI = d.dim == 2 ? 2 : 3;
+  for (int iz = 0; iz < d.nzs; ++iz) {
+    if (d.dim == 3 && iz == d.nzs / 2) continue;
+    const int mz = d.dim == 2 ? 0 : (iz < d.nzs / 2 ? iz : iz - d.nzs);
+    const double kz = d.dim == 2 ? 0.0 : 2.0 * M_PI * mz / d.lz;
+    for (int ix = 0; ix < d.nkx; ++ix) {
+      if (iz == 0 && ix == 0) continue;
+      const double kx = 2.0 * M_PI * ix / d.lx;
+      const double k2 = kx * kx + kz * kz;
+      auto ip = pots.find(std::make_tuple(0, ix, mz));
+      auto ic = pots.find(std::make_tuple(1, ix, mz));
+      if (ip == pots.end() && ic == pots.end()) continue;
+      const size_t mo = 2 * ((size_t)iz * d.nkx + ix);
+      for (int j = 0; j < n1; ++j) {
+        const cx zero(0);
+        const cx ps = ip != pots.end() ? ip->second.f[j] : zero, ps1 = ip != pots.end() ? ip->second.f1[j] : zero,
+                 ps2 = ip != pots.end() ? ip->second.f2[j] : zero;
+        const cx ch = ic != pots.end() ? ic->second.f[j] : zero, ch1 = ic != pots.end() ? ic->second.f1[j] : zero,
+                 ch2 = ic != pots.end() ? ic->second.f2[j] : zero;
+        const cx I(0, 1);
+        const cx u = ps1, w = ch1;
+        const cx v = -I * kx * ps - I * kz * ch;
+        const cx v2 = -I * kx * ps2 - I * kz * ch2;
+        const cx phi = v2 - k2 * v;
+        const size_t o = (size_t)j * d.cw + mo;
+        st[0 * fs + o] = u.real();
+        st[0 * fs + o + 1] = u.imag();
+        st[1 * fs + o] = v.real();
+        st[1 * fs + o + 1] = v.imag();
+        st[FPHI * fs + o] = phi.real();
+        st[FPHI * fs + o + 1] = phi.imag();
+        if (d.dim == 3) {
+          const cx g = I * kz * u - I * kx * w;
+          st[2 * fs + o] = w.real();
+          st[2 * fs + o + 1] = w.imag();
+          st[4 * fs + o] = g.real();
+          st[4 * fs + o + 1] = g.imag();
+        }
+      }
+    }
+  }
+}
+
+void build_jobs(pcs_sim* m) {
+  const Dims& d = m->d;
+  const int n1 = d.N + 1, m1 = d.M + 1, ni = d.N - 1, cw = d.cw;
+  const size_t fs = (size_t)n1 * cw, fsm = (size_t)m1 * cw, fsi = (size_t)ni * cw;
+  double* st = m->state;
+  const int FC = d.dim == 2 ? 3 : 5, FPHI = d.dim == 2 ? 2 : 3;
+  // G1: products of the state
+  JobList& g1 = m->G1;
+  const int velI[3] = {0, 1, 2};
+  const int nvel = d.dim;
+  for (int a = 0; a < nvel; ++a) g1.add(m->IMN, n1, st + velI[a] * fs, cw, m->Yin + a * fsm, cw, m1, cw, n1);
+  for (int a = 0; a < d.nc; ++a) g1.add(m->IMN, n1, st + (FC + a) * fs, cw, m->Yin + (nvel + a) * fsm, cw, m1, cw, n1);
+  const int yd0 = nvel + d.nc;  // first d/dy field in Yin
+  g1.add(m->DMN, n1, st + 0 * fs, cw, m->Yin + yd0 * fsm, cw, m1, cw, n1);
+  int o = yd0 + 1;
+  if (d.dim == 3) g1.add(m->DMN, n1, st + 2 * fs, cw, m->Yin + (o++) * fsm, cw, m1, cw, n1);
+  for (int a = 0; a < d.nc; ++a) g1.add(m->DMN, n1, st + (FC + a) * fs, cw, m->Yin + (o++) * fsm, cw, m1, cw, n1);
+  g1.add(m->D2, n1, st + FPHI * fs, cw, m->D2buf + 0 * fs, cw, n1, cw, n1);
+  if (d.dim == 3) g1.add(m->D2, n1, st + 4 * fs, cw, m->D2buf + 1 * fs, cw, n1, cw, n1);
+  for (int a = 0; a < d.nc; ++a) g1.add(m->D2, n1, st + (FC + a) * fs, cw, m->D2buf + (m->nsv + a) * fs, cw, n1, cw, n1);
+  double* D2U = m->D2buf + (size_t)m->nsolve * fs;
+  g1.add(m->D2, n1, st + 0 * fs, cw, D2U, 1, n1, 1, n1);
+  if (d.dim == 3) g1.add(m->D2, n1, st + 2 * fs, cw, D2U + n1, 1, n1, 1, n1);
+  // D c_y. for the stress divergence: 2D c_xy, c_yy; 3D c_xy, c_yy, c_yz
+  const int dci[3] = {1, d.dim == 2 ? 2 : 3, 4};
+  for (int q = 0; q < (d.dim == 2 ? 2 : 3); ++q)
+    g1.add(m->D, n1, st + (FC + dci[q]) * fs, cw, m->Dc + q * fs, cw, n1, cw, n1);
+  // G2: projection of the explicit terms
+  for (int f = 0; f < m->nout; ++f) m->G2.add(m->PNM, m1, m->Yout + f * fsm, cw, m->S + f * fs, cw, n1, cw, m1);
+  // G3: D s
+  m->G3.add(m->D, n1, m->sbuf, cw, m->Ds, cw, n1, cw, n1);
+  // G4: V^-1 R
+  for (int f = 0; f < m->nsolve; ++f) m->G4.add(m->Vinv, ni, m->R + f * fsi, cw, m->X + f * fsi, cw, ni, cw, ni);
+  m->H4.add(m->Vinv, ni, m->R, cw, m->X, cw, ni, cw, ni);
+  // G5: back from the eigenbasis
+  for (JobList* jl : {&m->G5, &m->H5}) {
+    jl->add(m->V, ni, m->Xs + 0 * fsi, cw, m->Zphi, cw, ni, cw, ni);
+    jl->add(m->V, ni, m->Xs + 1 * fsi, cw, m->Zv, cw, ni, cw, ni);
+    jl->add(m->DV, ni, m->Xs + 1 * fsi, cw, m->ZDv, cw, n1, cw, ni);
+  }
+  int xo = 2;
+  if (d.dim == 3) {
+    m->G5.add(m->V, ni, m->Xs + 2 * fsi, cw, st + 4 * fs + cw, cw, ni, cw, ni);
+    xo = 3;
+  }
+  for (int a = 0; a < d.nc; ++a)
+    m->G5.add(m->V, ni, m->Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
+  m->G5.add(m->wV, ni, m->Xs + 0 * fsi, cw, m->flux, cw, 1, cw, ni);
+  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5})
+    jl->tiles = gemm_prepare(jl->h.data(), jl->n());
+}
+
+void explicit_stage(pcs_sim* m) {
+  const Dims& d = m->d;
+  hipStream_t s = m->s;
+  gemm_f64(m->G1.dev, m->G1.tiles, m->G1.n(), s);
+  if (d.dim == 3) {
+    launch_zfft(d, m->plz, m->Yin, m->Zin, m->nzin, m->zsrc, m->zder, m->kz, m->twz, 1, d.M + 1, s);
+    launch_xpencil3d(d, m->p, m->plx, m->Zin, m->Zout, m->kx, m->twx, s);
+    launch_zfft(d, m->plz, m->Zout, m->Yout, m->nout, nullptr, nullptr, m->kz, m->twz, 0, d.M + 1, s);
+  } else {
+    launch_xpencil(d, m->p, m->plx, m->Yin, m->Yout, m->kx, m->twx, s);
+  }
+  gemm_f64(m->G2.dev, m->G2.tiles, m->G2.n(), s);
+  const size_t fs = (size_t)(d.N + 1) * d.cw;
+  launch_assemble_h(d, m->p, m->S, m->state + (d.dim == 2 ? 3 : 5) * fs, m->Dc, m->kx, m->kz, m->sbuf, m->hy, m->hgn,
+                    s);
+  gemm_f64(m->G3.dev, m->G3.tiles, m->G3.n(), s);
+  launch_rhs(d, m->p, m->state, m->D2buf, m->sbuf, m->Ds, m->hy, m->hgn, m->S, m->kx, m->kz, m->d2i0, m->d2in, m->R,
+             m->hvn, m->CB, s);
+}
+
+void enqueue_step(pcs_sim* m) {
+  const Dims& d = m->d;
+  hipStream_t s = m->s;
+  explicit_stage(m);
+  gemm_f64(m->G4.dev, m->G4.tiles, m->G4.n(), s);
+  launch_eigscale(d, m->p, m->X, m->Xs, m->lam, m->kx, m->kz, s);
+  gemm_f64(m->G5.dev, m->G5.tiles, m->G5.n(), s);
+  launch_finalize(d, m->p, m->Zphi, m->Zv, m->ZDv, m->flux, m->infl, m->U1, m->wU1, m->CB, m->hvn, m->hgn, m->S,
+                  m->kx, m->kz, m->state, m->sc, s);
+  launch_diag_rows(d, m->p, m->pbx, m->state, m->prep, m->zbuf, m->pbz, m->twbx, m->twbz, m->ydy, m->parts, s);
+  launch_diag_final(d, m->p, m->parts, m->w, m->sc, m->ring, RING, s);
+}
+
+// With PCS_DEBUG set in the environment, failing HIP calls are reported on stderr.
+void report(hipError_t e, const char* what, int line) {
+  static const bool dbg = std::getenv("PCS_DEBUG") != nullptr;
+  if (dbg) std::fprintf(stderr, "pcs: %s failed at api.cpp:%d: %s\n", what, line, hipGetErrorString(e));
+}
+
+#define HIPCHK(x)                        \
+  do {                                   \
+    hipError_t e_ = (x);                 \
+    if (e_ != hipSuccess) {              \
+      report(e_, #x, __LINE__);          \
+      (void)hipGetLastError();           \
+      return PCS_ERR_DEVICE;             \
+    }                                    \
+  } while (0)
+
+// Init-time uploads are blocking copies, so host temporaries may die at once.
+template <typename T>
+hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
+  const Dims& d = m->d;
+  const WallOps* op = m->ops;
+  const int n1 = d.N + 1, ni = d.N - 1;
+  hipStream_t s = m->s;
+  // operators
+  HIPCHK(up(m->IMN, op->IMN, s));
+  HIPCHK(up(m->DMN, op->DMN, s));
+  HIPCHK(up(m->D, op->D, s));
+  HIPCHK(up(m->D2, op->D2, s));
+  HIPCHK(up(m->PNM, op->PNM, s));
+  HIPCHK(up(m->V, op->V, s));
+  HIPCHK(up(m->Vinv, op->Vinv, s));
+  HIPCHK(up(m->lam, op->lam, s));
+  HIPCHK(up(m->d2i0, op->d2_i0, s));
+  HIPCHK(up(m->d2in, op->d2_in, s));
+  HIPCHK(up(m->w, op->w, s));
+  // D restricted to interior columns times V, and w (interior) times V
+  std::vector<double> DV((size_t)n1 * ni, 0.0), wV(ni, 0.0);
+  for (int i = 0; i < n1; ++i)
+    for (int e = 0; e < ni; ++e) {
+      long double acc = 0;
+      for (int j = 1; j < d.N; ++j) acc += (long double)op->D[(size_t)i * n1 + j] * op->V[(size_t)(j - 1) * ni + e];
+      DV[(size_t)i * ni + e] = (double)acc;
+    }
+  for (int e = 0; e < ni; ++e) {
+    long double acc = 0;
+    for (int j = 1; j < d.N; ++j) acc += (long double)op->w[j] * op->V[(size_t)(j - 1) * ni + e];
+    wV[e] = (double)acc;
+  }
+  HIPCHK(up(m->DV, DV, s));
+  HIPCHK(up(m->wV, wV, s));
+  std::vector<double> ydy(n1);
+  const double* y = op->y.data();
+  for (int j = 1; j < d.N; ++j) ydy[j] = 0.5 * (y[j - 1] - y[j + 1]);
+  ydy[0] = y[0] - y[1];
+  ydy[d.N] = y[d.N - 1] - y[d.N];
+  HIPCHK(up(m->ydy, ydy, s));
+  std::vector<double> kx(d.nkx), kz(d.nzs, 0.0);
+  for (int i = 0; i < d.nkx; ++i) kx[i] = 2.0 * M_PI * i / d.lx;
+  if (d.dim == 3)
+    for (int i = 0; i < d.nzs; ++i) {
+      const int mz = (i < d.nzs / 2) ? i : (i == d.nzs / 2 ? 0 : i - d.nzs);
+      kz[i] = 2.0 * M_PI * mz / d.lz;
+    }
+  HIPCHK(up(m->kx, kx, s));
+  HIPCHK(up(m->kz, kz, s));
+  HIPCHK(up(m->twx, twiddles(d.px, -1), s));
+  HIPCHK(up(m->twbx, twiddles(d.nx, -1), s));
+  if (d.dim == 3) {
+    HIPCHK(up(m->twz, twiddles(d.pz, -1), s));
+    HIPCHK(up(m->twbz, twiddles(d.nz, -1), s));
+    // z-transform input table: the 17 y-transformed fields, then d/dz of u v w c6
+    std::vector<int> src(26), der(26);
+    for (int f = 0; f < 17; ++f) {
+      src[f] = f;
+      der[f] = 0;
+    }
+    for (int f = 0; f < 9; ++f) {
+      src[17 + f] = f;
+      der[17 + f] = 1;
+    }
+    HIPCHK(up(m->zsrc, src, s));
+    HIPCHK(up(m->zder, der, s));
+  }
+  // initial state
+  std::vector<double> st;
+  initial_state(m, seed, amp, st);
+  HIPCHK(up(m->state, st, s));
+  DevScalars sc0{};
+  sc0.pi = m->p.forcing == 1 ? m->p.q_or_dpdx : 2.0 / m->p.re;
+  HIPCHK(hipMemcpy(m->sc, &sc0, sizeof(sc0), hipMemcpyHostToDevice));
+  // GEMM job tables
+  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5})
+    HIPCHK(up(jl->dev, jl->h, s));
+  return PCS_OK;
+}
+
+pcs_status homogeneous_solutions(pcs_sim* m) {
+  const Dims& d = m->d;
+  hipStream_t s = m->s;
+  const size_t fsi = (size_t)(d.N - 1) * d.cw;
+  HIPCHK(hipMemsetAsync(m->R, 0, m->nsolve * fsi * sizeof(double), s));
+  HIPCHK(hipMemsetAsync(m->X, 0, m->nsolve * fsi * sizeof(double), s));
+  launch_homog_rhs(d, m->p, m->d2i0, m->d2in, m->R, s);
+  gemm_f64(m->H4.dev, m->H4.tiles, m->H4.n(), s);
+  launch_eigscale(d, m->p, m->X, m->Xs, m->lam, m->kx, m->kz, s);
+  gemm_f64(m->H5.dev, m->H5.tiles, m->H5.n(), s);
+  launch_influence(d, m->Zphi, m->Zv, m->ZDv, m->kz, m->infl, m->U1, s);
+  HIPCHK(hipGetLastError());
+  std::vector<double> U1(d.N + 1);
+  HIPCHK(hipMemcpyAsync(U1.data(), m->U1, U1.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double acc = 0;
+  for (int j = 0; j <= d.N; ++j) acc += m->ops->w[j] * U1[j];
+  m->wU1 = acc;
+  return PCS_OK;
+}
+
+// History := explicit terms of the current state (the first step is CNAB1).
+pcs_status history_from_state(pcs_sim* m) {
+  const Dims& d = m->d;
+  hipStream_t s = m->s;
+  const size_t fs = (size_t)(d.N + 1) * d.cw;
+  explicit_stage(m);
+  HIPCHK(hipGetLastError());
+  double* hist = m->state + (size_t)m->nq * fs;
+  HIPCHK(hipMemcpyAsync(hist, m->hvn, fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  int h = 1;
+  if (d.dim == 3) HIPCHK(hipMemcpyAsync(hist + (h++) * fs, m->hgn, fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const int SF = d.dim == 2 ? 2 : 3;
+  HIPCHK(hipMemcpyAsync(hist + h * fs, m->S + SF * fs, d.nc * fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  return PCS_OK;
+}
+
+pcs_status capture(pcs_sim* m) {
+  if (m->s == nullptr) return PCS_OK;  // the legacy default stream cannot be captured
+  if (hipStreamBeginCapture(m->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+    (void)hipGetLastError();
+    return PCS_OK;
+  }
+  enqueue_step(m);
+  hipGraph_t g = nullptr;
+  if (hipStreamEndCapture(m->s, &g) != hipSuccess || g == nullptr) {
+    (void)hipGetLastError();
+    return PCS_OK;
+  }
+  hipGraphExec_t ge = nullptr;
+  if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
+    (void)hipGetLastError();
+    hipGraphDestroy(g);
+    return PCS_OK;
+  }
+  m->graph = g;
+  m->gexec = ge;
+  return PCS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pcs_status pcs_workspace_bytes(const pcs_grid* grid, const pcs_params* params, size_t* bytes) {
+  if (!bytes) return PCS_ERR_ARG;
+  pcs_sim tmp;
+  pcs_status st = setup_dims(&tmp, grid, params);
+  if (st != PCS_OK) return st;
+  *bytes = carve(&tmp, nullptr);
+  return PCS_OK;
+}
+
+pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t seed, double amp, void* workspace,
+                    size_t bytes, void* stream, pcs_sim** out) {
+  if (!out || !workspace) return PCS_ERR_ARG;
+  *out = nullptr;
+  if (!std::isfinite(amp)) return PCS_ERR_ARG;
+  pcs_sim* m = new (std::nothrow) pcs_sim();
+  if (!m) return PCS_ERR_ARG;
+  pcs_status st = setup_dims(m, grid, params);
+  if (st != PCS_OK) {
+    delete m;
+    return st;
+  }
+  const size_t need = carve(m, nullptr);
+  if (bytes < need || (reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0) {
+    delete m;
+    return PCS_ERR_WORKSPACE;
+  }
+  m->ops = wall_ops(m->d.N);
+  if (!m->ops) {
+    delete m;
+    return PCS_ERR_UNSUPPORTED;
+  }
+  carve(m, static_cast<char*>(workspace));
+  m->s = static_cast<hipStream_t>(stream);
+  if (hipError_t e = fft_set_attributes(); e != hipSuccess) {
+    report(e, "fft_set_attributes", __LINE__);
+    delete m;
+    return PCS_ERR_DEVICE;
+  }
+  build_jobs(m);
+  if ((st = upload_everything(m, seed, amp)) != PCS_OK || (st = homogeneous_solutions(m)) != PCS_OK ||
+      (st = history_from_state(m)) != PCS_OK) {
+    delete m;
+    return st;
+  }
+  hipError_t e1 = hipStreamSynchronize(m->s), e2 = hipGetLastError();
+  if (e1 != hipSuccess || e2 != hipSuccess) {
+    report(e1 != hipSuccess ? e1 : e2, "init synchronise", __LINE__);
+    delete m;
+    return PCS_ERR_DEVICE;
+  }
+  capture(m);
+  *out = m;
+  return PCS_OK;
+}
+
+pcs_status pcs_step(pcs_sim* m, int32_t nsteps) {
+  if (!m || nsteps < 0) return PCS_ERR_ARG;
+  if (m->blowup) return PCS_ERR_STATE;
+  for (int i = 0; i < nsteps; ++i) {
+    if (m->gexec) {
+      if (hipGraphLaunch(m->gexec, m->s) != hipSuccess) return PCS_ERR_DEVICE;
+    } else {
+      enqueue_step(m);
+    }
+  }
+  return hipGetLastError() == hipSuccess ? PCS_OK : PCS_ERR_DEVICE;
+}
+
+pcs_status pcs_diagnostics(pcs_sim* m, pcs_diag* outp, int32_t max, int32_t* n_out) {
+  if (!m || !n_out || max < 0 || (max > 0 && !outp)) return PCS_ERR_ARG;
+  *n_out = 0;
+  DevScalars sc;
+  HIPCHK(hipMemcpyAsync(&sc, m->sc, sizeof(sc), hipMemcpyDeviceToHost, m->s));
+  HIPCHK(hipStreamSynchronize(m->s));
+  long long first = m->drained + 1;
+  if (sc.step - first + 1 > RING) first = sc.step - RING + 1;
+  long long cnt = sc.step - first + 1;
+  if (cnt > max) cnt = max;
+  std::vector<DiagRec> recs((size_t)(cnt > 0 ? cnt : 0));
+  // records of steps first .. first+cnt-1 sit at ring slots (step-1) % RING:
+  // at most two contiguous pieces
+  long long done = 0;
+  while (done < cnt) {
+    const long long slot = (first + done - 1) % RING;
+    const long long piece = std::min<long long>(cnt - done, RING - slot);
+    HIPCHK(hipMemcpyAsync(&recs[done], m->ring + slot, (size_t)piece * sizeof(DiagRec), hipMemcpyDeviceToHost, m->s));
+    done += piece;
+  }
+  HIPCHK(hipStreamSynchronize(m->s));
+  static_assert(sizeof(DiagRec) == sizeof(pcs_diag), "diagnostic record layout");
+  if (cnt > 0) std::memcpy(outp, recs.data(), (size_t)cnt * sizeof(pcs_diag));
+  *n_out = (int32_t)cnt;
+  m->drained = first + cnt - 1;
+  if (sc.blowup) m->blowup = 1;
+  return m->blowup ? PCS_BLOWUP : PCS_OK;
+}
+
+pcs_status pcs_state_size(pcs_sim* m, size_t* n) {
+  if (!m || !n) return PCS_ERR_ARG;
+  *n = m->nstate;
+  return PCS_OK;
+}
+
+pcs_status pcs_get_state(pcs_sim* m, double* host, size_t n) {
+  if (!m || !host || n != m->nstate) return PCS_ERR_ARG;
+  DevScalars sc;
+  HIPCHK(hipMemcpyAsync(&sc, m->sc, sizeof(sc), hipMemcpyDeviceToHost, m->s));
+  HIPCHK(hipMemcpyAsync(host + 4, m->state, (n - 4) * sizeof(double), hipMemcpyDeviceToHost, m->s));
+  HIPCHK(hipStreamSynchronize(m->s));
+  host[0] = (double)sc.step;
+  host[1] = sc.t;
+  host[2] = sc.pi;
+  host[3] = 0.0;
+  return PCS_OK;
+}
+
+pcs_status pcs_set_state(pcs_sim* m, const double* host, size_t n) {
+  if (!m || !host || n != m->nstate) return PCS_ERR_ARG;
+  for (size_t i = 0; i < 3; ++i)
+    if (!std::isfinite(host[i])) return PCS_ERR_ARG;
+  DevScalars sc{};
+  sc.step = (long long)host[0];
+  sc.t = host[1];
+  sc.pi = host[2];
+  HIPCHK(hipMemcpyAsync(m->state, host + 4, (n - 4) * sizeof(double), hipMemcpyHostToDevice, m->s));
+  HIPCHK(hipMemcpyAsync(m->sc, &sc, sizeof(sc), hipMemcpyHostToDevice, m->s));
+  HIPCHK(hipStreamSynchronize(m->s));
+  m->drained = sc.step;
+  m->blowup = 0;
+  return PCS_OK;
+}
+
+pcs_status pcs_destroy(pcs_sim* m) {
+  if (!m) return PCS_ERR_ARG;
+  if (m->s) (void)hipStreamSynchronize(m->s);
+  else (void)hipDeviceSynchronize();
+  if (m->gexec) hipGraphExecDestroy(m->gexec);
+  if (m->graph) hipGraphDestroy(m->graph);
+  delete m;
+  return PCS_OK;
+}
+
+const char* pcs_status_string(pcs_status s) {
+  switch (s) {
+    case PCS_OK: return "ok";
+    case PCS_BLOWUP: return "blow-up flagged (non-finite value or |Tr c| > 1e12)";
+    case PCS_ERR_ARG: return "invalid argument";
+    case PCS_ERR_UNSUPPORTED: return "unsupported size or option";
+    case PCS_ERR_WORKSPACE: return "workspace too small or not 256-byte aligned";
+    case PCS_ERR_DEVICE: return "HIP runtime error";
+    case PCS_ERR_STATE: return "run has blown up; set a new state first";
+    default: return "unknown status";
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,431 @@
+// Spectral elementwise stages of the CNAB2 step (FP64).
+//
+// Layout of every spectral field: [y row j][kz slot][kx] complex, re/im
+// interleaved, i.e. a row-major (rows x cw) real matrix with
+// cw = 2 * nzs * nkx.  One thread owns one complex element (j, mode) and all
+// fields of it, so consecutive threads touch consecutive modes of one row.
+//
+// Equations (paper, Section 2): eq. (2) momentum with the polymer-stress
+// divergence, handled through its curl-curl and curl (velocity-vorticity
+// form, pressure eliminated); eq. (1) conformation update with the
+// relaxation -(c - I)/Wi split into an implicit -c/Wi and a constant +I/Wi,
+// polymer diffusion implicit in the interior and absent (kappa = 0) in the
+// two wall rows (the wall condition of Section 2); eq. (3) exactly, through
+// u = (i kx Dv - i kz g)/k^2 and w = (i kz Dv + i kx g)/k^2.
+#include "kernels.hpp"
+
+namespace pcs {
+
+namespace {
+
+struct Mode {
+  int j, mode, iz, ix;
+  double kx, kz, k2;
+  bool mean, nyq;
+};
+
+__device__ inline Mode decode(const Dims& d, int e, const double* kx, const double* kz) {
+  Mode m;
+  m.j = e / d.nm;
+  m.mode = e - m.j * d.nm;
+  m.iz = m.mode / d.nkx;
+  m.ix = m.mode - m.iz * d.nkx;
+  m.kx = kx[m.ix];
+  m.kz = (d.dim == 3) ? kz[m.iz] : 0.0;
+  m.k2 = m.kx * m.kx + m.kz * m.kz;
+  m.mean = (m.mode == 0);
+  m.nyq = (d.dim == 3) && (m.iz == d.nzs / 2);
+  return m;
+}
+
+struct cd {
+  double r, i;
+};
+__device__ inline cd ld2(const double* f, size_t off) { return cd{f[off], f[off + 1]}; }
+__device__ inline void st2(double* f, size_t off, cd v) {
+  f[off] = v.r;
+  f[off + 1] = v.i;
+}
+__device__ inline cd operator+(cd a, cd b) { return cd{a.r + b.r, a.i + b.i}; }
+__device__ inline cd operator-(cd a, cd b) { return cd{a.r - b.r, a.i - b.i}; }
+__device__ inline cd operator*(double s, cd a) { return cd{s * a.r, s * a.i}; }
+__device__ inline cd ik(double k, cd a) { return cd{-k * a.i, k * a.r}; }  // (i k) a
+
+// index of c_ab in the stored list (2D: xx xy yy; 3D: xx xy xz yy yz zz)
+__device__ inline int cidx(int dim, int a, int b) {
+  if (a > b) {
+    int t = a;
+    a = b;
+    b = t;
+  }
+  if (dim == 2) return (a == 0) ? b : 2;
+  return (a == 0) ? b : (a == 1 ? 2 + b : 5);
+}
+
+struct Layout {
+  int nq, F_U, F_V, F_W, F_PHI, F_G, F_C, H_HV, H_HG, H_F, nsv, nsolve, S_F;
+  __device__ Layout(int dim, int nc) {
+    if (dim == 2) {
+      nq = 6; F_U = 0; F_V = 1; F_W = -1; F_PHI = 2; F_G = -1; F_C = 3;
+      H_HV = 6; H_HG = -1; H_F = 7; nsv = 1; S_F = 2;
+    } else {
+      nq = 11; F_U = 0; F_V = 1; F_W = 2; F_PHI = 3; F_G = 4; F_C = 5;
+      H_HV = 11; H_HG = 12; H_F = 13; nsv = 2; S_F = 3;
+    }
+    nsolve = nsv + nc;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------- H, s, h_g
+// H_a = N_a + (1 - beta)/(Re Wi) (i kx c_xa + D c_ya + i kz c_za)
+// s   = i kx H_x + i kz H_z       (mean slot: Re H_x, the mean-flow forcing)
+// h_g = i kz H_x - i kx H_z       (mean slot: Re H_z)
+__global__ void assemble_h_kernel(Dims d, Phys p, const double* __restrict__ S, const double* __restrict__ cf,
+                                  const double* __restrict__ Dc, const double* __restrict__ kx,
+                                  const double* __restrict__ kz, double* __restrict__ sbuf,
+                                  double* __restrict__ hy, double* __restrict__ hgn) {
+  const int n1 = d.N + 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n1 * d.nm) return;
+  Mode m = decode(d, e, kx, kz);
+  const size_t fs = (size_t)n1 * d.cw;
+  const size_t off = (size_t)m.j * d.cw + 2 * m.mode;
+  if (m.nyq) {
+    st2(sbuf, off, cd{0, 0});
+    st2(hy, off, cd{0, 0});
+    if (d.dim == 3) st2(hgn, off, cd{0, 0});
+    return;
+  }
+  auto c = [&](int a, int b) { return ld2(cf, cidx(d.dim, a, b) * fs + off); };
+  if (d.dim == 2) {
+    cd Hx = ld2(S, 0 * fs + off) + p.coef * (ik(m.kx, c(0, 0)) + ld2(Dc, 0 * fs + off));
+    cd Hy = ld2(S, 1 * fs + off) + p.coef * (ik(m.kx, c(0, 1)) + ld2(Dc, 1 * fs + off));
+    st2(sbuf, off, m.mean ? cd{Hx.r, 0} : ik(m.kx, Hx));
+    st2(hy, off, Hy);
+  } else {
+    cd Hx = ld2(S, 0 * fs + off) + p.coef * (ik(m.kx, c(0, 0)) + ld2(Dc, 0 * fs + off) + ik(m.kz, c(2, 0)));
+    cd Hy = ld2(S, 1 * fs + off) + p.coef * (ik(m.kx, c(0, 1)) + ld2(Dc, 1 * fs + off) + ik(m.kz, c(2, 1)));
+    cd Hz = ld2(S, 2 * fs + off) + p.coef * (ik(m.kx, c(0, 2)) + ld2(Dc, 2 * fs + off) + ik(m.kz, c(2, 2)));
+    st2(sbuf, off, m.mean ? cd{Hx.r, 0} : ik(m.kx, Hx) + ik(m.kz, Hz));
+    st2(hy, off, Hy);
+    st2(hgn, off, m.mean ? cd{Hz.r, 0} : ik(m.kz, Hx) - ik(m.kx, Hz));
+  }
+}
+
+void launch_assemble_h(const Dims& d, const Phys& p, const double* S, const double* cfields, const double* Dc,
+                       const double* kx, const double* kz, double* sbuf, double* hy, double* hgn, hipStream_t s) {
+  const int n = (d.N + 1) * d.nm;
+  hipLaunchKernelGGL(assemble_h_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, S, cfields, Dc, kx, kz, sbuf,
+                     hy, hgn);
+}
+
+// ---------------------------------------------------------------- RHS
+// CNAB2 right-hand sides at interior rows (the solve works on rows 1..N-1):
+//   phi: (1/dt - nu k^2/2) phi + nu/2 D2 phi + 3/2 h_v - 1/2 h_v^old
+//   U  : U/dt + nu/2 D2 U + 3/2 H_x - 1/2 H_x^old        (mean slot of phi)
+//   g  : as phi with h_g, W in the mean slot (3D)
+//   c  : (1/dt - 1/(2Wi) - kappa k^2/2) c + kappa/2 D2 c + 3/2 F - 1/2 F^old
+//        + delta/Wi (mean slot) + kappa/2 (D2_i0 c_0^new + D2_iN c_N^new)
+// and the new wall rows of c (kappa = 0 there):
+//   c_B^new = ((1/dt - 1/(2Wi)) c_B + 3/2 F_B - 1/2 F_B^old + delta/Wi) / (1/dt + 1/(2Wi)).
+// Each thread recomputes the two wall values of its mode, so no thread
+// writes anything another thread reads.
+// Buffers: sbuf (mean slot = H_x), Ds = D sbuf, hy, hgn (3D), S = projected
+// explicit terms [N_x N_y (N_z) F...], D2buf = [D2 phi, (D2 g), D2 c...] then
+// D2U (N+1) and D2W (N+1).  Outputs: R [nsolve][N-1 rows], hvn (new h_v),
+// CB [nc][2 walls][cw].
+__global__ void rhs_kernel(Dims d, Phys p, const double* __restrict__ st, const double* __restrict__ D2buf,
+                           const double* __restrict__ sbuf, const double* __restrict__ Ds,
+                           const double* __restrict__ hy, const double* __restrict__ hgn,
+                           const double* __restrict__ S, const double* __restrict__ kx,
+                           const double* __restrict__ kz, const double* __restrict__ d2i0,
+                           const double* __restrict__ d2in, double* __restrict__ R, double* __restrict__ hvn,
+                           double* __restrict__ CB) {
+  const int n1 = d.N + 1, N = d.N, ni = d.N - 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n1 * d.nm) return;
+  const Layout L(d.dim, d.nc);
+  Mode m = decode(d, e, kx, kz);
+  const int j = m.j;
+  const bool inter = (j > 0 && j < N);
+  const size_t fs = (size_t)n1 * d.cw, fsi = (size_t)ni * d.cw;
+  const size_t off = (size_t)j * d.cw + 2 * m.mode;
+  const size_t offi = (size_t)(j - 1) * d.cw + 2 * m.mode;
+  const size_t off0 = 2 * (size_t)m.mode, offN = (size_t)N * d.cw + 2 * m.mode;
+  const double dt = p.dt, nu = p.nu;
+  if (m.nyq) {
+    st2(hvn, off, cd{0, 0});
+    if (inter)
+      for (int f = 0; f < L.nsolve; ++f) st2(R, f * fsi + offi, cd{0, 0});
+    if (!inter)
+      for (int a = 0; a < d.nc; ++a) st2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode, cd{0, 0});
+    return;
+  }
+  const double* D2U = D2buf + (size_t)L.nsolve * fs;
+  const double* D2W = D2U + n1;
+  // new h_v
+  cd hv = m.mean ? cd{ld2(sbuf, off).r, 0} : cd{0, 0} - ld2(Ds, off) - m.k2 * ld2(hy, off);
+  st2(hvn, off, hv);
+  if (inter) {
+    cd r;
+    const cd hvo = ld2(st, (size_t)L.H_HV * fs + off);
+    if (m.mean) {
+      const double U = st[(size_t)L.F_U * fs + off];
+      r = cd{U / dt + 0.5 * nu * D2U[j] + 1.5 * hv.r - 0.5 * hvo.r, 0};
+    } else {
+      const cd ph = ld2(st, (size_t)L.F_PHI * fs + off);
+      r = (1.0 / dt - 0.5 * nu * m.k2) * ph + (0.5 * nu) * ld2(D2buf, 0 * fs + off) + 1.5 * hv - 0.5 * hvo;
+    }
+    st2(R, 0 * fsi + offi, r);
+    if (d.dim == 3) {
+      const cd hg = ld2(hgn, off), hgo = ld2(st, (size_t)L.H_HG * fs + off);
+      if (m.mean) {
+        const double W = st[(size_t)L.F_W * fs + off];
+        r = cd{W / dt + 0.5 * nu * D2W[j] + 1.5 * hg.r - 0.5 * hgo.r, 0};
+      } else {
+        const cd g = ld2(st, (size_t)L.F_G * fs + off);
+        r = (1.0 / dt - 0.5 * nu * m.k2) * g + (0.5 * nu) * ld2(D2buf, 1 * fs + off) + 1.5 * hg - 0.5 * hgo;
+      }
+      st2(R, 1 * fsi + offi, r);
+    }
+  }
+  const double a_int = 1.0 / dt - 0.5 / p.wi, a_new = 1.0 / dt + 0.5 / p.wi;
+  for (int a = 0; a < d.nc; ++a) {
+    const double* cf = st + (size_t)(L.F_C + a) * fs;
+    const double* Fn = S + (size_t)(L.S_F + a) * fs;
+    const double* Fo = st + (size_t)(L.H_F + a) * fs;
+    const bool diag = (d.dim == 2) ? (a == 0 || a == 2) : (a == 0 || a == 3 || a == 5);
+    const cd src = cd{(m.mean && diag) ? 1.0 / p.wi : 0.0, 0};
+    const cd cb0 = (1.0 / a_new) * (a_int * ld2(cf, off0) + 1.5 * ld2(Fn, off0) - 0.5 * ld2(Fo, off0) + src);
+    const cd cbN = (1.0 / a_new) * (a_int * ld2(cf, offN) + 1.5 * ld2(Fn, offN) - 0.5 * ld2(Fo, offN) + src);
+    if (inter) {
+      cd r = (a_int - 0.5 * p.kappa * m.k2) * ld2(cf, off) + (0.5 * p.kappa) * ld2(D2buf, (L.nsv + a) * fs + off) +
+             1.5 * ld2(Fn, off) - 0.5 * ld2(Fo, off) + src;
+      if (p.kappa > 0) r = r + (0.5 * p.kappa) * (d2i0[j - 1] * cb0 + d2in[j - 1] * cbN);
+      st2(R, (size_t)(L.nsv + a) * fsi + offi, r);
+    } else {
+      st2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode, j == 0 ? cb0 : cbN);
+    }
+  }
+}
+
+void launch_rhs(const Dims& d, const Phys& p, const double* state, const double* D2buf, const double* sbuf,
+                const double* Ds, const double* hy, const double* hgn, const double* S, const double* kx,
+                const double* kz, const double* d2i0, const double* d2in, double* R, double* hvn, double* CB,
+                hipStream_t s) {
+  const int n = (d.N + 1) * d.nm;
+  hipLaunchKernelGGL(rhs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, state, D2buf, sbuf, Ds, hy, hgn, S,
+                     kx, kz, d2i0, d2in, R, hvn, CB);
+}
+
+// ---------------------------------------------------------------- eigen-space scaling
+// With D2_II = V diag(lam) V^-1 each Dirichlet Helmholtz operator
+// (alpha - gamma D2_II) is diagonal in X = V^-1 R:
+//   phi (and U in the mean slot): X / (1/dt + nu k^2/2 - nu/2 lam)
+//   v from lap v = phi:            (X / (...)) / (lam - k^2)
+//   g  (and W):                    X / (1/dt + nu k^2/2 - nu/2 lam)
+//   c:                             X / (1/dt + 1/(2Wi) + kappa k^2/2 - kappa/2 lam)
+// Xs order: phi, v, (g), c...
+__global__ void eigscale_kernel(Dims d, Phys p, const double* __restrict__ X, double* __restrict__ Xs,
+                                const double* __restrict__ lam, const double* __restrict__ kx,
+                                const double* __restrict__ kz) {
+  const int ni = d.N - 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ni * d.nm) return;
+  const Layout L(d.dim, d.nc);
+  Mode m = decode(d, e, kx, kz);  // m.j is the eigen index here
+  const double le = lam[m.j];
+  const size_t fsi = (size_t)ni * d.cw;
+  const size_t off = (size_t)m.j * d.cw + 2 * m.mode;
+  const double aphi = 1.0 / p.dt + 0.5 * p.nu * m.k2 - 0.5 * p.nu * le;
+  cd x = ld2(X, off);
+  cd xp = (1.0 / aphi) * x;
+  st2(Xs, 0 * fsi + off, xp);
+  st2(Xs, 1 * fsi + off, m.mean ? cd{0, 0} : (1.0 / (le - m.k2)) * xp);
+  int o = 2;
+  if (d.dim == 3) {
+    st2(Xs, 2 * fsi + off, (1.0 / aphi) * ld2(X, 1 * fsi + off));
+    o = 3;
+  }
+  const double ac = 1.0 / p.dt + 0.5 / p.wi + 0.5 * p.kappa * m.k2 - 0.5 * p.kappa * le;
+  for (int a = 0; a < d.nc; ++a) st2(Xs, (size_t)(o + a) * fsi + off, (1.0 / ac) * ld2(X, (size_t)(L.nsv + a) * fsi + off));
+}
+
+void launch_eigscale(const Dims& d, const Phys& p, const double* X, double* Xs, const double* lam, const double* kx,
+                     const double* kz, hipStream_t s) {
+  const int n = (d.N - 1) * d.nm;
+  hipLaunchKernelGGL(eigscale_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, X, Xs, lam, kx, kz);
+}
+
+// ---------------------------------------------------------------- finalize
+// Influence-matrix correction, flux constraint, u and w, c wall rows and the
+// history update.  Per mode (kx, kz) != 0, with particular solutions phi_p,
+// v_p (zero at the walls) and precomputed homogeneous pairs (phi_1, v_1),
+// (phi_2, v_2) (phi_1 = 1 at y = +1, phi_2 = 1 at y = -1):
+//   [a b]^T = -A^-1 [(D v_p)(+1), (D v_p)(-1)]^T,  A = [[Dv_1, Dv_2] at +1; at -1]
+//   phi = phi_p + a phi_1 + b phi_2,  v = v_p + a v_1 + b v_2
+//   u = (i kx Dv - i kz g)/k^2,  w = (i kz Dv + i kx g)/k^2
+// Mean mode: U = U_p + Pi U_1 with Pi = (Q - w.U_p)/(w.U_1) (constant flux)
+// or Pi = dp/dx (constant drive); W = g's mean slot (then cleared).
+// infl layout: [phi1 phi2 v1 v2 Dv1 Dv2][N+1][nm], then Ainv [4][nm].
+__global__ void finalize_kernel(Dims d, Phys p, const double* __restrict__ Zphi, const double* __restrict__ Zv,
+                                const double* __restrict__ ZDv, const double* __restrict__ flux,
+                                const double* __restrict__ infl, const double* __restrict__ U1, double wU1,
+                                const double* __restrict__ CB, const double* __restrict__ hvn,
+                                const double* __restrict__ hgn, const double* __restrict__ S,
+                                const double* __restrict__ kx, const double* __restrict__ kz,
+                                double* __restrict__ st, DevScalars* __restrict__ sc) {
+  const int n1 = d.N + 1, N = d.N;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n1 * d.nm) return;
+  const Layout L(d.dim, d.nc);
+  Mode m = decode(d, e, kx, kz);
+  const int j = m.j;
+  const bool inter = (j > 0 && j < N);
+  const size_t fs = (size_t)n1 * d.cw;
+  const size_t off = (size_t)j * d.cw + 2 * m.mode;
+  const size_t offi = (size_t)(j - 1) * d.cw + 2 * m.mode;
+  // history: h_v, h_g, F <- this step's explicit terms
+  st2(st, (size_t)L.H_HV * fs + off, ld2(hvn, off));
+  if (d.dim == 3) st2(st, (size_t)L.H_HG * fs + off, ld2(hgn, off));
+  for (int a = 0; a < d.nc; ++a) st2(st, (size_t)(L.H_F + a) * fs + off, ld2(S, (size_t)(L.S_F + a) * fs + off));
+  // c wall rows (interior rows were written by the solve product)
+  if (!inter)
+    for (int a = 0; a < d.nc; ++a)
+      st2(st, (size_t)(L.F_C + a) * fs + off, ld2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode));
+  if (m.nyq) {
+    for (int f = 0; f < L.nq; ++f) st2(st, (size_t)f * fs + off, cd{0, 0});
+    return;
+  }
+  if (m.mean) {
+    const double Up = inter ? Zphi[offi] : 0.0;
+    const double pi = (p.forcing == 0) ? (p.q_or_dpdx - flux[0]) / wU1 : p.q_or_dpdx;
+    if (e == 0) sc->pi = pi;
+    st2(st, (size_t)L.F_U * fs + off, cd{Up + pi * U1[j], 0});
+    st2(st, (size_t)L.F_V * fs + off, cd{0, 0});
+    st2(st, (size_t)L.F_PHI * fs + off, cd{0, 0});
+    if (d.dim == 3) {
+      const double W = st[(size_t)L.F_G * fs + off];  // interior rows from the solve, walls zero
+      st2(st, (size_t)L.F_W * fs + off, cd{inter ? W : 0.0, 0});
+      st2(st, (size_t)L.F_G * fs + off, cd{0, 0});
+    }
+    return;
+  }
+  const size_t pm = (size_t)n1 * d.nm;
+  const size_t io = (size_t)j * d.nm + m.mode;
+  const double* Ai = infl + 6 * pm;
+  const double a00 = Ai[0 * d.nm + m.mode], a01 = Ai[1 * d.nm + m.mode];
+  const double a10 = Ai[2 * d.nm + m.mode], a11 = Ai[3 * d.nm + m.mode];
+  const cd dp0 = ld2(ZDv, 2 * (size_t)m.mode), dpN = ld2(ZDv, (size_t)N * d.cw + 2 * m.mode);
+  const cd a = cd{0, 0} - (a00 * dp0 + a01 * dpN);
+  const cd b = cd{0, 0} - (a10 * dp0 + a11 * dpN);
+  const double phi1 = infl[0 * pm + io], phi2 = infl[1 * pm + io];
+  const double v1 = infl[2 * pm + io], v2 = infl[3 * pm + io];
+  const double Dv1 = infl[4 * pm + io], Dv2 = infl[5 * pm + io];
+  const cd php = inter ? ld2(Zphi, offi) : cd{0, 0};
+  const cd vp = inter ? ld2(Zv, offi) : cd{0, 0};
+  const cd phi = php + phi1 * a + phi2 * b;
+  const cd v = vp + v1 * a + v2 * b;
+  const cd Dv = ld2(ZDv, off) + Dv1 * a + Dv2 * b;
+  st2(st, (size_t)L.F_PHI * fs + off, phi);
+  st2(st, (size_t)L.F_V * fs + off, v);
+  const double ik2 = 1.0 / m.k2;
+  if (d.dim == 2) {
+    st2(st, (size_t)L.F_U * fs + off, ik2 * ik(m.kx, Dv));
+  } else {
+    // g: interior rows come from the solve product, wall rows are zero
+    const cd g = inter ? ld2(st, (size_t)L.F_G * fs + off) : cd{0, 0};
+    if (!inter) st2(st, (size_t)L.F_G * fs + off, cd{0, 0});
+    st2(st, (size_t)L.F_U * fs + off, ik2 * (ik(m.kx, Dv) - ik(m.kz, g)));
+    st2(st, (size_t)L.F_W * fs + off, ik2 * (ik(m.kz, Dv) + ik(m.kx, g)));
+  }
+}
+
+void launch_finalize(const Dims& d, const Phys& p, const double* Zphi, const double* Zv, const double* ZDv,
+                     const double* flux, const double* infl, const double* U1, double wU1, const double* CB,
+                     const double* hvn, const double* hgn, const double* S, const double* kx, const double* kz,
+                     double* state, DevScalars* sc, hipStream_t s) {
+  const int n = (d.N + 1) * d.nm;
+  hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, Zphi, Zv, ZDv, flux, infl, U1,
+                     wU1, CB, hvn, hgn, S, kx, kz, state, sc);
+}
+
+// ---------------------------------------------------------------- init: homogeneous solutions
+// Right-hand side whose solve yields phi_1 + i phi_2 in every mode's phi slot:
+// interior rows of (alpha - nu/2 D2) phi = 0 with phi(+1) = 1 (real part) or
+// phi(-1) = 1 (imaginary part) move the wall column to the right:
+//   R = nu/2 (D2_i0 + i D2_iN).   Mean slot: R = 1 (gives U_1).
+__global__ void homog_rhs_kernel(Dims d, Phys p, const double* __restrict__ d2i0, const double* __restrict__ d2in,
+                                 double* __restrict__ R) {
+  const int ni = d.N - 1;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= ni * d.nm) return;
+  const int j = e / d.nm, mode = e - j * d.nm;
+  const size_t off = (size_t)j * d.cw + 2 * mode;
+  if (mode == 0) {
+    R[off] = 1.0;
+    R[off + 1] = 0.0;
+  } else {
+    R[off] = 0.5 * p.nu * d2i0[j];
+    R[off + 1] = 0.5 * p.nu * d2in[j];
+  }
+}
+
+void launch_homog_rhs(const Dims& d, const Phys& p, const double* d2i0, const double* d2in, double* R,
+                      hipStream_t s) {
+  const int n = (d.N - 1) * d.nm;
+  hipLaunchKernelGGL(homog_rhs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, d2i0, d2in, R);
+}
+
+// Splits the homogeneous solves into the per-mode influence data and inverts
+// the 2x2 influence matrices.
+__global__ void influence_kernel(Dims d, const double* __restrict__ Zphi, const double* __restrict__ Zv,
+                                 const double* __restrict__ ZDv, const double* __restrict__ kz,
+                                 double* __restrict__ infl, double* __restrict__ U1) {
+  const int n1 = d.N + 1, N = d.N;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n1 * d.nm) return;
+  const int j = e / d.nm, mode = e - j * d.nm;
+  const int iz = mode / d.nkx;
+  const bool nyq = (d.dim == 3) && (iz == d.nzs / 2);
+  const bool inter = (j > 0 && j < N);
+  const size_t pm = (size_t)n1 * d.nm, io = (size_t)j * d.nm + mode;
+  const size_t offi = (size_t)(j - 1) * d.cw + 2 * mode, off = (size_t)j * d.cw + 2 * mode;
+  if (mode == 0) {
+    U1[j] = inter ? Zphi[offi] : 0.0;
+    for (int f = 0; f < 6; ++f) infl[f * pm + io] = 0.0;
+  } else if (nyq) {
+    for (int f = 0; f < 6; ++f) infl[f * pm + io] = 0.0;
+  } else {
+    infl[0 * pm + io] = (j == 0 ? 1.0 : 0.0) + (inter ? Zphi[offi] : 0.0);
+    infl[1 * pm + io] = (j == N ? 1.0 : 0.0) + (inter ? Zphi[offi + 1] : 0.0);
+    infl[2 * pm + io] = inter ? Zv[offi] : 0.0;
+    infl[3 * pm + io] = inter ? Zv[offi + 1] : 0.0;
+    infl[4 * pm + io] = ZDv[off];
+    infl[5 * pm + io] = ZDv[off + 1];
+  }
+  if (j == 0) {
+    double* Ai = infl + 6 * pm;
+    if (mode == 0 || nyq) {
+      Ai[0 * d.nm + mode] = Ai[1 * d.nm + mode] = Ai[2 * d.nm + mode] = Ai[3 * d.nm + mode] = 0.0;
+    } else {
+      const size_t oN = (size_t)N * d.cw + 2 * mode, o0 = 2 * (size_t)mode;
+      const double A00 = ZDv[o0], A01 = ZDv[o0 + 1], A10 = ZDv[oN], A11 = ZDv[oN + 1];
+      const double det = A00 * A11 - A01 * A10;
+      Ai[0 * d.nm + mode] = A11 / det;
+      Ai[1 * d.nm + mode] = -A01 / det;
+      Ai[2 * d.nm + mode] = -A10 / det;
+      Ai[3 * d.nm + mode] = A00 / det;
+    }
+  }
+}
+
+void launch_influence(const Dims& d, const double* Zphi, const double* Zv, const double* ZDv, const double* kz,
+                      double* infl, double* U1, hipStream_t s) {
+  const int n = (d.N + 1) * d.nm;
+  hipLaunchKernelGGL(influence_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, Zphi, Zv, ZDv, kz, infl, U1);
+}
+
+}  // namespace pcs

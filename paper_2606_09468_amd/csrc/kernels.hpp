@@ -1,0 +1,119 @@
+// Internal interface between the C-ABI layer (api.cpp) and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace pcs {
+
+// One dense product C = alpha * A * B + beta * C, all row-major, real.
+// Complex fields (re/im interleaved) are multiplied by a real operator by
+// treating each complex column as two real columns.
+template <typename T>
+struct GemmJob {
+  const T* A;
+  const T* B;
+  T* C;
+  int m, n, k, lda, ldb, ldc;
+  T alpha, beta;
+  int tiles_m, tile0;  // filled by gemm_prepare
+};
+
+constexpr int GEMM_BM = 64, GEMM_BN = 64, GEMM_BK = 16;
+constexpr int MAX_JOBS = 64;
+
+// Fills tiles_m / tile0 and returns the total number of tiles.
+template <typename T>
+int gemm_prepare(GemmJob<T>* jobs, int njobs);
+void gemm_f64(const GemmJob<double>* dev_jobs, int total_tiles, int njobs, hipStream_t s);
+void gemm_f32(const GemmJob<float>* dev_jobs, int total_tiles, int njobs, hipStream_t s);
+
+// Mixed-radix (4, 2, 3) Stockham plan for a length L = 2^a 3^b.
+struct FftPlan {
+  int L = 0;
+  int npass = 0;
+  int radix[12] = {0};
+};
+bool make_plan(int L, FftPlan* p);
+
+// Problem description shared by the elementwise kernels.
+struct Dims {
+  int dim;          // 2 or 3
+  int N, M;         // Ny - 1 and 3N/2
+  int nkx, nzs;     // retained kx, kz slots (Nz or 1)
+  int nm;           // nzs * nkx (complex modes per y row)
+  int cw;           // 2 * nm (real columns per y row)
+  int px, pz;       // padded x / z points
+  int nx, nz;       // base x / z points
+  int nc;           // conformation components (3 or 6)
+  double lx, lz;
+};
+
+struct Phys {
+  double re, wi, beta, kappa, eps, dt;
+  int forcing;
+  double q_or_dpdx;
+  double coef;      // (1 - beta)/(Re Wi)
+  double nu;        // beta / Re
+};
+
+// Device-resident scalars advanced by the step itself.
+struct DevScalars {
+  long long step;
+  double t;
+  double pi;
+  int blowup;
+  int pad;
+};
+
+struct DiagRec {
+  long long step;
+  double t, min_trc, mid_min_trc, cfl, dpdx, energy, mean_trc;
+  unsigned long long n_lt3, n_lt0, mid_n_lt3, mid_n_lt0;
+  int blowup, reserved;
+};
+
+// Per y-row partial reductions written by the diagnostics kernels.
+struct DiagPart {
+  double min_trc, cfl, esum, tsum;
+  unsigned long long n_lt3, n_lt0;
+  int nonfinite, big;
+};
+
+// ---- launchers (fft.hip)
+void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const double* yin, double* yout,
+                    const double* kx, const double* tw, hipStream_t s);
+void launch_xpencil3d(const Dims& d, const Phys& p, const FftPlan& plan, const double* zin, double* zout,
+                      const double* kx, const double* tw, hipStream_t s);
+void launch_zfft(const Dims& d, const FftPlan& plan, const double* in, double* out, int nfields,
+                 const int* src_field, const int* deriv, const double* kz, const double* tw, int inverse, int rows,
+                 hipStream_t s);
+void launch_diag_rows(const Dims& d, const Phys& p, const FftPlan& planx, const double* st, double* prep,
+                      double* zbuf, const FftPlan& planz, const double* twx, const double* twz, const double* ydy,
+                      DiagPart* parts, hipStream_t s);
+void launch_diag_final(const Dims& d, const Phys& p, const DiagPart* parts, const double* w, DevScalars* sc,
+                       DiagRec* ring, int ring_cap, hipStream_t s);
+// Raises the dynamic-LDS limit of the transform kernels (call once, outside capture).
+hipError_t fft_set_attributes();
+size_t xpencil_lds_bytes(int dim, int L);
+
+// ---- launchers (elem.hip)
+void launch_assemble_h(const Dims& d, const Phys& p, const double* S, const double* cfields, const double* Dc,
+                       const double* kx, const double* kz, double* sbuf, double* hy, double* hgn, hipStream_t s);
+void launch_rhs(const Dims& d, const Phys& p, const double* state, const double* D2buf, const double* sbuf,
+                const double* Ds, const double* hy, const double* hgn, const double* S, const double* kx,
+                const double* kz, const double* d2i0, const double* d2in, double* R, double* hvn, double* CB,
+                hipStream_t s);
+void launch_eigscale(const Dims& d, const Phys& p, const double* X, double* Xs, const double* lam, const double* kx,
+                     const double* kz, hipStream_t s);
+void launch_finalize(const Dims& d, const Phys& p, const double* Zphi, const double* Zv, const double* ZDv,
+                     const double* flux, const double* infl, const double* U1, double wU1, const double* CB,
+                     const double* hvn, const double* hgn, const double* S, const double* kx, const double* kz,
+                     double* state, DevScalars* sc, hipStream_t s);
+void launch_homog_rhs(const Dims& d, const Phys& p, const double* d2i0, const double* d2in, double* R,
+                      hipStream_t s);
+void launch_influence(const Dims& d, const double* Zphi, const double* Zv, const double* ZDv, const double* kz,
+                      double* infl, double* U1, hipStream_t s);
+
+}  // namespace pcs
