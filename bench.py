@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Throughput of the polymer channel-flow step on one MI355X.
+
+Workload (default): 2D channel, Oldroyd-B, Lx = 10, Nx = 256 Fourier points,
+Ny = 257 Chebyshev points, Re = 0.01, Wi = 50, beta = 0.8, kappa = 5e-5,
+constant flux, CNAB2 with dt = 5e-4; laminar state plus the seeded
+perturbation (seed 2, amplitude 1e-3).  A step is one full time step
+(explicit products, solves and the per-step diagnostics), replayed as one
+HIP graph.  Prints one JSON line.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time steps/s and grid-point-updates/s, mixed vs FP64 at stated error, 1 GPU"
+HBM_PEAK_GBS = 8000.0
+MFMA_F64_TFS = 78.6
+MFMA_F32_TFS = 157.3
+
+WORKLOADS = {
+    "c2": dict(desc="2D channel Oldroyd-B, Lx=10, Nx=256, Ny=257, Re=0.01, Wi=50, beta=0.8, kappa=5e-5, "
+                    "constant flux, CNAB2 dt=5e-4, seeded perturbation amp 1e-3 (seed 2)",
+               dim=2, nx=256, ny=257, nz=1, lz=5.0, wi=50.0, dt=5e-4, seed=2),
+    "c1": dict(desc="2D channel Oldroyd-B, Lx=10, Nx=64, Ny=65, Re=0.01, Wi=20, beta=0.8, kappa=5e-5, "
+                    "constant flux, CNAB2 dt=1e-3, seeded perturbation amp 1e-3 (seed 1)",
+               dim=2, nx=64, ny=65, nz=1, lz=5.0, wi=20.0, dt=1e-3, seed=1),
+    "c3": dict(desc="3D channel Oldroyd-B, Lx=10, Lz=5, Nx=128, Ny=129, Nz=64, Re=0.01, Wi=50, beta=0.8, "
+                    "kappa=5e-5, constant flux, CNAB2 dt=5e-4, seeded perturbation amp 1e-3 (seed 3)",
+               dim=3, nx=128, ny=129, nz=64, lz=5.0, wi=50.0, dt=5e-4, seed=3),
+    "c5": dict(desc="3D channel Oldroyd-B, Lx=10, Lz=5, Nx=256, Ny=257, Nz=128, Re=0.01, Wi=100, beta=0.8, "
+                    "kappa=5e-5, constant flux, CNAB2 dt=2.5e-4, seeded perturbation amp 1e-3 (seed 5)",
+               dim=3, nx=256, ny=257, nz=128, lz=5.0, wi=100.0, dt=2.5e-4, seed=5),
+}
+
+
+def stage_work(w, prec_bytes=16):
+    """Algorithmic work of one launch of each stage: ('hbm', bytes) for the
+    transform / elementwise stages (each input read once, each output written
+    once, complex values of prec_bytes), ('mfma', flops) for the products."""
+    dim, nx, ny, nz = w["dim"], w["nx"], w["ny"], w["nz"]
+    N = ny - 1
+    n1, m1, ni = N + 1, 3 * N // 2 + 1, N - 1
+    nkx = nx // 2
+    nzs = 1 if dim == 2 else nz
+    pz = 1 if dim == 2 else 3 * nz // 2
+    nm = nkx * nzs
+    cw = 2 * nm
+    nc = 3 if dim == 2 else 6
+    nvel = dim
+    nsolve = (1 if dim == 2 else 2) + nc
+    nout = 5 if dim == 2 else 9
+    nyin = 9 if dim == 2 else 17
+    cplx = prec_bytes
+    out = {}
+    g1 = (nvel + nc + (1 if dim == 2 else 2) + nc) * 2 * m1 * cw * n1     # I and D to the padded grid
+    g1 += nsolve * 2 * n1 * cw * n1 + (dim - 1) * 2 * n1 * n1             # D2 of phi, g, c and U, W
+    g1 += (2 if dim == 2 else 3) * 2 * n1 * cw * n1                       # D of c_y.
+    out["gemm_state"] = ("mfma", g1)
+    if dim == 3:
+        out["zfft_inv"] = ("hbm", (nyin * m1 * nzs * nkx + 26 * m1 * pz * nkx) * cplx)
+        out["xpencil"] = ("hbm", (26 + nout) * m1 * pz * nkx * cplx)
+        out["zfft_fwd"] = ("hbm", (nout * m1 * pz * nkx + nout * m1 * nzs * nkx) * cplx)
+    else:
+        out["xpencil"] = ("hbm", (nyin + nout) * m1 * nkx * cplx)
+    out["gemm_proj"] = ("mfma", nout * 2 * n1 * cw * m1)
+    out["gemm_ds"] = ("mfma", 2 * n1 * cw * n1)
+    out["gemm_vinv"] = ("mfma", nsolve * 2 * ni * cw * ni)
+    out["gemm_v"] = ("mfma", (nsolve + 1) * 2 * ni * cw * ni + 2 * n1 * cw * ni + 2 * cw * ni)
+    return out
+
+
+def cpu_baseline(w, sample_steps):
+    from threadpoolctl import threadpool_info
+
+    from oracle import Grid, Oracle, Params
+    g = Grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
+    prm = Params(wi=w["wi"], dt=w["dt"])
+    t0 = time.perf_counter()
+    o = Oracle(g, prm, seed=w["seed"], amp=1e-3)
+    o.step(1)           # builds the per-wavenumber LU factors
+    t1 = time.perf_counter()
+    o.step(sample_steps)
+    t2 = time.perf_counter()
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return o, dict(value=sample_steps / (t2 - t1), unit="steps/s", cores=threads, kind="oracle",
+                   sample="%d steps of the same workload after 1 warm-up step (setup %.1f s excluded), "
+                          "NumPy/SciPy FP64 on the host CPU" % (sample_steps, t1 - t0))
+
+
+def state_errors(a, b, w):
+    import numpy as np
+
+    from oracle import Grid, state_layout
+    g = Grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
+    hdr, names, per = state_layout(g)
+    errs, o = {}, hdr
+    for n in names:
+        x, y = a[o:o + 2 * per], b[o:o + 2 * per]
+        sc = np.abs(y).max()
+        errs[n] = float(np.abs(x - y).max() / sc) if sc > 0 else float(np.abs(x).max())
+        o += 2 * per
+    return errs
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--stage-steps", type=int, default=50)
+    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (each run, or each ensemble "
+              "member, would be sharded across GPUs without communication); run with --gpus 1.",
+              file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2606_09468_amd as P
+    if not os.path.exists(P.LIBPATH):
+        from paper_2606_09468_amd import build
+        build.build()
+    w = WORKLOADS[args.workload]
+    grid = P.make_grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
+    prm = P.make_params(wi=w["wi"], dt=w["dt"], precision=0)
+    sim = P.Sim(grid, prm, seed=w["seed"], amp=1e-3)
+    print("bench: %s, warmup %d" % (args.workload, args.warmup), file=sys.stderr, flush=True)
+    sim.step(args.warmup)
+    sim.diagnostics()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(sim.stream)
+    sim.step(args.steps)
+    ev1.record(sim.stream)
+    ev1.synchronize()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms = ev0.elapsed_time(ev1)
+    recs, st = sim.diagnostics()
+    assert st == P.PCS_OK and len(recs) == min(args.steps, 4096) and recs[-1]["blowup"] == 0
+    sps = args.steps / (ms / 1e3)
+    print("bench: timed %d steps in %.3f ms (wall %.3f s)" % (args.steps, ms, wall), file=sys.stderr, flush=True)
+    # per-stage durations (eager launches, HIP events on the run's stream)
+    stages = sim.stage_times(args.stage_steps)
+    sim.close()
+    work = stage_work(w)
+    dom = max((k for k in stages if k in work), key=lambda k: stages[k])
+    kind, amount = work[dom]
+    t = stages[dom] * 1e-3
+    if kind == "hbm":
+        roof = dict(kernel=dom, bound="hbm", achieved=amount / t / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
+                    traffic=None, algorithmic_bytes=amount, avg_ms=stages[dom])
+    else:
+        roof = dict(kernel=dom, bound="mfma", achieved=amount / t / 1e12, peak=MFMA_F64_TFS, unit="TFLOP/s",
+                    traffic=None, algorithmic_flops=amount, avg_ms=stages[dom])
+    roof["frac"] = roof["achieved"] / roof["peak"]
+    points = w["nx"] * w["ny"] * w["nz"]
+    line = {
+        "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": w["desc"], "grid": [w["nx"], w["ny"], w["nz"]], "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "grid_point_updates_per_s": sps * points,
+        "roofline": roof,
+        "stage_ms": stages,
+    }
+    if not args.no_cpu_baseline:
+        print("bench: oracle sample of %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
+        o, cb = cpu_baseline(w, args.cpu_steps)
+        line["cpu_baseline"] = cb
+        # error of the GPU step against the oracle over the same sample
+        sim2 = P.Sim(grid, prm, seed=w["seed"], amp=1e-3)
+        sim2.step(args.cpu_steps + 1)
+        a = sim2.get_state()
+        recs2, _ = sim2.diagnostics()
+        sim2.close()
+        errs = state_errors(a, o.get_state(), w)
+        d, e = recs2[-1], o.diag[-1]
+        line["error_vs_oracle"] = {
+            "steps": args.cpu_steps + 1,
+            "max_rel_velocity": max(errs[k] for k in errs if k in ("u", "v", "w", "phi", "g")),
+            "max_rel_conformation": max(errs[k] for k in errs if k.startswith("c")),
+            "min_trc_abs": abs(d["min_trc"] - e["min_trc"]),
+            "counts_equal": all(d[k] == e[k] for k in ("n_lt3", "n_lt0", "mid_n_lt3", "mid_n_lt0")),
+        }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

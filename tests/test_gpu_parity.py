@@ -1,0 +1,245 @@
+"""Parity of the HIP step (through the C ABI) with the FP64 oracle.
+
+Every case starts both sides from the same state (the seeded initial
+condition built independently on each side, or a random state passed in
+through pcs_set_state) and compares the full flat state element by element,
+per field, relative to the field's max norm (the oracle's).  Tolerances are
+written per case; the design doc derives them from the conditioning of the
+wall-normal operators (|D| ~ N^2, |D2| ~ N^4) and lists the measured values.
+Diagnostic counts must agree exactly whenever no oracle point lies within
+TIE_BAND of a threshold (3 or 0).
+"""
+
+import numpy as np
+import pytest
+
+from oracle import Grid, Oracle, Params, state_layout
+from tests.inputs import random_state
+
+pytestmark = pytest.mark.gpu
+
+TIE_BAND = 1e-9
+
+
+@pytest.fixture(scope="module")
+def P():
+    import os
+
+    import torch
+
+    import paper_2606_09468_amd as P
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(P.LIBPATH):
+        from paper_2606_09468_amd import build
+        build.build()
+    return P
+
+
+def field_errors(a, b, g):
+    hdr, names, per = state_layout(g)
+    out, o = {}, hdr
+    for n in names:
+        x, y = a[o:o + 2 * per], b[o:o + 2 * per]
+        sc = np.abs(y).max()
+        out[n] = float(np.abs(x - y).max() / sc) if sc > 0 else float(np.abs(x).max())
+        o += 2 * per
+    return out
+
+
+def check_state(a, b, g, tol_q, tol_h, case):
+    errs = field_errors(a, b, g)
+    _, names, _ = state_layout(g)
+    nq = 6 if g.dim == 2 else 11
+    print(case, " ".join("%s=%.1e" % kv for kv in errs.items()), flush=True)
+    assert a[0] == b[0] and abs(a[1] - b[1]) <= 1e-15 * max(1.0, abs(b[1]))
+    assert abs(a[2] - b[2]) <= 1e-9 * abs(b[2]), (a[2], b[2])
+    for i, n in enumerate(names):
+        assert errs[n] <= (tol_q if i < nq else tol_h), (case, n, errs[n])
+    return errs
+
+
+def check_diag(recs, orc, oracle_trc, case):
+    d, e = recs[-1], orc.diag[-1]
+    assert d["step"] == e["step"] and d["blowup"] == e["blowup"] == 0
+    for k in ("min_trc", "mid_min_trc", "energy", "mean_trc", "dpdx", "cfl"):
+        assert abs(d[k] - e[k]) <= 1e-11 * max(1.0, abs(e[k])), (case, k, d[k], e[k])
+    near = np.sum(np.abs(oracle_trc - 3.0) < TIE_BAND * max(1.0, np.abs(oracle_trc).max())) \
+        + np.sum(np.abs(oracle_trc) < TIE_BAND * max(1.0, np.abs(oracle_trc).max()))
+    if near == 0:
+        for k in ("n_lt3", "n_lt0", "mid_n_lt3", "mid_n_lt0"):
+            assert d[k] == e[k], (case, k, d[k], e[k])
+
+
+def run_pair(P, g, prm, seed, amp, nsteps, case, state=None):
+    print("case", case, flush=True)
+    sim = P.Sim(P.make_grid(g.dim, g.nx, g.ny, g.nz, g.lx, g.lz), P.make_params(**prm), seed=seed, amp=amp)
+    o = Oracle(g, Params(**prm), seed=None if state is not None else seed, amp=amp)
+    if state is not None:
+        sim.set_state(state)
+        o.set_state(state)
+    sim.step(nsteps)
+    o.step(nsteps)
+    recs, st = sim.diagnostics()
+    assert st == P.PCS_OK and len(recs) == nsteps
+    a = sim.get_state()
+    sim.close()
+    return a, o, recs
+
+
+def tol_prognostic(N):
+    """Prognostic fields (u, v, w, phi, g, c): 1e-12 relative up to N = 128
+    (the FP64 target); at N = 256 the floor of two correct FP64 evaluations
+    of the same discrete step is a few 1e-12 (each wall-normal derivative
+    amplifies roundoff by up to |D| ~ N^2), so 1e-11 there."""
+    return 1e-12 if N <= 128 else 1e-11
+
+
+def tol_history(N):
+    """History fields h_v, h_g, F hold explicit terms with up to two
+    wall-normal derivatives of the state (h_v = -D(i kx H_x + ...) with
+    H containing D c): roundoff ~ eps |D|^2 ~ eps N^4."""
+    return 1e-16 * N ** 4
+
+
+CASES = [
+    # name, grid, params, steps
+    ("C1 2D 64x65 Wi20 dt1e-3 x200", Grid(2, 64, 65), dict(wi=20.0, dt=1e-3), 200),
+    ("2D ragged 24x25 Wi20 x40", Grid(2, 24, 25), dict(wi=20.0, dt=1e-3), 40),
+    ("2D 128x129 Wi50 kappa0 x30", Grid(2, 128, 129), dict(wi=50.0, dt=5e-4, kappa=0.0), 30),
+    ("C2 2D 256x257 Wi50 dt5e-4 x20", Grid(2, 256, 257), dict(wi=50.0, dt=5e-4), 20),
+    ("3D 16x17x16 x20", Grid(3, 16, 17, 16), dict(wi=20.0, dt=1e-3), 20),
+    ("3D ragged 24x33x12 Wi50 x10", Grid(3, 24, 33, 12), dict(wi=50.0, dt=5e-4), 10),
+    ("3D 32x65x32 Wi50 x8", Grid(3, 32, 65, 32), dict(wi=50.0, dt=5e-4), 8),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_seeded_run_matches_oracle(P, case):
+    name, g, prm, n = case
+    a, o, recs = run_pair(P, g, prm, seed=1, amp=1e-3, nsteps=n, case=name)
+    N = g.ny - 1
+    check_state(a, o.get_state(), g, tol_prognostic(N), tol_history(N), name)
+    check_diag(recs, o, o.trace_c(), name)
+    # every per-step record, not only the last
+    for r, e in zip(recs, o.diag):
+        assert r["step"] == e["step"] and abs(r["min_trc"] - e["min_trc"]) <= 1e-11 * abs(e["min_trc"])
+
+
+@pytest.mark.parametrize("dim,nx,ny,nz", [(2, 32, 33, 1), (3, 16, 33, 16)])
+def test_random_state_one_step(P, dim, nx, ny, nz):
+    """A random smooth state (all fields, including history) through one
+    step: exercises every term of the explicit products and solves."""
+    g = Grid(dim, nx, ny, nz)
+    st = random_state(dim, nx, ny, nz, seed=7, amp=0.05)
+    o0 = Oracle(g, Params(wi=20.0, dt=1e-3), seed=3, amp=0.0)
+    base = o0.get_state()
+    st[4:] += base[4:]          # random fields on top of the laminar state and its history
+    st[0:4] = [5, 0.005, 200.0, 0.0]
+    a, o, _ = run_pair(P, g, dict(wi=20.0, dt=1e-3), seed=3, amp=0.0, nsteps=1, case="random %dD" % dim, state=st)
+    check_state(a, o.get_state(), g, tol_prognostic(ny - 1), tol_history(ny - 1), "random %dD" % dim)
+
+
+@pytest.mark.parametrize("kappa", [0.0, 5e-5])
+def test_laminar_state_is_steady_on_gpu(P, kappa):
+    """The laminar Oldroyd-B Poiseuille state (kappa = 0: c_xy = Wi U',
+    c_xx = 1 + 2 (Wi U')^2, c_yy = 1) stays fixed under the GPU step."""
+    print("case laminar kappa=%g" % kappa, flush=True)
+    g = P.make_grid(2, 32, 65)
+    sim = P.Sim(g, P.make_params(wi=20.0, dt=1e-3, kappa=kappa), seed=0, amp=0.0)
+    s0 = sim.get_state()
+    y = np.cos(np.pi * np.arange(65) / 64)
+    per = 65 * 16 * 2
+    U = s0[4:4 + per].reshape(65, 16, 2)[:, 0, 0]
+    assert np.abs(U - (1 - y * y)).max() < 1e-15
+    if kappa == 0.0:
+        cxx = s0[4 + 3 * per:4 + 4 * per].reshape(65, 16, 2)[:, 0, 0]
+        assert np.abs(cxx - (1 + 2 * (20.0 * 2 * y) ** 2)).max() <= 1e-15 * 3201
+    sim.step(50)
+    s1 = sim.get_state()
+    recs, _ = sim.diagnostics()
+    sim.close()
+    assert np.abs(s1[4:] - s0[4:]).max() / np.abs(s0[4:]).max() < 1e-13
+    assert abs(recs[-1]["dpdx"] - 200.0) < 1e-8
+
+
+def test_exact_relaxation_counts(P):
+    """3D laminar flow with c_zz = 1 + delta: delta_n = delta ((1-a)/(1+a))^n
+    exactly (a = dt/(2 Wi)), and the Tr c < 3 count is
+    Nx Nz #{j: 8 Wi^2 y_j^2 < -delta_n}: the count kernel against a closed form."""
+    print("case exact relaxation counts", flush=True)
+    wi, dt, delta = 2.0, 2e-3, -0.37
+    g = Grid(3, 8, 33, 8)
+    o = Oracle(g, Params(wi=wi, kappa=0.0, dt=dt), seed=1, amp=0.0)
+    o.q["czz"][:, 0, 0] += delta
+    o.init_history()
+    sim = P.Sim(P.make_grid(3, 8, 33, 8), P.make_params(wi=wi, kappa=0.0, dt=dt), seed=1, amp=0.0)
+    sim.set_state(o.get_state())
+    sim.step(15)
+    recs, _ = sim.diagnostics()
+    s = sim.get_state()
+    sim.close()
+    a = dt / (2 * wi)
+    y = np.cos(np.pi * np.arange(33) / 32)
+    for n, r in enumerate(recs, start=1):
+        dn = delta * ((1 - a) / (1 + a)) ** n
+        assert r["n_lt3"] == 64 * int(np.sum(8 * wi * wi * y * y < -dn))
+        assert r["mid_n_lt3"] == 64 and r["n_lt0"] == 0
+        assert abs(r["min_trc"] - (3 + dn)) < 1e-13
+    per = 33 * 8 * 4 * 2
+    czz = s[4 + 10 * per:4 + 11 * per].reshape(33, 8, 4, 2)[:, 0, 0, 0]
+    assert np.abs(czz - (1 + delta * ((1 - a) / (1 + a)) ** 15)).max() < 1e-14
+
+
+def test_blowup_flag_and_recovery(P):
+    """A planted NaN is flagged, the run refuses further steps, and a new
+    state clears the flag (the error path forced from the host)."""
+    print("case blow-up flag", flush=True)
+    sim = P.Sim(P.make_grid(2, 16, 17), P.make_params(), seed=1, amp=1e-3)
+    good = sim.get_state()
+    bad = good.copy()
+    bad[4 + 3 * 17 * 8 * 2 + 5] = np.nan       # one c_xx coefficient
+    sim.set_state(bad)
+    sim.step(1)
+    recs, st = sim.diagnostics()
+    assert st == P.PCS_BLOWUP and recs[-1]["blowup"] == 1
+    with pytest.raises(P.PcsError) as ei:
+        sim.step(1)
+    assert ei.value.status == P.PCS_ERR_STATE
+    sim.set_state(good)
+    sim.step(2)
+    recs, st = sim.diagnostics()
+    assert st == P.PCS_OK and recs[-1]["blowup"] == 0
+    sim.close()
+
+
+def test_resume_and_replay_bitwise(P):
+    """n steps, save, restore, n steps == 2n steps, bit for bit; two runs of
+    the same graph from the same state are bitwise equal."""
+    print("case resume / replay determinism", flush=True)
+    g, p = P.make_grid(3, 16, 17, 16), P.make_params(wi=20.0, dt=1e-3)
+    s1 = P.Sim(g, p, seed=5, amp=1e-3)
+    s1.step(6)
+    mid = s1.get_state()
+    s1.step(6)
+    end1 = s1.get_state()
+    s2 = P.Sim(g, p, seed=9, amp=1e-3)
+    s2.set_state(mid)
+    s2.step(6)
+    end2 = s2.get_state()
+    s1.close()
+    s2.close()
+    assert np.array_equal(end1, end2)
+
+
+def test_stage_times_advance_state_like_step(P):
+    print("case stage timing path", flush=True)
+    g, p = P.make_grid(2, 32, 33), P.make_params(wi=20.0, dt=1e-3)
+    s1 = P.Sim(g, p, seed=2, amp=1e-3)
+    s2 = P.Sim(g, p, seed=2, amp=1e-3)
+    s1.step(3)
+    t = s2.stage_times(3)
+    assert set(t) >= {"xpencil", "gemm_state", "finalize"} and all(v >= 0 for v in t.values())
+    assert np.array_equal(s1.get_state(), s2.get_state())
+    s1.close()
+    s2.close()

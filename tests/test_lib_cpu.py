@@ -1,0 +1,61 @@
+"""Host-side checks of the HIP library that need no GPU: the shared object
+loads, exports every function declared in include/pcs.h, and its host logic
+(workspace sizing, argument validation) behaves as documented."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_2606_09468_amd as P
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    if not os.path.exists(P.LIBPATH):
+        from paper_2606_09468_amd import build
+        build.build()
+    return P.lib()
+
+
+def test_exports_match_header(L):
+    hdr = open(os.path.join(ROOT, "include", "pcs.h")).read()
+    declared = set(re.findall(r"^\s*(?:pcs_status|const char\*)\s+(pcs_\w+)\s*\(", hdr, re.M))
+    assert declared, "no declarations found"
+    assert declared == set(P.EXPORTS)
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_workspace_bytes_and_validation(L):
+    g = P.make_grid(2, 256, 257)
+    p = P.make_params(wi=50.0, dt=5e-4)
+    n = P.pcs_workspace_bytes(g, p)
+    assert 10e6 < n < 100e6
+    g3 = P.make_grid(3, 256, 257, 128)
+    n3 = P.pcs_workspace_bytes(g3, p)
+    assert 1e9 < n3 < 40e9      # resident on one 288 GB device
+    sz = ctypes.c_size_t(0)
+    bad = [P.make_grid(2, 30, 33), P.make_grid(2, 16, 32), P.make_grid(2, 16, 7), P.make_grid(3, 16, 17, 10)]
+    for gb in bad:   # 3*30/2 = 45 (radix 5), even Ny, Ny < 9, 3*10/2 = 15
+        st = L.pcs_workspace_bytes(ctypes.byref(gb), ctypes.byref(p), ctypes.byref(sz))
+        assert st == P.PCS_ERR_UNSUPPORTED, (gb.nx, gb.ny, gb.nz)
+    pb = P.make_params(wi=-1.0)
+    assert L.pcs_workspace_bytes(ctypes.byref(g), ctypes.byref(pb), ctypes.byref(sz)) == P.PCS_ERR_ARG
+    assert L.pcs_workspace_bytes(None, ctypes.byref(p), ctypes.byref(sz)) == P.PCS_ERR_ARG
+    assert L.pcs_step(None, 1) == P.PCS_ERR_ARG
+    assert L.pcs_status_string(P.PCS_ERR_STATE).decode().startswith("run has blown up")
+
+
+def test_init_rejects_bad_workspace(L):
+    g = P.make_grid(2, 16, 17)
+    p = P.make_params()
+    h = ctypes.c_void_p(0)
+    # too small: rejected before any device call
+    st = L.pcs_init(ctypes.byref(g), ctypes.byref(p), 1, 1e-3, ctypes.c_void_p(256), 16, None, ctypes.byref(h))
+    assert st == P.PCS_ERR_WORKSPACE and not h.value
+    st = L.pcs_init(ctypes.byref(g), ctypes.byref(p), 1, 1e-3, None, 1 << 30, None, ctypes.byref(h))
+    assert st == P.PCS_ERR_ARG
