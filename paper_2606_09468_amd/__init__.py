@@ -26,7 +26,9 @@ PCS_ERR_DEVICE = -4
 PCS_ERR_STATE = -5
 
 EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pcs_state_size",
-           "pcs_get_state", "pcs_set_state", "pcs_destroy", "pcs_status_string")
+           "pcs_get_state", "pcs_set_state", "pcs_stage_times", "pcs_destroy", "pcs_status_string",
+           "pcs_stage_name")
+PCS_NSTAGE = 14
 
 
 class pcs_grid(ctypes.Structure):
@@ -68,11 +70,15 @@ def lib():
     L.pcs_state_size.argtypes = [vp, ctypes.POINTER(sz)]
     L.pcs_get_state.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
     L.pcs_set_state.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
+    L.pcs_stage_times.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    L.pcs_stage_name.argtypes = [st]
+    L.pcs_stage_name.restype = ctypes.c_char_p
     L.pcs_destroy.argtypes = [vp]
     L.pcs_status_string.argtypes = [st]
     L.pcs_status_string.restype = ctypes.c_char_p
-    for name in EXPORTS[:-1]:
-        getattr(L, name).restype = st
+    for name in EXPORTS:
+        if name not in ("pcs_status_string", "pcs_stage_name"):
+            getattr(L, name).restype = st
     _lib = L
     return L
 
@@ -153,6 +159,13 @@ class Sim:
             raise ValueError("state has %d values, expected %d" % (flat.size, self.state_size))
         _check(lib().pcs_set_state(self.handle, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), flat.size),
                "pcs_set_state")
+
+    def stage_times(self, nsteps):
+        """Mean milliseconds per stage over nsteps real steps (eager launch,
+        HIP events on this run's stream); returns {stage name: ms}."""
+        ms = (ctypes.c_double * PCS_NSTAGE)()
+        _check(lib().pcs_stage_times(self.handle, int(nsteps), ms, PCS_NSTAGE), "pcs_stage_times")
+        return {lib().pcs_stage_name(i).decode(): ms[i] for i in range(PCS_NSTAGE)}
 
     def synchronize(self):
         self.stream.synchronize()

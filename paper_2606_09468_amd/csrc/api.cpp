@@ -14,6 +14,7 @@
 #include <complex>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -44,7 +45,7 @@ struct Carve {
 struct JobList {
   std::vector<GemmJob<double>> h;
   GemmJob<double>* dev = nullptr;
-  int tiles = 0;
+  int tiles = 0, bm = 64, kmax = 0;
   void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int m, int n, int k,
            double alpha = 1.0, double beta = 0.0) {
     GemmJob<double> j{};
@@ -54,7 +55,8 @@ struct JobList {
     j.m = m;
     j.n = n;
     j.k = k;
-    j.lda = lda;
+    (void)lda;
+    j.lda = m;  // operators are stored K-major
     j.ldb = ldb;
     j.ldc = ldc;
     j.alpha = alpha;
@@ -62,7 +64,39 @@ struct JobList {
     h.push_back(j);
   }
   int n() const { return (int)h.size(); }
+  // Row-tile height before tuning: 16 (K split over the four waves) while
+  // 64-row tiles would leave most of the 256 CUs idle, 128 once 64-row tiles
+  // give more than eight workgroups per CU, 64 in between.
+  void prepare() {
+    kmax = 0;
+    for (auto& j : h) kmax = std::max(kmax, j.k);
+    const int t64 = gemm_prepare(h.data(), n(), 64);
+    set_bm(t64 < 2 * 256 ? 16 : (t64 > 8 * 256 ? 128 : 64));
+  }
+  void set_bm(int b) {
+    bm = b;
+    tiles = gemm_prepare(h.data(), n(), bm);
+  }
+  // shape signature for the tuning cache
+  std::vector<int> key() const {
+    std::vector<int> k;
+    for (auto& j : h) {
+      k.push_back(j.m);
+      k.push_back(j.n);
+      k.push_back(j.k);
+    }
+    return k;
+  }
+  void run(hipStream_t s) const { gemm_f64(dev, tiles, n(), bm, kmax, s); }
 };
+
+// Row-major (rows x cols) -> K-major copy used as the A operand of the products.
+std::vector<double> kmajor(const std::vector<double>& a, int rows, int cols) {
+  std::vector<double> t((size_t)rows * cols);
+  for (int i = 0; i < rows; ++i)
+    for (int k = 0; k < cols; ++k) t[(size_t)k * rows + i] = a[(size_t)i * cols + k];
+  return t;
+}
 
 bool valid_fft(int L) {
   FftPlan p;
@@ -402,41 +436,70 @@ void build_jobs(pcs_sim* m) {
   for (int a = 0; a < d.nc; ++a)
     m->G5.add(m->V, ni, m->Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
   m->G5.add(m->wV, ni, m->Xs + 0 * fsi, cw, m->flux, cw, 1, cw, ni);
-  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5})
-    jl->tiles = gemm_prepare(jl->h.data(), jl->n());
+  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5}) jl->prepare();
 }
 
-void explicit_stage(pcs_sim* m) {
+// Stage boundaries: mark(i) is called before stage i and once more at the
+// end; the eager profiling path records a HIP event there.
+enum Stage {
+  ST_GEMM_STATE, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_ASSEMBLE, ST_GEMM_DS, ST_RHS,
+  ST_GEMM_VINV, ST_EIGSCALE, ST_GEMM_V, ST_FINALIZE, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
+};
+const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv", "xpencil", "zfft_fwd", "gemm_proj",
+                                            "assemble_h", "gemm_ds", "rhs", "gemm_vinv", "eigscale",
+                                            "gemm_v", "finalize", "diag_rows", "diag_final"};
+
+struct NoMark {
+  void operator()(int) const {}
+};
+
+template <typename Mark>
+void explicit_stage(pcs_sim* m, const Mark& mark) {
   const Dims& d = m->d;
   hipStream_t s = m->s;
-  gemm_f64(m->G1.dev, m->G1.tiles, m->G1.n(), s);
-  if (d.dim == 3) {
-    launch_zfft(d, m->plz, m->Yin, m->Zin, m->nzin, m->zsrc, m->zder, m->kz, m->twz, 1, d.M + 1, s);
+  mark(ST_GEMM_STATE);
+  m->G1.run(s);
+  mark(ST_ZFFT_INV);
+  if (d.dim == 3) launch_zfft(d, m->plz, m->Yin, m->Zin, m->nzin, m->zsrc, m->zder, m->kz, m->twz, 1, d.M + 1, s);
+  mark(ST_XPENCIL);
+  if (d.dim == 3)
     launch_xpencil3d(d, m->p, m->plx, m->Zin, m->Zout, m->kx, m->twx, s);
-    launch_zfft(d, m->plz, m->Zout, m->Yout, m->nout, nullptr, nullptr, m->kz, m->twz, 0, d.M + 1, s);
-  } else {
+  else
     launch_xpencil(d, m->p, m->plx, m->Yin, m->Yout, m->kx, m->twx, s);
-  }
-  gemm_f64(m->G2.dev, m->G2.tiles, m->G2.n(), s);
+  mark(ST_ZFFT_FWD);
+  if (d.dim == 3) launch_zfft(d, m->plz, m->Zout, m->Yout, m->nout, nullptr, nullptr, m->kz, m->twz, 0, d.M + 1, s);
+  mark(ST_GEMM_PROJ);
+  m->G2.run(s);
+  mark(ST_ASSEMBLE);
   const size_t fs = (size_t)(d.N + 1) * d.cw;
   launch_assemble_h(d, m->p, m->S, m->state + (d.dim == 2 ? 3 : 5) * fs, m->Dc, m->kx, m->kz, m->sbuf, m->hy, m->hgn,
                     s);
-  gemm_f64(m->G3.dev, m->G3.tiles, m->G3.n(), s);
+  mark(ST_GEMM_DS);
+  m->G3.run(s);
+  mark(ST_RHS);
   launch_rhs(d, m->p, m->state, m->D2buf, m->sbuf, m->Ds, m->hy, m->hgn, m->S, m->kx, m->kz, m->d2i0, m->d2in, m->R,
              m->hvn, m->CB, s);
 }
 
-void enqueue_step(pcs_sim* m) {
+template <typename Mark>
+void enqueue_step(pcs_sim* m, const Mark& mark) {
   const Dims& d = m->d;
   hipStream_t s = m->s;
-  explicit_stage(m);
-  gemm_f64(m->G4.dev, m->G4.tiles, m->G4.n(), s);
+  explicit_stage(m, mark);
+  mark(ST_GEMM_VINV);
+  m->G4.run(s);
+  mark(ST_EIGSCALE);
   launch_eigscale(d, m->p, m->X, m->Xs, m->lam, m->kx, m->kz, s);
-  gemm_f64(m->G5.dev, m->G5.tiles, m->G5.n(), s);
+  mark(ST_GEMM_V);
+  m->G5.run(s);
+  mark(ST_FINALIZE);
   launch_finalize(d, m->p, m->Zphi, m->Zv, m->ZDv, m->flux, m->infl, m->U1, m->wU1, m->CB, m->hvn, m->hgn, m->S,
                   m->kx, m->kz, m->state, m->sc, s);
+  mark(ST_DIAG_ROWS);
   launch_diag_rows(d, m->p, m->pbx, m->state, m->prep, m->zbuf, m->pbz, m->twbx, m->twbz, m->ydy, m->parts, s);
+  mark(ST_DIAG_FINAL);
   launch_diag_final(d, m->p, m->parts, m->w, m->sc, m->ring, RING, s);
+  mark(ST_COUNT);
 }
 
 // With PCS_DEBUG set in the environment, failing HIP calls are reported on stderr.
@@ -455,6 +518,14 @@ void report(hipError_t e, const char* what, int line) {
     }                                    \
   } while (0)
 
+// Tile autotuner: times each candidate row-tile height of a product table on
+// the device (results of the timing launches are discarded) and keeps the
+// fastest.  Choices are cached per table shape for the process lifetime.
+std::map<std::vector<int>, int>& tune_cache() {
+  static std::map<std::vector<int>, int> c;
+  return c;
+}
+
 // Init-time uploads are blocking copies, so host temporaries may die at once.
 template <typename T>
 hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
@@ -469,13 +540,14 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
   const int n1 = d.N + 1, ni = d.N - 1;
   hipStream_t s = m->s;
   // operators
-  HIPCHK(up(m->IMN, op->IMN, s));
-  HIPCHK(up(m->DMN, op->DMN, s));
-  HIPCHK(up(m->D, op->D, s));
-  HIPCHK(up(m->D2, op->D2, s));
-  HIPCHK(up(m->PNM, op->PNM, s));
-  HIPCHK(up(m->V, op->V, s));
-  HIPCHK(up(m->Vinv, op->Vinv, s));
+  const int m1 = d.M + 1;
+  HIPCHK(up(m->IMN, kmajor(op->IMN, m1, n1), s));
+  HIPCHK(up(m->DMN, kmajor(op->DMN, m1, n1), s));
+  HIPCHK(up(m->D, kmajor(op->D, n1, n1), s));
+  HIPCHK(up(m->D2, kmajor(op->D2, n1, n1), s));
+  HIPCHK(up(m->PNM, kmajor(op->PNM, n1, m1), s));
+  HIPCHK(up(m->V, kmajor(op->V, ni, ni), s));
+  HIPCHK(up(m->Vinv, kmajor(op->Vinv, ni, ni), s));
   HIPCHK(up(m->lam, op->lam, s));
   HIPCHK(up(m->d2i0, op->d2_i0, s));
   HIPCHK(up(m->d2in, op->d2_in, s));
@@ -493,7 +565,7 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
     for (int j = 1; j < d.N; ++j) acc += (long double)op->w[j] * op->V[(size_t)(j - 1) * ni + e];
     wV[e] = (double)acc;
   }
-  HIPCHK(up(m->DV, DV, s));
+  HIPCHK(up(m->DV, kmajor(DV, n1, ni), s));
   HIPCHK(up(m->wV, wV, s));
   std::vector<double> ydy(n1);
   const double* y = op->y.data();
@@ -541,6 +613,58 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
   return PCS_OK;
 }
 
+// Initial state and device scalars (again after tuning, whose timing launches
+// write into the state's solve targets).
+pcs_status reset_state(pcs_sim* m, uint64_t seed, double amp) {
+  std::vector<double> st;
+  initial_state(m, seed, amp, st);
+  HIPCHK(up(m->state, st, m->s));
+  DevScalars sc0{};
+  sc0.pi = m->p.forcing == 1 ? m->p.q_or_dpdx : 2.0 / m->p.re;
+  HIPCHK(hipMemcpy(m->sc, &sc0, sizeof(sc0), hipMemcpyHostToDevice));
+  return PCS_OK;
+}
+
+pcs_status autotune(pcs_sim* m) {
+  static std::mutex mu;
+  std::lock_guard<std::mutex> g(mu);
+  hipStream_t s = m->s;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5}) {
+    const auto key = jl->key();
+    auto it = tune_cache().find(key);
+    int best = -1;
+    if (it != tune_cache().end()) {
+      best = it->second;
+    } else {
+      float tbest = 1e30f;
+      for (int bm : {16, 64, 128}) {
+        jl->set_bm(bm);
+        HIPCHK(up(jl->dev, jl->h, s));
+        jl->run(s);  // warm-up
+        HIPCHK(hipEventRecord(e0, s));
+        for (int r = 0; r < 3; ++r) jl->run(s);
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        if (ms < tbest) {
+          tbest = ms;
+          best = bm;
+        }
+      }
+      tune_cache()[key] = best;
+    }
+    jl->set_bm(best);
+    HIPCHK(up(jl->dev, jl->h, s));
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return PCS_OK;
+}
+
 pcs_status homogeneous_solutions(pcs_sim* m) {
   const Dims& d = m->d;
   hipStream_t s = m->s;
@@ -548,9 +672,9 @@ pcs_status homogeneous_solutions(pcs_sim* m) {
   HIPCHK(hipMemsetAsync(m->R, 0, m->nsolve * fsi * sizeof(double), s));
   HIPCHK(hipMemsetAsync(m->X, 0, m->nsolve * fsi * sizeof(double), s));
   launch_homog_rhs(d, m->p, m->d2i0, m->d2in, m->R, s);
-  gemm_f64(m->H4.dev, m->H4.tiles, m->H4.n(), s);
+  m->H4.run(s);
   launch_eigscale(d, m->p, m->X, m->Xs, m->lam, m->kx, m->kz, s);
-  gemm_f64(m->H5.dev, m->H5.tiles, m->H5.n(), s);
+  m->H5.run(s);
   launch_influence(d, m->Zphi, m->Zv, m->ZDv, m->kz, m->infl, m->U1, s);
   HIPCHK(hipGetLastError());
   std::vector<double> U1(d.N + 1);
@@ -567,7 +691,7 @@ pcs_status history_from_state(pcs_sim* m) {
   const Dims& d = m->d;
   hipStream_t s = m->s;
   const size_t fs = (size_t)(d.N + 1) * d.cw;
-  explicit_stage(m);
+  explicit_stage(m, NoMark());
   HIPCHK(hipGetLastError());
   double* hist = m->state + (size_t)m->nq * fs;
   HIPCHK(hipMemcpyAsync(hist, m->hvn, fs * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -584,7 +708,7 @@ pcs_status capture(pcs_sim* m) {
     (void)hipGetLastError();
     return PCS_OK;
   }
-  enqueue_step(m);
+  enqueue_step(m, NoMark());
   hipGraph_t g = nullptr;
   if (hipStreamEndCapture(m->s, &g) != hipSuccess || g == nullptr) {
     (void)hipGetLastError();
@@ -638,13 +762,19 @@ pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t see
   }
   carve(m, static_cast<char*>(workspace));
   m->s = static_cast<hipStream_t>(stream);
+  if (hipError_t e = gemm_set_attributes(); e != hipSuccess) {
+    report(e, "gemm_set_attributes", __LINE__);
+    delete m;
+    return PCS_ERR_DEVICE;
+  }
   if (hipError_t e = fft_set_attributes(); e != hipSuccess) {
     report(e, "fft_set_attributes", __LINE__);
     delete m;
     return PCS_ERR_DEVICE;
   }
   build_jobs(m);
-  if ((st = upload_everything(m, seed, amp)) != PCS_OK || (st = homogeneous_solutions(m)) != PCS_OK ||
+  if ((st = upload_everything(m, seed, amp)) != PCS_OK || (st = autotune(m)) != PCS_OK ||
+      (st = reset_state(m, seed, amp)) != PCS_OK || (st = homogeneous_solutions(m)) != PCS_OK ||
       (st = history_from_state(m)) != PCS_OK) {
     delete m;
     return st;
@@ -667,7 +797,7 @@ pcs_status pcs_step(pcs_sim* m, int32_t nsteps) {
     if (m->gexec) {
       if (hipGraphLaunch(m->gexec, m->s) != hipSuccess) return PCS_ERR_DEVICE;
     } else {
-      enqueue_step(m);
+      enqueue_step(m, NoMark());
     }
   }
   return hipGetLastError() == hipSuccess ? PCS_OK : PCS_ERR_DEVICE;
@@ -736,6 +866,33 @@ pcs_status pcs_set_state(pcs_sim* m, const double* host, size_t n) {
   m->blowup = 0;
   return PCS_OK;
 }
+
+pcs_status pcs_stage_times(pcs_sim* m, int32_t nsteps, double* ms, int32_t nstage) {
+  if (!m || nsteps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
+  if (m->blowup) return PCS_ERR_STATE;
+  hipEvent_t ev[ST_COUNT + 1];
+  for (int i = 0; i <= ST_COUNT; ++i) HIPCHK(hipEventCreate(&ev[i]));
+  std::vector<double> acc(ST_COUNT, 0.0);
+  pcs_status st = PCS_OK;
+  for (int k = 0; k < nsteps && st == PCS_OK; ++k) {
+    enqueue_step(m, [&](int i) { (void)hipEventRecord(ev[i], m->s); });
+    if (hipEventSynchronize(ev[ST_COUNT]) != hipSuccess) {
+      st = PCS_ERR_DEVICE;
+      break;
+    }
+    for (int i = 0; i < ST_COUNT; ++i) {
+      float t = 0;
+      if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) st = PCS_ERR_DEVICE;
+      acc[i] += t;
+    }
+  }
+  for (int i = 0; i <= ST_COUNT; ++i) (void)hipEventDestroy(ev[i]);
+  for (int i = 0; i < ST_COUNT; ++i) ms[i] = acc[i] / nsteps;
+  for (int i = ST_COUNT; i < nstage; ++i) ms[i] = 0.0;
+  return st;
+}
+
+const char* pcs_stage_name(int32_t i) { return (i >= 0 && i < ST_COUNT) ? STAGE_NAMES[i] : nullptr; }
 
 pcs_status pcs_destroy(pcs_sim* m) {
   if (!m) return PCS_ERR_ARG;

@@ -5,8 +5,10 @@
 // retained mode is placed at its own frequency in a transform of 3/2 the base
 // size, products are formed pointwise, and the forward transform is
 // truncated back to the retained modes.  Transforms are mixed-radix (4, 2, 3)
-// Stockham FFTs in LDS; two real fields share one complex transform
-// (z = a + i b), which halves the transform count.
+// Stockham FFTs done in place in LDS: each pass reads its butterfly inputs
+// into registers, synchronises, and writes the outputs to their sorted
+// positions, so one buffer suffices.  Two real fields share one complex
+// transform (z = a + i b).
 //
 // x pencil: one workgroup per padded (y', z') line.  It reads the needed
 // spectral fields of that line (kx modes), generates the d/dx variants by
@@ -41,6 +43,9 @@ bool make_plan(int L, FftPlan* p) {
 
 namespace {
 
+constexpr int NT = 256;     // threads per workgroup of the transform kernels
+constexpr int MAXV = 12;    // complex values a thread holds in one pass
+
 struct c2 {
   double x, y;
 };
@@ -49,13 +54,14 @@ __device__ inline c2 operator-(c2 a, c2 b) { return c2{a.x - b.x, a.y - b.y}; }
 __device__ inline c2 cmul(c2 a, c2 b) { return c2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
 __device__ inline c2 scal(double s, c2 a) { return c2{s * a.x, s * a.y}; }
 
-// In-LDS R-point DFT, R in {2, 3, 4}; sign -1 forward, +1 inverse.
-__device__ inline void butterfly(c2* v, int R, int sign) {
-  if (R == 2) {
+// R-point DFT in registers; sign -1 forward, +1 inverse.
+template <int R>
+__device__ inline void butterfly(c2* v, int sign) {
+  if constexpr (R == 2) {
     c2 t = v[0];
     v[0] = t + v[1];
     v[1] = t - v[1];
-  } else if (R == 4) {
+  } else if constexpr (R == 4) {
     c2 a = v[0] + v[2], b = v[0] - v[2], c = v[1] + v[3], d = v[1] - v[3];
     c2 sid = sign > 0 ? c2{-d.y, d.x} : c2{d.y, -d.x};  // (sign i) d
     v[0] = a + c;
@@ -74,269 +80,240 @@ __device__ inline void butterfly(c2* v, int R, int sign) {
   }
 }
 
-// Stockham passes over nseq sequences of length L stored contiguously at a;
-// b is the partner buffer.  Returns the buffer holding the result (a after an
-// even number of passes, b after an odd one).  tw[m] = exp(-2 pi i m / L).
-__device__ c2* lds_fft(c2* a, c2* b, const FftPlan& pl, int nseq, const c2* __restrict__ tw, int sign) {
-  const int L = pl.L;
-  int Ns = 1;
-  c2* in = a;
-  c2* out = b;
-  for (int ps = 0; ps < pl.npass; ++ps) {
-    const int R = pl.radix[ps], LR = L / R, stride = L / (Ns * R);
-    for (int idx = threadIdx.x; idx < nseq * LR; idx += blockDim.x) {
+// One in-place Stockham pass of radix R over nseq sequences of length L.
+// Ns = product of the radices of the earlier passes; tw[m] = exp(-2 pi i m/L).
+// Requires nseq * L / R <= NT * (MAXV / R).
+template <int R>
+__device__ void pass_ip(c2* buf, int L, int nseq, int Ns, const c2* __restrict__ tw, int sign) {
+  constexpr int NB = MAXV / R;
+  const int LR = L / R, stride = L / (Ns * R), tot = nseq * LR;
+  c2 v[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int idx = threadIdx.x + q * NT;
+    if (idx < tot) {
       const int s = idx / LR, j = idx - s * LR;
-      const c2* src = in + (size_t)s * L;
-      c2* dst = out + (size_t)s * L;
+      const c2* src = buf + (size_t)s * L + j;
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int idx = threadIdx.x + q * NT;
+    if (idx < tot) {
+      const int s = idx / LR, j = idx - s * LR;
       const int k = j % Ns;
-      c2 v[4];
-      for (int r = 0; r < R; ++r) v[r] = src[j + r * LR];
-      if (Ns > 1)
+      if (Ns > 1) {
+#pragma unroll
         for (int r = 1; r < R; ++r) {
           c2 w = tw[r * k * stride];
           if (sign > 0) w.y = -w.y;
-          v[r] = cmul(v[r], w);
+          v[q][r] = cmul(v[q][r], w);
         }
-      butterfly(v, R, sign);
-      const int base = (j - k) * R + k;
-      for (int r = 0; r < R; ++r) dst[base + r * Ns] = v[r];
+      }
+      butterfly<R>(v[q], sign);
+      c2* dst = buf + (size_t)s * L + (j - k) * R + k;
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
     }
-    __syncthreads();
-    c2* t = in;
-    in = out;
-    out = t;
+  }
+  __syncthreads();
+}
+
+__device__ void lds_fft(c2* buf, const FftPlan& pl, int nseq, const c2* __restrict__ tw, int sign) {
+  int Ns = 1;
+  for (int ps = 0; ps < pl.npass; ++ps) {
+    const int R = pl.radix[ps];
+    if (R == 4)
+      pass_ip<4>(buf, pl.L, nseq, Ns, tw, sign);
+    else if (R == 2)
+      pass_ip<2>(buf, pl.L, nseq, Ns, tw, sign);
+    else
+      pass_ip<3>(buf, pl.L, nseq, Ns, tw, sign);
     Ns *= R;
   }
-  return in;
 }
 
-// Source table of the real fields fed to the x transforms: field index in
-// the [field][row][kx] input buffer and whether d/dx is applied.
-struct XTable {
-  int nreal, npairs, nout, nopairs;
-  short src[36];
-  short dx[36];
-};
+// Largest batch of sequences a pass can hold in registers.
+__host__ __device__ inline int fft_batch(int L) { return (NT * MAXV) / L; }
+
+// Hermitian packing of two real-field spectra A_k, B_k into the complex
+// sequence whose inverse transform is a + i b.
+__device__ inline void pack_pair(c2* X, int L, int k, c2 A, c2 B) {
+  if (k == 0) {
+    X[0] = c2{A.x, B.x};
+  } else {
+    X[k] = c2{A.x - B.y, A.y + B.x};
+    X[L - k] = c2{A.x + B.y, B.x - A.y};
+  }
+}
+
+// Spectra of the two real fields packed in a forward transform Z, at k.
+__device__ inline void unpack_pair(const c2* Z, int L, int k, c2& A, c2& B) {
+  const c2 Zk = Z[k];
+  if (k == 0) {
+    A = c2{Zk.x, 0};
+    B = c2{Zk.y, 0};
+  } else {
+    const c2 Zc = Z[L - k];
+    A = c2{0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y - Zc.y)};
+    B = c2{0.5 * (Zk.y + Zc.y), -0.5 * (Zk.x - Zc.x)};
+  }
+}
 
 // index of c_ab in the stored list (2D: xx xy yy; 3D: xx xy xz yy yz zz)
-__device__ inline int cidx(int dim, int a, int b) {
-  if (a > b) {
-    int t = a;
-    a = b;
-    b = t;
-  }
-  if (dim == 2) return (a == 0) ? b : 2;
-  return (a == 0) ? b : (a == 1 ? 2 + b : 5);
+__host__ __device__ constexpr int cidx(int dim, int a, int b) {
+  return a > b ? cidx(dim, b, a) : (dim == 2 ? (a == 0 ? b : 2) : (a == 0 ? b : (a == 1 ? 2 + b : 5)));
 }
 
-// Products of eqs. (1)-(2) at one point.  Real-field order:
-//  2D: u v ux uy vx | cxx cxy cyy | dx c (3) | dy c (3)
-//  3D: u v w | c (6) | dx u v w | dx c (6) | dy u, dy w | dy c (6) | dz u v w | dz c (6)
-// Outputs: N_x N_y (N_z) F_ab (stored components).
+// Real fields fed to the x transforms: source field in the [field][row][kx]
+// input and whether d/dx is applied.
+//  2D (input: I u, I v, I c3, D u, D c3):
+//    u v ux uy vx | cxx cxy cyy | dx c (3) | dy c (3)
+//  3D (input: I u v w, I c6, D u, D w, D c6, dz u v w, dz c6):
+//    u v w | c (6) | dx u v w | dx c (6) | dy u, dy w | dy c (6) | dz u v w | dz c (6)
+__device__ const short XSRC[2][36] = {
+    {0, 1, 0, 5, 1, 2, 3, 4, 2, 3, 4, 6, 7, 8},
+    {0, 1, 2, 3, 4, 5, 6, 7, 8, 0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 10, 11, 12, 13, 14, 15, 16, 17, 18, 19, 20, 21, 22, 23,
+     24, 25}};
+__device__ const short XDX[2][36] = {{0, 0, 1, 0, 1, 0, 0, 0, 1, 1, 1, 0, 0, 0},
+                                     {0, 0, 0, 0, 0, 0, 0, 0, 0, 1, 1, 1, 1, 1, 1, 1, 1, 1}};
+
 template <int DIM>
-__device__ inline void pointwise(const double* r, double* o, double eps_wi) {
-  double u[3], du[3][3], c[3][3], dc[3][6];
-  const int nc = DIM == 2 ? 3 : 6;
-  if (DIM == 2) {
-    u[0] = r[0];
-    u[1] = r[1];
-    du[0][0] = r[2];
-    du[1][0] = r[3];
-    du[0][1] = r[4];
-    du[1][1] = -r[2];
-    for (int q = 0; q < 3; ++q) {
-      dc[0][q] = r[8 + q];
-      dc[1][q] = r[11 + q];
+struct XShape {
+  static constexpr int NREAL = DIM == 2 ? 14 : 35;
+  static constexpr int NP = (NREAL + 1) / 2;
+  static constexpr int NOUT = DIM == 2 ? 5 : 9;
+  static constexpr int NOP = (NOUT + 1) / 2;
+};
+
+// Products of eqs. (1)-(2) at one point (field order as in the tables above);
+// r(f) returns real field f at the point.  Outputs: N_x N_y (N_z) then F_ab
+// (stored components).
+template <int DIM, typename Rd>
+__device__ inline void pointwise(const Rd& r, double* o, double eps_wi) {
+  // velocity gradient du(k, a) = d_k u_a, with d_y v from continuity
+  auto u = [&](int a) -> double { return r(a); };
+  auto du = [&](int k, int a) -> double {
+    if constexpr (DIM == 2) {
+      if (k == 0) return a == 0 ? r(2) : r(4);
+      return a == 0 ? r(3) : -r(2);
+    } else {
+      if (k == 0) return r(9 + a);
+      if (k == 2) return r(26 + a);
+      return a == 0 ? r(18) : (a == 2 ? r(19) : -(r(9) + r(28)));
     }
-    for (int a = 0; a < 2; ++a)
-      for (int b = 0; b < 2; ++b) c[a][b] = r[5 + cidx(2, a, b)];
-  } else {
-    for (int a = 0; a < 3; ++a) {
-      u[a] = r[a];
-      du[0][a] = r[9 + a];
-      du[2][a] = r[26 + a];
-    }
-    du[1][0] = r[18];
-    du[1][2] = r[19];
-    du[1][1] = -(r[9] + r[28]);
-    for (int q = 0; q < 6; ++q) {
-      dc[0][q] = r[12 + q];
-      dc[1][q] = r[20 + q];
-      dc[2][q] = r[29 + q];
-    }
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 3; ++b) c[a][b] = r[3 + cidx(3, a, b)];
-  }
+  };
+  constexpr int C0 = DIM == 2 ? 5 : 3;                  // c components
+  constexpr int DX = DIM == 2 ? 8 : 12, DY = DIM == 2 ? 11 : 20, DZ = 29;
+  auto c = [&](int a, int b) -> double { return r(C0 + cidx(DIM, a, b)); };
+  auto dc = [&](int k, int q) -> double { return r((k == 0 ? DX : (k == 1 ? DY : DZ)) + q); };
+#pragma unroll
   for (int a = 0; a < DIM; ++a) {
     double s = 0;
-    for (int k = 0; k < DIM; ++k) s += u[k] * du[k][a];
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) s += u(k) * du(k, a);
     o[a] = -s;
   }
   double tr = 0;
-  for (int a = 0; a < DIM; ++a) tr += c[a][a] - 1.0;
-  for (int a = 0, q = 0; a < DIM; ++a)
-    for (int b = a; b < DIM; ++b, ++q) {
+  if (eps_wi != 0.0) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) tr += c(a, a) - 1.0;
+  }
+  int q = 0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int b = a; b < DIM; ++b) {
       double f = 0;
-      for (int k = 0; k < DIM; ++k) f += -u[k] * dc[k][q] + du[k][a] * c[k][b] + c[a][k] * du[k][b];
-      if (eps_wi != 0.0) f -= eps_wi * tr * (c[a][b] - (a == b ? 1.0 : 0.0));
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) f += -u(k) * dc(k, q) + du(k, a) * c(k, b) + c(a, k) * du(k, b);
+      if (eps_wi != 0.0) f -= eps_wi * tr * (c(a, b) - (a == b ? 1.0 : 0.0));
       o[DIM + q] = f;
+      ++q;
     }
-  (void)nc;
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void xpencil_kernel(const double* __restrict__ in, double* __restrict__ out,
-                                                      int nrows, int nkx, FftPlan pl, const double* __restrict__ kx,
-                                                      const c2* __restrict__ tw, XTable tab, int S, double eps_wi) {
+__global__ __launch_bounds__(NT) void xpencil_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                     int nrows, int nkx, FftPlan pl, const double* __restrict__ kx,
+                                                     const c2* __restrict__ tw, double eps_wi) {
+  using XS = XShape<DIM>;
   extern __shared__ double smem_d[];
   c2* P = reinterpret_cast<c2*>(smem_d);
   const int L = pl.L;
-  c2* Tm = P + (size_t)tab.npairs * L;
   const int row = blockIdx.x, tid = threadIdx.x;
   const size_t fstride = (size_t)nrows * nkx * 2;
   const double* base = in + (size_t)row * nkx * 2;
-  const bool odd = (pl.npass & 1) != 0;
-  for (int b0 = 0; b0 < tab.npairs; b0 += S) {
-    const int nb = min(S, tab.npairs - b0);
-    c2* X = odd ? Tm : P + (size_t)b0 * L;
-    c2* Y = odd ? P + (size_t)b0 * L : Tm;
-    for (int e = tid; e < nb * L; e += blockDim.x) X[e] = c2{0, 0};
+  const int S = fft_batch(L);
+  const short* src = XSRC[DIM - 2];
+  const short* dxf = XDX[DIM - 2];
+  for (int b0 = 0; b0 < XS::NP; b0 += S) {
+    const int nb = min(S, XS::NP - b0);
+    c2* X = P + (size_t)b0 * L;
+    for (int e = tid; e < nb * L; e += NT) X[e] = c2{0, 0};
     __syncthreads();
-    for (int e = tid; e < nb * nkx; e += blockDim.x) {
+    for (int e = tid; e < nb * nkx; e += NT) {
       const int q = e / nkx, k = e - q * nkx;
-      c2 A{0, 0}, B{0, 0};
       const int fa = 2 * (b0 + q), fb = fa + 1;
       const double kk = kx[k];
-      if (fa < tab.nreal) {
-        const double* p = base + tab.src[fa] * fstride + 2 * k;
+      c2 A{0, 0}, B{0, 0};
+      {
+        const double* p = base + src[fa] * fstride + 2 * k;
         A = c2{p[0], p[1]};
-        if (tab.dx[fa]) A = c2{-kk * A.y, kk * A.x};
+        if (dxf[fa]) A = c2{-kk * A.y, kk * A.x};
       }
-      if (fb < tab.nreal) {
-        const double* p = base + tab.src[fb] * fstride + 2 * k;
+      if (fb < XS::NREAL) {
+        const double* p = base + src[fb] * fstride + 2 * k;
         B = c2{p[0], p[1]};
-        if (tab.dx[fb]) B = c2{-kk * B.y, kk * B.x};
+        if (dxf[fb]) B = c2{-kk * B.y, kk * B.x};
       }
-      c2* Xq = X + (size_t)q * L;
-      if (k == 0) {
-        Xq[0] = c2{A.x, B.x};
-      } else {
-        Xq[k] = c2{A.x - B.y, A.y + B.x};
-        Xq[L - k] = c2{A.x + B.y, B.x - A.y};
-      }
+      pack_pair(X + (size_t)q * L, L, k, A, B);
     }
     __syncthreads();
-    lds_fft(X, Y, pl, nb, tw, +1);
+    lds_fft(X, pl, nb, tw, +1);
   }
   // pointwise products; outputs overwrite the first pairs at the same point
-  for (int n = tid; n < L; n += blockDim.x) {
-    double r[36], o[10];
-    for (int f = 0; f < tab.nreal; ++f) {
-      const c2 z = P[(size_t)(f >> 1) * L + n];
-      r[f] = (f & 1) ? z.y : z.x;
-    }
-    pointwise<DIM>(r, o, eps_wi);
-    o[tab.nout] = 0.0;
-    for (int q = 0; q < tab.nopairs; ++q) P[(size_t)q * L + n] = c2{o[2 * q], o[2 * q + 1]};
+  for (int n = tid; n < L; n += NT) {
+    double o[2 * XS::NOP];
+    auto rd = [&](int f) -> double {
+      const c2& z = P[(size_t)(f >> 1) * L + n];
+      return (f & 1) ? z.y : z.x;
+    };
+    pointwise<DIM>(rd, o, eps_wi);
+    if constexpr (XS::NOUT & 1) o[2 * XS::NOP - 1] = 0.0;
+#pragma unroll
+    for (int q = 0; q < XS::NOP; ++q) P[(size_t)q * L + n] = c2{o[2 * q], o[2 * q + 1]};
   }
   __syncthreads();
   const double inv = 1.0 / L;
   double* obase = out + (size_t)row * nkx * 2;
-  for (int q0 = 0; q0 < tab.nopairs; q0 += S) {
-    const int nb = min(S, tab.nopairs - q0);
-    const c2* res = lds_fft(P + (size_t)q0 * L, Tm, pl, nb, tw, -1);
-    for (int e = tid; e < nb * nkx; e += blockDim.x) {
+  for (int q0 = 0; q0 < XS::NOP; q0 += S) {
+    const int nb = min(S, XS::NOP - q0);
+    c2* Z = P + (size_t)q0 * L;
+    lds_fft(Z, pl, nb, tw, -1);
+    for (int e = tid; e < nb * nkx; e += NT) {
       const int q = e / nkx, k = e - q * nkx;
-      const c2* Rq = res + (size_t)q * L;
-      const c2 Zk = Rq[k];
       c2 A, B;
-      if (k == 0) {
-        A = c2{Zk.x, 0};
-        B = c2{Zk.y, 0};
-      } else {
-        const c2 Zc = Rq[L - k];
-        A = c2{0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y - Zc.y)};
-        B = c2{0.5 * (Zk.y + Zc.y), -0.5 * (Zk.x - Zc.x)};
-      }
+      unpack_pair(Z + (size_t)q * L, L, k, A, B);
       const int fa = 2 * (q0 + q), fb = fa + 1;
       double* pa = obase + (size_t)fa * fstride + 2 * k;
       pa[0] = A.x * inv;
       pa[1] = A.y * inv;
-      if (fb < tab.nout) {
+      if (fb < XS::NOUT) {
         double* pb = obase + (size_t)fb * fstride + 2 * k;
         pb[0] = B.x * inv;
         pb[1] = B.y * inv;
       }
     }
-    __syncthreads();
   }
 }
 
-XTable table2d() {
-  XTable t{};
-  const short src[14] = {0, 1, 0, 5, 1, 2, 3, 4, 2, 3, 4, 6, 7, 8};
-  const short dx[14] = {0, 0, 1, 0, 1, 0, 0, 0, 1, 1, 1, 0, 0, 0};
-  t.nreal = 14;
-  t.npairs = 7;
-  t.nout = 5;
-  t.nopairs = 3;
-  for (int i = 0; i < 14; ++i) {
-    t.src[i] = src[i];
-    t.dx[i] = dx[i];
-  }
-  return t;
-}
-
-XTable table3d() {
-  XTable t{};
-  int n = 0;
-  auto add = [&](int s, int d) {
-    t.src[n] = (short)s;
-    t.dx[n] = (short)d;
-    ++n;
-  };
-  for (int f = 0; f < 9; ++f) add(f, 0);       // u v w c6
-  for (int f = 0; f < 9; ++f) add(f, 1);       // dx u v w, dx c6
-  add(9, 0);                                   // dy u
-  add(10, 0);                                  // dy w
-  for (int f = 11; f < 17; ++f) add(f, 0);     // dy c6
-  for (int f = 17; f < 26; ++f) add(f, 0);     // dz u v w, dz c6
-  t.nreal = n;                                 // 35
-  t.npairs = (n + 1) / 2;
-  t.nout = 9;
-  t.nopairs = 5;
-  return t;
-}
-
-size_t xpencil_lds(int npairs, int L, int S) { return (size_t)(npairs + S) * L * sizeof(c2); }
-
-int pick_batch(int npairs, int L) {
-  const size_t budget = 160 * 1024;
-  int S = npairs;
-  while (S > 1 && xpencil_lds(npairs, L, S) > budget) --S;
-  return S;
-}
-
-}  // namespace
-
-void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const double* yin, double* yout,
-                    const double* kx, const double* tw, hipStream_t s) {
-  // 2D: rows are the padded y points
-  XTable t = table2d();
-  const int S = pick_batch(t.npairs, plan.L);
-  const size_t lds = xpencil_lds(t.npairs, plan.L, S);
-  hipLaunchKernelGGL(xpencil_kernel<2>, dim3(d.M + 1), dim3(256), lds, s, yin, yout, d.M + 1, d.nkx, plan, kx,
-                     reinterpret_cast<const c2*>(tw), t, S, p.eps / p.wi);
-}
-
-void launch_xpencil3d(const Dims& d, const Phys& p, const FftPlan& plan, const double* zin, double* zout,
-                      const double* kx, const double* tw, hipStream_t s) {
-  XTable t = table3d();
-  const int S = pick_batch(t.npairs, plan.L);
-  const size_t lds = xpencil_lds(t.npairs, plan.L, S);
-  const int rows = (d.M + 1) * d.pz;
-  hipLaunchKernelGGL(xpencil_kernel<3>, dim3(rows), dim3(256), lds, s, zin, zout, rows, d.nkx, plan, kx,
-                     reinterpret_cast<const c2*>(tw), t, S, p.eps / p.wi);
+template <int DIM>
+size_t xpencil_lds(int L) {
+  return (size_t)XShape<DIM>::NP * L * sizeof(c2);
 }
 
 // ---------------------------------------------------------------- z columns
@@ -344,18 +321,15 @@ void launch_xpencil3d(const Dims& d, const Phys& p, const FftPlan& plan, const d
 // inverse: kz slots (Nyquist slot skipped, optional i kz factor) are placed at
 // their own frequency in a length-Lz transform; forward: length-Lz data is
 // transformed, divided by Lz and truncated to the retained slots.
-constexpr int ZG = 8;  // kx columns per workgroup
+constexpr int ZG = 16;  // kx columns per workgroup
 
-namespace {
-__global__ __launch_bounds__(256) void zfft_kernel(const double* __restrict__ in, double* __restrict__ out,
-                                                   int nkx, int nzs, int rows_y, FftPlan pl,
-                                                   const int* __restrict__ src_field, const int* __restrict__ deriv,
-                                                   const double* __restrict__ kz, const c2* __restrict__ tw,
-                                                   int inverse) {
+__global__ __launch_bounds__(NT) void zfft_kernel(const double* __restrict__ in, double* __restrict__ out, int nkx,
+                                                  int nzs, int rows_y, FftPlan pl, const int* __restrict__ src_field,
+                                                  const int* __restrict__ deriv, const double* __restrict__ kz,
+                                                  const c2* __restrict__ tw, int inverse) {
   extern __shared__ double smem_z[];
   c2* A = reinterpret_cast<c2*>(smem_z);
   const int L = pl.L;
-  c2* B = A + (size_t)ZG * L;
   const int k0 = blockIdx.x * ZG, i = blockIdx.y, f = blockIdx.z;
   const int ng = min(ZG, nkx - k0);
   const int tid = threadIdx.x;
@@ -364,10 +338,10 @@ __global__ __launch_bounds__(256) void zfft_kernel(const double* __restrict__ in
   const int dz = deriv ? deriv[f] : 0;
   const double* ib = in + ((size_t)sf * rows_y + i) * rin * nkx * 2;
   double* ob = out + ((size_t)f * rows_y + i) * rout * nkx * 2;
-  for (int e = tid; e < ZG * L; e += blockDim.x) A[e] = c2{0, 0};
-  __syncthreads();
   if (inverse) {
-    for (int e = tid; e < nzs * ng; e += blockDim.x) {
+    for (int e = tid; e < ZG * L; e += NT) A[e] = c2{0, 0};
+    __syncthreads();
+    for (int e = tid; e < nzs * ng; e += NT) {
       const int s = e / ng, g = e - s * ng;
       if (nzs > 1 && s == nzs / 2) continue;
       const int mz = (s < nzs / 2) ? s : s - nzs;
@@ -379,43 +353,33 @@ __global__ __launch_bounds__(256) void zfft_kernel(const double* __restrict__ in
       A[(size_t)g * L + ((mz % L) + L) % L] = v;
     }
   } else {
-    for (int e = tid; e < L * ng; e += blockDim.x) {
+    for (int e = tid; e < L * ng; e += NT) {
       const int z = e / ng, g = e - z * ng;
       A[(size_t)g * L + z] = c2{ib[((size_t)z * nkx + k0 + g) * 2], ib[((size_t)z * nkx + k0 + g) * 2 + 1]};
     }
   }
   __syncthreads();
-  const c2* R = lds_fft(A, B, pl, ng, tw, inverse ? +1 : -1);
+  lds_fft(A, pl, ng, tw, inverse ? +1 : -1);
   if (inverse) {
-    for (int e = tid; e < L * ng; e += blockDim.x) {
+    for (int e = tid; e < L * ng; e += NT) {
       const int z = e / ng, g = e - z * ng;
-      const c2 v = R[(size_t)g * L + z];
+      const c2 v = A[(size_t)g * L + z];
       ob[((size_t)z * nkx + k0 + g) * 2] = v.x;
       ob[((size_t)z * nkx + k0 + g) * 2 + 1] = v.y;
     }
   } else {
     const double inv = 1.0 / L;
-    for (int e = tid; e < nzs * ng; e += blockDim.x) {
+    for (int e = tid; e < nzs * ng; e += NT) {
       const int s = e / ng, g = e - s * ng;
       c2 v{0, 0};
       if (!(nzs > 1 && s == nzs / 2)) {
         const int mz = (s < nzs / 2) ? s : s - nzs;
-        v = scal(inv, R[(size_t)g * L + ((mz % L) + L) % L]);
+        v = scal(inv, A[(size_t)g * L + ((mz % L) + L) % L]);
       }
       ob[((size_t)s * nkx + k0 + g) * 2] = v.x;
       ob[((size_t)s * nkx + k0 + g) * 2 + 1] = v.y;
     }
   }
-}
-}  // namespace
-
-void launch_zfft(const Dims& d, const FftPlan& plan, const double* in, double* out, int nfields,
-                 const int* src_field, const int* deriv, const double* kz, const double* tw, int inverse, int rows,
-                 hipStream_t s) {
-  const size_t lds = 2 * (size_t)ZG * plan.L * sizeof(c2);
-  dim3 grid((d.nkx + ZG - 1) / ZG, rows, nfields);
-  hipLaunchKernelGGL(zfft_kernel, grid, dim3(256), lds, s, in, out, d.nkx, d.nzs, rows, plan, src_field, deriv, kz,
-                     reinterpret_cast<const c2*>(tw), inverse);
 }
 
 // ---------------------------------------------------------------- diagnostics
@@ -423,9 +387,9 @@ void launch_zfft(const Dims& d, const FftPlan& plan, const double* in, double* o
 // c_xx + c_yy (+ c_zz) is formed first (2D adds the constant c_zz = 1 after
 // the transform), then the inverse x transform.  Per line: min Tr c, counts of
 // Tr c < 3 and < 0 (strict), max CFL contribution |u|/dx + |v|/dy_j + |w|/dz,
-// sums of |u|^2/2 and Tr c, and non-finite / |Tr c| > 1e12 flags.
-namespace {
-
+// sums of |u|^2/2 and Tr c, and non-finite / |Tr c| > 1e12 flags.  Sums are
+// reduced in a fixed order (wave butterflies, then waves in index order), so
+// replays are bitwise reproducible.
 __global__ void diag_prep_kernel(Dims d, const double* __restrict__ st, double* __restrict__ outb) {
   const int n1 = d.N + 1;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
@@ -450,49 +414,58 @@ __global__ void diag_prep_kernel(Dims d, const double* __restrict__ st, double* 
   }
 }
 
-__global__ __launch_bounds__(256) void diag_rows_kernel(Dims d, Phys p, const double* __restrict__ in, int zrows,
-                                                        FftPlan pl, const c2* __restrict__ tw,
-                                                        const double* __restrict__ ydy, DiagPart* __restrict__ parts) {
+__device__ inline double wave_min(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double wave_max(double v) {
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o));
+  return v;
+}
+__device__ inline double wave_sum(double v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline unsigned long long wave_sumu(unsigned long long v) {
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+  return v;
+}
+__device__ inline int wave_or(int v) {
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o);
+  return v;
+}
+
+__global__ __launch_bounds__(NT) void diag_rows_kernel(Dims d, const double* __restrict__ in, int zrows, FftPlan pl,
+                                                       const c2* __restrict__ tw, const double* __restrict__ ydy,
+                                                       DiagPart* __restrict__ parts) {
   extern __shared__ double smem_g[];
   c2* A = reinterpret_cast<c2*>(smem_g);
+  __shared__ DiagPart wpart[NT / 64];
   const int L = pl.L, nkx = d.nkx;
-  c2* B = A + 2 * (size_t)L;
-  __shared__ double rmin[256], rcfl[256], re[256], rt[256];
-  __shared__ unsigned long long c3[256], c0[256];
-  __shared__ int rnf[256], rbig[256];
   const int row = blockIdx.x, tid = threadIdx.x;
   const int nrows = (d.N + 1) * zrows;
   const int j = row / zrows;
   const size_t fstride = (size_t)nrows * nkx * 2;
   const double* base = in + (size_t)row * nkx * 2;
-  const bool odd = (pl.npass & 1) != 0;
-  c2* X = odd ? B : A;
-  c2* Y = odd ? A : B;
-  for (int e = tid; e < 2 * L; e += blockDim.x) X[e] = c2{0, 0};
+  for (int e = tid; e < 2 * L; e += NT) A[e] = c2{0, 0};
   __syncthreads();
   const int nf = d.dim == 2 ? 3 : 4;
-  for (int e = tid; e < 2 * nkx; e += blockDim.x) {
+  for (int e = tid; e < 2 * nkx; e += NT) {
     const int q = e / nkx, k = e - q * nkx;
     const int fa = 2 * q, fb = fa + 1;
     c2 Av{0, 0}, Bv{0, 0};
     if (fa < nf) Av = c2{base[fa * fstride + 2 * k], base[fa * fstride + 2 * k + 1]};
     if (fb < nf) Bv = c2{base[fb * fstride + 2 * k], base[fb * fstride + 2 * k + 1]};
-    c2* Xq = X + (size_t)q * L;
-    if (k == 0) {
-      Xq[0] = c2{Av.x, Bv.x};
-    } else {
-      Xq[k] = c2{Av.x - Bv.y, Av.y + Bv.x};
-      Xq[L - k] = c2{Av.x + Bv.y, Bv.x - Av.y};
-    }
+    pack_pair(A + (size_t)q * L, L, k, Av, Bv);
   }
   __syncthreads();
-  lds_fft(X, Y, pl, 2, tw, +1);  // result in A
+  lds_fft(A, pl, 2, tw, +1);
   const double dx = d.lx / d.nx, dz = d.dim == 3 ? d.lz / d.nz : 1.0;
   const double dyj = ydy[j];
   double mn = 1.0 / 0.0, cf = 0, es = 0, ts = 0;
   unsigned long long n3 = 0, n0 = 0;
-  int nfin = 0, big = 0;
-  for (int n = tid; n < L; n += blockDim.x) {
+  int flag = 0, big = 0;
+  for (int n = tid; n < L; n += NT) {
     const c2 z0 = A[n], z1 = A[L + n];
     const double trc = z0.x + (d.dim == 2 ? 1.0 : 0.0);
     const double u = z0.y, v = z1.x, w = d.dim == 3 ? z1.y : 0.0;
@@ -504,59 +477,62 @@ __global__ __launch_bounds__(256) void diag_rows_kernel(Dims d, Phys p, const do
     cf = fmax(cf, c);
     es += 0.5 * (u * u + v * v + w * w);
     ts += trc;
-    nfin |= !(isfinite(trc) && isfinite(u) && isfinite(v) && isfinite(w));
+    flag |= !(isfinite(trc) && isfinite(u) && isfinite(v) && isfinite(w));
     big |= (fabs(trc) > 1.0e12);
   }
-  rmin[tid] = mn;
-  rcfl[tid] = cf;
-  re[tid] = es;
-  rt[tid] = ts;
-  c3[tid] = n3;
-  c0[tid] = n0;
-  rnf[tid] = nfin;
-  rbig[tid] = big;
-  __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
-    if (tid < h) {
-      rmin[tid] = fmin(rmin[tid], rmin[tid + h]);
-      rcfl[tid] = fmax(rcfl[tid], rcfl[tid + h]);
-      re[tid] += re[tid + h];
-      rt[tid] += rt[tid + h];
-      c3[tid] += c3[tid + h];
-      c0[tid] += c0[tid + h];
-      rnf[tid] |= rnf[tid + h];
-      rbig[tid] |= rbig[tid + h];
-    }
-    __syncthreads();
-  }
-  if (tid == 0) {
+  mn = wave_min(mn);
+  cf = wave_max(cf);
+  es = wave_sum(es);
+  ts = wave_sum(ts);
+  n3 = wave_sumu(n3);
+  n0 = wave_sumu(n0);
+  flag = wave_or(flag);
+  big = wave_or(big);
+  const int wv = tid >> 6;
+  if ((tid & 63) == 0) {
     DiagPart q;
-    q.min_trc = rmin[0];
-    q.cfl = rcfl[0];
-    q.esum = re[0];
-    q.tsum = rt[0];
-    q.n_lt3 = c3[0];
-    q.n_lt0 = c0[0];
-    q.nonfinite = rnf[0];
-    q.big = rbig[0];
+    q.min_trc = mn;
+    q.cfl = cf;
+    q.esum = es;
+    q.tsum = ts;
+    q.n_lt3 = n3;
+    q.n_lt0 = n0;
+    q.nonfinite = flag;
+    q.big = big;
+    wpart[wv] = q;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    DiagPart q = wpart[0];
+    for (int w2 = 1; w2 < NT / 64; ++w2) {
+      const DiagPart& o = wpart[w2];
+      q.min_trc = fmin(q.min_trc, o.min_trc);
+      q.cfl = fmax(q.cfl, o.cfl);
+      q.esum += o.esum;
+      q.tsum += o.tsum;
+      q.n_lt3 += o.n_lt3;
+      q.n_lt0 += o.n_lt0;
+      q.nonfinite |= o.nonfinite;
+      q.big |= o.big;
+    }
     parts[row] = q;
   }
 }
 
-__global__ __launch_bounds__(256) void diag_final_kernel(Dims d, Phys p, const DiagPart* __restrict__ parts,
-                                                         int zrows, const double* __restrict__ w,
-                                                         DevScalars* __restrict__ sc, DiagRec* __restrict__ ring,
-                                                         int cap) {
-  __shared__ double smin[256], smmin[256], scfl[256], se[256], st_[256];
-  __shared__ unsigned long long s3[256], s0[256], sm3[256], sm0[256];
-  __shared__ int sb[256];
+__global__ __launch_bounds__(NT) void diag_final_kernel(Dims d, Phys p, const DiagPart* __restrict__ parts,
+                                                        int zrows, const double* __restrict__ w,
+                                                        DevScalars* __restrict__ sc, DiagRec* __restrict__ ring,
+                                                        int cap) {
+  __shared__ double smin[NT], smmin[NT], scfl[NT], se[NT], st_[NT];
+  __shared__ unsigned long long s3[NT], s0[NT], sm3[NT], sm0[NT];
+  __shared__ int sb[NT];
   const int tid = threadIdx.x;
   const int n1 = d.N + 1, nrows = n1 * zrows, mid = d.N / 2;
   const double norm = 1.0 / ((double)d.nx * (d.dim == 3 ? d.nz : 1));
   double mn = 1.0 / 0.0, mmn = 1.0 / 0.0, cf = 0, es = 0, ts = 0;
   unsigned long long n3 = 0, n0 = 0, m3 = 0, m0 = 0;
   int b = 0;
-  for (int r = tid; r < nrows; r += blockDim.x) {
+  for (int r = tid; r < nrows; r += NT) {
     const DiagPart q = parts[r];
     const int j = r / zrows;
     const double wj = 0.5 * w[j] * norm;
@@ -584,7 +560,7 @@ __global__ __launch_bounds__(256) void diag_final_kernel(Dims d, Phys p, const D
   sm0[tid] = m0;
   sb[tid] = b;
   __syncthreads();
-  for (int h = blockDim.x / 2; h > 0; h >>= 1) {
+  for (int h = NT / 2; h > 0; h >>= 1) {
     if (tid < h) {
       smin[tid] = fmin(smin[tid], smin[tid + h]);
       smmin[tid] = fmin(smmin[tid], smmin[tid + h]);
@@ -626,9 +602,32 @@ __global__ __launch_bounds__(256) void diag_final_kernel(Dims d, Phys p, const D
 
 }  // namespace
 
+void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const double* yin, double* yout,
+                    const double* kx, const double* tw, hipStream_t s) {
+  hipLaunchKernelGGL(xpencil_kernel<2>, dim3(d.M + 1), dim3(NT), xpencil_lds<2>(plan.L), s, yin, yout, d.M + 1,
+                     d.nkx, plan, kx, reinterpret_cast<const c2*>(tw), p.eps / p.wi);
+}
+
+void launch_xpencil3d(const Dims& d, const Phys& p, const FftPlan& plan, const double* zin, double* zout,
+                      const double* kx, const double* tw, hipStream_t s) {
+  const int rows = (d.M + 1) * d.pz;
+  hipLaunchKernelGGL(xpencil_kernel<3>, dim3(rows), dim3(NT), xpencil_lds<3>(plan.L), s, zin, zout, rows, d.nkx,
+                     plan, kx, reinterpret_cast<const c2*>(tw), p.eps / p.wi);
+}
+
+void launch_zfft(const Dims& d, const FftPlan& plan, const double* in, double* out, int nfields,
+                 const int* src_field, const int* deriv, const double* kz, const double* tw, int inverse, int rows,
+                 hipStream_t s) {
+  const size_t lds = (size_t)ZG * plan.L * sizeof(c2);
+  dim3 grid((d.nkx + ZG - 1) / ZG, rows, nfields);
+  hipLaunchKernelGGL(zfft_kernel, grid, dim3(NT), lds, s, in, out, d.nkx, d.nzs, rows, plan, src_field, deriv, kz,
+                     reinterpret_cast<const c2*>(tw), inverse);
+}
+
 void launch_diag_rows(const Dims& d, const Phys& p, const FftPlan& planx, const double* st, double* prep,
                       double* zbuf, const FftPlan& planz, const double* twx, const double* twz, const double* ydy,
                       DiagPart* parts, hipStream_t s) {
+  (void)p;
   const int n1 = d.N + 1;
   const int n = n1 * d.nm;
   hipLaunchKernelGGL(diag_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, st, prep);
@@ -639,9 +638,15 @@ void launch_diag_rows(const Dims& d, const Phys& p, const FftPlan& planx, const 
     src = zbuf;
     zrows = d.nz;
   }
-  const size_t lds = 4 * (size_t)planx.L * sizeof(c2);
-  hipLaunchKernelGGL(diag_rows_kernel, dim3(n1 * zrows), dim3(256), lds, s, d, p, src, zrows, planx,
+  const size_t lds = 2 * (size_t)planx.L * sizeof(c2);
+  hipLaunchKernelGGL(diag_rows_kernel, dim3(n1 * zrows), dim3(NT), lds, s, d, src, zrows, planx,
                      reinterpret_cast<const c2*>(twx), ydy, parts);
+}
+
+void launch_diag_final(const Dims& d, const Phys& p, const DiagPart* parts, const double* w, DevScalars* sc,
+                       DiagRec* ring, int ring_cap, hipStream_t s) {
+  const int zrows = d.dim == 3 ? d.nz : 1;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(NT), 0, s, d, p, parts, zrows, w, sc, ring, ring_cap);
 }
 
 hipError_t fft_set_attributes() {
@@ -650,21 +655,12 @@ hipError_t fft_set_attributes() {
   if (e == hipSuccess)
     e = hipFuncSetAttribute((const void*)xpencil_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   if (e == hipSuccess) e = hipFuncSetAttribute((const void*)zfft_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  // the row-diagnostics kernel also holds ~14 KB of static LDS for its reductions
+  // the row-diagnostics kernel also holds a little static LDS for its reductions
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)diag_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 96 * 1024);
+    e = hipFuncSetAttribute((const void*)diag_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
   return e;
 }
 
-size_t xpencil_lds_bytes(int dim, int L) {
-  XTable t = dim == 2 ? table2d() : table3d();
-  return xpencil_lds(t.npairs, L, pick_batch(t.npairs, L));
-}
-
-void launch_diag_final(const Dims& d, const Phys& p, const DiagPart* parts, const double* w, DevScalars* sc,
-                       DiagRec* ring, int ring_cap, hipStream_t s) {
-  const int zrows = d.dim == 3 ? d.nz : 1;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(256), 0, s, d, p, parts, zrows, w, sc, ring, ring_cap);
-}
+size_t xpencil_lds_bytes(int dim, int L) { return dim == 2 ? xpencil_lds<2>(L) : xpencil_lds<3>(L); }
 
 }  // namespace pcs

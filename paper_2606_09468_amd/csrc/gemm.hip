@@ -2,12 +2,17 @@
 //
 // The wall-normal transforms (interpolation / differentiation to the padded
 // grid, projection back), the spectral derivatives and the diagonalised
-// Dirichlet solves are all products of a small operator (at most 385 x 385)
-// with a wide matrix whose columns are the real and imaginary parts of every
-// Fourier mode.  One launch evaluates a table of such products; each 64 x 64
-// output tile is one workgroup of four waves, each wave owning a 32 x 32
-// sub-tile made of 2 x 2 MFMA 16x16x4 blocks.  Operands are staged through
-// LDS in K-chunks of 16.
+// Dirichlet solves are products C = alpha A B + beta C of a small operator A
+// (at most 385 x 385, stored K-major so that an MFMA operand fragment is one
+// 128-byte read) with a wide matrix B whose columns are the real and
+// imaginary parts of every Fourier mode.
+//
+// One launch evaluates a table of such products.  A workgroup (four waves)
+// owns a BM x 32 output tile: it stages the whole K x 32 panel of B in LDS
+// with a single round of coalesced loads, then accumulates with 16x16x4
+// MFMAs, reading A fragments straight from the L2-resident operator.  BM is
+// chosen per table by the host: 16 (the four waves split K) for products too
+// small to fill the chip, 64, or 128 for wide products (fewer re-reads of B).
 #include "kernels.hpp"
 
 namespace pcs {
@@ -16,18 +21,18 @@ typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
 template <typename T>
-int gemm_prepare(GemmJob<T>* jobs, int njobs) {
+int gemm_prepare(GemmJob<T>* jobs, int njobs, int bm) {
   int t = 0;
   for (int j = 0; j < njobs; ++j) {
-    jobs[j].tiles_m = (jobs[j].m + GEMM_BM - 1) / GEMM_BM;
-    int tn = (jobs[j].n + GEMM_BN - 1) / GEMM_BN;
+    jobs[j].tiles_m = (jobs[j].m + bm - 1) / bm;
+    const int tn = (jobs[j].n + GEMM_BN - 1) / GEMM_BN;
     jobs[j].tile0 = t;
     t += jobs[j].tiles_m * tn;
   }
   return t;
 }
-template int gemm_prepare<double>(GemmJob<double>*, int);
-template int gemm_prepare<float>(GemmJob<float>*, int);
+template int gemm_prepare<double>(GemmJob<double>*, int, int);
+template int gemm_prepare<float>(GemmJob<float>*, int, int);
 
 __device__ inline dbl4 mfma(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -36,77 +41,193 @@ __device__ inline flt4 mfma(float a, float b, flt4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <typename T, typename V4>
+constexpr int LDB = GEMM_BN + 16;  // padded LDS row of the B panel (spreads the four k rows of a read over the banks)
+
+// Tile shapes.  RB: 16-row blocks per wave.  KS = 1: the four waves stack
+// their rows (BM = 64 RB); KS = 4: the four waves share BM = 16 RB rows and
+// each takes a quarter of K, the partial sums being added through LDS (for
+// small products, where otherwise too few workgroups exist).
+template <int RB, int KS>
+struct Shape {
+  static constexpr int BM = (KS == 1 ? 4 : 1) * RB * 16;
+};
+
+template <typename T, int RB>
+__device__ inline void load_a(T (&a)[4][RB], const GemmJob<T>& J, const int (&arow)[RB], const bool (&aok)[RB], int k0,
+                              int lk) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int k = k0 + 4 * u + lk;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) a[u][rb] = (k < J.k && aok[rb]) ? J.A[(size_t)k * J.lda + arow[rb]] : T(0);
+  }
+}
+
+template <typename T, typename V4, int RB>
+__device__ inline void mma_block(V4 (&acc)[RB][2], const T (&a)[4][RB], const T* Bs, int k0, int kend, int lk,
+                                 int l16) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int kk = k0 + 4 * u;
+    if (kk < kend) {
+      const T b0 = Bs[(kk + lk) * LDB + l16], b1 = Bs[(kk + lk) * LDB + 16 + l16];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        acc[rb][0] = mfma(a[u][rb], b0, acc[rb][0]);
+        acc[rb][1] = mfma(a[u][rb], b1, acc[rb][1]);
+      }
+    }
+  }
+}
+
+template <typename T, typename V4, int RB, int KS>
 __global__ __launch_bounds__(256) void gemm_kernel(const GemmJob<T>* __restrict__ jobs, int njobs) {
-  __shared__ T As[GEMM_BK][GEMM_BM + 1];
-  __shared__ T Bs[GEMM_BK][GEMM_BN + 1];
+  extern __shared__ double gsm[];
+  T* Bs = reinterpret_cast<T*>(gsm);  // [K4][LDB], K rounded up to a multiple of 4
+  constexpr int BM = Shape<RB, KS>::BM;
   const int t = blockIdx.x;
   int jb = 0;
   while (jb + 1 < njobs && jobs[jb + 1].tile0 <= t) ++jb;
   const GemmJob<T> J = jobs[jb];
   const int lt = t - J.tile0;
-  const int row0 = (lt % J.tiles_m) * GEMM_BM;
+  const int row0 = (lt % J.tiles_m) * BM;
   const int col0 = (lt / J.tiles_m) * GEMM_BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wm = (wave & 1) * 32, wn = (wave >> 1) * 32;
-  const int l16 = lane & 15, lk = lane >> 4;
-  V4 acc[2][2];
-  for (int i = 0; i < 2; ++i)
-    for (int j = 0; j < 2; ++j) acc[i][j] = V4{0, 0, 0, 0};
-
-  for (int k0 = 0; k0 < J.k; k0 += GEMM_BK) {
-    for (int e = tid; e < GEMM_BM * GEMM_BK; e += 256) {
-      const int r = e / GEMM_BK, c = e % GEMM_BK;
-      const int gr = row0 + r, gc = k0 + c;
-      As[c][r] = (gr < J.m && gc < J.k) ? J.A[(size_t)gr * J.lda + gc] : T(0);
-    }
-    for (int e = tid; e < GEMM_BK * GEMM_BN; e += 256) {
-      const int r = e / GEMM_BN, c = e % GEMM_BN;
-      const int gr = k0 + r, gc = col0 + c;
-      Bs[r][c] = (gr < J.k && gc < J.n) ? J.B[(size_t)gr * J.ldb + gc] : T(0);
-    }
-    __syncthreads();
+  const int K4 = (J.k + 3) & ~3;
+  // stage the K x 32 panel of B (zero outside the matrix): 16 loads in
+  // flight per thread before any LDS store
+  {
+    constexpr int UNR = 16, RPP = 256 / GEMM_BN;  // rows per pass of the workgroup
+    const int c = tid % GEMM_BN, rr = tid / GEMM_BN;
+    const int gc = col0 + c;
+    const bool cok = gc < J.n;
+    for (int r0 = 0; r0 < K4; r0 += UNR * RPP) {
+      T v[UNR];
 #pragma unroll
-    for (int kk = 0; kk < GEMM_BK; kk += 4) {
-      const int kl = kk + lk;
-      const T a0 = As[kl][wm + l16], a1 = As[kl][wm + 16 + l16];
-      const T b0 = Bs[kl][wn + l16], b1 = Bs[kl][wn + 16 + l16];
-      acc[0][0] = mfma(a0, b0, acc[0][0]);
-      acc[0][1] = mfma(a0, b1, acc[0][1]);
-      acc[1][0] = mfma(a1, b0, acc[1][0]);
-      acc[1][1] = mfma(a1, b1, acc[1][1]);
+      for (int u = 0; u < UNR; ++u) {
+        const int r = r0 + u * RPP + rr;
+        v[u] = (r < J.k && cok) ? J.B[(size_t)r * J.ldb + gc] : T(0);
+      }
+#pragma unroll
+      for (int u = 0; u < UNR; ++u) {
+        const int r = r0 + u * RPP + rr;
+        if (r < K4) Bs[r * LDB + c] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int wrow = row0 + (KS == 1 ? wave * RB * 16 : 0);
+  int kbeg = 0, kend = K4;
+  if (KS > 1) {
+    const int kq = ((K4 / 4 + KS - 1) / KS) * 4;
+    kbeg = min(wave * kq, K4);
+    kend = min(kbeg + kq, K4);
+  }
+  int arow[RB];
+  bool aok[RB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) {
+    arow[rb] = wrow + rb * 16 + l16;
+    aok[rb] = arow[rb] < J.m;
+  }
+  V4 acc[RB][2];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = V4{0, 0, 0, 0};
+  // A fragments come straight from the L2-resident operator, prefetched one
+  // 16-deep block ahead of the products that use them
+  T aA[4][RB], aB[4][RB];
+  if (kbeg < kend) load_a(aA, J, arow, aok, kbeg, lk);
+  for (int k0 = kbeg; k0 < kend; k0 += 32) {
+    if (k0 + 16 < kend) load_a(aB, J, arow, aok, k0 + 16, lk);
+    mma_block<T, V4, RB>(acc, aA, Bs, k0, kend, lk, l16);
+    if (k0 + 32 < kend) load_a(aA, J, arow, aok, k0 + 32, lk);
+    if (k0 + 16 < kend) mma_block<T, V4, RB>(acc, aB, Bs, k0 + 16, kend, lk, l16);
+  }
+  if (KS > 1) {
+    // add the K-quarters: waves 1..3 park their partial tiles in LDS
+    __syncthreads();
+    T* red = Bs;
+    if (wave > 0) {
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) red[(((wave - 1) * RB + rb) * 8 + bj * 4 + r) * 64 + lane] = acc[rb][bj][r];
     }
     __syncthreads();
+    if (wave != 0) return;
+#pragma unroll
+    for (int w2 = 1; w2 < KS; ++w2)
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[rb][bj][r] += red[(((w2 - 1) * RB + rb) * 8 + bj * 4 + r) * 64 + lane];
   }
   // Element D[i][j] of a 16x16 block lives in lane j + 16 * (i / 4), register
   // i % 4 for the f32 instruction, and in lane j + 16 * (i % 4), register
   // i / 4 for the f64 one (checked on gfx950 with a one-hot product).
   constexpr bool f64 = sizeof(T) == 8;
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gr = row0 + wm + bi * 16 + (f64 ? 4 * r + lk : 4 * lk + r);
-        const int gc = col0 + wn + bj * 16 + l16;
+        const int gr = wrow + rb * 16 + (f64 ? 4 * r + lk : 4 * lk + r);
+        const int gc = col0 + bj * 16 + l16;
         if (gr < J.m && gc < J.n) {
           T* cp = J.C + (size_t)gr * J.ldc + gc;
-          T v = J.alpha * acc[bi][bj][r];
+          T v = J.alpha * acc[rb][bj][r];
           if (J.beta != T(0)) v += J.beta * *cp;
           *cp = v;
         }
       }
 }
 
-void gemm_f64(const GemmJob<double>* dev_jobs, int total_tiles, int njobs, hipStream_t s) {
-  if (total_tiles <= 0) return;
-  hipLaunchKernelGGL((gemm_kernel<double, dbl4>), dim3(total_tiles), dim3(256), 0, s, dev_jobs, njobs);
+size_t gemm_lds_bytes(int kmax, int elem) {
+  const size_t panel = (size_t)((kmax + 3) & ~3) * LDB * elem;
+  const size_t red = (size_t)3 * 2 * 8 * 64 * elem;  // KS = 4 partial tiles (RB <= 2)
+  return panel > red ? panel : red;
 }
 
-void gemm_f32(const GemmJob<float>* dev_jobs, int total_tiles, int njobs, hipStream_t s) {
+template <typename T, typename V4>
+hipError_t set_attr_all() {
+  const int lim = 160 * 1024;
+  hipError_t e = hipFuncSetAttribute((const void*)gemm_kernel<T, V4, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)gemm_kernel<T, V4, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void*)gemm_kernel<T, V4, 2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  return e;
+}
+
+hipError_t gemm_set_attributes() {
+  hipError_t e = set_attr_all<double, dbl4>();
+  return e == hipSuccess ? set_attr_all<float, flt4>() : e;
+}
+
+template <typename T, typename V4>
+void launch_gemm(const GemmJob<T>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
   if (total_tiles <= 0) return;
-  hipLaunchKernelGGL((gemm_kernel<float, flt4>), dim3(total_tiles), dim3(256), 0, s, dev_jobs, njobs);
+  const size_t lds = gemm_lds_bytes(kmax, sizeof(T));
+  if (bm == 16)
+    hipLaunchKernelGGL((gemm_kernel<T, V4, 1, 4>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
+  else if (bm == 128)
+    hipLaunchKernelGGL((gemm_kernel<T, V4, 2, 1>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
+  else
+    hipLaunchKernelGGL((gemm_kernel<T, V4, 1, 1>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
+}
+
+void gemm_f64(const GemmJob<double>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
+  launch_gemm<double, dbl4>(dev_jobs, total_tiles, njobs, bm, kmax, s);
+}
+
+void gemm_f32(const GemmJob<float>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
+  launch_gemm<float, flt4>(dev_jobs, total_tiles, njobs, bm, kmax, s);
 }
 
 }  // namespace pcs

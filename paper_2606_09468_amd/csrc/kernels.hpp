@@ -7,9 +7,10 @@
 
 namespace pcs {
 
-// One dense product C = alpha * A * B + beta * C, all row-major, real.
-// Complex fields (re/im interleaved) are multiplied by a real operator by
-// treating each complex column as two real columns.
+// One dense product C = alpha * A * B + beta * C, real.  A (m x k) is stored
+// K-major, A[i][kk] at A[kk * lda + i] (lda >= m); B (k x n) and C (m x n) are
+// row-major.  Complex fields (re/im interleaved) are multiplied by a real
+// operator by treating each complex column as two real columns.
 template <typename T>
 struct GemmJob {
   const T* A;
@@ -20,14 +21,18 @@ struct GemmJob {
   int tiles_m, tile0;  // filled by gemm_prepare
 };
 
-constexpr int GEMM_BM = 64, GEMM_BN = 64, GEMM_BK = 16;
+constexpr int GEMM_BN = 32;  // output columns per workgroup
 constexpr int MAX_JOBS = 64;
 
-// Fills tiles_m / tile0 and returns the total number of tiles.
+// Fills tiles_m / tile0 for row tiles of bm (64 or 128) and returns the
+// total number of workgroups.
 template <typename T>
-int gemm_prepare(GemmJob<T>* jobs, int njobs);
-void gemm_f64(const GemmJob<double>* dev_jobs, int total_tiles, int njobs, hipStream_t s);
-void gemm_f32(const GemmJob<float>* dev_jobs, int total_tiles, int njobs, hipStream_t s);
+int gemm_prepare(GemmJob<T>* jobs, int njobs, int bm);
+// kmax: largest k of the table (sizes the LDS panel of B).
+void gemm_f64(const GemmJob<double>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s);
+void gemm_f32(const GemmJob<float>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s);
+size_t gemm_lds_bytes(int kmax, int elem);
+hipError_t gemm_set_attributes();
 
 // Mixed-radix (4, 2, 3) Stockham plan for a length L = 2^a 3^b.
 struct FftPlan {
