@@ -114,7 +114,8 @@ def main():
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
     ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
-    ap.add_argument("--precision", default="fp64", choices=["fp64"])
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed", "mixed64y"],
+                    help="both: time mixed (value) and FP64 (reported beside it)")
     ap.add_argument("--stage-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -133,71 +134,84 @@ def main():
         build.build()
     w = WORKLOADS[args.workload]
     grid = P.make_grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
-    prm = P.make_params(wi=w["wi"], dt=w["dt"], precision=0)
-    sim = P.Sim(grid, prm, seed=w["seed"], amp=1e-3)
-    print("bench: %s, warmup %d" % (args.workload, args.warmup), file=sys.stderr, flush=True)
-    sim.step(args.warmup)
-    sim.diagnostics()
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    wall0 = time.perf_counter()
-    ev0.record(sim.stream)
-    sim.step(args.steps)
-    ev1.record(sim.stream)
-    ev1.synchronize()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - wall0
-    ms = ev0.elapsed_time(ev1)
-    recs, st = sim.diagnostics()
-    assert st == P.PCS_OK and len(recs) == min(args.steps, 4096) and recs[-1]["blowup"] == 0
-    sps = args.steps / (ms / 1e3)
-    print("bench: timed %d steps in %.3f ms (wall %.3f s)" % (args.steps, ms, wall), file=sys.stderr, flush=True)
-    # per-stage durations (eager launches, HIP events on the run's stream)
-    stages = sim.stage_times(args.stage_steps)
-    sim.close()
-    work = stage_work(w)
+    precs = {"both": [1, 0], "fp64": [0], "mixed": [1], "mixed64y": [2]}[args.precision]
+    timed = {}
+    for prec in precs:
+        prm = P.make_params(wi=w["wi"], dt=w["dt"], precision=prec)
+        sim = P.Sim(grid, prm, seed=w["seed"], amp=1e-3)
+        print("bench: %s precision %d, warmup %d" % (args.workload, prec, args.warmup), file=sys.stderr, flush=True)
+        sim.step(args.warmup)
+        sim.diagnostics()
+        torch.cuda.synchronize()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        wall0 = time.perf_counter()
+        ev0.record(sim.stream)
+        sim.step(args.steps)
+        ev1.record(sim.stream)
+        ev1.synchronize()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - wall0
+        ms = ev0.elapsed_time(ev1)
+        recs, st = sim.diagnostics()
+        assert st == P.PCS_OK and len(recs) == min(args.steps, 4096) and recs[-1]["blowup"] == 0
+        print("bench: timed %d steps in %.3f ms (wall %.3f s)" % (args.steps, ms, wall), file=sys.stderr, flush=True)
+        # per-stage durations (eager launches, HIP events on the run's stream)
+        stages = sim.stage_times(args.stage_steps)
+        sim.close()
+        timed[prec] = dict(ms=ms, sps=args.steps / (ms / 1e3), stages=stages, prm=prm)
+    head = precs[0]
+    ms, sps, stages, prm = timed[head]["ms"], timed[head]["sps"], timed[head]["stages"], timed[head]["prm"]
+    work = stage_work(w, prec_bytes=16 if head == 0 else 8)
     dom = max((k for k in stages if k in work), key=lambda k: stages[k])
     kind, amount = work[dom]
     t = stages[dom] * 1e-3
+    mfma_peak = MFMA_F32_TFS if (head == 1 and dom in ("gemm_state", "gemm_proj")) else MFMA_F64_TFS
     if kind == "hbm":
         roof = dict(kernel=dom, bound="hbm", achieved=amount / t / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
                     traffic=None, algorithmic_bytes=amount, avg_ms=stages[dom])
     else:
-        roof = dict(kernel=dom, bound="mfma", achieved=amount / t / 1e12, peak=MFMA_F64_TFS, unit="TFLOP/s",
+        roof = dict(kernel=dom, bound="mfma", achieved=amount / t / 1e12, peak=mfma_peak, unit="TFLOP/s",
                     traffic=None, algorithmic_flops=amount, avg_ms=stages[dom])
     roof["frac"] = roof["achieved"] / roof["peak"]
     points = w["nx"] * w["ny"] * w["nz"]
     line = {
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": w["desc"], "grid": [w["nx"], w["ny"], w["nz"]], "precision": args.precision,
+        "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64"}[head], "data": "synthetic",
+        "config": {"workload": w["desc"], "grid": [w["nx"], w["ny"], w["nz"]],
+                   "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms"}[head],
                    "parallelism": "single GPU"},
         "grid_point_updates_per_s": sps * points,
         "roofline": roof,
         "stage_ms": stages,
     }
+    if len(precs) > 1:
+        line["fp64"] = {"value": timed[0]["sps"], "ms_per_step": timed[0]["ms"] / args.steps,
+                        "grid_point_updates_per_s": timed[0]["sps"] * points}
+        line["speedup_mixed_vs_fp64"] = timed[1]["sps"] / timed[0]["sps"]
     if not args.no_cpu_baseline:
         print("bench: oracle sample of %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
         o, cb = cpu_baseline(w, args.cpu_steps)
         line["cpu_baseline"] = cb
-        # error of the GPU step against the oracle over the same sample
-        sim2 = P.Sim(grid, prm, seed=w["seed"], amp=1e-3)
-        sim2.step(args.cpu_steps + 1)
-        a = sim2.get_state()
-        recs2, _ = sim2.diagnostics()
-        sim2.close()
-        errs = state_errors(a, o.get_state(), w)
-        d, e = recs2[-1], o.diag[-1]
-        line["error_vs_oracle"] = {
-            "steps": args.cpu_steps + 1,
-            "max_rel_velocity": max(errs[k] for k in errs if k in ("u", "v", "w", "phi", "g")),
-            "max_rel_conformation": max(errs[k] for k in errs if k.startswith("c")),
-            "min_trc_abs": abs(d["min_trc"] - e["min_trc"]),
-            "counts_equal": all(d[k] == e[k] for k in ("n_lt3", "n_lt0", "mid_n_lt3", "mid_n_lt0")),
-        }
+        # error of each timed precision against the oracle over the same sample
+        line["error_vs_oracle"] = {}
+        for prec in precs:
+            sim2 = P.Sim(grid, timed[prec]["prm"], seed=w["seed"], amp=1e-3)
+            sim2.step(args.cpu_steps + 1)
+            a = sim2.get_state()
+            recs2, _ = sim2.diagnostics()
+            sim2.close()
+            errs = state_errors(a, o.get_state(), w)
+            d, e = recs2[-1], o.diag[-1]
+            line["error_vs_oracle"][{0: "fp64", 1: "mixed", 2: "mixed64y"}[prec]] = {
+                "steps": args.cpu_steps + 1,
+                "max_rel_velocity": max(errs[k] for k in errs if k in ("u", "v", "w", "phi", "g")),
+                "max_rel_conformation": max(errs[k] for k in errs if k.startswith("c")),
+                "min_trc_abs": abs(d["min_trc"] - e["min_trc"]),
+                "counts_equal": all(d[k] == e[k] for k in ("n_lt3", "n_lt0", "mid_n_lt3", "mid_n_lt0")),
+            }
     print(json.dumps(line), flush=True)
 
 

@@ -43,24 +43,24 @@ struct Carve {
 };
 
 struct JobList {
-  std::vector<GemmJob<double>> h;
-  GemmJob<double>* dev = nullptr;
+  std::vector<GemmJob> h;
+  GemmJob* dev = nullptr;
+  GemmType type = GEMM_DDD;
   int tiles = 0, bm = 64, kmax = 0;
-  void add(const double* A, int lda, const double* B, int ldb, double* C, int ldc, int m, int n, int k,
-           double alpha = 1.0, double beta = 0.0) {
-    GemmJob<double> j{};
+  void add(const void* A, const void* B, int ldb, void* C, int ldc, int m, int n, int k, int flags = 0) {
+    GemmJob j{};
     j.A = A;
     j.B = B;
     j.C = C;
     j.m = m;
     j.n = n;
     j.k = k;
-    (void)lda;
     j.lda = m;  // operators are stored K-major
     j.ldb = ldb;
     j.ldc = ldc;
-    j.alpha = alpha;
-    j.beta = beta;
+    j.alpha = 1.0;
+    j.beta = 0.0;
+    j.flags = flags;
     h.push_back(j);
   }
   int n() const { return (int)h.size(); }
@@ -79,7 +79,7 @@ struct JobList {
   }
   // shape signature for the tuning cache
   std::vector<int> key() const {
-    std::vector<int> k;
+    std::vector<int> k{(int)type};
     for (auto& j : h) {
       k.push_back(j.m);
       k.push_back(j.n);
@@ -87,14 +87,15 @@ struct JobList {
     }
     return k;
   }
-  void run(hipStream_t s) const { gemm_f64(dev, tiles, n(), bm, kmax, s); }
+  void run(hipStream_t s) const { gemm_run(type, dev, tiles, n(), bm, kmax, s); }
 };
 
 // Row-major (rows x cols) -> K-major copy used as the A operand of the products.
-std::vector<double> kmajor(const std::vector<double>& a, int rows, int cols) {
-  std::vector<double> t((size_t)rows * cols);
+template <typename T = double>
+std::vector<T> kmajor(const std::vector<double>& a, int rows, int cols) {
+  std::vector<T> t((size_t)rows * cols);
   for (int i = 0; i < rows; ++i)
-    for (int k = 0; k < cols; ++k) t[(size_t)k * rows + i] = a[(size_t)i * cols + k];
+    for (int k = 0; k < cols; ++k) t[(size_t)k * rows + i] = (T)a[(size_t)i * cols + k];
   return t;
 }
 
@@ -119,17 +120,23 @@ struct pcs_sim {
   double *twx, *twz, *twbx, *twbz;
   double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *Dc, *D2buf, *sbuf, *hy, *hgn, *Ds, *hvn;
   double *R, *X, *Xs, *Zphi, *Zv, *ZDv, *flux, *CB, *prep, *zbuf;
+  // mixed precision: FP32 operators, twiddles and padded-grid buffers, FP64
+  // mean profiles on the padded grid and the mean-mode fix column
+  float *IMN32, *DMN32, *PNM32, *twx32, *twz32, *Yin32, *Zin32, *Zout32, *Yout32;
+  double *Ybar, *mfix;
   int *zsrc, *zder;
   DiagPart* parts;
   DiagRec* ring;
   DevScalars* sc;
-  JobList G1, G2, G3, G4, G5, H4, H5;
+  JobList G1, G1b, G2, G2b, G3, G4, G5, H4, H5;
+  int prec = 0;
   double wU1 = 0;
   long long drained = 0;
   int blowup = 0;
   size_t nstate = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
+  std::vector<JobList*> lists() { return {&G1, &G1b, &G2, &G2b, &G3, &G4, &G5, &H4, &H5}; }
 };
 
 namespace {
@@ -162,11 +169,23 @@ size_t carve(pcs_sim* m, char* base) {
   m->twbz = c.take<double>(2 * (size_t)d.nz);
   m->infl = c.take<double>(6 * n1 * d.nm + 4 * (size_t)d.nm);
   m->state = c.take<double>((size_t)(m->nq + m->nh) * n1 * cw);
-  m->Yin = c.take<double>((size_t)m->nyin * m1 * cw);
   const size_t zrow = (size_t)m1 * d.pz * d.nkx * 2;
-  m->Zin = d.dim == 3 ? c.take<double>((size_t)m->nzin * zrow) : nullptr;
-  m->Zout = d.dim == 3 ? c.take<double>((size_t)m->nout * zrow) : nullptr;
-  m->Yout = c.take<double>((size_t)m->nout * m1 * cw);
+  const bool mixed = m->prec != 0;
+  m->Yin = !mixed ? c.take<double>((size_t)m->nyin * m1 * cw) : nullptr;
+  m->Zin = (!mixed && d.dim == 3) ? c.take<double>((size_t)m->nzin * zrow) : nullptr;
+  m->Zout = (!mixed && d.dim == 3) ? c.take<double>((size_t)m->nout * zrow) : nullptr;
+  m->Yout = !mixed ? c.take<double>((size_t)m->nout * m1 * cw) : nullptr;
+  m->Yin32 = mixed ? c.take<float>((size_t)m->nyin * m1 * cw) : nullptr;
+  m->Zin32 = (mixed && d.dim == 3) ? c.take<float>((size_t)m->nzin * zrow) : nullptr;
+  m->Zout32 = (mixed && d.dim == 3) ? c.take<float>((size_t)m->nout * zrow) : nullptr;
+  m->Yout32 = mixed ? c.take<float>((size_t)m->nout * m1 * cw) : nullptr;
+  m->IMN32 = mixed ? c.take<float>(m1 * n1) : nullptr;
+  m->DMN32 = mixed ? c.take<float>(m1 * n1) : nullptr;
+  m->PNM32 = mixed ? c.take<float>(n1 * m1) : nullptr;
+  m->twx32 = mixed ? c.take<float>(2 * (size_t)d.px) : nullptr;
+  m->twz32 = mixed ? c.take<float>(2 * (size_t)d.pz) : nullptr;
+  m->Ybar = mixed ? c.take<double>(16 * m1) : nullptr;
+  m->mfix = mixed ? c.take<double>((size_t)m->nout * m1) : nullptr;
   m->S = c.take<double>((size_t)m->nout * n1 * cw);
   m->Dc = c.take<double>((size_t)(d.dim == 2 ? 2 : 3) * n1 * cw);
   m->D2buf = c.take<double>((size_t)m->nsolve * n1 * cw + 2 * n1);
@@ -191,8 +210,7 @@ size_t carve(pcs_sim* m, char* base) {
   m->parts = c.take<DiagPart>(n1 * zrows);
   m->ring = c.take<DiagRec>(RING);
   m->sc = c.take<DevScalars>(1);
-  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5})
-    jl->dev = c.take<GemmJob<double>>(MAX_JOBS);
+  for (JobList* jl : m->lists()) jl->dev = c.take<GemmJob>(MAX_JOBS);
   return c.off;
 }
 
@@ -206,7 +224,8 @@ pcs_status setup_dims(pcs_sim* m, const pcs_grid* g, const pcs_params* p) {
   if (!(p->re > 0) || !(p->wi > 0) || !(p->beta >= 0 && p->beta <= 1) || !(p->kappa >= 0) || !(p->dt > 0))
     return PCS_ERR_ARG;
   if (p->forcing != 0 && p->forcing != 1) return PCS_ERR_ARG;
-  if (p->precision != 0) return PCS_ERR_UNSUPPORTED;
+  if (p->precision < 0 || p->precision > 2) return PCS_ERR_ARG;
+  if (p->precision != 0 && p->eps != 0.0) return PCS_ERR_UNSUPPORTED;  // the mixed split is for bilinear products
   if (!valid_fft(3 * g->nx / 2) || !valid_fft(g->nx)) return PCS_ERR_UNSUPPORTED;
   if (g->dim == 3 && (!valid_fft(3 * g->nz / 2) || !valid_fft(g->nz))) return PCS_ERR_UNSUPPORTED;
   m->g = *g;
@@ -226,7 +245,8 @@ pcs_status setup_dims(pcs_sim* m, const pcs_grid* g, const pcs_params* p) {
   d.nc = g->dim == 2 ? 3 : 6;
   d.lx = g->lx;
   d.lz = g->dim == 2 ? 1.0 : g->lz;
-  if (xpencil_lds_bytes(d.dim, d.px) > 160 * 1024) return PCS_ERR_UNSUPPORTED;
+  m->prec = p->precision;
+  if (xpencil_lds_bytes(d.dim, d.px, m->prec) > 160 * 1024) return PCS_ERR_UNSUPPORTED;
   Phys& q = m->p;
   q.re = p->re;
   q.wi = p->wi;
@@ -394,49 +414,80 @@ void build_jobs(pcs_sim* m) {
   const size_t fs = (size_t)n1 * cw, fsm = (size_t)m1 * cw, fsi = (size_t)ni * cw;
   double* st = m->state;
   const int FC = d.dim == 2 ? 3 : 5, FPHI = d.dim == 2 ? 2 : 3;
-  // G1: products of the state
+  const bool mixed = m->prec != 0;
+  // G1: values and d/dy on the padded grid (mixed: of the fluctuation only,
+  // written in FP32; computed in FP32, or in FP64 for precision 2)
   JobList& g1 = m->G1;
-  const int velI[3] = {0, 1, 2};
+  JobList& g1b = mixed ? m->G1b : m->G1;  // FP64 products of the state
+  g1.type = mixed ? (m->prec == 1 ? GEMM_FDF : GEMM_DDF) : GEMM_DDD;
+  m->G1b.type = GEMM_DDD;
+  const void* I = mixed && m->prec == 1 ? (const void*)m->IMN32 : (const void*)m->IMN;
+  const void* DI = mixed && m->prec == 1 ? (const void*)m->DMN32 : (const void*)m->DMN;
+  void* Y = mixed ? (void*)m->Yin32 : (void*)m->Yin;
+  const size_t ysz = mixed ? sizeof(float) : sizeof(double);
+  auto yf = [&](int f) { return (void*)((char*)Y + (size_t)f * fsm * ysz); };
+  const int zm = mixed ? GEMM_ZERO_MEAN : 0;
   const int nvel = d.dim;
-  for (int a = 0; a < nvel; ++a) g1.add(m->IMN, n1, st + velI[a] * fs, cw, m->Yin + a * fsm, cw, m1, cw, n1);
-  for (int a = 0; a < d.nc; ++a) g1.add(m->IMN, n1, st + (FC + a) * fs, cw, m->Yin + (nvel + a) * fsm, cw, m1, cw, n1);
-  const int yd0 = nvel + d.nc;  // first d/dy field in Yin
-  g1.add(m->DMN, n1, st + 0 * fs, cw, m->Yin + yd0 * fsm, cw, m1, cw, n1);
+  const int vel[3] = {0, 1, 2};
+  for (int a = 0; a < nvel; ++a) g1.add(I, st + vel[a] * fs, cw, yf(a), cw, m1, cw, n1, zm);
+  for (int a = 0; a < d.nc; ++a) g1.add(I, st + (FC + a) * fs, cw, yf(nvel + a), cw, m1, cw, n1, zm);
+  const int yd0 = nvel + d.nc;  // first d/dy field in the padded-grid input
+  g1.add(DI, st + 0 * fs, cw, yf(yd0), cw, m1, cw, n1, zm);
   int o = yd0 + 1;
-  if (d.dim == 3) g1.add(m->DMN, n1, st + 2 * fs, cw, m->Yin + (o++) * fsm, cw, m1, cw, n1);
-  for (int a = 0; a < d.nc; ++a) g1.add(m->DMN, n1, st + (FC + a) * fs, cw, m->Yin + (o++) * fsm, cw, m1, cw, n1);
-  g1.add(m->D2, n1, st + FPHI * fs, cw, m->D2buf + 0 * fs, cw, n1, cw, n1);
-  if (d.dim == 3) g1.add(m->D2, n1, st + 4 * fs, cw, m->D2buf + 1 * fs, cw, n1, cw, n1);
-  for (int a = 0; a < d.nc; ++a) g1.add(m->D2, n1, st + (FC + a) * fs, cw, m->D2buf + (m->nsv + a) * fs, cw, n1, cw, n1);
+  if (d.dim == 3) g1.add(DI, st + 2 * fs, cw, yf(o++), cw, m1, cw, n1, zm);
+  for (int a = 0; a < d.nc; ++a) g1.add(DI, st + (FC + a) * fs, cw, yf(o++), cw, m1, cw, n1, zm);
+  g1b.add(m->D2, st + FPHI * fs, cw, m->D2buf + 0 * fs, cw, n1, cw, n1);
+  if (d.dim == 3) g1b.add(m->D2, st + 4 * fs, cw, m->D2buf + 1 * fs, cw, n1, cw, n1);
+  for (int a = 0; a < d.nc; ++a) g1b.add(m->D2, st + (FC + a) * fs, cw, m->D2buf + (m->nsv + a) * fs, cw, n1, cw, n1);
   double* D2U = m->D2buf + (size_t)m->nsolve * fs;
-  g1.add(m->D2, n1, st + 0 * fs, cw, D2U, 1, n1, 1, n1);
-  if (d.dim == 3) g1.add(m->D2, n1, st + 2 * fs, cw, D2U + n1, 1, n1, 1, n1);
+  g1b.add(m->D2, st + 0 * fs, cw, D2U, 1, n1, 1, n1);
+  if (d.dim == 3) g1b.add(m->D2, st + 2 * fs, cw, D2U + n1, 1, n1, 1, n1);
   // D c_y. for the stress divergence: 2D c_xy, c_yy; 3D c_xy, c_yy, c_yz
   const int dci[3] = {1, d.dim == 2 ? 2 : 3, 4};
-  for (int q = 0; q < (d.dim == 2 ? 2 : 3); ++q)
-    g1.add(m->D, n1, st + (FC + dci[q]) * fs, cw, m->Dc + q * fs, cw, n1, cw, n1);
-  // G2: projection of the explicit terms
-  for (int f = 0; f < m->nout; ++f) m->G2.add(m->PNM, m1, m->Yout + f * fsm, cw, m->S + f * fs, cw, n1, cw, m1);
+  for (int q = 0; q < (d.dim == 2 ? 2 : 3); ++q) g1b.add(m->D, st + (FC + dci[q]) * fs, cw, m->Dc + q * fs, cw, n1, cw, n1);
+  if (mixed) {
+    // FP64 mean profiles on the padded grid (real part of the kx = kz = 0 column)
+    // 2D: U U' c (3) c' (3); 3D: U W U' W' c (6) c' (6)
+    double* Yb = m->Ybar;
+    int q = 0;
+    g1b.add(m->IMN, st + 0 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    if (d.dim == 3) g1b.add(m->IMN, st + 2 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    g1b.add(m->DMN, st + 0 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    if (d.dim == 3) g1b.add(m->DMN, st + 2 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    for (int a = 0; a < d.nc; ++a) g1b.add(m->IMN, st + (FC + a) * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    for (int a = 0; a < d.nc; ++a) g1b.add(m->DMN, st + (FC + a) * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+  }
+  // G2: projection of the explicit terms (mixed: FP32 operands, FP64 result;
+  // then the mean column again in FP64 from the mean-mode fix)
+  m->G2.type = mixed ? (m->prec == 1 ? GEMM_FFD : GEMM_DFD) : GEMM_DDD;
+  const void* P = mixed && m->prec == 1 ? (const void*)m->PNM32 : (const void*)m->PNM;
+  const void* Yo = mixed ? (const void*)m->Yout32 : (const void*)m->Yout;
+  for (int f = 0; f < m->nout; ++f)
+    m->G2.add(P, (const char*)Yo + (size_t)f * fsm * ysz, cw, m->S + f * fs, cw, n1, cw, m1);
+  if (mixed) {
+    m->G2b.type = GEMM_DDD;
+    for (int f = 0; f < m->nout; ++f) m->G2b.add(m->PNM, m->mfix + (size_t)f * m1, 1, m->S + f * fs, cw, n1, 1, m1);
+  }
   // G3: D s
-  m->G3.add(m->D, n1, m->sbuf, cw, m->Ds, cw, n1, cw, n1);
+  m->G3.add(m->D, m->sbuf, cw, m->Ds, cw, n1, cw, n1);
   // G4: V^-1 R
-  for (int f = 0; f < m->nsolve; ++f) m->G4.add(m->Vinv, ni, m->R + f * fsi, cw, m->X + f * fsi, cw, ni, cw, ni);
-  m->H4.add(m->Vinv, ni, m->R, cw, m->X, cw, ni, cw, ni);
+  for (int f = 0; f < m->nsolve; ++f) m->G4.add(m->Vinv, m->R + f * fsi, cw, m->X + f * fsi, cw, ni, cw, ni);
+  m->H4.add(m->Vinv, m->R, cw, m->X, cw, ni, cw, ni);
   // G5: back from the eigenbasis
   for (JobList* jl : {&m->G5, &m->H5}) {
-    jl->add(m->V, ni, m->Xs + 0 * fsi, cw, m->Zphi, cw, ni, cw, ni);
-    jl->add(m->V, ni, m->Xs + 1 * fsi, cw, m->Zv, cw, ni, cw, ni);
-    jl->add(m->DV, ni, m->Xs + 1 * fsi, cw, m->ZDv, cw, n1, cw, ni);
+    jl->add(m->V, m->Xs + 0 * fsi, cw, m->Zphi, cw, ni, cw, ni);
+    jl->add(m->V, m->Xs + 1 * fsi, cw, m->Zv, cw, ni, cw, ni);
+    jl->add(m->DV, m->Xs + 1 * fsi, cw, m->ZDv, cw, n1, cw, ni);
   }
   int xo = 2;
   if (d.dim == 3) {
-    m->G5.add(m->V, ni, m->Xs + 2 * fsi, cw, st + 4 * fs + cw, cw, ni, cw, ni);
+    m->G5.add(m->V, m->Xs + 2 * fsi, cw, st + 4 * fs + cw, cw, ni, cw, ni);
     xo = 3;
   }
-  for (int a = 0; a < d.nc; ++a)
-    m->G5.add(m->V, ni, m->Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
-  m->G5.add(m->wV, ni, m->Xs + 0 * fsi, cw, m->flux, cw, 1, cw, ni);
-  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5}) jl->prepare();
+  for (int a = 0; a < d.nc; ++a) m->G5.add(m->V, m->Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
+  m->G5.add(m->wV, m->Xs + 0 * fsi, cw, m->flux, cw, 1, cw, ni);
+  for (JobList* jl : m->lists())
+    if (jl->n()) jl->prepare();
 }
 
 // Stage boundaries: mark(i) is called before stage i and once more at the
@@ -457,19 +508,31 @@ template <typename Mark>
 void explicit_stage(pcs_sim* m, const Mark& mark) {
   const Dims& d = m->d;
   hipStream_t s = m->s;
+  const bool mixed = m->prec != 0;
   mark(ST_GEMM_STATE);
   m->G1.run(s);
+  if (mixed) m->G1b.run(s);
+  const void* twx = mixed ? (const void*)m->twx32 : (const void*)m->twx;
+  const void* twz = mixed ? (const void*)m->twz32 : (const void*)m->twz;
+  const void* yin = mixed ? (const void*)m->Yin32 : (const void*)m->Yin;
+  void* yout = mixed ? (void*)m->Yout32 : (void*)m->Yout;
+  void* zin = mixed ? (void*)m->Zin32 : (void*)m->Zin;
+  void* zout = mixed ? (void*)m->Zout32 : (void*)m->Zout;
   mark(ST_ZFFT_INV);
-  if (d.dim == 3) launch_zfft(d, m->plz, m->Yin, m->Zin, m->nzin, m->zsrc, m->zder, m->kz, m->twz, 1, d.M + 1, s);
+  if (d.dim == 3) launch_zfft(d, m->plz, yin, zin, m->nzin, m->zsrc, m->zder, m->kz, twz, 1, d.M + 1, m->prec, s);
   mark(ST_XPENCIL);
   if (d.dim == 3)
-    launch_xpencil3d(d, m->p, m->plx, m->Zin, m->Zout, m->kx, m->twx, s);
+    launch_xpencil(d, m->p, m->plx, zin, zout, m->kx, twx, m->prec, m->Ybar, s);
   else
-    launch_xpencil(d, m->p, m->plx, m->Yin, m->Yout, m->kx, m->twx, s);
+    launch_xpencil(d, m->p, m->plx, yin, yout, m->kx, twx, m->prec, m->Ybar, s);
   mark(ST_ZFFT_FWD);
-  if (d.dim == 3) launch_zfft(d, m->plz, m->Zout, m->Yout, m->nout, nullptr, nullptr, m->kz, m->twz, 0, d.M + 1, s);
+  if (d.dim == 3) launch_zfft(d, m->plz, zout, yout, m->nout, nullptr, nullptr, m->kz, twz, 0, d.M + 1, m->prec, s);
   mark(ST_GEMM_PROJ);
   m->G2.run(s);
+  if (mixed) {
+    launch_mean_fix(d, m->Yout32, m->Ybar, m->mfix, s);
+    m->G2b.run(s);
+  }
   mark(ST_ASSEMBLE);
   const size_t fs = (size_t)(d.N + 1) * d.cw;
   launch_assemble_h(d, m->p, m->S, m->state + (d.dim == 2 ? 3 : 5) * fs, m->Dc, m->kx, m->kz, m->sbuf, m->hy, m->hgn,
@@ -584,6 +647,14 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
   HIPCHK(up(m->kz, kz, s));
   HIPCHK(up(m->twx, twiddles(d.px, -1), s));
   HIPCHK(up(m->twbx, twiddles(d.nx, -1), s));
+  if (m->prec != 0) {
+    HIPCHK(up(m->IMN32, kmajor<float>(op->IMN, m1, n1), s));
+    HIPCHK(up(m->DMN32, kmajor<float>(op->DMN, m1, n1), s));
+    HIPCHK(up(m->PNM32, kmajor<float>(op->PNM, n1, m1), s));
+    auto tf = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
+    HIPCHK(up(m->twx32, tf(twiddles(d.px, -1)), s));
+    if (d.dim == 3) HIPCHK(up(m->twz32, tf(twiddles(d.pz, -1)), s));
+  }
   if (d.dim == 3) {
     HIPCHK(up(m->twz, twiddles(d.pz, -1), s));
     HIPCHK(up(m->twbz, twiddles(d.nz, -1), s));
@@ -608,8 +679,8 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
   sc0.pi = m->p.forcing == 1 ? m->p.q_or_dpdx : 2.0 / m->p.re;
   HIPCHK(hipMemcpy(m->sc, &sc0, sizeof(sc0), hipMemcpyHostToDevice));
   // GEMM job tables
-  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5})
-    HIPCHK(up(jl->dev, jl->h, s));
+  for (JobList* jl : m->lists())
+    if (jl->n()) HIPCHK(up(jl->dev, jl->h, s));
   return PCS_OK;
 }
 
@@ -632,7 +703,8 @@ pcs_status autotune(pcs_sim* m) {
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (JobList* jl : {&m->G1, &m->G2, &m->G3, &m->G4, &m->G5, &m->H4, &m->H5}) {
+  for (JobList* jl : m->lists()) {
+    if (!jl->n()) continue;
     const auto key = jl->key();
     auto it = tune_cache().find(key);
     int best = -1;

@@ -43,37 +43,55 @@ bool make_plan(int L, FftPlan* p) {
 
 namespace {
 
-constexpr int NT = 256;     // threads per workgroup of the transform kernels
-constexpr int MAXV = 12;    // complex values a thread holds in one pass
+constexpr int NT = 256;  // threads per workgroup of the transform kernels
 
-struct c2 {
-  double x, y;
+// complex values a thread holds in one pass (24 doubles' worth of registers)
+template <typename T>
+__host__ __device__ constexpr int maxv() {
+  return 12;
+}
+
+template <typename T>
+struct cx {
+  T x, y;
 };
-__device__ inline c2 operator+(c2 a, c2 b) { return c2{a.x + b.x, a.y + b.y}; }
-__device__ inline c2 operator-(c2 a, c2 b) { return c2{a.x - b.x, a.y - b.y}; }
-__device__ inline c2 cmul(c2 a, c2 b) { return c2{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x}; }
-__device__ inline c2 scal(double s, c2 a) { return c2{s * a.x, s * a.y}; }
+template <typename T>
+__device__ inline cx<T> operator+(cx<T> a, cx<T> b) {
+  return cx<T>{a.x + b.x, a.y + b.y};
+}
+template <typename T>
+__device__ inline cx<T> operator-(cx<T> a, cx<T> b) {
+  return cx<T>{a.x - b.x, a.y - b.y};
+}
+template <typename T>
+__device__ inline cx<T> cmul(cx<T> a, cx<T> b) {
+  return cx<T>{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+template <typename T>
+__device__ inline cx<T> scal(T s, cx<T> a) {
+  return cx<T>{s * a.x, s * a.y};
+}
 
 // R-point DFT in registers; sign -1 forward, +1 inverse.
-template <int R>
-__device__ inline void butterfly(c2* v, int sign) {
+template <typename T, int R>
+__device__ inline void butterfly(cx<T>* v, int sign) {
   if constexpr (R == 2) {
-    c2 t = v[0];
+    cx<T> t = v[0];
     v[0] = t + v[1];
     v[1] = t - v[1];
   } else if constexpr (R == 4) {
-    c2 a = v[0] + v[2], b = v[0] - v[2], c = v[1] + v[3], d = v[1] - v[3];
-    c2 sid = sign > 0 ? c2{-d.y, d.x} : c2{d.y, -d.x};  // (sign i) d
+    cx<T> a = v[0] + v[2], b = v[0] - v[2], c = v[1] + v[3], d = v[1] - v[3];
+    cx<T> sid = sign > 0 ? cx<T>{-d.y, d.x} : cx<T>{d.y, -d.x};  // (sign i) d
     v[0] = a + c;
     v[2] = a - c;
     v[1] = b + sid;
     v[3] = b - sid;
   } else {
-    const double h = 0.86602540378443864676 * sign;  // sign * sqrt(3)/2
-    c2 t1 = v[1] + v[2];
-    c2 t2 = v[0] - scal(0.5, t1);
-    c2 t3 = scal(h, v[1] - v[2]);
-    c2 it3 = c2{-t3.y, t3.x};
+    const T h = T(0.86602540378443864676) * T(sign);  // sign * sqrt(3)/2
+    cx<T> t1 = v[1] + v[2];
+    cx<T> t2 = v[0] - scal(T(0.5), t1);
+    cx<T> t3 = scal(h, v[1] - v[2]);
+    cx<T> it3 = cx<T>{-t3.y, t3.x};
     v[0] = v[0] + t1;
     v[1] = t2 + it3;
     v[2] = t2 - it3;
@@ -82,18 +100,18 @@ __device__ inline void butterfly(c2* v, int sign) {
 
 // One in-place Stockham pass of radix R over nseq sequences of length L.
 // Ns = product of the radices of the earlier passes; tw[m] = exp(-2 pi i m/L).
-// Requires nseq * L / R <= NT * (MAXV / R).
-template <int R>
-__device__ void pass_ip(c2* buf, int L, int nseq, int Ns, const c2* __restrict__ tw, int sign) {
-  constexpr int NB = MAXV / R;
+// Requires nseq * L <= NT * maxv<T>().
+template <typename T, int R>
+__device__ void pass_ip(cx<T>* buf, int L, int nseq, int Ns, const cx<T>* __restrict__ tw, int sign) {
+  constexpr int NB = maxv<T>() / R;
   const int LR = L / R, stride = L / (Ns * R), tot = nseq * LR;
-  c2 v[NB][R];
+  cx<T> v[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int idx = threadIdx.x + q * NT;
     if (idx < tot) {
       const int s = idx / LR, j = idx - s * LR;
-      const c2* src = buf + (size_t)s * L + j;
+      const cx<T>* src = buf + (size_t)s * L + j;
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
     }
@@ -108,13 +126,13 @@ __device__ void pass_ip(c2* buf, int L, int nseq, int Ns, const c2* __restrict__
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
-          c2 w = tw[r * k * stride];
+          cx<T> w = tw[r * k * stride];
           if (sign > 0) w.y = -w.y;
           v[q][r] = cmul(v[q][r], w);
         }
       }
-      butterfly<R>(v[q], sign);
-      c2* dst = buf + (size_t)s * L + (j - k) * R + k;
+      butterfly<T, R>(v[q], sign);
+      cx<T>* dst = buf + (size_t)s * L + (j - k) * R + k;
 #pragma unroll
       for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
     }
@@ -122,46 +140,54 @@ __device__ void pass_ip(c2* buf, int L, int nseq, int Ns, const c2* __restrict__
   __syncthreads();
 }
 
-__device__ void lds_fft(c2* buf, const FftPlan& pl, int nseq, const c2* __restrict__ tw, int sign) {
+template <typename T>
+__device__ void lds_fft(cx<T>* buf, const FftPlan& pl, int nseq, const cx<T>* __restrict__ tw, int sign) {
   int Ns = 1;
   for (int ps = 0; ps < pl.npass; ++ps) {
     const int R = pl.radix[ps];
     if (R == 4)
-      pass_ip<4>(buf, pl.L, nseq, Ns, tw, sign);
+      pass_ip<T, 4>(buf, pl.L, nseq, Ns, tw, sign);
     else if (R == 2)
-      pass_ip<2>(buf, pl.L, nseq, Ns, tw, sign);
+      pass_ip<T, 2>(buf, pl.L, nseq, Ns, tw, sign);
     else
-      pass_ip<3>(buf, pl.L, nseq, Ns, tw, sign);
+      pass_ip<T, 3>(buf, pl.L, nseq, Ns, tw, sign);
     Ns *= R;
   }
 }
 
 // Largest batch of sequences a pass can hold in registers.
-__host__ __device__ inline int fft_batch(int L) { return (NT * MAXV) / L; }
+template <typename T>
+__host__ __device__ inline int fft_batch(int L) {
+  return (NT * maxv<T>()) / L;
+}
 
 // Hermitian packing of two real-field spectra A_k, B_k into the complex
 // sequence whose inverse transform is a + i b.
-__device__ inline void pack_pair(c2* X, int L, int k, c2 A, c2 B) {
+template <typename T>
+__device__ inline void pack_pair(cx<T>* X, int L, int k, cx<T> A, cx<T> B) {
   if (k == 0) {
-    X[0] = c2{A.x, B.x};
+    X[0] = cx<T>{A.x, B.x};
   } else {
-    X[k] = c2{A.x - B.y, A.y + B.x};
-    X[L - k] = c2{A.x + B.y, B.x - A.y};
+    X[k] = cx<T>{A.x - B.y, A.y + B.x};
+    X[L - k] = cx<T>{A.x + B.y, B.x - A.y};
   }
 }
 
 // Spectra of the two real fields packed in a forward transform Z, at k.
-__device__ inline void unpack_pair(const c2* Z, int L, int k, c2& A, c2& B) {
-  const c2 Zk = Z[k];
+template <typename T>
+__device__ inline void unpack_pair(const cx<T>* Z, int L, int k, cx<T>& A, cx<T>& B) {
+  const cx<T> Zk = Z[k];
   if (k == 0) {
-    A = c2{Zk.x, 0};
-    B = c2{Zk.y, 0};
+    A = cx<T>{Zk.x, 0};
+    B = cx<T>{Zk.y, 0};
   } else {
-    const c2 Zc = Z[L - k];
-    A = c2{0.5 * (Zk.x + Zc.x), 0.5 * (Zk.y - Zc.y)};
-    B = c2{0.5 * (Zk.y + Zc.y), -0.5 * (Zk.x - Zc.x)};
+    const cx<T> Zc = Z[L - k];
+    A = cx<T>{T(0.5) * (Zk.x + Zc.x), T(0.5) * (Zk.y - Zc.y)};
+    B = cx<T>{T(0.5) * (Zk.y + Zc.y), T(-0.5) * (Zk.x - Zc.x)};
   }
 }
+
+typedef cx<double> c2;
 
 // index of c_ab in the stored list (2D: xx xy yy; 3D: xx xy xz yy yz zz)
 __host__ __device__ constexpr int cidx(int dim, int a, int b) {
@@ -236,39 +262,106 @@ __device__ inline void pointwise(const Rd& r, double* o, double eps_wi) {
     }
 }
 
-template <int DIM>
-__global__ __launch_bounds__(NT) void xpencil_kernel(const double* __restrict__ in, double* __restrict__ out,
-                                                     int nrows, int nkx, FftPlan pl, const double* __restrict__ kx,
-                                                     const c2* __restrict__ tw, double eps_wi) {
+// Mixed precision split: every padded-grid field is mean(y') + fluctuation,
+// the mean being the kx = kz = 0 profile.  Mean profile index of each real
+// field (-1: the field has no mean part):
+//  2D means: U U' cxx cxy cyy cxx' cxy' cyy'
+//  3D means: U W U' W' c (6) c' (6)
+__host__ __device__ constexpr int mean_of(int dim, int f) {
+  return dim == 2 ? (f == 0 ? 0 : f == 3 ? 1 : (f >= 5 && f <= 7) ? f - 3 : (f >= 11 && f <= 13) ? f - 6 : -1)
+                  : (f == 0 ? 0 : f == 2 ? 1 : f == 18 ? 2 : f == 19 ? 3 : (f >= 3 && f <= 8) ? f + 1
+                                                                         : (f >= 20 && f <= 25) ? f - 10 : -1);
+}
+__host__ __device__ constexpr int n_means(int dim) { return dim == 2 ? 8 : 16; }
+
+template <typename T>
+struct MF {
+  T m, f;  // mean part and fluctuation
+};
+// fluctuation-containing part of the product of two split fields:
+// a b - abar bbar = (abar + a') b' + a' bbar
+template <typename T>
+__device__ inline T fprod(MF<T> a, MF<T> b) {
+  return (a.m + a.f) * b.f + a.f * b.m;
+}
+
+// Fluctuation-containing part of the products of eqs. (1)-(2) (eps = 0);
+// r(f), m(f): fluctuation and mean of real field f at the point.
+template <int DIM, typename T, typename Rd, typename Md>
+__device__ inline void pointwise_mixed(const Rd& r, const Md& m, T* o) {
+  auto F = [&](int f) -> MF<T> { return MF<T>{m(f), r(f)}; };
+  auto neg = [](MF<T> a) -> MF<T> { return MF<T>{-a.m, -a.f}; };
+  auto du = [&](int k, int a) -> MF<T> {
+    if constexpr (DIM == 2) {
+      if (k == 0) return a == 0 ? F(2) : F(4);
+      return a == 0 ? F(3) : neg(F(2));
+    } else {
+      if (k == 0) return F(9 + a);
+      if (k == 2) return F(26 + a);
+      if (a == 0) return F(18);
+      if (a == 2) return F(19);
+      return MF<T>{-(m(9) + m(28)), -(r(9) + r(28))};
+    }
+  };
+  constexpr int C0 = DIM == 2 ? 5 : 3;
+  constexpr int DX = DIM == 2 ? 8 : 12, DY = DIM == 2 ? 11 : 20, DZ = 29;
+  auto c = [&](int a, int b) -> MF<T> { return F(C0 + cidx(DIM, a, b)); };
+  auto dc = [&](int k, int q) -> MF<T> { return F((k == 0 ? DX : (k == 1 ? DY : DZ)) + q); };
+#pragma unroll
+  for (int a = 0; a < DIM; ++a) {
+    T s = 0;
+#pragma unroll
+    for (int k = 0; k < DIM; ++k) s += fprod(F(k), du(k, a));
+    o[a] = -s;
+  }
+  int q = 0;
+#pragma unroll
+  for (int a = 0; a < DIM; ++a)
+#pragma unroll
+    for (int b = a; b < DIM; ++b) {
+      T f = 0;
+#pragma unroll
+      for (int k = 0; k < DIM; ++k) f += -fprod(F(k), dc(k, q)) + fprod(du(k, a), c(k, b)) + fprod(c(a, k), du(k, b));
+      o[DIM + q] = f;
+      ++q;
+    }
+}
+
+// mean: [n_means][M+1] FP64 profiles (MIXED only); pz: padded z rows per y'.
+template <typename T, int DIM, bool MIXED>
+__global__ __launch_bounds__(NT) void xpencil_kernel(const T* __restrict__ in, T* __restrict__ out, int nrows,
+                                                     int nkx, FftPlan pl, const double* __restrict__ kx,
+                                                     const cx<T>* __restrict__ tw, double eps_wi,
+                                                     const double* __restrict__ mean, int m1, int pz) {
   using XS = XShape<DIM>;
   extern __shared__ double smem_d[];
-  c2* P = reinterpret_cast<c2*>(smem_d);
+  cx<T>* P = reinterpret_cast<cx<T>*>(smem_d);
   const int L = pl.L;
   const int row = blockIdx.x, tid = threadIdx.x;
   const size_t fstride = (size_t)nrows * nkx * 2;
-  const double* base = in + (size_t)row * nkx * 2;
-  const int S = fft_batch(L);
+  const T* base = in + (size_t)row * nkx * 2;
+  const int S = fft_batch<T>(L);
   const short* src = XSRC[DIM - 2];
   const short* dxf = XDX[DIM - 2];
   for (int b0 = 0; b0 < XS::NP; b0 += S) {
     const int nb = min(S, XS::NP - b0);
-    c2* X = P + (size_t)b0 * L;
-    for (int e = tid; e < nb * L; e += NT) X[e] = c2{0, 0};
+    cx<T>* X = P + (size_t)b0 * L;
+    for (int e = tid; e < nb * L; e += NT) X[e] = cx<T>{0, 0};
     __syncthreads();
     for (int e = tid; e < nb * nkx; e += NT) {
       const int q = e / nkx, k = e - q * nkx;
       const int fa = 2 * (b0 + q), fb = fa + 1;
-      const double kk = kx[k];
-      c2 A{0, 0}, B{0, 0};
+      const T kk = T(kx[k]);
+      cx<T> A{0, 0}, B{0, 0};
       {
-        const double* p = base + src[fa] * fstride + 2 * k;
-        A = c2{p[0], p[1]};
-        if (dxf[fa]) A = c2{-kk * A.y, kk * A.x};
+        const T* p = base + src[fa] * fstride + 2 * k;
+        A = cx<T>{p[0], p[1]};
+        if (dxf[fa]) A = cx<T>{-kk * A.y, kk * A.x};
       }
       if (fb < XS::NREAL) {
-        const double* p = base + src[fb] * fstride + 2 * k;
-        B = c2{p[0], p[1]};
-        if (dxf[fb]) B = c2{-kk * B.y, kk * B.x};
+        const T* p = base + src[fb] * fstride + 2 * k;
+        B = cx<T>{p[0], p[1]};
+        if (dxf[fb]) B = cx<T>{-kk * B.y, kk * B.x};
       }
       pack_pair(X + (size_t)q * L, L, k, A, B);
     }
@@ -276,34 +369,45 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const double* __restrict__ 
     lds_fft(X, pl, nb, tw, +1);
   }
   // pointwise products; outputs overwrite the first pairs at the same point
+  T mrow[16];
+  if constexpr (MIXED) {
+    const int yrow = row / pz;
+#pragma unroll
+    for (int i = 0; i < n_means(DIM); ++i) mrow[i] = T(mean[(size_t)i * m1 + yrow]);
+  }
   for (int n = tid; n < L; n += NT) {
-    double o[2 * XS::NOP];
-    auto rd = [&](int f) -> double {
-      const c2& z = P[(size_t)(f >> 1) * L + n];
+    T o[2 * XS::NOP];
+    auto rd = [&](int f) -> T {
+      const cx<T>& z = P[(size_t)(f >> 1) * L + n];
       return (f & 1) ? z.y : z.x;
     };
-    pointwise<DIM>(rd, o, eps_wi);
-    if constexpr (XS::NOUT & 1) o[2 * XS::NOP - 1] = 0.0;
+    if constexpr (MIXED) {
+      auto md = [&](int f) -> T { return mean_of(DIM, f) >= 0 ? mrow[mean_of(DIM, f)] : T(0); };
+      pointwise_mixed<DIM, T>(rd, md, o);
+    } else {
+      pointwise<DIM>(rd, o, eps_wi);
+    }
+    if constexpr (XS::NOUT & 1) o[2 * XS::NOP - 1] = 0;
 #pragma unroll
-    for (int q = 0; q < XS::NOP; ++q) P[(size_t)q * L + n] = c2{o[2 * q], o[2 * q + 1]};
+    for (int q = 0; q < XS::NOP; ++q) P[(size_t)q * L + n] = cx<T>{o[2 * q], o[2 * q + 1]};
   }
   __syncthreads();
-  const double inv = 1.0 / L;
-  double* obase = out + (size_t)row * nkx * 2;
+  const T inv = T(1.0 / L);
+  T* obase = out + (size_t)row * nkx * 2;
   for (int q0 = 0; q0 < XS::NOP; q0 += S) {
     const int nb = min(S, XS::NOP - q0);
-    c2* Z = P + (size_t)q0 * L;
+    cx<T>* Z = P + (size_t)q0 * L;
     lds_fft(Z, pl, nb, tw, -1);
     for (int e = tid; e < nb * nkx; e += NT) {
       const int q = e / nkx, k = e - q * nkx;
-      c2 A, B;
+      cx<T> A, B;
       unpack_pair(Z + (size_t)q * L, L, k, A, B);
       const int fa = 2 * (q0 + q), fb = fa + 1;
-      double* pa = obase + (size_t)fa * fstride + 2 * k;
+      T* pa = obase + (size_t)fa * fstride + 2 * k;
       pa[0] = A.x * inv;
       pa[1] = A.y * inv;
       if (fb < XS::NOUT) {
-        double* pb = obase + (size_t)fb * fstride + 2 * k;
+        T* pb = obase + (size_t)fb * fstride + 2 * k;
         pb[0] = B.x * inv;
         pb[1] = B.y * inv;
       }
@@ -311,9 +415,9 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const double* __restrict__ 
   }
 }
 
-template <int DIM>
+template <typename T, int DIM>
 size_t xpencil_lds(int L) {
-  return (size_t)XShape<DIM>::NP * L * sizeof(c2);
+  return (size_t)XShape<DIM>::NP * L * sizeof(cx<T>);
 }
 
 // ---------------------------------------------------------------- z columns
@@ -323,10 +427,12 @@ size_t xpencil_lds(int L) {
 // transformed, divided by Lz and truncated to the retained slots.
 constexpr int ZG = 16;  // kx columns per workgroup
 
-__global__ __launch_bounds__(NT) void zfft_kernel(const double* __restrict__ in, double* __restrict__ out, int nkx,
-                                                  int nzs, int rows_y, FftPlan pl, const int* __restrict__ src_field,
+template <typename T>
+__global__ __launch_bounds__(NT) void zfft_kernel(const T* __restrict__ in, T* __restrict__ out, int nkx, int nzs,
+                                                  int rows_y, FftPlan pl, const int* __restrict__ src_field,
                                                   const int* __restrict__ deriv, const double* __restrict__ kz,
-                                                  const c2* __restrict__ tw, int inverse) {
+                                                  const cx<T>* __restrict__ tw, int inverse) {
+  typedef cx<T> c2;
   extern __shared__ double smem_z[];
   c2* A = reinterpret_cast<c2*>(smem_z);
   const int L = pl.L;
@@ -336,8 +442,8 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const double* __restrict__ in,
   const int rin = inverse ? nzs : L, rout = inverse ? L : nzs;
   const int sf = src_field ? src_field[f] : f;
   const int dz = deriv ? deriv[f] : 0;
-  const double* ib = in + ((size_t)sf * rows_y + i) * rin * nkx * 2;
-  double* ob = out + ((size_t)f * rows_y + i) * rout * nkx * 2;
+  const T* ib = in + ((size_t)sf * rows_y + i) * rin * nkx * 2;
+  T* ob = out + ((size_t)f * rows_y + i) * rout * nkx * 2;
   if (inverse) {
     for (int e = tid; e < ZG * L; e += NT) A[e] = c2{0, 0};
     __syncthreads();
@@ -347,7 +453,7 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const double* __restrict__ in,
       const int mz = (s < nzs / 2) ? s : s - nzs;
       c2 v = c2{ib[((size_t)s * nkx + k0 + g) * 2], ib[((size_t)s * nkx + k0 + g) * 2 + 1]};
       if (dz) {
-        const double kk = kz[s];
+        const T kk = T(kz[s]);
         v = c2{-kk * v.y, kk * v.x};
       }
       A[(size_t)g * L + ((mz % L) + L) % L] = v;
@@ -368,7 +474,7 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const double* __restrict__ in,
       ob[((size_t)z * nkx + k0 + g) * 2 + 1] = v.y;
     }
   } else {
-    const double inv = 1.0 / L;
+    const T inv = T(1.0 / L);
     for (int e = tid; e < nzs * ng; e += NT) {
       const int s = e / ng, g = e - s * ng;
       c2 v{0, 0};
@@ -600,28 +706,82 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(Dims d, Phys p, const Di
   }
 }
 
+// Mean-mode fix of the mixed path: the kx = kz = 0 column of each explicit
+// term on the padded grid is the FP32 mean of the fluctuation products plus
+// the FP64 product of the mean profiles.  Only the y-derivatives of the mean
+// velocity (U', W') survive (v = 0 and d/dx, d/dz vanish for a profile), so
+// N = 0 and F_ab = U'_a c_yb + c_ay U'_b with U'_x = U', U'_z = W'.
+__global__ void mean_fix_kernel(Dims d, const float* __restrict__ yout32, const double* __restrict__ mean,
+                                double* __restrict__ tmp) {
+  const int m1 = d.M + 1;
+  const int nout = d.dim == 2 ? 5 : 9;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nout * m1) return;
+  const int o = e / m1, i = e - o * m1;
+  const double fl = (double)yout32[((size_t)o * m1 + i) * d.cw];
+  double mm = 0.0;
+  auto M = [&](int k) { return mean[(size_t)k * m1 + i]; };
+  if (d.dim == 2) {
+    // means: U U' cxx cxy cyy ...; outputs: Nx Ny Fxx Fxy Fyy
+    if (o == 2) mm = 2.0 * M(1) * M(3);
+    if (o == 3) mm = M(1) * M(4);
+  } else {
+    // means: U W U' W' cxx cxy cxz cyy cyz czz ...; outputs: Nx Ny Nz Fxx Fxy Fxz Fyy Fyz Fzz
+    const double Up = M(2), Wp = M(3), cxy = M(5), cyy = M(7), cyz = M(8);
+    if (o == 3) mm = 2.0 * Up * cxy;
+    if (o == 4) mm = Up * cyy;
+    if (o == 5) mm = Up * cyz + cxy * Wp;
+    if (o == 7) mm = Wp * cyy;
+    if (o == 8) mm = 2.0 * Wp * cyz;
+  }
+  tmp[e] = fl + mm;
+}
+
 }  // namespace
 
-void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const double* yin, double* yout,
-                    const double* kx, const double* tw, hipStream_t s) {
-  hipLaunchKernelGGL(xpencil_kernel<2>, dim3(d.M + 1), dim3(NT), xpencil_lds<2>(plan.L), s, yin, yout, d.M + 1,
-                     d.nkx, plan, kx, reinterpret_cast<const c2*>(tw), p.eps / p.wi);
-}
-
-void launch_xpencil3d(const Dims& d, const Phys& p, const FftPlan& plan, const double* zin, double* zout,
-                      const double* kx, const double* tw, hipStream_t s) {
+void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const void* in, void* out, const double* kx,
+                    const void* tw, int precision, const double* mean, hipStream_t s) {
   const int rows = (d.M + 1) * d.pz;
-  hipLaunchKernelGGL(xpencil_kernel<3>, dim3(rows), dim3(NT), xpencil_lds<3>(plan.L), s, zin, zout, rows, d.nkx,
-                     plan, kx, reinterpret_cast<const c2*>(tw), p.eps / p.wi);
+  const int m1 = d.M + 1;
+  if (precision == 0) {
+    if (d.dim == 2)
+      hipLaunchKernelGGL((xpencil_kernel<double, 2, false>), dim3(rows), dim3(NT), (xpencil_lds<double, 2>(plan.L)), s,
+                         (const double*)in, (double*)out, rows, d.nkx, plan, kx, (const cx<double>*)tw, p.eps / p.wi,
+                         mean, m1, d.pz);
+    else
+      hipLaunchKernelGGL((xpencil_kernel<double, 3, false>), dim3(rows), dim3(NT), (xpencil_lds<double, 3>(plan.L)), s,
+                         (const double*)in, (double*)out, rows, d.nkx, plan, kx, (const cx<double>*)tw, p.eps / p.wi,
+                         mean, m1, d.pz);
+  } else {
+    if (d.dim == 2)
+      hipLaunchKernelGGL((xpencil_kernel<float, 2, true>), dim3(rows), dim3(NT), (xpencil_lds<float, 2>(plan.L)), s,
+                         (const float*)in, (float*)out, rows, d.nkx, plan, kx, (const cx<float>*)tw, 0.0, mean, m1,
+                         d.pz);
+    else
+      hipLaunchKernelGGL((xpencil_kernel<float, 3, true>), dim3(rows), dim3(NT), (xpencil_lds<float, 3>(plan.L)), s,
+                         (const float*)in, (float*)out, rows, d.nkx, plan, kx, (const cx<float>*)tw, 0.0, mean, m1,
+                         d.pz);
+  }
 }
 
-void launch_zfft(const Dims& d, const FftPlan& plan, const double* in, double* out, int nfields,
-                 const int* src_field, const int* deriv, const double* kz, const double* tw, int inverse, int rows,
+void launch_zfft(const Dims& d, const FftPlan& plan, const void* in, void* out, int nfields, const int* src_field,
+                 const int* deriv, const double* kz, const void* tw, int inverse, int rows, int precision,
                  hipStream_t s) {
-  const size_t lds = (size_t)ZG * plan.L * sizeof(c2);
   dim3 grid((d.nkx + ZG - 1) / ZG, rows, nfields);
-  hipLaunchKernelGGL(zfft_kernel, grid, dim3(NT), lds, s, in, out, d.nkx, d.nzs, rows, plan, src_field, deriv, kz,
-                     reinterpret_cast<const c2*>(tw), inverse);
+  if (precision == 0) {
+    const size_t lds = (size_t)ZG * plan.L * sizeof(cx<double>);
+    hipLaunchKernelGGL(zfft_kernel<double>, grid, dim3(NT), lds, s, (const double*)in, (double*)out, d.nkx, d.nzs, rows,
+                       plan, src_field, deriv, kz, (const cx<double>*)tw, inverse);
+  } else {
+    const size_t lds = (size_t)ZG * plan.L * sizeof(cx<float>);
+    hipLaunchKernelGGL(zfft_kernel<float>, grid, dim3(NT), lds, s, (const float*)in, (float*)out, d.nkx, d.nzs, rows,
+                       plan, src_field, deriv, kz, (const cx<float>*)tw, inverse);
+  }
+}
+
+void launch_mean_fix(const Dims& d, const float* yout32, const double* mean, double* tmp, hipStream_t s) {
+  const int n = (d.dim == 2 ? 5 : 9) * (d.M + 1);
+  hipLaunchKernelGGL(mean_fix_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, yout32, mean, tmp);
 }
 
 void launch_diag_rows(const Dims& d, const Phys& p, const FftPlan& planx, const double* st, double* prep,
@@ -634,7 +794,7 @@ void launch_diag_rows(const Dims& d, const Phys& p, const FftPlan& planx, const 
   const double* src = prep;
   int zrows = 1;
   if (d.dim == 3) {
-    launch_zfft(d, planz, prep, zbuf, 4, nullptr, nullptr, nullptr, twz, 1, n1, s);
+    launch_zfft(d, planz, prep, zbuf, 4, nullptr, nullptr, nullptr, twz, 1, n1, 0, s);
     src = zbuf;
     zrows = d.nz;
   }
@@ -651,16 +811,20 @@ void launch_diag_final(const Dims& d, const Phys& p, const DiagPart* parts, cons
 
 hipError_t fft_set_attributes() {
   const int lim = 160 * 1024;
-  hipError_t e = hipFuncSetAttribute((const void*)xpencil_kernel<2>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)xpencil_kernel<3>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (e == hipSuccess) e = hipFuncSetAttribute((const void*)zfft_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  const void* k160[] = {(const void*)xpencil_kernel<double, 2, false>, (const void*)xpencil_kernel<double, 3, false>,
+                        (const void*)xpencil_kernel<float, 2, true>,   (const void*)xpencil_kernel<float, 3, true>,
+                        (const void*)zfft_kernel<double>,             (const void*)zfft_kernel<float>};
+  for (const void* k : k160) {
+    hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    if (e != hipSuccess) return e;
+  }
   // the row-diagnostics kernel also holds a little static LDS for its reductions
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)diag_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
-  return e;
+  return hipFuncSetAttribute((const void*)diag_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
 }
 
-size_t xpencil_lds_bytes(int dim, int L) { return dim == 2 ? xpencil_lds<2>(L) : xpencil_lds<3>(L); }
+size_t xpencil_lds_bytes(int dim, int L, int precision) {
+  if (precision == 0) return dim == 2 ? xpencil_lds<double, 2>(L) : xpencil_lds<double, 3>(L);
+  return dim == 2 ? xpencil_lds<float, 2>(L) : xpencil_lds<float, 3>(L);
+}
 
 }  // namespace pcs

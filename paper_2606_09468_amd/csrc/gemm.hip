@@ -9,10 +9,11 @@
 //
 // One launch evaluates a table of such products.  A workgroup (four waves)
 // owns a BM x 32 output tile: it stages the whole K x 32 panel of B in LDS
-// with a single round of coalesced loads, then accumulates with 16x16x4
-// MFMAs, reading A fragments straight from the L2-resident operator.  BM is
-// chosen per table by the host: 16 (the four waves split K) for products too
-// small to fill the chip, 64, or 128 for wide products (fewer re-reads of B).
+// (converted to the compute precision) with unrolled loads, then accumulates
+// with 16x16x4 MFMAs (f64 or f32), reading A fragments straight from the
+// L2-resident operator through a prefetch ring.  BM is chosen per table by
+// the host: 16 (the four waves split K) for products too small to fill the
+// chip, 64, or 128 for wide products (fewer re-reads of B).
 #include "kernels.hpp"
 
 namespace pcs {
@@ -20,8 +21,7 @@ namespace pcs {
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
 
-template <typename T>
-int gemm_prepare(GemmJob<T>* jobs, int njobs, int bm) {
+int gemm_prepare(GemmJob* jobs, int njobs, int bm) {
   int t = 0;
   for (int j = 0; j < njobs; ++j) {
     jobs[j].tiles_m = (jobs[j].m + bm - 1) / bm;
@@ -31,8 +31,6 @@ int gemm_prepare(GemmJob<T>* jobs, int njobs, int bm) {
   }
   return t;
 }
-template int gemm_prepare<double>(GemmJob<double>*, int, int);
-template int gemm_prepare<float>(GemmJob<float>*, int, int);
 
 __device__ inline dbl4 mfma(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -41,7 +39,18 @@ __device__ inline flt4 mfma(float a, float b, flt4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-constexpr int LDB = GEMM_BN + 16;  // padded LDS row of the B panel (spreads the four k rows of a read over the banks)
+template <typename T>
+struct Vec4;
+template <>
+struct Vec4<double> {
+  typedef dbl4 type;
+};
+template <>
+struct Vec4<float> {
+  typedef flt4 type;
+};
+
+constexpr int LDB = GEMM_BN + 8;  // padded LDS row of the B panel: the four k rows of one read start 16 banks apart
 
 // Tile shapes.  RB: 16-row blocks per wave.  KS = 1: the four waves stack
 // their rows (BM = 64 RB); KS = 4: the four waves share BM = 16 RB rows and
@@ -53,13 +62,13 @@ struct Shape {
 };
 
 template <typename T, int RB>
-__device__ inline void load_a(T (&a)[4][RB], const GemmJob<T>& J, const int (&arow)[RB], const bool (&aok)[RB], int k0,
-                              int lk) {
+__device__ inline void load_a(T (&a)[4][RB], const T* A, int lda, int K, const int (&arow)[RB],
+                              const bool (&aok)[RB], int k0, int lk) {
 #pragma unroll
   for (int u = 0; u < 4; ++u) {
     const int k = k0 + 4 * u + lk;
 #pragma unroll
-    for (int rb = 0; rb < RB; ++rb) a[u][rb] = (k < J.k && aok[rb]) ? J.A[(size_t)k * J.lda + arow[rb]] : T(0);
+    for (int rb = 0; rb < RB; ++rb) a[u][rb] = (k < K && aok[rb]) ? A[(size_t)k * lda + arow[rb]] : T(0);
   }
 }
 
@@ -80,33 +89,37 @@ __device__ inline void mma_block(V4 (&acc)[RB][2], const T (&a)[4][RB], const T*
   }
 }
 
-template <typename T, typename V4, int RB, int KS>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmJob<T>* __restrict__ jobs, int njobs) {
+template <typename T, typename TB, typename TC, int RB, int KS>
+__global__ __launch_bounds__(256) void gemm_kernel(const GemmJob* __restrict__ jobs, int njobs) {
+  typedef typename Vec4<T>::type V4;
   extern __shared__ double gsm[];
   T* Bs = reinterpret_cast<T*>(gsm);  // [K4][LDB], K rounded up to a multiple of 4
   constexpr int BM = Shape<RB, KS>::BM;
   const int t = blockIdx.x;
   int jb = 0;
   while (jb + 1 < njobs && jobs[jb + 1].tile0 <= t) ++jb;
-  const GemmJob<T> J = jobs[jb];
+  const GemmJob J = jobs[jb];
+  const T* A = static_cast<const T*>(J.A);
+  const TB* B = static_cast<const TB*>(J.B);
+  TC* C = static_cast<TC*>(J.C);
   const int lt = t - J.tile0;
   const int row0 = (lt % J.tiles_m) * BM;
   const int col0 = (lt / J.tiles_m) * GEMM_BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int K4 = (J.k + 3) & ~3;
-  // stage the K x 32 panel of B (zero outside the matrix): 16 loads in
-  // flight per thread before any LDS store
+  // stage the K x 32 panel of B (zero outside the matrix, and in the mean
+  // columns when asked): 16 loads in flight per thread before any LDS store
   {
     constexpr int UNR = 16, RPP = 256 / GEMM_BN;  // rows per pass of the workgroup
     const int c = tid % GEMM_BN, rr = tid / GEMM_BN;
     const int gc = col0 + c;
-    const bool cok = gc < J.n;
+    const bool cok = gc < J.n && !((J.flags & GEMM_ZERO_MEAN) && gc < 2);
     for (int r0 = 0; r0 < K4; r0 += UNR * RPP) {
       T v[UNR];
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
         const int r = r0 + u * RPP + rr;
-        v[u] = (r < J.k && cok) ? J.B[(size_t)r * J.ldb + gc] : T(0);
+        v[u] = (r < J.k && cok) ? T(B[(size_t)r * J.ldb + gc]) : T(0);
       }
 #pragma unroll
       for (int u = 0; u < UNR; ++u) {
@@ -134,15 +147,27 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmJob<T>* __restrict_
   V4 acc[RB][2];
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = V4{0, 0, 0, 0};
-  // A fragments come straight from the L2-resident operator, prefetched one
-  // 16-deep block ahead of the products that use them
-  T aA[4][RB], aB[4][RB];
-  if (kbeg < kend) load_a(aA, J, arow, aok, kbeg, lk);
-  for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    if (k0 + 16 < kend) load_a(aB, J, arow, aok, k0 + 16, lk);
-    mma_block<T, V4, RB>(acc, aA, Bs, k0, kend, lk, l16);
-    if (k0 + 32 < kend) load_a(aA, J, arow, aok, k0 + 32, lk);
-    if (k0 + 16 < kend) mma_block<T, V4, RB>(acc, aB, Bs, k0 + 16, kend, lk, l16);
+  // A fragments come straight from the L2-resident operator through a ring of
+  // four 16-deep register blocks: block b + 3 is requested while block b is
+  // multiplied
+  T a0[4][RB], a1[4][RB], a2[4][RB], a3[4][RB];
+  const int nblk = (kend - kbeg + 15) / 16;
+  auto kb = [&](int b) { return kbeg + 16 * b; };
+  if (nblk > 0) load_a(a0, A, J.lda, J.k, arow, aok, kb(0), lk);
+  if (nblk > 1) load_a(a1, A, J.lda, J.k, arow, aok, kb(1), lk);
+  if (nblk > 2) load_a(a2, A, J.lda, J.k, arow, aok, kb(2), lk);
+  for (int b = 0; b < nblk; b += 4) {
+    if (b + 3 < nblk) load_a(a3, A, J.lda, J.k, arow, aok, kb(b + 3), lk);
+    mma_block<T, V4, RB>(acc, a0, Bs, kb(b), kend, lk, l16);
+    if (b + 1 >= nblk) break;
+    if (b + 4 < nblk) load_a(a0, A, J.lda, J.k, arow, aok, kb(b + 4), lk);
+    mma_block<T, V4, RB>(acc, a1, Bs, kb(b + 1), kend, lk, l16);
+    if (b + 2 >= nblk) break;
+    if (b + 5 < nblk) load_a(a1, A, J.lda, J.k, arow, aok, kb(b + 5), lk);
+    mma_block<T, V4, RB>(acc, a2, Bs, kb(b + 2), kend, lk, l16);
+    if (b + 3 >= nblk) break;
+    if (b + 6 < nblk) load_a(a2, A, J.lda, J.k, arow, aok, kb(b + 6), lk);
+    mma_block<T, V4, RB>(acc, a3, Bs, kb(b + 3), kend, lk, l16);
   }
   if (KS > 1) {
     // add the K-quarters: waves 1..3 park their partial tiles in LDS
@@ -180,10 +205,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmJob<T>* __restrict_
         const int gr = wrow + rb * 16 + (f64 ? 4 * r + lk : 4 * lk + r);
         const int gc = col0 + bj * 16 + l16;
         if (gr < J.m && gc < J.n) {
-          T* cp = J.C + (size_t)gr * J.ldc + gc;
-          T v = J.alpha * acc[rb][bj][r];
-          if (J.beta != T(0)) v += J.beta * *cp;
-          *cp = v;
+          TC* cp = C + (size_t)gr * J.ldc + gc;
+          double v = J.alpha * (double)acc[rb][bj][r];
+          if (J.beta != 0.0) v += J.beta * (double)*cp;
+          *cp = TC(v);
         }
       }
 }
@@ -194,40 +219,54 @@ size_t gemm_lds_bytes(int kmax, int elem) {
   return panel > red ? panel : red;
 }
 
-template <typename T, typename V4>
-hipError_t set_attr_all() {
+namespace {
+
+template <typename T, typename TB, typename TC>
+hipError_t set_attr3() {
   const int lim = 160 * 1024;
-  hipError_t e = hipFuncSetAttribute((const void*)gemm_kernel<T, V4, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+  hipError_t e =
+      hipFuncSetAttribute((const void*)gemm_kernel<T, TB, TC, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)gemm_kernel<T, V4, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    e = hipFuncSetAttribute((const void*)gemm_kernel<T, TB, TC, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim);
   if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)gemm_kernel<T, V4, 2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
+    e = hipFuncSetAttribute((const void*)gemm_kernel<T, TB, TC, 2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            lim);
   return e;
 }
 
-hipError_t gemm_set_attributes() {
-  hipError_t e = set_attr_all<double, dbl4>();
-  return e == hipSuccess ? set_attr_all<float, flt4>() : e;
-}
-
-template <typename T, typename V4>
-void launch_gemm(const GemmJob<T>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
-  if (total_tiles <= 0) return;
+template <typename T, typename TB, typename TC>
+void launch3(const GemmJob* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
   const size_t lds = gemm_lds_bytes(kmax, sizeof(T));
   if (bm == 16)
-    hipLaunchKernelGGL((gemm_kernel<T, V4, 1, 4>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
+    hipLaunchKernelGGL((gemm_kernel<T, TB, TC, 1, 4>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
   else if (bm == 128)
-    hipLaunchKernelGGL((gemm_kernel<T, V4, 2, 1>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
+    hipLaunchKernelGGL((gemm_kernel<T, TB, TC, 2, 1>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
   else
-    hipLaunchKernelGGL((gemm_kernel<T, V4, 1, 1>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
+    hipLaunchKernelGGL((gemm_kernel<T, TB, TC, 1, 1>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
 }
 
-void gemm_f64(const GemmJob<double>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
-  launch_gemm<double, dbl4>(dev_jobs, total_tiles, njobs, bm, kmax, s);
+}  // namespace
+
+hipError_t gemm_set_attributes() {
+  hipError_t e = set_attr3<double, double, double>();
+  if (e == hipSuccess) e = set_attr3<float, double, float>();
+  if (e == hipSuccess) e = set_attr3<float, float, double>();
+  if (e == hipSuccess) e = set_attr3<double, double, float>();
+  if (e == hipSuccess) e = set_attr3<double, float, double>();
+  return e;
 }
 
-void gemm_f32(const GemmJob<float>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
-  launch_gemm<float, flt4>(dev_jobs, total_tiles, njobs, bm, kmax, s);
+void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
+  if (total_tiles <= 0 || njobs <= 0) return;
+  switch (t) {
+    case GEMM_DDD: launch3<double, double, double>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
+    case GEMM_FDF: launch3<float, double, float>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
+    case GEMM_FFD: launch3<float, float, double>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
+    case GEMM_DDF: launch3<double, double, float>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
+    case GEMM_DFD: launch3<double, float, double>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
+    default: break;
+  }
 }
 
 }  // namespace pcs

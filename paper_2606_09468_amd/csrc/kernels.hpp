@@ -8,29 +8,32 @@
 namespace pcs {
 
 // One dense product C = alpha * A * B + beta * C, real.  A (m x k) is stored
-// K-major, A[i][kk] at A[kk * lda + i] (lda >= m); B (k x n) and C (m x n) are
-// row-major.  Complex fields (re/im interleaved) are multiplied by a real
+// K-major, A[i][kk] at A[kk * lda + i] (lda >= m), in the compute precision;
+// B (k x n) and C (m x n) are row-major, each in its own precision (see
+// GemmType).  Complex fields (re/im interleaved) are multiplied by a real
 // operator by treating each complex column as two real columns.
-template <typename T>
 struct GemmJob {
-  const T* A;
-  const T* B;
-  T* C;
+  const void* A;
+  const void* B;
+  void* C;
   int m, n, k, lda, ldb, ldc;
-  T alpha, beta;
+  double alpha, beta;
+  int flags;           // GEMM_ZERO_MEAN: B columns 0 and 1 (the kx = kz = 0 mode) read as zero
   int tiles_m, tile0;  // filled by gemm_prepare
 };
+constexpr int GEMM_ZERO_MEAN = 1;
+
+// compute / B / C precisions: D = double, F = float
+enum GemmType { GEMM_DDD = 0, GEMM_FDF, GEMM_FFD, GEMM_DDF, GEMM_DFD, GEMM_NTYPES };
 
 constexpr int GEMM_BN = 32;  // output columns per workgroup
 constexpr int MAX_JOBS = 64;
 
-// Fills tiles_m / tile0 for row tiles of bm (64 or 128) and returns the
+// Fills tiles_m / tile0 for row tiles of bm (16, 64 or 128) and returns the
 // total number of workgroups.
-template <typename T>
-int gemm_prepare(GemmJob<T>* jobs, int njobs, int bm);
+int gemm_prepare(GemmJob* jobs, int njobs, int bm);
 // kmax: largest k of the table (sizes the LDS panel of B).
-void gemm_f64(const GemmJob<double>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s);
-void gemm_f32(const GemmJob<float>* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s);
+void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s);
 size_t gemm_lds_bytes(int kmax, int elem);
 hipError_t gemm_set_attributes();
 
@@ -87,13 +90,14 @@ struct DiagPart {
 };
 
 // ---- launchers (fft.hip)
-void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const double* yin, double* yout,
-                    const double* kx, const double* tw, hipStream_t s);
-void launch_xpencil3d(const Dims& d, const Phys& p, const FftPlan& plan, const double* zin, double* zout,
-                      const double* kx, const double* tw, hipStream_t s);
-void launch_zfft(const Dims& d, const FftPlan& plan, const double* in, double* out, int nfields,
-                 const int* src_field, const int* deriv, const double* kz, const double* tw, int inverse, int rows,
+// precision 0: FP64 buffers and products; otherwise FP32 buffers, the mixed
+// mean/fluctuation products and `mean` = [n_means][M+1] FP64 profiles.
+void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const void* in, void* out, const double* kx,
+                    const void* tw, int precision, const double* mean, hipStream_t s);
+void launch_zfft(const Dims& d, const FftPlan& plan, const void* in, void* out, int nfields, const int* src_field,
+                 const int* deriv, const double* kz, const void* tw, int inverse, int rows, int precision,
                  hipStream_t s);
+void launch_mean_fix(const Dims& d, const float* yout32, const double* mean, double* tmp, hipStream_t s);
 void launch_diag_rows(const Dims& d, const Phys& p, const FftPlan& planx, const double* st, double* prep,
                       double* zbuf, const FftPlan& planz, const double* twx, const double* twz, const double* ydy,
                       DiagPart* parts, hipStream_t s);
@@ -101,7 +105,7 @@ void launch_diag_final(const Dims& d, const Phys& p, const DiagPart* parts, cons
                        DiagRec* ring, int ring_cap, hipStream_t s);
 // Raises the dynamic-LDS limit of the transform kernels (call once, outside capture).
 hipError_t fft_set_attributes();
-size_t xpencil_lds_bytes(int dim, int L);
+size_t xpencil_lds_bytes(int dim, int L, int precision);
 
 // ---- launchers (elem.hip)
 void launch_assemble_h(const Dims& d, const Phys& p, const double* S, const double* cfields, const double* Dc,
