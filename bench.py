@@ -60,7 +60,7 @@ def stage_work(w, prec_bytes=16):
     out = {}
     g1 = (nvel + nc + (1 if dim == 2 else 2) + nc) * 2 * m1 * cw * n1     # I and D to the padded grid
     g1 += nsolve * 2 * n1 * cw * n1 + (dim - 1) * 2 * n1 * n1             # D2 of phi, g, c and U, W
-    g1 += (2 if dim == 2 else 3) * 2 * n1 * cw * n1                       # D of c_y.
+    g1 += nc * 2 * n1 * cw * n1                                           # D of every c
     out["gemm_state"] = ("mfma", g1)
     if dim == 3:
         out["zfft_inv"] = ("hbm", (nyin * m1 * nzs * nkx + 26 * m1 * pz * nkx) * cplx)
@@ -68,10 +68,9 @@ def stage_work(w, prec_bytes=16):
         out["zfft_fwd"] = ("hbm", (nout * m1 * pz * nkx + nout * m1 * nzs * nkx) * cplx)
     else:
         out["xpencil"] = ("hbm", (nyin + nout) * m1 * nkx * cplx)
-    out["gemm_proj"] = ("mfma", nout * 2 * n1 * cw * m1)
-    out["gemm_ds"] = ("mfma", 2 * n1 * cw * n1)
+    out["gemm_proj"] = ("mfma", (nout + dim - 1) * 2 * n1 * cw * m1)      # P N and (D P) N_x, N_z
     out["gemm_vinv"] = ("mfma", nsolve * 2 * ni * cw * ni)
-    out["gemm_v"] = ("mfma", (nsolve + 1) * 2 * ni * cw * ni + 2 * n1 * cw * ni + 2 * cw * ni)
+    out["gemm_v"] = ("mfma", (nsolve + 1) * 2 * ni * cw * ni + 2 * n1 * cw * ni + 2 * 2 * ni)
     return out
 
 

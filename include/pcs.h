@@ -135,7 +135,7 @@ pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
  * stage i over the steps.  nstage must be at least PCS_NSTAGE; stages that
  * do not apply (the z transforms in 2D) report their empty interval.
  * Stage names come from pcs_stage_name.  Synchronises the stream. */
-#define PCS_NSTAGE 14
+#define PCS_NSTAGE 11
 pcs_status pcs_stage_times(struct pcs_sim* sim, int32_t nsteps, double* ms, int32_t nstage);
 const char* pcs_stage_name(int32_t i);
 

@@ -28,7 +28,7 @@ PCS_ERR_STATE = -5
 EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pcs_state_size",
            "pcs_get_state", "pcs_set_state", "pcs_stage_times", "pcs_destroy", "pcs_status_string",
            "pcs_stage_name")
-PCS_NSTAGE = 14
+PCS_NSTAGE = 11
 
 
 class pcs_grid(ctypes.Structure):

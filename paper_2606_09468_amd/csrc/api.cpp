@@ -16,6 +16,7 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pcs.h"
@@ -47,7 +48,8 @@ struct JobList {
   GemmJob* dev = nullptr;
   GemmType type = GEMM_DDD;
   int tiles = 0, bm = 64, kmax = 0;
-  void add(const void* A, const void* B, int ldb, void* C, int ldc, int m, int n, int k, int flags = 0) {
+  void add(const void* A, const void* B, int ldb, void* C, int ldc, int m, int n, int k, int flags = 0,
+           int scale = SCALE_NONE, const EigScale* es = nullptr) {
     GemmJob j{};
     j.A = A;
     j.B = B;
@@ -61,6 +63,8 @@ struct JobList {
     j.alpha = 1.0;
     j.beta = 0.0;
     j.flags = flags;
+    j.scale = scale;
+    j.es = es;
     h.push_back(j);
   }
   int n() const { return (int)h.size(); }
@@ -112,23 +116,33 @@ struct pcs_sim {
   Dims d{};
   Phys p{};
   hipStream_t s = nullptr;
+  // second stream (default priority) for the products of the state that do
+  // not feed the transforms; forked from and joined to s inside the step
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_bar = nullptr, ev_fwd = nullptr, ev_join = nullptr;
   const WallOps* ops = nullptr;
   FftPlan plx, plz, pbx, pbz;
   int nq = 0, nh = 0, nyin = 0, nzin = 0, nout = 0, nsolve = 0, nsv = 0;
   // device buffers (all inside the caller's workspace)
-  double *IMN, *DMN, *D, *D2, *PNM, *V, *Vinv, *DV, *wV, *lam, *d2i0, *d2in, *w, *ydy, *U1, *kx, *kz;
+  double *IMN, *DMN, *D, *D2, *PNM, *DP, *V, *Vinv, *DV, *wV, *lam, *d2i0, *d2in, *w, *ydy, *U1, *kx, *kz;
   double *twx, *twz, *twbx, *twbz;
-  double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *Dc, *D2buf, *sbuf, *hy, *hgn, *Ds, *hvn;
-  double *R, *X, *Xs, *Zphi, *Zv, *ZDv, *flux, *CB, *prep, *zbuf;
+  double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *DN, *Dc, *D2buf, *hgn, *hvn;
+  double *R, *X, *Zphi, *Zv, *ZDv, *flux, *CB, *prep, *zbuf;
+  EigScale* es;
   // mixed precision: FP32 operators, twiddles and padded-grid buffers, FP64
-  // mean profiles on the padded grid and the mean-mode fix column
-  float *IMN32, *DMN32, *PNM32, *twx32, *twz32, *Yin32, *Zin32, *Zout32, *Yout32;
-  double *Ybar, *mfix;
+  // mean profiles on the padded grid, the FP64 mean column of the explicit
+  // terms there (mcol) and its projection (smean)
+  float *IMN32, *DMN32, *PNM32, *DP32, *twx32, *twz32, *Yin32, *Zin32, *Zout32, *Yout32;
+  double *Ybar, *mcol, *smean;
   int *zsrc, *zder;
   DiagPart* parts;
   DiagRec* ring;
   DevScalars* sc;
-  JobList G1, G1b, G2, G2b, G3, G4, G5, H4, H5;
+  // G1: state -> padded grid; Gbar: FP64 mean profiles there (mixed);
+  // G1b: D2 and D of the state; G2: projection and D of it; Gm: FP64 mean
+  // column projection (mixed); G4 / G5: into / out of the eigenbasis;
+  // H4 / H5: the same for the homogeneous solutions at init
+  JobList G1, Gbar, G1b, G2, Gm, G4, G5, H4, H5;
   int prec = 0;
   double wU1 = 0;
   long long drained = 0;
@@ -136,7 +150,15 @@ struct pcs_sim {
   size_t nstate = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  std::vector<JobList*> lists() { return {&G1, &G1b, &G2, &G2b, &G3, &G4, &G5, &H4, &H5}; }
+  std::vector<JobList*> lists() { return {&G1, &Gbar, &G1b, &G2, &Gm, &G4, &G5, &H4, &H5}; }
+  ~pcs_sim() {
+    if (s2) (void)hipStreamSynchronize(s2);
+    if (gexec) (void)hipGraphExecDestroy(gexec);
+    if (graph) (void)hipGraphDestroy(graph);
+    for (hipEvent_t e : {ev_fork, ev_bar, ev_fwd, ev_join})
+      if (e) (void)hipEventDestroy(e);
+    if (s2) (void)hipStreamDestroy(s2);
+  }
 };
 
 namespace {
@@ -151,6 +173,7 @@ size_t carve(pcs_sim* m, char* base) {
   m->D = c.take<double>(n1 * n1);
   m->D2 = c.take<double>(n1 * n1);
   m->PNM = c.take<double>(n1 * m1);
+  m->DP = c.take<double>(n1 * m1);
   m->V = c.take<double>(ni * ni);
   m->Vinv = c.take<double>(ni * ni);
   m->DV = c.take<double>(n1 * ni);
@@ -182,21 +205,21 @@ size_t carve(pcs_sim* m, char* base) {
   m->IMN32 = mixed ? c.take<float>(m1 * n1) : nullptr;
   m->DMN32 = mixed ? c.take<float>(m1 * n1) : nullptr;
   m->PNM32 = mixed ? c.take<float>(n1 * m1) : nullptr;
+  m->DP32 = mixed ? c.take<float>(n1 * m1) : nullptr;
   m->twx32 = mixed ? c.take<float>(2 * (size_t)d.px) : nullptr;
   m->twz32 = mixed ? c.take<float>(2 * (size_t)d.pz) : nullptr;
   m->Ybar = mixed ? c.take<double>(16 * m1) : nullptr;
-  m->mfix = mixed ? c.take<double>((size_t)m->nout * m1) : nullptr;
+  m->mcol = mixed ? c.take<double>((size_t)m->nout * m1) : nullptr;
+  m->smean = mixed ? c.take<double>((size_t)m->nout * n1) : nullptr;
   m->S = c.take<double>((size_t)m->nout * n1 * cw);
-  m->Dc = c.take<double>((size_t)(d.dim == 2 ? 2 : 3) * n1 * cw);
+  m->DN = c.take<double>((size_t)(d.dim == 2 ? 1 : 2) * n1 * cw);
+  m->Dc = c.take<double>((size_t)d.nc * n1 * cw);
   m->D2buf = c.take<double>((size_t)m->nsolve * n1 * cw + 2 * n1);
-  m->sbuf = c.take<double>(n1 * cw);
-  m->hy = c.take<double>(n1 * cw);
   m->hgn = c.take<double>(n1 * cw);
-  m->Ds = c.take<double>(n1 * cw);
   m->hvn = c.take<double>(n1 * cw);
   m->R = c.take<double>((size_t)m->nsolve * ni * cw);
   m->X = c.take<double>((size_t)m->nsolve * ni * cw);
-  m->Xs = c.take<double>((size_t)(m->nsolve + 1) * ni * cw);
+  m->es = c.take<EigScale>(1);
   m->Zphi = c.take<double>(ni * cw);
   m->Zv = c.take<double>(ni * cw);
   m->ZDv = c.take<double>(n1 * cw);
@@ -418,9 +441,7 @@ void build_jobs(pcs_sim* m) {
   // G1: values and d/dy on the padded grid (mixed: of the fluctuation only,
   // written in FP32; computed in FP32, or in FP64 for precision 2)
   JobList& g1 = m->G1;
-  JobList& g1b = mixed ? m->G1b : m->G1;  // FP64 products of the state
   g1.type = mixed ? (m->prec == 1 ? GEMM_FDF : GEMM_DDF) : GEMM_DDD;
-  m->G1b.type = GEMM_DDD;
   const void* I = mixed && m->prec == 1 ? (const void*)m->IMN32 : (const void*)m->IMN;
   const void* DI = mixed && m->prec == 1 ? (const void*)m->DMN32 : (const void*)m->DMN;
   void* Y = mixed ? (void*)m->Yin32 : (void*)m->Yin;
@@ -428,77 +449,85 @@ void build_jobs(pcs_sim* m) {
   auto yf = [&](int f) { return (void*)((char*)Y + (size_t)f * fsm * ysz); };
   const int zm = mixed ? GEMM_ZERO_MEAN : 0;
   const int nvel = d.dim;
-  const int vel[3] = {0, 1, 2};
-  for (int a = 0; a < nvel; ++a) g1.add(I, st + vel[a] * fs, cw, yf(a), cw, m1, cw, n1, zm);
+  for (int a = 0; a < nvel; ++a) g1.add(I, st + a * fs, cw, yf(a), cw, m1, cw, n1, zm);
   for (int a = 0; a < d.nc; ++a) g1.add(I, st + (FC + a) * fs, cw, yf(nvel + a), cw, m1, cw, n1, zm);
   const int yd0 = nvel + d.nc;  // first d/dy field in the padded-grid input
   g1.add(DI, st + 0 * fs, cw, yf(yd0), cw, m1, cw, n1, zm);
   int o = yd0 + 1;
   if (d.dim == 3) g1.add(DI, st + 2 * fs, cw, yf(o++), cw, m1, cw, n1, zm);
   for (int a = 0; a < d.nc; ++a) g1.add(DI, st + (FC + a) * fs, cw, yf(o++), cw, m1, cw, n1, zm);
+  if (mixed) {
+    // FP64 mean profiles on the padded grid (real part of the kx = kz = 0 column)
+    // 2D: U U' c (3) c' (3); 3D: U W U' W' c (6) c' (6)
+    JobList& gb = m->Gbar;
+    gb.type = GEMM_DDD;
+    double* Yb = m->Ybar;
+    int q = 0;
+    gb.add(m->IMN, st + 0 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    if (d.dim == 3) gb.add(m->IMN, st + 2 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    gb.add(m->DMN, st + 0 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    if (d.dim == 3) gb.add(m->DMN, st + 2 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    for (int a = 0; a < d.nc; ++a) gb.add(m->IMN, st + (FC + a) * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    for (int a = 0; a < d.nc; ++a) gb.add(m->DMN, st + (FC + a) * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+  }
+  // G1b (FP64): D2 of phi, (g), c and of the mean U, (W); D of every c
+  JobList& g1b = m->G1b;
+  g1b.type = GEMM_DDD;
   g1b.add(m->D2, st + FPHI * fs, cw, m->D2buf + 0 * fs, cw, n1, cw, n1);
   if (d.dim == 3) g1b.add(m->D2, st + 4 * fs, cw, m->D2buf + 1 * fs, cw, n1, cw, n1);
   for (int a = 0; a < d.nc; ++a) g1b.add(m->D2, st + (FC + a) * fs, cw, m->D2buf + (m->nsv + a) * fs, cw, n1, cw, n1);
   double* D2U = m->D2buf + (size_t)m->nsolve * fs;
   g1b.add(m->D2, st + 0 * fs, cw, D2U, 1, n1, 1, n1);
   if (d.dim == 3) g1b.add(m->D2, st + 2 * fs, cw, D2U + n1, 1, n1, 1, n1);
-  // D c_y. for the stress divergence: 2D c_xy, c_yy; 3D c_xy, c_yy, c_yz
-  const int dci[3] = {1, d.dim == 2 ? 2 : 3, 4};
-  for (int q = 0; q < (d.dim == 2 ? 2 : 3); ++q) g1b.add(m->D, st + (FC + dci[q]) * fs, cw, m->Dc + q * fs, cw, n1, cw, n1);
-  if (mixed) {
-    // FP64 mean profiles on the padded grid (real part of the kx = kz = 0 column)
-    // 2D: U U' c (3) c' (3); 3D: U W U' W' c (6) c' (6)
-    double* Yb = m->Ybar;
-    int q = 0;
-    g1b.add(m->IMN, st + 0 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    if (d.dim == 3) g1b.add(m->IMN, st + 2 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    g1b.add(m->DMN, st + 0 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    if (d.dim == 3) g1b.add(m->DMN, st + 2 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    for (int a = 0; a < d.nc; ++a) g1b.add(m->IMN, st + (FC + a) * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    for (int a = 0; a < d.nc; ++a) g1b.add(m->DMN, st + (FC + a) * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-  }
-  // G2: projection of the explicit terms (mixed: FP32 operands, FP64 result;
-  // then the mean column again in FP64 from the mean-mode fix)
+  for (int a = 0; a < d.nc; ++a) g1b.add(m->D, st + (FC + a) * fs, cw, m->Dc + a * fs, cw, n1, cw, n1);
+  // G2: projection of the explicit terms, and D of the projected N_x, N_z
+  // through (D P) (mixed: FP32 operands, FP64 result)
   m->G2.type = mixed ? (m->prec == 1 ? GEMM_FFD : GEMM_DFD) : GEMM_DDD;
   const void* P = mixed && m->prec == 1 ? (const void*)m->PNM32 : (const void*)m->PNM;
-  const void* Yo = mixed ? (const void*)m->Yout32 : (const void*)m->Yout;
-  for (int f = 0; f < m->nout; ++f)
-    m->G2.add(P, (const char*)Yo + (size_t)f * fsm * ysz, cw, m->S + f * fs, cw, n1, cw, m1);
+  const void* DP = mixed && m->prec == 1 ? (const void*)m->DP32 : (const void*)m->DP;
+  const char* Yo = mixed ? (const char*)m->Yout32 : (const char*)m->Yout;
+  for (int f = 0; f < m->nout; ++f) m->G2.add(P, Yo + (size_t)f * fsm * ysz, cw, m->S + f * fs, cw, n1, cw, m1);
+  m->G2.add(DP, Yo, cw, m->DN, cw, n1, cw, m1);
+  if (d.dim == 3) m->G2.add(DP, Yo + 2 * fsm * ysz, cw, m->DN + fs, cw, n1, cw, m1);
   if (mixed) {
-    m->G2b.type = GEMM_DDD;
-    for (int f = 0; f < m->nout; ++f) m->G2b.add(m->PNM, m->mfix + (size_t)f * m1, 1, m->S + f * fs, cw, n1, 1, m1);
+    // the mean column again, in FP64, from the FP64-completed padded-grid means
+    m->Gm.type = GEMM_DDD;
+    for (int f = 0; f < m->nout; ++f) m->Gm.add(m->PNM, m->mcol + (size_t)f * m1, 1, m->smean + f * n1, 1, n1, 1, m1);
   }
-  // G3: D s
-  m->G3.add(m->D, m->sbuf, cw, m->Ds, cw, n1, cw, n1);
   // G4: V^-1 R
   for (int f = 0; f < m->nsolve; ++f) m->G4.add(m->Vinv, m->R + f * fsi, cw, m->X + f * fsi, cw, ni, cw, ni);
   m->H4.add(m->Vinv, m->R, cw, m->X, cw, ni, cw, ni);
-  // G5: back from the eigenbasis
+  // G5: back from the eigenbasis, each B panel scaled by the inverse symbol
+  // of its Helmholtz operator while it is staged
+  const EigScale* es = m->es;
   for (JobList* jl : {&m->G5, &m->H5}) {
-    jl->add(m->V, m->Xs + 0 * fsi, cw, m->Zphi, cw, ni, cw, ni);
-    jl->add(m->V, m->Xs + 1 * fsi, cw, m->Zv, cw, ni, cw, ni);
-    jl->add(m->DV, m->Xs + 1 * fsi, cw, m->ZDv, cw, n1, cw, ni);
+    jl->add(m->V, m->X, cw, m->Zphi, cw, ni, cw, ni, 0, SCALE_PHI, es);
+    jl->add(m->V, m->X, cw, m->Zv, cw, ni, cw, ni, 0, SCALE_V, es);
+    jl->add(m->DV, m->X, cw, m->ZDv, cw, n1, cw, ni, 0, SCALE_V, es);
   }
-  int xo = 2;
-  if (d.dim == 3) {
-    m->G5.add(m->V, m->Xs + 2 * fsi, cw, st + 4 * fs + cw, cw, ni, cw, ni);
-    xo = 3;
-  }
-  for (int a = 0; a < d.nc; ++a) m->G5.add(m->V, m->Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
-  m->G5.add(m->wV, m->Xs + 0 * fsi, cw, m->flux, cw, 1, cw, ni);
+  if (d.dim == 3) m->G5.add(m->V, m->X + fsi, cw, st + 4 * fs + cw, cw, ni, cw, ni, 0, SCALE_PHI, es);
+  for (int a = 0; a < d.nc; ++a)
+    m->G5.add(m->V, m->X + (m->nsv + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni, 0, SCALE_C, es);
+  // w . U_p for the flux constraint: the mean column only
+  m->G5.add(m->wV, m->X, cw, m->flux, cw, 1, 2, ni, 0, SCALE_PHI, es);
   for (JobList* jl : m->lists())
     if (jl->n()) jl->prepare();
 }
 
 // Stage boundaries: mark(i) is called before stage i and once more at the
-// end; the eager profiling path records a HIP event there.
+// end; the eager profiling path records a HIP event there and runs every
+// stage on the caller's stream in order.  Otherwise the products of the
+// state that the transforms do not need (G1b, and in mixed precision the
+// FP64 mean profiles and mean-column projection) run on the second stream:
+//   s : G1 -> [z inv] -> (wait bar) -> x pencils -> [z fwd] -> G2 -> (wait join) -> RHS ...
+//   s2: (wait fork) -> [Gbar] -> bar -> G1b -> [(wait fwd) -> Gm] -> join
 enum Stage {
-  ST_GEMM_STATE, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_ASSEMBLE, ST_GEMM_DS, ST_RHS,
-  ST_GEMM_VINV, ST_EIGSCALE, ST_GEMM_V, ST_FINALIZE, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
+  ST_GEMM_STATE, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_RHS, ST_GEMM_VINV, ST_GEMM_V,
+  ST_FINALIZE, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
 };
-const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv", "xpencil", "zfft_fwd", "gemm_proj",
-                                            "assemble_h", "gemm_ds", "rhs", "gemm_vinv", "eigscale",
-                                            "gemm_v", "finalize", "diag_rows", "diag_final"};
+static_assert(ST_COUNT == PCS_NSTAGE, "stage table");
+const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv", "xpencil", "zfft_fwd", "gemm_proj", "rhs",
+                                            "gemm_vinv",  "gemm_v",   "finalize", "diag_rows", "diag_final"};
 
 struct NoMark {
   void operator()(int) const {}
@@ -509,9 +538,17 @@ void explicit_stage(pcs_sim* m, const Mark& mark) {
   const Dims& d = m->d;
   hipStream_t s = m->s;
   const bool mixed = m->prec != 0;
+  constexpr bool fork = std::is_same<Mark, NoMark>::value;  // eager profiling stays on one stream
+  hipStream_t s2 = fork ? m->s2 : s;
   mark(ST_GEMM_STATE);
+  if (fork) {
+    (void)hipEventRecord(m->ev_fork, s);
+    (void)hipStreamWaitEvent(s2, m->ev_fork, 0);
+  }
+  if (mixed) m->Gbar.run(s2);
+  if (fork) (void)hipEventRecord(m->ev_bar, s2);
   m->G1.run(s);
-  if (mixed) m->G1b.run(s);
+  m->G1b.run(s2);
   const void* twx = mixed ? (const void*)m->twx32 : (const void*)m->twx;
   const void* twz = mixed ? (const void*)m->twz32 : (const void*)m->twz;
   const void* yin = mixed ? (const void*)m->Yin32 : (const void*)m->Yin;
@@ -519,29 +556,34 @@ void explicit_stage(pcs_sim* m, const Mark& mark) {
   void* zin = mixed ? (void*)m->Zin32 : (void*)m->Zin;
   void* zout = mixed ? (void*)m->Zout32 : (void*)m->Zout;
   mark(ST_ZFFT_INV);
-  if (d.dim == 3) launch_zfft(d, m->plz, yin, zin, m->nzin, m->zsrc, m->zder, m->kz, twz, 1, d.M + 1, m->prec, s);
-  mark(ST_XPENCIL);
   if (d.dim == 3)
-    launch_xpencil(d, m->p, m->plx, zin, zout, m->kx, twx, m->prec, m->Ybar, s);
+    launch_zfft(d, m->plz, yin, zin, m->nzin, m->zsrc, m->zder, m->kz, twz, 1, d.M + 1, m->prec, nullptr, nullptr, s);
+  mark(ST_XPENCIL);
+  if (fork && mixed) (void)hipStreamWaitEvent(s, m->ev_bar, 0);
+  if (d.dim == 3)
+    launch_xpencil(d, m->p, m->plx, zin, zout, m->kx, twx, m->prec, m->Ybar, nullptr, s);
   else
-    launch_xpencil(d, m->p, m->plx, yin, yout, m->kx, twx, m->prec, m->Ybar, s);
+    launch_xpencil(d, m->p, m->plx, yin, yout, m->kx, twx, m->prec, m->Ybar, m->mcol, s);
   mark(ST_ZFFT_FWD);
-  if (d.dim == 3) launch_zfft(d, m->plz, zout, yout, m->nout, nullptr, nullptr, m->kz, twz, 0, d.M + 1, m->prec, s);
+  if (d.dim == 3)
+    launch_zfft(d, m->plz, zout, yout, m->nout, nullptr, nullptr, m->kz, twz, 0, d.M + 1, m->prec, m->Ybar, m->mcol,
+                s);
   mark(ST_GEMM_PROJ);
-  m->G2.run(s);
   if (mixed) {
-    launch_mean_fix(d, m->Yout32, m->Ybar, m->mfix, s);
-    m->G2b.run(s);
+    if (fork) {
+      (void)hipEventRecord(m->ev_fwd, s);
+      (void)hipStreamWaitEvent(s2, m->ev_fwd, 0);
+    }
+    m->Gm.run(s2);
   }
-  mark(ST_ASSEMBLE);
-  const size_t fs = (size_t)(d.N + 1) * d.cw;
-  launch_assemble_h(d, m->p, m->S, m->state + (d.dim == 2 ? 3 : 5) * fs, m->Dc, m->kx, m->kz, m->sbuf, m->hy, m->hgn,
-                    s);
-  mark(ST_GEMM_DS);
-  m->G3.run(s);
+  m->G2.run(s);
+  if (fork) {
+    (void)hipEventRecord(m->ev_join, s2);
+    (void)hipStreamWaitEvent(s, m->ev_join, 0);
+  }
   mark(ST_RHS);
-  launch_rhs(d, m->p, m->state, m->D2buf, m->sbuf, m->Ds, m->hy, m->hgn, m->S, m->kx, m->kz, m->d2i0, m->d2in, m->R,
-             m->hvn, m->CB, s);
+  launch_rhs(d, m->p, m->state, m->D2buf, m->Dc, m->S, m->smean, m->DN, m->kx, m->kz, m->d2i0, m->d2in, m->R, m->hvn,
+             m->hgn, m->CB, s);
 }
 
 template <typename Mark>
@@ -551,15 +593,13 @@ void enqueue_step(pcs_sim* m, const Mark& mark) {
   explicit_stage(m, mark);
   mark(ST_GEMM_VINV);
   m->G4.run(s);
-  mark(ST_EIGSCALE);
-  launch_eigscale(d, m->p, m->X, m->Xs, m->lam, m->kx, m->kz, s);
   mark(ST_GEMM_V);
   m->G5.run(s);
   mark(ST_FINALIZE);
   launch_finalize(d, m->p, m->Zphi, m->Zv, m->ZDv, m->flux, m->infl, m->U1, m->wU1, m->CB, m->hvn, m->hgn, m->S,
-                  m->kx, m->kz, m->state, m->sc, s);
+                  m->smean, m->kx, m->kz, m->state, m->prep, m->sc, s);
   mark(ST_DIAG_ROWS);
-  launch_diag_rows(d, m->p, m->pbx, m->state, m->prep, m->zbuf, m->pbz, m->twbx, m->twbz, m->ydy, m->parts, s);
+  launch_diag_rows(d, m->pbx, m->prep, m->zbuf, m->pbz, m->twbx, m->twbz, m->ydy, m->parts, s);
   mark(ST_DIAG_FINAL);
   launch_diag_final(d, m->p, m->parts, m->w, m->sc, m->ring, RING, s);
   mark(ST_COUNT);
@@ -609,6 +649,15 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
   HIPCHK(up(m->D, kmajor(op->D, n1, n1), s));
   HIPCHK(up(m->D2, kmajor(op->D2, n1, n1), s));
   HIPCHK(up(m->PNM, kmajor(op->PNM, n1, m1), s));
+  // D P: derivative of a projected field straight from the padded grid
+  std::vector<double> DP((size_t)n1 * m1);
+  for (int i = 0; i < n1; ++i)
+    for (int k = 0; k < m1; ++k) {
+      long double acc = 0;
+      for (int j = 0; j < n1; ++j) acc += (long double)op->D[(size_t)i * n1 + j] * op->PNM[(size_t)j * m1 + k];
+      DP[(size_t)i * m1 + k] = (double)acc;
+    }
+  HIPCHK(up(m->DP, kmajor(DP, n1, m1), s));
   HIPCHK(up(m->V, kmajor(op->V, ni, ni), s));
   HIPCHK(up(m->Vinv, kmajor(op->Vinv, ni, ni), s));
   HIPCHK(up(m->lam, op->lam, s));
@@ -645,12 +694,24 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
     }
   HIPCHK(up(m->kx, kx, s));
   HIPCHK(up(m->kz, kz, s));
+  EigScale es{};
+  es.lam = m->lam;
+  es.kx = m->kx;
+  es.kz = m->kz;
+  es.nkx = d.nkx;
+  es.dim = d.dim;
+  es.dt = m->p.dt;
+  es.nu = m->p.nu;
+  es.wi = m->p.wi;
+  es.kappa = m->p.kappa;
+  HIPCHK(up(m->es, std::vector<EigScale>{es}, s));
   HIPCHK(up(m->twx, twiddles(d.px, -1), s));
   HIPCHK(up(m->twbx, twiddles(d.nx, -1), s));
   if (m->prec != 0) {
     HIPCHK(up(m->IMN32, kmajor<float>(op->IMN, m1, n1), s));
     HIPCHK(up(m->DMN32, kmajor<float>(op->DMN, m1, n1), s));
     HIPCHK(up(m->PNM32, kmajor<float>(op->PNM, n1, m1), s));
+    HIPCHK(up(m->DP32, kmajor<float>(DP, n1, m1), s));
     auto tf = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
     HIPCHK(up(m->twx32, tf(twiddles(d.px, -1)), s));
     if (d.dim == 3) HIPCHK(up(m->twz32, tf(twiddles(d.pz, -1)), s));
@@ -745,7 +806,6 @@ pcs_status homogeneous_solutions(pcs_sim* m) {
   HIPCHK(hipMemsetAsync(m->X, 0, m->nsolve * fsi * sizeof(double), s));
   launch_homog_rhs(d, m->p, m->d2i0, m->d2in, m->R, s);
   m->H4.run(s);
-  launch_eigscale(d, m->p, m->X, m->Xs, m->lam, m->kx, m->kz, s);
   m->H5.run(s);
   launch_influence(d, m->Zphi, m->Zv, m->ZDv, m->kz, m->infl, m->U1, s);
   HIPCHK(hipGetLastError());
@@ -771,6 +831,13 @@ pcs_status history_from_state(pcs_sim* m) {
   if (d.dim == 3) HIPCHK(hipMemcpyAsync(hist + (h++) * fs, m->hgn, fs * sizeof(double), hipMemcpyDeviceToDevice, s));
   const int SF = d.dim == 2 ? 2 : 3;
   HIPCHK(hipMemcpyAsync(hist + h * fs, m->S + SF * fs, d.nc * fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+  if (m->smean) {
+    // mixed precision: the mean column of F comes from the FP64 projection
+    const int n1 = d.N + 1;
+    for (int a = 0; a < d.nc; ++a)
+      HIPCHK(hipMemcpy2DAsync(hist + (h + a) * fs, d.cw * sizeof(double), m->smean + (size_t)(SF + a) * n1,
+                              sizeof(double), sizeof(double), n1, hipMemcpyDeviceToDevice, s));
+  }
   return PCS_OK;
 }
 
@@ -789,7 +856,7 @@ pcs_status capture(pcs_sim* m) {
   hipGraphExec_t ge = nullptr;
   if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
     (void)hipGetLastError();
-    hipGraphDestroy(g);
+    (void)hipGraphDestroy(g);
     return PCS_OK;
   }
   m->graph = g;
@@ -834,6 +901,15 @@ pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t see
   }
   carve(m, static_cast<char*>(workspace));
   m->s = static_cast<hipStream_t>(stream);
+  if (hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_bar, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_fwd, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) != hipSuccess) {
+    (void)hipGetLastError();
+    delete m;
+    return PCS_ERR_DEVICE;
+  }
   if (hipError_t e = gemm_set_attributes(); e != hipSuccess) {
     report(e, "gemm_set_attributes", __LINE__);
     delete m;
@@ -970,8 +1046,6 @@ pcs_status pcs_destroy(pcs_sim* m) {
   if (!m) return PCS_ERR_ARG;
   if (m->s) (void)hipStreamSynchronize(m->s);
   else (void)hipDeviceSynchronize();
-  if (m->gexec) hipGraphExecDestroy(m->gexec);
-  if (m->graph) hipGraphDestroy(m->graph);
   delete m;
   return PCS_OK;
 }

@@ -78,51 +78,15 @@ struct Layout {
 
 }  // namespace
 
-// ---------------------------------------------------------------- H, s, h_g
-// H_a = N_a + (1 - beta)/(Re Wi) (i kx c_xa + D c_ya + i kz c_za)
-// s   = i kx H_x + i kz H_z       (mean slot: Re H_x, the mean-flow forcing)
-// h_g = i kz H_x - i kx H_z       (mean slot: Re H_z)
-__global__ void assemble_h_kernel(Dims d, Phys p, const double* __restrict__ S, const double* __restrict__ cf,
-                                  const double* __restrict__ Dc, const double* __restrict__ kx,
-                                  const double* __restrict__ kz, double* __restrict__ sbuf,
-                                  double* __restrict__ hy, double* __restrict__ hgn) {
-  const int n1 = d.N + 1;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n1 * d.nm) return;
-  Mode m = decode(d, e, kx, kz);
-  const size_t fs = (size_t)n1 * d.cw;
-  const size_t off = (size_t)m.j * d.cw + 2 * m.mode;
-  if (m.nyq) {
-    st2(sbuf, off, cd{0, 0});
-    st2(hy, off, cd{0, 0});
-    if (d.dim == 3) st2(hgn, off, cd{0, 0});
-    return;
-  }
-  auto c = [&](int a, int b) { return ld2(cf, cidx(d.dim, a, b) * fs + off); };
-  if (d.dim == 2) {
-    cd Hx = ld2(S, 0 * fs + off) + p.coef * (ik(m.kx, c(0, 0)) + ld2(Dc, 0 * fs + off));
-    cd Hy = ld2(S, 1 * fs + off) + p.coef * (ik(m.kx, c(0, 1)) + ld2(Dc, 1 * fs + off));
-    st2(sbuf, off, m.mean ? cd{Hx.r, 0} : ik(m.kx, Hx));
-    st2(hy, off, Hy);
-  } else {
-    cd Hx = ld2(S, 0 * fs + off) + p.coef * (ik(m.kx, c(0, 0)) + ld2(Dc, 0 * fs + off) + ik(m.kz, c(2, 0)));
-    cd Hy = ld2(S, 1 * fs + off) + p.coef * (ik(m.kx, c(0, 1)) + ld2(Dc, 1 * fs + off) + ik(m.kz, c(2, 1)));
-    cd Hz = ld2(S, 2 * fs + off) + p.coef * (ik(m.kx, c(0, 2)) + ld2(Dc, 2 * fs + off) + ik(m.kz, c(2, 2)));
-    st2(sbuf, off, m.mean ? cd{Hx.r, 0} : ik(m.kx, Hx) + ik(m.kz, Hz));
-    st2(hy, off, Hy);
-    st2(hgn, off, m.mean ? cd{Hz.r, 0} : ik(m.kz, Hx) - ik(m.kx, Hz));
-  }
-}
-
-void launch_assemble_h(const Dims& d, const Phys& p, const double* S, const double* cfields, const double* Dc,
-                       const double* kx, const double* kz, double* sbuf, double* hy, double* hgn, hipStream_t s) {
-  const int n = (d.N + 1) * d.nm;
-  hipLaunchKernelGGL(assemble_h_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, S, cfields, Dc, kx, kz, sbuf,
-                     hy, hgn);
-}
-
-// ---------------------------------------------------------------- RHS
-// CNAB2 right-hand sides at interior rows (the solve works on rows 1..N-1):
+// ---------------------------------------------------------------- explicit assembly and RHS
+// Per element (j, mode), from the projected explicit terms S = [N_x N_y (N_z)
+// F...], DN = [D N_x, (D N_z)], and D c, D2 c of the conformation components:
+//   H_a = N_a + (1 - beta)/(Re Wi) (i kx c_xa + D c_ya + i kz c_za)
+//   D H_x, D H_z: the same with one more D (D2 on c_y.)
+//   h_v = -(i kx D H_x + i kz D H_z) - k^2 H_y,   h_g = i kz H_x - i kx H_z
+//   (mean slot: h_v holds Re H_x, h_g holds Re H_z, the mean-flow forcing)
+// then the CNAB2 right-hand sides at interior rows (the solve works on rows
+// 1..N-1):
 //   phi: (1/dt - nu k^2/2) phi + nu/2 D2 phi + 3/2 h_v - 1/2 h_v^old
 //   U  : U/dt + nu/2 D2 U + 3/2 H_x - 1/2 H_x^old        (mean slot of phi)
 //   g  : as phi with h_g, W in the mean slot (3D)
@@ -131,18 +95,16 @@ void launch_assemble_h(const Dims& d, const Phys& p, const double* S, const doub
 // and the new wall rows of c (kappa = 0 there):
 //   c_B^new = ((1/dt - 1/(2Wi)) c_B + 3/2 F_B - 1/2 F_B^old + delta/Wi) / (1/dt + 1/(2Wi)).
 // Each thread recomputes the two wall values of its mode, so no thread
-// writes anything another thread reads.
-// Buffers: sbuf (mean slot = H_x), Ds = D sbuf, hy, hgn (3D), S = projected
-// explicit terms [N_x N_y (N_z) F...], D2buf = [D2 phi, (D2 g), D2 c...] then
-// D2U (N+1) and D2W (N+1).  Outputs: R [nsolve][N-1 rows], hvn (new h_v),
-// CB [nc][2 walls][cw].
+// writes anything another thread reads.  D2buf = [D2 phi, (D2 g), D2 c...]
+// then D2U (N+1) and D2W (N+1); Dc = [D c...].  smean (mixed precision
+// only) replaces S in the mean column.  Outputs: R [nsolve][N-1 rows], hvn,
+// hgn (3D), CB [nc][2 walls][cw].
 __global__ void rhs_kernel(Dims d, Phys p, const double* __restrict__ st, const double* __restrict__ D2buf,
-                           const double* __restrict__ sbuf, const double* __restrict__ Ds,
-                           const double* __restrict__ hy, const double* __restrict__ hgn,
-                           const double* __restrict__ S, const double* __restrict__ kx,
-                           const double* __restrict__ kz, const double* __restrict__ d2i0,
-                           const double* __restrict__ d2in, double* __restrict__ R, double* __restrict__ hvn,
-                           double* __restrict__ CB) {
+                           const double* __restrict__ Dc, const double* __restrict__ S,
+                           const double* __restrict__ smean, const double* __restrict__ DN,
+                           const double* __restrict__ kx, const double* __restrict__ kz,
+                           const double* __restrict__ d2i0, const double* __restrict__ d2in, double* __restrict__ R,
+                           double* __restrict__ hvn, double* __restrict__ hgn, double* __restrict__ CB) {
   const int n1 = d.N + 1, N = d.N, ni = d.N - 1;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n1 * d.nm) return;
@@ -157,17 +119,41 @@ __global__ void rhs_kernel(Dims d, Phys p, const double* __restrict__ st, const 
   const double dt = p.dt, nu = p.nu;
   if (m.nyq) {
     st2(hvn, off, cd{0, 0});
+    if (d.dim == 3) st2(hgn, off, cd{0, 0});
     if (inter)
       for (int f = 0; f < L.nsolve; ++f) st2(R, f * fsi + offi, cd{0, 0});
     if (!inter)
       for (int a = 0; a < d.nc; ++a) st2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode, cd{0, 0});
     return;
   }
+  const bool msub = m.mean && smean != nullptr;
+  auto Sx = [&](int o, int jj) -> cd {  // explicit term o at row jj of this mode
+    if (msub) return cd{smean[(size_t)o * n1 + jj], 0.0};
+    return ld2(S, (size_t)o * fs + (size_t)jj * d.cw + 2 * m.mode);
+  };
+  auto c = [&](int a, int b) { return ld2(st, (size_t)(L.F_C + cidx(d.dim, a, b)) * fs + off); };
+  auto Dcv = [&](int a, int b) { return ld2(Dc, (size_t)cidx(d.dim, a, b) * fs + off); };
+  auto D2c = [&](int a, int b) { return ld2(D2buf, (size_t)(L.nsv + cidx(d.dim, a, b)) * fs + off); };
+  const double coef = p.coef;
+  cd hv, hg{0, 0};
+  if (d.dim == 2) {
+    const cd Hx = Sx(0, j) + coef * (ik(m.kx, c(0, 0)) + Dcv(0, 1));
+    const cd Hy = Sx(1, j) + coef * (ik(m.kx, c(0, 1)) + Dcv(1, 1));
+    const cd DHx = ld2(DN, off) + coef * (ik(m.kx, Dcv(0, 0)) + D2c(0, 1));
+    hv = m.mean ? cd{Hx.r, 0} : cd{0, 0} - ik(m.kx, DHx) - m.k2 * Hy;
+  } else {
+    const cd Hx = Sx(0, j) + coef * (ik(m.kx, c(0, 0)) + Dcv(0, 1) + ik(m.kz, c(0, 2)));
+    const cd Hy = Sx(1, j) + coef * (ik(m.kx, c(0, 1)) + Dcv(1, 1) + ik(m.kz, c(1, 2)));
+    const cd Hz = Sx(2, j) + coef * (ik(m.kx, c(0, 2)) + Dcv(1, 2) + ik(m.kz, c(2, 2)));
+    const cd DHx = ld2(DN, off) + coef * (ik(m.kx, Dcv(0, 0)) + D2c(0, 1) + ik(m.kz, Dcv(0, 2)));
+    const cd DHz = ld2(DN, fs + off) + coef * (ik(m.kx, Dcv(0, 2)) + D2c(1, 2) + ik(m.kz, Dcv(2, 2)));
+    hv = m.mean ? cd{Hx.r, 0} : cd{0, 0} - ik(m.kx, DHx) - ik(m.kz, DHz) - m.k2 * Hy;
+    hg = m.mean ? cd{Hz.r, 0} : ik(m.kz, Hx) - ik(m.kx, Hz);
+    st2(hgn, off, hg);
+  }
+  st2(hvn, off, hv);
   const double* D2U = D2buf + (size_t)L.nsolve * fs;
   const double* D2W = D2U + n1;
-  // new h_v
-  cd hv = m.mean ? cd{ld2(sbuf, off).r, 0} : cd{0, 0} - ld2(Ds, off) - m.k2 * ld2(hy, off);
-  st2(hvn, off, hv);
   if (inter) {
     cd r;
     const cd hvo = ld2(st, (size_t)L.H_HV * fs + off);
@@ -180,7 +166,7 @@ __global__ void rhs_kernel(Dims d, Phys p, const double* __restrict__ st, const 
     }
     st2(R, 0 * fsi + offi, r);
     if (d.dim == 3) {
-      const cd hg = ld2(hgn, off), hgo = ld2(st, (size_t)L.H_HG * fs + off);
+      const cd hgo = ld2(st, (size_t)L.H_HG * fs + off);
       if (m.mean) {
         const double W = st[(size_t)L.F_W * fs + off];
         r = cd{W / dt + 0.5 * nu * D2W[j] + 1.5 * hg.r - 0.5 * hgo.r, 0};
@@ -194,15 +180,15 @@ __global__ void rhs_kernel(Dims d, Phys p, const double* __restrict__ st, const 
   const double a_int = 1.0 / dt - 0.5 / p.wi, a_new = 1.0 / dt + 0.5 / p.wi;
   for (int a = 0; a < d.nc; ++a) {
     const double* cf = st + (size_t)(L.F_C + a) * fs;
-    const double* Fn = S + (size_t)(L.S_F + a) * fs;
     const double* Fo = st + (size_t)(L.H_F + a) * fs;
     const bool diag = (d.dim == 2) ? (a == 0 || a == 2) : (a == 0 || a == 3 || a == 5);
     const cd src = cd{(m.mean && diag) ? 1.0 / p.wi : 0.0, 0};
-    const cd cb0 = (1.0 / a_new) * (a_int * ld2(cf, off0) + 1.5 * ld2(Fn, off0) - 0.5 * ld2(Fo, off0) + src);
-    const cd cbN = (1.0 / a_new) * (a_int * ld2(cf, offN) + 1.5 * ld2(Fn, offN) - 0.5 * ld2(Fo, offN) + src);
+    const int o = L.S_F + a;
+    const cd cb0 = (1.0 / a_new) * (a_int * ld2(cf, off0) + 1.5 * Sx(o, 0) - 0.5 * ld2(Fo, off0) + src);
+    const cd cbN = (1.0 / a_new) * (a_int * ld2(cf, offN) + 1.5 * Sx(o, N) - 0.5 * ld2(Fo, offN) + src);
     if (inter) {
       cd r = (a_int - 0.5 * p.kappa * m.k2) * ld2(cf, off) + (0.5 * p.kappa) * ld2(D2buf, (L.nsv + a) * fs + off) +
-             1.5 * ld2(Fn, off) - 0.5 * ld2(Fo, off) + src;
+             1.5 * Sx(o, j) - 0.5 * ld2(Fo, off) + src;
       if (p.kappa > 0) r = r + (0.5 * p.kappa) * (d2i0[j - 1] * cb0 + d2in[j - 1] * cbN);
       st2(R, (size_t)(L.nsv + a) * fsi + offi, r);
     } else {
@@ -211,52 +197,13 @@ __global__ void rhs_kernel(Dims d, Phys p, const double* __restrict__ st, const 
   }
 }
 
-void launch_rhs(const Dims& d, const Phys& p, const double* state, const double* D2buf, const double* sbuf,
-                const double* Ds, const double* hy, const double* hgn, const double* S, const double* kx,
-                const double* kz, const double* d2i0, const double* d2in, double* R, double* hvn, double* CB,
+void launch_rhs(const Dims& d, const Phys& p, const double* state, const double* D2buf, const double* Dc,
+                const double* S, const double* smean, const double* DN, const double* kx, const double* kz,
+                const double* d2i0, const double* d2in, double* R, double* hvn, double* hgn, double* CB,
                 hipStream_t s) {
   const int n = (d.N + 1) * d.nm;
-  hipLaunchKernelGGL(rhs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, state, D2buf, sbuf, Ds, hy, hgn, S,
-                     kx, kz, d2i0, d2in, R, hvn, CB);
-}
-
-// ---------------------------------------------------------------- eigen-space scaling
-// With D2_II = V diag(lam) V^-1 each Dirichlet Helmholtz operator
-// (alpha - gamma D2_II) is diagonal in X = V^-1 R:
-//   phi (and U in the mean slot): X / (1/dt + nu k^2/2 - nu/2 lam)
-//   v from lap v = phi:            (X / (...)) / (lam - k^2)
-//   g  (and W):                    X / (1/dt + nu k^2/2 - nu/2 lam)
-//   c:                             X / (1/dt + 1/(2Wi) + kappa k^2/2 - kappa/2 lam)
-// Xs order: phi, v, (g), c...
-__global__ void eigscale_kernel(Dims d, Phys p, const double* __restrict__ X, double* __restrict__ Xs,
-                                const double* __restrict__ lam, const double* __restrict__ kx,
-                                const double* __restrict__ kz) {
-  const int ni = d.N - 1;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ni * d.nm) return;
-  const Layout L(d.dim, d.nc);
-  Mode m = decode(d, e, kx, kz);  // m.j is the eigen index here
-  const double le = lam[m.j];
-  const size_t fsi = (size_t)ni * d.cw;
-  const size_t off = (size_t)m.j * d.cw + 2 * m.mode;
-  const double aphi = 1.0 / p.dt + 0.5 * p.nu * m.k2 - 0.5 * p.nu * le;
-  cd x = ld2(X, off);
-  cd xp = (1.0 / aphi) * x;
-  st2(Xs, 0 * fsi + off, xp);
-  st2(Xs, 1 * fsi + off, m.mean ? cd{0, 0} : (1.0 / (le - m.k2)) * xp);
-  int o = 2;
-  if (d.dim == 3) {
-    st2(Xs, 2 * fsi + off, (1.0 / aphi) * ld2(X, 1 * fsi + off));
-    o = 3;
-  }
-  const double ac = 1.0 / p.dt + 0.5 / p.wi + 0.5 * p.kappa * m.k2 - 0.5 * p.kappa * le;
-  for (int a = 0; a < d.nc; ++a) st2(Xs, (size_t)(o + a) * fsi + off, (1.0 / ac) * ld2(X, (size_t)(L.nsv + a) * fsi + off));
-}
-
-void launch_eigscale(const Dims& d, const Phys& p, const double* X, double* Xs, const double* lam, const double* kx,
-                     const double* kz, hipStream_t s) {
-  const int n = (d.N - 1) * d.nm;
-  hipLaunchKernelGGL(eigscale_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, X, Xs, lam, kx, kz);
+  hipLaunchKernelGGL(rhs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, state, D2buf, Dc, S, smean, DN, kx, kz,
+                     d2i0, d2in, R, hvn, hgn, CB);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -275,8 +222,9 @@ __global__ void finalize_kernel(Dims d, Phys p, const double* __restrict__ Zphi,
                                 const double* __restrict__ infl, const double* __restrict__ U1, double wU1,
                                 const double* __restrict__ CB, const double* __restrict__ hvn,
                                 const double* __restrict__ hgn, const double* __restrict__ S,
-                                const double* __restrict__ kx, const double* __restrict__ kz,
-                                double* __restrict__ st, DevScalars* __restrict__ sc) {
+                                const double* __restrict__ smean, const double* __restrict__ kx,
+                                const double* __restrict__ kz, double* __restrict__ st, double* __restrict__ prep,
+                                DevScalars* __restrict__ sc) {
   const int n1 = d.N + 1, N = d.N;
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n1 * d.nm) return;
@@ -290,27 +238,45 @@ __global__ void finalize_kernel(Dims d, Phys p, const double* __restrict__ Zphi,
   // history: h_v, h_g, F <- this step's explicit terms
   st2(st, (size_t)L.H_HV * fs + off, ld2(hvn, off));
   if (d.dim == 3) st2(st, (size_t)L.H_HG * fs + off, ld2(hgn, off));
-  for (int a = 0; a < d.nc; ++a) st2(st, (size_t)(L.H_F + a) * fs + off, ld2(S, (size_t)(L.S_F + a) * fs + off));
+  for (int a = 0; a < d.nc; ++a) {
+    const cd F = (m.mean && smean) ? cd{smean[(size_t)(L.S_F + a) * n1 + j], 0.0}
+                                   : ld2(S, (size_t)(L.S_F + a) * fs + off);
+    st2(st, (size_t)(L.H_F + a) * fs + off, F);
+  }
   // c wall rows (interior rows were written by the solve product)
   if (!inter)
     for (int a = 0; a < d.nc; ++a)
       st2(st, (size_t)(L.F_C + a) * fs + off, ld2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode));
+  // spectral inputs of the diagnostics: Tr c (c_xx + c_yy (+ c_zz)), u, v, w
+  auto diag_prep = [&](cd u, cd v, cd w) {
+    cd tr = ld2(st, (size_t)L.F_C * fs + off) + ld2(st, (size_t)(L.F_C + (d.dim == 2 ? 2 : 3)) * fs + off);
+    if (d.dim == 3) tr = tr + ld2(st, (size_t)(L.F_C + 5) * fs + off);
+    st2(prep, off, tr);
+    st2(prep, fs + off, u);
+    st2(prep, 2 * fs + off, v);
+    if (d.dim == 3) st2(prep, 3 * fs + off, w);
+  };
   if (m.nyq) {
     for (int f = 0; f < L.nq; ++f) st2(st, (size_t)f * fs + off, cd{0, 0});
+    diag_prep(cd{0, 0}, cd{0, 0}, cd{0, 0});
     return;
   }
   if (m.mean) {
     const double Up = inter ? Zphi[offi] : 0.0;
     const double pi = (p.forcing == 0) ? (p.q_or_dpdx - flux[0]) / wU1 : p.q_or_dpdx;
     if (e == 0) sc->pi = pi;
-    st2(st, (size_t)L.F_U * fs + off, cd{Up + pi * U1[j], 0});
+    const cd U{Up + pi * U1[j], 0};
+    st2(st, (size_t)L.F_U * fs + off, U);
     st2(st, (size_t)L.F_V * fs + off, cd{0, 0});
     st2(st, (size_t)L.F_PHI * fs + off, cd{0, 0});
+    cd W{0, 0};
     if (d.dim == 3) {
-      const double W = st[(size_t)L.F_G * fs + off];  // interior rows from the solve, walls zero
-      st2(st, (size_t)L.F_W * fs + off, cd{inter ? W : 0.0, 0});
+      const double Wv = st[(size_t)L.F_G * fs + off];  // interior rows from the solve, walls zero
+      W = cd{inter ? Wv : 0.0, 0};
+      st2(st, (size_t)L.F_W * fs + off, W);
       st2(st, (size_t)L.F_G * fs + off, cd{0, 0});
     }
+    diag_prep(U, cd{0, 0}, W);
     return;
   }
   const size_t pm = (size_t)n1 * d.nm;
@@ -333,23 +299,28 @@ __global__ void finalize_kernel(Dims d, Phys p, const double* __restrict__ Zphi,
   st2(st, (size_t)L.F_V * fs + off, v);
   const double ik2 = 1.0 / m.k2;
   if (d.dim == 2) {
-    st2(st, (size_t)L.F_U * fs + off, ik2 * ik(m.kx, Dv));
+    const cd u = ik2 * ik(m.kx, Dv);
+    st2(st, (size_t)L.F_U * fs + off, u);
+    diag_prep(u, v, cd{0, 0});
   } else {
     // g: interior rows come from the solve product, wall rows are zero
     const cd g = inter ? ld2(st, (size_t)L.F_G * fs + off) : cd{0, 0};
     if (!inter) st2(st, (size_t)L.F_G * fs + off, cd{0, 0});
-    st2(st, (size_t)L.F_U * fs + off, ik2 * (ik(m.kx, Dv) - ik(m.kz, g)));
-    st2(st, (size_t)L.F_W * fs + off, ik2 * (ik(m.kz, Dv) + ik(m.kx, g)));
+    const cd u = ik2 * (ik(m.kx, Dv) - ik(m.kz, g));
+    const cd w = ik2 * (ik(m.kz, Dv) + ik(m.kx, g));
+    st2(st, (size_t)L.F_U * fs + off, u);
+    st2(st, (size_t)L.F_W * fs + off, w);
+    diag_prep(u, v, w);
   }
 }
 
 void launch_finalize(const Dims& d, const Phys& p, const double* Zphi, const double* Zv, const double* ZDv,
                      const double* flux, const double* infl, const double* U1, double wU1, const double* CB,
-                     const double* hvn, const double* hgn, const double* S, const double* kx, const double* kz,
-                     double* state, DevScalars* sc, hipStream_t s) {
+                     const double* hvn, const double* hgn, const double* S, const double* smean, const double* kx,
+                     const double* kz, double* state, double* prep, DevScalars* sc, hipStream_t s) {
   const int n = (d.N + 1) * d.nm;
   hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, Zphi, Zv, ZDv, flux, infl, U1,
-                     wU1, CB, hvn, hgn, S, kx, kz, state, sc);
+                     wU1, CB, hvn, hgn, S, smean, kx, kz, state, prep, sc);
 }
 
 // ---------------------------------------------------------------- init: homogeneous solutions

@@ -274,6 +274,28 @@ __host__ __device__ constexpr int mean_of(int dim, int f) {
 }
 __host__ __device__ constexpr int n_means(int dim) { return dim == 2 ? 8 : 16; }
 
+// Product of the mean profiles in explicit term o at padded row i, FP64.  For
+// profiles only the y-derivatives of the mean velocity (U', W') survive
+// (v = 0, d/dx = d/dz = 0), so N = 0 and F_ab = U'_a c_yb + c_ay U'_b with
+// U'_x = U', U'_z = W'.
+__device__ inline double mean_product(int dim, int o, const double* __restrict__ mean, int m1, int i) {
+  auto M = [&](int k) { return mean[(size_t)k * m1 + i]; };
+  if (dim == 2) {
+    // means: U U' cxx cxy cyy ...; outputs: Nx Ny Fxx Fxy Fyy
+    if (o == 2) return 2.0 * M(1) * M(3);
+    if (o == 3) return M(1) * M(4);
+    return 0.0;
+  }
+  // means: U W U' W' cxx cxy cxz cyy cyz czz ...; outputs: Nx Ny Nz Fxx Fxy Fxz Fyy Fyz Fzz
+  const double Up = M(2), Wp = M(3);
+  if (o == 3) return 2.0 * Up * M(5);
+  if (o == 4) return Up * M(7);
+  if (o == 5) return Up * M(8) + M(5) * Wp;
+  if (o == 7) return Wp * M(7);
+  if (o == 8) return 2.0 * Wp * M(8);
+  return 0.0;
+}
+
 template <typename T>
 struct MF {
   T m, f;  // mean part and fluctuation
@@ -332,7 +354,8 @@ template <typename T, int DIM, bool MIXED>
 __global__ __launch_bounds__(NT) void xpencil_kernel(const T* __restrict__ in, T* __restrict__ out, int nrows,
                                                      int nkx, FftPlan pl, const double* __restrict__ kx,
                                                      const cx<T>* __restrict__ tw, double eps_wi,
-                                                     const double* __restrict__ mean, int m1, int pz) {
+                                                     const double* __restrict__ mean, double* __restrict__ mcol,
+                                                     int m1, int pz) {
   using XS = XShape<DIM>;
   extern __shared__ double smem_d[];
   cx<T>* P = reinterpret_cast<cx<T>*>(smem_d);
@@ -411,6 +434,13 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const T* __restrict__ in, T
         pb[0] = B.x * inv;
         pb[1] = B.y * inv;
       }
+      if constexpr (MIXED && DIM == 2) {
+        // the kx = 0 column is the whole mean (2D has no z): complete it in FP64
+        if (k == 0) {
+          mcol[(size_t)fa * m1 + row] = double(A.x * inv) + mean_product(2, fa, mean, m1, row);
+          if (fb < XS::NOUT) mcol[(size_t)fb * m1 + row] = double(B.x * inv) + mean_product(2, fb, mean, m1, row);
+        }
+      }
     }
   }
 }
@@ -431,7 +461,8 @@ template <typename T>
 __global__ __launch_bounds__(NT) void zfft_kernel(const T* __restrict__ in, T* __restrict__ out, int nkx, int nzs,
                                                   int rows_y, FftPlan pl, const int* __restrict__ src_field,
                                                   const int* __restrict__ deriv, const double* __restrict__ kz,
-                                                  const cx<T>* __restrict__ tw, int inverse) {
+                                                  const cx<T>* __restrict__ tw, int inverse,
+                                                  const double* __restrict__ mean, double* __restrict__ mcol) {
   typedef cx<T> c2;
   extern __shared__ double smem_z[];
   c2* A = reinterpret_cast<c2*>(smem_z);
@@ -484,42 +515,21 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const T* __restrict__ in, T* _
       }
       ob[((size_t)s * nkx + k0 + g) * 2] = v.x;
       ob[((size_t)s * nkx + k0 + g) * 2 + 1] = v.y;
+      // mixed forward transform: the kx = kz = 0 value completed in FP64
+      if (mcol && s == 0 && k0 + g == 0)
+        mcol[(size_t)f * rows_y + i] = double(v.x) + mean_product(3, f, mean, rows_y, i);
     }
   }
 }
 
 // ---------------------------------------------------------------- diagnostics
-// Base-grid values of Tr c, u, v, w on every (y_j, z) line: spectral Tr c =
-// c_xx + c_yy (+ c_zz) is formed first (2D adds the constant c_zz = 1 after
-// the transform), then the inverse x transform.  Per line: min Tr c, counts of
+// Base-grid values of Tr c, u, v, w on every (y_j, z) line from their spectral
+// values (Tr c = c_xx + c_yy (+ c_zz) is formed by the step's last kernel; 2D
+// adds the constant c_zz = 1 after the transform) by the inverse x transform.  Per line: min Tr c, counts of
 // Tr c < 3 and < 0 (strict), max CFL contribution |u|/dx + |v|/dy_j + |w|/dz,
 // sums of |u|^2/2 and Tr c, and non-finite / |Tr c| > 1e12 flags.  Sums are
 // reduced in a fixed order (wave butterflies, then waves in index order), so
 // replays are bitwise reproducible.
-__global__ void diag_prep_kernel(Dims d, const double* __restrict__ st, double* __restrict__ outb) {
-  const int n1 = d.N + 1;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n1 * d.nm) return;
-  const size_t fs = (size_t)n1 * d.cw;
-  const size_t off = (size_t)(e / d.nm) * d.cw + 2 * (e % d.nm);
-  const int FC = d.dim == 2 ? 3 : 5;
-  double tr_r, tr_i;
-  if (d.dim == 2) {
-    tr_r = st[(FC + 0) * fs + off] + st[(FC + 2) * fs + off];
-    tr_i = st[(FC + 0) * fs + off + 1] + st[(FC + 2) * fs + off + 1];
-  } else {
-    tr_r = st[(FC + 0) * fs + off] + st[(FC + 3) * fs + off] + st[(FC + 5) * fs + off];
-    tr_i = st[(FC + 0) * fs + off + 1] + st[(FC + 3) * fs + off + 1] + st[(FC + 5) * fs + off + 1];
-  }
-  outb[off] = tr_r;
-  outb[off + 1] = tr_i;
-  const int nv = d.dim == 2 ? 2 : 3;
-  for (int q = 0; q < nv; ++q) {
-    outb[(q + 1) * fs + off] = st[q * fs + off];
-    outb[(q + 1) * fs + off + 1] = st[q * fs + off + 1];
-  }
-}
-
 __device__ inline double wave_min(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmin(v, __shfl_xor(v, o));
   return v;
@@ -706,95 +716,55 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(Dims d, Phys p, const Di
   }
 }
 
-// Mean-mode fix of the mixed path: the kx = kz = 0 column of each explicit
-// term on the padded grid is the FP32 mean of the fluctuation products plus
-// the FP64 product of the mean profiles.  Only the y-derivatives of the mean
-// velocity (U', W') survive (v = 0 and d/dx, d/dz vanish for a profile), so
-// N = 0 and F_ab = U'_a c_yb + c_ay U'_b with U'_x = U', U'_z = W'.
-__global__ void mean_fix_kernel(Dims d, const float* __restrict__ yout32, const double* __restrict__ mean,
-                                double* __restrict__ tmp) {
-  const int m1 = d.M + 1;
-  const int nout = d.dim == 2 ? 5 : 9;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= nout * m1) return;
-  const int o = e / m1, i = e - o * m1;
-  const double fl = (double)yout32[((size_t)o * m1 + i) * d.cw];
-  double mm = 0.0;
-  auto M = [&](int k) { return mean[(size_t)k * m1 + i]; };
-  if (d.dim == 2) {
-    // means: U U' cxx cxy cyy ...; outputs: Nx Ny Fxx Fxy Fyy
-    if (o == 2) mm = 2.0 * M(1) * M(3);
-    if (o == 3) mm = M(1) * M(4);
-  } else {
-    // means: U W U' W' cxx cxy cxz cyy cyz czz ...; outputs: Nx Ny Nz Fxx Fxy Fxz Fyy Fyz Fzz
-    const double Up = M(2), Wp = M(3), cxy = M(5), cyy = M(7), cyz = M(8);
-    if (o == 3) mm = 2.0 * Up * cxy;
-    if (o == 4) mm = Up * cyy;
-    if (o == 5) mm = Up * cyz + cxy * Wp;
-    if (o == 7) mm = Wp * cyy;
-    if (o == 8) mm = 2.0 * Wp * cyz;
-  }
-  tmp[e] = fl + mm;
-}
-
 }  // namespace
 
 void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const void* in, void* out, const double* kx,
-                    const void* tw, int precision, const double* mean, hipStream_t s) {
+                    const void* tw, int precision, const double* mean, double* mcol, hipStream_t s) {
   const int rows = (d.M + 1) * d.pz;
   const int m1 = d.M + 1;
   if (precision == 0) {
     if (d.dim == 2)
       hipLaunchKernelGGL((xpencil_kernel<double, 2, false>), dim3(rows), dim3(NT), (xpencil_lds<double, 2>(plan.L)), s,
                          (const double*)in, (double*)out, rows, d.nkx, plan, kx, (const cx<double>*)tw, p.eps / p.wi,
-                         mean, m1, d.pz);
+                         nullptr, nullptr, m1, d.pz);
     else
       hipLaunchKernelGGL((xpencil_kernel<double, 3, false>), dim3(rows), dim3(NT), (xpencil_lds<double, 3>(plan.L)), s,
                          (const double*)in, (double*)out, rows, d.nkx, plan, kx, (const cx<double>*)tw, p.eps / p.wi,
-                         mean, m1, d.pz);
+                         nullptr, nullptr, m1, d.pz);
   } else {
     if (d.dim == 2)
       hipLaunchKernelGGL((xpencil_kernel<float, 2, true>), dim3(rows), dim3(NT), (xpencil_lds<float, 2>(plan.L)), s,
-                         (const float*)in, (float*)out, rows, d.nkx, plan, kx, (const cx<float>*)tw, 0.0, mean, m1,
-                         d.pz);
+                         (const float*)in, (float*)out, rows, d.nkx, plan, kx, (const cx<float>*)tw, 0.0, mean, mcol,
+                         m1, d.pz);
     else
       hipLaunchKernelGGL((xpencil_kernel<float, 3, true>), dim3(rows), dim3(NT), (xpencil_lds<float, 3>(plan.L)), s,
-                         (const float*)in, (float*)out, rows, d.nkx, plan, kx, (const cx<float>*)tw, 0.0, mean, m1,
-                         d.pz);
+                         (const float*)in, (float*)out, rows, d.nkx, plan, kx, (const cx<float>*)tw, 0.0, mean,
+                         nullptr, m1, d.pz);
   }
 }
 
 void launch_zfft(const Dims& d, const FftPlan& plan, const void* in, void* out, int nfields, const int* src_field,
                  const int* deriv, const double* kz, const void* tw, int inverse, int rows, int precision,
-                 hipStream_t s) {
+                 const double* mean, double* mcol, hipStream_t s) {
   dim3 grid((d.nkx + ZG - 1) / ZG, rows, nfields);
   if (precision == 0) {
     const size_t lds = (size_t)ZG * plan.L * sizeof(cx<double>);
     hipLaunchKernelGGL(zfft_kernel<double>, grid, dim3(NT), lds, s, (const double*)in, (double*)out, d.nkx, d.nzs, rows,
-                       plan, src_field, deriv, kz, (const cx<double>*)tw, inverse);
+                       plan, src_field, deriv, kz, (const cx<double>*)tw, inverse, nullptr, nullptr);
   } else {
     const size_t lds = (size_t)ZG * plan.L * sizeof(cx<float>);
     hipLaunchKernelGGL(zfft_kernel<float>, grid, dim3(NT), lds, s, (const float*)in, (float*)out, d.nkx, d.nzs, rows,
-                       plan, src_field, deriv, kz, (const cx<float>*)tw, inverse);
+                       plan, src_field, deriv, kz, (const cx<float>*)tw, inverse, mean, inverse ? nullptr : mcol);
   }
 }
 
-void launch_mean_fix(const Dims& d, const float* yout32, const double* mean, double* tmp, hipStream_t s) {
-  const int n = (d.dim == 2 ? 5 : 9) * (d.M + 1);
-  hipLaunchKernelGGL(mean_fix_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, yout32, mean, tmp);
-}
-
-void launch_diag_rows(const Dims& d, const Phys& p, const FftPlan& planx, const double* st, double* prep,
-                      double* zbuf, const FftPlan& planz, const double* twx, const double* twz, const double* ydy,
-                      DiagPart* parts, hipStream_t s) {
-  (void)p;
+void launch_diag_rows(const Dims& d, const FftPlan& planx, const double* prep, double* zbuf, const FftPlan& planz,
+                      const double* twx, const double* twz, const double* ydy, DiagPart* parts, hipStream_t s) {
   const int n1 = d.N + 1;
-  const int n = n1 * d.nm;
-  hipLaunchKernelGGL(diag_prep_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, st, prep);
   const double* src = prep;
   int zrows = 1;
   if (d.dim == 3) {
-    launch_zfft(d, planz, prep, zbuf, 4, nullptr, nullptr, nullptr, twz, 1, n1, 0, s);
+    launch_zfft(d, planz, prep, zbuf, 4, nullptr, nullptr, nullptr, twz, 1, n1, 0, nullptr, nullptr, s);
     src = zbuf;
     zrows = d.nz;
   }

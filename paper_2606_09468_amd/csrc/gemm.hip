@@ -114,17 +114,56 @@ __global__ __launch_bounds__(256) void gemm_kernel(const GemmJob* __restrict__ j
     const int c = tid % GEMM_BN, rr = tid / GEMM_BN;
     const int gc = col0 + c;
     const bool cok = gc < J.n && !((J.flags & GEMM_ZERO_MEAN) && gc < 2);
-    for (int r0 = 0; r0 < K4; r0 += UNR * RPP) {
-      T v[UNR];
+    if (J.scale == SCALE_NONE) {
+      for (int r0 = 0; r0 < K4; r0 += UNR * RPP) {
+        T v[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int r = r0 + u * RPP + rr;
-        v[u] = (r < J.k && cok) ? T(B[(size_t)r * J.ldb + gc]) : T(0);
+        for (int u = 0; u < UNR; ++u) {
+          const int r = r0 + u * RPP + rr;
+          v[u] = (r < J.k && cok) ? T(B[(size_t)r * J.ldb + gc]) : T(0);
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int r = r0 + u * RPP + rr;
+          if (r < K4) Bs[r * LDB + c] = v[u];
+        }
       }
+    } else {
+      // B row r is eigen coefficient r of column gc's mode: scale by the
+      // inverse of that mode's Helmholtz symbol (see EigScale)
+      const EigScale es = *J.es;
+      const int mode = cok ? gc >> 1 : 0, iz = mode / es.nkx, ix = mode - iz * es.nkx;
+      const double kxv = es.kx[ix], kzv = (es.dim == 3) ? es.kz[iz] : 0.0;
+      const double k2 = kxv * kxv + kzv * kzv;
+      double a0, a1;  // symbol = a0 - a1 * lam
+      if (J.scale == SCALE_C) {
+        a0 = 1.0 / es.dt + 0.5 / es.wi + 0.5 * es.kappa * k2;
+        a1 = 0.5 * es.kappa;
+      } else {
+        a0 = 1.0 / es.dt + 0.5 * es.nu * k2;
+        a1 = 0.5 * es.nu;
+      }
+      const bool vz = (J.scale == SCALE_V) && mode == 0;
+      for (int r0 = 0; r0 < K4; r0 += UNR * RPP) {
+        double v[UNR];
 #pragma unroll
-      for (int u = 0; u < UNR; ++u) {
-        const int r = r0 + u * RPP + rr;
-        if (r < K4) Bs[r * LDB + c] = v[u];
+        for (int u = 0; u < UNR; ++u) {
+          const int r = r0 + u * RPP + rr;
+          v[u] = (r < J.k && cok && !vz) ? double(B[(size_t)r * J.ldb + gc]) : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < UNR; ++u) {
+          const int r = r0 + u * RPP + rr;
+          if (r < K4) {
+            double f = 0.0;
+            if (r < J.k) {
+              const double lam = es.lam[r];
+              f = 1.0 / (a0 - a1 * lam);
+              if (J.scale == SCALE_V) f = f / (lam - k2);
+            }
+            Bs[r * LDB + c] = T(v[u] * f);
+          }
+        }
       }
     }
   }

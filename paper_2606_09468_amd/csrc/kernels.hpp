@@ -12,6 +12,7 @@ namespace pcs {
 // B (k x n) and C (m x n) are row-major, each in its own precision (see
 // GemmType).  Complex fields (re/im interleaved) are multiplied by a real
 // operator by treating each complex column as two real columns.
+struct EigScale;
 struct GemmJob {
   const void* A;
   const void* B;
@@ -19,9 +20,25 @@ struct GemmJob {
   int m, n, k, lda, ldb, ldc;
   double alpha, beta;
   int flags;           // GEMM_ZERO_MEAN: B columns 0 and 1 (the kx = kz = 0 mode) read as zero
+  int scale;           // SCALE_*: B rows are eigen coefficients scaled on the way into LDS
+  const EigScale* es;  // per-solve constants for the scaling
   int tiles_m, tile0;  // filled by gemm_prepare
 };
 constexpr int GEMM_ZERO_MEAN = 1;
+
+// Diagonal of the Dirichlet Helmholtz operators in the eigenbasis of the
+// interior D2 block (D2_II = V diag(lam) V^-1), applied to X = V^-1 R:
+//   SCALE_PHI: 1/(1/dt + nu k^2/2 - nu lam/2)       (phi, g; U and W in the mean slot)
+//   SCALE_V:   that / (lam - k^2), 0 in the mean slot (v from lap v = phi)
+//   SCALE_C:   1/(1/dt + 1/(2Wi) + kappa k^2/2 - kappa lam/2)
+enum { SCALE_NONE = 0, SCALE_PHI, SCALE_V, SCALE_C };
+struct EigScale {
+  const double* lam;
+  const double* kx;
+  const double* kz;
+  int nkx, dim;
+  double dt, nu, wi, kappa;
+};
 
 // compute / B / C precisions: D = double, F = float
 enum GemmType { GEMM_DDD = 0, GEMM_FDF, GEMM_FFD, GEMM_DDF, GEMM_DFD, GEMM_NTYPES };
@@ -93,14 +110,15 @@ struct DiagPart {
 // precision 0: FP64 buffers and products; otherwise FP32 buffers, the mixed
 // mean/fluctuation products and `mean` = [n_means][M+1] FP64 profiles.
 void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const void* in, void* out, const double* kx,
-                    const void* tw, int precision, const double* mean, hipStream_t s);
+                    const void* tw, int precision, const double* mean, double* mcol, hipStream_t s);
+// mcol (mixed forward only, else null): [nfields][rows] FP64 kx = kz = 0 column
+// of the output plus the product of the mean profiles `mean`.
 void launch_zfft(const Dims& d, const FftPlan& plan, const void* in, void* out, int nfields, const int* src_field,
                  const int* deriv, const double* kz, const void* tw, int inverse, int rows, int precision,
-                 hipStream_t s);
-void launch_mean_fix(const Dims& d, const float* yout32, const double* mean, double* tmp, hipStream_t s);
-void launch_diag_rows(const Dims& d, const Phys& p, const FftPlan& planx, const double* st, double* prep,
-                      double* zbuf, const FftPlan& planz, const double* twx, const double* twz, const double* ydy,
-                      DiagPart* parts, hipStream_t s);
+                 const double* mean, double* mcol, hipStream_t s);
+// prep: [4][N+1][kz][kx] spectral Tr c, u, v, w written by the finalize kernel
+void launch_diag_rows(const Dims& d, const FftPlan& planx, const double* prep, double* zbuf, const FftPlan& planz,
+                      const double* twx, const double* twz, const double* ydy, DiagPart* parts, hipStream_t s);
 void launch_diag_final(const Dims& d, const Phys& p, const DiagPart* parts, const double* w, DevScalars* sc,
                        DiagRec* ring, int ring_cap, hipStream_t s);
 // Raises the dynamic-LDS limit of the transform kernels (call once, outside capture).
@@ -108,18 +126,16 @@ hipError_t fft_set_attributes();
 size_t xpencil_lds_bytes(int dim, int L, int precision);
 
 // ---- launchers (elem.hip)
-void launch_assemble_h(const Dims& d, const Phys& p, const double* S, const double* cfields, const double* Dc,
-                       const double* kx, const double* kz, double* sbuf, double* hy, double* hgn, hipStream_t s);
-void launch_rhs(const Dims& d, const Phys& p, const double* state, const double* D2buf, const double* sbuf,
-                const double* Ds, const double* hy, const double* hgn, const double* S, const double* kx,
-                const double* kz, const double* d2i0, const double* d2in, double* R, double* hvn, double* CB,
+// smean: mixed path only, [nout][N+1] FP64 projection of the kx = kz = 0
+// column of the explicit terms (null in FP64, where S holds it).
+void launch_rhs(const Dims& d, const Phys& p, const double* state, const double* D2buf, const double* Dc,
+                const double* S, const double* smean, const double* DN, const double* kx, const double* kz,
+                const double* d2i0, const double* d2in, double* R, double* hvn, double* hgn, double* CB,
                 hipStream_t s);
-void launch_eigscale(const Dims& d, const Phys& p, const double* X, double* Xs, const double* lam, const double* kx,
-                     const double* kz, hipStream_t s);
 void launch_finalize(const Dims& d, const Phys& p, const double* Zphi, const double* Zv, const double* ZDv,
                      const double* flux, const double* infl, const double* U1, double wU1, const double* CB,
-                     const double* hvn, const double* hgn, const double* S, const double* kx, const double* kz,
-                     double* state, DevScalars* sc, hipStream_t s);
+                     const double* hvn, const double* hgn, const double* S, const double* smean, const double* kx,
+                     const double* kz, double* state, double* prep, DevScalars* sc, hipStream_t s);
 void launch_homog_rhs(const Dims& d, const Phys& p, const double* d2i0, const double* d2in, double* R,
                       hipStream_t s);
 void launch_influence(const Dims& d, const double* Zphi, const double* Zv, const double* ZDv, const double* kz,
