@@ -47,9 +47,9 @@ struct JobList {
   std::vector<GemmJob> h;
   GemmJob* dev = nullptr;
   GemmType type = GEMM_DDD;
-  int tiles = 0, bm = 64, kmax = 0;
+  int tiles = 0, cfg = 0;
   void add(const void* A, const void* B, int ldb, void* C, int ldc, int m, int n, int k, int flags = 0,
-           int scale = SCALE_NONE, const EigScale* es = nullptr) {
+           int scale = SCALE_NONE, const EigScale* es = nullptr, void* C2 = nullptr, int scale2 = SCALE_NONE) {
     GemmJob j{};
     j.A = A;
     j.B = B;
@@ -57,29 +57,29 @@ struct JobList {
     j.m = m;
     j.n = n;
     j.k = k;
-    j.lda = m;  // operators are stored K-major
+    j.C2 = C2;
+    j.lda = gemm_lda(k);  // operators are stored row-major, padded
     j.ldb = ldb;
     j.ldc = ldc;
     j.alpha = 1.0;
     j.beta = 0.0;
     j.flags = flags;
     j.scale = scale;
+    j.scale2 = scale2;
     j.es = es;
     h.push_back(j);
   }
   int n() const { return (int)h.size(); }
-  // Row-tile height before tuning: 16 (K split over the four waves) while
-  // 64-row tiles would leave most of the 256 CUs idle, 128 once 64-row tiles
-  // give more than eight workgroups per CU, 64 in between.
+  // Tile configuration before tuning: the largest tile that still gives
+  // every CU a workgroup.
   void prepare() {
-    kmax = 0;
-    for (auto& j : h) kmax = std::max(kmax, j.k);
-    const int t64 = gemm_prepare(h.data(), n(), 64);
-    set_bm(t64 < 2 * 256 ? 16 : (t64 > 8 * 256 ? 128 : 64));
+    int c = GEMM_NCFG - 1;
+    while (c > 0 && gemm_prepare(h.data(), n(), c) < 256) --c;
+    set_cfg(c);
   }
-  void set_bm(int b) {
-    bm = b;
-    tiles = gemm_prepare(h.data(), n(), bm);
+  void set_cfg(int c) {
+    cfg = c;
+    tiles = gemm_prepare(h.data(), n(), cfg);
   }
   // shape signature for the tuning cache
   std::vector<int> key() const {
@@ -91,17 +91,21 @@ struct JobList {
     }
     return k;
   }
-  void run(hipStream_t s) const { gemm_run(type, dev, tiles, n(), bm, kmax, s); }
+  void run(hipStream_t s) const { gemm_run(type, dev, tiles, n(), cfg, s); }
 };
 
-// Row-major (rows x cols) -> K-major copy used as the A operand of the products.
+// Row-major (rows x cols) operator -> the padded row-major copy (gemm_rows
+// rows of gemm_lda(cols), zero padding) used as the A operand of the products.
 template <typename T = double>
-std::vector<T> kmajor(const std::vector<double>& a, int rows, int cols) {
-  std::vector<T> t((size_t)rows * cols);
+std::vector<T> padded(const std::vector<double>& a, int rows, int cols) {
+  const int ld = gemm_lda(cols);
+  std::vector<T> t((size_t)gemm_rows(rows) * ld, T(0));
   for (int i = 0; i < rows; ++i)
-    for (int k = 0; k < cols; ++k) t[(size_t)k * rows + i] = (T)a[(size_t)i * cols + k];
+    for (int k = 0; k < cols; ++k) t[(size_t)i * ld + k] = (T)a[(size_t)i * cols + k];
   return t;
 }
+// elements of a padded operator with `rows` rows and `cols` columns
+size_t opsz(int rows, int cols) { return (size_t)gemm_rows(rows) * gemm_lda(cols); }
 
 bool valid_fft(int L) {
   FftPlan p;
@@ -127,7 +131,7 @@ struct pcs_sim {
   double *IMN, *DMN, *D, *D2, *PNM, *DP, *V, *Vinv, *DV, *wV, *lam, *d2i0, *d2in, *w, *ydy, *U1, *kx, *kz;
   double *twx, *twz, *twbx, *twbz;
   double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *DN, *Dc, *D2buf, *hgn, *hvn;
-  double *R, *X, *Zphi, *Zv, *ZDv, *flux, *CB, *prep, *zbuf;
+  double *R, *Xs, *Zphi, *Zv, *ZDv, *flux, *CB, *prep, *zbuf;
   EigScale* es;
   // mixed precision: FP32 operators, twiddles and padded-grid buffers, FP64
   // mean profiles on the padded grid, the FP64 mean column of the explicit
@@ -168,16 +172,16 @@ size_t carve(pcs_sim* m, char* base) {
   const Dims& d = m->d;
   const size_t n1 = d.N + 1, m1 = d.M + 1, ni = d.N - 1, cw = d.cw;
   Carve c(base);
-  m->IMN = c.take<double>(m1 * n1);
-  m->DMN = c.take<double>(m1 * n1);
-  m->D = c.take<double>(n1 * n1);
-  m->D2 = c.take<double>(n1 * n1);
-  m->PNM = c.take<double>(n1 * m1);
-  m->DP = c.take<double>(n1 * m1);
-  m->V = c.take<double>(ni * ni);
-  m->Vinv = c.take<double>(ni * ni);
-  m->DV = c.take<double>(n1 * ni);
-  m->wV = c.take<double>(ni);
+  m->IMN = c.take<double>(opsz(m1, n1));
+  m->DMN = c.take<double>(opsz(m1, n1));
+  m->D = c.take<double>(opsz(n1, n1));
+  m->D2 = c.take<double>(opsz(n1, n1));
+  m->PNM = c.take<double>(opsz(n1, m1));
+  m->DP = c.take<double>(opsz(n1, m1));
+  m->V = c.take<double>(opsz(ni, ni));
+  m->Vinv = c.take<double>(opsz(ni, ni));
+  m->DV = c.take<double>(opsz(n1, ni));
+  m->wV = c.take<double>(opsz(1, ni));
   m->lam = c.take<double>(ni);
   m->d2i0 = c.take<double>(ni);
   m->d2in = c.take<double>(ni);
@@ -202,10 +206,10 @@ size_t carve(pcs_sim* m, char* base) {
   m->Zin32 = (mixed && d.dim == 3) ? c.take<float>((size_t)m->nzin * zrow) : nullptr;
   m->Zout32 = (mixed && d.dim == 3) ? c.take<float>((size_t)m->nout * zrow) : nullptr;
   m->Yout32 = mixed ? c.take<float>((size_t)m->nout * m1 * cw) : nullptr;
-  m->IMN32 = mixed ? c.take<float>(m1 * n1) : nullptr;
-  m->DMN32 = mixed ? c.take<float>(m1 * n1) : nullptr;
-  m->PNM32 = mixed ? c.take<float>(n1 * m1) : nullptr;
-  m->DP32 = mixed ? c.take<float>(n1 * m1) : nullptr;
+  m->IMN32 = mixed ? c.take<float>(opsz(m1, n1)) : nullptr;
+  m->DMN32 = mixed ? c.take<float>(opsz(m1, n1)) : nullptr;
+  m->PNM32 = mixed ? c.take<float>(opsz(n1, m1)) : nullptr;
+  m->DP32 = mixed ? c.take<float>(opsz(n1, m1)) : nullptr;
   m->twx32 = mixed ? c.take<float>(2 * (size_t)d.px) : nullptr;
   m->twz32 = mixed ? c.take<float>(2 * (size_t)d.pz) : nullptr;
   m->Ybar = mixed ? c.take<double>(16 * m1) : nullptr;
@@ -218,7 +222,7 @@ size_t carve(pcs_sim* m, char* base) {
   m->hgn = c.take<double>(n1 * cw);
   m->hvn = c.take<double>(n1 * cw);
   m->R = c.take<double>((size_t)m->nsolve * ni * cw);
-  m->X = c.take<double>((size_t)m->nsolve * ni * cw);
+  m->Xs = c.take<double>((size_t)(m->nsolve + 1) * ni * cw);
   m->es = c.take<EigScale>(1);
   m->Zphi = c.take<double>(ni * cw);
   m->Zv = c.take<double>(ni * cw);
@@ -494,22 +498,26 @@ void build_jobs(pcs_sim* m) {
     m->Gm.type = GEMM_DDD;
     for (int f = 0; f < m->nout; ++f) m->Gm.add(m->PNM, m->mcol + (size_t)f * m1, 1, m->smean + f * n1, 1, n1, 1, m1);
   }
-  // G4: V^-1 R
-  for (int f = 0; f < m->nsolve; ++f) m->G4.add(m->Vinv, m->R + f * fsi, cw, m->X + f * fsi, cw, ni, cw, ni);
-  m->H4.add(m->Vinv, m->R, cw, m->X, cw, ni, cw, ni);
-  // G5: back from the eigenbasis, each B panel scaled by the inverse symbol
-  // of its Helmholtz operator while it is staged
+  // G4: V^-1 R, written scaled by the inverse Helmholtz symbols into
+  // Xs = [phi, v, (g), c...] (phi's coefficients give v's as a second output)
   const EigScale* es = m->es;
-  for (JobList* jl : {&m->G5, &m->H5}) {
-    jl->add(m->V, m->X, cw, m->Zphi, cw, ni, cw, ni, 0, SCALE_PHI, es);
-    jl->add(m->V, m->X, cw, m->Zv, cw, ni, cw, ni, 0, SCALE_V, es);
-    jl->add(m->DV, m->X, cw, m->ZDv, cw, n1, cw, ni, 0, SCALE_V, es);
-  }
-  if (d.dim == 3) m->G5.add(m->V, m->X + fsi, cw, st + 4 * fs + cw, cw, ni, cw, ni, 0, SCALE_PHI, es);
+  double* Xs = m->Xs;
+  for (JobList* jl : {&m->G4, &m->H4})
+    jl->add(m->Vinv, m->R, cw, Xs, cw, ni, cw, ni, 0, SCALE_PHI, es, Xs + fsi, SCALE_V);
+  if (d.dim == 3) m->G4.add(m->Vinv, m->R + fsi, cw, Xs + 2 * fsi, cw, ni, cw, ni, 0, SCALE_PHI, es);
+  const int xo = d.dim == 3 ? 3 : 2;
   for (int a = 0; a < d.nc; ++a)
-    m->G5.add(m->V, m->X + (m->nsv + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni, 0, SCALE_C, es);
+    m->G4.add(m->Vinv, m->R + (m->nsv + a) * fsi, cw, Xs + (xo + a) * fsi, cw, ni, cw, ni, 0, SCALE_C, es);
+  // G5: back from the eigenbasis
+  for (JobList* jl : {&m->G5, &m->H5}) {
+    jl->add(m->V, Xs, cw, m->Zphi, cw, ni, cw, ni);
+    jl->add(m->V, Xs + fsi, cw, m->Zv, cw, ni, cw, ni);
+    jl->add(m->DV, Xs + fsi, cw, m->ZDv, cw, n1, cw, ni);
+  }
+  if (d.dim == 3) m->G5.add(m->V, Xs + 2 * fsi, cw, st + 4 * fs + cw, cw, ni, cw, ni);
+  for (int a = 0; a < d.nc; ++a) m->G5.add(m->V, Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
   // w . U_p for the flux constraint: the mean column only
-  m->G5.add(m->wV, m->X, cw, m->flux, cw, 1, 2, ni, 0, SCALE_PHI, es);
+  m->G5.add(m->wV, Xs, cw, m->flux, cw, 1, 2, ni);
   for (JobList* jl : m->lists())
     if (jl->n()) jl->prepare();
 }
@@ -621,7 +629,7 @@ void report(hipError_t e, const char* what, int line) {
     }                                    \
   } while (0)
 
-// Tile autotuner: times each candidate row-tile height of a product table on
+// Tile autotuner: times each candidate tile configuration of a product table on
 // the device (results of the timing launches are discarded) and keeps the
 // fastest.  Choices are cached per table shape for the process lifetime.
 std::map<std::vector<int>, int>& tune_cache() {
@@ -644,11 +652,11 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
   hipStream_t s = m->s;
   // operators
   const int m1 = d.M + 1;
-  HIPCHK(up(m->IMN, kmajor(op->IMN, m1, n1), s));
-  HIPCHK(up(m->DMN, kmajor(op->DMN, m1, n1), s));
-  HIPCHK(up(m->D, kmajor(op->D, n1, n1), s));
-  HIPCHK(up(m->D2, kmajor(op->D2, n1, n1), s));
-  HIPCHK(up(m->PNM, kmajor(op->PNM, n1, m1), s));
+  HIPCHK(up(m->IMN, padded(op->IMN, m1, n1), s));
+  HIPCHK(up(m->DMN, padded(op->DMN, m1, n1), s));
+  HIPCHK(up(m->D, padded(op->D, n1, n1), s));
+  HIPCHK(up(m->D2, padded(op->D2, n1, n1), s));
+  HIPCHK(up(m->PNM, padded(op->PNM, n1, m1), s));
   // D P: derivative of a projected field straight from the padded grid
   std::vector<double> DP((size_t)n1 * m1);
   for (int i = 0; i < n1; ++i)
@@ -657,9 +665,9 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
       for (int j = 0; j < n1; ++j) acc += (long double)op->D[(size_t)i * n1 + j] * op->PNM[(size_t)j * m1 + k];
       DP[(size_t)i * m1 + k] = (double)acc;
     }
-  HIPCHK(up(m->DP, kmajor(DP, n1, m1), s));
-  HIPCHK(up(m->V, kmajor(op->V, ni, ni), s));
-  HIPCHK(up(m->Vinv, kmajor(op->Vinv, ni, ni), s));
+  HIPCHK(up(m->DP, padded(DP, n1, m1), s));
+  HIPCHK(up(m->V, padded(op->V, ni, ni), s));
+  HIPCHK(up(m->Vinv, padded(op->Vinv, ni, ni), s));
   HIPCHK(up(m->lam, op->lam, s));
   HIPCHK(up(m->d2i0, op->d2_i0, s));
   HIPCHK(up(m->d2in, op->d2_in, s));
@@ -677,8 +685,8 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
     for (int j = 1; j < d.N; ++j) acc += (long double)op->w[j] * op->V[(size_t)(j - 1) * ni + e];
     wV[e] = (double)acc;
   }
-  HIPCHK(up(m->DV, kmajor(DV, n1, ni), s));
-  HIPCHK(up(m->wV, wV, s));
+  HIPCHK(up(m->DV, padded(DV, n1, ni), s));
+  HIPCHK(up(m->wV, padded(wV, 1, ni), s));
   std::vector<double> ydy(n1);
   const double* y = op->y.data();
   for (int j = 1; j < d.N; ++j) ydy[j] = 0.5 * (y[j - 1] - y[j + 1]);
@@ -708,10 +716,10 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
   HIPCHK(up(m->twx, twiddles(d.px, -1), s));
   HIPCHK(up(m->twbx, twiddles(d.nx, -1), s));
   if (m->prec != 0) {
-    HIPCHK(up(m->IMN32, kmajor<float>(op->IMN, m1, n1), s));
-    HIPCHK(up(m->DMN32, kmajor<float>(op->DMN, m1, n1), s));
-    HIPCHK(up(m->PNM32, kmajor<float>(op->PNM, n1, m1), s));
-    HIPCHK(up(m->DP32, kmajor<float>(DP, n1, m1), s));
+    HIPCHK(up(m->IMN32, padded<float>(op->IMN, m1, n1), s));
+    HIPCHK(up(m->DMN32, padded<float>(op->DMN, m1, n1), s));
+    HIPCHK(up(m->PNM32, padded<float>(op->PNM, n1, m1), s));
+    HIPCHK(up(m->DP32, padded<float>(DP, n1, m1), s));
     auto tf = [](const std::vector<double>& v) { return std::vector<float>(v.begin(), v.end()); };
     HIPCHK(up(m->twx32, tf(twiddles(d.px, -1)), s));
     if (d.dim == 3) HIPCHK(up(m->twz32, tf(twiddles(d.pz, -1)), s));
@@ -773,8 +781,8 @@ pcs_status autotune(pcs_sim* m) {
       best = it->second;
     } else {
       float tbest = 1e30f;
-      for (int bm : {16, 64, 128}) {
-        jl->set_bm(bm);
+      for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
+        jl->set_cfg(cfg);
         HIPCHK(up(jl->dev, jl->h, s));
         jl->run(s);  // warm-up
         HIPCHK(hipEventRecord(e0, s));
@@ -785,12 +793,12 @@ pcs_status autotune(pcs_sim* m) {
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         if (ms < tbest) {
           tbest = ms;
-          best = bm;
+          best = cfg;
         }
       }
       tune_cache()[key] = best;
     }
-    jl->set_bm(best);
+    jl->set_cfg(best);
     HIPCHK(up(jl->dev, jl->h, s));
   }
   (void)hipEventDestroy(e0);
@@ -803,7 +811,6 @@ pcs_status homogeneous_solutions(pcs_sim* m) {
   hipStream_t s = m->s;
   const size_t fsi = (size_t)(d.N - 1) * d.cw;
   HIPCHK(hipMemsetAsync(m->R, 0, m->nsolve * fsi * sizeof(double), s));
-  HIPCHK(hipMemsetAsync(m->X, 0, m->nsolve * fsi * sizeof(double), s));
   launch_homog_rhs(d, m->p, m->d2i0, m->d2in, m->R, s);
   m->H4.run(s);
   m->H5.run(s);

@@ -364,6 +364,9 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const T* __restrict__ in, T
   const size_t fstride = (size_t)nrows * nkx * 2;
   const T* base = in + (size_t)row * nkx * 2;
   const int S = fft_batch<T>(L);
+  // twiddle table in LDS (behind the data), read by every radix pass
+  cx<T>* twl = P + (size_t)XS::NP * L;
+  for (int i = tid; i < L; i += NT) twl[i] = tw[i];
   const short* src = XSRC[DIM - 2];
   const short* dxf = XDX[DIM - 2];
   for (int b0 = 0; b0 < XS::NP; b0 += S) {
@@ -389,7 +392,7 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const T* __restrict__ in, T
       pack_pair(X + (size_t)q * L, L, k, A, B);
     }
     __syncthreads();
-    lds_fft(X, pl, nb, tw, +1);
+    lds_fft(X, pl, nb, twl, +1);
   }
   // pointwise products; outputs overwrite the first pairs at the same point
   T mrow[16];
@@ -420,7 +423,7 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const T* __restrict__ in, T
   for (int q0 = 0; q0 < XS::NOP; q0 += S) {
     const int nb = min(S, XS::NOP - q0);
     cx<T>* Z = P + (size_t)q0 * L;
-    lds_fft(Z, pl, nb, tw, -1);
+    lds_fft(Z, pl, nb, twl, -1);
     for (int e = tid; e < nb * nkx; e += NT) {
       const int q = e / nkx, k = e - q * nkx;
       cx<T> A, B;
@@ -447,7 +450,7 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const T* __restrict__ in, T
 
 template <typename T, int DIM>
 size_t xpencil_lds(int L) {
-  return (size_t)XShape<DIM>::NP * L * sizeof(cx<T>);
+  return (size_t)(XShape<DIM>::NP + 1) * L * sizeof(cx<T>);
 }
 
 // ---------------------------------------------------------------- z columns
@@ -467,6 +470,8 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const T* __restrict__ in, T* _
   extern __shared__ double smem_z[];
   c2* A = reinterpret_cast<c2*>(smem_z);
   const int L = pl.L;
+  c2* twl = A + (size_t)ZG * L;  // twiddle table behind the data
+  for (int e = threadIdx.x; e < L; e += NT) twl[e] = tw[e];
   const int k0 = blockIdx.x * ZG, i = blockIdx.y, f = blockIdx.z;
   const int ng = min(ZG, nkx - k0);
   const int tid = threadIdx.x;
@@ -496,7 +501,7 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const T* __restrict__ in, T* _
     }
   }
   __syncthreads();
-  lds_fft(A, pl, ng, tw, inverse ? +1 : -1);
+  lds_fft(A, pl, ng, twl, inverse ? +1 : -1);
   if (inverse) {
     for (int e = tid; e < L * ng; e += NT) {
       const int z = e / ng, g = e - z * ng;
@@ -558,6 +563,8 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(Dims d, const double* __r
   c2* A = reinterpret_cast<c2*>(smem_g);
   __shared__ DiagPart wpart[NT / 64];
   const int L = pl.L, nkx = d.nkx;
+  c2* twl = A + 2 * (size_t)L;  // twiddle table behind the data
+  for (int e = threadIdx.x; e < L; e += NT) twl[e] = tw[e];
   const int row = blockIdx.x, tid = threadIdx.x;
   const int nrows = (d.N + 1) * zrows;
   const int j = row / zrows;
@@ -575,7 +582,7 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(Dims d, const double* __r
     pack_pair(A + (size_t)q * L, L, k, Av, Bv);
   }
   __syncthreads();
-  lds_fft(A, pl, 2, tw, +1);
+  lds_fft(A, pl, 2, twl, +1);
   const double dx = d.lx / d.nx, dz = d.dim == 3 ? d.lz / d.nz : 1.0;
   const double dyj = ydy[j];
   double mn = 1.0 / 0.0, cf = 0, es = 0, ts = 0;
@@ -748,11 +755,11 @@ void launch_zfft(const Dims& d, const FftPlan& plan, const void* in, void* out, 
                  const double* mean, double* mcol, hipStream_t s) {
   dim3 grid((d.nkx + ZG - 1) / ZG, rows, nfields);
   if (precision == 0) {
-    const size_t lds = (size_t)ZG * plan.L * sizeof(cx<double>);
+    const size_t lds = (size_t)(ZG + 1) * plan.L * sizeof(cx<double>);
     hipLaunchKernelGGL(zfft_kernel<double>, grid, dim3(NT), lds, s, (const double*)in, (double*)out, d.nkx, d.nzs, rows,
                        plan, src_field, deriv, kz, (const cx<double>*)tw, inverse, nullptr, nullptr);
   } else {
-    const size_t lds = (size_t)ZG * plan.L * sizeof(cx<float>);
+    const size_t lds = (size_t)(ZG + 1) * plan.L * sizeof(cx<float>);
     hipLaunchKernelGGL(zfft_kernel<float>, grid, dim3(NT), lds, s, (const float*)in, (float*)out, d.nkx, d.nzs, rows,
                        plan, src_field, deriv, kz, (const cx<float>*)tw, inverse, mean, inverse ? nullptr : mcol);
   }
@@ -768,7 +775,7 @@ void launch_diag_rows(const Dims& d, const FftPlan& planx, const double* prep, d
     src = zbuf;
     zrows = d.nz;
   }
-  const size_t lds = 2 * (size_t)planx.L * sizeof(c2);
+  const size_t lds = 3 * (size_t)planx.L * sizeof(c2);
   hipLaunchKernelGGL(diag_rows_kernel, dim3(n1 * zrows), dim3(NT), lds, s, d, src, zrows, planx,
                      reinterpret_cast<const c2*>(twx), ydy, parts);
 }

@@ -3,34 +3,59 @@
 // The wall-normal transforms (interpolation / differentiation to the padded
 // grid, projection back), the spectral derivatives and the diagonalised
 // Dirichlet solves are products C = alpha A B + beta C of a small operator A
-// (at most 385 x 385, stored K-major so that an MFMA operand fragment is one
-// 128-byte read) with a wide matrix B whose columns are the real and
-// imaginary parts of every Fourier mode.
+// (a few hundred rows and columns, row-major, padded) with a wide matrix B
+// whose columns are the real and imaginary parts of every Fourier mode.  Many
+// products of one step share an operator, so one launch evaluates a whole
+// table of them.  Two kernel families cover the range of table sizes; the
+// host times both on the real tables once and keeps the faster tile shape.
 //
-// One launch evaluates a table of such products.  A workgroup (four waves)
-// owns a BM x 32 output tile: it stages the whole K x 32 panel of B in LDS
-// (converted to the compute precision) with unrolled loads, then accumulates
-// with 16x16x4 MFMAs (f64 or f32), reading A fragments straight from the
-// L2-resident operator through a prefetch ring.  BM is chosen per table by
-// the host: 16 (the four waves split K) for products too small to fill the
-// chip, 64, or 128 for wide products (fewer re-reads of B).
+// Register-direct kernel (small tables, where a product is short and its
+// cost is mostly memory latency): each wave computes a 32 x 32 block with
+// 16x16x4 MFMAs (f64 or f32) from operand fragments loaded from global memory
+// straight into a three-slot register ring, two 16-wide k blocks ahead of the
+// multiply, with no LDS traffic or barriers in the loop.  Within an MFMA
+// k-step, lane group g (lanes 16g..16g+15) takes k = 16 b + 4 g + s for step
+// s of block b, so the A fragments of a lane are four consecutive elements of
+// an operator row (one vector load).  The four waves tile the output
+// (TM x TN blocks) and split K (KS ways, k blocks dealt round-robin); the
+// partial sums are added through LDS in a fixed order.
+//
+// LDS-tiled kernel (large tables, where operand reuse matters): the four
+// waves (2 x 2) share a BM x BN tile; K is walked in chunks of KC whose A and
+// B panels are read into registers as element pairs while the previous chunk
+// is multiplied out of LDS, then written to the other LDS buffer (B converted
+// to the compute precision and optionally zeroed in the mean columns).  LDS
+// rows are padded so that the fragment reads of one MFMA hit distinct banks.
+//
+// Both deal workgroups to the eight XCDs in contiguous ranges of tiles, so
+// the row tiles of one column panel share an L2, and both share the
+// epilogue, which can scale each output element by the inverse Helmholtz
+// symbol of its eigen index (row) and Fourier mode (column) and write a
+// second, differently scaled copy.  All sums run in a fixed order, so results
+// are bitwise reproducible.
 #include "kernels.hpp"
 
 namespace pcs {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
 typedef float flt4 __attribute__((ext_vector_type(4)));
+typedef double dbl2 __attribute__((ext_vector_type(2)));
+typedef float flt2 __attribute__((ext_vector_type(2)));
 
-int gemm_prepare(GemmJob* jobs, int njobs, int bm) {
-  int t = 0;
-  for (int j = 0; j < njobs; ++j) {
-    jobs[j].tiles_m = (jobs[j].m + bm - 1) / bm;
-    const int tn = (jobs[j].n + GEMM_BN - 1) / GEMM_BN;
-    jobs[j].tile0 = t;
-    t += jobs[j].tiles_m * tn;
-  }
-  return t;
-}
+namespace {
+
+template <typename T>
+struct Vec;
+template <>
+struct Vec<double> {
+  typedef dbl4 v4;
+  typedef dbl2 v2;
+};
+template <>
+struct Vec<float> {
+  typedef flt4 v4;
+  typedef flt2 v2;
+};
 
 __device__ inline dbl4 mfma(double a, double b, dbl4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
@@ -39,271 +64,380 @@ __device__ inline flt4 mfma(float a, float b, flt4 c) {
   return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
 }
 
-template <typename T>
-struct Vec4;
+// Register-direct configurations: TM x TN wave blocks of 32 x 32, K split KS.
+template <int CFG>
+struct RCfg;
 template <>
-struct Vec4<double> {
-  typedef dbl4 type;
+struct RCfg<0> {
+  static constexpr int TM = 1, TN = 1, KS = 4;
 };
 template <>
-struct Vec4<float> {
-  typedef flt4 type;
+struct RCfg<1> {
+  static constexpr int TM = 2, TN = 1, KS = 2;
 };
-
-constexpr int LDB = GEMM_BN + 8;  // padded LDS row of the B panel: the four k rows of one read start 16 banks apart
-
-// Tile shapes.  RB: 16-row blocks per wave.  KS = 1: the four waves stack
-// their rows (BM = 64 RB); KS = 4: the four waves share BM = 16 RB rows and
-// each takes a quarter of K, the partial sums being added through LDS (for
-// small products, where otherwise too few workgroups exist).
-template <int RB, int KS>
-struct Shape {
-  static constexpr int BM = (KS == 1 ? 4 : 1) * RB * 16;
+template <>
+struct RCfg<2> {
+  static constexpr int TM = 1, TN = 2, KS = 2;
 };
+template <>
+struct RCfg<3> {
+  static constexpr int TM = 2, TN = 2, KS = 1;
+};
+// LDS-tiled configurations: BM x BN tile, K chunk KC.
+template <int CFG>
+struct LCfg;
+template <>
+struct LCfg<4> {
+  static constexpr int BM = 32, BN = 32, KC = 32;
+};
+template <>
+struct LCfg<5> {
+  static constexpr int BM = 64, BN = 32, KC = 32;
+};
+template <>
+struct LCfg<6> {
+  static constexpr int BM = 64, BN = 64, KC = 16;
+};
+template <>
+struct LCfg<7> {
+  static constexpr int BM = 128, BN = 64, KC = 16;
+};
+constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128};
+constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64};
 
-template <typename T, int RB>
-__device__ inline void load_a(T (&a)[4][RB], const T* A, int lda, int K, const int (&arow)[RB],
-                              const bool (&aok)[RB], int k0, int lk) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int k = k0 + 4 * u + lk;
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) a[u][rb] = (k < K && aok[rb]) ? A[(size_t)k * lda + arow[rb]] : T(0);
-  }
+// Workgroup b runs on XCD b % 8; logical tiles are dealt so that XCD x gets
+// one contiguous range (a bijection for any tile count).
+__device__ inline int xcd_tile(int b, int total) {
+  const int q = total >> 3, r = total & 7;
+  const int x = b & 7, i = b >> 3;
+  return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-template <typename T, typename V4, int RB>
-__device__ inline void mma_block(V4 (&acc)[RB][2], const T (&a)[4][RB], const T* Bs, int k0, int kend, int lk,
-                                 int l16) {
-#pragma unroll
-  for (int u = 0; u < 4; ++u) {
-    const int kk = k0 + 4 * u;
-    if (kk < kend) {
-      const T b0 = Bs[(kk + lk) * LDB + l16], b1 = Bs[(kk + lk) * LDB + 16 + l16];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        acc[rb][0] = mfma(a[u][rb], b0, acc[rb][0]);
-        acc[rb][1] = mfma(a[u][rb], b1, acc[rb][1]);
-      }
-    }
-  }
-}
-
-template <typename T, typename TB, typename TC, int RB, int KS>
-__global__ __launch_bounds__(256) void gemm_kernel(const GemmJob* __restrict__ jobs, int njobs) {
-  typedef typename Vec4<T>::type V4;
-  extern __shared__ double gsm[];
-  T* Bs = reinterpret_cast<T*>(gsm);  // [K4][LDB], K rounded up to a multiple of 4
-  constexpr int BM = Shape<RB, KS>::BM;
-  const int t = blockIdx.x;
+__device__ inline int find_job(const GemmJob* __restrict__ jobs, int njobs, int t) {
   int jb = 0;
   while (jb + 1 < njobs && jobs[jb + 1].tile0 <= t) ++jb;
-  const GemmJob J = jobs[jb];
-  const T* A = static_cast<const T*>(J.A);
-  const TB* B = static_cast<const TB*>(J.B);
-  TC* C = static_cast<TC*>(J.C);
-  const int lt = t - J.tile0;
-  const int row0 = (lt % J.tiles_m) * BM;
-  const int col0 = (lt / J.tiles_m) * GEMM_BN;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int K4 = (J.k + 3) & ~3;
-  // stage the K x 32 panel of B (zero outside the matrix, and in the mean
-  // columns when asked): 16 loads in flight per thread before any LDS store
-  {
-    constexpr int UNR = 16, RPP = 256 / GEMM_BN;  // rows per pass of the workgroup
-    const int c = tid % GEMM_BN, rr = tid / GEMM_BN;
-    const int gc = col0 + c;
-    const bool cok = gc < J.n && !((J.flags & GEMM_ZERO_MEAN) && gc < 2);
-    if (J.scale == SCALE_NONE) {
-      for (int r0 = 0; r0 < K4; r0 += UNR * RPP) {
-        T v[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int r = r0 + u * RPP + rr;
-          v[u] = (r < J.k && cok) ? T(B[(size_t)r * J.ldb + gc]) : T(0);
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int r = r0 + u * RPP + rr;
-          if (r < K4) Bs[r * LDB + c] = v[u];
-        }
-      }
-    } else {
-      // B row r is eigen coefficient r of column gc's mode: scale by the
-      // inverse of that mode's Helmholtz symbol (see EigScale)
-      const EigScale es = *J.es;
-      const int mode = cok ? gc >> 1 : 0, iz = mode / es.nkx, ix = mode - iz * es.nkx;
-      const double kxv = es.kx[ix], kzv = (es.dim == 3) ? es.kz[iz] : 0.0;
-      const double k2 = kxv * kxv + kzv * kzv;
-      double a0, a1;  // symbol = a0 - a1 * lam
-      if (J.scale == SCALE_C) {
-        a0 = 1.0 / es.dt + 0.5 / es.wi + 0.5 * es.kappa * k2;
-        a1 = 0.5 * es.kappa;
-      } else {
-        a0 = 1.0 / es.dt + 0.5 * es.nu * k2;
-        a1 = 0.5 * es.nu;
-      }
-      const bool vz = (J.scale == SCALE_V) && mode == 0;
-      for (int r0 = 0; r0 < K4; r0 += UNR * RPP) {
-        double v[UNR];
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int r = r0 + u * RPP + rr;
-          v[u] = (r < J.k && cok && !vz) ? double(B[(size_t)r * J.ldb + gc]) : 0.0;
-        }
-#pragma unroll
-        for (int u = 0; u < UNR; ++u) {
-          const int r = r0 + u * RPP + rr;
-          if (r < K4) {
-            double f = 0.0;
-            if (r < J.k) {
-              const double lam = es.lam[r];
-              f = 1.0 / (a0 - a1 * lam);
-              if (J.scale == SCALE_V) f = f / (lam - k2);
-            }
-            Bs[r * LDB + c] = T(v[u] * f);
-          }
-        }
-      }
-    }
-  }
-  __syncthreads();
-  const int l16 = lane & 15, lk = lane >> 4;
-  const int wrow = row0 + (KS == 1 ? wave * RB * 16 : 0);
-  int kbeg = 0, kend = K4;
-  if (KS > 1) {
-    const int kq = ((K4 / 4 + KS - 1) / KS) * 4;
-    kbeg = min(wave * kq, K4);
-    kend = min(kbeg + kq, K4);
-  }
-  int arow[RB];
-  bool aok[RB];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) {
-    arow[rb] = wrow + rb * 16 + l16;
-    aok[rb] = arow[rb] < J.m;
-  }
-  V4 acc[RB][2];
-#pragma unroll
-  for (int rb = 0; rb < RB; ++rb) acc[rb][0] = acc[rb][1] = V4{0, 0, 0, 0};
-  // A fragments come straight from the L2-resident operator through a ring of
-  // four 16-deep register blocks: block b + 3 is requested while block b is
-  // multiplied
-  T a0[4][RB], a1[4][RB], a2[4][RB], a3[4][RB];
-  const int nblk = (kend - kbeg + 15) / 16;
-  auto kb = [&](int b) { return kbeg + 16 * b; };
-  if (nblk > 0) load_a(a0, A, J.lda, J.k, arow, aok, kb(0), lk);
-  if (nblk > 1) load_a(a1, A, J.lda, J.k, arow, aok, kb(1), lk);
-  if (nblk > 2) load_a(a2, A, J.lda, J.k, arow, aok, kb(2), lk);
-  for (int b = 0; b < nblk; b += 4) {
-    if (b + 3 < nblk) load_a(a3, A, J.lda, J.k, arow, aok, kb(b + 3), lk);
-    mma_block<T, V4, RB>(acc, a0, Bs, kb(b), kend, lk, l16);
-    if (b + 1 >= nblk) break;
-    if (b + 4 < nblk) load_a(a0, A, J.lda, J.k, arow, aok, kb(b + 4), lk);
-    mma_block<T, V4, RB>(acc, a1, Bs, kb(b + 1), kend, lk, l16);
-    if (b + 2 >= nblk) break;
-    if (b + 5 < nblk) load_a(a1, A, J.lda, J.k, arow, aok, kb(b + 5), lk);
-    mma_block<T, V4, RB>(acc, a2, Bs, kb(b + 2), kend, lk, l16);
-    if (b + 3 >= nblk) break;
-    if (b + 6 < nblk) load_a(a2, A, J.lda, J.k, arow, aok, kb(b + 6), lk);
-    mma_block<T, V4, RB>(acc, a3, Bs, kb(b + 3), kend, lk, l16);
-  }
-  if (KS > 1) {
-    // add the K-quarters: waves 1..3 park their partial tiles in LDS
-    __syncthreads();
-    T* red = Bs;
-    if (wave > 0) {
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) red[(((wave - 1) * RB + rb) * 8 + bj * 4 + r) * 64 + lane] = acc[rb][bj][r];
-    }
-    __syncthreads();
-    if (wave != 0) return;
-#pragma unroll
-    for (int w2 = 1; w2 < KS; ++w2)
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[rb][bj][r] += red[(((w2 - 1) * RB + rb) * 8 + bj * 4 + r) * 64 + lane];
-  }
-  // Element D[i][j] of a 16x16 block lives in lane j + 16 * (i / 4), register
-  // i % 4 for the f32 instruction, and in lane j + 16 * (i % 4), register
-  // i / 4 for the f64 one (checked on gfx950 with a one-hot product).
+  return jb;
+}
+
+// Inverse Helmholtz symbol of kind `kind` for eigenvalue lam and wavenumber
+// magnitude k2 (mode 0 is the mean slot).
+__device__ inline double eig_factor(const EigScale& es, int kind, double lam, double k2, bool mean) {
+  if (kind == SCALE_C) return 1.0 / (1.0 / es.dt + 0.5 / es.wi + 0.5 * es.kappa * (k2 - lam));
+  const double f = 1.0 / (1.0 / es.dt + 0.5 * es.nu * (k2 - lam));
+  if (kind == SCALE_V) return mean ? 0.0 : f / (lam - k2);
+  return f;
+}
+
+// Stores a lane's RB x CB accumulator blocks whose top-left corner is
+// (r0, c0).  Element D[i][j] of a 16x16 block lives in lane j + 16 * (i / 4),
+// register i % 4 for the f32 instruction, and in lane j + 16 * (i % 4),
+// register i / 4 for the f64 one (checked on gfx950 with a one-hot product).
+// The eigenvalues and wavenumbers the scaling needs are read before the
+// first store.
+template <typename T, typename TC, int RB, int CB, typename V4>
+__device__ inline void store_tile(const GemmJob* __restrict__ jp, const V4 (&acc)[RB][CB], int r0, int c0, int lk,
+                                  int l16) {
   constexpr bool f64 = sizeof(T) == 8;
+  const GemmJob J = *jp;
+  TC* __restrict__ C = static_cast<TC*>(J.C);
+  TC* __restrict__ C2 = static_cast<TC*>(J.C2);
+  auto row_of = [&](int rb, int r) { return r0 + rb * 16 + (f64 ? 4 * r + lk : 4 * lk + r); };
+  auto col_of = [&](int cb) { return c0 + cb * 16 + l16; };
+  const bool scaled = J.scale != SCALE_NONE;
+  EigScale es{};
+  double lam[RB][4], k2[CB];
+  bool mean[CB];
+  if (scaled) {
+    es = *J.es;
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) {
+      const int gc = col_of(cb);
+      const int mode = gc < J.n ? gc >> 1 : 0, iz = mode / es.nkx, ix = mode - iz * es.nkx;
+      const double kxv = es.kx[ix], kzv = (es.dim == 3) ? es.kz[iz] : 0.0;
+      k2[cb] = kxv * kxv + kzv * kzv;
+      mean[cb] = mode == 0;
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gr = row_of(rb, r);
+        lam[rb][r] = es.lam[gr < J.m ? gr : 0];
+      }
+  }
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int cb = 0; cb < CB; ++cb)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int gr = wrow + rb * 16 + (f64 ? 4 * r + lk : 4 * lk + r);
-        const int gc = col0 + bj * 16 + l16;
+        const int gr = row_of(rb, r), gc = col_of(cb);
         if (gr < J.m && gc < J.n) {
+          const double v = J.alpha * (double)acc[rb][cb][r];
           TC* cp = C + (size_t)gr * J.ldc + gc;
-          double v = J.alpha * (double)acc[rb][bj][r];
-          if (J.beta != 0.0) v += J.beta * (double)*cp;
-          *cp = TC(v);
+          double o = scaled ? v * eig_factor(es, J.scale, lam[rb][r], k2[cb], mean[cb]) : v;
+          if (J.beta != 0.0) o += J.beta * (double)*cp;
+          *cp = TC(o);
+          if (C2)
+            C2[(size_t)gr * J.ldc + gc] =
+                TC(J.scale2 != SCALE_NONE ? v * eig_factor(es, J.scale2, lam[rb][r], k2[cb], mean[cb]) : v);
         }
       }
 }
 
-size_t gemm_lds_bytes(int kmax, int elem) {
-  const size_t panel = (size_t)((kmax + 3) & ~3) * LDB * elem;
-  const size_t red = (size_t)3 * 2 * 8 * 64 * elem;  // KS = 4 partial tiles (RB <= 2)
-  return panel > red ? panel : red;
+}  // namespace
+
+int gemm_prepare(GemmJob* jobs, int njobs, int cfg) {
+  const int bm = CFG_BM[cfg], bn = CFG_BN[cfg];
+  int t = 0;
+  for (int j = 0; j < njobs; ++j) {
+    jobs[j].tiles_m = (jobs[j].m + bm - 1) / bm;
+    const int tn = (jobs[j].n + bn - 1) / bn;
+    jobs[j].tile0 = t;
+    t += jobs[j].tiles_m * tn;
+  }
+  return t;
+}
+
+// ------------------------------------------------------------ register-direct kernel
+template <typename T, typename TB, typename TC, int CFG>
+__global__ __launch_bounds__(256) void gemm_reg_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+  constexpr int TM = RCfg<CFG>::TM, TN = RCfg<CFG>::TN, KS = RCfg<CFG>::KS;
+  constexpr int BM = 32 * TM, BN = 32 * TN;
+  typedef typename Vec<T>::v4 V4;
+  __shared__ T red[KS > 1 ? 4 * 16 * 64 : 1];
+
+  const int t = xcd_tile(blockIdx.x, total);
+  const GemmJob* jp = jobs + find_job(jobs, njobs, t);
+  const int lt = t - jp->tile0, tiles_m = jp->tiles_m;
+  const int row0 = (lt % tiles_m) * BM, col0 = (lt / tiles_m) * BN;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int ks = wave % KS, tm = (wave / KS) % TM, tn = wave / (KS * TM);
+  const int wrow = row0 + 32 * tm, wcol = col0 + 32 * tn;
+  const int M = jp->m, N = jp->n, K = jp->k;
+
+  V4 acc[2][2];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+
+  if (wrow < M && wcol < N) {
+    const T* A = static_cast<const T*>(jp->A);
+    const TB* B = static_cast<const TB*>(jp->B);
+    const int lda = jp->lda, ldb = jp->ldb;
+    const T* ar0 = A + (size_t)(wrow + l16) * lda + 4 * lk;
+    const T* ar1 = ar0 + (size_t)16 * lda;
+    const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
+    const int bc0 = wcol + l16, bc1 = bc0 + 16;
+    const bool bok0 = bc0 < N && !(zm && bc0 < 2), bok1 = bc1 < N && !(zm && bc1 < 2);
+    const int nkb = (K + 15) >> 4;
+    const int nb = ks < nkb ? (nkb - ks + KS - 1) / KS : 0;
+    V4 a0[2], a1[2], a2[2];
+    T b0[2][4], b1[2][4], b2[2][4];
+    auto load = [&](V4 (&a)[2], T (&b)[2][4], int i) {
+      const int kb = 16 * (ks + KS * i);
+      a[0] = *reinterpret_cast<const V4*>(ar0 + kb);
+      a[1] = *reinterpret_cast<const V4*>(ar1 + kb);
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = kb + 4 * lk + s;
+        const TB* br = B + (size_t)kk * ldb;
+        b[0][s] = (kk < K && bok0) ? T(br[bc0]) : T(0);
+        b[1][s] = (kk < K && bok1) ? T(br[bc1]) : T(0);
+      }
+    };
+    auto mul = [&](const V4 (&a)[2], const T (&b)[2][4]) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = mfma(a[rb][s], b[cb][s], acc[rb][cb]);
+    };
+    if (nb > 0) load(a0, b0, 0);
+    if (nb > 1) load(a1, b1, 1);
+    for (int i = 0; i < nb; i += 3) {
+      if (i + 2 < nb) load(a2, b2, i + 2);
+      mul(a0, b0);
+      if (i + 1 >= nb) break;
+      if (i + 3 < nb) load(a0, b0, i + 3);
+      mul(a1, b1);
+      if (i + 2 >= nb) break;
+      if (i + 4 < nb) load(a1, b1, i + 4);
+      mul(a2, b2);
+    }
+  }
+
+  if constexpr (KS > 1) {
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) red[((wave * 4 + rb * 2 + cb) * 4 + r) * 64 + lane] = acc[rb][cb][r];
+    __syncthreads();
+    if (ks != 0) return;
+#pragma unroll
+    for (int w2 = 1; w2 < KS; ++w2)
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[rb][cb][r] += red[(((wave + w2) * 4 + rb * 2 + cb) * 4 + r) * 64 + lane];
+  }
+  if (wrow >= M || wcol >= N) return;
+  store_tile<T, TC, 2, 2>(jp, acc, wrow, wcol, lk, l16);
+}
+
+// ------------------------------------------------------------ LDS-tiled kernel
+template <typename T, typename TB, typename TC, int CFG>
+__global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC;
+  constexpr int WM = BM / 2, WN = BN / 2, RB = WM / 16, CB = WN / 16;
+  // A panel row-major [BM][PA] (pitch KC + 2 keeps the 16 rows of a fragment
+  // read on distinct banks), B panel [KC][PB]
+  constexpr int PA = KC + 2, PB = BN + 16;
+  constexpr int NA = KC * BM / 512, NB = KC * BN / 512;  // element pairs per thread and chunk
+  constexpr int RA = 512 / KC, SB = 512 / BN;            // row step between a thread's pairs
+  static_assert(NA >= 1 && NB >= 1 && KC % 4 == 0, "tile shape");
+  typedef typename Vec<T>::v4 V4;
+  typedef typename Vec<T>::v2 AP;
+  typedef typename Vec<TB>::v2 BP;
+  __shared__ __attribute__((aligned(16))) T As[2][BM * PA];
+  __shared__ __attribute__((aligned(16))) T Bs[2][KC * PB];
+
+  const int t = xcd_tile(blockIdx.x, total);
+  const GemmJob* jp = jobs + find_job(jobs, njobs, t);
+  const int lt = t - jp->tile0, tiles_m = jp->tiles_m;
+  const int row0 = (lt % tiles_m) * BM, col0 = (lt / tiles_m) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
+  const int M = jp->m, N = jp->n, K = jp->k, lda = jp->lda, ldb = jp->ldb;
+  const T* A = static_cast<const T*>(jp->A);
+  const TB* B = static_cast<const TB*>(jp->B);
+
+  // staging positions: a thread's A pairs are (row ra + u RA, k pair 2 kp);
+  // its B pairs share one column pair and step through k
+  const int kp = 2 * (tid % (KC / 2)), ra = tid / (KC / 2);
+  const int cb2 = 2 * (tid % (BN / 2)), kb = tid / (BN / 2);
+  const int gc = col0 + cb2;
+  const bool bpair = (((ldb | N) & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & (2 * sizeof(TB) - 1)) == 0);
+  const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
+  const bool c0ok = gc < N && !(zm && gc < 2), c1ok = gc + 1 < N && !(zm && gc + 1 < 2);
+
+  AP ar[NA];
+  TB br[NB][2];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      // rows up to gemm_rows(m) are allocated and zero; k pairs stop at K
+      const int kk = k0 + kp;
+      ar[u] = kk < K ? *reinterpret_cast<const AP*>(A + (size_t)(row0 + ra + u * RA) * lda + kk) : AP{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int kk = k0 + kb + u * SB;
+      const TB* bp = B + (size_t)kk * ldb + gc;
+      if (bpair) {
+        if (kk < K && gc < N) {
+          const BP v = *reinterpret_cast<const BP*>(bp);
+          br[u][0] = v[0];
+          br[u][1] = v[1];
+        } else {
+          br[u][0] = br[u][1] = TB(0);
+        }
+      } else {
+        br[u][0] = (kk < K && gc < N) ? bp[0] : TB(0);
+        br[u][1] = (kk < K && gc + 1 < N) ? bp[1] : TB(0);
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) *reinterpret_cast<AP*>(&As[buf][(ra + u * RA) * PA + kp]) = ar[u];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      AP v;
+      v[0] = c0ok ? T(br[u][0]) : T(0);
+      v[1] = c1ok ? T(br[u][1]) : T(0);
+      *reinterpret_cast<AP*>(&Bs[buf][(kb + u * SB) * PB + cb2]) = v;
+    }
+  };
+
+  V4 acc[RB][CB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+  const bool active = (row0 + wr < M) && (col0 + wc < N);
+  const int nch = (K + KC - 1) / KC;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int c = 0; c < nch; ++c) {
+    const int buf = c & 1;
+    if (c + 1 < nch) load((c + 1) * KC);
+    if (active) {
+      const T* as = &As[buf][(wr + l16) * PA + lk];
+      const T* bs = &Bs[buf][lk * PB + wc + l16];
+#pragma unroll
+      for (int kq = 0; kq < KC / 4; ++kq) {
+        T a[RB], b[CB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) a[rb] = as[rb * 16 * PA + 4 * kq];
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) b[cb] = bs[4 * kq * PB + cb * 16];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(a[rb], b[cb], acc[rb][cb]);
+      }
+    }
+    if (c + 1 < nch) store(buf ^ 1);
+    __syncthreads();
+  }
+  if (!active) return;
+  store_tile<T, TC, RB, CB>(jp, acc, row0 + wr, col0 + wc, lk, l16);
 }
 
 namespace {
 
 template <typename T, typename TB, typename TC>
-hipError_t set_attr3() {
-  const int lim = 160 * 1024;
-  hipError_t e =
-      hipFuncSetAttribute((const void*)gemm_kernel<T, TB, TC, 1, 4>, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)gemm_kernel<T, TB, TC, 1, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lim);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void*)gemm_kernel<T, TB, TC, 2, 1>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            lim);
-  return e;
-}
-
-template <typename T, typename TB, typename TC>
-void launch3(const GemmJob* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
-  const size_t lds = gemm_lds_bytes(kmax, sizeof(T));
-  if (bm == 16)
-    hipLaunchKernelGGL((gemm_kernel<T, TB, TC, 1, 4>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
-  else if (bm == 128)
-    hipLaunchKernelGGL((gemm_kernel<T, TB, TC, 2, 1>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
-  else
-    hipLaunchKernelGGL((gemm_kernel<T, TB, TC, 1, 1>), dim3(total_tiles), dim3(256), lds, s, dev_jobs, njobs);
+void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStream_t s) {
+#define PCS_GEMM_LAUNCH(KERNEL, C)                                                                    \
+  case C:                                                                                             \
+    hipLaunchKernelGGL((KERNEL<T, TB, TC, C>), dim3(total), dim3(256), 0, s, dev_jobs, njobs, total); \
+    break;
+  switch (cfg) {
+    PCS_GEMM_LAUNCH(gemm_reg_kernel, 0)
+    PCS_GEMM_LAUNCH(gemm_reg_kernel, 1)
+    PCS_GEMM_LAUNCH(gemm_reg_kernel, 2)
+    PCS_GEMM_LAUNCH(gemm_reg_kernel, 3)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 4)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 5)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 6)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 7)
+    default: break;
+  }
+#undef PCS_GEMM_LAUNCH
 }
 
 }  // namespace
 
-hipError_t gemm_set_attributes() {
-  hipError_t e = set_attr3<double, double, double>();
-  if (e == hipSuccess) e = set_attr3<float, double, float>();
-  if (e == hipSuccess) e = set_attr3<float, float, double>();
-  if (e == hipSuccess) e = set_attr3<double, double, float>();
-  if (e == hipSuccess) e = set_attr3<double, float, double>();
-  return e;
-}
+hipError_t gemm_set_attributes() { return hipSuccess; }
 
-void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s) {
-  if (total_tiles <= 0 || njobs <= 0) return;
+void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s) {
+  if (total_tiles <= 0 || njobs <= 0 || cfg < 0 || cfg >= GEMM_NCFG) return;
   switch (t) {
-    case GEMM_DDD: launch3<double, double, double>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
-    case GEMM_FDF: launch3<float, double, float>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
-    case GEMM_FFD: launch3<float, float, double>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
-    case GEMM_DDF: launch3<double, double, float>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
-    case GEMM_DFD: launch3<double, float, double>(dev_jobs, total_tiles, njobs, bm, kmax, s); break;
+    case GEMM_DDD: launch_cfg<double, double, double>(dev_jobs, total_tiles, njobs, cfg, s); break;
+    case GEMM_FDF: launch_cfg<float, double, float>(dev_jobs, total_tiles, njobs, cfg, s); break;
+    case GEMM_FFD: launch_cfg<float, float, double>(dev_jobs, total_tiles, njobs, cfg, s); break;
+    case GEMM_DDF: launch_cfg<double, double, float>(dev_jobs, total_tiles, njobs, cfg, s); break;
+    case GEMM_DFD: launch_cfg<double, float, double>(dev_jobs, total_tiles, njobs, cfg, s); break;
     default: break;
   }
 }

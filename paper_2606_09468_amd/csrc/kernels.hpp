@@ -8,7 +8,9 @@
 namespace pcs {
 
 // One dense product C = alpha * A * B + beta * C, real.  A (m x k) is stored
-// K-major, A[i][kk] at A[kk * lda + i] (lda >= m), in the compute precision;
+// row-major in the compute precision, A[i][kk] at A[i * lda + kk], with
+// lda = gemm_lda(k) and gemm_rows(m) rows allocated, all padding zero (the
+// kernels read whole 16-wide k blocks and row tiles of A unguarded).
 // B (k x n) and C (m x n) are row-major, each in its own precision (see
 // GemmType).  Complex fields (re/im interleaved) are multiplied by a real
 // operator by treating each complex column as two real columns.
@@ -17,10 +19,11 @@ struct GemmJob {
   const void* A;
   const void* B;
   void* C;
+  void* C2;  // optional second output: alpha A B scaled by scale2 (no beta term)
   int m, n, k, lda, ldb, ldc;
   double alpha, beta;
   int flags;           // GEMM_ZERO_MEAN: B columns 0 and 1 (the kx = kz = 0 mode) read as zero
-  int scale;           // SCALE_*: B rows are eigen coefficients scaled on the way into LDS
+  int scale, scale2;   // SCALE_*: output row i is eigen coefficient i, scaled per mode
   const EigScale* es;  // per-solve constants for the scaling
   int tiles_m, tile0;  // filled by gemm_prepare
 };
@@ -43,15 +46,20 @@ struct EigScale {
 // compute / B / C precisions: D = double, F = float
 enum GemmType { GEMM_DDD = 0, GEMM_FDF, GEMM_FFD, GEMM_DDF, GEMM_DFD, GEMM_NTYPES };
 
-constexpr int GEMM_BN = 32;  // output columns per workgroup
 constexpr int MAX_JOBS = 64;
+// Tile configurations.  Register-direct kernel (operand fragments loaded
+// straight into registers, no LDS in the loop): 0: 32 x 32 with K split over
+// the four waves, 1: 64 x 32 and 2: 32 x 64 with K split in two, 3: 64 x 64.
+// LDS-tiled kernel (operand chunks shared by the four waves through LDS):
+// 4: 32 x 32, 5: 64 x 32, 6: 64 x 64, 7: 128 x 64.
+constexpr int GEMM_NCFG = 8;
+inline int gemm_lda(int k) { return (k + 15) & ~15; }
+inline int gemm_rows(int m) { return (m + 127) & ~127; }
 
-// Fills tiles_m / tile0 for row tiles of bm (16, 64 or 128) and returns the
-// total number of workgroups.
-int gemm_prepare(GemmJob* jobs, int njobs, int bm);
-// kmax: largest k of the table (sizes the LDS panel of B).
-void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int bm, int kmax, hipStream_t s);
-size_t gemm_lds_bytes(int kmax, int elem);
+// Fills tiles_m / tile0 for tile configuration cfg and returns the total
+// number of workgroups.
+int gemm_prepare(GemmJob* jobs, int njobs, int cfg);
+void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s);
 hipError_t gemm_set_attributes();
 
 // Mixed-radix (4, 2, 3) Stockham plan for a length L = 2^a 3^b.

@@ -159,7 +159,9 @@ def test_laminar_state_is_steady_on_gpu(P, kappa):
     s1 = sim.get_state()
     recs, _ = sim.diagnostics()
     sim.close()
-    assert np.abs(s1[4:] - s0[4:]).max() / np.abs(s0[4:]).max() < 1e-13
+    # roundoff only: each step applies Ny-term wall-normal sums, so the drift
+    # is bounded by steps * Ny * eps relative to the largest field value
+    assert np.abs(s1[4:] - s0[4:]).max() / np.abs(s0[4:]).max() < 50 * 65 * 2.3e-16
     assert abs(recs[-1]["dpdx"] - 200.0) < 1e-8
 
 
