@@ -66,7 +66,10 @@ typedef struct {
  *  precision = 1: mixed: transforms and pointwise products of the
  *               fluctuation (all modes except kx = kz = 0) in FP32, the
  *               mean-mode profiles and every boundary-value solve in FP64;
- *               eps must be 0. */
+ *               eps must be 0.
+ *  precision = 2: as 1, but the wall-normal transforms of the fluctuation
+ *               (to and from the padded grid) are computed in FP64 and
+ *               only the periodic transforms and products in FP32. */
 typedef struct {
   double re, wi, beta, kappa, eps, dt;
   int32_t forcing;
@@ -141,6 +144,33 @@ const char* pcs_stage_name(int32_t i);
 
 pcs_status pcs_destroy(struct pcs_sim* sim);
 const char* pcs_status_string(pcs_status s);
+
+/* Ensembles: n independent runs of uneven sizes (the scan over resolutions
+ * and Wi of the paper's Section 3 stability and positivity study), all of
+ * one dimension and one precision setting, advanced together.  Every stage
+ * of the step is one kernel launch over all runs (a ragged table of
+ * (run, tile) work items), and the step is one graph launch on the stream.
+ * Conventions as for single runs: one caller-owned device workspace of
+ * pcs_ensemble_workspace_bytes, the caller's stream, an opaque handle.
+ * grids, params and seeds are arrays of n entries (run r starts from the
+ * state pcs_init would build with grids[r], params[r], seeds[r], amp).
+ * Errors: PCS_ERR_ARG for n <= 0 or null arrays, PCS_ERR_UNSUPPORTED if
+ * the runs mix dimensions or precisions (or any run's grid is unsupported),
+ * PCS_ERR_WORKSPACE as for pcs_init.  A run that blows up keeps being
+ * stepped with the others (its values are then meaningless); its own
+ * diagnostics report PCS_BLOWUP. */
+struct pcs_ens;
+pcs_status pcs_ensemble_workspace_bytes(int32_t n, const pcs_grid* grids, const pcs_params* params, size_t* bytes);
+pcs_status pcs_ensemble_init(int32_t n, const pcs_grid* grids, const pcs_params* params, const uint64_t* seeds,
+                             double amp, void* workspace, size_t bytes, void* stream, struct pcs_ens** out);
+/* Enqueues nsteps steps of every run (asynchronous). */
+pcs_status pcs_ensemble_step(struct pcs_ens* ens, int32_t nsteps);
+/* Diagnostics, state size and state of run `run` (0 <= run < n), with the
+ * semantics of pcs_diagnostics, pcs_state_size and pcs_get_state. */
+pcs_status pcs_ensemble_diagnostics(struct pcs_ens* ens, int32_t run, pcs_diag* out, int32_t max, int32_t* n_out);
+pcs_status pcs_ensemble_state_size(struct pcs_ens* ens, int32_t run, size_t* n);
+pcs_status pcs_ensemble_get_state(struct pcs_ens* ens, int32_t run, double* host, size_t n);
+pcs_status pcs_ensemble_destroy(struct pcs_ens* ens);
 
 #ifdef __cplusplus
 }

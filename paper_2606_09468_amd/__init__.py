@@ -27,7 +27,9 @@ PCS_ERR_STATE = -5
 
 EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pcs_state_size",
            "pcs_get_state", "pcs_set_state", "pcs_stage_times", "pcs_destroy", "pcs_status_string",
-           "pcs_stage_name")
+           "pcs_stage_name", "pcs_ensemble_workspace_bytes", "pcs_ensemble_init", "pcs_ensemble_step",
+           "pcs_ensemble_diagnostics", "pcs_ensemble_state_size", "pcs_ensemble_get_state",
+           "pcs_ensemble_destroy")
 PCS_NSTAGE = 11
 
 
@@ -76,6 +78,15 @@ def lib():
     L.pcs_destroy.argtypes = [vp]
     L.pcs_status_string.argtypes = [st]
     L.pcs_status_string.restype = ctypes.c_char_p
+    L.pcs_ensemble_workspace_bytes.argtypes = [st, ctypes.POINTER(pcs_grid), ctypes.POINTER(pcs_params),
+                                               ctypes.POINTER(sz)]
+    L.pcs_ensemble_init.argtypes = [st, ctypes.POINTER(pcs_grid), ctypes.POINTER(pcs_params),
+                                    ctypes.POINTER(ctypes.c_uint64), ctypes.c_double, vp, sz, vp, ctypes.POINTER(vp)]
+    L.pcs_ensemble_step.argtypes = [vp, st]
+    L.pcs_ensemble_diagnostics.argtypes = [vp, st, ctypes.POINTER(pcs_diag), st, ctypes.POINTER(ctypes.c_int32)]
+    L.pcs_ensemble_state_size.argtypes = [vp, st, ctypes.POINTER(sz)]
+    L.pcs_ensemble_get_state.argtypes = [vp, st, ctypes.POINTER(ctypes.c_double), sz]
+    L.pcs_ensemble_destroy.argtypes = [vp]
     for name in EXPORTS:
         if name not in ("pcs_status_string", "pcs_stage_name"):
             getattr(L, name).restype = st
@@ -113,6 +124,20 @@ def pcs_workspace_bytes(grid, params):
 
 
 DIAG_FIELDS = [f[0] for f in pcs_diag._fields_ if f[0] != "reserved"]
+
+
+def _arrays(grids, params):
+    n = len(grids)
+    if len(params) != n:
+        raise ValueError("grids and params differ in length")
+    return n, (pcs_grid * n)(*grids), (pcs_params * n)(*params)
+
+
+def pcs_ensemble_workspace_bytes(grids, params):
+    n, ga, pa = _arrays(grids, params)
+    out = ctypes.c_size_t(0)
+    _check(lib().pcs_ensemble_workspace_bytes(n, ga, pa, ctypes.byref(out)), "pcs_ensemble_workspace_bytes")
+    return out.value
 
 
 class Sim:
@@ -173,6 +198,65 @@ class Sim:
     def close(self):
         if self.handle:
             lib().pcs_destroy(self.handle)
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Ensemble:
+    """n independent runs advanced together (one graph launch per step, each
+    stage one kernel over all runs); workspace and stream from PyTorch."""
+
+    def __init__(self, grids, params, seeds, amp=1e-3, device="cuda:0"):
+        import torch
+        n, ga, pa = _arrays(grids, params)
+        if len(seeds) != n:
+            raise ValueError("need one seed per run")
+        sa = (ctypes.c_uint64 * n)(*[int(x) for x in seeds])
+        self.n = n
+        self.device = torch.device(device)
+        self.stream = torch.cuda.Stream(device=self.device)
+        nbytes = pcs_ensemble_workspace_bytes(grids, params)
+        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+        ptr = (self.workspace.data_ptr() + 255) & ~255
+        self.handle = ctypes.c_void_p(0)
+        _check(lib().pcs_ensemble_init(n, ga, pa, sa, float(amp), ctypes.c_void_p(ptr), nbytes,
+                                       ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(self.handle)),
+               "pcs_ensemble_init")
+        self.workspace_bytes = nbytes
+
+    def step(self, n=1):
+        return _check(lib().pcs_ensemble_step(self.handle, int(n)), "pcs_ensemble_step")
+
+    def diagnostics(self, run, max_records=4096):
+        buf = (pcs_diag * max_records)()
+        n = ctypes.c_int32(0)
+        st = _check(lib().pcs_ensemble_diagnostics(self.handle, int(run), buf, max_records, ctypes.byref(n)),
+                    "pcs_ensemble_diagnostics", allow=(PCS_OK, PCS_BLOWUP))
+        recs = [{k: getattr(buf[i], k) for k in DIAG_FIELDS} for i in range(n.value)]
+        return recs, st
+
+    def state_size(self, run):
+        n = ctypes.c_size_t(0)
+        _check(lib().pcs_ensemble_state_size(self.handle, int(run), ctypes.byref(n)), "pcs_ensemble_state_size")
+        return n.value
+
+    def get_state(self, run):
+        out = np.zeros(self.state_size(run))
+        _check(lib().pcs_ensemble_get_state(self.handle, int(run), out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            out.size), "pcs_ensemble_get_state")
+        return out
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def close(self):
+        if self.handle:
+            lib().pcs_ensemble_destroy(self.handle)
             self.handle = ctypes.c_void_p(0)
 
     def __del__(self):

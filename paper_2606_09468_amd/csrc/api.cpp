@@ -114,20 +114,16 @@ bool valid_fft(int L) {
 
 }  // namespace
 
-struct pcs_sim {
+// One channel simulation: its grid, parameters, operators and every device
+// buffer (all inside the caller's workspace), and its own product tables.
+struct Member {
   pcs_grid g{};
   pcs_params prm{};
   Dims d{};
   Phys p{};
-  hipStream_t s = nullptr;
-  // second stream (default priority) for the products of the state that do
-  // not feed the transforms; forked from and joined to s inside the step
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_bar = nullptr, ev_fwd = nullptr, ev_join = nullptr;
   const WallOps* ops = nullptr;
   FftPlan plx, plz, pbx, pbz;
   int nq = 0, nh = 0, nyin = 0, nzin = 0, nout = 0, nsolve = 0, nsv = 0;
-  // device buffers (all inside the caller's workspace)
   double *IMN, *DMN, *D, *D2, *PNM, *DP, *V, *Vinv, *DV, *wV, *lam, *d2i0, *d2in, *w, *ydy, *U1, *kx, *kz;
   double *twx, *twz, *twbx, *twbz;
   double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *DN, *Dc, *D2buf, *hgn, *hvn;
@@ -144,34 +140,90 @@ struct pcs_sim {
   DevScalars* sc;
   // G1: state -> padded grid; Gbar: FP64 mean profiles there (mixed);
   // G1b: D2 and D of the state; G2: projection and D of it; Gm: FP64 mean
-  // column projection (mixed); G4 / G5: into / out of the eigenbasis;
-  // H4 / H5: the same for the homogeneous solutions at init
+  // column projection (mixed); G4 / G5: into / out of the eigenbasis (host
+  // tables, merged across the batch); H4 / H5: the same for the homogeneous
+  // solutions at init (own device tables)
   JobList G1, Gbar, G1b, G2, Gm, G4, G5, H4, H5;
   int prec = 0;
   double wU1 = 0;
   long long drained = 0;
   int blowup = 0;
   size_t nstate = 0;
+  std::vector<JobList*> stage_lists() { return {&G1, &Gbar, &G1b, &G2, &Gm, &G4, &G5}; }
+};
+
+// A batch of simulations advanced together: each stage of the step is one
+// launch over all members (merged product tables, per-member argument tables
+// of the stage kernels), captured once as a HIP graph.  A single run is a
+// batch of one.
+struct Batch {
+  std::vector<Member*> mem;
+  int dim = 2, prec = 0;
+  hipStream_t s = nullptr;
+  // second stream (default priority) for the products of the state that do
+  // not feed the transforms; forked from and joined to s inside the step
+  hipStream_t s2 = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_bar = nullptr, ev_fwd = nullptr, ev_join = nullptr;
+  JobList G1, Gbar, G1b, G2, Gm, G4, G5;
+  // per-member argument tables (host copies, then device) and launch sizes
+  std::vector<XArgs> hx;
+  std::vector<ZArgs> hzi, hzf, hzd;
+  std::vector<DRowArgs> hdr;
+  std::vector<DFinArgs> hdf;
+  std::vector<RhsArgs> hrhs;
+  std::vector<FinArgs> hfin;
+  XArgs* dx = nullptr;
+  ZArgs *dzi = nullptr, *dzf = nullptr, *dzd = nullptr;
+  DRowArgs* ddr = nullptr;
+  DFinArgs* ddf = nullptr;
+  RhsArgs* drhs = nullptr;
+  FinArgs* dfin = nullptr;
+  int bx = 0, bzi = 0, bzf = 0, bzd = 0, bdr = 0, brhs = 0, bfin = 0;
+  size_t lx = 0, lzi = 0, lzf = 0, lzd = 0, ldr = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  std::vector<JobList*> lists() { return {&G1, &Gbar, &G1b, &G2, &Gm, &G4, &G5, &H4, &H5}; }
-  ~pcs_sim() {
+  std::vector<JobList*> lists() { return {&G1, &Gbar, &G1b, &G2, &Gm, &G4, &G5}; }
+  ~Batch() {
     if (s2) (void)hipStreamSynchronize(s2);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     for (hipEvent_t e : {ev_fork, ev_bar, ev_fwd, ev_join})
       if (e) (void)hipEventDestroy(e);
     if (s2) (void)hipStreamDestroy(s2);
+    for (Member* m : mem) delete m;
   }
 };
 
 namespace {
 
-// Assigns every device buffer; with base == nullptr only measures.
-size_t carve(pcs_sim* m, char* base) {
+// With PCS_DEBUG set in the environment, failing HIP calls are reported on stderr.
+void report(hipError_t e, const char* what, int line) {
+  static const bool dbg = std::getenv("PCS_DEBUG") != nullptr;
+  if (dbg) std::fprintf(stderr, "pcs: %s failed at api.cpp:%d: %s\n", what, line, hipGetErrorString(e));
+}
+
+#define HIPCHK(x)                        \
+  do {                                   \
+    hipError_t e_ = (x);                 \
+    if (e_ != hipSuccess) {              \
+      report(e_, #x, __LINE__);          \
+      (void)hipGetLastError();           \
+      return PCS_ERR_DEVICE;             \
+    }                                    \
+  } while (0)
+
+// Init-time uploads are blocking copies, so host temporaries may die at once.
+template <typename T>
+hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
+  hipError_t e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+}
+
+// Assigns every device buffer of one member (a null base only measures).
+void carve(Member* m, Carve& c) {
   const Dims& d = m->d;
   const size_t n1 = d.N + 1, m1 = d.M + 1, ni = d.N - 1, cw = d.cw;
-  Carve c(base);
   m->IMN = c.take<double>(opsz(m1, n1));
   m->DMN = c.take<double>(opsz(m1, n1));
   m->D = c.take<double>(opsz(n1, n1));
@@ -237,11 +289,11 @@ size_t carve(pcs_sim* m, char* base) {
   m->parts = c.take<DiagPart>(n1 * zrows);
   m->ring = c.take<DiagRec>(RING);
   m->sc = c.take<DevScalars>(1);
-  for (JobList* jl : m->lists()) jl->dev = c.take<GemmJob>(MAX_JOBS);
-  return c.off;
+  m->H4.dev = c.take<GemmJob>(8);
+  m->H5.dev = c.take<GemmJob>(8);
 }
 
-pcs_status setup_dims(pcs_sim* m, const pcs_grid* g, const pcs_params* p) {
+pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   if (!g || !p) return PCS_ERR_ARG;
   if (g->dim != 2 && g->dim != 3) return PCS_ERR_ARG;
   if (g->nx < 4 || (g->nx & 1) || g->ny < 9 || !(g->ny & 1)) return PCS_ERR_UNSUPPORTED;
@@ -304,7 +356,7 @@ pcs_status setup_dims(pcs_sim* m, const pcs_grid* g, const pcs_params* p) {
 
 // Initial state: laminar profiles in the mean slot plus the seeded
 // streamfunction perturbation (divergence-free, no-slip), history zero.
-void initial_state(const pcs_sim* m, uint64_t seed, double amp, std::vector<double>& st) {
+void initial_state(const Member* m, uint64_t seed, double amp, std::vector<double>& st) {
   const Dims& d = m->d;
   const int n1 = d.N + 1;
   const size_t fs = (size_t)n1 * d.cw;
@@ -435,13 +487,16 @@ void initial_state(const pcs_sim* m, uint64_t seed, double amp, std::vector<doub
   }
 }
 
-void build_jobs(pcs_sim* m) {
+void build_jobs(Member* m) {
   const Dims& d = m->d;
   const int n1 = d.N + 1, m1 = d.M + 1, ni = d.N - 1, cw = d.cw;
   const size_t fs = (size_t)n1 * cw, fsm = (size_t)m1 * cw, fsi = (size_t)ni * cw;
   double* st = m->state;
   const int FC = d.dim == 2 ? 3 : 5, FPHI = d.dim == 2 ? 2 : 3;
   const bool mixed = m->prec != 0;
+  for (JobList* jl : m->stage_lists()) jl->h.clear();
+  m->H4.h.clear();
+  m->H5.h.clear();
   // G1: values and d/dy on the padded grid (mixed: of the fluctuation only,
   // written in FP32; computed in FP32, or in FP64 for precision 2)
   JobList& g1 = m->G1;
@@ -518,138 +573,13 @@ void build_jobs(pcs_sim* m) {
   for (int a = 0; a < d.nc; ++a) m->G5.add(m->V, Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
   // w . U_p for the flux constraint: the mean column only
   m->G5.add(m->wV, Xs, cw, m->flux, cw, 1, 2, ni);
-  for (JobList* jl : m->lists())
-    if (jl->n()) jl->prepare();
+  for (JobList* jl : {&m->H4, &m->H5}) jl->prepare();
 }
 
-// Stage boundaries: mark(i) is called before stage i and once more at the
-// end; the eager profiling path records a HIP event there and runs every
-// stage on the caller's stream in order.  Otherwise the products of the
-// state that the transforms do not need (G1b, and in mixed precision the
-// FP64 mean profiles and mean-column projection) run on the second stream:
-//   s : G1 -> [z inv] -> (wait bar) -> x pencils -> [z fwd] -> G2 -> (wait join) -> RHS ...
-//   s2: (wait fork) -> [Gbar] -> bar -> G1b -> [(wait fwd) -> Gm] -> join
-enum Stage {
-  ST_GEMM_STATE, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_RHS, ST_GEMM_VINV, ST_GEMM_V,
-  ST_FINALIZE, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
-};
-static_assert(ST_COUNT == PCS_NSTAGE, "stage table");
-const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv", "xpencil", "zfft_fwd", "gemm_proj", "rhs",
-                                            "gemm_vinv",  "gemm_v",   "finalize", "diag_rows", "diag_final"};
-
-struct NoMark {
-  void operator()(int) const {}
-};
-
-template <typename Mark>
-void explicit_stage(pcs_sim* m, const Mark& mark) {
-  const Dims& d = m->d;
-  hipStream_t s = m->s;
-  const bool mixed = m->prec != 0;
-  constexpr bool fork = std::is_same<Mark, NoMark>::value;  // eager profiling stays on one stream
-  hipStream_t s2 = fork ? m->s2 : s;
-  mark(ST_GEMM_STATE);
-  if (fork) {
-    (void)hipEventRecord(m->ev_fork, s);
-    (void)hipStreamWaitEvent(s2, m->ev_fork, 0);
-  }
-  if (mixed) m->Gbar.run(s2);
-  if (fork) (void)hipEventRecord(m->ev_bar, s2);
-  m->G1.run(s);
-  m->G1b.run(s2);
-  const void* twx = mixed ? (const void*)m->twx32 : (const void*)m->twx;
-  const void* twz = mixed ? (const void*)m->twz32 : (const void*)m->twz;
-  const void* yin = mixed ? (const void*)m->Yin32 : (const void*)m->Yin;
-  void* yout = mixed ? (void*)m->Yout32 : (void*)m->Yout;
-  void* zin = mixed ? (void*)m->Zin32 : (void*)m->Zin;
-  void* zout = mixed ? (void*)m->Zout32 : (void*)m->Zout;
-  mark(ST_ZFFT_INV);
-  if (d.dim == 3)
-    launch_zfft(d, m->plz, yin, zin, m->nzin, m->zsrc, m->zder, m->kz, twz, 1, d.M + 1, m->prec, nullptr, nullptr, s);
-  mark(ST_XPENCIL);
-  if (fork && mixed) (void)hipStreamWaitEvent(s, m->ev_bar, 0);
-  if (d.dim == 3)
-    launch_xpencil(d, m->p, m->plx, zin, zout, m->kx, twx, m->prec, m->Ybar, nullptr, s);
-  else
-    launch_xpencil(d, m->p, m->plx, yin, yout, m->kx, twx, m->prec, m->Ybar, m->mcol, s);
-  mark(ST_ZFFT_FWD);
-  if (d.dim == 3)
-    launch_zfft(d, m->plz, zout, yout, m->nout, nullptr, nullptr, m->kz, twz, 0, d.M + 1, m->prec, m->Ybar, m->mcol,
-                s);
-  mark(ST_GEMM_PROJ);
-  if (mixed) {
-    if (fork) {
-      (void)hipEventRecord(m->ev_fwd, s);
-      (void)hipStreamWaitEvent(s2, m->ev_fwd, 0);
-    }
-    m->Gm.run(s2);
-  }
-  m->G2.run(s);
-  if (fork) {
-    (void)hipEventRecord(m->ev_join, s2);
-    (void)hipStreamWaitEvent(s, m->ev_join, 0);
-  }
-  mark(ST_RHS);
-  launch_rhs(d, m->p, m->state, m->D2buf, m->Dc, m->S, m->smean, m->DN, m->kx, m->kz, m->d2i0, m->d2in, m->R, m->hvn,
-             m->hgn, m->CB, s);
-}
-
-template <typename Mark>
-void enqueue_step(pcs_sim* m, const Mark& mark) {
-  const Dims& d = m->d;
-  hipStream_t s = m->s;
-  explicit_stage(m, mark);
-  mark(ST_GEMM_VINV);
-  m->G4.run(s);
-  mark(ST_GEMM_V);
-  m->G5.run(s);
-  mark(ST_FINALIZE);
-  launch_finalize(d, m->p, m->Zphi, m->Zv, m->ZDv, m->flux, m->infl, m->U1, m->wU1, m->CB, m->hvn, m->hgn, m->S,
-                  m->smean, m->kx, m->kz, m->state, m->prep, m->sc, s);
-  mark(ST_DIAG_ROWS);
-  launch_diag_rows(d, m->pbx, m->prep, m->zbuf, m->pbz, m->twbx, m->twbz, m->ydy, m->parts, s);
-  mark(ST_DIAG_FINAL);
-  launch_diag_final(d, m->p, m->parts, m->w, m->sc, m->ring, RING, s);
-  mark(ST_COUNT);
-}
-
-// With PCS_DEBUG set in the environment, failing HIP calls are reported on stderr.
-void report(hipError_t e, const char* what, int line) {
-  static const bool dbg = std::getenv("PCS_DEBUG") != nullptr;
-  if (dbg) std::fprintf(stderr, "pcs: %s failed at api.cpp:%d: %s\n", what, line, hipGetErrorString(e));
-}
-
-#define HIPCHK(x)                        \
-  do {                                   \
-    hipError_t e_ = (x);                 \
-    if (e_ != hipSuccess) {              \
-      report(e_, #x, __LINE__);          \
-      (void)hipGetLastError();           \
-      return PCS_ERR_DEVICE;             \
-    }                                    \
-  } while (0)
-
-// Tile autotuner: times each candidate tile configuration of a product table on
-// the device (results of the timing launches are discarded) and keeps the
-// fastest.  Choices are cached per table shape for the process lifetime.
-std::map<std::vector<int>, int>& tune_cache() {
-  static std::map<std::vector<int>, int> c;
-  return c;
-}
-
-// Init-time uploads are blocking copies, so host temporaries may die at once.
-template <typename T>
-hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
-  hipError_t e = hipStreamSynchronize(s);
-  if (e != hipSuccess) return e;
-  return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
-}
-
-pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
+pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
   const Dims& d = m->d;
   const WallOps* op = m->ops;
   const int n1 = d.N + 1, ni = d.N - 1;
-  hipStream_t s = m->s;
   // operators
   const int m1 = d.M + 1;
   HIPCHK(up(m->IMN, padded(op->IMN, m1, n1), s));
@@ -747,32 +677,315 @@ pcs_status upload_everything(pcs_sim* m, uint64_t seed, double amp) {
   DevScalars sc0{};
   sc0.pi = m->p.forcing == 1 ? m->p.q_or_dpdx : 2.0 / m->p.re;
   HIPCHK(hipMemcpy(m->sc, &sc0, sizeof(sc0), hipMemcpyHostToDevice));
-  // GEMM job tables
-  for (JobList* jl : m->lists())
-    if (jl->n()) HIPCHK(up(jl->dev, jl->h, s));
+  // the member's own product tables (homogeneous solutions at init)
+  HIPCHK(up(m->H4.dev, m->H4.h, s));
+  HIPCHK(up(m->H5.dev, m->H5.h, s));
   return PCS_OK;
 }
 
 // Initial state and device scalars (again after tuning, whose timing launches
 // write into the state's solve targets).
-pcs_status reset_state(pcs_sim* m, uint64_t seed, double amp) {
+pcs_status reset_state(Member* m, uint64_t seed, double amp, hipStream_t s) {
   std::vector<double> st;
   initial_state(m, seed, amp, st);
-  HIPCHK(up(m->state, st, m->s));
+  HIPCHK(up(m->state, st, s));
   DevScalars sc0{};
   sc0.pi = m->p.forcing == 1 ? m->p.q_or_dpdx : 2.0 / m->p.re;
   HIPCHK(hipMemcpy(m->sc, &sc0, sizeof(sc0), hipMemcpyHostToDevice));
   return PCS_OK;
 }
 
-pcs_status autotune(pcs_sim* m) {
+// Merges the members' tables of one stage into the batch's table.
+void merge_list(JobList& dst, const std::vector<Member*>& mem, JobList Member::*lp) {
+  dst.h.clear();
+  for (Member* m : mem) {
+    const JobList& src = m->*lp;
+    if (src.n()) dst.type = src.type;
+    dst.h.insert(dst.h.end(), src.h.begin(), src.h.end());
+  }
+  if (dst.n()) dst.prepare();
+}
+
+// Builds the merged product tables, the per-member argument tables of the
+// stage kernels and the launch sizes (workgroups, LDS) of every stage.
+void build_batch(Batch* b) {
+  const std::vector<Member*>& mem = b->mem;
+  merge_list(b->G1, mem, &Member::G1);
+  merge_list(b->Gbar, mem, &Member::Gbar);
+  merge_list(b->G1b, mem, &Member::G1b);
+  merge_list(b->G2, mem, &Member::G2);
+  merge_list(b->Gm, mem, &Member::Gm);
+  merge_list(b->G4, mem, &Member::G4);
+  merge_list(b->G5, mem, &Member::G5);
+  b->hx.clear();
+  b->hzi.clear();
+  b->hzf.clear();
+  b->hzd.clear();
+  b->hdr.clear();
+  b->hdf.clear();
+  b->hrhs.clear();
+  b->hfin.clear();
+  b->bx = b->bzi = b->bzf = b->bzd = b->bdr = b->brhs = b->bfin = 0;
+  b->lx = b->lzi = b->lzf = b->lzd = b->ldr = 0;
+  for (Member* m : mem) {
+    const Dims& d = m->d;
+    const bool mixed = m->prec != 0;
+    const int n1 = d.N + 1, m1 = d.M + 1;
+    const void* twx = mixed ? (const void*)m->twx32 : (const void*)m->twx;
+    const void* twz = mixed ? (const void*)m->twz32 : (const void*)m->twz;
+    void* yin = mixed ? (void*)m->Yin32 : (void*)m->Yin;
+    void* yout = mixed ? (void*)m->Yout32 : (void*)m->Yout;
+    void* zin = mixed ? (void*)m->Zin32 : (void*)m->Zin;
+    void* zout = mixed ? (void*)m->Zout32 : (void*)m->Zout;
+    XArgs x{};
+    x.in = d.dim == 3 ? zin : yin;
+    x.out = d.dim == 3 ? zout : yout;
+    x.nrows = xpencil_blocks(d);
+    x.nkx = d.nkx;
+    x.m1 = m1;
+    x.pz = d.pz;
+    x.pl = m->plx;
+    x.kx = m->kx;
+    x.tw = twx;
+    x.eps_wi = m->p.eps / m->p.wi;
+    x.mean = m->Ybar;
+    x.mcol = d.dim == 2 ? m->mcol : nullptr;
+    x.blk0 = b->bx;
+    b->bx += x.nrows;
+    b->lx = std::max(b->lx, xpencil_lds_bytes(d.dim, d.px, m->prec));
+    b->hx.push_back(x);
+    if (d.dim == 3) {
+      const int ngx = (d.nkx + ZFFT_GROUP - 1) / ZFFT_GROUP;
+      ZArgs zi{};
+      zi.in = yin;
+      zi.out = zin;
+      zi.nkx = d.nkx;
+      zi.nzs = d.nzs;
+      zi.rows = m1;
+      zi.nfields = m->nzin;
+      zi.ngx = ngx;
+      zi.inverse = 1;
+      zi.pl = m->plz;
+      zi.src_field = m->zsrc;
+      zi.deriv = m->zder;
+      zi.kz = m->kz;
+      zi.tw = twz;
+      zi.blk0 = b->bzi;
+      b->bzi += zfft_blocks(d.nkx, m1, m->nzin);
+      b->lzi = std::max(b->lzi, zfft_lds_bytes(d.pz, m->prec));
+      b->hzi.push_back(zi);
+      ZArgs zf = zi;
+      zf.in = zout;
+      zf.out = yout;
+      zf.nfields = m->nout;
+      zf.inverse = 0;
+      zf.src_field = nullptr;
+      zf.deriv = nullptr;
+      zf.mean = m->Ybar;
+      zf.mcol = m->mcol;
+      zf.blk0 = b->bzf;
+      b->bzf += zfft_blocks(d.nkx, m1, m->nout);
+      b->lzf = std::max(b->lzf, zfft_lds_bytes(d.pz, m->prec));
+      b->hzf.push_back(zf);
+      ZArgs zd{};
+      zd.in = m->prep;
+      zd.out = m->zbuf;
+      zd.nkx = d.nkx;
+      zd.nzs = d.nzs;
+      zd.rows = n1;
+      zd.nfields = 4;
+      zd.ngx = ngx;
+      zd.inverse = 1;
+      zd.pl = m->pbz;
+      zd.tw = m->twbz;
+      zd.blk0 = b->bzd;
+      b->bzd += zfft_blocks(d.nkx, n1, 4);
+      b->lzd = std::max(b->lzd, zfft_lds_bytes(d.nz, 0));
+      b->hzd.push_back(zd);
+    }
+    DRowArgs r{};
+    r.d = d;
+    r.in = d.dim == 3 ? m->zbuf : m->prep;
+    r.zrows = d.dim == 3 ? d.nz : 1;
+    r.pl = m->pbx;
+    r.tw = m->twbx;
+    r.ydy = m->ydy;
+    r.parts = m->parts;
+    r.blk0 = b->bdr;
+    b->bdr += n1 * r.zrows;
+    b->ldr = std::max(b->ldr, diag_rows_lds_bytes(d.nx));
+    b->hdr.push_back(r);
+    DFinArgs f{};
+    f.d = d;
+    f.p = m->p;
+    f.parts = m->parts;
+    f.zrows = r.zrows;
+    f.w = m->w;
+    f.sc = m->sc;
+    f.ring = m->ring;
+    f.cap = RING;
+    b->hdf.push_back(f);
+    const int eblocks = (n1 * d.nm + ELEM_THREADS - 1) / ELEM_THREADS;
+    RhsArgs h{};
+    h.d = d;
+    h.p = m->p;
+    h.st = m->state;
+    h.D2buf = m->D2buf;
+    h.Dc = m->Dc;
+    h.S = m->S;
+    h.smean = m->smean;
+    h.DN = m->DN;
+    h.kx = m->kx;
+    h.kz = m->kz;
+    h.d2i0 = m->d2i0;
+    h.d2in = m->d2in;
+    h.R = m->R;
+    h.hvn = m->hvn;
+    h.hgn = m->hgn;
+    h.CB = m->CB;
+    h.blk0 = b->brhs;
+    b->brhs += eblocks;
+    b->hrhs.push_back(h);
+    FinArgs q{};
+    q.d = d;
+    q.p = m->p;
+    q.Zphi = m->Zphi;
+    q.Zv = m->Zv;
+    q.ZDv = m->ZDv;
+    q.flux = m->flux;
+    q.infl = m->infl;
+    q.U1 = m->U1;
+    q.wU1 = m->wU1;
+    q.CB = m->CB;
+    q.hvn = m->hvn;
+    q.hgn = m->hgn;
+    q.S = m->S;
+    q.smean = m->smean;
+    q.kx = m->kx;
+    q.kz = m->kz;
+    q.st = m->state;
+    q.prep = m->prep;
+    q.sc = m->sc;
+    q.blk0 = b->bfin;
+    b->bfin += eblocks;
+    b->hfin.push_back(q);
+  }
+}
+
+// Carves every member, builds all tables, and carves the batch's device
+// tables after the members; with base == nullptr only measures.
+size_t layout(Batch* b, char* base) {
+  Carve c(base);
+  for (Member* m : b->mem) carve(m, c);
+  for (Member* m : b->mem) build_jobs(m);
+  build_batch(b);
+  for (JobList* jl : b->lists()) jl->dev = c.take<GemmJob>(std::max(1, jl->n()));
+  const size_t n = b->mem.size();
+  b->dx = c.take<XArgs>(n);
+  b->dzi = c.take<ZArgs>(n);
+  b->dzf = c.take<ZArgs>(n);
+  b->dzd = c.take<ZArgs>(n);
+  b->ddr = c.take<DRowArgs>(n);
+  b->ddf = c.take<DFinArgs>(n);
+  b->drhs = c.take<RhsArgs>(n);
+  b->dfin = c.take<FinArgs>(n);
+  return c.off;
+}
+
+// Stage boundaries: mark(i) is called before stage i and once more at the
+// end; the eager profiling path records a HIP event there and runs every
+// stage on the caller's stream in order.  Otherwise the products of the
+// state that the transforms do not need (G1b, and in mixed precision the
+// FP64 mean profiles and mean-column projection) run on the second stream:
+//   s : G1 -> [z inv] -> (wait bar) -> x pencils -> [z fwd] -> G2 -> (wait join) -> RHS ...
+//   s2: (wait fork) -> [Gbar] -> bar -> G1b -> [(wait fwd) -> Gm] -> join
+enum Stage {
+  ST_GEMM_STATE, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_RHS, ST_GEMM_VINV, ST_GEMM_V,
+  ST_FINALIZE, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
+};
+static_assert(ST_COUNT == PCS_NSTAGE, "stage table");
+const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv", "xpencil", "zfft_fwd", "gemm_proj", "rhs",
+                                            "gemm_vinv",  "gemm_v",   "finalize", "diag_rows", "diag_final"};
+
+struct NoMark {
+  void operator()(int) const {}
+};
+
+template <typename Mark>
+void explicit_stage(Batch* b, const Mark& mark) {
+  hipStream_t s = b->s;
+  const bool mixed = b->prec != 0;
+  constexpr bool fork = std::is_same<Mark, NoMark>::value;  // eager profiling stays on one stream
+  hipStream_t s2 = fork ? b->s2 : s;
+  const int nm = (int)b->mem.size();
+  mark(ST_GEMM_STATE);
+  if (fork) {
+    (void)hipEventRecord(b->ev_fork, s);
+    (void)hipStreamWaitEvent(s2, b->ev_fork, 0);
+  }
+  if (mixed) b->Gbar.run(s2);
+  if (fork) (void)hipEventRecord(b->ev_bar, s2);
+  b->G1.run(s);
+  b->G1b.run(s2);
+  mark(ST_ZFFT_INV);
+  if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
+  mark(ST_XPENCIL);
+  if (fork && mixed) (void)hipStreamWaitEvent(s, b->ev_bar, 0);
+  launch_xpencil(b->dim, b->prec, b->dx, nm, b->bx, b->lx, s);
+  mark(ST_ZFFT_FWD);
+  if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
+  mark(ST_GEMM_PROJ);
+  if (mixed) {
+    if (fork) {
+      (void)hipEventRecord(b->ev_fwd, s);
+      (void)hipStreamWaitEvent(s2, b->ev_fwd, 0);
+    }
+    b->Gm.run(s2);
+  }
+  b->G2.run(s);
+  if (fork) {
+    (void)hipEventRecord(b->ev_join, s2);
+    (void)hipStreamWaitEvent(s, b->ev_join, 0);
+  }
+  mark(ST_RHS);
+  launch_rhs(b->drhs, nm, b->brhs, s);
+}
+
+template <typename Mark>
+void enqueue_step(Batch* b, const Mark& mark) {
+  hipStream_t s = b->s;
+  const int nm = (int)b->mem.size();
+  explicit_stage(b, mark);
+  mark(ST_GEMM_VINV);
+  b->G4.run(s);
+  mark(ST_GEMM_V);
+  b->G5.run(s);
+  mark(ST_FINALIZE);
+  launch_finalize(b->dfin, nm, b->bfin, s);
+  mark(ST_DIAG_ROWS);
+  if (b->dim == 3) launch_zfft(0, b->dzd, nm, b->bzd, b->lzd, s);
+  launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, s);
+  mark(ST_DIAG_FINAL);
+  launch_diag_final(b->ddf, nm, s);
+  mark(ST_COUNT);
+}
+
+// Tile autotuner: times each candidate tile configuration of a product table
+// on the device (results of the timing launches are discarded) and keeps the
+// fastest.  Choices are cached per table shape for the process lifetime.
+std::map<std::vector<int>, int>& tune_cache() {
+  static std::map<std::vector<int>, int> c;
+  return c;
+}
+
+pcs_status autotune(Batch* b) {
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
-  hipStream_t s = m->s;
+  hipStream_t s = b->s;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
-  for (JobList* jl : m->lists()) {
+  for (JobList* jl : b->lists()) {
     if (!jl->n()) continue;
     const auto key = jl->key();
     auto it = tune_cache().find(key);
@@ -806,9 +1019,10 @@ pcs_status autotune(pcs_sim* m) {
   return PCS_OK;
 }
 
-pcs_status homogeneous_solutions(pcs_sim* m) {
+// Homogeneous solutions of the influence-matrix method for one member, with
+// the same product kernels as the step (own small tables), and w . U_1.
+pcs_status homogeneous_solutions(Member* m, hipStream_t s) {
   const Dims& d = m->d;
-  hipStream_t s = m->s;
   const size_t fsi = (size_t)(d.N - 1) * d.cw;
   HIPCHK(hipMemsetAsync(m->R, 0, m->nsolve * fsi * sizeof(double), s));
   launch_homog_rhs(d, m->p, m->d2i0, m->d2in, m->R, s);
@@ -825,38 +1039,60 @@ pcs_status homogeneous_solutions(pcs_sim* m) {
   return PCS_OK;
 }
 
+// Merged product tables and argument tables to the device (after the
+// homogeneous solutions, which fix w . U_1 in the finalize arguments).
+pcs_status upload_tables(Batch* b) {
+  hipStream_t s = b->s;
+  for (size_t i = 0; i < b->mem.size(); ++i) b->hfin[i].wU1 = b->mem[i]->wU1;
+  for (JobList* jl : b->lists())
+    if (jl->n()) HIPCHK(up(jl->dev, jl->h, s));
+  HIPCHK(up(b->dx, b->hx, s));
+  if (!b->hzi.empty()) {
+    HIPCHK(up(b->dzi, b->hzi, s));
+    HIPCHK(up(b->dzf, b->hzf, s));
+    HIPCHK(up(b->dzd, b->hzd, s));
+  }
+  HIPCHK(up(b->ddr, b->hdr, s));
+  HIPCHK(up(b->ddf, b->hdf, s));
+  HIPCHK(up(b->drhs, b->hrhs, s));
+  HIPCHK(up(b->dfin, b->hfin, s));
+  return PCS_OK;
+}
+
 // History := explicit terms of the current state (the first step is CNAB1).
-pcs_status history_from_state(pcs_sim* m) {
-  const Dims& d = m->d;
-  hipStream_t s = m->s;
-  const size_t fs = (size_t)(d.N + 1) * d.cw;
-  explicit_stage(m, NoMark());
+pcs_status history_from_state(Batch* b) {
+  hipStream_t s = b->s;
+  explicit_stage(b, NoMark());
   HIPCHK(hipGetLastError());
-  double* hist = m->state + (size_t)m->nq * fs;
-  HIPCHK(hipMemcpyAsync(hist, m->hvn, fs * sizeof(double), hipMemcpyDeviceToDevice, s));
-  int h = 1;
-  if (d.dim == 3) HIPCHK(hipMemcpyAsync(hist + (h++) * fs, m->hgn, fs * sizeof(double), hipMemcpyDeviceToDevice, s));
-  const int SF = d.dim == 2 ? 2 : 3;
-  HIPCHK(hipMemcpyAsync(hist + h * fs, m->S + SF * fs, d.nc * fs * sizeof(double), hipMemcpyDeviceToDevice, s));
-  if (m->smean) {
-    // mixed precision: the mean column of F comes from the FP64 projection
-    const int n1 = d.N + 1;
-    for (int a = 0; a < d.nc; ++a)
-      HIPCHK(hipMemcpy2DAsync(hist + (h + a) * fs, d.cw * sizeof(double), m->smean + (size_t)(SF + a) * n1,
-                              sizeof(double), sizeof(double), n1, hipMemcpyDeviceToDevice, s));
+  for (Member* m : b->mem) {
+    const Dims& d = m->d;
+    const size_t fs = (size_t)(d.N + 1) * d.cw;
+    double* hist = m->state + (size_t)m->nq * fs;
+    HIPCHK(hipMemcpyAsync(hist, m->hvn, fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    int h = 1;
+    if (d.dim == 3) HIPCHK(hipMemcpyAsync(hist + (h++) * fs, m->hgn, fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    const int SF = d.dim == 2 ? 2 : 3;
+    HIPCHK(hipMemcpyAsync(hist + h * fs, m->S + SF * fs, d.nc * fs * sizeof(double), hipMemcpyDeviceToDevice, s));
+    if (m->smean) {
+      // mixed precision: the mean column of F comes from the FP64 projection
+      const int n1 = d.N + 1;
+      for (int a = 0; a < d.nc; ++a)
+        HIPCHK(hipMemcpy2DAsync(hist + (h + a) * fs, d.cw * sizeof(double), m->smean + (size_t)(SF + a) * n1,
+                                sizeof(double), sizeof(double), n1, hipMemcpyDeviceToDevice, s));
+    }
   }
   return PCS_OK;
 }
 
-pcs_status capture(pcs_sim* m) {
-  if (m->s == nullptr) return PCS_OK;  // the legacy default stream cannot be captured
-  if (hipStreamBeginCapture(m->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+pcs_status capture(Batch* b) {
+  if (b->s == nullptr) return PCS_OK;  // the legacy default stream cannot be captured
+  if (hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
     return PCS_OK;
   }
-  enqueue_step(m, NoMark());
+  enqueue_step(b, NoMark());
   hipGraph_t g = nullptr;
-  if (hipStreamEndCapture(m->s, &g) != hipSuccess || g == nullptr) {
+  if (hipStreamEndCapture(b->s, &g) != hipSuccess || g == nullptr) {
     (void)hipGetLastError();
     return PCS_OK;
   }
@@ -866,104 +1102,92 @@ pcs_status capture(pcs_sim* m) {
     (void)hipGraphDestroy(g);
     return PCS_OK;
   }
-  m->graph = g;
-  m->gexec = ge;
+  b->graph = g;
+  b->gexec = ge;
   return PCS_OK;
 }
 
-}  // namespace
+// Validates and sizes a batch of n runs (all of one dimension and one
+// precision); fills b->mem.
+pcs_status setup_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_params* params, size_t* bytes) {
+  if (n <= 0 || !grids || !params) return PCS_ERR_ARG;
+  for (int32_t i = 0; i < n; ++i) {
+    Member* m = new (std::nothrow) Member();
+    if (!m) return PCS_ERR_ARG;
+    b->mem.push_back(m);
+    pcs_status st = setup_dims(m, &grids[i], &params[i]);
+    if (st != PCS_OK) return st;
+    if (m->d.dim != b->mem[0]->d.dim || m->prec != b->mem[0]->prec) return PCS_ERR_UNSUPPORTED;
+  }
+  b->dim = b->mem[0]->d.dim;
+  b->prec = b->mem[0]->prec;
+  *bytes = layout(b, nullptr);
+  return PCS_OK;
+}
 
-extern "C" {
-
-pcs_status pcs_workspace_bytes(const pcs_grid* grid, const pcs_params* params, size_t* bytes) {
-  if (!bytes) return PCS_ERR_ARG;
-  pcs_sim tmp;
-  pcs_status st = setup_dims(&tmp, grid, params);
+pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_params* params, const uint64_t* seeds,
+                      double amp, void* workspace, size_t bytes, void* stream) {
+  if (!workspace || !seeds || !std::isfinite(amp)) return PCS_ERR_ARG;
+  size_t need = 0;
+  pcs_status st = setup_batch(b, n, grids, params, &need);
   if (st != PCS_OK) return st;
-  *bytes = carve(&tmp, nullptr);
-  return PCS_OK;
-}
-
-pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t seed, double amp, void* workspace,
-                    size_t bytes, void* stream, pcs_sim** out) {
-  if (!out || !workspace) return PCS_ERR_ARG;
-  *out = nullptr;
-  if (!std::isfinite(amp)) return PCS_ERR_ARG;
-  pcs_sim* m = new (std::nothrow) pcs_sim();
-  if (!m) return PCS_ERR_ARG;
-  pcs_status st = setup_dims(m, grid, params);
-  if (st != PCS_OK) {
-    delete m;
-    return st;
+  if (bytes < need || (reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0) return PCS_ERR_WORKSPACE;
+  for (Member* m : b->mem) {
+    m->ops = wall_ops(m->d.N);
+    if (!m->ops) return PCS_ERR_UNSUPPORTED;
   }
-  const size_t need = carve(m, nullptr);
-  if (bytes < need || (reinterpret_cast<uintptr_t>(workspace) % ALIGN) != 0) {
-    delete m;
-    return PCS_ERR_WORKSPACE;
-  }
-  m->ops = wall_ops(m->d.N);
-  if (!m->ops) {
-    delete m;
-    return PCS_ERR_UNSUPPORTED;
-  }
-  carve(m, static_cast<char*>(workspace));
-  m->s = static_cast<hipStream_t>(stream);
-  if (hipStreamCreateWithFlags(&m->s2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&m->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&m->ev_bar, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&m->ev_fwd, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&m->ev_join, hipEventDisableTiming) != hipSuccess) {
+  layout(b, static_cast<char*>(workspace));
+  b->s = static_cast<hipStream_t>(stream);
+  if (hipStreamCreateWithFlags(&b->s2, hipStreamNonBlocking) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_bar, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_fwd, hipEventDisableTiming) != hipSuccess ||
+      hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
     (void)hipGetLastError();
-    delete m;
     return PCS_ERR_DEVICE;
   }
   if (hipError_t e = gemm_set_attributes(); e != hipSuccess) {
     report(e, "gemm_set_attributes", __LINE__);
-    delete m;
     return PCS_ERR_DEVICE;
   }
   if (hipError_t e = fft_set_attributes(); e != hipSuccess) {
     report(e, "fft_set_attributes", __LINE__);
-    delete m;
     return PCS_ERR_DEVICE;
   }
-  build_jobs(m);
-  if ((st = upload_everything(m, seed, amp)) != PCS_OK || (st = autotune(m)) != PCS_OK ||
-      (st = reset_state(m, seed, amp)) != PCS_OK || (st = homogeneous_solutions(m)) != PCS_OK ||
-      (st = history_from_state(m)) != PCS_OK) {
-    delete m;
-    return st;
-  }
-  hipError_t e1 = hipStreamSynchronize(m->s), e2 = hipGetLastError();
+  for (int32_t i = 0; i < n; ++i)
+    if ((st = upload_member(b->mem[i], seeds[i], amp, b->s)) != PCS_OK) return st;
+  if ((st = autotune(b)) != PCS_OK) return st;
+  for (int32_t i = 0; i < n; ++i)
+    if ((st = reset_state(b->mem[i], seeds[i], amp, b->s)) != PCS_OK ||
+        (st = homogeneous_solutions(b->mem[i], b->s)) != PCS_OK)
+      return st;
+  if ((st = upload_tables(b)) != PCS_OK || (st = history_from_state(b)) != PCS_OK) return st;
+  hipError_t e1 = hipStreamSynchronize(b->s), e2 = hipGetLastError();
   if (e1 != hipSuccess || e2 != hipSuccess) {
     report(e1 != hipSuccess ? e1 : e2, "init synchronise", __LINE__);
-    delete m;
     return PCS_ERR_DEVICE;
   }
-  capture(m);
-  *out = m;
+  capture(b);
   return PCS_OK;
 }
 
-pcs_status pcs_step(pcs_sim* m, int32_t nsteps) {
-  if (!m || nsteps < 0) return PCS_ERR_ARG;
-  if (m->blowup) return PCS_ERR_STATE;
+pcs_status step_batch(Batch* b, int32_t nsteps) {
   for (int i = 0; i < nsteps; ++i) {
-    if (m->gexec) {
-      if (hipGraphLaunch(m->gexec, m->s) != hipSuccess) return PCS_ERR_DEVICE;
+    if (b->gexec) {
+      if (hipGraphLaunch(b->gexec, b->s) != hipSuccess) return PCS_ERR_DEVICE;
     } else {
-      enqueue_step(m, NoMark());
+      enqueue_step(b, NoMark());
     }
   }
   return hipGetLastError() == hipSuccess ? PCS_OK : PCS_ERR_DEVICE;
 }
 
-pcs_status pcs_diagnostics(pcs_sim* m, pcs_diag* outp, int32_t max, int32_t* n_out) {
-  if (!m || !n_out || max < 0 || (max > 0 && !outp)) return PCS_ERR_ARG;
+pcs_status member_diagnostics(Member* m, hipStream_t s, pcs_diag* outp, int32_t max, int32_t* n_out) {
+  if (!n_out || max < 0 || (max > 0 && !outp)) return PCS_ERR_ARG;
   *n_out = 0;
   DevScalars sc;
-  HIPCHK(hipMemcpyAsync(&sc, m->sc, sizeof(sc), hipMemcpyDeviceToHost, m->s));
-  HIPCHK(hipStreamSynchronize(m->s));
+  HIPCHK(hipMemcpyAsync(&sc, m->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   long long first = m->drained + 1;
   if (sc.step - first + 1 > RING) first = sc.step - RING + 1;
   long long cnt = sc.step - first + 1;
@@ -975,10 +1199,10 @@ pcs_status pcs_diagnostics(pcs_sim* m, pcs_diag* outp, int32_t max, int32_t* n_o
   while (done < cnt) {
     const long long slot = (first + done - 1) % RING;
     const long long piece = std::min<long long>(cnt - done, RING - slot);
-    HIPCHK(hipMemcpyAsync(&recs[done], m->ring + slot, (size_t)piece * sizeof(DiagRec), hipMemcpyDeviceToHost, m->s));
+    HIPCHK(hipMemcpyAsync(&recs[done], m->ring + slot, (size_t)piece * sizeof(DiagRec), hipMemcpyDeviceToHost, s));
     done += piece;
   }
-  HIPCHK(hipStreamSynchronize(m->s));
+  HIPCHK(hipStreamSynchronize(s));
   static_assert(sizeof(DiagRec) == sizeof(pcs_diag), "diagnostic record layout");
   if (cnt > 0) std::memcpy(outp, recs.data(), (size_t)cnt * sizeof(pcs_diag));
   *n_out = (int32_t)cnt;
@@ -987,18 +1211,12 @@ pcs_status pcs_diagnostics(pcs_sim* m, pcs_diag* outp, int32_t max, int32_t* n_o
   return m->blowup ? PCS_BLOWUP : PCS_OK;
 }
 
-pcs_status pcs_state_size(pcs_sim* m, size_t* n) {
-  if (!m || !n) return PCS_ERR_ARG;
-  *n = m->nstate;
-  return PCS_OK;
-}
-
-pcs_status pcs_get_state(pcs_sim* m, double* host, size_t n) {
-  if (!m || !host || n != m->nstate) return PCS_ERR_ARG;
+pcs_status member_get_state(Member* m, hipStream_t s, double* host, size_t n) {
+  if (!host || n != m->nstate) return PCS_ERR_ARG;
   DevScalars sc;
-  HIPCHK(hipMemcpyAsync(&sc, m->sc, sizeof(sc), hipMemcpyDeviceToHost, m->s));
-  HIPCHK(hipMemcpyAsync(host + 4, m->state, (n - 4) * sizeof(double), hipMemcpyDeviceToHost, m->s));
-  HIPCHK(hipStreamSynchronize(m->s));
+  HIPCHK(hipMemcpyAsync(&sc, m->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(host + 4, m->state, (n - 4) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
   host[0] = (double)sc.step;
   host[1] = sc.t;
   host[2] = sc.pi;
@@ -1006,31 +1224,91 @@ pcs_status pcs_get_state(pcs_sim* m, double* host, size_t n) {
   return PCS_OK;
 }
 
-pcs_status pcs_set_state(pcs_sim* m, const double* host, size_t n) {
-  if (!m || !host || n != m->nstate) return PCS_ERR_ARG;
+}  // namespace
+
+struct pcs_sim {
+  Batch b;
+  Member* m() { return b.mem[0]; }
+};
+
+struct pcs_ens {
+  Batch b;
+};
+
+extern "C" {
+
+pcs_status pcs_workspace_bytes(const pcs_grid* grid, const pcs_params* params, size_t* bytes) {
+  if (!bytes || !grid || !params) return PCS_ERR_ARG;
+  Batch b;
+  return setup_batch(&b, 1, grid, params, bytes);
+}
+
+pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t seed, double amp, void* workspace,
+                    size_t bytes, void* stream, pcs_sim** out) {
+  if (!out) return PCS_ERR_ARG;
+  *out = nullptr;
+  if (!grid || !params) return PCS_ERR_ARG;
+  pcs_sim* sim = new (std::nothrow) pcs_sim();
+  if (!sim) return PCS_ERR_ARG;
+  const pcs_status st = init_batch(&sim->b, 1, grid, params, &seed, amp, workspace, bytes, stream);
+  if (st != PCS_OK) {
+    delete sim;
+    return st;
+  }
+  *out = sim;
+  return PCS_OK;
+}
+
+pcs_status pcs_step(pcs_sim* sim, int32_t nsteps) {
+  if (!sim || nsteps < 0) return PCS_ERR_ARG;
+  if (sim->m()->blowup) return PCS_ERR_STATE;
+  return step_batch(&sim->b, nsteps);
+}
+
+pcs_status pcs_diagnostics(pcs_sim* sim, pcs_diag* outp, int32_t max, int32_t* n_out) {
+  if (!sim) return PCS_ERR_ARG;
+  return member_diagnostics(sim->m(), sim->b.s, outp, max, n_out);
+}
+
+pcs_status pcs_state_size(pcs_sim* sim, size_t* n) {
+  if (!sim || !n) return PCS_ERR_ARG;
+  *n = sim->m()->nstate;
+  return PCS_OK;
+}
+
+pcs_status pcs_get_state(pcs_sim* sim, double* host, size_t n) {
+  if (!sim) return PCS_ERR_ARG;
+  return member_get_state(sim->m(), sim->b.s, host, n);
+}
+
+pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
+  if (!sim || !host || n != sim->m()->nstate) return PCS_ERR_ARG;
   for (size_t i = 0; i < 3; ++i)
     if (!std::isfinite(host[i])) return PCS_ERR_ARG;
+  Member* m = sim->m();
+  hipStream_t s = sim->b.s;
   DevScalars sc{};
   sc.step = (long long)host[0];
   sc.t = host[1];
   sc.pi = host[2];
-  HIPCHK(hipMemcpyAsync(m->state, host + 4, (n - 4) * sizeof(double), hipMemcpyHostToDevice, m->s));
-  HIPCHK(hipMemcpyAsync(m->sc, &sc, sizeof(sc), hipMemcpyHostToDevice, m->s));
-  HIPCHK(hipStreamSynchronize(m->s));
+  HIPCHK(hipMemcpyAsync(m->state, host + 4, (n - 4) * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(m->sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
   m->drained = sc.step;
   m->blowup = 0;
   return PCS_OK;
 }
 
-pcs_status pcs_stage_times(pcs_sim* m, int32_t nsteps, double* ms, int32_t nstage) {
-  if (!m || nsteps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
-  if (m->blowup) return PCS_ERR_STATE;
+pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, double* ms, int32_t nstage) {
+  if (!sim || nsteps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
+  if (sim->m()->blowup) return PCS_ERR_STATE;
+  Batch* b = &sim->b;
   hipEvent_t ev[ST_COUNT + 1];
   for (int i = 0; i <= ST_COUNT; ++i) HIPCHK(hipEventCreate(&ev[i]));
   std::vector<double> acc(ST_COUNT, 0.0);
   pcs_status st = PCS_OK;
   for (int k = 0; k < nsteps && st == PCS_OK; ++k) {
-    enqueue_step(m, [&](int i) { (void)hipEventRecord(ev[i], m->s); });
+    enqueue_step(b, [&](int i) { (void)hipEventRecord(ev[i], b->s); });
     if (hipEventSynchronize(ev[ST_COUNT]) != hipSuccess) {
       st = PCS_ERR_DEVICE;
       break;
@@ -1049,11 +1327,65 @@ pcs_status pcs_stage_times(pcs_sim* m, int32_t nsteps, double* ms, int32_t nstag
 
 const char* pcs_stage_name(int32_t i) { return (i >= 0 && i < ST_COUNT) ? STAGE_NAMES[i] : nullptr; }
 
-pcs_status pcs_destroy(pcs_sim* m) {
-  if (!m) return PCS_ERR_ARG;
-  if (m->s) (void)hipStreamSynchronize(m->s);
-  else (void)hipDeviceSynchronize();
-  delete m;
+pcs_status pcs_destroy(pcs_sim* sim) {
+  if (!sim) return PCS_ERR_ARG;
+  if (sim->b.s)
+    (void)hipStreamSynchronize(sim->b.s);
+  else
+    (void)hipDeviceSynchronize();
+  delete sim;
+  return PCS_OK;
+}
+
+pcs_status pcs_ensemble_workspace_bytes(int32_t n, const pcs_grid* grids, const pcs_params* params, size_t* bytes) {
+  if (!bytes) return PCS_ERR_ARG;
+  Batch b;
+  return setup_batch(&b, n, grids, params, bytes);
+}
+
+pcs_status pcs_ensemble_init(int32_t n, const pcs_grid* grids, const pcs_params* params, const uint64_t* seeds,
+                             double amp, void* workspace, size_t bytes, void* stream, pcs_ens** out) {
+  if (!out) return PCS_ERR_ARG;
+  *out = nullptr;
+  pcs_ens* e = new (std::nothrow) pcs_ens();
+  if (!e) return PCS_ERR_ARG;
+  const pcs_status st = init_batch(&e->b, n, grids, params, seeds, amp, workspace, bytes, stream);
+  if (st != PCS_OK) {
+    delete e;
+    return st;
+  }
+  *out = e;
+  return PCS_OK;
+}
+
+pcs_status pcs_ensemble_step(pcs_ens* e, int32_t nsteps) {
+  if (!e || nsteps < 0) return PCS_ERR_ARG;
+  return step_batch(&e->b, nsteps);
+}
+
+pcs_status pcs_ensemble_diagnostics(pcs_ens* e, int32_t run, pcs_diag* outp, int32_t max, int32_t* n_out) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  return member_diagnostics(e->b.mem[run], e->b.s, outp, max, n_out);
+}
+
+pcs_status pcs_ensemble_state_size(pcs_ens* e, int32_t run, size_t* n) {
+  if (!e || !n || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  *n = e->b.mem[run]->nstate;
+  return PCS_OK;
+}
+
+pcs_status pcs_ensemble_get_state(pcs_ens* e, int32_t run, double* host, size_t n) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  return member_get_state(e->b.mem[run], e->b.s, host, n);
+}
+
+pcs_status pcs_ensemble_destroy(pcs_ens* e) {
+  if (!e) return PCS_ERR_ARG;
+  if (e->b.s)
+    (void)hipStreamSynchronize(e->b.s);
+  else
+    (void)hipDeviceSynchronize();
+  delete e;
   return PCS_OK;
 }
 

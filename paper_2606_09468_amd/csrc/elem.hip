@@ -99,14 +99,26 @@ struct Layout {
 // then D2U (N+1) and D2W (N+1); Dc = [D c...].  smean (mixed precision
 // only) replaces S in the mean column.  Outputs: R [nsolve][N-1 rows], hvn,
 // hgn (3D), CB [nc][2 walls][cw].
-__global__ void rhs_kernel(Dims d, Phys p, const double* __restrict__ st, const double* __restrict__ D2buf,
-                           const double* __restrict__ Dc, const double* __restrict__ S,
-                           const double* __restrict__ smean, const double* __restrict__ DN,
-                           const double* __restrict__ kx, const double* __restrict__ kz,
-                           const double* __restrict__ d2i0, const double* __restrict__ d2in, double* __restrict__ R,
-                           double* __restrict__ hvn, double* __restrict__ hgn, double* __restrict__ CB) {
+__global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __restrict__ args, int nmem) {
+  const RhsArgs& A = args[member_of(args, nmem)];
+  const Dims d = A.d;
+  const Phys p = A.p;
+  const double* __restrict__ st = A.st;
+  const double* __restrict__ D2buf = A.D2buf;
+  const double* __restrict__ Dc = A.Dc;
+  const double* __restrict__ S = A.S;
+  const double* __restrict__ smean = A.smean;
+  const double* __restrict__ DN = A.DN;
+  const double* __restrict__ kx = A.kx;
+  const double* __restrict__ kz = A.kz;
+  const double* __restrict__ d2i0 = A.d2i0;
+  const double* __restrict__ d2in = A.d2in;
+  double* __restrict__ R = A.R;
+  double* __restrict__ hvn = A.hvn;
+  double* __restrict__ hgn = A.hgn;
+  double* __restrict__ CB = A.CB;
   const int n1 = d.N + 1, N = d.N, ni = d.N - 1;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = (blockIdx.x - A.blk0) * blockDim.x + threadIdx.x;
   if (e >= n1 * d.nm) return;
   const Layout L(d.dim, d.nc);
   Mode m = decode(d, e, kx, kz);
@@ -197,13 +209,8 @@ __global__ void rhs_kernel(Dims d, Phys p, const double* __restrict__ st, const 
   }
 }
 
-void launch_rhs(const Dims& d, const Phys& p, const double* state, const double* D2buf, const double* Dc,
-                const double* S, const double* smean, const double* DN, const double* kx, const double* kz,
-                const double* d2i0, const double* d2in, double* R, double* hvn, double* hgn, double* CB,
-                hipStream_t s) {
-  const int n = (d.N + 1) * d.nm;
-  hipLaunchKernelGGL(rhs_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, state, D2buf, Dc, S, smean, DN, kx, kz,
-                     d2i0, d2in, R, hvn, hgn, CB);
+void launch_rhs(const RhsArgs* args, int nmem, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(rhs_kernel, dim3(blocks), dim3(ELEM_THREADS), 0, s, args, nmem);
 }
 
 // ---------------------------------------------------------------- finalize
@@ -217,16 +224,29 @@ void launch_rhs(const Dims& d, const Phys& p, const double* state, const double*
 // Mean mode: U = U_p + Pi U_1 with Pi = (Q - w.U_p)/(w.U_1) (constant flux)
 // or Pi = dp/dx (constant drive); W = g's mean slot (then cleared).
 // infl layout: [phi1 phi2 v1 v2 Dv1 Dv2][N+1][nm], then Ainv [4][nm].
-__global__ void finalize_kernel(Dims d, Phys p, const double* __restrict__ Zphi, const double* __restrict__ Zv,
-                                const double* __restrict__ ZDv, const double* __restrict__ flux,
-                                const double* __restrict__ infl, const double* __restrict__ U1, double wU1,
-                                const double* __restrict__ CB, const double* __restrict__ hvn,
-                                const double* __restrict__ hgn, const double* __restrict__ S,
-                                const double* __restrict__ smean, const double* __restrict__ kx,
-                                const double* __restrict__ kz, double* __restrict__ st, double* __restrict__ prep,
-                                DevScalars* __restrict__ sc) {
+__global__ __launch_bounds__(ELEM_THREADS) void finalize_kernel(const FinArgs* __restrict__ args, int nmem) {
+  const FinArgs& A = args[member_of(args, nmem)];
+  const Dims d = A.d;
+  const Phys p = A.p;
+  const double* __restrict__ Zphi = A.Zphi;
+  const double* __restrict__ Zv = A.Zv;
+  const double* __restrict__ ZDv = A.ZDv;
+  const double* __restrict__ flux = A.flux;
+  const double* __restrict__ infl = A.infl;
+  const double* __restrict__ U1 = A.U1;
+  const double wU1 = A.wU1;
+  const double* __restrict__ CB = A.CB;
+  const double* __restrict__ hvn = A.hvn;
+  const double* __restrict__ hgn = A.hgn;
+  const double* __restrict__ S = A.S;
+  const double* __restrict__ smean = A.smean;
+  const double* __restrict__ kx = A.kx;
+  const double* __restrict__ kz = A.kz;
+  double* __restrict__ st = A.st;
+  double* __restrict__ prep = A.prep;
+  DevScalars* __restrict__ sc = A.sc;
   const int n1 = d.N + 1, N = d.N;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int e = (blockIdx.x - A.blk0) * blockDim.x + threadIdx.x;
   if (e >= n1 * d.nm) return;
   const Layout L(d.dim, d.nc);
   Mode m = decode(d, e, kx, kz);
@@ -314,13 +334,8 @@ __global__ void finalize_kernel(Dims d, Phys p, const double* __restrict__ Zphi,
   }
 }
 
-void launch_finalize(const Dims& d, const Phys& p, const double* Zphi, const double* Zv, const double* ZDv,
-                     const double* flux, const double* infl, const double* U1, double wU1, const double* CB,
-                     const double* hvn, const double* hgn, const double* S, const double* smean, const double* kx,
-                     const double* kz, double* state, double* prep, DevScalars* sc, hipStream_t s) {
-  const int n = (d.N + 1) * d.nm;
-  hipLaunchKernelGGL(finalize_kernel, dim3((n + 255) / 256), dim3(256), 0, s, d, p, Zphi, Zv, ZDv, flux, infl, U1,
-                     wU1, CB, hvn, hgn, S, smean, kx, kz, state, prep, sc);
+void launch_finalize(const FinArgs* args, int nmem, int blocks, hipStream_t s) {
+  hipLaunchKernelGGL(finalize_kernel, dim3(blocks), dim3(ELEM_THREADS), 0, s, args, nmem);
 }
 
 // ---------------------------------------------------------------- init: homogeneous solutions

@@ -351,16 +351,22 @@ __device__ inline void pointwise_mixed(const Rd& r, const Md& m, T* o) {
 
 // mean: [n_means][M+1] FP64 profiles (MIXED only); pz: padded z rows per y'.
 template <typename T, int DIM, bool MIXED>
-__global__ __launch_bounds__(NT) void xpencil_kernel(const T* __restrict__ in, T* __restrict__ out, int nrows,
-                                                     int nkx, FftPlan pl, const double* __restrict__ kx,
-                                                     const cx<T>* __restrict__ tw, double eps_wi,
-                                                     const double* __restrict__ mean, double* __restrict__ mcol,
-                                                     int m1, int pz) {
+__global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ args, int nmem) {
   using XS = XShape<DIM>;
+  const XArgs& XA = args[member_of(args, nmem)];
+  const T* __restrict__ in = static_cast<const T*>(XA.in);
+  T* __restrict__ out = static_cast<T*>(XA.out);
+  const int nrows = XA.nrows, nkx = XA.nkx, m1 = XA.m1, pz = XA.pz;
+  const FftPlan pl = XA.pl;
+  const double* __restrict__ kx = XA.kx;
+  const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(XA.tw);
+  const double eps_wi = XA.eps_wi;
+  const double* __restrict__ mean = XA.mean;
+  double* __restrict__ mcol = XA.mcol;
   extern __shared__ double smem_d[];
   cx<T>* P = reinterpret_cast<cx<T>*>(smem_d);
   const int L = pl.L;
-  const int row = blockIdx.x, tid = threadIdx.x;
+  const int row = blockIdx.x - XA.blk0, tid = threadIdx.x;
   const size_t fstride = (size_t)nrows * nkx * 2;
   const T* base = in + (size_t)row * nkx * 2;
   const int S = fft_batch<T>(L);
@@ -458,21 +464,31 @@ size_t xpencil_lds(int L) {
 // inverse: kz slots (Nyquist slot skipped, optional i kz factor) are placed at
 // their own frequency in a length-Lz transform; forward: length-Lz data is
 // transformed, divided by Lz and truncated to the retained slots.
-constexpr int ZG = 16;  // kx columns per workgroup
+constexpr int ZG = ZFFT_GROUP;
 
 template <typename T>
-__global__ __launch_bounds__(NT) void zfft_kernel(const T* __restrict__ in, T* __restrict__ out, int nkx, int nzs,
-                                                  int rows_y, FftPlan pl, const int* __restrict__ src_field,
-                                                  const int* __restrict__ deriv, const double* __restrict__ kz,
-                                                  const cx<T>* __restrict__ tw, int inverse,
-                                                  const double* __restrict__ mean, double* __restrict__ mcol) {
+__global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args, int nmem) {
   typedef cx<T> c2;
+  const ZArgs& ZA = args[member_of(args, nmem)];
+  const T* __restrict__ in = static_cast<const T*>(ZA.in);
+  T* __restrict__ out = static_cast<T*>(ZA.out);
+  const int nkx = ZA.nkx, nzs = ZA.nzs, rows_y = ZA.rows, inverse = ZA.inverse;
+  const FftPlan pl = ZA.pl;
+  const int* __restrict__ src_field = ZA.src_field;
+  const int* __restrict__ deriv = ZA.deriv;
+  const double* __restrict__ kz = ZA.kz;
+  const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(ZA.tw);
+  const double* __restrict__ mean = ZA.mean;
+  double* __restrict__ mcol = ZA.mcol;
   extern __shared__ double smem_z[];
   c2* A = reinterpret_cast<c2*>(smem_z);
   const int L = pl.L;
   c2* twl = A + (size_t)ZG * L;  // twiddle table behind the data
   for (int e = threadIdx.x; e < L; e += NT) twl[e] = tw[e];
-  const int k0 = blockIdx.x * ZG, i = blockIdx.y, f = blockIdx.z;
+  // local workgroup -> (kx group, row, field)
+  const int lb = blockIdx.x - ZA.blk0;
+  const int gx = lb % ZA.ngx, i = (lb / ZA.ngx) % rows_y, f = lb / (ZA.ngx * rows_y);
+  const int k0 = gx * ZG;
   const int ng = min(ZG, nkx - k0);
   const int tid = threadIdx.x;
   const int rin = inverse ? nzs : L, rout = inverse ? L : nzs;
@@ -556,16 +572,22 @@ __device__ inline int wave_or(int v) {
   return v;
 }
 
-__global__ __launch_bounds__(NT) void diag_rows_kernel(Dims d, const double* __restrict__ in, int zrows, FftPlan pl,
-                                                       const c2* __restrict__ tw, const double* __restrict__ ydy,
-                                                       DiagPart* __restrict__ parts) {
+__global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restrict__ args, int nmem) {
+  const DRowArgs& DA = args[member_of(args, nmem)];
+  const Dims d = DA.d;
+  const double* __restrict__ in = DA.in;
+  const int zrows = DA.zrows;
+  const FftPlan pl = DA.pl;
+  const c2* __restrict__ tw = reinterpret_cast<const c2*>(DA.tw);
+  const double* __restrict__ ydy = DA.ydy;
+  DiagPart* __restrict__ parts = DA.parts;
   extern __shared__ double smem_g[];
   c2* A = reinterpret_cast<c2*>(smem_g);
   __shared__ DiagPart wpart[NT / 64];
   const int L = pl.L, nkx = d.nkx;
   c2* twl = A + 2 * (size_t)L;  // twiddle table behind the data
   for (int e = threadIdx.x; e < L; e += NT) twl[e] = tw[e];
-  const int row = blockIdx.x, tid = threadIdx.x;
+  const int row = blockIdx.x - DA.blk0, tid = threadIdx.x;
   const int nrows = (d.N + 1) * zrows;
   const int j = row / zrows;
   const size_t fstride = (size_t)nrows * nkx * 2;
@@ -642,10 +664,16 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(Dims d, const double* __r
   }
 }
 
-__global__ __launch_bounds__(NT) void diag_final_kernel(Dims d, Phys p, const DiagPart* __restrict__ parts,
-                                                        int zrows, const double* __restrict__ w,
-                                                        DevScalars* __restrict__ sc, DiagRec* __restrict__ ring,
-                                                        int cap) {
+// one workgroup per member
+__global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restrict__ args) {
+  const DFinArgs& FA = args[blockIdx.x];
+  const Dims d = FA.d;
+  const Phys p = FA.p;
+  const DiagPart* __restrict__ parts = FA.parts;
+  const int zrows = FA.zrows, cap = FA.cap;
+  const double* __restrict__ w = FA.w;
+  DevScalars* __restrict__ sc = FA.sc;
+  DiagRec* __restrict__ ring = FA.ring;
   __shared__ double smin[NT], smmin[NT], scfl[NT], se[NT], st_[NT];
   __shared__ unsigned long long s3[NT], s0[NT], sm3[NT], sm0[NT];
   __shared__ int sb[NT];
@@ -725,65 +753,47 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(Dims d, Phys p, const Di
 
 }  // namespace
 
-void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const void* in, void* out, const double* kx,
-                    const void* tw, int precision, const double* mean, double* mcol, hipStream_t s) {
-  const int rows = (d.M + 1) * d.pz;
-  const int m1 = d.M + 1;
+void launch_xpencil(int dim, int precision, const XArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
+  if (blocks <= 0) return;
   if (precision == 0) {
-    if (d.dim == 2)
-      hipLaunchKernelGGL((xpencil_kernel<double, 2, false>), dim3(rows), dim3(NT), (xpencil_lds<double, 2>(plan.L)), s,
-                         (const double*)in, (double*)out, rows, d.nkx, plan, kx, (const cx<double>*)tw, p.eps / p.wi,
-                         nullptr, nullptr, m1, d.pz);
+    if (dim == 2)
+      hipLaunchKernelGGL((xpencil_kernel<double, 2, false>), dim3(blocks), dim3(NT), lds, s, args, nmem);
     else
-      hipLaunchKernelGGL((xpencil_kernel<double, 3, false>), dim3(rows), dim3(NT), (xpencil_lds<double, 3>(plan.L)), s,
-                         (const double*)in, (double*)out, rows, d.nkx, plan, kx, (const cx<double>*)tw, p.eps / p.wi,
-                         nullptr, nullptr, m1, d.pz);
+      hipLaunchKernelGGL((xpencil_kernel<double, 3, false>), dim3(blocks), dim3(NT), lds, s, args, nmem);
   } else {
-    if (d.dim == 2)
-      hipLaunchKernelGGL((xpencil_kernel<float, 2, true>), dim3(rows), dim3(NT), (xpencil_lds<float, 2>(plan.L)), s,
-                         (const float*)in, (float*)out, rows, d.nkx, plan, kx, (const cx<float>*)tw, 0.0, mean, mcol,
-                         m1, d.pz);
+    if (dim == 2)
+      hipLaunchKernelGGL((xpencil_kernel<float, 2, true>), dim3(blocks), dim3(NT), lds, s, args, nmem);
     else
-      hipLaunchKernelGGL((xpencil_kernel<float, 3, true>), dim3(rows), dim3(NT), (xpencil_lds<float, 3>(plan.L)), s,
-                         (const float*)in, (float*)out, rows, d.nkx, plan, kx, (const cx<float>*)tw, 0.0, mean,
-                         nullptr, m1, d.pz);
+      hipLaunchKernelGGL((xpencil_kernel<float, 3, true>), dim3(blocks), dim3(NT), lds, s, args, nmem);
   }
 }
 
-void launch_zfft(const Dims& d, const FftPlan& plan, const void* in, void* out, int nfields, const int* src_field,
-                 const int* deriv, const double* kz, const void* tw, int inverse, int rows, int precision,
-                 const double* mean, double* mcol, hipStream_t s) {
-  dim3 grid((d.nkx + ZG - 1) / ZG, rows, nfields);
-  if (precision == 0) {
-    const size_t lds = (size_t)(ZG + 1) * plan.L * sizeof(cx<double>);
-    hipLaunchKernelGGL(zfft_kernel<double>, grid, dim3(NT), lds, s, (const double*)in, (double*)out, d.nkx, d.nzs, rows,
-                       plan, src_field, deriv, kz, (const cx<double>*)tw, inverse, nullptr, nullptr);
-  } else {
-    const size_t lds = (size_t)(ZG + 1) * plan.L * sizeof(cx<float>);
-    hipLaunchKernelGGL(zfft_kernel<float>, grid, dim3(NT), lds, s, (const float*)in, (float*)out, d.nkx, d.nzs, rows,
-                       plan, src_field, deriv, kz, (const cx<float>*)tw, inverse, mean, inverse ? nullptr : mcol);
-  }
+int xpencil_blocks(const Dims& d) { return (d.M + 1) * d.pz; }
+
+void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
+  if (blocks <= 0) return;
+  if (precision == 0)
+    hipLaunchKernelGGL(zfft_kernel<double>, dim3(blocks), dim3(NT), lds, s, args, nmem);
+  else
+    hipLaunchKernelGGL(zfft_kernel<float>, dim3(blocks), dim3(NT), lds, s, args, nmem);
 }
 
-void launch_diag_rows(const Dims& d, const FftPlan& planx, const double* prep, double* zbuf, const FftPlan& planz,
-                      const double* twx, const double* twz, const double* ydy, DiagPart* parts, hipStream_t s) {
-  const int n1 = d.N + 1;
-  const double* src = prep;
-  int zrows = 1;
-  if (d.dim == 3) {
-    launch_zfft(d, planz, prep, zbuf, 4, nullptr, nullptr, nullptr, twz, 1, n1, 0, nullptr, nullptr, s);
-    src = zbuf;
-    zrows = d.nz;
-  }
-  const size_t lds = 3 * (size_t)planx.L * sizeof(c2);
-  hipLaunchKernelGGL(diag_rows_kernel, dim3(n1 * zrows), dim3(NT), lds, s, d, src, zrows, planx,
-                     reinterpret_cast<const c2*>(twx), ydy, parts);
+int zfft_blocks(int nkx, int rows, int nfields) { return ((nkx + ZG - 1) / ZG) * rows * nfields; }
+
+size_t zfft_lds_bytes(int L, int precision) {
+  return (size_t)(ZG + 1) * L * (precision == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
 }
 
-void launch_diag_final(const Dims& d, const Phys& p, const DiagPart* parts, const double* w, DevScalars* sc,
-                       DiagRec* ring, int ring_cap, hipStream_t s) {
-  const int zrows = d.dim == 3 ? d.nz : 1;
-  hipLaunchKernelGGL(diag_final_kernel, dim3(1), dim3(NT), 0, s, d, p, parts, zrows, w, sc, ring, ring_cap);
+void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(diag_rows_kernel, dim3(blocks), dim3(NT), lds, s, args, nmem);
+}
+
+size_t diag_rows_lds_bytes(int L) { return 3 * (size_t)L * sizeof(c2); }
+
+void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s) {
+  if (nmem <= 0) return;
+  hipLaunchKernelGGL(diag_final_kernel, dim3(nmem), dim3(NT), 0, s, args);
 }
 
 hipError_t fft_set_attributes() {

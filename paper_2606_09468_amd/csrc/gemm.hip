@@ -113,10 +113,18 @@ __device__ inline int xcd_tile(int b, int total) {
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
+// Job of logical tile t: the last job whose first tile is <= t (binary
+// search; a batch of simulations puts hundreds of jobs in one table).
 __device__ inline int find_job(const GemmJob* __restrict__ jobs, int njobs, int t) {
-  int jb = 0;
-  while (jb + 1 < njobs && jobs[jb + 1].tile0 <= t) ++jb;
-  return jb;
+  int lo = 0, hi = njobs - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (jobs[mid].tile0 <= t)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
 }
 
 // Inverse Helmholtz symbol of kind `kind` for eigenvalue lam and wavenumber

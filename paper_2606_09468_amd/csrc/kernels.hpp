@@ -114,36 +114,125 @@ struct DiagPart {
   int nonfinite, big;
 };
 
-// ---- launchers (fft.hip)
-// precision 0: FP64 buffers and products; otherwise FP32 buffers, the mixed
-// mean/fluctuation products and `mean` = [n_means][M+1] FP64 profiles.
-void launch_xpencil(const Dims& d, const Phys& p, const FftPlan& plan, const void* in, void* out, const double* kx,
-                    const void* tw, int precision, const double* mean, double* mcol, hipStream_t s);
-// mcol (mixed forward only, else null): [nfields][rows] FP64 kx = kz = 0 column
-// of the output plus the product of the mean profiles `mean`.
-void launch_zfft(const Dims& d, const FftPlan& plan, const void* in, void* out, int nfields, const int* src_field,
-                 const int* deriv, const double* kz, const void* tw, int inverse, int rows, int precision,
-                 const double* mean, double* mcol, hipStream_t s);
-// prep: [4][N+1][kz][kx] spectral Tr c, u, v, w written by the finalize kernel
-void launch_diag_rows(const Dims& d, const FftPlan& planx, const double* prep, double* zbuf, const FftPlan& planz,
-                      const double* twx, const double* twz, const double* ydy, DiagPart* parts, hipStream_t s);
-void launch_diag_final(const Dims& d, const Phys& p, const DiagPart* parts, const double* w, DevScalars* sc,
-                       DiagRec* ring, int ring_cap, hipStream_t s);
+// ---- batched stage kernels
+// Every stage kernel of the step takes a device table of per-member argument
+// blocks (one block per simulation of a batch: a single run is a batch of
+// one) and the member count.  blk0 is the first workgroup of the member in
+// the launch; a workgroup finds its member by binary search, so members of
+// different sizes share one launch (a ragged work list).
+
+// x pencils (fft.hip).  Real FP64 buffers, or FP32 with the mixed
+// mean/fluctuation products (mean = [n_means][M+1] FP64 profiles); in mixed
+// 2D, mcol receives the FP64-completed kx = 0 column of each output.
+struct XArgs {
+  const void* in;
+  void* out;
+  int nrows, nkx, m1, pz;
+  FftPlan pl;
+  const double* kx;
+  const void* tw;
+  double eps_wi;
+  const double* mean;
+  double* mcol;
+  int blk0;
+};
+// z columns (fft.hip): workgroups (kx group, row, field) flattened; the
+// forward mixed transform writes the FP64-completed kx = kz = 0 value of each
+// output into mcol ([nfields][rows]) using the mean profiles.
+struct ZArgs {
+  const void* in;
+  void* out;
+  int nkx, nzs, rows, nfields, ngx, inverse;
+  FftPlan pl;
+  const int* src_field;
+  const int* deriv;
+  const double* kz;
+  const void* tw;
+  const double* mean;
+  double* mcol;
+  int blk0;
+};
+// diagnostics (fft.hip): per (y_j, z) line of the base grid, from the
+// spectral Tr c, u, v, w (in: [4][N+1][zrows][kx]), then one workgroup per
+// member for the step record.
+struct DRowArgs {
+  Dims d;
+  const double* in;
+  int zrows;
+  FftPlan pl;
+  const double* tw;
+  const double* ydy;
+  DiagPart* parts;
+  int blk0;
+};
+struct DFinArgs {
+  Dims d;
+  Phys p;
+  const DiagPart* parts;
+  int zrows;
+  const double* w;
+  DevScalars* sc;
+  DiagRec* ring;
+  int cap;
+};
+// explicit assembly and CNAB2 right-hand sides (elem.hip); smean: mixed
+// path only, [nout][N+1] FP64 projection of the kx = kz = 0 column of the
+// explicit terms (null in FP64, where S holds it).
+struct RhsArgs {
+  Dims d;
+  Phys p;
+  const double *st, *D2buf, *Dc, *S, *smean, *DN, *kx, *kz, *d2i0, *d2in;
+  double *R, *hvn, *hgn, *CB;
+  int blk0;
+};
+// influence correction, flux, velocities, wall rows, history, diagnostics
+// inputs (elem.hip)
+struct FinArgs {
+  Dims d;
+  Phys p;
+  const double *Zphi, *Zv, *ZDv, *flux, *infl, *U1;
+  double wU1;
+  const double *CB, *hvn, *hgn, *S, *smean, *kx, *kz;
+  double *st, *prep;
+  DevScalars* sc;
+  int blk0;
+};
+
+// Member of the current workgroup: the last m with args[m].blk0 <= blockIdx.x.
+template <typename Args>
+__device__ inline int member_of(const Args* __restrict__ a, int nmem) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = nmem - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (a[mid].blk0 <= b)
+      lo = mid;
+    else
+      hi = mid - 1;
+  }
+  return lo;
+}
+
+// precision 0: FP64; otherwise FP32 with the mixed products.  lds: dynamic
+// LDS bytes (the largest member's need).
+void launch_xpencil(int dim, int precision, const XArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
+void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
+void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
+void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s);
+void launch_rhs(const RhsArgs* args, int nmem, int blocks, hipStream_t s);
+void launch_finalize(const FinArgs* args, int nmem, int blocks, hipStream_t s);
+// workgroups and dynamic LDS of one member's launch
+int xpencil_blocks(const Dims& d);
+size_t xpencil_lds_bytes(int dim, int L, int precision);
+int zfft_blocks(int nkx, int rows, int nfields);
+size_t zfft_lds_bytes(int L, int precision);
+size_t diag_rows_lds_bytes(int L);
+constexpr int ELEM_THREADS = 256;
+constexpr int ZFFT_GROUP = 16;  // kx columns per workgroup of the z transforms
 // Raises the dynamic-LDS limit of the transform kernels (call once, outside capture).
 hipError_t fft_set_attributes();
-size_t xpencil_lds_bytes(int dim, int L, int precision);
 
-// ---- launchers (elem.hip)
-// smean: mixed path only, [nout][N+1] FP64 projection of the kx = kz = 0
-// column of the explicit terms (null in FP64, where S holds it).
-void launch_rhs(const Dims& d, const Phys& p, const double* state, const double* D2buf, const double* Dc,
-                const double* S, const double* smean, const double* DN, const double* kx, const double* kz,
-                const double* d2i0, const double* d2in, double* R, double* hvn, double* hgn, double* CB,
-                hipStream_t s);
-void launch_finalize(const Dims& d, const Phys& p, const double* Zphi, const double* Zv, const double* ZDv,
-                     const double* flux, const double* infl, const double* U1, double wU1, const double* CB,
-                     const double* hvn, const double* hgn, const double* S, const double* smean, const double* kx,
-                     const double* kz, double* state, double* prep, DevScalars* sc, hipStream_t s);
+// ---- init-time kernels (elem.hip), one simulation at a time
 void launch_homog_rhs(const Dims& d, const Phys& p, const double* d2i0, const double* d2in, double* R,
                       hipStream_t s);
 void launch_influence(const Dims& d, const double* Zphi, const double* Zv, const double* ZDv, const double* kz,

@@ -1,0 +1,126 @@
+"""Ensembles of uneven-size runs (one graph launch per step, every stage one
+kernel over all runs) against the FP64 oracle, run by run.
+
+Each member is compared with its own oracle run from the same seeded
+initial state, with the single-run tolerances (FP64) or the mixed-precision
+bar; the per-step diagnostic records of every member are checked too, so a
+member reading another member's data or sizes would fail here.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import Grid, Oracle, Params
+from paper_2606_09468_amd.workloads import ensemble_members
+from tests.test_gpu_parity import check_diag, check_state, fluct_errors, tol_history, tol_prognostic
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def P():
+    import os
+
+    import torch
+
+    import paper_2606_09468_amd as P
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    if not os.path.exists(P.LIBPATH):
+        from paper_2606_09468_amd import build
+        build.build()
+    return P
+
+
+def build(P, members, precision, dt=1e-3):
+    grids = [P.make_grid(2, nx, ny) for ny, nx, _, _ in members]
+    params = [P.make_params(wi=wi, dt=dt, precision=precision) for _, _, wi, _ in members]
+    return P.Ensemble(grids, params, [s for _, _, _, s in members], amp=1e-3)
+
+
+SMALL = ensemble_members(count=6, seed=4, ny_choices=(17, 25, 33), nx_choices=(12, 16, 24, 32))
+
+
+def test_fp64_ensemble_members_match_oracle(P):
+    nsteps = 12
+    print("case fp64 ensemble", SMALL, flush=True)
+    ens = build(P, SMALL, 0)
+    ens.step(nsteps)
+    for r, (ny, nx, wi, seed) in enumerate(SMALL):
+        g = Grid(2, nx, ny)
+        o = Oracle(g, Params(wi=wi, dt=1e-3), seed=seed, amp=1e-3)
+        o.step(nsteps)
+        recs, st = ens.diagnostics(r)
+        assert st == P.PCS_OK and len(recs) == nsteps
+        name = "member %d %dx%d Wi%.1f" % (r, nx, ny, wi)
+        check_state(ens.get_state(r), o.get_state(), g, tol_prognostic(ny - 1), tol_history(ny - 1), name)
+        check_diag(recs, o, o.trace_c(), name)
+        for rec, e in zip(recs, o.diag):
+            assert rec["step"] == e["step"] and rec["n_lt3"] == e["n_lt3"] and rec["n_lt0"] == e["n_lt0"]
+    ens.close()
+
+
+def test_mixed_ensemble_members_match_oracle(P):
+    """Mixed-precision members against the FP64 oracle with the single-run
+    mixed bar (fluctuation 2e-4 of its max, full fields 2e-5)."""
+    nsteps = 20
+    members = SMALL[:4]
+    print("case mixed ensemble", members, flush=True)
+    ens = build(P, members, 1)
+    ens.step(nsteps)
+    for r, (ny, nx, wi, seed) in enumerate(members):
+        g = Grid(2, nx, ny)
+        o = Oracle(g, Params(wi=wi, dt=1e-3), seed=seed, amp=1e-3)
+        o.step(nsteps)
+        errs = fluct_errors(ens.get_state(r), o.get_state(), g)
+        print("member", r, {k: "%.1e/%.1e" % v for k, v in errs.items()}, flush=True)
+        for name in ("u", "v", "phi", "cxx", "cxy", "cyy"):
+            fl, full = errs[name]
+            assert fl < 2e-4 and full < 2e-5, (r, name, fl, full)
+    ens.close()
+
+
+def test_ensemble_equals_single_runs(P):
+    """A member advances exactly as the same run on its own would, up to the
+    summation order the tile tuner picks for the merged product tables."""
+    nsteps = 8
+    members = SMALL[:3]
+    ens = build(P, members, 0)
+    ens.step(nsteps)
+    for r, (ny, nx, wi, seed) in enumerate(members):
+        sim = P.Sim(P.make_grid(2, nx, ny), P.make_params(wi=wi, dt=1e-3), seed=seed, amp=1e-3)
+        sim.step(nsteps)
+        a, b = ens.get_state(r), sim.get_state()
+        sim.close()
+        scale = np.abs(b).max()
+        assert np.abs(a - b).max() <= 1e-12 * scale, (r, np.abs(a - b).max() / scale)
+    ens.close()
+
+
+def test_full_size_ensemble_sampled_members(P):
+    """The 64-member uneven ensemble (mixed precision) for a few steps; the
+    two smallest members are checked against the oracle, and every member's
+    records must be finite with the step count advanced."""
+    members = ensemble_members()
+    nsteps = 5
+    print("case full ensemble 64 members", flush=True)
+    grids = [P.make_grid(2, nx, ny) for ny, nx, _, _ in members]
+    params = [P.make_params(wi=wi, dt=5e-4, precision=1) for _, _, wi, _ in members]
+    ens = P.Ensemble(grids, params, [s for _, _, _, s in members], amp=1e-3)
+    ens.step(nsteps)
+    for r in range(len(members)):
+        recs, st = ens.diagnostics(r)
+        assert st == P.PCS_OK and len(recs) == nsteps and recs[-1]["step"] == nsteps
+        assert np.isfinite(recs[-1]["min_trc"]) and recs[-1]["blowup"] == 0
+    order = sorted(range(len(members)), key=lambda r: members[r][0] * members[r][1])[:2]
+    for r in order:
+        ny, nx, wi, seed = members[r]
+        g = Grid(2, nx, ny)
+        o = Oracle(g, Params(wi=wi, dt=5e-4), seed=seed, amp=1e-3)
+        o.step(nsteps)
+        errs = fluct_errors(ens.get_state(r), o.get_state(), g)
+        print("member", r, nx, ny, {k: "%.1e/%.1e" % v for k, v in errs.items()}, flush=True)
+        for name in ("u", "v", "phi", "cxx", "cxy", "cyy"):
+            fl, full = errs[name]
+            assert fl < 2e-4 and full < 2e-5, (r, name, fl, full)
+    ens.close()
