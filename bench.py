@@ -23,20 +23,7 @@ HBM_PEAK_GBS = 8000.0
 MFMA_F64_TFS = 78.6
 MFMA_F32_TFS = 157.3
 
-WORKLOADS = {
-    "c2": dict(desc="2D channel Oldroyd-B, Lx=10, Nx=256, Ny=257, Re=0.01, Wi=50, beta=0.8, kappa=5e-5, "
-                    "constant flux, CNAB2 dt=5e-4, seeded perturbation amp 1e-3 (seed 2)",
-               dim=2, nx=256, ny=257, nz=1, lz=5.0, wi=50.0, dt=5e-4, seed=2),
-    "c1": dict(desc="2D channel Oldroyd-B, Lx=10, Nx=64, Ny=65, Re=0.01, Wi=20, beta=0.8, kappa=5e-5, "
-                    "constant flux, CNAB2 dt=1e-3, seeded perturbation amp 1e-3 (seed 1)",
-               dim=2, nx=64, ny=65, nz=1, lz=5.0, wi=20.0, dt=1e-3, seed=1),
-    "c3": dict(desc="3D channel Oldroyd-B, Lx=10, Lz=5, Nx=128, Ny=129, Nz=64, Re=0.01, Wi=50, beta=0.8, "
-                    "kappa=5e-5, constant flux, CNAB2 dt=5e-4, seeded perturbation amp 1e-3 (seed 3)",
-               dim=3, nx=128, ny=129, nz=64, lz=5.0, wi=50.0, dt=5e-4, seed=3),
-    "c5": dict(desc="3D channel Oldroyd-B, Lx=10, Lz=5, Nx=256, Ny=257, Nz=128, Re=0.01, Wi=100, beta=0.8, "
-                    "kappa=5e-5, constant flux, CNAB2 dt=2.5e-4, seeded perturbation amp 1e-3 (seed 5)",
-               dim=3, nx=256, ny=257, nz=128, lz=5.0, wi=100.0, dt=2.5e-4, seed=5),
-}
+from paper_2606_09468_amd.workloads import ENSEMBLE, WORKLOADS, ensemble_members  # noqa: E402
 
 
 def stage_work(w, prec_bytes=16):
@@ -112,7 +99,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2000)
     ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"],
+                    help="c4: the 64-member uneven 2D ensemble, one graph launch per step")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed", "mixed64y"],
                     help="both: time mixed (value) and FP64 (reported beside it)")
     ap.add_argument("--stage-steps", type=int, default=50)
@@ -131,6 +119,8 @@ def main():
     if not os.path.exists(P.LIBPATH):
         from paper_2606_09468_amd import build
         build.build()
+    if args.workload == "c4":
+        return bench_ensemble(args, P)
     w = WORKLOADS[args.workload]
     grid = P.make_grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
     precs = {"both": [1, 0], "fp64": [0], "mixed": [1], "mixed64y": [2]}[args.precision]
@@ -211,6 +201,72 @@ def main():
                 "min_trc_abs": abs(d["min_trc"] - e["min_trc"]),
                 "counts_equal": all(d[k] == e[k] for k in ("n_lt3", "n_lt0", "mid_n_lt3", "mid_n_lt0")),
             }
+    print(json.dumps(line), flush=True)
+
+
+def ensemble_cpu_baseline(members, dt, steps=2):
+    """Oracle seconds per ensemble step: each distinct member size is timed
+    over `steps` steps after one warm-up step, and the members are summed."""
+    from threadpoolctl import threadpool_info
+
+    from oracle import Grid, Oracle, Params
+    per = {}
+    t_all = time.perf_counter()
+    for ny, nx, wi, seed in members:
+        if (ny, nx) in per:
+            continue
+        o = Oracle(Grid(2, nx, ny), Params(wi=wi, dt=dt), seed=seed, amp=1e-3)
+        o.step(1)
+        t0 = time.perf_counter()
+        o.step(steps)
+        per[(ny, nx)] = (time.perf_counter() - t0) / steps
+    total = sum(per[(ny, nx)] for ny, nx, _, _ in members)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
+    return dict(value=1.0 / total, unit="steps/s", cores=threads, kind="oracle",
+                sample="each of the %d distinct member sizes timed over %d oracle steps after a warm-up step "
+                       "(%.1f s in all), summed over the %d members" % (len(per), steps,
+                                                                        time.perf_counter() - t_all, len(members)))
+
+
+def bench_ensemble(args, P):
+    """The uneven 64-member ensemble: steps/s of the whole ensemble (every
+    member advanced one step per graph launch) and summed point updates."""
+    import torch
+    members = ensemble_members(ENSEMBLE["count"], ENSEMBLE["seed"])
+    prec = {"both": 1, "fp64": 0, "mixed": 1, "mixed64y": 2}[args.precision]
+    grids = [P.make_grid(2, nx, ny) for ny, nx, _, _ in members]
+    params = [P.make_params(wi=wi, dt=ENSEMBLE["dt"], precision=prec) for _, _, wi, _ in members]
+    ens = P.Ensemble(grids, params, [s for _, _, _, s in members], amp=1e-3)
+    print("bench: ensemble of %d, precision %d, warmup %d" % (len(members), prec, args.warmup),
+          file=sys.stderr, flush=True)
+    ens.step(args.warmup)
+    ens.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record(ens.stream)
+    ens.step(args.steps)
+    ev1.record(ens.stream)
+    ev1.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    for r in range(len(members)):
+        recs, st = ens.diagnostics(r)
+        assert st == P.PCS_OK and recs[-1]["step"] == args.warmup + args.steps and recs[-1]["blowup"] == 0
+    ens.close()
+    sps = args.steps / (ms / 1e3)
+    points = sum(nx * ny for ny, nx, _, _ in members)
+    line = {
+        "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64"}[prec], "data": "synthetic",
+        "config": {"workload": ENSEMBLE["desc"], "members": len(members), "base_points": points,
+                   "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms"}[prec],
+                   "parallelism": "single GPU, one graph launch per ensemble step"},
+        "grid_point_updates_per_s": sps * points,
+        "roofline": None,
+    }
+    if not args.no_cpu_baseline:
+        line["cpu_baseline"] = ensemble_cpu_baseline(members, ENSEMBLE["dt"])
     print(json.dumps(line), flush=True)
 
 

@@ -23,37 +23,86 @@
 namespace pcs {
 
 bool make_plan(int L, FftPlan* p) {
+  *p = FftPlan{};
   p->L = L;
-  p->npass = 0;
   int r = L;
-  while (r % 4 == 0 && p->npass < 12) {
-    p->radix[p->npass++] = 4;
-    r /= 4;
+  auto take = [&](int R) {
+    while (r % R == 0 && p->npass < 12) {
+      p->radix[p->npass++] = R;
+      r /= R;
+    }
+  };
+  take(8);
+  take(4);
+  take(2);
+  take(3);
+  if (r != 1 || L < 2) return false;
+  int ns = 1;
+  for (int i = 0; i < p->npass; ++i) {
+    const int R = p->radix[i];
+    p->lr[i] = L / R;
+    p->ns[i] = ns;
+    p->ts[i] = L / (ns * R);
+    p->mlr[i] = fast_div_magic((unsigned)p->lr[i]);
+    p->mns[i] = fast_div_magic((unsigned)ns);
+    ns *= R;
   }
-  while (r % 2 == 0 && p->npass < 12) {
-    p->radix[p->npass++] = 2;
-    r /= 2;
-  }
-  while (r % 3 == 0 && p->npass < 12) {
-    p->radix[p->npass++] = 3;
-    r /= 3;
-  }
-  return r == 1 && L >= 2;
+  return true;
 }
 
 namespace {
 
 constexpr int NT = 256;  // threads per workgroup of the transform kernels
 
-// complex values a thread holds in one pass (24 doubles' worth of registers)
+// complex values a thread holds in one pass, and the largest multiple of
+// every radix that fits (the elements per thread any pass can cover)
 template <typename T>
 __host__ __device__ constexpr int maxv() {
-  return 12;
+  return sizeof(T) == 4 ? 24 : 16;
 }
+__host__ __device__ constexpr int cover(int mv) {
+  const int c8 = (mv / 8) * 8, c4 = (mv / 4) * 4, c2 = (mv / 2) * 2, c3 = (mv / 3) * 3;
+  const int a = c8 < c4 ? c8 : c4, b = c2 < c3 ? c2 : c3;
+  return a < b ? a : b;
+}
+
+// floor(n / d) from a multiply-high reciprocal (m = 0 encodes d = 1)
+__device__ inline int fdiv(int n, unsigned m) { return m ? (int)__umulhi((unsigned)n, m) : n; }
 
 template <typename T>
 struct cx {
   T x, y;
+};
+template <typename T>
+struct V2 {
+  typedef T type __attribute__((ext_vector_type(2)));
+};
+
+// LDS view of the transform buffers.  FP64: logical element p lives at
+// p + p / 16 (one spare slot every 16 complex values), so the strided writes
+// of a Stockham pass (lanes R or R Ns elements apart) and the column-wise
+// accesses of the z transforms spread over all banks.  FP32 keeps the plain
+// layout: there the extra address arithmetic costs more registers (and
+// occupancy) than the conflicts it removes (measured on the 3D x pencils).
+template <typename T>
+__host__ __device__ constexpr size_t lds_padded(size_t n) {
+  return sizeof(T) == 4 ? n : n + (n >> 4) + 1;
+}
+// dynamic LDS of the transform kernels (indexed through the symbol, so
+// every access stays an LDS instruction)
+extern __shared__ double fft_lds[];
+template <typename T>
+struct LV {
+  int off;
+  __device__ cx<T>& operator[](int i) const {
+    cx<T>* b = reinterpret_cast<cx<T>*>(fft_lds);
+    const int q = off + i;
+    if constexpr (sizeof(T) == 4)
+      return b[q];
+    else
+      return b[q + (q >> 4)];
+  }
+  __device__ LV at(int d) const { return LV{off + d}; }
 };
 template <typename T>
 __device__ inline cx<T> operator+(cx<T> a, cx<T> b) {
@@ -86,6 +135,30 @@ __device__ inline void butterfly(cx<T>* v, int sign) {
     v[2] = a - c;
     v[1] = b + sid;
     v[3] = b - sid;
+  } else if constexpr (R == 8) {
+    // split into even and odd halves: a_q = v_q + v_(q+4) and
+    // b_q = w^q (v_q - v_(q+4)), w = exp(sign 2 pi i / 8); X_2m = DFT4(a)_m,
+    // X_2m+1 = DFT4(b)_m
+    const T h = T(0.70710678118654752440);
+    cx<T> a[4], b[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      a[q] = v[q] + v[q + 4];
+      b[q] = v[q] - v[q + 4];
+    }
+    // w^1 = h (1 + sign i), w^2 = sign i, w^3 = h (-1 + sign i)
+    b[1] = sign > 0 ? cx<T>{h * (b[1].x - b[1].y), h * (b[1].x + b[1].y)}
+                    : cx<T>{h * (b[1].x + b[1].y), h * (b[1].y - b[1].x)};
+    b[2] = sign > 0 ? cx<T>{-b[2].y, b[2].x} : cx<T>{b[2].y, -b[2].x};
+    b[3] = sign > 0 ? cx<T>{-h * (b[3].x + b[3].y), h * (b[3].x - b[3].y)}
+                    : cx<T>{h * (b[3].y - b[3].x), -h * (b[3].x + b[3].y)};
+    butterfly<T, 4>(a, sign);
+    butterfly<T, 4>(b, sign);
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      v[2 * m] = a[m];
+      v[2 * m + 1] = b[m];
+    }
   } else {
     const T h = T(0.86602540378443864676) * T(sign);  // sign * sqrt(3)/2
     cx<T> t1 = v[1] + v[2];
@@ -98,20 +171,24 @@ __device__ inline void butterfly(cx<T>* v, int sign) {
   }
 }
 
-// One in-place Stockham pass of radix R over nseq sequences of length L.
-// Ns = product of the radices of the earlier passes; tw[m] = exp(-2 pi i m/L).
-// Requires nseq * L <= NT * maxv<T>().
+// One in-place Stockham pass (pass p of the plan, radix R) over nseq
+// sequences of length L: every thread reads its butterfly inputs into
+// registers, the workgroup synchronises, and the outputs go to their sorted
+// positions.  twl[m] = exp(-2 pi i m / L).  Requires nseq L <= NT cover(maxv<T>()).
 template <typename T, int R>
-__device__ void pass_ip(cx<T>* buf, int L, int nseq, int Ns, const cx<T>* __restrict__ tw, int sign) {
+__device__ void pass_ip(LV<T> buf, int sl, const FftPlan& pl, int p, int nseq, const cx<T>* __restrict__ tw,
+                        int sign) {
   constexpr int NB = maxv<T>() / R;
-  const int LR = L / R, stride = L / (Ns * R), tot = nseq * LR;
+  const int L = pl.L, LR = pl.lr[p], Ns = pl.ns[p], stride = pl.ts[p];
+  const unsigned mLR = pl.mlr[p], mNs = pl.mns[p];
+  const int tot = nseq * LR;
   cx<T> v[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
     const int idx = threadIdx.x + q * NT;
     if (idx < tot) {
-      const int s = idx / LR, j = idx - s * LR;
-      const cx<T>* src = buf + (size_t)s * L + j;
+      const int s = fdiv(idx, mLR), j = idx - s * LR;
+      const LV<T> src = buf.at(s * sl + j);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
     }
@@ -121,8 +198,8 @@ __device__ void pass_ip(cx<T>* buf, int L, int nseq, int Ns, const cx<T>* __rest
   for (int q = 0; q < NB; ++q) {
     const int idx = threadIdx.x + q * NT;
     if (idx < tot) {
-      const int s = idx / LR, j = idx - s * LR;
-      const int k = j % Ns;
+      const int s = fdiv(idx, mLR), j = idx - s * LR;
+      const int k = j - fdiv(j, mNs) * Ns;
       if (Ns > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
@@ -132,7 +209,7 @@ __device__ void pass_ip(cx<T>* buf, int L, int nseq, int Ns, const cx<T>* __rest
         }
       }
       butterfly<T, R>(v[q], sign);
-      cx<T>* dst = buf + (size_t)s * L + (j - k) * R + k;
+      const LV<T> dst = buf.at(s * sl + (j - k) * R + k);
 #pragma unroll
       for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
     }
@@ -140,31 +217,32 @@ __device__ void pass_ip(cx<T>* buf, int L, int nseq, int Ns, const cx<T>* __rest
   __syncthreads();
 }
 
+// nseq sequences of length pl.L, sequence s at buf + s * sl (sl >= L).
 template <typename T>
-__device__ void lds_fft(cx<T>* buf, const FftPlan& pl, int nseq, const cx<T>* __restrict__ tw, int sign) {
-  int Ns = 1;
-  for (int ps = 0; ps < pl.npass; ++ps) {
-    const int R = pl.radix[ps];
-    if (R == 4)
-      pass_ip<T, 4>(buf, pl.L, nseq, Ns, tw, sign);
+__device__ void lds_fft(LV<T> buf, int sl, const FftPlan& pl, int nseq, const cx<T>* __restrict__ tw, int sign) {
+  for (int p = 0; p < pl.npass; ++p) {
+    const int R = pl.radix[p];
+    if (R == 8)
+      pass_ip<T, 8>(buf, sl, pl, p, nseq, tw, sign);
+    else if (R == 4)
+      pass_ip<T, 4>(buf, sl, pl, p, nseq, tw, sign);
     else if (R == 2)
-      pass_ip<T, 2>(buf, pl.L, nseq, Ns, tw, sign);
+      pass_ip<T, 2>(buf, sl, pl, p, nseq, tw, sign);
     else
-      pass_ip<T, 3>(buf, pl.L, nseq, Ns, tw, sign);
-    Ns *= R;
+      pass_ip<T, 3>(buf, sl, pl, p, nseq, tw, sign);
   }
 }
 
 // Largest batch of sequences a pass can hold in registers.
 template <typename T>
 __host__ __device__ inline int fft_batch(int L) {
-  return (NT * maxv<T>()) / L;
+  return (NT * cover(maxv<T>())) / L;
 }
 
 // Hermitian packing of two real-field spectra A_k, B_k into the complex
 // sequence whose inverse transform is a + i b.
 template <typename T>
-__device__ inline void pack_pair(cx<T>* X, int L, int k, cx<T> A, cx<T> B) {
+__device__ inline void pack_pair(LV<T> X, int L, int k, cx<T> A, cx<T> B) {
   if (k == 0) {
     X[0] = cx<T>{A.x, B.x};
   } else {
@@ -175,7 +253,7 @@ __device__ inline void pack_pair(cx<T>* X, int L, int k, cx<T> A, cx<T> B) {
 
 // Spectra of the two real fields packed in a forward transform Z, at k.
 template <typename T>
-__device__ inline void unpack_pair(const cx<T>* Z, int L, int k, cx<T>& A, cx<T>& B) {
+__device__ inline void unpack_pair(LV<T> Z, int L, int k, cx<T>& A, cx<T>& B) {
   const cx<T> Zk = Z[k];
   if (k == 0) {
     A = cx<T>{Zk.x, 0};
@@ -357,48 +435,68 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
   const T* __restrict__ in = static_cast<const T*>(XA.in);
   T* __restrict__ out = static_cast<T*>(XA.out);
   const int nrows = XA.nrows, nkx = XA.nkx, m1 = XA.m1, pz = XA.pz;
-  const FftPlan pl = XA.pl;
+  const FftPlan& pl = XA.pl;
   const double* __restrict__ kx = XA.kx;
   const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(XA.tw);
   const double eps_wi = XA.eps_wi;
   const double* __restrict__ mean = XA.mean;
   double* __restrict__ mcol = XA.mcol;
-  extern __shared__ double smem_d[];
-  cx<T>* P = reinterpret_cast<cx<T>*>(smem_d);
+  cx<T>* P = reinterpret_cast<cx<T>*>(fft_lds);
   const int L = pl.L;
   const int row = blockIdx.x - XA.blk0, tid = threadIdx.x;
   const size_t fstride = (size_t)nrows * nkx * 2;
   const T* base = in + (size_t)row * nkx * 2;
   const int S = fft_batch<T>(L);
+  const LV<T> PV{0};
   // twiddle table in LDS (behind the data), read by every radix pass
-  cx<T>* twl = P + (size_t)XS::NP * L;
+  cx<T>* twl = P + lds_padded<T>((size_t)XS::NP * L);
   for (int i = tid; i < L; i += NT) twl[i] = tw[i];
   const short* src = XSRC[DIM - 2];
   const short* dxf = XDX[DIM - 2];
+  typedef typename V2<T>::type T2;
+  // each wave packs whole field pairs, so the field tables are read once per
+  // pair (wave-uniform) and the lanes stream one field's kx modes
+  const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   for (int b0 = 0; b0 < XS::NP; b0 += S) {
     const int nb = min(S, XS::NP - b0);
-    cx<T>* X = P + (size_t)b0 * L;
+    const LV<T> X = PV.at(b0 * L);
     for (int e = tid; e < nb * L; e += NT) X[e] = cx<T>{0, 0};
     __syncthreads();
-    for (int e = tid; e < nb * nkx; e += NT) {
-      const int q = e / nkx, k = e - q * nkx;
-      const int fa = 2 * (b0 + q), fb = fa + 1;
-      const T kk = T(kx[k]);
-      cx<T> A{0, 0}, B{0, 0};
-      {
-        const T* p = base + src[fa] * fstride + 2 * k;
-        A = cx<T>{p[0], p[1]};
-        if (dxf[fa]) A = cx<T>{-kk * A.y, kk * A.x};
+    // the wave's items are (pair q = wave + 4 i, block of 64 kx); G items'
+    // loads are issued before any of them is packed
+    const int nkb = (nkx + 63) >> 6;
+    const int items = max(0, (nb - wave + 3) >> 2) * nkb;
+    constexpr int G = 4;
+    for (int i0 = 0; i0 < items; i0 += G) {
+      T2 va[G], vb[G];
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int it = i0 + u, qi = it / nkb, k = lane + 64 * (it - qi * nkb);
+        const int fa = 2 * (b0 + wave + 4 * qi), fb = fa + 1;
+        va[u] = vb[u] = T2{0, 0};
+        if (it < items && k < nkx) {
+          va[u] = *reinterpret_cast<const T2*>(base + src[fa] * fstride + 2 * k);
+          if (fb < XS::NREAL) vb[u] = *reinterpret_cast<const T2*>(base + src[fb] * fstride + 2 * k);
+        }
       }
-      if (fb < XS::NREAL) {
-        const T* p = base + src[fb] * fstride + 2 * k;
-        B = cx<T>{p[0], p[1]};
-        if (dxf[fb]) B = cx<T>{-kk * B.y, kk * B.x};
+#pragma unroll
+      for (int u = 0; u < G; ++u) {
+        const int it = i0 + u, qi = it / nkb, k = lane + 64 * (it - qi * nkb);
+        const int q = wave + 4 * qi, fa = 2 * (b0 + q), fb = fa + 1;
+        if (it < items && k < nkx) {
+          cx<T> A{va[u][0], va[u][1]}, B{vb[u][0], vb[u][1]};
+          const bool da = dxf[fa] != 0, db = fb < XS::NREAL && dxf[fb] != 0;
+          if (da || db) {
+            const T kk = T(kx[k]);
+            if (da) A = cx<T>{-kk * A.y, kk * A.x};
+            if (db) B = cx<T>{-kk * B.y, kk * B.x};
+          }
+          pack_pair(X.at(q * L), L, k, A, B);
+        }
       }
-      pack_pair(X + (size_t)q * L, L, k, A, B);
     }
     __syncthreads();
-    lds_fft(X, pl, nb, twl, +1);
+    lds_fft(X, L, pl, nb, twl, +1);
   }
   // pointwise products; outputs overwrite the first pairs at the same point
   T mrow[16];
@@ -410,7 +508,7 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
   for (int n = tid; n < L; n += NT) {
     T o[2 * XS::NOP];
     auto rd = [&](int f) -> T {
-      const cx<T>& z = P[(size_t)(f >> 1) * L + n];
+      const cx<T>& z = PV[(f >> 1) * L + n];
       return (f & 1) ? z.y : z.x;
     };
     if constexpr (MIXED) {
@@ -421,42 +519,36 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
     }
     if constexpr (XS::NOUT & 1) o[2 * XS::NOP - 1] = 0;
 #pragma unroll
-    for (int q = 0; q < XS::NOP; ++q) P[(size_t)q * L + n] = cx<T>{o[2 * q], o[2 * q + 1]};
+    for (int q = 0; q < XS::NOP; ++q) PV[q * L + n] = cx<T>{o[2 * q], o[2 * q + 1]};
   }
   __syncthreads();
   const T inv = T(1.0 / L);
   T* obase = out + (size_t)row * nkx * 2;
   for (int q0 = 0; q0 < XS::NOP; q0 += S) {
     const int nb = min(S, XS::NOP - q0);
-    cx<T>* Z = P + (size_t)q0 * L;
-    lds_fft(Z, pl, nb, twl, -1);
-    for (int e = tid; e < nb * nkx; e += NT) {
-      const int q = e / nkx, k = e - q * nkx;
-      cx<T> A, B;
-      unpack_pair(Z + (size_t)q * L, L, k, A, B);
-      const int fa = 2 * (q0 + q), fb = fa + 1;
-      T* pa = obase + (size_t)fa * fstride + 2 * k;
-      pa[0] = A.x * inv;
-      pa[1] = A.y * inv;
-      if (fb < XS::NOUT) {
-        T* pb = obase + (size_t)fb * fstride + 2 * k;
-        pb[0] = B.x * inv;
-        pb[1] = B.y * inv;
-      }
-      if constexpr (MIXED && DIM == 2) {
-        // the kx = 0 column is the whole mean (2D has no z): complete it in FP64
-        if (k == 0) {
-          mcol[(size_t)fa * m1 + row] = double(A.x * inv) + mean_product(2, fa, mean, m1, row);
-          if (fb < XS::NOUT) mcol[(size_t)fb * m1 + row] = double(B.x * inv) + mean_product(2, fb, mean, m1, row);
+    const LV<T> Z = PV.at(q0 * L);
+    lds_fft(Z, L, pl, nb, twl, -1);
+    for (int q = wave; q < nb; q += NT / 64)
+      for (int k = lane; k < nkx; k += 64) {
+        cx<T> A, B;
+        unpack_pair(Z.at(q * L), L, k, A, B);
+        const int fa = 2 * (q0 + q), fb = fa + 1;
+        *reinterpret_cast<T2*>(obase + (size_t)fa * fstride + 2 * k) = T2{A.x * inv, A.y * inv};
+        if (fb < XS::NOUT) *reinterpret_cast<T2*>(obase + (size_t)fb * fstride + 2 * k) = T2{B.x * inv, B.y * inv};
+        if constexpr (MIXED && DIM == 2) {
+          // the kx = 0 column is the whole mean (2D has no z): complete it in FP64
+          if (k == 0) {
+            mcol[(size_t)fa * m1 + row] = double(A.x * inv) + mean_product(2, fa, mean, m1, row);
+            if (fb < XS::NOUT) mcol[(size_t)fb * m1 + row] = double(B.x * inv) + mean_product(2, fb, mean, m1, row);
+          }
         }
       }
-    }
   }
 }
 
 template <typename T, int DIM>
 size_t xpencil_lds(int L) {
-  return (size_t)(XShape<DIM>::NP + 1) * L * sizeof(cx<T>);
+  return (lds_padded<T>((size_t)XShape<DIM>::NP * L) + L) * sizeof(cx<T>);
 }
 
 // ---------------------------------------------------------------- z columns
@@ -473,69 +565,105 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
   const T* __restrict__ in = static_cast<const T*>(ZA.in);
   T* __restrict__ out = static_cast<T*>(ZA.out);
   const int nkx = ZA.nkx, nzs = ZA.nzs, rows_y = ZA.rows, inverse = ZA.inverse;
-  const FftPlan pl = ZA.pl;
+  const FftPlan& pl = ZA.pl;
   const int* __restrict__ src_field = ZA.src_field;
   const int* __restrict__ deriv = ZA.deriv;
   const double* __restrict__ kz = ZA.kz;
   const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(ZA.tw);
   const double* __restrict__ mean = ZA.mean;
   double* __restrict__ mcol = ZA.mcol;
-  extern __shared__ double smem_z[];
-  c2* A = reinterpret_cast<c2*>(smem_z);
+  c2* A = reinterpret_cast<c2*>(fft_lds);
   const int L = pl.L;
-  c2* twl = A + (size_t)ZG * L;  // twiddle table behind the data
+  // sequences (one per kx column) at stride L + 1: the column-wise loads and
+  // stores of neighbouring kx then fall on different LDS banks
+  const int SL = L + 1;
+  const LV<T> AV{0};
+  c2* twl = A + lds_padded<T>((size_t)ZG * SL);  // twiddle table behind the data
   for (int e = threadIdx.x; e < L; e += NT) twl[e] = tw[e];
   // local workgroup -> (kx group, row, field)
   const int lb = blockIdx.x - ZA.blk0;
   const int gx = lb % ZA.ngx, i = (lb / ZA.ngx) % rows_y, f = lb / (ZA.ngx * rows_y);
   const int k0 = gx * ZG;
   const int ng = min(ZG, nkx - k0);
+  const unsigned mng = fast_div_magic((unsigned)ng);
   const int tid = threadIdx.x;
   const int rin = inverse ? nzs : L, rout = inverse ? L : nzs;
   const int sf = src_field ? src_field[f] : f;
   const int dz = deriv ? deriv[f] : 0;
   const T* ib = in + ((size_t)sf * rows_y + i) * rin * nkx * 2;
   T* ob = out + ((size_t)f * rows_y + i) * rout * nkx * 2;
+  // gather PER elements per thread before writing LDS, so that many global
+  // loads are in flight at once
+  constexpr int PER = 8;
+  typedef typename V2<T>::type T2;
   if (inverse) {
-    for (int e = tid; e < ZG * L; e += NT) A[e] = c2{0, 0};
+    for (int e = tid; e < ZG * SL; e += NT) AV[e] = c2{0, 0};
     __syncthreads();
-    for (int e = tid; e < nzs * ng; e += NT) {
-      const int s = e / ng, g = e - s * ng;
-      if (nzs > 1 && s == nzs / 2) continue;
-      const int mz = (s < nzs / 2) ? s : s - nzs;
-      c2 v = c2{ib[((size_t)s * nkx + k0 + g) * 2], ib[((size_t)s * nkx + k0 + g) * 2 + 1]};
-      if (dz) {
-        const T kk = T(kz[s]);
-        v = c2{-kk * v.y, kk * v.x};
+    const int tot = nzs * ng;
+    for (int e0 = 0; e0 < tot; e0 += PER * NT) {
+      c2 v[PER];
+      int pos[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + tid + u * NT;
+        pos[u] = -1;
+        if (e < tot) {
+          const int s = fdiv(e, mng), g = e - s * ng;
+          if (!(nzs > 1 && s == nzs / 2)) {
+            const T2 x = *reinterpret_cast<const T2*>(ib + ((size_t)s * nkx + k0 + g) * 2);
+            v[u] = c2{x[0], x[1]};
+            if (dz) {
+              const T kk = T(kz[s]);
+              v[u] = c2{-kk * v[u].y, kk * v[u].x};
+            }
+            const int mz = (s < nzs / 2) ? s : s - nzs;
+            pos[u] = g * SL + (mz < 0 ? mz + L : mz);
+          }
+        }
       }
-      A[(size_t)g * L + ((mz % L) + L) % L] = v;
+#pragma unroll
+      for (int u = 0; u < PER; ++u)
+        if (pos[u] >= 0) AV[pos[u]] = v[u];
     }
   } else {
-    for (int e = tid; e < L * ng; e += NT) {
-      const int z = e / ng, g = e - z * ng;
-      A[(size_t)g * L + z] = c2{ib[((size_t)z * nkx + k0 + g) * 2], ib[((size_t)z * nkx + k0 + g) * 2 + 1]};
+    const int tot = L * ng;
+    for (int e0 = 0; e0 < tot; e0 += PER * NT) {
+      c2 v[PER];
+      int pos[PER];
+#pragma unroll
+      for (int u = 0; u < PER; ++u) {
+        const int e = e0 + tid + u * NT;
+        pos[u] = -1;
+        if (e < tot) {
+          const int z = fdiv(e, mng), g = e - z * ng;
+          const T2 x = *reinterpret_cast<const T2*>(ib + ((size_t)z * nkx + k0 + g) * 2);
+          v[u] = c2{x[0], x[1]};
+          pos[u] = g * SL + z;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < PER; ++u)
+        if (pos[u] >= 0) AV[pos[u]] = v[u];
     }
   }
   __syncthreads();
-  lds_fft(A, pl, ng, twl, inverse ? +1 : -1);
+  lds_fft(AV, SL, pl, ng, twl, inverse ? +1 : -1);
   if (inverse) {
     for (int e = tid; e < L * ng; e += NT) {
-      const int z = e / ng, g = e - z * ng;
-      const c2 v = A[(size_t)g * L + z];
-      ob[((size_t)z * nkx + k0 + g) * 2] = v.x;
-      ob[((size_t)z * nkx + k0 + g) * 2 + 1] = v.y;
+      const int z = fdiv(e, mng), g = e - z * ng;
+      const c2 v = AV[g * SL + z];
+      *reinterpret_cast<T2*>(ob + ((size_t)z * nkx + k0 + g) * 2) = T2{v.x, v.y};
     }
   } else {
     const T inv = T(1.0 / L);
     for (int e = tid; e < nzs * ng; e += NT) {
-      const int s = e / ng, g = e - s * ng;
+      const int s = fdiv(e, mng), g = e - s * ng;
       c2 v{0, 0};
       if (!(nzs > 1 && s == nzs / 2)) {
         const int mz = (s < nzs / 2) ? s : s - nzs;
-        v = scal(inv, A[(size_t)g * L + ((mz % L) + L) % L]);
+        v = scal(inv, AV[g * SL + (mz < 0 ? mz + L : mz)]);
       }
-      ob[((size_t)s * nkx + k0 + g) * 2] = v.x;
-      ob[((size_t)s * nkx + k0 + g) * 2 + 1] = v.y;
+      *reinterpret_cast<T2*>(ob + ((size_t)s * nkx + k0 + g) * 2) = T2{v.x, v.y};
       // mixed forward transform: the kx = kz = 0 value completed in FP64
       if (mcol && s == 0 && k0 + g == 0)
         mcol[(size_t)f * rows_y + i] = double(v.x) + mean_product(3, f, mean, rows_y, i);
@@ -577,41 +705,42 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restric
   const Dims d = DA.d;
   const double* __restrict__ in = DA.in;
   const int zrows = DA.zrows;
-  const FftPlan pl = DA.pl;
+  const FftPlan& pl = DA.pl;
   const c2* __restrict__ tw = reinterpret_cast<const c2*>(DA.tw);
   const double* __restrict__ ydy = DA.ydy;
   DiagPart* __restrict__ parts = DA.parts;
-  extern __shared__ double smem_g[];
-  c2* A = reinterpret_cast<c2*>(smem_g);
+  c2* A = reinterpret_cast<c2*>(fft_lds);
   __shared__ DiagPart wpart[NT / 64];
   const int L = pl.L, nkx = d.nkx;
-  c2* twl = A + 2 * (size_t)L;  // twiddle table behind the data
+  const unsigned mkx = fast_div_magic((unsigned)nkx);
+  const LV<double> AV{0};
+  c2* twl = A + lds_padded<double>(2 * (size_t)L);  // twiddle table behind the data
   for (int e = threadIdx.x; e < L; e += NT) twl[e] = tw[e];
   const int row = blockIdx.x - DA.blk0, tid = threadIdx.x;
   const int nrows = (d.N + 1) * zrows;
   const int j = row / zrows;
   const size_t fstride = (size_t)nrows * nkx * 2;
   const double* base = in + (size_t)row * nkx * 2;
-  for (int e = tid; e < 2 * L; e += NT) A[e] = c2{0, 0};
+  for (int e = tid; e < 2 * L; e += NT) AV[e] = c2{0, 0};
   __syncthreads();
   const int nf = d.dim == 2 ? 3 : 4;
   for (int e = tid; e < 2 * nkx; e += NT) {
-    const int q = e / nkx, k = e - q * nkx;
+    const int q = fdiv(e, mkx), k = e - q * nkx;
     const int fa = 2 * q, fb = fa + 1;
     c2 Av{0, 0}, Bv{0, 0};
     if (fa < nf) Av = c2{base[fa * fstride + 2 * k], base[fa * fstride + 2 * k + 1]};
     if (fb < nf) Bv = c2{base[fb * fstride + 2 * k], base[fb * fstride + 2 * k + 1]};
-    pack_pair(A + (size_t)q * L, L, k, Av, Bv);
+    pack_pair(AV.at(q * L), L, k, Av, Bv);
   }
   __syncthreads();
-  lds_fft(A, pl, 2, twl, +1);
+  lds_fft(AV, L, pl, 2, twl, +1);
   const double dx = d.lx / d.nx, dz = d.dim == 3 ? d.lz / d.nz : 1.0;
   const double dyj = ydy[j];
   double mn = 1.0 / 0.0, cf = 0, es = 0, ts = 0;
   unsigned long long n3 = 0, n0 = 0;
   int flag = 0, big = 0;
   for (int n = tid; n < L; n += NT) {
-    const c2 z0 = A[n], z1 = A[L + n];
+    const c2 z0 = AV[n], z1 = AV[L + n];
     const double trc = z0.x + (d.dim == 2 ? 1.0 : 0.0);
     const double u = z0.y, v = z1.x, w = d.dim == 3 ? z1.y : 0.0;
     mn = fmin(mn, trc);
@@ -781,7 +910,8 @@ void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t 
 int zfft_blocks(int nkx, int rows, int nfields) { return ((nkx + ZG - 1) / ZG) * rows * nfields; }
 
 size_t zfft_lds_bytes(int L, int precision) {
-  return (size_t)(ZG + 1) * L * (precision == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+  return precision == 0 ? (lds_padded<double>((size_t)ZG * (L + 1)) + L) * sizeof(cx<double>)
+                        : (lds_padded<float>((size_t)ZG * (L + 1)) + L) * sizeof(cx<float>);
 }
 
 void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
@@ -789,7 +919,7 @@ void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hi
   hipLaunchKernelGGL(diag_rows_kernel, dim3(blocks), dim3(NT), lds, s, args, nmem);
 }
 
-size_t diag_rows_lds_bytes(int L) { return 3 * (size_t)L * sizeof(c2); }
+size_t diag_rows_lds_bytes(int L) { return (lds_padded<double>(2 * (size_t)L) + L) * sizeof(c2); }
 
 void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s) {
   if (nmem <= 0) return;

@@ -62,12 +62,23 @@ int gemm_prepare(GemmJob* jobs, int njobs, int cfg);
 void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s);
 hipError_t gemm_set_attributes();
 
-// Mixed-radix (4, 2, 3) Stockham plan for a length L = 2^a 3^b.
+// Mixed-radix (8, 4, 2, 3) Stockham plan for a length L = 2^a 3^b.  Per
+// pass p: radix, L / radix (lr), product of the earlier radices (ns), the
+// twiddle stride L / (ns radix) (ts), and multiply-high reciprocals of lr and
+// ns (mlr, mns: floor(n / d) = umulhi(n, m) for the n < 2^16 the passes use;
+// 0 when d = 1).
 struct FftPlan {
   int L = 0;
   int npass = 0;
   int radix[12] = {0};
+  int lr[12] = {0};
+  int ns[12] = {0};
+  int ts[12] = {0};
+  unsigned mlr[12] = {0};
+  unsigned mns[12] = {0};
 };
+// Multiply-high reciprocal of d >= 2 (0 for d = 1), exact for n d < 2^32.
+__host__ __device__ inline unsigned fast_div_magic(unsigned d) { return d <= 1 ? 0u : 0xFFFFFFFFu / d + 1u; }
 bool make_plan(int L, FftPlan* p);
 
 // Problem description shared by the elementwise kernels.
@@ -228,7 +239,7 @@ int zfft_blocks(int nkx, int rows, int nfields);
 size_t zfft_lds_bytes(int L, int precision);
 size_t diag_rows_lds_bytes(int L);
 constexpr int ELEM_THREADS = 256;
-constexpr int ZFFT_GROUP = 16;  // kx columns per workgroup of the z transforms
+constexpr int ZFFT_GROUP = 32;  // kx columns per workgroup of the z transforms
 // Raises the dynamic-LDS limit of the transform kernels (call once, outside capture).
 hipError_t fft_set_attributes();
 
