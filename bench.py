@@ -26,10 +26,13 @@ MFMA_F32_TFS = 157.3
 from paper_2606_09468_amd.workloads import ENSEMBLE, WORKLOADS, ensemble_members  # noqa: E402
 
 
-def stage_work(w, prec_bytes=16):
-    """Algorithmic work of one launch of each stage: ('hbm', bytes) for the
-    transform / elementwise stages (each input read once, each output written
-    once, complex values of prec_bytes), ('mfma', flops) for the products."""
+def stage_work(w, precision):
+    """Algorithmic work of one launch of each stage kernel at this workload:
+    {stage: (bound, amount, peak)}.  Products: ('mfma', 2 m n k summed over
+    the table, peak of the compute precision).  Transform and elementwise
+    kernels: ('hbm', bytes), every input field read once and every output
+    written once, complex values of the kernel's precision (FP32 in the mixed
+    transforms, FP64 elsewhere); small per-mode tables are not counted."""
     dim, nx, ny, nz = w["dim"], w["nx"], w["ny"], w["nz"]
     N = ny - 1
     n1, m1, ni = N + 1, 3 * N // 2 + 1, N - 1
@@ -39,26 +42,88 @@ def stage_work(w, prec_bytes=16):
     nm = nkx * nzs
     cw = 2 * nm
     nc = 3 if dim == 2 else 6
-    nvel = dim
-    nsolve = (1 if dim == 2 else 2) + nc
+    nsv = 1 if dim == 2 else 2
+    nsolve = nsv + nc
     nout = 5 if dim == 2 else 9
     nyin = 9 if dim == 2 else 17
-    cplx = prec_bytes
+    nh = 1 + (dim - 2) + nc
+    mixed = precision != 0
+    f32_state = precision == 1            # the state -> padded-grid products in FP32
+    f32_proj = precision == 1
+    tb = 8 if mixed else 16               # bytes per complex value in the transforms
+    pk = lambda f32: MFMA_F32_TFS if f32 else MFMA_F64_TFS
     out = {}
-    g1 = (nvel + nc + (1 if dim == 2 else 2) + nc) * 2 * m1 * cw * n1     # I and D to the padded grid
-    g1 += nsolve * 2 * n1 * cw * n1 + (dim - 1) * 2 * n1 * n1             # D2 of phi, g, c and U, W
-    g1 += nc * 2 * n1 * cw * n1                                           # D of every c
-    out["gemm_state"] = ("mfma", g1)
+    nderiv = 1 if dim == 2 else 2
+
+    def mixed_table(parts):
+        """One launch holding FP32 and FP64 products: the peak is the rate at
+        which this flop mix would run if every product ran at its own peak."""
+        flops = sum(f for f, _ in parts)
+        ideal = sum(f / (p * 1e12) for f, p in parts)
+        return ("mfma", flops, flops / ideal / 1e12)
+    state = [((dim + nc + nderiv + nc) * 2 * m1 * cw * n1, pk(f32_state)),                  # to the padded grid
+             ((nsolve + nc) * 2 * n1 * cw * n1 + (dim - 1) * 2 * n1 * n1, MFMA_F64_TFS)]  # D2, D of the state
+    proj = [((nout + dim - 1) * 2 * n1 * cw * m1, pk(f32_proj))]                           # P N, (D P) N
+    if mixed:
+        state.append(((2 * (dim - 1) + 2 * nc) * 2 * m1 * n1, MFMA_F64_TFS))               # mean profiles
+        proj.append((nout * 2 * n1 * m1, MFMA_F64_TFS))                                    # mean column
+    out["gemm_state"] = mixed_table(state)
     if dim == 3:
-        out["zfft_inv"] = ("hbm", (nyin * m1 * nzs * nkx + 26 * m1 * pz * nkx) * cplx)
-        out["xpencil"] = ("hbm", (26 + nout) * m1 * pz * nkx * cplx)
-        out["zfft_fwd"] = ("hbm", (nout * m1 * pz * nkx + nout * m1 * nzs * nkx) * cplx)
+        out["zfft_inv"] = ("hbm", (nyin * m1 * nzs * nkx + 26 * m1 * pz * nkx) * tb, HBM_PEAK_GBS)
+        out["xpencil"] = ("hbm", (26 + nout) * m1 * pz * nkx * tb, HBM_PEAK_GBS)
+        out["zfft_fwd"] = ("hbm", (nout * m1 * pz * nkx + nout * m1 * nzs * nkx) * tb, HBM_PEAK_GBS)
+        out["diag_zfft"] = ("hbm", (4 * n1 * nzs * nkx + 4 * n1 * nz * nkx) * 16, HBM_PEAK_GBS)
     else:
-        out["xpencil"] = ("hbm", (nyin + nout) * m1 * nkx * cplx)
-    out["gemm_proj"] = ("mfma", (nout + dim - 1) * 2 * n1 * cw * m1)      # P N and (D P) N_x, N_z
-    out["gemm_vinv"] = ("mfma", nsolve * 2 * ni * cw * ni)
-    out["gemm_v"] = ("mfma", (nsolve + 1) * 2 * ni * cw * ni + 2 * n1 * cw * ni + 2 * 2 * ni)
+        out["xpencil"] = ("hbm", (nyin + nout) * m1 * nkx * tb, HBM_PEAK_GBS)
+    out["gemm_proj"] = mixed_table(proj)
+    out["gemm_vinv"] = ("mfma", nsolve * 2 * ni * cw * ni, MFMA_F64_TFS)
+    out["gemm_v"] = ("mfma", (2 + (dim - 2) + nc) * 2 * ni * cw * ni + 2 * n1 * cw * ni + 2 * 2 * ni, MFMA_F64_TFS)
+    fld = n1 * nm * 16                     # one FP64 spectral field
+    rhs_in = (nsv + nc) + nh + nsolve + nc + nout + (dim - 1)
+    rhs_out = nsolve + (dim - 1)
+    out["rhs"] = ("hbm", (rhs_in + rhs_out) * fld, HBM_PEAK_GBS)
+    fin_in = 3 + (dim - 1) + nc + 3 + nc + (dim - 2)
+    fin_out = (2 + 1 + 2 * (dim - 2)) + nh + (3 if dim == 2 else 4)
+    out["finalize"] = ("hbm", (fin_in + fin_out) * fld, HBM_PEAK_GBS)
+    out["diag_rows"] = ("hbm", (3 if dim == 2 else 4) * n1 * (nz if dim == 3 else 1) * nkx * 16, HBM_PEAK_GBS)
     return out
+
+
+def roofline_table(stages, work):
+    """Per-kernel roofline from the measured per-launch durations."""
+    table = {}
+    for k, ms in stages.items():
+        if k not in work or ms <= 0:
+            continue
+        bound, amount, peak = work[k]
+        t = ms * 1e-3
+        if bound == "hbm":
+            ach, unit = amount / t / 1e9, "GB/s"
+        else:
+            ach, unit = amount / t / 1e12, "TFLOP/s"
+        table[k] = dict(bound=bound, achieved=ach, peak=peak, unit=unit, frac=ach / peak, avg_ms=ms,
+                        **({"algorithmic_bytes": amount} if bound == "hbm" else {"algorithmic_flops": amount}))
+    return table
+
+
+def traffic_for(kernel, workload, precision):
+    """HBM bytes per launch from the committed counter summary of this kernel
+    and workload, if the transform sources have not changed since (else None)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.md")
+    if not os.path.exists(path):
+        return None
+    src = open(os.path.join(ROOT, "paper_2606_09468_amd", "csrc", "fft.hip"), "rb").read() + \
+        open(os.path.join(ROOT, "paper_2606_09468_amd", "csrc", "gemm.hip"), "rb").read() + \
+        open(os.path.join(ROOT, "paper_2606_09468_amd", "csrc", "elem.hip"), "rb").read()
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    for line in open(path):
+        parts = [x.strip() for x in line.strip().strip("|").split("|")]
+        if len(parts) >= 6 and parts[0] == kernel and parts[1] == workload and parts[2] == str(precision):
+            if parts[5] != digest:
+                return None
+            return float(parts[3]) + float(parts[4])
+    return None
 
 
 def cpu_baseline(w, sample_steps):
@@ -106,6 +171,9 @@ def main():
     ap.add_argument("--stage-steps", type=int, default=50)
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first copy MIB MiB device to device (a plain copy kernel of known traffic, the "
+                         "reference for HBM counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (each run, or each ensemble "
@@ -119,6 +187,12 @@ def main():
     if not os.path.exists(P.LIBPATH):
         from paper_2606_09468_amd import build
         build.build()
+    if args.copy_calibration > 0:
+        src = torch.ones(args.copy_calibration << 20, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "c4":
         return bench_ensemble(args, P)
     w = WORKLOADS[args.workload]
@@ -152,18 +226,10 @@ def main():
         timed[prec] = dict(ms=ms, sps=args.steps / (ms / 1e3), stages=stages, prm=prm)
     head = precs[0]
     ms, sps, stages, prm = timed[head]["ms"], timed[head]["sps"], timed[head]["stages"], timed[head]["prm"]
-    work = stage_work(w, prec_bytes=16 if head == 0 else 8)
-    dom = max((k for k in stages if k in work), key=lambda k: stages[k])
-    kind, amount = work[dom]
-    t = stages[dom] * 1e-3
-    mfma_peak = MFMA_F32_TFS if (head == 1 and dom in ("gemm_state", "gemm_proj")) else MFMA_F64_TFS
-    if kind == "hbm":
-        roof = dict(kernel=dom, bound="hbm", achieved=amount / t / 1e9, peak=HBM_PEAK_GBS, unit="GB/s",
-                    traffic=None, algorithmic_bytes=amount, avg_ms=stages[dom])
-    else:
-        roof = dict(kernel=dom, bound="mfma", achieved=amount / t / 1e12, peak=mfma_peak, unit="TFLOP/s",
-                    traffic=None, algorithmic_flops=amount, avg_ms=stages[dom])
-    roof["frac"] = roof["achieved"] / roof["peak"]
+    table = roofline_table(stages, stage_work(w, head))
+    dom = max(table, key=lambda k: table[k]["avg_ms"])
+    roof = dict(kernel=dom, **table[dom])
+    roof["traffic"] = traffic_for(dom, args.workload, head)
     points = w["nx"] * w["ny"] * w["nz"]
     line = {
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
@@ -175,6 +241,8 @@ def main():
         "grid_point_updates_per_s": sps * points,
         "roofline": roof,
         "stage_ms": stages,
+        "stage_roofline": {k: {"frac": round(v["frac"], 4), "achieved": round(v["achieved"], 2),
+                               "unit": v["unit"], "avg_ms": round(v["avg_ms"], 5)} for k, v in table.items()},
     }
     if len(precs) > 1:
         line["fp64"] = {"value": timed[0]["sps"], "ms_per_step": timed[0]["ms"] / args.steps,

@@ -30,7 +30,7 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_stage_name", "pcs_ensemble_workspace_bytes", "pcs_ensemble_init", "pcs_ensemble_step",
            "pcs_ensemble_diagnostics", "pcs_ensemble_state_size", "pcs_ensemble_get_state",
            "pcs_ensemble_destroy")
-PCS_NSTAGE = 11
+PCS_NSTAGE = 12
 
 
 class pcs_grid(ctypes.Structure):

@@ -16,7 +16,6 @@
 #include <map>
 #include <mutex>
 #include <new>
-#include <type_traits>
 #include <vector>
 
 #include "../../include/pcs.h"
@@ -51,6 +50,7 @@ struct JobList {
   void add(const void* A, const void* B, int ldb, void* C, int ldc, int m, int n, int k, int flags = 0,
            int scale = SCALE_NONE, const EigScale* es = nullptr, void* C2 = nullptr, int scale2 = SCALE_NONE) {
     GemmJob j{};
+    j.type = type;
     j.A = A;
     j.B = B;
     j.C = C;
@@ -160,11 +160,11 @@ struct Batch {
   std::vector<Member*> mem;
   int dim = 2, prec = 0;
   hipStream_t s = nullptr;
-  // second stream (default priority) for the products of the state that do
-  // not feed the transforms; forked from and joined to s inside the step
-  hipStream_t s2 = nullptr;
-  hipEvent_t ev_fork = nullptr, ev_bar = nullptr, ev_fwd = nullptr, ev_join = nullptr;
-  JobList G1, Gbar, G1b, G2, Gm, G4, G5;
+  // GS: every product of the state (padded-grid values and derivatives,
+  // mixed: the FP64 mean profiles, D2 and D of the state); GP: projections of
+  // the explicit terms (mixed: and the FP64 mean column); G4 / G5: solves.
+  // Mixed-precision tables hold FP32 and FP64 products in one launch.
+  JobList GS, GP, G4, G5;
   // per-member argument tables (host copies, then device) and launch sizes
   std::vector<XArgs> hx;
   std::vector<ZArgs> hzi, hzf, hzd;
@@ -182,14 +182,10 @@ struct Batch {
   size_t lx = 0, lzi = 0, lzf = 0, lzd = 0, ldr = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
-  std::vector<JobList*> lists() { return {&G1, &Gbar, &G1b, &G2, &Gm, &G4, &G5}; }
+  std::vector<JobList*> lists() { return {&GS, &GP, &G4, &G5}; }
   ~Batch() {
-    if (s2) (void)hipStreamSynchronize(s2);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
-    for (hipEvent_t e : {ev_fork, ev_bar, ev_fwd, ev_join})
-      if (e) (void)hipEventDestroy(e);
-    if (s2) (void)hipStreamDestroy(s2);
     for (Member* m : mem) delete m;
   }
 };
@@ -695,14 +691,17 @@ pcs_status reset_state(Member* m, uint64_t seed, double amp, hipStream_t s) {
   return PCS_OK;
 }
 
-// Merges the members' tables of one stage into the batch's table.
-void merge_list(JobList& dst, const std::vector<Member*>& mem, JobList Member::*lp) {
+// Merges the members' tables of the given stages into one batch table (in
+// that order; the table's type is the first non-FP64 type among them).
+void merge_list(JobList& dst, const std::vector<Member*>& mem, std::initializer_list<JobList Member::*> lps) {
   dst.h.clear();
-  for (Member* m : mem) {
-    const JobList& src = m->*lp;
-    if (src.n()) dst.type = src.type;
-    dst.h.insert(dst.h.end(), src.h.begin(), src.h.end());
-  }
+  dst.type = GEMM_DDD;
+  for (JobList Member::*lp : lps)
+    for (Member* m : mem) {
+      const JobList& src = m->*lp;
+      if (src.n() && src.type != GEMM_DDD && dst.type == GEMM_DDD) dst.type = src.type;
+      dst.h.insert(dst.h.end(), src.h.begin(), src.h.end());
+    }
   if (dst.n()) dst.prepare();
 }
 
@@ -710,13 +709,11 @@ void merge_list(JobList& dst, const std::vector<Member*>& mem, JobList Member::*
 // stage kernels and the launch sizes (workgroups, LDS) of every stage.
 void build_batch(Batch* b) {
   const std::vector<Member*>& mem = b->mem;
-  merge_list(b->G1, mem, &Member::G1);
-  merge_list(b->Gbar, mem, &Member::Gbar);
-  merge_list(b->G1b, mem, &Member::G1b);
-  merge_list(b->G2, mem, &Member::G2);
-  merge_list(b->Gm, mem, &Member::Gm);
-  merge_list(b->G4, mem, &Member::G4);
-  merge_list(b->G5, mem, &Member::G5);
+  // the single-column mean-mode products first: their short tiles start early
+  merge_list(b->GS, mem, {&Member::Gbar, &Member::G1, &Member::G1b});
+  merge_list(b->GP, mem, {&Member::Gm, &Member::G2});
+  merge_list(b->G4, mem, {&Member::G4});
+  merge_list(b->G5, mem, {&Member::G5});
   b->hx.clear();
   b->hzi.clear();
   b->hzf.clear();
@@ -893,19 +890,17 @@ size_t layout(Batch* b, char* base) {
 }
 
 // Stage boundaries: mark(i) is called before stage i and once more at the
-// end; the eager profiling path records a HIP event there and runs every
-// stage on the caller's stream in order.  Otherwise the products of the
-// state that the transforms do not need (G1b, and in mixed precision the
-// FP64 mean profiles and mean-column projection) run on the second stream:
-//   s : G1 -> [z inv] -> (wait bar) -> x pencils -> [z fwd] -> G2 -> (wait join) -> RHS ...
-//   s2: (wait fork) -> [Gbar] -> bar -> G1b -> [(wait fwd) -> Gm] -> join
+// end; the eager profiling path records a HIP event there.  Every stage is
+// one kernel launch (or none where it does not apply), all on the caller's
+// stream.
 enum Stage {
-  ST_GEMM_STATE, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_RHS, ST_GEMM_VINV, ST_GEMM_V,
-  ST_FINALIZE, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
+  ST_GEMM_STATE, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_RHS, ST_GEMM_VINV, ST_GEMM_V, ST_FINALIZE,
+  ST_DIAG_ZFFT, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
 };
 static_assert(ST_COUNT == PCS_NSTAGE, "stage table");
-const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv", "xpencil", "zfft_fwd", "gemm_proj", "rhs",
-                                            "gemm_vinv",  "gemm_v",   "finalize", "diag_rows", "diag_final"};
+const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv",  "xpencil",   "zfft_fwd",
+                                            "gemm_proj",  "rhs",       "gemm_vinv", "gemm_v",
+                                            "finalize",   "diag_zfft", "diag_rows", "diag_final"};
 
 struct NoMark {
   void operator()(int) const {}
@@ -914,39 +909,17 @@ struct NoMark {
 template <typename Mark>
 void explicit_stage(Batch* b, const Mark& mark) {
   hipStream_t s = b->s;
-  const bool mixed = b->prec != 0;
-  constexpr bool fork = std::is_same<Mark, NoMark>::value;  // eager profiling stays on one stream
-  hipStream_t s2 = fork ? b->s2 : s;
   const int nm = (int)b->mem.size();
   mark(ST_GEMM_STATE);
-  if (fork) {
-    (void)hipEventRecord(b->ev_fork, s);
-    (void)hipStreamWaitEvent(s2, b->ev_fork, 0);
-  }
-  if (mixed) b->Gbar.run(s2);
-  if (fork) (void)hipEventRecord(b->ev_bar, s2);
-  b->G1.run(s);
-  b->G1b.run(s2);
+  b->GS.run(s);
   mark(ST_ZFFT_INV);
   if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
   mark(ST_XPENCIL);
-  if (fork && mixed) (void)hipStreamWaitEvent(s, b->ev_bar, 0);
   launch_xpencil(b->dim, b->prec, b->dx, nm, b->bx, b->lx, s);
   mark(ST_ZFFT_FWD);
   if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
   mark(ST_GEMM_PROJ);
-  if (mixed) {
-    if (fork) {
-      (void)hipEventRecord(b->ev_fwd, s);
-      (void)hipStreamWaitEvent(s2, b->ev_fwd, 0);
-    }
-    b->Gm.run(s2);
-  }
-  b->G2.run(s);
-  if (fork) {
-    (void)hipEventRecord(b->ev_join, s2);
-    (void)hipStreamWaitEvent(s, b->ev_join, 0);
-  }
+  b->GP.run(s);
   mark(ST_RHS);
   launch_rhs(b->drhs, nm, b->brhs, s);
 }
@@ -962,8 +935,9 @@ void enqueue_step(Batch* b, const Mark& mark) {
   b->G5.run(s);
   mark(ST_FINALIZE);
   launch_finalize(b->dfin, nm, b->bfin, s);
-  mark(ST_DIAG_ROWS);
+  mark(ST_DIAG_ZFFT);
   if (b->dim == 3) launch_zfft(0, b->dzd, nm, b->bzd, b->lzd, s);
+  mark(ST_DIAG_ROWS);
   launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, s);
   mark(ST_DIAG_FINAL);
   launch_diag_final(b->ddf, nm, s);
@@ -986,7 +960,7 @@ pcs_status autotune(Batch* b) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   for (JobList* jl : b->lists()) {
-    if (!jl->n()) continue;
+    if (!jl->n() || jl->cfg < 0) continue;  // nothing to tune on the matrix-vector kernel
     const auto key = jl->key();
     auto it = tune_cache().find(key);
     int best = -1;
@@ -1138,14 +1112,6 @@ pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_para
   }
   layout(b, static_cast<char*>(workspace));
   b->s = static_cast<hipStream_t>(stream);
-  if (hipStreamCreateWithFlags(&b->s2, hipStreamNonBlocking) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_bar, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_fwd, hipEventDisableTiming) != hipSuccess ||
-      hipEventCreateWithFlags(&b->ev_join, hipEventDisableTiming) != hipSuccess) {
-    (void)hipGetLastError();
-    return PCS_ERR_DEVICE;
-  }
   if (hipError_t e = gemm_set_attributes(); e != hipSuccess) {
     report(e, "gemm_set_attributes", __LINE__);
     return PCS_ERR_DEVICE;

@@ -35,6 +35,8 @@
 // are bitwise reproducible.
 #include "kernels.hpp"
 
+#include <type_traits>
+
 namespace pcs {
 
 typedef double dbl4 __attribute__((ext_vector_type(4)));
@@ -209,14 +211,12 @@ int gemm_prepare(GemmJob* jobs, int njobs, int cfg) {
 
 // ------------------------------------------------------------ register-direct kernel
 template <typename T, typename TB, typename TC, int CFG>
-__global__ __launch_bounds__(256) void gemm_reg_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+__device__ __attribute__((always_inline)) inline void reg_body(const GemmJob* __restrict__ jp, int t,
+                                                               double* smem) {
   constexpr int TM = RCfg<CFG>::TM, TN = RCfg<CFG>::TN, KS = RCfg<CFG>::KS;
   constexpr int BM = 32 * TM, BN = 32 * TN;
   typedef typename Vec<T>::v4 V4;
-  __shared__ T red[KS > 1 ? 4 * 16 * 64 : 1];
-
-  const int t = xcd_tile(blockIdx.x, total);
-  const GemmJob* jp = jobs + find_job(jobs, njobs, t);
+  T* red = reinterpret_cast<T*>(smem);
   const int lt = t - jp->tile0, tiles_m = jp->tiles_m;
   const int row0 = (lt % tiles_m) * BM, col0 = (lt / tiles_m) * BN;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -300,9 +300,28 @@ __global__ __launch_bounds__(256) void gemm_reg_kernel(const GemmJob* __restrict
   store_tile<T, TC, 2, 2>(jp, acc, wrow, wcol, lk, l16);
 }
 
+// A table may mix FP64 products (type GEMM_DDD) with products of its own
+// precision combination; each workgroup branches once on its job's type.
+template <typename T, typename TB, typename TC>
+constexpr bool dual_type() {
+  return !(std::is_same<T, double>::value && std::is_same<TB, double>::value && std::is_same<TC, double>::value);
+}
+
+template <typename T, typename TB, typename TC, int CFG>
+__global__ __launch_bounds__(256) void gemm_reg_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+  __shared__ double red[RCfg<CFG>::KS > 1 ? 4 * 16 * 64 : 1];
+  const int t = xcd_tile(blockIdx.x, total);
+  const GemmJob* jp = jobs + find_job(jobs, njobs, t);
+  if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
+    reg_body<double, double, double, CFG>(jp, t, red);
+  else
+    reg_body<T, TB, TC, CFG>(jp, t, red);
+}
+
 // ------------------------------------------------------------ LDS-tiled kernel
 template <typename T, typename TB, typename TC, int CFG>
-__global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+__device__ __attribute__((always_inline)) inline void lds_body(const GemmJob* __restrict__ jp, int t,
+                                                               double* smem) {
   constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC;
   constexpr int WM = BM / 2, WN = BN / 2, RB = WM / 16, CB = WN / 16;
   // A panel row-major [BM][PA] (pitch KC + 2 keeps the 16 rows of a fragment
@@ -314,11 +333,8 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict
   typedef typename Vec<T>::v4 V4;
   typedef typename Vec<T>::v2 AP;
   typedef typename Vec<TB>::v2 BP;
-  __shared__ __attribute__((aligned(16))) T As[2][BM * PA];
-  __shared__ __attribute__((aligned(16))) T Bs[2][KC * PB];
-
-  const int t = xcd_tile(blockIdx.x, total);
-  const GemmJob* jp = jobs + find_job(jobs, njobs, t);
+  T (*As)[BM * PA] = reinterpret_cast<T (*)[BM * PA]>(smem);
+  T (*Bs)[KC * PB] = reinterpret_cast<T (*)[KC * PB]>(smem + (2 * BM * PA * sizeof(T) + 7) / 8);
   const int lt = t - jp->tile0, tiles_m = jp->tiles_m;
   const int row0 = (lt % tiles_m) * BM, col0 = (lt / tiles_m) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -410,6 +426,19 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict
   }
   if (!active) return;
   store_tile<T, TC, RB, CB>(jp, acc, row0 + wr, col0 + wc, lk, l16);
+}
+
+template <typename T, typename TB, typename TC, int CFG>
+__global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC;
+  // sized for FP64 operands, shared by both precisions of a mixed table
+  __shared__ __attribute__((aligned(16))) double smem[2 * BM * (KC + 2) + 2 * KC * (BN + 16)];
+  const int t = xcd_tile(blockIdx.x, total);
+  const GemmJob* jp = jobs + find_job(jobs, njobs, t);
+  if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
+    lds_body<double, double, double, CFG>(jp, t, smem);
+  else
+    lds_body<T, TB, TC, CFG>(jp, t, smem);
 }
 
 namespace {

@@ -16,6 +16,7 @@ namespace pcs {
 // operator by treating each complex column as two real columns.
 struct EigScale;
 struct GemmJob {
+  int type;  // GemmType of this product (a table may mix GEMM_DDD with its own type)
   const void* A;
   const void* B;
   void* C;
@@ -59,7 +60,9 @@ inline int gemm_rows(int m) { return (m + 127) & ~127; }
 // Fills tiles_m / tile0 for tile configuration cfg and returns the total
 // number of workgroups.
 int gemm_prepare(GemmJob* jobs, int njobs, int cfg);
+// t: the table's precision combination; its jobs are of type t or GEMM_DDD.
 void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s);
+
 hipError_t gemm_set_attributes();
 
 // Mixed-radix (8, 4, 2, 3) Stockham plan for a length L = 2^a 3^b.  Per
