@@ -168,7 +168,9 @@ def main():
                     help="c4: the 64-member uneven 2D ensemble, one graph launch per step")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed", "mixed64y"],
                     help="both: time mixed (value) and FP64 (reported beside it)")
-    ap.add_argument("--stage-steps", type=int, default=50)
+    ap.add_argument("--stage-steps", type=int, default=20)
+    ap.add_argument("--stage-reps", type=int, default=5,
+                    help="back-to-back launches of each stage per profiled step (per-launch kernel times)")
     ap.add_argument("--cpu-steps", type=int, default=60)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -221,7 +223,7 @@ def main():
         assert st == P.PCS_OK and len(recs) == min(args.steps, 4096) and recs[-1]["blowup"] == 0
         print("bench: timed %d steps in %.3f ms (wall %.3f s)" % (args.steps, ms, wall), file=sys.stderr, flush=True)
         # per-stage durations (eager launches, HIP events on the run's stream)
-        stages = sim.stage_times(args.stage_steps)
+        stages = sim.stage_times(args.stage_steps, reps=args.stage_reps)
         sim.close()
         timed[prec] = dict(ms=ms, sps=args.steps / (ms / 1e3), stages=stages, prm=prm)
     head = precs[0]

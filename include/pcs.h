@@ -135,14 +135,17 @@ pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
 /* Profiling: runs nsteps real time steps (the state advances exactly as with
  * pcs_step) launched stage by stage, with a HIP event recorded on the
  * handle's stream between stages, and returns in ms[i] the mean duration of
- * stage i over the steps.  Every stage is one kernel launch: the products
+ * one launch of stage i.  Every stage is one kernel launch: the products
  * (gemm_*), the z and x transforms, the RHS, finalize and diagnostics
- * kernels.  nstage must be at least PCS_NSTAGE; stages that do not apply
- * (the z transforms in 2D, the mean-mode products in FP64) report their
- * empty interval.  Stage names come from pcs_stage_name.  Synchronises the
- * stream. */
+ * kernels.  Each stage except the last (the step record) is launched reps
+ * times back to back between its two events (these stages recompute the
+ * same outputs from unchanged inputs), so that with reps > 1 the GPU does
+ * not wait for the host between launches and ms[i] approaches the kernel's
+ * own duration.  nstage must be at least PCS_NSTAGE; stages that do not
+ * apply (the z transforms in 2D) report their empty interval.  Stage names
+ * come from pcs_stage_name.  Synchronises the stream. */
 #define PCS_NSTAGE 12
-pcs_status pcs_stage_times(struct pcs_sim* sim, int32_t nsteps, double* ms, int32_t nstage);
+pcs_status pcs_stage_times(struct pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage);
 const char* pcs_stage_name(int32_t i);
 
 pcs_status pcs_destroy(struct pcs_sim* sim);

@@ -72,7 +72,8 @@ def lib():
     L.pcs_state_size.argtypes = [vp, ctypes.POINTER(sz)]
     L.pcs_get_state.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
     L.pcs_set_state.argtypes = [vp, ctypes.POINTER(ctypes.c_double), sz]
-    L.pcs_stage_times.argtypes = [vp, ctypes.c_int32, ctypes.POINTER(ctypes.c_double), ctypes.c_int32]
+    L.pcs_stage_times.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.c_int32]
     L.pcs_stage_name.argtypes = [st]
     L.pcs_stage_name.restype = ctypes.c_char_p
     L.pcs_destroy.argtypes = [vp]
@@ -185,11 +186,12 @@ class Sim:
         _check(lib().pcs_set_state(self.handle, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), flat.size),
                "pcs_set_state")
 
-    def stage_times(self, nsteps):
-        """Mean milliseconds per stage over nsteps real steps (eager launch,
-        HIP events on this run's stream); returns {stage name: ms}."""
+    def stage_times(self, nsteps, reps=1):
+        """Mean milliseconds per launch of each stage over nsteps real steps
+        (eager launch, every stage but the last repeated reps times back to
+        back, HIP events on this run's stream); returns {stage name: ms}."""
         ms = (ctypes.c_double * PCS_NSTAGE)()
-        _check(lib().pcs_stage_times(self.handle, int(nsteps), ms, PCS_NSTAGE), "pcs_stage_times")
+        _check(lib().pcs_stage_times(self.handle, int(nsteps), int(reps), ms, PCS_NSTAGE), "pcs_stage_times")
         return {lib().pcs_stage_name(i).decode(): ms[i] for i in range(PCS_NSTAGE)}
 
     def synchronize(self):

@@ -4,7 +4,8 @@
 // device workspace, uploads operators and the initial state, computes the
 // per-mode homogeneous solutions of the influence-matrix method with the
 // same device kernels as the step, evaluates the first explicit terms as
-// history, and captures one step as a HIP graph.  pcs_step replays it.
+// history, and captures the step as HIP graphs (one step, and eight steps
+// back to back); pcs_step replays them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -127,7 +128,7 @@ struct Member {
   double *IMN, *DMN, *D, *D2, *PNM, *DP, *V, *Vinv, *DV, *wV, *lam, *d2i0, *d2in, *w, *ydy, *U1, *kx, *kz;
   double *twx, *twz, *twbx, *twbz;
   double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *DN, *Dc, *D2buf, *hgn, *hvn;
-  double *R, *Xs, *Zphi, *Zv, *ZDv, *flux, *CB, *prep, *zbuf;
+  double *R, *Xs, *Zphi, *Zv, *Zg, *ZDv, *flux, *CB, *prep, *zbuf;
   EigScale* es;
   // mixed precision: FP32 operators, twiddles and padded-grid buffers, FP64
   // mean profiles on the padded grid, the FP64 mean column of the explicit
@@ -180,12 +181,15 @@ struct Batch {
   FinArgs* dfin = nullptr;
   int bx = 0, bzi = 0, bzf = 0, bzd = 0, bdr = 0, brhs = 0, bfin = 0;
   size_t lx = 0, lzi = 0, lzf = 0, lzd = 0, ldr = 0;
-  hipGraph_t graph = nullptr;
-  hipGraphExec_t gexec = nullptr;
+  // one step, and GRAPH_STEPS steps back to back (fewer launches between steps)
+  hipGraph_t graph = nullptr, graphn = nullptr;
+  hipGraphExec_t gexec = nullptr, gexecn = nullptr;
   std::vector<JobList*> lists() { return {&GS, &GP, &G4, &G5}; }
   ~Batch() {
-    if (gexec) (void)hipGraphExecDestroy(gexec);
-    if (graph) (void)hipGraphDestroy(graph);
+    for (hipGraphExec_t e : {gexec, gexecn})
+      if (e) (void)hipGraphExecDestroy(e);
+    for (hipGraph_t g : {graph, graphn})
+      if (g) (void)hipGraphDestroy(g);
     for (Member* m : mem) delete m;
   }
 };
@@ -274,6 +278,7 @@ void carve(Member* m, Carve& c) {
   m->es = c.take<EigScale>(1);
   m->Zphi = c.take<double>(ni * cw);
   m->Zv = c.take<double>(ni * cw);
+  m->Zg = d.dim == 3 ? c.take<double>(ni * cw) : nullptr;
   m->ZDv = c.take<double>(n1 * cw);
   m->flux = c.take<double>(cw);
   m->CB = c.take<double>((size_t)d.nc * 2 * cw);
@@ -565,7 +570,7 @@ void build_jobs(Member* m) {
     jl->add(m->V, Xs + fsi, cw, m->Zv, cw, ni, cw, ni);
     jl->add(m->DV, Xs + fsi, cw, m->ZDv, cw, n1, cw, ni);
   }
-  if (d.dim == 3) m->G5.add(m->V, Xs + 2 * fsi, cw, st + 4 * fs + cw, cw, ni, cw, ni);
+  if (d.dim == 3) m->G5.add(m->V, Xs + 2 * fsi, cw, m->Zg, cw, ni, cw, ni);
   for (int a = 0; a < d.nc; ++a) m->G5.add(m->V, Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
   // w . U_p for the flux constraint: the mean column only
   m->G5.add(m->wV, Xs, cw, m->flux, cw, 1, 2, ni);
@@ -848,6 +853,7 @@ void build_batch(Batch* b) {
     q.p = m->p;
     q.Zphi = m->Zphi;
     q.Zv = m->Zv;
+    q.Zg = m->Zg;
     q.ZDv = m->ZDv;
     q.flux = m->flux;
     q.infl = m->infl;
@@ -902,26 +908,25 @@ const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv",  "xpencil",
                                             "gemm_proj",  "rhs",       "gemm_vinv", "gemm_v",
                                             "finalize",   "diag_zfft", "diag_rows", "diag_final"};
 
+// mark(i) returns how many times stage i is launched back to back (1 in a
+// normal step; the profiling path repeats every stage whose outputs do not
+// feed its own inputs, i.e. all but the final diagnostics record).
 struct NoMark {
-  void operator()(int) const {}
+  int operator()(int) const { return 1; }
 };
 
 template <typename Mark>
 void explicit_stage(Batch* b, const Mark& mark) {
   hipStream_t s = b->s;
   const int nm = (int)b->mem.size();
-  mark(ST_GEMM_STATE);
-  b->GS.run(s);
-  mark(ST_ZFFT_INV);
-  if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
-  mark(ST_XPENCIL);
-  launch_xpencil(b->dim, b->prec, b->dx, nm, b->bx, b->lx, s);
-  mark(ST_ZFFT_FWD);
-  if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
-  mark(ST_GEMM_PROJ);
-  b->GP.run(s);
-  mark(ST_RHS);
-  launch_rhs(b->drhs, nm, b->brhs, s);
+  for (int r = mark(ST_GEMM_STATE); r > 0; --r) b->GS.run(s);
+  for (int r = mark(ST_ZFFT_INV); r > 0; --r)
+    if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
+  for (int r = mark(ST_XPENCIL); r > 0; --r) launch_xpencil(b->dim, b->prec, b->dx, nm, b->bx, b->lx, s);
+  for (int r = mark(ST_ZFFT_FWD); r > 0; --r)
+    if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
+  for (int r = mark(ST_GEMM_PROJ); r > 0; --r) b->GP.run(s);
+  for (int r = mark(ST_RHS); r > 0; --r) launch_rhs(b->drhs, nm, b->brhs, s);
 }
 
 template <typename Mark>
@@ -929,18 +934,13 @@ void enqueue_step(Batch* b, const Mark& mark) {
   hipStream_t s = b->s;
   const int nm = (int)b->mem.size();
   explicit_stage(b, mark);
-  mark(ST_GEMM_VINV);
-  b->G4.run(s);
-  mark(ST_GEMM_V);
-  b->G5.run(s);
-  mark(ST_FINALIZE);
-  launch_finalize(b->dfin, nm, b->bfin, s);
-  mark(ST_DIAG_ZFFT);
-  if (b->dim == 3) launch_zfft(0, b->dzd, nm, b->bzd, b->lzd, s);
-  mark(ST_DIAG_ROWS);
-  launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, s);
-  mark(ST_DIAG_FINAL);
-  launch_diag_final(b->ddf, nm, s);
+  for (int r = mark(ST_GEMM_VINV); r > 0; --r) b->G4.run(s);
+  for (int r = mark(ST_GEMM_V); r > 0; --r) b->G5.run(s);
+  for (int r = mark(ST_FINALIZE); r > 0; --r) launch_finalize(b->dfin, nm, b->bfin, s);
+  for (int r = mark(ST_DIAG_ZFFT); r > 0; --r)
+    if (b->dim == 3) launch_zfft(0, b->dzd, nm, b->bzd, b->lzd, s);
+  for (int r = mark(ST_DIAG_ROWS); r > 0; --r) launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, s);
+  for (int r = mark(ST_DIAG_FINAL); r > 0; --r) launch_diag_final(b->ddf, nm, s);
   mark(ST_COUNT);
 }
 
@@ -1058,26 +1058,37 @@ pcs_status history_from_state(Batch* b) {
   return PCS_OK;
 }
 
-pcs_status capture(Batch* b) {
-  if (b->s == nullptr) return PCS_OK;  // the legacy default stream cannot be captured
+constexpr int GRAPH_STEPS = 8;
+
+// Captures `steps` consecutive steps as one graph (null on failure: the
+// caller then launches eagerly).
+void capture_steps(Batch* b, int steps, hipGraph_t* graph, hipGraphExec_t* exec) {
+  *graph = nullptr;
+  *exec = nullptr;
   if (hipStreamBeginCapture(b->s, hipStreamCaptureModeThreadLocal) != hipSuccess) {
     (void)hipGetLastError();
-    return PCS_OK;
+    return;
   }
-  enqueue_step(b, NoMark());
+  for (int i = 0; i < steps; ++i) enqueue_step(b, NoMark());
   hipGraph_t g = nullptr;
   if (hipStreamEndCapture(b->s, &g) != hipSuccess || g == nullptr) {
     (void)hipGetLastError();
-    return PCS_OK;
+    return;
   }
   hipGraphExec_t ge = nullptr;
   if (hipGraphInstantiate(&ge, g, nullptr, nullptr, 0) != hipSuccess) {
     (void)hipGetLastError();
     (void)hipGraphDestroy(g);
-    return PCS_OK;
+    return;
   }
-  b->graph = g;
-  b->gexec = ge;
+  *graph = g;
+  *exec = ge;
+}
+
+pcs_status capture(Batch* b) {
+  if (b->s == nullptr) return PCS_OK;  // the legacy default stream cannot be captured
+  capture_steps(b, 1, &b->graph, &b->gexec);
+  if (b->gexec) capture_steps(b, GRAPH_STEPS, &b->graphn, &b->gexecn);
   return PCS_OK;
 }
 
@@ -1138,7 +1149,11 @@ pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_para
 }
 
 pcs_status step_batch(Batch* b, int32_t nsteps) {
-  for (int i = 0; i < nsteps; ++i) {
+  int left = nsteps;
+  if (b->gexecn)
+    for (; left >= GRAPH_STEPS; left -= GRAPH_STEPS)
+      if (hipGraphLaunch(b->gexecn, b->s) != hipSuccess) return PCS_ERR_DEVICE;
+  for (; left > 0; --left) {
     if (b->gexec) {
       if (hipGraphLaunch(b->gexec, b->s) != hipSuccess) return PCS_ERR_DEVICE;
     } else {
@@ -1265,8 +1280,8 @@ pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
   return PCS_OK;
 }
 
-pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, double* ms, int32_t nstage) {
-  if (!sim || nsteps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
+pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
+  if (!sim || nsteps <= 0 || reps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
   if (sim->m()->blowup) return PCS_ERR_STATE;
   Batch* b = &sim->b;
   hipEvent_t ev[ST_COUNT + 1];
@@ -1274,7 +1289,10 @@ pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, double* ms, int32_t nst
   std::vector<double> acc(ST_COUNT, 0.0);
   pcs_status st = PCS_OK;
   for (int k = 0; k < nsteps && st == PCS_OK; ++k) {
-    enqueue_step(b, [&](int i) { (void)hipEventRecord(ev[i], b->s); });
+    enqueue_step(b, [&](int i) {
+      (void)hipEventRecord(ev[i], b->s);
+      return i == ST_DIAG_FINAL ? 1 : (int)reps;
+    });
     if (hipEventSynchronize(ev[ST_COUNT]) != hipSuccess) {
       st = PCS_ERR_DEVICE;
       break;
@@ -1282,7 +1300,7 @@ pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, double* ms, int32_t nst
     for (int i = 0; i < ST_COUNT; ++i) {
       float t = 0;
       if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) st = PCS_ERR_DEVICE;
-      acc[i] += t;
+      acc[i] += t / (i == ST_DIAG_FINAL ? 1 : reps);
     }
   }
   for (int i = 0; i <= ST_COUNT; ++i) (void)hipEventDestroy(ev[i]);

@@ -230,6 +230,7 @@ __global__ __launch_bounds__(ELEM_THREADS) void finalize_kernel(const FinArgs* _
   const Phys p = A.p;
   const double* __restrict__ Zphi = A.Zphi;
   const double* __restrict__ Zv = A.Zv;
+  const double* __restrict__ Zg = A.Zg;
   const double* __restrict__ ZDv = A.ZDv;
   const double* __restrict__ flux = A.flux;
   const double* __restrict__ infl = A.infl;
@@ -291,8 +292,7 @@ __global__ __launch_bounds__(ELEM_THREADS) void finalize_kernel(const FinArgs* _
     st2(st, (size_t)L.F_PHI * fs + off, cd{0, 0});
     cd W{0, 0};
     if (d.dim == 3) {
-      const double Wv = st[(size_t)L.F_G * fs + off];  // interior rows from the solve, walls zero
-      W = cd{inter ? Wv : 0.0, 0};
+      W = cd{inter ? Zg[offi] : 0.0, 0};  // interior rows from the solve, walls zero
       st2(st, (size_t)L.F_W * fs + off, W);
       st2(st, (size_t)L.F_G * fs + off, cd{0, 0});
     }
@@ -324,8 +324,8 @@ __global__ __launch_bounds__(ELEM_THREADS) void finalize_kernel(const FinArgs* _
     diag_prep(u, v, cd{0, 0});
   } else {
     // g: interior rows come from the solve product, wall rows are zero
-    const cd g = inter ? ld2(st, (size_t)L.F_G * fs + off) : cd{0, 0};
-    if (!inter) st2(st, (size_t)L.F_G * fs + off, cd{0, 0});
+    const cd g = inter ? ld2(Zg, offi) : cd{0, 0};
+    st2(st, (size_t)L.F_G * fs + off, g);
     const cd u = ik2 * (ik(m.kx, Dv) - ik(m.kz, g));
     const cd w = ik2 * (ik(m.kz, Dv) + ik(m.kx, g));
     st2(st, (size_t)L.F_U * fs + off, u);

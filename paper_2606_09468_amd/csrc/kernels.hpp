@@ -204,7 +204,7 @@ struct RhsArgs {
 struct FinArgs {
   Dims d;
   Phys p;
-  const double *Zphi, *Zv, *ZDv, *flux, *infl, *U1;
+  const double *Zphi, *Zv, *Zg, *ZDv, *flux, *infl, *U1;  // Zg: g (3D) interior rows, else null
   double wU1;
   const double *CB, *hvn, *hgn, *S, *smean, *kx, *kz;
   double *st, *prep;
