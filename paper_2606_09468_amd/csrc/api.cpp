@@ -74,7 +74,7 @@ struct JobList {
   // Tile configuration before tuning: the largest tile that still gives
   // every CU a workgroup.
   void prepare() {
-    int c = GEMM_NCFG - 1;
+    int c = 7;  // configurations 0 .. 7 grow with the tile
     while (c > 0 && gemm_prepare(h.data(), n(), c) < 256) --c;
     set_cfg(c);
   }

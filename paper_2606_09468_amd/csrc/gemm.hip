@@ -85,27 +85,37 @@ template <>
 struct RCfg<3> {
   static constexpr int TM = 2, TN = 2, KS = 1;
 };
-// LDS-tiled configurations: BM x BN tile, K chunk KC.
+// LDS-tiled configurations: BM x BN tile, K chunk KC, NBUF LDS buffers (2:
+// the next chunk is written to the other buffer while this one is multiplied;
+// 1: twice the chunk in the same LDS, one more barrier per chunk).
 template <int CFG>
 struct LCfg;
 template <>
 struct LCfg<4> {
-  static constexpr int BM = 32, BN = 32, KC = 32;
+  static constexpr int BM = 32, BN = 32, KC = 32, NBUF = 2;
 };
 template <>
 struct LCfg<5> {
-  static constexpr int BM = 64, BN = 32, KC = 32;
+  static constexpr int BM = 64, BN = 32, KC = 32, NBUF = 2;
 };
 template <>
 struct LCfg<6> {
-  static constexpr int BM = 64, BN = 64, KC = 16;
+  static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 2;
 };
 template <>
 struct LCfg<7> {
-  static constexpr int BM = 128, BN = 64, KC = 16;
+  static constexpr int BM = 128, BN = 64, KC = 16, NBUF = 2;
 };
-constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128};
-constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64};
+template <>
+struct LCfg<8> {
+  static constexpr int BM = 32, BN = 32, KC = 64, NBUF = 1;
+};
+template <>
+struct LCfg<9> {
+  static constexpr int BM = 64, BN = 32, KC = 64, NBUF = 1;
+};
+constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64};
+constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32};
 
 // Workgroup b runs on XCD b % 8; logical tiles are dealt so that XCD x gets
 // one contiguous range (a bijection for any tile count).
@@ -322,7 +332,7 @@ __global__ __launch_bounds__(256) void gemm_reg_kernel(const GemmJob* __restrict
 template <typename T, typename TB, typename TC, int CFG>
 __device__ __attribute__((always_inline)) inline void lds_body(const GemmJob* __restrict__ jp, int t,
                                                                double* smem) {
-  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC;
+  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC, NBUF = LCfg<CFG>::NBUF;
   constexpr int WM = BM / 2, WN = BN / 2, RB = WM / 16, CB = WN / 16;
   // A panel row-major [BM][PA] (pitch KC + 2 keeps the 16 rows of a fragment
   // read on distinct banks), B panel [KC][PB]
@@ -333,8 +343,8 @@ __device__ __attribute__((always_inline)) inline void lds_body(const GemmJob* __
   typedef typename Vec<T>::v4 V4;
   typedef typename Vec<T>::v2 AP;
   typedef typename Vec<TB>::v2 BP;
-  T (*As)[BM * PA] = reinterpret_cast<T (*)[BM * PA]>(smem);
-  T (*Bs)[KC * PB] = reinterpret_cast<T (*)[KC * PB]>(smem + (2 * BM * PA * sizeof(T) + 7) / 8);
+  T (*As)[BM * PA] = reinterpret_cast<T (*)[BM * PA]>(smem);  // [NBUF][BM * PA]
+  T (*Bs)[KC * PB] = reinterpret_cast<T (*)[KC * PB]>(smem + (NBUF * BM * PA * sizeof(T) + 7) / 8);
   const int lt = t - jp->tile0, tiles_m = jp->tiles_m;
   const int row0 = (lt % tiles_m) * BM, col0 = (lt / tiles_m) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -399,30 +409,42 @@ __device__ __attribute__((always_inline)) inline void lds_body(const GemmJob* __
     for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
   const bool active = (row0 + wr < M) && (col0 + wc < N);
   const int nch = (K + KC - 1) / KC;
-  load(0);
-  store(0);
-  __syncthreads();
-  for (int c = 0; c < nch; ++c) {
-    const int buf = c & 1;
-    if (c + 1 < nch) load((c + 1) * KC);
-    if (active) {
-      const T* as = &As[buf][(wr + l16) * PA + lk];
-      const T* bs = &Bs[buf][lk * PB + wc + l16];
+  auto multiply = [&](int buf) {
+    if (!active) return;
+    const T* as = &As[buf][(wr + l16) * PA + lk];
+    const T* bs = &Bs[buf][lk * PB + wc + l16];
 #pragma unroll
-      for (int kq = 0; kq < KC / 4; ++kq) {
-        T a[RB], b[CB];
+    for (int kq = 0; kq < KC / 4; ++kq) {
+      T a[RB], b[CB];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) a[rb] = as[rb * 16 * PA + 4 * kq];
+      for (int rb = 0; rb < RB; ++rb) a[rb] = as[rb * 16 * PA + 4 * kq];
 #pragma unroll
-        for (int cb = 0; cb < CB; ++cb) b[cb] = bs[4 * kq * PB + cb * 16];
+      for (int cb = 0; cb < CB; ++cb) b[cb] = bs[4 * kq * PB + cb * 16];
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-          for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(a[rb], b[cb], acc[rb][cb]);
-      }
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(a[rb], b[cb], acc[rb][cb]);
     }
-    if (c + 1 < nch) store(buf ^ 1);
+  };
+  load(0);
+  if constexpr (NBUF == 2) {
+    store(0);
     __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < nch) load((c + 1) * KC);
+      multiply(buf);
+      if (c + 1 < nch) store(buf ^ 1);
+      __syncthreads();
+    }
+  } else {
+    for (int c = 0; c < nch; ++c) {
+      store(0);
+      __syncthreads();
+      if (c + 1 < nch) load((c + 1) * KC);
+      multiply(0);
+      __syncthreads();
+    }
   }
   if (!active) return;
   store_tile<T, TC, RB, CB>(jp, acc, row0 + wr, col0 + wc, lk, l16);
@@ -430,9 +452,9 @@ __device__ __attribute__((always_inline)) inline void lds_body(const GemmJob* __
 
 template <typename T, typename TB, typename TC, int CFG>
 __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
-  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC;
+  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC, NBUF = LCfg<CFG>::NBUF;
   // sized for FP64 operands, shared by both precisions of a mixed table
-  __shared__ __attribute__((aligned(16))) double smem[2 * BM * (KC + 2) + 2 * KC * (BN + 16)];
+  __shared__ __attribute__((aligned(16))) double smem[NBUF * BM * (KC + 2) + NBUF * KC * (BN + 16)];
   const int t = xcd_tile(blockIdx.x, total);
   const GemmJob* jp = jobs + find_job(jobs, njobs, t);
   if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
@@ -458,6 +480,8 @@ void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStrea
     PCS_GEMM_LAUNCH(gemm_lds_kernel, 5)
     PCS_GEMM_LAUNCH(gemm_lds_kernel, 6)
     PCS_GEMM_LAUNCH(gemm_lds_kernel, 7)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 8)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 9)
     default: break;
   }
 #undef PCS_GEMM_LAUNCH

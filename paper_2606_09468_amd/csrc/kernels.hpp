@@ -52,8 +52,9 @@ constexpr int MAX_JOBS = 64;
 // straight into registers, no LDS in the loop): 0: 32 x 32 with K split over
 // the four waves, 1: 64 x 32 and 2: 32 x 64 with K split in two, 3: 64 x 64.
 // LDS-tiled kernel (operand chunks shared by the four waves through LDS):
-// 4: 32 x 32, 5: 64 x 32, 6: 64 x 64, 7: 128 x 64.
-constexpr int GEMM_NCFG = 8;
+// 4: 32 x 32, 5: 64 x 32, 6: 64 x 64, 7: 128 x 64 (double-buffered chunks),
+// 8: 32 x 32, 9: 64 x 32 (one buffer, chunks of 64 k).
+constexpr int GEMM_NCFG = 10;
 inline int gemm_lda(int k) { return (k + 15) & ~15; }
 inline int gemm_rows(int m) { return (m + 127) & ~127; }
 
