@@ -181,6 +181,7 @@ struct Batch {
   FinArgs* dfin = nullptr;
   int bx = 0, bzi = 0, bzf = 0, bzd = 0, bdr = 0, brhs = 0, bfin = 0;
   size_t lx = 0, lzi = 0, lzf = 0, lzd = 0, ldr = 0;
+  int xnt = 0;  // threads per x-pencil workgroup
   // one step, and GRAPH_STEPS steps back to back (fewer launches between steps)
   hipGraph_t graph = nullptr, graphn = nullptr;
   hipGraphExec_t gexec = nullptr, gexecn = nullptr;
@@ -326,7 +327,12 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   d.lx = g->lx;
   d.lz = g->dim == 2 ? 1.0 : g->lz;
   m->prec = p->precision;
-  if (xpencil_lds_bytes(d.dim, d.px, m->prec) > 160 * 1024) return PCS_ERR_UNSUPPORTED;
+  // every transform's working set must fit one workgroup's LDS
+  const size_t lds_max = 160 * 1024;
+  if (xpencil_lds_bytes(d.dim, d.px, m->prec) > lds_max) return PCS_ERR_UNSUPPORTED;
+  if (diag_rows_lds_bytes(d.nx) > 128 * 1024) return PCS_ERR_UNSUPPORTED;
+  if (d.dim == 3 && (zfft_lds_bytes(d.pz, m->prec) > lds_max || zfft_lds_bytes(d.nz, 0) > lds_max))
+    return PCS_ERR_UNSUPPORTED;
   Phys& q = m->p;
   q.re = p->re;
   q.wi = p->wi;
@@ -873,6 +879,7 @@ void build_batch(Batch* b) {
     b->bfin += eblocks;
     b->hfin.push_back(q);
   }
+  b->xnt = xpencil_threads(b->prec, b->lx);
 }
 
 // Carves every member, builds all tables, and carves the batch's device
@@ -922,7 +929,7 @@ void explicit_stage(Batch* b, const Mark& mark) {
   for (int r = mark(ST_GEMM_STATE); r > 0; --r) b->GS.run(s);
   for (int r = mark(ST_ZFFT_INV); r > 0; --r)
     if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
-  for (int r = mark(ST_XPENCIL); r > 0; --r) launch_xpencil(b->dim, b->prec, b->dx, nm, b->bx, b->lx, s);
+  for (int r = mark(ST_XPENCIL); r > 0; --r) launch_xpencil(b->dim, b->prec, b->xnt, b->dx, nm, b->bx, b->lx, s);
   for (int r = mark(ST_ZFFT_FWD); r > 0; --r)
     if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
   for (int r = mark(ST_GEMM_PROJ); r > 0; --r) b->GP.run(s);

@@ -174,18 +174,19 @@ __device__ inline void butterfly(cx<T>* v, int sign) {
 // One in-place Stockham pass (pass p of the plan, radix R) over nseq
 // sequences of length L: every thread reads its butterfly inputs into
 // registers, the workgroup synchronises, and the outputs go to their sorted
-// positions.  twl[m] = exp(-2 pi i m / L).  Requires nseq L <= NT cover(maxv<T>()).
-template <typename T, int R>
-__device__ void pass_ip(LV<T> buf, int sl, const FftPlan& pl, int p, int nseq, const cx<T>* __restrict__ tw,
+// positions.  twl[m] = exp(-2 pi i m / L).  NTH threads, at most MV complex
+// values per thread: requires nseq L <= NTH cover(MV).
+template <typename T, int R, int NTH, int MV>
+__device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl, const FftPlan& pl, int p, int nseq, const cx<T>* __restrict__ tw,
                         int sign) {
-  constexpr int NB = maxv<T>() / R;
+  constexpr int NB = MV / R;
   const int L = pl.L, LR = pl.lr[p], Ns = pl.ns[p], stride = pl.ts[p];
   const unsigned mLR = pl.mlr[p], mNs = pl.mns[p];
   const int tot = nseq * LR;
   cx<T> v[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int idx = threadIdx.x + q * NT;
+    const int idx = threadIdx.x + q * NTH;
     if (idx < tot) {
       const int s = fdiv(idx, mLR), j = idx - s * LR;
       const LV<T> src = buf.at(s * sl + j);
@@ -196,7 +197,7 @@ __device__ void pass_ip(LV<T> buf, int sl, const FftPlan& pl, int p, int nseq, c
   __syncthreads();
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int idx = threadIdx.x + q * NT;
+    const int idx = threadIdx.x + q * NTH;
     if (idx < tot) {
       const int s = fdiv(idx, mLR), j = idx - s * LR;
       const int k = j - fdiv(j, mNs) * Ns;
@@ -218,25 +219,27 @@ __device__ void pass_ip(LV<T> buf, int sl, const FftPlan& pl, int p, int nseq, c
 }
 
 // nseq sequences of length pl.L, sequence s at buf + s * sl (sl >= L).
-template <typename T>
-__device__ void lds_fft(LV<T> buf, int sl, const FftPlan& pl, int nseq, const cx<T>* __restrict__ tw, int sign) {
+// Inlined at every call: as a called function its register needs add to the
+// caller's (measured: 211-228 VGPRs in the x-pencil and diagnostics kernels).
+template <typename T, int NTH = NT, int MV = maxv<T>()>
+__device__ __attribute__((always_inline)) inline void lds_fft(LV<T> buf, int sl, const FftPlan& pl, int nseq, const cx<T>* __restrict__ tw, int sign) {
   for (int p = 0; p < pl.npass; ++p) {
     const int R = pl.radix[p];
     if (R == 8)
-      pass_ip<T, 8>(buf, sl, pl, p, nseq, tw, sign);
+      pass_ip<T, 8, NTH, MV>(buf, sl, pl, p, nseq, tw, sign);
     else if (R == 4)
-      pass_ip<T, 4>(buf, sl, pl, p, nseq, tw, sign);
+      pass_ip<T, 4, NTH, MV>(buf, sl, pl, p, nseq, tw, sign);
     else if (R == 2)
-      pass_ip<T, 2>(buf, sl, pl, p, nseq, tw, sign);
+      pass_ip<T, 2, NTH, MV>(buf, sl, pl, p, nseq, tw, sign);
     else
-      pass_ip<T, 3>(buf, sl, pl, p, nseq, tw, sign);
+      pass_ip<T, 3, NTH, MV>(buf, sl, pl, p, nseq, tw, sign);
   }
 }
 
 // Largest batch of sequences a pass can hold in registers.
-template <typename T>
+template <typename T, int NTH = NT, int MV = maxv<T>()>
 __host__ __device__ inline int fft_batch(int L) {
-  return (NT * cover(maxv<T>())) / L;
+  return (NTH * cover(MV)) / L;
 }
 
 // Hermitian packing of two real-field spectra A_k, B_k into the complex
@@ -428,8 +431,9 @@ __device__ inline void pointwise_mixed(const Rd& r, const Md& m, T* o) {
 }
 
 // mean: [n_means][M+1] FP64 profiles (MIXED only); pz: padded z rows per y'.
-template <typename T, int DIM, bool MIXED>
-__global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ args, int nmem) {
+template <typename T, int DIM, bool MIXED, int NTH, int MV>
+__global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ args, int nmem) {
+  constexpr int NW = NTH / 64;  // waves
   using XS = XShape<DIM>;
   const XArgs& XA = args[member_of(args, nmem)];
   const T* __restrict__ in = static_cast<const T*>(XA.in);
@@ -446,11 +450,11 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
   const int row = blockIdx.x - XA.blk0, tid = threadIdx.x;
   const size_t fstride = (size_t)nrows * nkx * 2;
   const T* base = in + (size_t)row * nkx * 2;
-  const int S = fft_batch<T>(L);
+  const int S = fft_batch<T, NTH, MV>(L);
   const LV<T> PV{0};
   // twiddle table in LDS (behind the data), read by every radix pass
   cx<T>* twl = P + lds_padded<T>((size_t)XS::NP * L);
-  for (int i = tid; i < L; i += NT) twl[i] = tw[i];
+  for (int i = tid; i < L; i += NTH) twl[i] = tw[i];
   const short* src = XSRC[DIM - 2];
   const short* dxf = XDX[DIM - 2];
   typedef typename V2<T>::type T2;
@@ -460,19 +464,19 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
   for (int b0 = 0; b0 < XS::NP; b0 += S) {
     const int nb = min(S, XS::NP - b0);
     const LV<T> X = PV.at(b0 * L);
-    for (int e = tid; e < nb * L; e += NT) X[e] = cx<T>{0, 0};
+    for (int e = tid; e < nb * L; e += NTH) X[e] = cx<T>{0, 0};
     __syncthreads();
-    // the wave's items are (pair q = wave + 4 i, block of 64 kx); G items'
+    // the wave's items are (pair q = wave + NW i, block of 64 kx); G items'
     // loads are issued before any of them is packed
     const int nkb = (nkx + 63) >> 6;
-    const int items = max(0, (nb - wave + 3) >> 2) * nkb;
+    const int items = max(0, (nb - wave + NW - 1) / NW) * nkb;
     constexpr int G = 4;
     for (int i0 = 0; i0 < items; i0 += G) {
       T2 va[G], vb[G];
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int it = i0 + u, qi = it / nkb, k = lane + 64 * (it - qi * nkb);
-        const int fa = 2 * (b0 + wave + 4 * qi), fb = fa + 1;
+        const int fa = 2 * (b0 + wave + NW * qi), fb = fa + 1;
         va[u] = vb[u] = T2{0, 0};
         if (it < items && k < nkx) {
           va[u] = *reinterpret_cast<const T2*>(base + src[fa] * fstride + 2 * k);
@@ -482,7 +486,7 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int it = i0 + u, qi = it / nkb, k = lane + 64 * (it - qi * nkb);
-        const int q = wave + 4 * qi, fa = 2 * (b0 + q), fb = fa + 1;
+        const int q = wave + NW * qi, fa = 2 * (b0 + q), fb = fa + 1;
         if (it < items && k < nkx) {
           cx<T> A{va[u][0], va[u][1]}, B{vb[u][0], vb[u][1]};
           const bool da = dxf[fa] != 0, db = fb < XS::NREAL && dxf[fb] != 0;
@@ -496,7 +500,7 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
       }
     }
     __syncthreads();
-    lds_fft(X, L, pl, nb, twl, +1);
+    lds_fft<T, NTH, MV>(X, L, pl, nb, twl, +1);
   }
   // pointwise products; outputs overwrite the first pairs at the same point
   T mrow[16];
@@ -505,7 +509,7 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
 #pragma unroll
     for (int i = 0; i < n_means(DIM); ++i) mrow[i] = T(mean[(size_t)i * m1 + yrow]);
   }
-  for (int n = tid; n < L; n += NT) {
+  for (int n = tid; n < L; n += NTH) {
     T o[2 * XS::NOP];
     auto rd = [&](int f) -> T {
       const cx<T>& z = PV[(f >> 1) * L + n];
@@ -527,8 +531,8 @@ __global__ __launch_bounds__(NT) void xpencil_kernel(const XArgs* __restrict__ a
   for (int q0 = 0; q0 < XS::NOP; q0 += S) {
     const int nb = min(S, XS::NOP - q0);
     const LV<T> Z = PV.at(q0 * L);
-    lds_fft(Z, L, pl, nb, twl, -1);
-    for (int q = wave; q < nb; q += NT / 64)
+    lds_fft<T, NTH, MV>(Z, L, pl, nb, twl, -1);
+    for (int q = wave; q < nb; q += NW)
       for (int k = lane; k < nkx; k += 64) {
         cx<T> A, B;
         unpack_pair(Z.at(q * L), L, k, A, B);
@@ -557,8 +561,12 @@ size_t xpencil_lds(int L) {
 // their own frequency in a length-Lz transform; forward: length-Lz data is
 // transformed, divided by Lz and truncated to the retained slots.
 constexpr int ZG = ZFFT_GROUP;
+// Complex values per thread of the z columns: 24 (one register batch holds
+// all 32 columns up to length 192; measured faster than 16 in both precisions,
+// the compiler also allocating fewer registers for it).
+constexpr int ZMV = 24;
 
-template <typename T>
+template <typename T, int MV>
 __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args, int nmem) {
   typedef cx<T> c2;
   const ZArgs& ZA = args[member_of(args, nmem)];
@@ -647,7 +655,10 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
     }
   }
   __syncthreads();
-  lds_fft(AV, SL, pl, ng, twl, inverse ? +1 : -1);
+  // as many columns per batch as one pass holds in registers
+  const int S = fft_batch<T, NT, MV>(L);
+  for (int b0 = 0; b0 < ng; b0 += S)
+    lds_fft<T, NT, MV>(AV.at(b0 * SL), SL, pl, min(S, ng - b0), twl, inverse ? +1 : -1);
   if (inverse) {
     for (int e = tid; e < L * ng; e += NT) {
       const int z = fdiv(e, mng), g = e - z * ng;
@@ -882,18 +893,44 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
 
 }  // namespace
 
-void launch_xpencil(int dim, int precision, const XArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
+// x pencils: 16 complex values per thread (83 VGPRs in FP32 3D, 108 in FP64:
+// five and four waves per SIMD).  A CU runs four or five 256-thread
+// workgroups unless their LDS does not fit four times; then 512-thread
+// workgroups keep 16 waves per CU in flight on the same LDS.
+constexpr int XMV32 = 16;
+int xpencil_threads(int precision, size_t lds) {
+  (void)precision;
+  if (lds == 0) return NT;
+  return (160 * 1024) / lds < 4 ? 2 * NT : NT;
+}
+
+void launch_xpencil(int dim, int precision, int threads, const XArgs* args, int nmem, int blocks, size_t lds,
+                    hipStream_t s) {
   if (blocks <= 0) return;
-  if (precision == 0) {
+  if (precision == 0 && threads == NT) {
     if (dim == 2)
-      hipLaunchKernelGGL((xpencil_kernel<double, 2, false>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+      hipLaunchKernelGGL((xpencil_kernel<double, 2, false, NT, 16>), dim3(blocks), dim3(NT), lds, s, args, nmem);
     else
-      hipLaunchKernelGGL((xpencil_kernel<double, 3, false>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+      hipLaunchKernelGGL((xpencil_kernel<double, 3, false, NT, 16>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+  } else if (precision == 0) {
+    if (dim == 2)
+      hipLaunchKernelGGL((xpencil_kernel<double, 2, false, 2 * NT, 16>), dim3(blocks), dim3(2 * NT), lds, s, args,
+                         nmem);
+    else
+      hipLaunchKernelGGL((xpencil_kernel<double, 3, false, 2 * NT, 16>), dim3(blocks), dim3(2 * NT), lds, s, args,
+                         nmem);
+  } else if (threads == NT) {
+    if (dim == 2)
+      hipLaunchKernelGGL((xpencil_kernel<float, 2, true, NT, XMV32>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+    else
+      hipLaunchKernelGGL((xpencil_kernel<float, 3, true, NT, XMV32>), dim3(blocks), dim3(NT), lds, s, args, nmem);
   } else {
     if (dim == 2)
-      hipLaunchKernelGGL((xpencil_kernel<float, 2, true>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+      hipLaunchKernelGGL((xpencil_kernel<float, 2, true, 2 * NT, XMV32>), dim3(blocks), dim3(2 * NT), lds, s, args,
+                         nmem);
     else
-      hipLaunchKernelGGL((xpencil_kernel<float, 3, true>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+      hipLaunchKernelGGL((xpencil_kernel<float, 3, true, 2 * NT, XMV32>), dim3(blocks), dim3(2 * NT), lds, s, args,
+                         nmem);
   }
 }
 
@@ -902,9 +939,9 @@ int xpencil_blocks(const Dims& d) { return (d.M + 1) * d.pz; }
 void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
   if (blocks <= 0) return;
   if (precision == 0)
-    hipLaunchKernelGGL(zfft_kernel<double>, dim3(blocks), dim3(NT), lds, s, args, nmem);
+    hipLaunchKernelGGL((zfft_kernel<double, ZMV>), dim3(blocks), dim3(NT), lds, s, args, nmem);
   else
-    hipLaunchKernelGGL(zfft_kernel<float>, dim3(blocks), dim3(NT), lds, s, args, nmem);
+    hipLaunchKernelGGL((zfft_kernel<float, ZMV>), dim3(blocks), dim3(NT), lds, s, args, nmem);
 }
 
 int zfft_blocks(int nkx, int rows, int nfields) { return ((nkx + ZG - 1) / ZG) * rows * nfields; }
@@ -928,9 +965,16 @@ void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s) {
 
 hipError_t fft_set_attributes() {
   const int lim = 160 * 1024;
-  const void* k160[] = {(const void*)xpencil_kernel<double, 2, false>, (const void*)xpencil_kernel<double, 3, false>,
-                        (const void*)xpencil_kernel<float, 2, true>,   (const void*)xpencil_kernel<float, 3, true>,
-                        (const void*)zfft_kernel<double>,             (const void*)zfft_kernel<float>};
+  const void* k160[] = {(const void*)xpencil_kernel<double, 2, false, NT, 16>,
+                        (const void*)xpencil_kernel<double, 3, false, NT, 16>,
+                        (const void*)xpencil_kernel<double, 2, false, 2 * NT, 16>,
+                        (const void*)xpencil_kernel<double, 3, false, 2 * NT, 16>,
+                        (const void*)xpencil_kernel<float, 2, true, NT, XMV32>,
+                        (const void*)xpencil_kernel<float, 3, true, NT, XMV32>,
+                        (const void*)xpencil_kernel<float, 2, true, 2 * NT, XMV32>,
+                        (const void*)xpencil_kernel<float, 3, true, 2 * NT, XMV32>,
+                        (const void*)zfft_kernel<double, ZMV>,
+                        (const void*)zfft_kernel<float, ZMV>};
   for (const void* k : k160) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if (e != hipSuccess) return e;

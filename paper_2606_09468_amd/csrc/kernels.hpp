@@ -229,8 +229,12 @@ __device__ inline int member_of(const Args* __restrict__ a, int nmem) {
 }
 
 // precision 0: FP64; otherwise FP32 with the mixed products.  lds: dynamic
-// LDS bytes (the largest member's need).
-void launch_xpencil(int dim, int precision, const XArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
+// LDS bytes (the largest member's need).  The launch shape is chosen once per
+// launch from its largest member: threads per x-pencil workgroup
+// (xpencil_threads of that LDS size).
+int xpencil_threads(int precision, size_t lds);
+void launch_xpencil(int dim, int precision, int threads, const XArgs* args, int nmem, int blocks, size_t lds,
+                    hipStream_t s);
 void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
 void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
 void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s);

@@ -120,6 +120,8 @@ CASES = [
     ("3D 16x17x16 x20", Grid(3, 16, 17, 16), dict(wi=20.0, dt=1e-3), 20),
     ("3D ragged 24x33x12 Wi50 x10", Grid(3, 24, 33, 12), dict(wi=50.0, dt=5e-4), 10),
     ("3D 32x65x32 Wi50 x8", Grid(3, 32, 65, 32), dict(wi=50.0, dt=5e-4), 8),
+    # 32 kx columns of length 144 exceed one register pass: z columns in two batches
+    ("3D wide-z 64x17x96 x3", Grid(3, 64, 17, 96), dict(wi=50.0, dt=5e-4), 3),
 ]
 
 
@@ -281,6 +283,8 @@ MIXED_CASES = [
     ("C1 2D 64x65 x100", Grid(2, 64, 65), dict(wi=20.0, dt=1e-3), 100),
     ("C2 2D 256x257 x50", Grid(2, 256, 257), dict(wi=50.0, dt=5e-4), 50),
     ("3D 32x33x32 x20", Grid(3, 32, 33, 32), dict(wi=50.0, dt=5e-4), 20),
+    # FP32 z columns: 32 of length 288 exceed one register pass (two batches)
+    ("3D wide-z 64x17x192 x3", Grid(3, 64, 17, 192), dict(wi=50.0, dt=5e-4), 3),
 ]
 
 
