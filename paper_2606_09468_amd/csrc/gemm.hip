@@ -114,8 +114,14 @@ template <>
 struct LCfg<9> {
   static constexpr int BM = 64, BN = 32, KC = 64, NBUF = 1;
 };
-constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64};
-constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32};
+constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 0};
+constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 0};
+// operator-stationary kernel: threads, columns per unit, 16-row blocks per
+// panel, LDS bytes for the panel
+constexpr int PNT = 512;
+constexpr int PBN = 64;
+constexpr int PMAXRB = 14;
+constexpr size_t PLDS = 150 * 1024;
 
 // Workgroup b runs on XCD b % 8; logical tiles are dealt so that XCD x gets
 // one contiguous range (a bijection for any tile count).
@@ -149,18 +155,18 @@ __device__ inline double eig_factor(const EigScale& es, int kind, double lam, do
 }
 
 // Stores a lane's RB x CB accumulator blocks whose top-left corner is
-// (r0, c0).  Element D[i][j] of a 16x16 block lives in lane j + 16 * (i / 4),
+// (r0, c0), rows below min(m, mlim) only.  Element D[i][j] of a 16x16 block lives in lane j + 16 * (i / 4),
 // register i % 4 for the f32 instruction, and in lane j + 16 * (i % 4),
 // register i / 4 for the f64 one (checked on gfx950 with a one-hot product).
 // The eigenvalues and wavenumbers the scaling needs are read before the
 // first store.
 template <typename T, typename TC, int RB, int CB, typename V4>
 __device__ inline void store_tile(const GemmJob* __restrict__ jp, const V4 (&acc)[RB][CB], int r0, int c0, int lk,
-                                  int l16) {
+                                  int l16, int mlim = 1 << 30) {
   constexpr bool f64 = sizeof(T) == 8;
   const GemmJob J = *jp;
-  TC* __restrict__ C = static_cast<TC*>(J.C);
-  TC* __restrict__ C2 = static_cast<TC*>(J.C2);
+  const gptr<TC> C = gmem(static_cast<TC*>(J.C));
+  const gptr<TC> C2 = gmem(static_cast<TC*>(J.C2));
   auto row_of = [&](int rb, int r) { return r0 + rb * 16 + (f64 ? 4 * r + lk : 4 * lk + r); };
   auto col_of = [&](int cb) { return c0 + cb * 16 + l16; };
   const bool scaled = J.scale != SCALE_NONE;
@@ -173,7 +179,7 @@ __device__ inline void store_tile(const GemmJob* __restrict__ jp, const V4 (&acc
     for (int cb = 0; cb < CB; ++cb) {
       const int gc = col_of(cb);
       const int mode = gc < J.n ? gc >> 1 : 0, iz = mode / es.nkx, ix = mode - iz * es.nkx;
-      const double kxv = es.kx[ix], kzv = (es.dim == 3) ? es.kz[iz] : 0.0;
+      const double kxv = gmem(es.kx)[ix], kzv = (es.dim == 3) ? gmem(es.kz)[iz] : 0.0;
       k2[cb] = kxv * kxv + kzv * kzv;
       mean[cb] = mode == 0;
     }
@@ -182,7 +188,7 @@ __device__ inline void store_tile(const GemmJob* __restrict__ jp, const V4 (&acc
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = row_of(rb, r);
-        lam[rb][r] = es.lam[gr < J.m ? gr : 0];
+        lam[rb][r] = gmem(es.lam)[gr < J.m ? gr : 0];
       }
   }
 #pragma unroll
@@ -192,9 +198,9 @@ __device__ inline void store_tile(const GemmJob* __restrict__ jp, const V4 (&acc
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
         const int gr = row_of(rb, r), gc = col_of(cb);
-        if (gr < J.m && gc < J.n) {
+        if (gr < J.m && gr < mlim && gc < J.n) {
           const double v = J.alpha * (double)acc[rb][cb][r];
-          TC* cp = C + (size_t)gr * J.ldc + gc;
+          const gptr<TC> cp = C + (size_t)gr * J.ldc + gc;
           double o = scaled ? v * eig_factor(es, J.scale, lam[rb][r], k2[cb], mean[cb]) : v;
           if (J.beta != 0.0) o += J.beta * (double)*cp;
           *cp = TC(o);
@@ -208,6 +214,20 @@ __device__ inline void store_tile(const GemmJob* __restrict__ jp, const V4 (&acc
 }  // namespace
 
 int gemm_prepare(GemmJob* jobs, int njobs, int cfg) {
+  if (cfg == GEMM_PANEL) {
+    // panels: as many operator rows as fit the LDS budget, split evenly
+    int t = 0;
+    for (int j = 0; j < njobs; ++j) {
+      GemmJob& J = jobs[j];
+      const int sz = (J.type == GEMM_FDF || J.type == GEMM_FFD) ? 4 : 8;
+      const int pa = gemm_lda(J.k) + 16 / sz;
+      const int hmax = std::min<int>(PMAXRB * 16, (int)(PLDS / ((size_t)pa * sz)));
+      J.tiles_m = (J.m + hmax - 1) / hmax;
+      J.tile0 = t;
+      t += J.tiles_m * ((J.n + PBN - 1) / PBN);
+    }
+    return t;
+  }
   const int bm = CFG_BM[cfg], bn = CFG_BN[cfg];
   int t = 0;
   for (int j = 0; j < njobs; ++j) {
@@ -242,11 +262,11 @@ __device__ __attribute__((always_inline)) inline void reg_body(const GemmJob* __
     for (int cb = 0; cb < 2; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
 
   if (wrow < M && wcol < N) {
-    const T* A = static_cast<const T*>(jp->A);
-    const TB* B = static_cast<const TB*>(jp->B);
+    const gptr<const T> A = gmem(static_cast<const T*>(jp->A));
+    const gptr<const TB> B = gmem(static_cast<const TB*>(jp->B));
     const int lda = jp->lda, ldb = jp->ldb;
-    const T* ar0 = A + (size_t)(wrow + l16) * lda + 4 * lk;
-    const T* ar1 = ar0 + (size_t)16 * lda;
+    const gptr<const T> ar0 = A + (size_t)(wrow + l16) * lda + 4 * lk;
+    const gptr<const T> ar1 = ar0 + (size_t)16 * lda;
     const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
     const int bc0 = wcol + l16, bc1 = bc0 + 16;
     const bool bok0 = bc0 < N && !(zm && bc0 < 2), bok1 = bc1 < N && !(zm && bc1 < 2);
@@ -256,12 +276,12 @@ __device__ __attribute__((always_inline)) inline void reg_body(const GemmJob* __
     T b0[2][4], b1[2][4], b2[2][4];
     auto load = [&](V4 (&a)[2], T (&b)[2][4], int i) {
       const int kb = 16 * (ks + KS * i);
-      a[0] = *reinterpret_cast<const V4*>(ar0 + kb);
-      a[1] = *reinterpret_cast<const V4*>(ar1 + kb);
+      a[0] = *reinterpret_cast<gptr<const V4>>(ar0 + kb);
+      a[1] = *reinterpret_cast<gptr<const V4>>(ar1 + kb);
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const int kk = kb + 4 * lk + s;
-        const TB* br = B + (size_t)kk * ldb;
+        const gptr<const TB> br = B + (size_t)kk * ldb;
         b[0][s] = (kk < K && bok0) ? T(br[bc0]) : T(0);
         b[1][s] = (kk < K && bok1) ? T(br[bc1]) : T(0);
       }
@@ -351,8 +371,8 @@ __device__ __attribute__((always_inline)) inline void lds_body(const GemmJob* __
   const int l16 = lane & 15, lk = lane >> 4;
   const int wr = (wave >> 1) * WM, wc = (wave & 1) * WN;
   const int M = jp->m, N = jp->n, K = jp->k, lda = jp->lda, ldb = jp->ldb;
-  const T* A = static_cast<const T*>(jp->A);
-  const TB* B = static_cast<const TB*>(jp->B);
+  const gptr<const T> A = gmem(static_cast<const T*>(jp->A));
+  const gptr<const TB> B = gmem(static_cast<const TB*>(jp->B));
 
   // staging positions: a thread's A pairs are (row ra + u RA, k pair 2 kp);
   // its B pairs share one column pair and step through k
@@ -370,15 +390,15 @@ __device__ __attribute__((always_inline)) inline void lds_body(const GemmJob* __
     for (int u = 0; u < NA; ++u) {
       // rows up to gemm_rows(m) are allocated and zero; k pairs stop at K
       const int kk = k0 + kp;
-      ar[u] = kk < K ? *reinterpret_cast<const AP*>(A + (size_t)(row0 + ra + u * RA) * lda + kk) : AP{0, 0};
+      ar[u] = kk < K ? *reinterpret_cast<gptr<const AP>>(A + (size_t)(row0 + ra + u * RA) * lda + kk) : AP{0, 0};
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int kk = k0 + kb + u * SB;
-      const TB* bp = B + (size_t)kk * ldb + gc;
+      const gptr<const TB> bp = B + (size_t)kk * ldb + gc;
       if (bpair) {
         if (kk < K && gc < N) {
-          const BP v = *reinterpret_cast<const BP*>(bp);
+          const BP v = *reinterpret_cast<gptr<const BP>>(bp);
           br[u][0] = v[0];
           br[u][1] = v[1];
         } else {
@@ -463,10 +483,161 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict
     lds_body<T, TB, TC, CFG>(jp, t, smem);
 }
 
+// ------------------------------------------------------------ operator-stationary kernel
+// For wide tables (the 3D fields: thousands of columns per product) one
+// 512-thread workgroup per CU keeps a row panel of the operator in LDS and
+// walks a contiguous range of 64-column units, so every element of B is read
+// from HBM once per panel and the operator once per workgroup.  Unit u of
+// job j is panel (u - tile0) / nch, column chunk (u - tile0) % nch, with
+// nch = ceil(n / 64) and tiles_m the job's panel count (rows split evenly).
+// Wave w takes the 16-column block w % 4 of a unit and the row blocks of
+// parity w / 4; its B values stream through a three-slot register ring of
+// 16-wide k blocks with the k permutation of the register-direct kernel, so
+// an A fragment is four consecutive panel elements (16 or 32 bytes of LDS).
+// Panel rows are PA = round16(k) + 16 / sizeof(T) elements apart, which puts
+// the 16 rows of a fragment read on distinct banks.
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+template <typename T, typename TB, typename TC>
+__device__ __attribute__((always_inline)) inline void panel_run(const GemmJob* __restrict__ jp, int p, int ch0,
+                                                                int ch1, bool load_panel, char* lds) {
+  typedef typename Vec<T>::v4 V4;
+  constexpr int SZ = sizeof(T), HALF = PMAXRB / 2;
+  const int M = jp->m, N = jp->n, K = jp->k;
+  const int K16 = (K + 15) & ~15, PA = K16 + 16 / SZ;
+  const int np = jp->tiles_m, hm = (M + np - 1) / np;
+  const int r0 = p * hm, rows = min(hm, M - r0);
+  T* __restrict__ Ap = reinterpret_cast<T*>(lds);
+  const int tid = threadIdx.x;
+  if (load_panel) {
+    __syncthreads();  // every wave is done with the previous panel
+    const gptr<const char> A = reinterpret_cast<gptr<const char>>(gmem(static_cast<const T*>(jp->A)) + (size_t)r0 * jp->lda);
+    const int vpr = K16 * SZ / 16;  // 16-byte vectors per row
+    for (int e = tid; e < rows * vpr; e += PNT) {
+      const int r = e / vpr, c = e - r * vpr;
+      *reinterpret_cast<u32x4*>(lds + (size_t)r * PA * SZ + 16 * c) =
+          *reinterpret_cast<gptr<const u32x4>>(A + (size_t)r * jp->lda * SZ + 16 * c);
+    }
+    __syncthreads();
+  }
+  const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lk = lane >> 4;
+  const int cb = wave & 3, par = wave >> 2;
+  const int nrb = (rows + 15) >> 4, myrb = (nrb - par + 1) >> 1;
+  const int nkb = K16 >> 4;
+  const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
+  const gptr<const TB> B = gmem(static_cast<const TB*>(jp->B));
+  const int ldb = jp->ldb;
+  // this lane's A fragment row in each of the wave's row blocks (rows past
+  // the panel read its last row; their outputs are not stored)
+  int aoff[HALF];
+#pragma unroll
+  for (int i = 0; i < HALF; ++i) aoff[i] = min((par + 2 * i) * 16 + l16, rows - 1) * PA + 4 * lk;
+  for (int ch = ch0; ch < ch1; ++ch) {
+    const int col = ch * PBN + cb * 16 + l16;
+    const bool cok = col < N && !(zm && col < 2);
+    V4 acc[HALF];
+#pragma unroll
+    for (int i = 0; i < HALF; ++i) acc[i] = V4{0, 0, 0, 0};
+    T b0[4], b1[4], b2[4];
+    auto ld = [&](T (&b)[4], int kb) {
+#pragma unroll
+      for (int s = 0; s < 4; ++s) {
+        const int kk = 16 * kb + 4 * lk + s;
+        b[s] = (kk < K && cok) ? T(B[(size_t)kk * ldb + col]) : T(0);
+      }
+    };
+    // row blocks in pairs: two independent accumulation chains, few live A values
+    auto mul = [&](const T (&b)[4], int kb) {
+#pragma unroll
+      for (int i = 0; i < HALF; i += 2) {
+        if (i >= myrb) break;
+        T a[2][4];
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+          const T* ap = Ap + aoff[i + h < HALF ? i + h : i] + 16 * kb;
+          if constexpr (SZ == 4) {
+            const V4 v = *reinterpret_cast<const V4*>(ap);
+            a[h][0] = v[0];
+            a[h][1] = v[1];
+            a[h][2] = v[2];
+            a[h][3] = v[3];
+          } else {
+            const dbl2 v0 = *reinterpret_cast<const dbl2*>(ap), v1 = *reinterpret_cast<const dbl2*>(ap + 2);
+            a[h][0] = v0[0];
+            a[h][1] = v0[1];
+            a[h][2] = v1[0];
+            a[h][3] = v1[1];
+          }
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+          acc[i] = mfma(a[0][s], b[s], acc[i]);
+          if (i + 1 < HALF && i + 1 < myrb) acc[i + 1] = mfma(a[1][s], b[s], acc[i + 1]);
+        }
+      }
+    };
+    ld(b0, 0);
+    if (nkb > 1) ld(b1, 1);
+    for (int kb = 0; kb < nkb; kb += 3) {
+      if (kb + 2 < nkb) ld(b2, kb + 2);
+      mul(b0, kb);
+      if (kb + 1 >= nkb) break;
+      if (kb + 3 < nkb) ld(b0, kb + 3);
+      mul(b1, kb + 1);
+      if (kb + 2 >= nkb) break;
+      if (kb + 4 < nkb) ld(b1, kb + 4);
+      mul(b2, kb + 2);
+    }
+#pragma unroll
+    for (int i = 0; i < HALF; ++i)
+      if (i < myrb) {
+        const V4 one[1][1] = {{acc[i]}};
+        store_tile<T, TC, 1, 1>(jp, one, r0 + (par + 2 * i) * 16, ch * PBN + cb * 16, lk, l16, r0 + rows);
+      }
+  }
+}
+
+template <typename T, typename TB, typename TC>
+__global__ __launch_bounds__(PNT) void gemm_panel_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+  extern __shared__ __attribute__((aligned(16))) char panel_lds[];
+  const int G = gridDim.x, w = blockIdx.x;
+  const int u1 = (int)((long long)total * (w + 1) / G);
+  int u = (int)((long long)total * w / G);
+  const void* curA = nullptr;
+  int curp = -1;
+  while (u < u1) {
+    const GemmJob* jp = jobs + find_job(jobs, njobs, u);
+    const int nch = (jp->n + PBN - 1) / PBN;
+    const int local = u - jp->tile0, p = local / nch;
+    const int end = min(u1, jp->tile0 + (p + 1) * nch);  // the rest of this panel's units
+    // consecutive products of one operator (single panel) keep it in LDS
+    const bool load = jp->A != curA || p != curp;
+    curA = jp->A;
+    curp = p;
+    const int ch0 = local - p * nch, ch1 = ch0 + (end - u);
+    if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
+      panel_run<double, double, double>(jp, p, ch0, ch1, load, panel_lds);
+    else
+      panel_run<T, TB, TC>(jp, p, ch0, ch1, load, panel_lds);
+    u = end;
+  }
+}
+
 namespace {
 
 template <typename T, typename TB, typename TC>
 void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStream_t s) {
+  if (cfg == GEMM_PANEL) {
+    static int ncu = 0;
+    if (!ncu) {
+      hipDeviceProp_t pr;
+      ncu = hipGetDeviceProperties(&pr, 0) == hipSuccess ? pr.multiProcessorCount : 256;
+    }
+    hipLaunchKernelGGL((gemm_panel_kernel<T, TB, TC>), dim3(std::min(total, ncu)), dim3(PNT), PLDS, s, dev_jobs,
+                       njobs, total);
+    return;
+  }
 #define PCS_GEMM_LAUNCH(KERNEL, C)                                                                    \
   case C:                                                                                             \
     hipLaunchKernelGGL((KERNEL<T, TB, TC, C>), dim3(total), dim3(256), 0, s, dev_jobs, njobs, total); \
@@ -489,7 +660,18 @@ void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStrea
 
 }  // namespace
 
-hipError_t gemm_set_attributes() { return hipSuccess; }
+hipError_t gemm_set_attributes() {
+  const void* k[] = {(const void*)gemm_panel_kernel<double, double, double>,
+                     (const void*)gemm_panel_kernel<float, double, float>,
+                     (const void*)gemm_panel_kernel<float, float, double>,
+                     (const void*)gemm_panel_kernel<double, double, float>,
+                     (const void*)gemm_panel_kernel<double, float, double>};
+  for (const void* f : k) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLDS);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s) {
   if (total_tiles <= 0 || njobs <= 0 || cfg < 0 || cfg >= GEMM_NCFG) return;

@@ -7,6 +7,19 @@
 
 namespace pcs {
 
+// Global-memory view of a pointer read from an argument table.  Pointers
+// loaded from device memory are generic to the compiler, and generic (flat)
+// accesses also count as LDS operations: every wait for an LDS access would
+// then wait for all outstanding global loads too, which serialises prefetch
+// with compute.  Casting to the global address space yields global_load /
+// global_store instructions instead.
+template <typename T>
+using gptr = __attribute__((address_space(1))) T*;
+template <typename T>
+__device__ inline gptr<T> gmem(T* p) {
+  return (gptr<T>)p;
+}
+
 // One dense product C = alpha * A * B + beta * C, real.  A (m x k) is stored
 // row-major in the compute precision, A[i][kk] at A[i * lda + kk], with
 // lda = gemm_lda(k) and gemm_rows(m) rows allocated, all padding zero (the
@@ -54,7 +67,11 @@ constexpr int MAX_JOBS = 64;
 // LDS-tiled kernel (operand chunks shared by the four waves through LDS):
 // 4: 32 x 32, 5: 64 x 32, 6: 64 x 64, 7: 128 x 64 (double-buffered chunks),
 // 8: 32 x 32, 9: 64 x 32 (one buffer, chunks of 64 k).
-constexpr int GEMM_NCFG = 10;
+// Operator-stationary kernel (10, wide tables): one 512-thread workgroup per
+// CU holds a row panel of the operator in LDS and streams 64-column units of
+// B through it.
+constexpr int GEMM_PANEL = 10;
+constexpr int GEMM_NCFG = 11;
 inline int gemm_lda(int k) { return (k + 15) & ~15; }
 inline int gemm_rows(int m) { return (m + 127) & ~127; }
 
