@@ -24,7 +24,8 @@ struct Mode {
   bool mean, nyq;
 };
 
-__device__ inline Mode decode(const Dims& d, int e, const double* kx, const double* kz) {
+template <typename P>
+__device__ inline Mode decode(const Dims& d, int e, P kx, P kz) {
   Mode m;
   m.j = e / d.nm;
   m.mode = e - m.j * d.nm;
@@ -41,8 +42,12 @@ __device__ inline Mode decode(const Dims& d, int e, const double* kx, const doub
 struct cd {
   double r, i;
 };
-__device__ inline cd ld2(const double* f, size_t off) { return cd{f[off], f[off + 1]}; }
-__device__ inline void st2(double* f, size_t off, cd v) {
+template <typename P>
+__device__ inline cd ld2(P f, size_t off) {
+  return cd{f[off], f[off + 1]};
+}
+template <typename P>
+__device__ inline void st2(P f, size_t off, cd v) {
   f[off] = v.r;
   f[off + 1] = v.i;
 }
@@ -103,20 +108,20 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
   const RhsArgs& A = args[member_of(args, nmem)];
   const Dims d = A.d;
   const Phys p = A.p;
-  const double* __restrict__ st = A.st;
-  const double* __restrict__ D2buf = A.D2buf;
-  const double* __restrict__ Dc = A.Dc;
-  const double* __restrict__ S = A.S;
-  const double* __restrict__ smean = A.smean;
-  const double* __restrict__ DN = A.DN;
-  const double* __restrict__ kx = A.kx;
-  const double* __restrict__ kz = A.kz;
-  const double* __restrict__ d2i0 = A.d2i0;
-  const double* __restrict__ d2in = A.d2in;
-  double* __restrict__ R = A.R;
-  double* __restrict__ hvn = A.hvn;
-  double* __restrict__ hgn = A.hgn;
-  double* __restrict__ CB = A.CB;
+  const auto st = gmem(A.st);
+  const auto D2buf = gmem(A.D2buf);
+  const auto Dc = gmem(A.Dc);
+  const auto S = gmem(A.S);
+  const auto smean = gmem(A.smean);
+  const auto DN = gmem(A.DN);
+  const auto kx = gmem(A.kx);
+  const auto kz = gmem(A.kz);
+  const auto d2i0 = gmem(A.d2i0);
+  const auto d2in = gmem(A.d2in);
+  const auto R = gmem(A.R);
+  const auto hvn = gmem(A.hvn);
+  const auto hgn = gmem(A.hgn);
+  const auto CB = gmem(A.CB);
   const int n1 = d.N + 1, N = d.N, ni = d.N - 1;
   const int e = (blockIdx.x - A.blk0) * blockDim.x + threadIdx.x;
   if (e >= n1 * d.nm) return;
@@ -164,8 +169,8 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
     st2(hgn, off, hg);
   }
   st2(hvn, off, hv);
-  const double* D2U = D2buf + (size_t)L.nsolve * fs;
-  const double* D2W = D2U + n1;
+  const auto D2U = D2buf + (size_t)L.nsolve * fs;
+  const auto D2W = D2U + n1;
   if (inter) {
     cd r;
     const cd hvo = ld2(st, (size_t)L.H_HV * fs + off);
@@ -191,8 +196,8 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
   }
   const double a_int = 1.0 / dt - 0.5 / p.wi, a_new = 1.0 / dt + 0.5 / p.wi;
   for (int a = 0; a < d.nc; ++a) {
-    const double* cf = st + (size_t)(L.F_C + a) * fs;
-    const double* Fo = st + (size_t)(L.H_F + a) * fs;
+    const auto cf = st + (size_t)(L.F_C + a) * fs;
+    const auto Fo = st + (size_t)(L.H_F + a) * fs;
     const bool diag = (d.dim == 2) ? (a == 0 || a == 2) : (a == 0 || a == 3 || a == 5);
     const cd src = cd{(m.mean && diag) ? 1.0 / p.wi : 0.0, 0};
     const int o = L.S_F + a;
@@ -228,23 +233,23 @@ __global__ __launch_bounds__(ELEM_THREADS) void finalize_kernel(const FinArgs* _
   const FinArgs& A = args[member_of(args, nmem)];
   const Dims d = A.d;
   const Phys p = A.p;
-  const double* __restrict__ Zphi = A.Zphi;
-  const double* __restrict__ Zv = A.Zv;
-  const double* __restrict__ Zg = A.Zg;
-  const double* __restrict__ ZDv = A.ZDv;
-  const double* __restrict__ flux = A.flux;
-  const double* __restrict__ infl = A.infl;
-  const double* __restrict__ U1 = A.U1;
+  const auto Zphi = gmem(A.Zphi);
+  const auto Zv = gmem(A.Zv);
+  const auto Zg = gmem(A.Zg);
+  const auto ZDv = gmem(A.ZDv);
+  const auto flux = gmem(A.flux);
+  const auto infl = gmem(A.infl);
+  const auto U1 = gmem(A.U1);
   const double wU1 = A.wU1;
-  const double* __restrict__ CB = A.CB;
-  const double* __restrict__ hvn = A.hvn;
-  const double* __restrict__ hgn = A.hgn;
-  const double* __restrict__ S = A.S;
-  const double* __restrict__ smean = A.smean;
-  const double* __restrict__ kx = A.kx;
-  const double* __restrict__ kz = A.kz;
-  double* __restrict__ st = A.st;
-  double* __restrict__ prep = A.prep;
+  const auto CB = gmem(A.CB);
+  const auto hvn = gmem(A.hvn);
+  const auto hgn = gmem(A.hgn);
+  const auto S = gmem(A.S);
+  const auto smean = gmem(A.smean);
+  const auto kx = gmem(A.kx);
+  const auto kz = gmem(A.kz);
+  const auto st = gmem(A.st);
+  const auto prep = gmem(A.prep);
   DevScalars* __restrict__ sc = A.sc;
   const int n1 = d.N + 1, N = d.N;
   const int e = (blockIdx.x - A.blk0) * blockDim.x + threadIdx.x;
@@ -301,7 +306,7 @@ __global__ __launch_bounds__(ELEM_THREADS) void finalize_kernel(const FinArgs* _
   }
   const size_t pm = (size_t)n1 * d.nm;
   const size_t io = (size_t)j * d.nm + m.mode;
-  const double* Ai = infl + 6 * pm;
+  const auto Ai = infl + 6 * pm;
   const double a00 = Ai[0 * d.nm + m.mode], a01 = Ai[1 * d.nm + m.mode];
   const double a10 = Ai[2 * d.nm + m.mode], a11 = Ai[3 * d.nm + m.mode];
   const cd dp0 = ld2(ZDv, 2 * (size_t)m.mode), dpN = ld2(ZDv, (size_t)N * d.cw + 2 * m.mode);

@@ -359,7 +359,7 @@ __host__ __device__ constexpr int n_means(int dim) { return dim == 2 ? 8 : 16; }
 // profiles only the y-derivatives of the mean velocity (U', W') survive
 // (v = 0, d/dx = d/dz = 0), so N = 0 and F_ab = U'_a c_yb + c_ay U'_b with
 // U'_x = U', U'_z = W'.
-__device__ inline double mean_product(int dim, int o, const double* __restrict__ mean, int m1, int i) {
+__device__ inline double mean_product(int dim, int o, gptr<const double> mean, int m1, int i) {
   auto M = [&](int k) { return mean[(size_t)k * m1 + i]; };
   if (dim == 2) {
     // means: U U' cxx cxy cyy ...; outputs: Nx Ny Fxx Fxy Fyy
@@ -436,28 +436,33 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
   constexpr int NW = NTH / 64;  // waves
   using XS = XShape<DIM>;
   const XArgs& XA = args[member_of(args, nmem)];
-  const T* __restrict__ in = static_cast<const T*>(XA.in);
-  T* __restrict__ out = static_cast<T*>(XA.out);
+  const gptr<const T> in = gmem(static_cast<const T*>(XA.in));
+  const gptr<T> out = gmem(static_cast<T*>(XA.out));
   const int nrows = XA.nrows, nkx = XA.nkx, m1 = XA.m1, pz = XA.pz;
   const FftPlan& pl = XA.pl;
-  const double* __restrict__ kx = XA.kx;
-  const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(XA.tw);
+  const gptr<const double> kx = gmem(XA.kx);
   const double eps_wi = XA.eps_wi;
-  const double* __restrict__ mean = XA.mean;
-  double* __restrict__ mcol = XA.mcol;
+  const gptr<const double> mean = gmem(XA.mean);
+  const gptr<double> mcol = gmem(XA.mcol);
   cx<T>* P = reinterpret_cast<cx<T>*>(fft_lds);
   const int L = pl.L;
   const int row = blockIdx.x - XA.blk0, tid = threadIdx.x;
   const size_t fstride = (size_t)nrows * nkx * 2;
-  const T* base = in + (size_t)row * nkx * 2;
+  const gptr<const T> base = in + (size_t)row * nkx * 2;
   const int S = fft_batch<T, NTH, MV>(L);
   const LV<T> PV{0};
   // twiddle table in LDS (behind the data), read by every radix pass
   cx<T>* twl = P + lds_padded<T>((size_t)XS::NP * L);
-  for (int i = tid; i < L; i += NTH) twl[i] = tw[i];
+  typedef typename V2<T>::type T2;
+  {
+    const gptr<const T2> tw = gmem(static_cast<const T2*>(XA.tw));
+    for (int i = tid; i < L; i += NTH) {
+      const T2 t = tw[i];
+      twl[i] = cx<T>{t[0], t[1]};
+    }
+  }
   const short* src = XSRC[DIM - 2];
   const short* dxf = XDX[DIM - 2];
-  typedef typename V2<T>::type T2;
   // each wave packs whole field pairs, so the field tables are read once per
   // pair (wave-uniform) and the lanes stream one field's kx modes
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -479,8 +484,8 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
         const int fa = 2 * (b0 + wave + NW * qi), fb = fa + 1;
         va[u] = vb[u] = T2{0, 0};
         if (it < items && k < nkx) {
-          va[u] = *reinterpret_cast<const T2*>(base + src[fa] * fstride + 2 * k);
-          if (fb < XS::NREAL) vb[u] = *reinterpret_cast<const T2*>(base + src[fb] * fstride + 2 * k);
+          va[u] = *reinterpret_cast<gptr<const T2>>(base + src[fa] * fstride + 2 * k);
+          if (fb < XS::NREAL) vb[u] = *reinterpret_cast<gptr<const T2>>(base + src[fb] * fstride + 2 * k);
         }
       }
 #pragma unroll
@@ -527,7 +532,7 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
   }
   __syncthreads();
   const T inv = T(1.0 / L);
-  T* obase = out + (size_t)row * nkx * 2;
+  const gptr<T> obase = out + (size_t)row * nkx * 2;
   for (int q0 = 0; q0 < XS::NOP; q0 += S) {
     const int nb = min(S, XS::NOP - q0);
     const LV<T> Z = PV.at(q0 * L);
@@ -537,8 +542,8 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
         cx<T> A, B;
         unpack_pair(Z.at(q * L), L, k, A, B);
         const int fa = 2 * (q0 + q), fb = fa + 1;
-        *reinterpret_cast<T2*>(obase + (size_t)fa * fstride + 2 * k) = T2{A.x * inv, A.y * inv};
-        if (fb < XS::NOUT) *reinterpret_cast<T2*>(obase + (size_t)fb * fstride + 2 * k) = T2{B.x * inv, B.y * inv};
+        *reinterpret_cast<gptr<T2>>(obase + (size_t)fa * fstride + 2 * k) = T2{A.x * inv, A.y * inv};
+        if (fb < XS::NOUT) *reinterpret_cast<gptr<T2>>(obase + (size_t)fb * fstride + 2 * k) = T2{B.x * inv, B.y * inv};
         if constexpr (MIXED && DIM == 2) {
           // the kx = 0 column is the whole mean (2D has no z): complete it in FP64
           if (k == 0) {
@@ -570,16 +575,15 @@ template <typename T, int MV>
 __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args, int nmem) {
   typedef cx<T> c2;
   const ZArgs& ZA = args[member_of(args, nmem)];
-  const T* __restrict__ in = static_cast<const T*>(ZA.in);
-  T* __restrict__ out = static_cast<T*>(ZA.out);
+  const gptr<const T> in = gmem(static_cast<const T*>(ZA.in));
+  const gptr<T> out = gmem(static_cast<T*>(ZA.out));
   const int nkx = ZA.nkx, nzs = ZA.nzs, rows_y = ZA.rows, inverse = ZA.inverse;
   const FftPlan& pl = ZA.pl;
-  const int* __restrict__ src_field = ZA.src_field;
-  const int* __restrict__ deriv = ZA.deriv;
-  const double* __restrict__ kz = ZA.kz;
-  const cx<T>* __restrict__ tw = static_cast<const cx<T>*>(ZA.tw);
-  const double* __restrict__ mean = ZA.mean;
-  double* __restrict__ mcol = ZA.mcol;
+  const int* src_field = ZA.src_field;
+  const int* deriv = ZA.deriv;
+  const gptr<const double> kz = gmem(ZA.kz);
+  const gptr<const double> mean = gmem(ZA.mean);
+  const gptr<double> mcol = gmem(ZA.mcol);
   c2* A = reinterpret_cast<c2*>(fft_lds);
   const int L = pl.L;
   // sequences (one per kx column) at stride L + 1: the column-wise loads and
@@ -587,7 +591,14 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
   const int SL = L + 1;
   const LV<T> AV{0};
   c2* twl = A + lds_padded<T>((size_t)ZG * SL);  // twiddle table behind the data
-  for (int e = threadIdx.x; e < L; e += NT) twl[e] = tw[e];
+  typedef typename V2<T>::type T2;
+  {
+    const gptr<const T2> tw = gmem(static_cast<const T2*>(ZA.tw));
+    for (int e = threadIdx.x; e < L; e += NT) {
+      const T2 t = tw[e];
+      twl[e] = c2{t[0], t[1]};
+    }
+  }
   // local workgroup -> (kx group, row, field)
   const int lb = blockIdx.x - ZA.blk0;
   const int gx = lb % ZA.ngx, i = (lb / ZA.ngx) % rows_y, f = lb / (ZA.ngx * rows_y);
@@ -598,12 +609,11 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
   const int rin = inverse ? nzs : L, rout = inverse ? L : nzs;
   const int sf = src_field ? src_field[f] : f;
   const int dz = deriv ? deriv[f] : 0;
-  const T* ib = in + ((size_t)sf * rows_y + i) * rin * nkx * 2;
-  T* ob = out + ((size_t)f * rows_y + i) * rout * nkx * 2;
+  const gptr<const T> ib = in + ((size_t)sf * rows_y + i) * rin * nkx * 2;
+  const gptr<T> ob = out + ((size_t)f * rows_y + i) * rout * nkx * 2;
   // gather PER elements per thread before writing LDS, so that many global
   // loads are in flight at once
   constexpr int PER = 8;
-  typedef typename V2<T>::type T2;
   if (inverse) {
     for (int e = tid; e < ZG * SL; e += NT) AV[e] = c2{0, 0};
     __syncthreads();
@@ -618,7 +628,7 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
         if (e < tot) {
           const int s = fdiv(e, mng), g = e - s * ng;
           if (!(nzs > 1 && s == nzs / 2)) {
-            const T2 x = *reinterpret_cast<const T2*>(ib + ((size_t)s * nkx + k0 + g) * 2);
+            const T2 x = *reinterpret_cast<gptr<const T2>>(ib + ((size_t)s * nkx + k0 + g) * 2);
             v[u] = c2{x[0], x[1]};
             if (dz) {
               const T kk = T(kz[s]);
@@ -644,7 +654,7 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
         pos[u] = -1;
         if (e < tot) {
           const int z = fdiv(e, mng), g = e - z * ng;
-          const T2 x = *reinterpret_cast<const T2*>(ib + ((size_t)z * nkx + k0 + g) * 2);
+          const T2 x = *reinterpret_cast<gptr<const T2>>(ib + ((size_t)z * nkx + k0 + g) * 2);
           v[u] = c2{x[0], x[1]};
           pos[u] = g * SL + z;
         }
@@ -663,7 +673,7 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
     for (int e = tid; e < L * ng; e += NT) {
       const int z = fdiv(e, mng), g = e - z * ng;
       const c2 v = AV[g * SL + z];
-      *reinterpret_cast<T2*>(ob + ((size_t)z * nkx + k0 + g) * 2) = T2{v.x, v.y};
+      *reinterpret_cast<gptr<T2>>(ob + ((size_t)z * nkx + k0 + g) * 2) = T2{v.x, v.y};
     }
   } else {
     const T inv = T(1.0 / L);
@@ -674,7 +684,7 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
         const int mz = (s < nzs / 2) ? s : s - nzs;
         v = scal(inv, AV[g * SL + (mz < 0 ? mz + L : mz)]);
       }
-      *reinterpret_cast<T2*>(ob + ((size_t)s * nkx + k0 + g) * 2) = T2{v.x, v.y};
+      *reinterpret_cast<gptr<T2>>(ob + ((size_t)s * nkx + k0 + g) * 2) = T2{v.x, v.y};
       // mixed forward transform: the kx = kz = 0 value completed in FP64
       if (mcol && s == 0 && k0 + g == 0)
         mcol[(size_t)f * rows_y + i] = double(v.x) + mean_product(3, f, mean, rows_y, i);
@@ -714,11 +724,10 @@ __device__ inline int wave_or(int v) {
 __global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restrict__ args, int nmem) {
   const DRowArgs& DA = args[member_of(args, nmem)];
   const Dims d = DA.d;
-  const double* __restrict__ in = DA.in;
+  const gptr<const double> in = gmem(DA.in);
   const int zrows = DA.zrows;
   const FftPlan& pl = DA.pl;
-  const c2* __restrict__ tw = reinterpret_cast<const c2*>(DA.tw);
-  const double* __restrict__ ydy = DA.ydy;
+  const gptr<const double> ydy = gmem(DA.ydy);
   DiagPart* __restrict__ parts = DA.parts;
   c2* A = reinterpret_cast<c2*>(fft_lds);
   __shared__ DiagPart wpart[NT / 64];
@@ -726,12 +735,19 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restric
   const unsigned mkx = fast_div_magic((unsigned)nkx);
   const LV<double> AV{0};
   c2* twl = A + lds_padded<double>(2 * (size_t)L);  // twiddle table behind the data
-  for (int e = threadIdx.x; e < L; e += NT) twl[e] = tw[e];
+  {
+    typedef V2<double>::type D2;
+    const gptr<const D2> tw = gmem(reinterpret_cast<const D2*>(DA.tw));
+    for (int e = threadIdx.x; e < L; e += NT) {
+      const D2 t = tw[e];
+      twl[e] = c2{t[0], t[1]};
+    }
+  }
   const int row = blockIdx.x - DA.blk0, tid = threadIdx.x;
   const int nrows = (d.N + 1) * zrows;
   const int j = row / zrows;
   const size_t fstride = (size_t)nrows * nkx * 2;
-  const double* base = in + (size_t)row * nkx * 2;
+  const gptr<const double> base = in + (size_t)row * nkx * 2;
   for (int e = tid; e < 2 * L; e += NT) AV[e] = c2{0, 0};
   __syncthreads();
   const int nf = d.dim == 2 ? 3 : 4;
