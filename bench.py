@@ -28,8 +28,11 @@ from paper_2606_09468_amd.workloads import ENSEMBLE, WORKLOADS, ensemble_members
 
 def stage_work(w, precision):
     """Algorithmic work of one launch of each stage kernel at this workload:
-    {stage: (bound, amount, peak)}.  Products: ('mfma', 2 m n k summed over
-    the table, peak of the compute precision).  Transform and elementwise
+    {stage: (bound, amount, peak)}.  Products: ('mfma', flops summed over
+    the table, peak of the compute precision), each wall-normal product in its
+    parity form: an m x k centro(anti)symmetric operator on n columns costs
+    2 ceil(m/2) k n (the even and odd halves), the eigenbasis products
+    2 (ne^2 + no^2) n with ne, no the even and odd eigenvector counts.  Transform and elementwise
     kernels: ('hbm', bytes), every input field read once and every output
     written once, complex values of the kernel's precision (FP32 in the mixed
     transforms, FP64 elsewhere); small per-mode tables are not counted."""
@@ -61,9 +64,12 @@ def stage_work(w, precision):
         flops = sum(f for f, _ in parts)
         ideal = sum(f / (p * 1e12) for f, p in parts)
         return ("mfma", flops, flops / ideal / 1e12)
-    state = [((dim + nc + nderiv + nc) * 2 * m1 * cw * n1, pk(f32_state)),                  # to the padded grid
-             ((nsolve + nc) * 2 * n1 * cw * n1 + (dim - 1) * 2 * n1 * n1, MFMA_F64_TFS)]  # D2, D of the state
-    proj = [((nout + dim - 1) * 2 * n1 * cw * m1, pk(f32_proj))]                           # P N, (D P) N
+    half = lambda r: (r + 1) // 2
+    ne, no = half(ni), ni // 2
+    eig = 2 * (ne * ne + no * no) * cw      # one product in the eigenbasis (either direction)
+    state = [((dim + nc + nderiv + nc) * 2 * half(m1) * cw * n1, pk(f32_state)),                  # to the padded grid
+             ((nsolve + nc) * 2 * half(n1) * cw * n1 + (dim - 1) * 2 * n1 * n1, MFMA_F64_TFS)]  # D2, D of the state
+    proj = [((nout + dim - 1) * 2 * half(n1) * cw * m1, pk(f32_proj))]                           # P N, (D P) N
     if mixed:
         state.append(((2 * (dim - 1) + 2 * nc) * 2 * m1 * n1, MFMA_F64_TFS))               # mean profiles
         proj.append((nout * 2 * n1 * m1, MFMA_F64_TFS))                                    # mean column
@@ -76,8 +82,8 @@ def stage_work(w, precision):
     else:
         out["xpencil"] = ("hbm", (nyin + nout) * m1 * nkx * tb, HBM_PEAK_GBS)
     out["gemm_proj"] = mixed_table(proj)
-    out["gemm_vinv"] = ("mfma", nsolve * 2 * ni * cw * ni, MFMA_F64_TFS)
-    out["gemm_v"] = ("mfma", (2 + (dim - 2) + nc) * 2 * ni * cw * ni + 2 * n1 * cw * ni + 2 * 2 * ni, MFMA_F64_TFS)
+    out["gemm_vinv"] = ("mfma", nsolve * eig, MFMA_F64_TFS)
+    out["gemm_v"] = ("mfma", (2 + (dim - 2) + nc) * eig + 2 * half(n1) * cw * ni + 2 * 2 * ni, MFMA_F64_TFS)
     fld = n1 * nm * 16                     # one FP64 spectral field
     rhs_in = (nsv + nc) + nh + nsolve + nc + nout + (dim - 1)
     rhs_out = nsolve + (dim - 1)

@@ -43,11 +43,15 @@ struct Carve {
   }
 };
 
+// A table of products in two equivalent forms: form 0 evaluates every
+// product plainly, form 1 the wall-normal ones as parity products (half-size
+// E and O products, see GemmJob).  The autotuner times both and keeps the
+// faster form and tile configuration; h is the form in use.
 struct JobList {
-  std::vector<GemmJob> h;
+  std::vector<GemmJob> h, forms[2];
   GemmJob* dev = nullptr;
   GemmType type = GEMM_DDD;
-  int tiles = 0, cfg = 0;
+  int tiles = 0, cfg = 0, form = 0;
   void add(const void* A, const void* B, int ldb, void* C, int ldc, int m, int n, int k, int flags = 0,
            int scale = SCALE_NONE, const EigScale* es = nullptr, void* C2 = nullptr, int scale2 = SCALE_NONE) {
     GemmJob j{};
@@ -68,14 +72,45 @@ struct JobList {
     j.scale = scale;
     j.scale2 = scale2;
     j.es = es;
-    h.push_back(j);
+    forms[0].push_back(j);
+    forms[1].push_back(j);
   }
-  int n() const { return (int)h.size(); }
+  // Parity product (kinds and operator halves as described with GemmJob):
+  // E and O have mh rows and ke columns; the full sizes are mf and kf.
+  // A is the full operator (the plain form's product), Ae / Ao its halves.
+  void addp(int kind, const void* A, const void* Ae, const void* Ao, const void* B, int ldb, void* C, int ldc, int mh,
+            int n, int ke, int mf, int kf, int sigma, int flags = 0, int scale = SCALE_NONE,
+            const EigScale* es = nullptr, void* C2 = nullptr, int scale2 = SCALE_NONE) {
+    add(A, B, ldb, C, ldc, mf, n, kf, flags, scale, es, C2, scale2);
+    GemmJob& j = forms[1].back();
+    j.A = Ae;
+    j.m = mh;
+    j.k = ke;
+    j.lda = gemm_lda(ke);
+    j.kind = kind;
+    j.A2 = Ao;
+    j.mf = mf;
+    j.kf = kf;
+    j.sigma = sigma;
+  }
+  int n() const { return (int)forms[0].size(); }
+  void clear() {
+    h.clear();
+    forms[0].clear();
+    forms[1].clear();
+  }
+  void use(int f) {
+    form = f;
+    h = forms[f];
+  }
+  bool allowed(int c) const { return form == 0 || gemm_cfg_parity(c); }
   // Tile configuration before tuning: the largest tile that still gives
   // every CU a workgroup.
   void prepare() {
+    h = forms[form];
     int c = 7;  // configurations 0 .. 7 grow with the tile
-    while (c > 0 && gemm_prepare(h.data(), n(), c) < 256) --c;
+    while (c > 0 && (!allowed(c) || gemm_prepare(h.data(), n(), c) < 256)) --c;
+    if (!allowed(c)) c = 4;
     set_cfg(c);
   }
   void set_cfg(int c) {
@@ -84,7 +119,7 @@ struct JobList {
   }
   // shape signature for the tuning cache
   std::vector<int> key() const {
-    std::vector<int> k{(int)type};
+    std::vector<int> k{(int)type, form};
     for (auto& j : h) {
       k.push_back(j.m);
       k.push_back(j.n);
@@ -108,6 +143,36 @@ std::vector<T> padded(const std::vector<double>& a, int rows, int cols) {
 // elements of a padded operator with `rows` rows and `cols` columns
 size_t opsz(int rows, int cols) { return (size_t)gemm_rows(rows) * gemm_lda(cols); }
 
+// Parity halves of rows [r0, r0 + rows) of the m x k operator A, as rows x
+// ceil(k/2) matrices padded to `out_rows` rows: Ae[i][j] = (A[i][j] +
+// A[i][k-1-j]) / 2 and Ao[i][j] = (A[i][j] - A[i][k-1-j]) / 2 for j < k-1-j,
+// Ae[i][mid] = A[i][mid] and Ao[i][mid] = 0 for the middle column of odd k.
+// Acting on B[j] + B[k-1-j] and B[j] - B[k-1-j] they give A B exactly.
+void fold(const std::vector<double>& A, int k, int r0, int rows, int out_rows, std::vector<double>& Ae,
+          std::vector<double>& Ao) {
+  const int ke = (k + 1) / 2;
+  Ae.assign((size_t)out_rows * ke, 0.0);
+  Ao.assign((size_t)out_rows * ke, 0.0);
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < ke; ++j) {
+      const long double a = A[(size_t)(r0 + i) * k + j], b = A[(size_t)(r0 + i) * k + (k - 1 - j)];
+      if (k - 1 - j > j) {
+        Ae[(size_t)i * ke + j] = (double)((a + b) / 2);
+        Ao[(size_t)i * ke + j] = (double)((a - b) / 2);
+      } else {
+        Ae[(size_t)i * ke + j] = (double)a;
+      }
+    }
+}
+// Columns [c0, c0 + cols) of rows [0, rows) of the m x k matrix A, as a
+// rows x out_cols matrix (zero beyond cols).
+std::vector<double> block(const std::vector<double>& A, int k, int rows, int c0, int cols, int out_cols) {
+  std::vector<double> t((size_t)rows * out_cols, 0.0);
+  for (int i = 0; i < rows; ++i)
+    for (int j = 0; j < cols; ++j) t[(size_t)i * out_cols + j] = A[(size_t)i * k + c0 + j];
+  return t;
+}
+
 bool valid_fft(int L) {
   FftPlan p;
   return make_plan(L, &p);
@@ -126,6 +191,11 @@ struct Member {
   FftPlan plx, plz, pbx, pbz;
   int nq = 0, nh = 0, nyin = 0, nzin = 0, nout = 0, nsolve = 0, nsv = 0;
   double *IMN, *DMN, *D, *D2, *PNM, *DP, *V, *Vinv, *DV, *wV, *lam, *d2i0, *d2in, *w, *ydy, *U1, *kx, *kz;
+  // parity halves [even, odd] of the operators of the wide products:
+  // padded-grid values and d/dy, D2, D, projection and D P (fold / unfold);
+  // V^-1 (fold / split), V and D V (split / unfold)
+  double *IMNp[2], *DMNp[2], *D2p[2], *Dp[2], *PNMp[2], *DPp[2], *V4p[2], *V5p[2], *DVp[2];
+  float *IMN32p[2], *DMN32p[2], *PNM32p[2], *DP32p[2];
   double *twx, *twz, *twbx, *twbz;
   double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *DN, *Dc, *D2buf, *hgn, *hvn;
   double *R, *Xs, *Zphi, *Zv, *Zg, *ZDv, *flux, *CB, *prep, *zbuf;
@@ -235,6 +305,24 @@ void carve(Member* m, Carve& c) {
   m->Vinv = c.take<double>(opsz(ni, ni));
   m->DV = c.take<double>(opsz(n1, ni));
   m->wV = c.take<double>(opsz(1, ni));
+  {
+    const int mh = (m1 + 1) / 2, nh = (n1 + 1) / 2, ne = (ni + 1) / 2;
+    for (int q = 0; q < 2; ++q) {
+      m->IMNp[q] = c.take<double>(opsz(mh, nh));
+      m->DMNp[q] = c.take<double>(opsz(mh, nh));
+      m->D2p[q] = c.take<double>(opsz(nh, nh));
+      m->Dp[q] = c.take<double>(opsz(nh, nh));
+      m->PNMp[q] = c.take<double>(opsz(nh, mh));
+      m->DPp[q] = c.take<double>(opsz(nh, mh));
+      m->V4p[q] = c.take<double>(opsz(ne, ne));
+      m->V5p[q] = c.take<double>(opsz(ne, ne));
+      m->DVp[q] = c.take<double>(opsz(nh, ne));
+      m->IMN32p[q] = m->prec != 0 ? c.take<float>(opsz(mh, nh)) : nullptr;
+      m->DMN32p[q] = m->prec != 0 ? c.take<float>(opsz(mh, nh)) : nullptr;
+      m->PNM32p[q] = m->prec != 0 ? c.take<float>(opsz(nh, mh)) : nullptr;
+      m->DP32p[q] = m->prec != 0 ? c.take<float>(opsz(nh, mh)) : nullptr;
+    }
+  }
   m->lam = c.take<double>(ni);
   m->d2i0 = c.take<double>(ni);
   m->d2in = c.take<double>(ni);
@@ -501,27 +589,40 @@ void build_jobs(Member* m) {
   double* st = m->state;
   const int FC = d.dim == 2 ? 3 : 5, FPHI = d.dim == 2 ? 2 : 3;
   const bool mixed = m->prec != 0;
-  for (JobList* jl : m->stage_lists()) jl->h.clear();
-  m->H4.h.clear();
-  m->H5.h.clear();
+  for (JobList* jl : m->stage_lists()) jl->clear();
+  m->H4.clear();
+  m->H5.clear();
   // G1: values and d/dy on the padded grid (mixed: of the fluctuation only,
   // written in FP32; computed in FP32, or in FP64 for precision 2)
+  // The wide products are parity products (operator halves of the even and
+  // odd parts): half rows mh / nh, half columns nh / mh, ne eigen pairs.
+  const int mh = (m1 + 1) / 2, nh = (n1 + 1) / 2, ne = (ni + 1) / 2;  // ne: even eigenvectors
   JobList& g1 = m->G1;
   g1.type = mixed ? (m->prec == 1 ? GEMM_FDF : GEMM_DDF) : GEMM_DDD;
-  const void* I = mixed && m->prec == 1 ? (const void*)m->IMN32 : (const void*)m->IMN;
-  const void* DI = mixed && m->prec == 1 ? (const void*)m->DMN32 : (const void*)m->DMN;
+  const bool f32ops = mixed && m->prec == 1;
+  const void* I = f32ops ? (const void*)m->IMN32 : (const void*)m->IMN;
+  const void* DI = f32ops ? (const void*)m->DMN32 : (const void*)m->DMN;
+  const void* Ip[2] = {f32ops ? (const void*)m->IMN32p[0] : m->IMNp[0], f32ops ? (const void*)m->IMN32p[1] : m->IMNp[1]};
+  const void* DIp[2] = {f32ops ? (const void*)m->DMN32p[0] : m->DMNp[0], f32ops ? (const void*)m->DMN32p[1] : m->DMNp[1]};
   void* Y = mixed ? (void*)m->Yin32 : (void*)m->Yin;
   const size_t ysz = mixed ? sizeof(float) : sizeof(double);
   auto yf = [&](int f) { return (void*)((char*)Y + (size_t)f * fsm * ysz); };
   const int zm = mixed ? GEMM_ZERO_MEAN : 0;
   const int nvel = d.dim;
-  for (int a = 0; a < nvel; ++a) g1.add(I, st + a * fs, cw, yf(a), cw, m1, cw, n1, zm);
-  for (int a = 0; a < d.nc; ++a) g1.add(I, st + (FC + a) * fs, cw, yf(nvel + a), cw, m1, cw, n1, zm);
+  // values (centrosymmetric operator) and d/dy (centro-antisymmetric) on the padded grid
+  auto val = [&](const double* src, void* dst) {
+    g1.addp(PAR_FOLD_UNFOLD, I, Ip[0], Ip[1], src, cw, dst, cw, mh, cw, nh, m1, n1, +1, zm);
+  };
+  auto dy = [&](const double* src, void* dst) {
+    g1.addp(PAR_FOLD_UNFOLD, DI, DIp[0], DIp[1], src, cw, dst, cw, mh, cw, nh, m1, n1, -1, zm);
+  };
+  for (int a = 0; a < nvel; ++a) val(st + a * fs, yf(a));
+  for (int a = 0; a < d.nc; ++a) val(st + (FC + a) * fs, yf(nvel + a));
   const int yd0 = nvel + d.nc;  // first d/dy field in the padded-grid input
-  g1.add(DI, st + 0 * fs, cw, yf(yd0), cw, m1, cw, n1, zm);
+  dy(st + 0 * fs, yf(yd0));
   int o = yd0 + 1;
-  if (d.dim == 3) g1.add(DI, st + 2 * fs, cw, yf(o++), cw, m1, cw, n1, zm);
-  for (int a = 0; a < d.nc; ++a) g1.add(DI, st + (FC + a) * fs, cw, yf(o++), cw, m1, cw, n1, zm);
+  if (d.dim == 3) dy(st + 2 * fs, yf(o++));
+  for (int a = 0; a < d.nc; ++a) dy(st + (FC + a) * fs, yf(o++));
   if (mixed) {
     // FP64 mean profiles on the padded grid (real part of the kx = kz = 0 column)
     // 2D: U U' c (3) c' (3); 3D: U W U' W' c (6) c' (6)
@@ -539,22 +640,32 @@ void build_jobs(Member* m) {
   // G1b (FP64): D2 of phi, (g), c and of the mean U, (W); D of every c
   JobList& g1b = m->G1b;
   g1b.type = GEMM_DDD;
-  g1b.add(m->D2, st + FPHI * fs, cw, m->D2buf + 0 * fs, cw, n1, cw, n1);
-  if (d.dim == 3) g1b.add(m->D2, st + 4 * fs, cw, m->D2buf + 1 * fs, cw, n1, cw, n1);
-  for (int a = 0; a < d.nc; ++a) g1b.add(m->D2, st + (FC + a) * fs, cw, m->D2buf + (m->nsv + a) * fs, cw, n1, cw, n1);
+  auto d2 = [&](const double* src, double* dst) {
+    g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], src, cw, dst, cw, nh, cw, nh, n1, n1, +1);
+  };
+  d2(st + FPHI * fs, m->D2buf + 0 * fs);
+  if (d.dim == 3) d2(st + 4 * fs, m->D2buf + 1 * fs);
+  for (int a = 0; a < d.nc; ++a) d2(st + (FC + a) * fs, m->D2buf + (m->nsv + a) * fs);
   double* D2U = m->D2buf + (size_t)m->nsolve * fs;
   g1b.add(m->D2, st + 0 * fs, cw, D2U, 1, n1, 1, n1);
   if (d.dim == 3) g1b.add(m->D2, st + 2 * fs, cw, D2U + n1, 1, n1, 1, n1);
-  for (int a = 0; a < d.nc; ++a) g1b.add(m->D, st + (FC + a) * fs, cw, m->Dc + a * fs, cw, n1, cw, n1);
+  for (int a = 0; a < d.nc; ++a)
+    g1b.addp(PAR_FOLD_UNFOLD, m->D, m->Dp[0], m->Dp[1], st + (FC + a) * fs, cw, m->Dc + a * fs, cw, nh, cw, nh, n1, n1,
+             -1);
   // G2: projection of the explicit terms, and D of the projected N_x, N_z
   // through (D P) (mixed: FP32 operands, FP64 result)
   m->G2.type = mixed ? (m->prec == 1 ? GEMM_FFD : GEMM_DFD) : GEMM_DDD;
-  const void* P = mixed && m->prec == 1 ? (const void*)m->PNM32 : (const void*)m->PNM;
-  const void* DP = mixed && m->prec == 1 ? (const void*)m->DP32 : (const void*)m->DP;
+  const void* P = f32ops ? (const void*)m->PNM32 : (const void*)m->PNM;
+  const void* DP = f32ops ? (const void*)m->DP32 : (const void*)m->DP;
+  const void* Pp[2] = {f32ops ? (const void*)m->PNM32p[0] : m->PNMp[0], f32ops ? (const void*)m->PNM32p[1] : m->PNMp[1]};
+  const void* DPp[2] = {f32ops ? (const void*)m->DP32p[0] : m->DPp[0], f32ops ? (const void*)m->DP32p[1] : m->DPp[1]};
   const char* Yo = mixed ? (const char*)m->Yout32 : (const char*)m->Yout;
-  for (int f = 0; f < m->nout; ++f) m->G2.add(P, Yo + (size_t)f * fsm * ysz, cw, m->S + f * fs, cw, n1, cw, m1);
-  m->G2.add(DP, Yo, cw, m->DN, cw, n1, cw, m1);
-  if (d.dim == 3) m->G2.add(DP, Yo + 2 * fsm * ysz, cw, m->DN + fs, cw, n1, cw, m1);
+  for (int f = 0; f < m->nout; ++f)
+    m->G2.addp(PAR_FOLD_UNFOLD, P, Pp[0], Pp[1], Yo + (size_t)f * fsm * ysz, cw, m->S + f * fs, cw, nh, cw, mh, n1, m1,
+               +1);
+  m->G2.addp(PAR_FOLD_UNFOLD, DP, DPp[0], DPp[1], Yo, cw, m->DN, cw, nh, cw, mh, n1, m1, -1);
+  if (d.dim == 3)
+    m->G2.addp(PAR_FOLD_UNFOLD, DP, DPp[0], DPp[1], Yo + 2 * fsm * ysz, cw, m->DN + fs, cw, nh, cw, mh, n1, m1, -1);
   if (mixed) {
     // the mean column again, in FP64, from the FP64-completed padded-grid means
     m->Gm.type = GEMM_DDD;
@@ -564,20 +675,27 @@ void build_jobs(Member* m) {
   // Xs = [phi, v, (g), c...] (phi's coefficients give v's as a second output)
   const EigScale* es = m->es;
   double* Xs = m->Xs;
-  for (JobList* jl : {&m->G4, &m->H4})
-    jl->add(m->Vinv, m->R, cw, Xs, cw, ni, cw, ni, 0, SCALE_PHI, es, Xs + fsi, SCALE_V);
-  if (d.dim == 3) m->G4.add(m->Vinv, m->R + fsi, cw, Xs + 2 * fsi, cw, ni, cw, ni, 0, SCALE_PHI, es);
+  // (eigen coefficients of the even part in rows [0, ne), of the odd part after)
+  auto vinv = [&](JobList& jl, const double* src, double* dst, int scale, double* dst2, int scale2) {
+    jl.addp(PAR_FOLD_SPLIT, m->Vinv, m->V4p[0], m->V4p[1], src, cw, dst, cw, ne, cw, ne, ni, ni, +1, 0, scale, es, dst2,
+            scale2);
+  };
+  for (JobList* jl : {&m->G4, &m->H4}) vinv(*jl, m->R, Xs, SCALE_PHI, Xs + fsi, SCALE_V);
+  if (d.dim == 3) vinv(m->G4, m->R + fsi, Xs + 2 * fsi, SCALE_PHI, nullptr, SCALE_NONE);
   const int xo = d.dim == 3 ? 3 : 2;
   for (int a = 0; a < d.nc; ++a)
-    m->G4.add(m->Vinv, m->R + (m->nsv + a) * fsi, cw, Xs + (xo + a) * fsi, cw, ni, cw, ni, 0, SCALE_C, es);
+    vinv(m->G4, m->R + (m->nsv + a) * fsi, Xs + (xo + a) * fsi, SCALE_C, nullptr, SCALE_NONE);
   // G5: back from the eigenbasis
+  auto vmul = [&](JobList& jl, const double* src, double* dst) {
+    jl.addp(PAR_SPLIT_UNFOLD, m->V, m->V5p[0], m->V5p[1], src, cw, dst, cw, ne, cw, ne, ni, ni, +1);
+  };
   for (JobList* jl : {&m->G5, &m->H5}) {
-    jl->add(m->V, Xs, cw, m->Zphi, cw, ni, cw, ni);
-    jl->add(m->V, Xs + fsi, cw, m->Zv, cw, ni, cw, ni);
-    jl->add(m->DV, Xs + fsi, cw, m->ZDv, cw, n1, cw, ni);
+    vmul(*jl, Xs, m->Zphi);
+    vmul(*jl, Xs + fsi, m->Zv);
+    jl->addp(PAR_SPLIT_UNFOLD, m->DV, m->DVp[0], m->DVp[1], Xs + fsi, cw, m->ZDv, cw, nh, cw, ne, n1, ni, -1);
   }
-  if (d.dim == 3) m->G5.add(m->V, Xs + 2 * fsi, cw, m->Zg, cw, ni, cw, ni);
-  for (int a = 0; a < d.nc; ++a) m->G5.add(m->V, Xs + (xo + a) * fsi, cw, st + (FC + a) * fs + cw, cw, ni, cw, ni);
+  if (d.dim == 3) vmul(m->G5, Xs + 2 * fsi, m->Zg);
+  for (int a = 0; a < d.nc; ++a) vmul(m->G5, Xs + (xo + a) * fsi, st + (FC + a) * fs + cw);
   // w . U_p for the flux constraint: the mean column only
   m->G5.add(m->wV, Xs, cw, m->flux, cw, 1, 2, ni);
   for (JobList* jl : {&m->H4, &m->H5}) jl->prepare();
@@ -624,6 +742,48 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
   }
   HIPCHK(up(m->DV, padded(DV, n1, ni), s));
   HIPCHK(up(m->wV, padded(wV, 1, ni), s));
+  {
+    // parity halves (the eigenvectors are even first, then odd)
+    const int mh = (m1 + 1) / 2, nh = (n1 + 1) / 2, ne = op->ne, no = op->no;
+    std::vector<double> e, o;
+    auto put2 = [&](double* const (&dst)[2], int rows, int cols) -> hipError_t {
+      hipError_t r = up(dst[0], padded(e, rows, cols), s);
+      return r != hipSuccess ? r : up(dst[1], padded(o, rows, cols), s);
+    };
+    auto put2f = [&](float* const (&dst)[2], int rows, int cols) -> hipError_t {
+      hipError_t r = up(dst[0], padded<float>(e, rows, cols), s);
+      return r != hipSuccess ? r : up(dst[1], padded<float>(o, rows, cols), s);
+    };
+    const bool mixed = m->prec != 0;
+    fold(op->IMN, n1, 0, mh, mh, e, o);
+    HIPCHK(put2(m->IMNp, mh, nh));
+    if (mixed) HIPCHK(put2f(m->IMN32p, mh, nh));
+    fold(op->DMN, n1, 0, mh, mh, e, o);
+    HIPCHK(put2(m->DMNp, mh, nh));
+    if (mixed) HIPCHK(put2f(m->DMN32p, mh, nh));
+    fold(op->D2, n1, 0, nh, nh, e, o);
+    HIPCHK(put2(m->D2p, nh, nh));
+    fold(op->D, n1, 0, nh, nh, e, o);
+    HIPCHK(put2(m->Dp, nh, nh));
+    fold(op->PNM, m1, 0, nh, nh, e, o);
+    HIPCHK(put2(m->PNMp, nh, mh));
+    if (mixed) HIPCHK(put2f(m->PNM32p, nh, mh));
+    fold(DP, m1, 0, nh, nh, e, o);
+    HIPCHK(put2(m->DPp, nh, mh));
+    if (mixed) HIPCHK(put2f(m->DP32p, nh, mh));
+    // V^-1: even rows act on the folded sums, odd rows on the differences
+    std::vector<double> e2, o2;
+    fold(op->Vinv, ni, 0, ne, ne, e, o2);
+    fold(op->Vinv, ni, ne, no, ne, e2, o);
+    HIPCHK(put2(m->V4p, ne, ne));
+    // V and D V: first half of the rows, even and odd eigenvector columns
+    e = block(op->V, ni, ne, 0, ne, ne);
+    o = block(op->V, ni, ne, ne, no, ne);
+    HIPCHK(put2(m->V5p, ne, ne));
+    e = block(DV, ni, nh, 0, ne, ne);
+    o = block(DV, ni, nh, ne, no, ne);
+    HIPCHK(put2(m->DVp, nh, ne));
+  }
   std::vector<double> ydy(n1);
   const double* y = op->y.data();
   for (int j = 1; j < d.N; ++j) ydy[j] = 0.5 * (y[j - 1] - y[j + 1]);
@@ -705,14 +865,15 @@ pcs_status reset_state(Member* m, uint64_t seed, double amp, hipStream_t s) {
 // Merges the members' tables of the given stages into one batch table (in
 // that order; the table's type is the first non-FP64 type among them).
 void merge_list(JobList& dst, const std::vector<Member*>& mem, std::initializer_list<JobList Member::*> lps) {
-  dst.h.clear();
+  dst.clear();
   dst.type = GEMM_DDD;
   for (JobList Member::*lp : lps)
     for (Member* m : mem) {
       const JobList& src = m->*lp;
       if (src.n() && src.type != GEMM_DDD && dst.type == GEMM_DDD) dst.type = src.type;
-      dst.h.insert(dst.h.end(), src.h.begin(), src.h.end());
+      for (int f = 0; f < 2; ++f) dst.forms[f].insert(dst.forms[f].end(), src.forms[f].begin(), src.forms[f].end());
     }
+  dst.use(0);
   if (dst.n()) dst.prepare();
 }
 
@@ -968,30 +1129,38 @@ pcs_status autotune(Batch* b) {
   HIPCHK(hipEventCreate(&e1));
   for (JobList* jl : b->lists()) {
     if (!jl->n() || jl->cfg < 0) continue;  // nothing to tune on the matrix-vector kernel
+    jl->use(0);
     const auto key = jl->key();
     auto it = tune_cache().find(key);
-    int best = -1;
+    int best = -1, bestf = 0;
     if (it != tune_cache().end()) {
-      best = it->second;
+      best = it->second % GEMM_NCFG;
+      bestf = it->second / GEMM_NCFG;
     } else {
       float tbest = 1e30f;
-      for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
-        jl->set_cfg(cfg);
-        HIPCHK(up(jl->dev, jl->h, s));
-        jl->run(s);  // warm-up
-        HIPCHK(hipEventRecord(e0, s));
-        for (int r = 0; r < 3; ++r) jl->run(s);
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        float ms = 0;
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-        if (ms < tbest) {
-          tbest = ms;
-          best = cfg;
+      for (int f = 0; f < 2; ++f) {
+        jl->use(f);
+        for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
+          if (!jl->allowed(cfg)) continue;
+          jl->set_cfg(cfg);
+          HIPCHK(up(jl->dev, jl->h, s));
+          jl->run(s);  // warm-up
+          HIPCHK(hipEventRecord(e0, s));
+          for (int r = 0; r < 3; ++r) jl->run(s);
+          HIPCHK(hipEventRecord(e1, s));
+          HIPCHK(hipEventSynchronize(e1));
+          float ms = 0;
+          HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          if (ms < tbest) {
+            tbest = ms;
+            best = cfg;
+            bestf = f;
+          }
         }
       }
-      tune_cache()[key] = best;
+      tune_cache()[key] = bestf * GEMM_NCFG + best;
     }
+    jl->use(bestf);
     jl->set_cfg(best);
     HIPCHK(up(jl->dev, jl->h, s));
   }

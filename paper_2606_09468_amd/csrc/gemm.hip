@@ -87,35 +87,53 @@ struct RCfg<3> {
 };
 // LDS-tiled configurations: BM x BN tile, K chunk KC, NBUF LDS buffers (2:
 // the next chunk is written to the other buffer while this one is multiplied;
-// 1: twice the chunk in the same LDS, one more barrier per chunk).
+// 1: twice the chunk in the same LDS, one more barrier per chunk).  Parity
+// products use K chunks of PKC (their B panel holds both halves).
 template <int CFG>
 struct LCfg;
 template <>
 struct LCfg<4> {
-  static constexpr int BM = 32, BN = 32, KC = 32, NBUF = 2;
+  static constexpr int BM = 32, BN = 32, KC = 32, NBUF = 2, PKC = 32;
 };
 template <>
 struct LCfg<5> {
-  static constexpr int BM = 64, BN = 32, KC = 32, NBUF = 2;
+  static constexpr int BM = 64, BN = 32, KC = 32, NBUF = 2, PKC = 16;
 };
 template <>
 struct LCfg<6> {
-  static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 2;
+  static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 2, PKC = 16;
 };
 template <>
 struct LCfg<7> {
-  static constexpr int BM = 128, BN = 64, KC = 16, NBUF = 2;
+  static constexpr int BM = 128, BN = 64, KC = 16, NBUF = 2, PKC = 8;
 };
 template <>
 struct LCfg<8> {
-  static constexpr int BM = 32, BN = 32, KC = 64, NBUF = 1;
+  static constexpr int BM = 32, BN = 32, KC = 64, NBUF = 1, PKC = 64;
 };
 template <>
 struct LCfg<9> {
-  static constexpr int BM = 64, BN = 32, KC = 64, NBUF = 1;
+  static constexpr int BM = 64, BN = 32, KC = 64, NBUF = 1, PKC = 32;
 };
 constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 0};
 constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 0};
+// LDS (in doubles) of an LDS-tiled configuration: the plain panels, the
+// parity panels (A: BM rows of PKC, B: both halves, rows of BN + 4) and the
+// larger of the two, which the kernel declares.
+template <int CFG>
+constexpr int lds_plain() {
+  return LCfg<CFG>::NBUF * LCfg<CFG>::BM * (LCfg<CFG>::KC + 2) +
+         LCfg<CFG>::NBUF * LCfg<CFG>::KC * (LCfg<CFG>::BN + 16);
+}
+template <int CFG>
+constexpr int lds_par() {
+  return LCfg<CFG>::NBUF * LCfg<CFG>::BM * (LCfg<CFG>::PKC + 2) +
+         LCfg<CFG>::NBUF * 2 * LCfg<CFG>::PKC * (LCfg<CFG>::BN + 4);
+}
+template <int CFG>
+constexpr int lds_doubles() {
+  return lds_plain<CFG>() > lds_par<CFG>() ? lds_plain<CFG>() : lds_par<CFG>();
+}
 // operator-stationary kernel: threads, columns per unit, 16-row blocks per
 // panel, LDS bytes for the panel
 constexpr int PNT = 512;
@@ -231,7 +249,8 @@ int gemm_prepare(GemmJob* jobs, int njobs, int cfg) {
   const int bm = CFG_BM[cfg], bn = CFG_BN[cfg];
   int t = 0;
   for (int j = 0; j < njobs; ++j) {
-    jobs[j].tiles_m = (jobs[j].m + bm - 1) / bm;
+    const int rows = jobs[j].kind != PAR_NONE ? bm / 2 : bm;  // a parity tile: BM/2 rows of E and of O
+    jobs[j].tiles_m = (jobs[j].m + rows - 1) / rows;
     const int tn = (jobs[j].n + bn - 1) / bn;
     jobs[j].tile0 = t;
     t += jobs[j].tiles_m * tn;
@@ -470,17 +489,251 @@ __device__ __attribute__((always_inline)) inline void lds_body(const GemmJob* __
   store_tile<T, TC, RB, CB>(jp, acc, row0 + wr, col0 + wc, lk, l16);
 }
 
+// ------------------------------------------------------------ parity products (LDS-tiled)
+// Writes the E and O blocks of one lane (same layout as store_tile) as the
+// outputs of a parity product: E + O at row i and sigma (E - O) at row
+// mf-1-i, or E at row i and O at row m + i (eigen coefficients, optionally
+// scaled by the inverse Helmholtz symbol of their row).
+template <typename T, typename TC, int RB, int CB, typename V4>
+__device__ inline void store_par(const GemmJob* __restrict__ jp, const V4 (&accE)[RB][CB], const V4 (&accO)[RB][CB],
+                                 int r0, int c0, int lk, int l16) {
+  constexpr bool f64 = sizeof(T) == 8;
+  const GemmJob J = *jp;
+  const gptr<TC> C = gmem(static_cast<TC*>(J.C));
+  const gptr<TC> C2 = gmem(static_cast<TC*>(J.C2));
+  const bool split = J.kind == PAR_FOLD_SPLIT;
+  const bool scaled = split && J.scale != SCALE_NONE;
+  EigScale es{};
+  if (scaled) es = *J.es;
+#pragma unroll
+  for (int cb = 0; cb < CB; ++cb) {
+    const int gc = c0 + cb * 16 + l16;
+    if (gc >= J.n) continue;
+    double k2 = 0;
+    bool mean = false;
+    if (scaled) {
+      const int mode = gc >> 1, iz = mode / es.nkx, ix = mode - iz * es.nkx;
+      const double kxv = gmem(es.kx)[ix], kzv = (es.dim == 3) ? gmem(es.kz)[iz] : 0.0;
+      k2 = kxv * kxv + kzv * kzv;
+      mean = mode == 0;
+    }
+    auto put = [&](int row, double v) {
+      if (scaled) {
+        const double lam = gmem(es.lam)[row];
+        C[(size_t)row * J.ldc + gc] = TC(v * eig_factor(es, J.scale, lam, k2, mean));
+        if (C2) C2[(size_t)row * J.ldc + gc] = TC(J.scale2 != SCALE_NONE ? v * eig_factor(es, J.scale2, lam, k2, mean) : v);
+      } else {
+        C[(size_t)row * J.ldc + gc] = TC(v);
+        if (C2) C2[(size_t)row * J.ldc + gc] = TC(v);
+      }
+    };
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gi = r0 + rb * 16 + (f64 ? 4 * r + lk : 4 * lk + r);
+        if (gi >= J.m) continue;
+        const double e = J.alpha * (double)accE[rb][cb][r], o = J.alpha * (double)accO[rb][cb][r];
+        if (split) {
+          put(gi, e);
+          if (J.m + gi < J.mf) put(J.m + gi, o);
+        } else {
+          put(gi, e + o);
+          const int mr = J.mf - 1 - gi;
+          if (mr > gi) put(mr, J.sigma * (e - o));
+        }
+      }
+  }
+}
+
+// A tile covers BM/2 rows of E and the same rows of O: waves 0, 1 multiply
+// the even part (Ae rows, Be panel), waves 2, 3 the odd part (Ao rows, Bo
+// panel); at the end the odd waves hand their blocks to the even waves
+// through LDS, which write both mirrored output rows.
+template <typename T, typename TB, typename TC, int CFG>
+__device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob* __restrict__ jp, int t,
+                                                                   double* smem) {
+  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::PKC, NBUF = LCfg<CFG>::NBUF;
+  constexpr int HM = BM / 2, WN = BN / 2, RB = HM / 16, CB = WN / 16;
+  constexpr int PA = KC + 2, PB = BN + 4;
+  constexpr int NA = KC * BM / 512, NB = KC * BN / 512;
+  constexpr int RA = 512 / KC, SB = 512 / BN;
+  static_assert(NA >= 1 && NB >= 1 && KC % 4 == 0, "tile shape");
+  static_assert(lds_par<CFG>() <= lds_doubles<CFG>() && lds_doubles<CFG>() * 8 <= 64 * 1024, "LDS");
+  static_assert(2 * RB * CB * 4 * 64 <= lds_doubles<CFG>(), "exchange area");
+  typedef typename Vec<T>::v4 V4;
+  typedef typename Vec<T>::v2 AP;
+  typedef typename Vec<TB>::v2 BP;
+  T (*As)[BM * PA] = reinterpret_cast<T (*)[BM * PA]>(smem);  // [NBUF][BM * PA]: Ae rows, then Ao rows
+  T (*Bs)[2][KC * PB] = reinterpret_cast<T (*)[2][KC * PB]>(smem + (NBUF * BM * PA * sizeof(T) + 7) / 8);
+  const int lt = t - jp->tile0, tiles_m = jp->tiles_m;
+  const int row0 = (lt % tiles_m) * HM, col0 = (lt / tiles_m) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int par = wave >> 1, wc = (wave & 1) * WN;
+  const int M = jp->m, N = jp->n, K = jp->k, KF = jp->kf, lda = jp->lda, ldb = jp->ldb;
+  const bool fold = jp->kind != PAR_SPLIT_UNFOLD;
+  const gptr<const T> A = gmem(static_cast<const T*>(jp->A));
+  const gptr<const T> A2 = gmem(static_cast<const T*>(jp->A2));
+  const gptr<const TB> B = gmem(static_cast<const TB*>(jp->B));
+
+  const int kp = 2 * (tid % (KC / 2)), ra = tid / (KC / 2);
+  const int cb2 = 2 * (tid % (BN / 2)), kb = tid / (BN / 2);
+  const int gc = col0 + cb2;
+  const bool bpair = (((ldb | N) & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & (2 * sizeof(TB) - 1)) == 0);
+  const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
+  const bool c0ok = gc < N && !(zm && gc < 2), c1ok = gc + 1 < N && !(zm && gc + 1 < 2);
+
+  AP ar[NA];
+  TB be[NB][2], bo[NB][2];
+  auto brow = [&](int kk, TB (&v)[2]) {  // B row kk at this thread's column pair
+    const gptr<const TB> bp = B + (size_t)kk * ldb + gc;
+    if (bpair) {
+      if (gc < N) {
+        const BP x = *reinterpret_cast<gptr<const BP>>(bp);
+        v[0] = x[0];
+        v[1] = x[1];
+      } else {
+        v[0] = v[1] = TB(0);
+      }
+    } else {
+      v[0] = gc < N ? bp[0] : TB(0);
+      v[1] = gc + 1 < N ? bp[1] : TB(0);
+    }
+  };
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) {
+      const int r = ra + u * RA, kk = k0 + kp;
+      const gptr<const T> src = (r < HM ? A : A2) + (size_t)(row0 + (r < HM ? r : r - HM)) * lda + kk;
+      ar[u] = kk < K ? *reinterpret_cast<gptr<const AP>>(src) : AP{0, 0};
+    }
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      const int kk = k0 + kb + u * SB;
+      be[u][0] = be[u][1] = bo[u][0] = bo[u][1] = TB(0);
+      if (kk < K) {
+        if (fold) {
+          const int km = KF - 1 - kk;
+          TB x[2];
+          brow(kk, x);
+          if (km > kk) {
+            TB y[2];
+            brow(km, y);
+            be[u][0] = x[0] + y[0];
+            be[u][1] = x[1] + y[1];
+            bo[u][0] = x[0] - y[0];
+            bo[u][1] = x[1] - y[1];
+          } else {
+            be[u][0] = x[0];
+            be[u][1] = x[1];
+          }
+        } else {
+          brow(kk, be[u]);
+          if (K + kk < KF) brow(K + kk, bo[u]);
+        }
+      }
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int u = 0; u < NA; ++u) *reinterpret_cast<AP*>(&As[buf][(ra + u * RA) * PA + kp]) = ar[u];
+#pragma unroll
+    for (int u = 0; u < NB; ++u) {
+      AP v;
+      v[0] = c0ok ? T(be[u][0]) : T(0);
+      v[1] = c1ok ? T(be[u][1]) : T(0);
+      *reinterpret_cast<AP*>(&Bs[buf][0][(kb + u * SB) * PB + cb2]) = v;
+      v[0] = c0ok ? T(bo[u][0]) : T(0);
+      v[1] = c1ok ? T(bo[u][1]) : T(0);
+      *reinterpret_cast<AP*>(&Bs[buf][1][(kb + u * SB) * PB + cb2]) = v;
+    }
+  };
+
+  V4 acc[RB][CB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = V4{0, 0, 0, 0};
+  const bool active = (row0 < M) && (col0 + wc < N);
+  const int nch = (K + KC - 1) / KC;
+  auto multiply = [&](int buf) {
+    if (!active) return;
+    const T* as = &As[buf][(par * HM + l16) * PA + lk];
+    const T* bs = &Bs[buf][par][lk * PB + wc + l16];
+#pragma unroll
+    for (int kq = 0; kq < KC / 4; ++kq) {
+      T a[RB], b[CB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) a[rb] = as[rb * 16 * PA + 4 * kq];
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb) b[cb] = bs[4 * kq * PB + cb * 16];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) acc[rb][cb] = mfma(a[rb], b[cb], acc[rb][cb]);
+    }
+  };
+  load(0);
+  if constexpr (NBUF == 2) {
+    store(0);
+    __syncthreads();
+    for (int c = 0; c < nch; ++c) {
+      const int buf = c & 1;
+      if (c + 1 < nch) load((c + 1) * KC);
+      multiply(buf);
+      if (c + 1 < nch) store(buf ^ 1);
+      __syncthreads();
+    }
+  } else {
+    for (int c = 0; c < nch; ++c) {
+      store(0);
+      __syncthreads();
+      if (c + 1 < nch) load((c + 1) * KC);
+      multiply(0);
+      __syncthreads();
+    }
+  }
+  // odd waves hand their blocks to the even waves (the panels are no longer read)
+  T* xch = reinterpret_cast<T*>(smem) + (size_t)(wave & 1) * RB * CB * 4 * 64;
+  if (par == 1) {
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) xch[((rb * CB + cb) * 4 + r) * 64 + lane] = acc[rb][cb][r];
+  }
+  __syncthreads();
+  if (par == 1 || !active) return;
+  V4 accO[RB][CB];
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) accO[rb][cb][r] = xch[((rb * CB + cb) * 4 + r) * 64 + lane];
+  store_par<T, TC, RB, CB>(jp, acc, accO, row0, col0 + wc, lk, l16);
+}
+
 template <typename T, typename TB, typename TC, int CFG>
 __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
   constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC, NBUF = LCfg<CFG>::NBUF;
   // sized for FP64 operands, shared by both precisions of a mixed table
-  __shared__ __attribute__((aligned(16))) double smem[NBUF * BM * (KC + 2) + NBUF * KC * (BN + 16)];
+  __shared__ __attribute__((aligned(16))) double smem[lds_doubles<CFG>()];
   const int t = xcd_tile(blockIdx.x, total);
   const GemmJob* jp = jobs + find_job(jobs, njobs, t);
-  if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
+  const bool ddd = dual_type<T, TB, TC>() && jp->type == GEMM_DDD;
+  if (jp->kind != PAR_NONE) {
+    if (ddd)
+      lds_par_body<double, double, double, CFG>(jp, t, smem);
+    else
+      lds_par_body<T, TB, TC, CFG>(jp, t, smem);
+  } else if (ddd) {
     lds_body<double, double, double, CFG>(jp, t, smem);
-  else
+  } else {
     lds_body<T, TB, TC, CFG>(jp, t, smem);
+  }
 }
 
 // ------------------------------------------------------------ operator-stationary kernel
@@ -659,6 +912,8 @@ void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStrea
 }
 
 }  // namespace
+
+bool gemm_cfg_parity(int cfg) { return cfg >= 4 && cfg <= 9; }
 
 hipError_t gemm_set_attributes() {
   const void* k[] = {(const void*)gemm_panel_kernel<double, double, double>,

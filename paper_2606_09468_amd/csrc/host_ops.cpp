@@ -13,7 +13,8 @@
 //   PNM  : padded values -> Chebyshev coefficients, keep degrees 0..N,
 //          evaluate on y_j; summed in closed form with the Dirichlet kernel
 //   w    : Clenshaw-Curtis weights (closed form)
-//   V, lam, Vinv : eigendecomposition of the interior block of D2, from a
+//   V, lam, Vinv : eigendecomposition of the interior block of D2, per
+//          parity block (even eigenvectors first, then odd), each from a
 //          Hessenberg reduction, shifted QR for the eigenvalues and inverse
 //          iteration for the eigenvectors.
 #include "host_ops.hpp"
@@ -328,14 +329,50 @@ static std::unique_ptr<WallOps> build(int N) {
     op->w[j] = (double)(2 * v / N);
   }
 
-  // Interior block of D2 and its eigendecomposition
-  const int ni = N - 1;
+  // Interior block of D2 and its eigendecomposition.  The block is
+  // centrosymmetric (A[ni-1-i][ni-1-j] = A[i][j]), so it maps even vectors
+  // (x_j = x_{ni-1-j}) to even and odd to odd: on the first half of an even
+  // vector (j <= mid) it acts as Ke[i][j] = A[i][j] + A[i][ni-1-j] (j < mid),
+  // Ke[i][mid] = A[i][mid]; on the first half of an odd one (j < mid, the
+  // middle entry being zero) as Ko[i][j] = A[i][j] - A[i][ni-1-j].  The two
+  // half-size blocks are diagonalised separately, so every eigenvector is
+  // exactly even or odd; the even ones are listed first.
+  const int ni = N - 1, mid = ni / 2, ne = mid + 1, no = mid;
   std::vector<ld> A((size_t)ni * ni);
   for (int i = 0; i < ni; ++i)
     for (int j = 0; j < ni; ++j) A[(size_t)i * ni + j] = D2[(size_t)(i + 1) * n1 + (j + 1)];
-  std::vector<ld> lam, V, Vi;
-  if (!eig_real(ni, A, lam, V)) return nullptr;
-  if (!invert(ni, V, Vi)) return nullptr;
+  std::vector<ld> Ke((size_t)ne * ne), Ko((size_t)no * no);
+  for (int i = 0; i < ne; ++i)
+    for (int j = 0; j < ne; ++j)
+      Ke[(size_t)i * ne + j] = j < mid ? A[(size_t)i * ni + j] + A[(size_t)i * ni + (ni - 1 - j)] : A[(size_t)i * ni + j];
+  for (int i = 0; i < no; ++i)
+    for (int j = 0; j < no; ++j) Ko[(size_t)i * no + j] = A[(size_t)i * ni + j] - A[(size_t)i * ni + (ni - 1 - j)];
+  std::vector<ld> lame, lamo, We, Wo, Wei, Woi;
+  if (!eig_real(ne, Ke, lame, We) || !eig_real(no, Ko, lamo, Wo)) return nullptr;
+  if (!invert(ne, We, Wei) || !invert(no, Wo, Woi)) return nullptr;
+  // full eigenvectors (columns: even, then odd) and the inverse, whose rows
+  // act on the half sums / differences
+  std::vector<ld> lam(ni), V((size_t)ni * ni, 0), Vi((size_t)ni * ni, 0);
+  for (int p = 0; p < ne; ++p) {
+    lam[p] = lame[p];
+    for (int j = 0; j <= mid; ++j) {
+      V[(size_t)j * ni + p] = V[(size_t)(ni - 1 - j) * ni + p] = We[(size_t)j * ne + p];
+      const ld wi = Wei[(size_t)p * ne + j];
+      if (j < mid)
+        Vi[(size_t)p * ni + j] = Vi[(size_t)p * ni + (ni - 1 - j)] = wi / 2;
+      else
+        Vi[(size_t)p * ni + j] = wi;
+    }
+  }
+  for (int q = 0; q < no; ++q) {
+    lam[ne + q] = lamo[q];
+    for (int j = 0; j < mid; ++j) {
+      V[(size_t)j * ni + ne + q] = Wo[(size_t)j * no + q];
+      V[(size_t)(ni - 1 - j) * ni + ne + q] = -Wo[(size_t)j * no + q];
+      Vi[(size_t)(ne + q) * ni + j] = Woi[(size_t)q * no + j] / 2;
+      Vi[(size_t)(ne + q) * ni + (ni - 1 - j)] = -Woi[(size_t)q * no + j] / 2;
+    }
+  }
   // self-check: || V diag(lam) V^-1 - A || relative to ||A||
   ld errmax = 0, amax = 0;
   for (int i = 0; i < ni; ++i)
@@ -346,6 +383,8 @@ static std::unique_ptr<WallOps> build(int N) {
       amax = std::max(amax, fabsl(A[(size_t)i * ni + j]));
     }
   if (!(errmax <= 1e-14L * amax)) return nullptr;
+  op->ne = ne;
+  op->no = no;
   op->V.assign(V.begin(), V.end());
   op->Vinv.assign(Vi.begin(), Vi.end());
   op->lam.assign(lam.begin(), lam.end());

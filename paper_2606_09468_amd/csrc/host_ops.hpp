@@ -22,8 +22,10 @@ struct WallOps {
   std::vector<double> IMN, DMN;     // (M+1)x(N+1): interpolate / differentiate to the padded grid
   std::vector<double> PNM;          // (N+1)x(M+1): padded values -> degree-N truncation on y_j
   std::vector<double> w;            // N+1 Clenshaw-Curtis weights
-  // Interior (j = 1..N-1) block of D2 diagonalised: D2_II = V diag(lam) V^-1
+  // Interior (j = 1..N-1) block of D2 diagonalised: D2_II = V diag(lam) V^-1,
+  // the first ne eigenvectors even about the midplane, the other no odd
   std::vector<double> V, Vinv, lam; // (N-1)^2, (N-1)^2, N-1
+  int ne = 0, no = 0;
   std::vector<double> d2_i0, d2_in; // interior rows of the two boundary columns of D2
 };
 

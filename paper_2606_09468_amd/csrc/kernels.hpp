@@ -27,15 +27,37 @@ __device__ inline gptr<T> gmem(T* p) {
 // B (k x n) and C (m x n) are row-major, each in its own precision (see
 // GemmType).  Complex fields (re/im interleaved) are multiplied by a real
 // operator by treating each complex column as two real columns.
+//
+// Parity products.  Every wall-normal operator of the step is
+// centrosymmetric or centro-antisymmetric (the Lobatto and padded grids are
+// symmetric about the midplane): A[mf-1-i][kf-1-j] = sigma A[i][j].  Writing
+// B = Be + Bo with Be[j] = B[j] + B[kf-1-j], Bo[j] = B[j] - B[kf-1-j]
+// (j < kf-1-j; Be[mid] = B[mid], Bo[mid] = 0), one product becomes two of
+// half the size, E = Ae Be and O = Ao Bo over the first ceil(kf/2) rows of
+// B, with (A B)[i] = E[i] + O[i] and (A B)[mf-1-i] = sigma (E[i] - O[i]).
+// The interior eigenbasis has the same structure (even eigenvectors first),
+// which gives the other two kinds: the eigen coefficients of the even and
+// odd parts as separate output rows, and a product whose B rows are already
+// split into an even and an odd block.
+enum {
+  PAR_NONE = 0,
+  PAR_FOLD_UNFOLD,   // B folded (kf rows), output unfolded (mf rows, sign sigma)
+  PAR_FOLD_SPLIT,    // B folded; E to rows [0, m), O to rows [m, mf)
+  PAR_SPLIT_UNFOLD,  // Be = B rows [0, k), Bo = B rows [k, kf); output unfolded
+};
 struct EigScale;
 struct GemmJob {
   int type;  // GemmType of this product (a table may mix GEMM_DDD with its own type)
+  int kind;  // PAR_*; for the parity kinds m and k are the sizes of E (and of O,
+             // whose operator A2 is padded to the same shape) and lda serves both
   const void* A;
+  const void* A2;
   const void* B;
   void* C;
   void* C2;  // optional second output: alpha A B scaled by scale2 (no beta term)
   int m, n, k, lda, ldb, ldc;
-  double alpha, beta;
+  int mf, kf, sigma;   // parity kinds: full output rows, full B rows, mirror sign
+  double alpha, beta;  // parity kinds: beta must be 0
   int flags;           // GEMM_ZERO_MEAN: B columns 0 and 1 (the kx = kz = 0 mode) read as zero
   int scale, scale2;   // SCALE_*: output row i is eigen coefficient i, scaled per mode
   const EigScale* es;  // per-solve constants for the scaling
@@ -78,6 +100,8 @@ inline int gemm_rows(int m) { return (m + 127) & ~127; }
 // Fills tiles_m / tile0 for tile configuration cfg and returns the total
 // number of workgroups.
 int gemm_prepare(GemmJob* jobs, int njobs, int cfg);
+// Whether configuration cfg evaluates parity products (the LDS-tiled ones).
+bool gemm_cfg_parity(int cfg);
 // t: the table's precision combination; its jobs are of type t or GEMM_DDD.
 void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s);
 
