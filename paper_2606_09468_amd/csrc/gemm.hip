@@ -88,12 +88,15 @@ struct RCfg<3> {
 // LDS-tiled configurations: BM x BN tile, K chunk KC, NBUF LDS buffers (2:
 // the next chunk is written to the other buffer while this one is multiplied;
 // 1: twice the chunk in the same LDS, one more barrier per chunk).  Parity
-// products use K chunks of PKC (their B panel holds both halves).
+// products use K chunks of PKC, so that their panels (B holds both halves)
+// fit the LDS of the plain ones and the occupancy stays that of the plain
+// kernel (measured: full-size parity chunks gain nothing and cost a
+// workgroup per CU).
 template <int CFG>
 struct LCfg;
 template <>
 struct LCfg<4> {
-  static constexpr int BM = 32, BN = 32, KC = 32, NBUF = 2, PKC = 32;
+  static constexpr int BM = 32, BN = 32, KC = 32, NBUF = 2, PKC = 16;
 };
 template <>
 struct LCfg<5> {
@@ -101,7 +104,7 @@ struct LCfg<5> {
 };
 template <>
 struct LCfg<6> {
-  static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 2, PKC = 16;
+  static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 2, PKC = 8;
 };
 template <>
 struct LCfg<7> {
@@ -109,14 +112,14 @@ struct LCfg<7> {
 };
 template <>
 struct LCfg<8> {
-  static constexpr int BM = 32, BN = 32, KC = 64, NBUF = 1, PKC = 64;
+  static constexpr int BM = 32, BN = 32, KC = 64, NBUF = 1, PKC = 32;
 };
 template <>
 struct LCfg<9> {
   static constexpr int BM = 64, BN = 32, KC = 64, NBUF = 1, PKC = 32;
 };
-constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 0};
-constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 0};
+constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64};
+constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32};
 // LDS (in doubles) of an LDS-tiled configuration: the plain panels, the
 // parity panels (A: BM rows of PKC, B: both halves, rows of BN + 4) and the
 // larger of the two, which the kernel declares.
@@ -134,12 +137,7 @@ template <int CFG>
 constexpr int lds_doubles() {
   return lds_plain<CFG>() > lds_par<CFG>() ? lds_plain<CFG>() : lds_par<CFG>();
 }
-// operator-stationary kernel: threads, columns per unit, 16-row blocks per
-// panel, LDS bytes for the panel
-constexpr int PNT = 512;
-constexpr int PBN = 64;
-constexpr int PMAXRB = 14;
-constexpr size_t PLDS = 150 * 1024;
+
 
 // Workgroup b runs on XCD b % 8; logical tiles are dealt so that XCD x gets
 // one contiguous range (a bijection for any tile count).
@@ -232,20 +230,6 @@ __device__ inline void store_tile(const GemmJob* __restrict__ jp, const V4 (&acc
 }  // namespace
 
 int gemm_prepare(GemmJob* jobs, int njobs, int cfg) {
-  if (cfg == GEMM_PANEL) {
-    // panels: as many operator rows as fit the LDS budget, split evenly
-    int t = 0;
-    for (int j = 0; j < njobs; ++j) {
-      GemmJob& J = jobs[j];
-      const int sz = (J.type == GEMM_FDF || J.type == GEMM_FFD) ? 4 : 8;
-      const int pa = gemm_lda(J.k) + 16 / sz;
-      const int hmax = std::min<int>(PMAXRB * 16, (int)(PLDS / ((size_t)pa * sz)));
-      J.tiles_m = (J.m + hmax - 1) / hmax;
-      J.tile0 = t;
-      t += J.tiles_m * ((J.n + PBN - 1) / PBN);
-    }
-    return t;
-  }
   const int bm = CFG_BM[cfg], bn = CFG_BN[cfg];
   int t = 0;
   for (int j = 0; j < njobs; ++j) {
@@ -559,8 +543,10 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
   constexpr int NA = KC * BM / 512, NB = KC * BN / 512;
   constexpr int RA = 512 / KC, SB = 512 / BN;
   static_assert(NA >= 1 && NB >= 1 && KC % 4 == 0, "tile shape");
-  static_assert(lds_par<CFG>() <= lds_doubles<CFG>() && lds_doubles<CFG>() * 8 <= 64 * 1024, "LDS");
-  static_assert(2 * RB * CB * 4 * 64 <= lds_doubles<CFG>(), "exchange area");
+  static_assert(lds_par<CFG>() <= lds_plain<CFG>() && lds_doubles<CFG>() * 8 <= 64 * 1024, "LDS");
+  // odd -> even hand-over in rounds of XR row blocks (whatever fits the LDS)
+  constexpr int XR = (2 * RB * CB * 4 * 64 <= lds_doubles<CFG>()) ? RB : 1;
+  static_assert(2 * XR * CB * 4 * 64 <= lds_doubles<CFG>() && RB % XR == 0, "exchange area");
   typedef typename Vec<T>::v4 V4;
   typedef typename Vec<T>::v2 AP;
   typedef typename Vec<TB>::v2 BP;
@@ -695,24 +681,30 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
     }
   }
   // odd waves hand their blocks to the even waves (the panels are no longer read)
-  T* xch = reinterpret_cast<T*>(smem) + (size_t)(wave & 1) * RB * CB * 4 * 64;
-  if (par == 1) {
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int cb = 0; cb < CB; ++cb)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) xch[((rb * CB + cb) * 4 + r) * 64 + lane] = acc[rb][cb][r];
-  }
-  __syncthreads();
-  if (par == 1 || !active) return;
+  T* xch = reinterpret_cast<T*>(smem) + (size_t)(wave & 1) * XR * CB * 4 * 64;
   V4 accO[RB][CB];
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+  for (int r0 = 0; r0 < RB; r0 += XR) {
+    if (par == 1) {
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb)
+      for (int rb = 0; rb < XR; ++rb)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) accO[rb][cb][r] = xch[((rb * CB + cb) * 4 + r) * 64 + lane];
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) xch[((rb * CB + cb) * 4 + r) * 64 + lane] = acc[r0 + rb][cb][r];
+    }
+    __syncthreads();
+    if (par == 0) {
+#pragma unroll
+      for (int rb = 0; rb < XR; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) accO[r0 + rb][cb][r] = xch[((rb * CB + cb) * 4 + r) * 64 + lane];
+    }
+    if (r0 + XR < RB) __syncthreads();
+  }
+  if (par == 1 || !active) return;
   store_par<T, TC, RB, CB>(jp, acc, accO, row0, col0 + wc, lk, l16);
 }
 
@@ -736,161 +728,10 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict
   }
 }
 
-// ------------------------------------------------------------ operator-stationary kernel
-// For wide tables (the 3D fields: thousands of columns per product) one
-// 512-thread workgroup per CU keeps a row panel of the operator in LDS and
-// walks a contiguous range of 64-column units, so every element of B is read
-// from HBM once per panel and the operator once per workgroup.  Unit u of
-// job j is panel (u - tile0) / nch, column chunk (u - tile0) % nch, with
-// nch = ceil(n / 64) and tiles_m the job's panel count (rows split evenly).
-// Wave w takes the 16-column block w % 4 of a unit and the row blocks of
-// parity w / 4; its B values stream through a three-slot register ring of
-// 16-wide k blocks with the k permutation of the register-direct kernel, so
-// an A fragment is four consecutive panel elements (16 or 32 bytes of LDS).
-// Panel rows are PA = round16(k) + 16 / sizeof(T) elements apart, which puts
-// the 16 rows of a fragment read on distinct banks.
-
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-
-template <typename T, typename TB, typename TC>
-__device__ __attribute__((always_inline)) inline void panel_run(const GemmJob* __restrict__ jp, int p, int ch0,
-                                                                int ch1, bool load_panel, char* lds) {
-  typedef typename Vec<T>::v4 V4;
-  constexpr int SZ = sizeof(T), HALF = PMAXRB / 2;
-  const int M = jp->m, N = jp->n, K = jp->k;
-  const int K16 = (K + 15) & ~15, PA = K16 + 16 / SZ;
-  const int np = jp->tiles_m, hm = (M + np - 1) / np;
-  const int r0 = p * hm, rows = min(hm, M - r0);
-  T* __restrict__ Ap = reinterpret_cast<T*>(lds);
-  const int tid = threadIdx.x;
-  if (load_panel) {
-    __syncthreads();  // every wave is done with the previous panel
-    const gptr<const char> A = reinterpret_cast<gptr<const char>>(gmem(static_cast<const T*>(jp->A)) + (size_t)r0 * jp->lda);
-    const int vpr = K16 * SZ / 16;  // 16-byte vectors per row
-    for (int e = tid; e < rows * vpr; e += PNT) {
-      const int r = e / vpr, c = e - r * vpr;
-      *reinterpret_cast<u32x4*>(lds + (size_t)r * PA * SZ + 16 * c) =
-          *reinterpret_cast<gptr<const u32x4>>(A + (size_t)r * jp->lda * SZ + 16 * c);
-    }
-    __syncthreads();
-  }
-  const int lane = tid & 63, wave = tid >> 6, l16 = lane & 15, lk = lane >> 4;
-  const int cb = wave & 3, par = wave >> 2;
-  const int nrb = (rows + 15) >> 4, myrb = (nrb - par + 1) >> 1;
-  const int nkb = K16 >> 4;
-  const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
-  const gptr<const TB> B = gmem(static_cast<const TB*>(jp->B));
-  const int ldb = jp->ldb;
-  // this lane's A fragment row in each of the wave's row blocks (rows past
-  // the panel read its last row; their outputs are not stored)
-  int aoff[HALF];
-#pragma unroll
-  for (int i = 0; i < HALF; ++i) aoff[i] = min((par + 2 * i) * 16 + l16, rows - 1) * PA + 4 * lk;
-  for (int ch = ch0; ch < ch1; ++ch) {
-    const int col = ch * PBN + cb * 16 + l16;
-    const bool cok = col < N && !(zm && col < 2);
-    V4 acc[HALF];
-#pragma unroll
-    for (int i = 0; i < HALF; ++i) acc[i] = V4{0, 0, 0, 0};
-    T b0[4], b1[4], b2[4];
-    auto ld = [&](T (&b)[4], int kb) {
-#pragma unroll
-      for (int s = 0; s < 4; ++s) {
-        const int kk = 16 * kb + 4 * lk + s;
-        b[s] = (kk < K && cok) ? T(B[(size_t)kk * ldb + col]) : T(0);
-      }
-    };
-    // row blocks in pairs: two independent accumulation chains, few live A values
-    auto mul = [&](const T (&b)[4], int kb) {
-#pragma unroll
-      for (int i = 0; i < HALF; i += 2) {
-        if (i >= myrb) break;
-        T a[2][4];
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-          const T* ap = Ap + aoff[i + h < HALF ? i + h : i] + 16 * kb;
-          if constexpr (SZ == 4) {
-            const V4 v = *reinterpret_cast<const V4*>(ap);
-            a[h][0] = v[0];
-            a[h][1] = v[1];
-            a[h][2] = v[2];
-            a[h][3] = v[3];
-          } else {
-            const dbl2 v0 = *reinterpret_cast<const dbl2*>(ap), v1 = *reinterpret_cast<const dbl2*>(ap + 2);
-            a[h][0] = v0[0];
-            a[h][1] = v0[1];
-            a[h][2] = v1[0];
-            a[h][3] = v1[1];
-          }
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-          acc[i] = mfma(a[0][s], b[s], acc[i]);
-          if (i + 1 < HALF && i + 1 < myrb) acc[i + 1] = mfma(a[1][s], b[s], acc[i + 1]);
-        }
-      }
-    };
-    ld(b0, 0);
-    if (nkb > 1) ld(b1, 1);
-    for (int kb = 0; kb < nkb; kb += 3) {
-      if (kb + 2 < nkb) ld(b2, kb + 2);
-      mul(b0, kb);
-      if (kb + 1 >= nkb) break;
-      if (kb + 3 < nkb) ld(b0, kb + 3);
-      mul(b1, kb + 1);
-      if (kb + 2 >= nkb) break;
-      if (kb + 4 < nkb) ld(b1, kb + 4);
-      mul(b2, kb + 2);
-    }
-#pragma unroll
-    for (int i = 0; i < HALF; ++i)
-      if (i < myrb) {
-        const V4 one[1][1] = {{acc[i]}};
-        store_tile<T, TC, 1, 1>(jp, one, r0 + (par + 2 * i) * 16, ch * PBN + cb * 16, lk, l16, r0 + rows);
-      }
-  }
-}
-
-template <typename T, typename TB, typename TC>
-__global__ __launch_bounds__(PNT) void gemm_panel_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
-  extern __shared__ __attribute__((aligned(16))) char panel_lds[];
-  const int G = gridDim.x, w = blockIdx.x;
-  const int u1 = (int)((long long)total * (w + 1) / G);
-  int u = (int)((long long)total * w / G);
-  const void* curA = nullptr;
-  int curp = -1;
-  while (u < u1) {
-    const GemmJob* jp = jobs + find_job(jobs, njobs, u);
-    const int nch = (jp->n + PBN - 1) / PBN;
-    const int local = u - jp->tile0, p = local / nch;
-    const int end = min(u1, jp->tile0 + (p + 1) * nch);  // the rest of this panel's units
-    // consecutive products of one operator (single panel) keep it in LDS
-    const bool load = jp->A != curA || p != curp;
-    curA = jp->A;
-    curp = p;
-    const int ch0 = local - p * nch, ch1 = ch0 + (end - u);
-    if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
-      panel_run<double, double, double>(jp, p, ch0, ch1, load, panel_lds);
-    else
-      panel_run<T, TB, TC>(jp, p, ch0, ch1, load, panel_lds);
-    u = end;
-  }
-}
-
 namespace {
 
 template <typename T, typename TB, typename TC>
 void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStream_t s) {
-  if (cfg == GEMM_PANEL) {
-    static int ncu = 0;
-    if (!ncu) {
-      hipDeviceProp_t pr;
-      ncu = hipGetDeviceProperties(&pr, 0) == hipSuccess ? pr.multiProcessorCount : 256;
-    }
-    hipLaunchKernelGGL((gemm_panel_kernel<T, TB, TC>), dim3(std::min(total, ncu)), dim3(PNT), PLDS, s, dev_jobs,
-                       njobs, total);
-    return;
-  }
 #define PCS_GEMM_LAUNCH(KERNEL, C)                                                                    \
   case C:                                                                                             \
     hipLaunchKernelGGL((KERNEL<T, TB, TC, C>), dim3(total), dim3(256), 0, s, dev_jobs, njobs, total); \
@@ -913,20 +754,9 @@ void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStrea
 
 }  // namespace
 
-bool gemm_cfg_parity(int cfg) { return cfg >= 4 && cfg <= 9; }
+bool gemm_cfg_parity(int cfg) { return cfg >= 4 && cfg < GEMM_NCFG; }
 
-hipError_t gemm_set_attributes() {
-  const void* k[] = {(const void*)gemm_panel_kernel<double, double, double>,
-                     (const void*)gemm_panel_kernel<float, double, float>,
-                     (const void*)gemm_panel_kernel<float, float, double>,
-                     (const void*)gemm_panel_kernel<double, double, float>,
-                     (const void*)gemm_panel_kernel<double, float, double>};
-  for (const void* f : k) {
-    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)PLDS);
-    if (e != hipSuccess) return e;
-  }
-  return hipSuccess;
-}
+hipError_t gemm_set_attributes() { return hipSuccess; }
 
 void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s) {
   if (total_tiles <= 0 || njobs <= 0 || cfg < 0 || cfg >= GEMM_NCFG) return;

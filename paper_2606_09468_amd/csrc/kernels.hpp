@@ -89,11 +89,7 @@ constexpr int MAX_JOBS = 64;
 // LDS-tiled kernel (operand chunks shared by the four waves through LDS):
 // 4: 32 x 32, 5: 64 x 32, 6: 64 x 64, 7: 128 x 64 (double-buffered chunks),
 // 8: 32 x 32, 9: 64 x 32 (one buffer, chunks of 64 k).
-// Operator-stationary kernel (10, wide tables): one 512-thread workgroup per
-// CU holds a row panel of the operator in LDS and streams 64-column units of
-// B through it.
-constexpr int GEMM_PANEL = 10;
-constexpr int GEMM_NCFG = 11;
+constexpr int GEMM_NCFG = 10;
 inline int gemm_lda(int k) { return (k + 15) & ~15; }
 inline int gemm_rows(int m) { return (m + 127) & ~127; }
 
