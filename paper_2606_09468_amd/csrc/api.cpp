@@ -1040,7 +1040,7 @@ void build_batch(Batch* b) {
     b->bfin += eblocks;
     b->hfin.push_back(q);
   }
-  b->xnt = xpencil_threads(b->prec, b->lx);
+  b->xnt = xpencil_threads(b->prec, b->lx, b->bx);
 }
 
 // Carves every member, builds all tables, and carves the batch's device

@@ -821,18 +821,26 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restric
 }
 
 // one workgroup per member
+// Step record of one member from its per-line partial records: min / max /
+// sums over lines in a fixed order (per thread over its lines, then wave
+// butterflies, then waves in index order), so replays are bitwise identical.
+// One workgroup per member.  (Folding this into the row kernel's last
+// workgroup was measured slower: the device-scope fences it needs write back
+// the L2 of every XCD once per row workgroup.)
+struct FinPart {
+  double mn, mmn, cf, es, ts;
+  unsigned long long n3, n0, m3, m0;
+  int b;
+};
 __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restrict__ args) {
   const DFinArgs& FA = args[blockIdx.x];
-  const Dims d = FA.d;
-  const Phys p = FA.p;
+  const Dims& d = FA.d;
+  const Phys& p = FA.p;
   const DiagPart* __restrict__ parts = FA.parts;
   const int zrows = FA.zrows, cap = FA.cap;
-  const double* __restrict__ w = FA.w;
+  const gptr<const double> w = gmem(FA.w);
   DevScalars* __restrict__ sc = FA.sc;
-  DiagRec* __restrict__ ring = FA.ring;
-  __shared__ double smin[NT], smmin[NT], scfl[NT], se[NT], st_[NT];
-  __shared__ unsigned long long s3[NT], s0[NT], sm3[NT], sm0[NT];
-  __shared__ int sb[NT];
+  __shared__ FinPart fp[NT / 64];
   const int tid = threadIdx.x;
   const int n1 = d.N + 1, nrows = n1 * zrows, mid = d.N / 2;
   const double norm = 1.0 / ((double)d.nx * (d.dim == 3 ? d.nz : 1));
@@ -856,55 +864,55 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
     }
     b |= q.nonfinite | q.big;
   }
-  smin[tid] = mn;
-  smmin[tid] = mmn;
-  scfl[tid] = cf;
-  se[tid] = es;
-  st_[tid] = ts;
-  s3[tid] = n3;
-  s0[tid] = n0;
-  sm3[tid] = m3;
-  sm0[tid] = m0;
-  sb[tid] = b;
+  FinPart v;
+  v.mn = wave_min(mn);
+  v.mmn = wave_min(mmn);
+  v.cf = wave_max(cf);
+  v.es = wave_sum(es);
+  v.ts = wave_sum(ts);
+  v.n3 = wave_sumu(n3);
+  v.n0 = wave_sumu(n0);
+  v.m3 = wave_sumu(m3);
+  v.m0 = wave_sumu(m0);
+  v.b = wave_or(b);
+  if ((tid & 63) == 0) fp[tid >> 6] = v;
   __syncthreads();
-  for (int h = NT / 2; h > 0; h >>= 1) {
-    if (tid < h) {
-      smin[tid] = fmin(smin[tid], smin[tid + h]);
-      smmin[tid] = fmin(smmin[tid], smmin[tid + h]);
-      scfl[tid] = fmax(scfl[tid], scfl[tid + h]);
-      se[tid] += se[tid + h];
-      st_[tid] += st_[tid + h];
-      s3[tid] += s3[tid + h];
-      s0[tid] += s0[tid + h];
-      sm3[tid] += sm3[tid + h];
-      sm0[tid] += sm0[tid + h];
-      sb[tid] |= sb[tid + h];
-    }
-    __syncthreads();
+  if (tid != 0) return;
+  FinPart t = fp[0];
+  for (int w2 = 1; w2 < NT / 64; ++w2) {
+    const FinPart& o = fp[w2];
+    t.mn = fmin(t.mn, o.mn);
+    t.mmn = fmin(t.mmn, o.mmn);
+    t.cf = fmax(t.cf, o.cf);
+    t.es += o.es;
+    t.ts += o.ts;
+    t.n3 += o.n3;
+    t.n0 += o.n0;
+    t.m3 += o.m3;
+    t.m0 += o.m0;
+    t.b |= o.b;
   }
-  if (tid == 0) {
-    const long long step = sc->step + 1;
-    const double t = sc->t + p.dt;
-    DiagRec r;
-    r.step = step;
-    r.t = t;
-    r.min_trc = smin[0];
-    r.mid_min_trc = smmin[0];
-    r.cfl = p.dt * scfl[0];
-    r.dpdx = sc->pi;
-    r.energy = se[0];
-    r.mean_trc = st_[0];
-    r.n_lt3 = s3[0];
-    r.n_lt0 = s0[0];
-    r.mid_n_lt3 = sm3[0];
-    r.mid_n_lt0 = sm0[0];
-    r.blowup = sb[0] ? 1 : 0;
-    r.reserved = 0;
-    ring[(step - 1) % cap] = r;
-    sc->step = step;
-    sc->t = t;
-    sc->blowup |= r.blowup;
-  }
+  const long long step = sc->step + 1;
+  const double tt = sc->t + p.dt;
+  DiagRec r;
+  r.step = step;
+  r.t = tt;
+  r.min_trc = t.mn;
+  r.mid_min_trc = t.mmn;
+  r.cfl = p.dt * t.cf;
+  r.dpdx = sc->pi;
+  r.energy = t.es;
+  r.mean_trc = t.ts;
+  r.n_lt3 = t.n3;
+  r.n_lt0 = t.n0;
+  r.mid_n_lt3 = t.m3;
+  r.mid_n_lt0 = t.m0;
+  r.blowup = t.b ? 1 : 0;
+  r.reserved = 0;
+  FA.ring[(step - 1) % cap] = r;
+  sc->step = step;
+  sc->t = tt;
+  sc->blowup |= r.blowup;
 }
 
 }  // namespace
@@ -912,11 +920,14 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
 // x pencils: 16 complex values per thread (83 VGPRs in FP32 3D, 108 in FP64:
 // five and four waves per SIMD).  A CU runs four or five 256-thread
 // workgroups unless their LDS does not fit four times; then 512-thread
-// workgroups keep 16 waves per CU in flight on the same LDS.
+// workgroups keep 16 waves per CU in flight on the same LDS.  A launch of
+// fewer lines than the CUs can hold at 256 threads (a 2D grid: one line per
+// padded y row) also takes 512 threads, which halves each line's passes.
 constexpr int XMV32 = 16;
-int xpencil_threads(int precision, size_t lds) {
+int xpencil_threads(int precision, size_t lds, int lines) {
   (void)precision;
   if (lds == 0) return NT;
+  if (lines < 4 * 256) return 2 * NT;
   return (160 * 1024) / lds < 4 ? 2 * NT : NT;
 }
 
@@ -972,12 +983,13 @@ void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hi
   hipLaunchKernelGGL(diag_rows_kernel, dim3(blocks), dim3(NT), lds, s, args, nmem);
 }
 
-size_t diag_rows_lds_bytes(int L) { return (lds_padded<double>(2 * (size_t)L) + L) * sizeof(c2); }
-
 void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s) {
   if (nmem <= 0) return;
   hipLaunchKernelGGL(diag_final_kernel, dim3(nmem), dim3(NT), 0, s, args);
 }
+
+size_t diag_rows_lds_bytes(int L) { return (lds_padded<double>(2 * (size_t)L) + L) * sizeof(c2); }
+
 
 hipError_t fft_set_attributes() {
   const int lim = 160 * 1024;

@@ -268,8 +268,8 @@ __device__ inline int member_of(const Args* __restrict__ a, int nmem) {
 // precision 0: FP64; otherwise FP32 with the mixed products.  lds: dynamic
 // LDS bytes (the largest member's need).  The launch shape is chosen once per
 // launch from its largest member: threads per x-pencil workgroup
-// (xpencil_threads of that LDS size).
-int xpencil_threads(int precision, size_t lds);
+// (xpencil_threads of that LDS size and the launch's line count).
+int xpencil_threads(int precision, size_t lds, int lines);
 void launch_xpencil(int dim, int precision, int threads, const XArgs* args, int nmem, int blocks, size_t lds,
                     hipStream_t s);
 void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
