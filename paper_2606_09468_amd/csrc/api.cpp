@@ -1123,6 +1123,13 @@ std::map<std::vector<int>, int>& tune_cache() {
 pcs_status autotune(Batch* b) {
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
+  // PCS_PRODUCT_FORM=plain or =parity restricts the choice to one form of
+  // every table (for testing both; default: both forms are timed)
+  int forms = 3;
+  if (const char* f = std::getenv("PCS_PRODUCT_FORM")) {
+    if (!std::strcmp(f, "plain")) forms = 1;
+    if (!std::strcmp(f, "parity")) forms = 2;
+  }
   hipStream_t s = b->s;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1130,7 +1137,8 @@ pcs_status autotune(Batch* b) {
   for (JobList* jl : b->lists()) {
     if (!jl->n() || jl->cfg < 0) continue;  // nothing to tune on the matrix-vector kernel
     jl->use(0);
-    const auto key = jl->key();
+    auto key = jl->key();
+    key.push_back(forms);
     auto it = tune_cache().find(key);
     int best = -1, bestf = 0;
     if (it != tune_cache().end()) {
@@ -1139,6 +1147,7 @@ pcs_status autotune(Batch* b) {
     } else {
       float tbest = 1e30f;
       for (int f = 0; f < 2; ++f) {
+        if (!(forms & (1 << f))) continue;
         jl->use(f);
         for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
           if (!jl->allowed(cfg)) continue;

@@ -4,8 +4,8 @@ Every case starts both sides from the same state (the seeded initial
 condition built independently on each side, or a random state passed in
 through pcs_set_state) and compares the full flat state element by element,
 per field, relative to the field's max norm (the oracle's).  Tolerances are
-written per case; the design doc derives them from the conditioning of the
-wall-normal operators (|D| ~ N^2, |D2| ~ N^4) and lists the measured values.
+written per case and derived (in the helpers below) from the conditioning
+of the wall-normal operators (|D| ~ N^2, |D2| ~ N^4).
 Diagnostic counts must agree exactly whenever no oracle point lies within
 TIE_BAND of a threshold (3 or 0).
 """
@@ -123,6 +123,23 @@ CASES = [
     # 32 kx columns of length 144 exceed one register pass: z columns in two batches
     ("3D wide-z 64x17x96 x3", Grid(3, 64, 17, 96), dict(wi=50.0, dt=5e-4), 3),
 ]
+
+
+@pytest.mark.parametrize("form", ["plain", "parity"])
+def test_both_product_forms_match_oracle(P, form, monkeypatch):
+    """The autotuner picks, per product table, the plain or the parity
+    (even/odd folded) form; either must reproduce the oracle.  The form is
+    forced through PCS_PRODUCT_FORM, read when a simulation is set up.  Odd
+    and even padded sizes (N = 24: M + 1 = 37; N = 10: M + 1 = 16) and 3D."""
+    monkeypatch.setenv("PCS_PRODUCT_FORM", form)
+    for name, g, prm, n in (("2D 24x25", Grid(2, 24, 25), dict(wi=20.0, dt=1e-3), 10),
+                            ("2D 16x11", Grid(2, 16, 11), dict(wi=20.0, dt=1e-3), 10),
+                            ("3D 16x17x16", Grid(3, 16, 17, 16), dict(wi=20.0, dt=1e-3), 5)):
+        case = "%s %s" % (form, name)
+        a, o, recs = run_pair(P, g, prm, seed=1, amp=1e-3, nsteps=n, case=case)
+        N = g.ny - 1
+        check_state(a, o.get_state(), g, tol_prognostic(N), tol_history(N), case)
+        check_diag(recs, o, o.trace_c(), case)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
