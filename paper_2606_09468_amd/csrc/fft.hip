@@ -475,7 +475,7 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
     // loads are issued before any of them is packed
     const int nkb = (nkx + 63) >> 6;
     const int items = max(0, (nb - wave + NW - 1) / NW) * nkb;
-    constexpr int G = 4;
+    constexpr int G = (sizeof(T) == 4 && DIM == 3) ? 8 : 4;  // measured: 8 costs FP64 and 2D more registers than it saves
     for (int i0 = 0; i0 < items; i0 += G) {
       T2 va[G], vb[G];
 #pragma unroll
