@@ -52,6 +52,7 @@ struct JobList {
   GemmJob* dev = nullptr;
   GemmType type = GEMM_DDD;
   int tiles = 0, cfg = 0, form = 0;
+  size_t lds = 0;
   void add(const void* A, const void* B, int ldb, void* C, int ldc, int m, int n, int k, int flags = 0,
            int scale = SCALE_NONE, const EigScale* es = nullptr, void* C2 = nullptr, int scale2 = SCALE_NONE) {
     GemmJob j{};
@@ -116,6 +117,7 @@ struct JobList {
   void set_cfg(int c) {
     cfg = c;
     tiles = gemm_prepare(h.data(), n(), cfg);
+    lds = gemm_lds_bytes(type, h.data(), n(), cfg);
   }
   // shape signature for the tuning cache
   std::vector<int> key() const {
@@ -127,7 +129,7 @@ struct JobList {
     }
     return k;
   }
-  void run(hipStream_t s) const { gemm_run(type, dev, tiles, n(), cfg, s); }
+  void run(hipStream_t s) const { gemm_run(type, dev, tiles, n(), cfg, lds, s); }
 };
 
 // Row-major (rows x cols) operator -> the padded row-major copy (gemm_rows
@@ -194,7 +196,7 @@ struct Member {
   // parity halves [even, odd] of the operators of the wide products:
   // padded-grid values and d/dy, D2, D, projection and D P (fold / unfold);
   // V^-1 (fold / split), V and D V (split / unfold)
-  double *IMNp[2], *DMNp[2], *D2p[2], *Dp[2], *PNMp[2], *DPp[2], *V4p[2], *V5p[2], *DVp[2];
+  double *IMNp[2], *DMNp[2], *D2p[2], *Dp[2], *PNMp[2], *DPp[2], *V4p[2], *V5p[2], *DVp[2], *wVp[2];
   float *IMN32p[2], *DMN32p[2], *PNM32p[2], *DP32p[2];
   double *twx, *twz, *twbx, *twbz;
   double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *DN, *Dc, *D2buf, *hgn, *hvn;
@@ -317,6 +319,7 @@ void carve(Member* m, Carve& c) {
       m->V4p[q] = c.take<double>(opsz(ne, ne));
       m->V5p[q] = c.take<double>(opsz(ne, ne));
       m->DVp[q] = c.take<double>(opsz(nh, ne));
+      m->wVp[q] = c.take<double>(opsz(1, ne));
       m->IMN32p[q] = m->prec != 0 ? c.take<float>(opsz(mh, nh)) : nullptr;
       m->DMN32p[q] = m->prec != 0 ? c.take<float>(opsz(mh, nh)) : nullptr;
       m->PNM32p[q] = m->prec != 0 ? c.take<float>(opsz(nh, mh)) : nullptr;
@@ -630,12 +633,18 @@ void build_jobs(Member* m) {
     gb.type = GEMM_DDD;
     double* Yb = m->Ybar;
     int q = 0;
-    gb.add(m->IMN, st + 0 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    if (d.dim == 3) gb.add(m->IMN, st + 2 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    gb.add(m->DMN, st + 0 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    if (d.dim == 3) gb.add(m->DMN, st + 2 * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    for (int a = 0; a < d.nc; ++a) gb.add(m->IMN, st + (FC + a) * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
-    for (int a = 0; a < d.nc; ++a) gb.add(m->DMN, st + (FC + a) * fs, cw, Yb + (q++) * m1, 1, m1, 1, n1);
+    auto mval = [&](const double* src) {
+      gb.addp(PAR_FOLD_UNFOLD, m->IMN, m->IMNp[0], m->IMNp[1], src, cw, Yb + (q++) * m1, 1, mh, 1, nh, m1, n1, +1);
+    };
+    auto mdy = [&](const double* src) {
+      gb.addp(PAR_FOLD_UNFOLD, m->DMN, m->DMNp[0], m->DMNp[1], src, cw, Yb + (q++) * m1, 1, mh, 1, nh, m1, n1, -1);
+    };
+    mval(st + 0 * fs);
+    if (d.dim == 3) mval(st + 2 * fs);
+    mdy(st + 0 * fs);
+    if (d.dim == 3) mdy(st + 2 * fs);
+    for (int a = 0; a < d.nc; ++a) mval(st + (FC + a) * fs);
+    for (int a = 0; a < d.nc; ++a) mdy(st + (FC + a) * fs);
   }
   // G1b (FP64): D2 of phi, (g), c and of the mean U, (W); D of every c
   JobList& g1b = m->G1b;
@@ -647,8 +656,9 @@ void build_jobs(Member* m) {
   if (d.dim == 3) d2(st + 4 * fs, m->D2buf + 1 * fs);
   for (int a = 0; a < d.nc; ++a) d2(st + (FC + a) * fs, m->D2buf + (m->nsv + a) * fs);
   double* D2U = m->D2buf + (size_t)m->nsolve * fs;
-  g1b.add(m->D2, st + 0 * fs, cw, D2U, 1, n1, 1, n1);
-  if (d.dim == 3) g1b.add(m->D2, st + 2 * fs, cw, D2U + n1, 1, n1, 1, n1);
+  g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], st + 0 * fs, cw, D2U, 1, nh, 1, nh, n1, n1, +1);
+  if (d.dim == 3)
+    g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], st + 2 * fs, cw, D2U + n1, 1, nh, 1, nh, n1, n1, +1);
   for (int a = 0; a < d.nc; ++a)
     g1b.addp(PAR_FOLD_UNFOLD, m->D, m->Dp[0], m->Dp[1], st + (FC + a) * fs, cw, m->Dc + a * fs, cw, nh, cw, nh, n1, n1,
              -1);
@@ -669,7 +679,9 @@ void build_jobs(Member* m) {
   if (mixed) {
     // the mean column again, in FP64, from the FP64-completed padded-grid means
     m->Gm.type = GEMM_DDD;
-    for (int f = 0; f < m->nout; ++f) m->Gm.add(m->PNM, m->mcol + (size_t)f * m1, 1, m->smean + f * n1, 1, n1, 1, m1);
+    for (int f = 0; f < m->nout; ++f)
+      m->Gm.addp(PAR_FOLD_UNFOLD, m->PNM, m->PNMp[0], m->PNMp[1], m->mcol + (size_t)f * m1, 1, m->smean + f * n1, 1, nh,
+                 1, mh, n1, m1, +1);
   }
   // G4: V^-1 R, written scaled by the inverse Helmholtz symbols into
   // Xs = [phi, v, (g), c...] (phi's coefficients give v's as a second output)
@@ -696,8 +708,8 @@ void build_jobs(Member* m) {
   }
   if (d.dim == 3) vmul(m->G5, Xs + 2 * fsi, m->Zg);
   for (int a = 0; a < d.nc; ++a) vmul(m->G5, Xs + (xo + a) * fsi, st + (FC + a) * fs + cw);
-  // w . U_p for the flux constraint: the mean column only
-  m->G5.add(m->wV, Xs, cw, m->flux, cw, 1, 2, ni);
+  // w . U_p for the flux constraint: the mean column only (w V split like V)
+  m->G5.addp(PAR_SPLIT_UNFOLD, m->wV, m->wVp[0], m->wVp[1], Xs, cw, m->flux, cw, 1, 2, ne, 1, ni, +1);
   for (JobList* jl : {&m->H4, &m->H5}) jl->prepare();
 }
 
@@ -783,6 +795,9 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
     e = block(DV, ni, nh, 0, ne, ne);
     o = block(DV, ni, nh, ne, no, ne);
     HIPCHK(put2(m->DVp, nh, ne));
+    e = block(wV, ni, 1, 0, ne, ne);
+    o = block(wV, ni, 1, ne, no, ne);
+    HIPCHK(put2(m->wVp, 1, ne));
   }
   std::vector<double> ydy(n1);
   const double* y = op->y.data();
@@ -1135,7 +1150,7 @@ pcs_status autotune(Batch* b) {
   HIPCHK(hipEventCreate(&e0));
   HIPCHK(hipEventCreate(&e1));
   for (JobList* jl : b->lists()) {
-    if (!jl->n() || jl->cfg < 0) continue;  // nothing to tune on the matrix-vector kernel
+    if (!jl->n()) continue;
     jl->use(0);
     auto key = jl->key();
     key.push_back(forms);

@@ -120,9 +120,10 @@ struct LCfg<9> {
 };
 constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64};
 constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32};
-// LDS (in doubles) of an LDS-tiled configuration: the plain panels, the
-// parity panels (A: BM rows of PKC, B: both halves, rows of BN + 4) and the
-// larger of the two, which the kernel declares.
+// LDS (in elements of the compute precision) of an LDS-tiled configuration:
+// the plain panels, the parity panels (A: BM rows of PKC, B: both halves,
+// rows of BN + 4) and the larger of the two.  The kernel takes its LDS
+// dynamically, sized for the forms and precisions its table holds.
 template <int CFG>
 constexpr int lds_plain() {
   return LCfg<CFG>::NBUF * LCfg<CFG>::BM * (LCfg<CFG>::KC + 2) +
@@ -543,10 +544,11 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
   constexpr int NA = KC * BM / 512, NB = KC * BN / 512;
   constexpr int RA = 512 / KC, SB = 512 / BN;
   static_assert(NA >= 1 && NB >= 1 && KC % 4 == 0, "tile shape");
-  static_assert(lds_par<CFG>() <= lds_plain<CFG>() && lds_doubles<CFG>() * 8 <= 64 * 1024, "LDS");
-  // odd -> even hand-over in rounds of XR row blocks (whatever fits the LDS)
-  constexpr int XR = (2 * RB * CB * 4 * 64 <= lds_doubles<CFG>()) ? RB : 1;
-  static_assert(2 * XR * CB * 4 * 64 <= lds_doubles<CFG>() && RB % XR == 0, "exchange area");
+  static_assert(lds_doubles<CFG>() * 8 <= 64 * 1024, "LDS");
+  // odd -> even hand-over in rounds of XR row blocks (whatever fits the
+  // parity panels' LDS)
+  constexpr int XR = (2 * RB * CB * 4 * 64 <= lds_par<CFG>()) ? RB : 1;
+  static_assert(2 * XR * CB * 4 * 64 <= lds_par<CFG>() && RB % XR == 0, "exchange area");
   typedef typename Vec<T>::v4 V4;
   typedef typename Vec<T>::v2 AP;
   typedef typename Vec<TB>::v2 BP;
@@ -711,8 +713,8 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
 template <typename T, typename TB, typename TC, int CFG>
 __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
   constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC, NBUF = LCfg<CFG>::NBUF;
-  // sized for FP64 operands, shared by both precisions of a mixed table
-  __shared__ __attribute__((aligned(16))) double smem[lds_doubles<CFG>()];
+  // gemm_lds_bytes of the table: the panels of its largest form and precision
+  extern __shared__ __attribute__((aligned(16))) double smem[];
   const int t = xcd_tile(blockIdx.x, total);
   const GemmJob* jp = jobs + find_job(jobs, njobs, t);
   const bool ddd = dual_type<T, TB, TC>() && jp->type == GEMM_DDD;
@@ -731,10 +733,11 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict
 namespace {
 
 template <typename T, typename TB, typename TC>
-void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStream_t s) {
-#define PCS_GEMM_LAUNCH(KERNEL, C)                                                                    \
-  case C:                                                                                             \
-    hipLaunchKernelGGL((KERNEL<T, TB, TC, C>), dim3(total), dim3(256), 0, s, dev_jobs, njobs, total); \
+void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, size_t lds, hipStream_t s) {
+#define PCS_GEMM_LAUNCH(KERNEL, C)                                                                            \
+  case C:                                                                                                     \
+    hipLaunchKernelGGL((KERNEL<T, TB, TC, C>), dim3(total), dim3(256), C < 4 ? 0 : lds, s, dev_jobs, njobs, \
+                       total);                                                                                \
     break;
   switch (cfg) {
     PCS_GEMM_LAUNCH(gemm_reg_kernel, 0)
@@ -756,16 +759,46 @@ void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, hipStrea
 
 bool gemm_cfg_parity(int cfg) { return cfg >= 4 && cfg < GEMM_NCFG; }
 
+namespace {
+template <int CFG>
+size_t lds_form(bool parity, size_t esize) {
+  // + 8: the B panel starts on a double boundary
+  return esize * (size_t)(parity ? lds_par<CFG>() : lds_plain<CFG>()) + 8;
+}
+}  // namespace
+
+size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
+  // compute precision of the table's own type (its GEMM_DDD jobs compute in FP64)
+  const size_t own = (t == GEMM_FDF || t == GEMM_FFD) ? 4 : 8;
+  size_t b = 0;
+  for (int j = 0; j < njobs; ++j) {
+    const bool par = jobs[j].kind != PAR_NONE;
+    const size_t es = jobs[j].type == GEMM_DDD ? 8 : own;
+    size_t x = 0;
+    switch (cfg) {
+      case 4: x = lds_form<4>(par, es); break;
+      case 5: x = lds_form<5>(par, es); break;
+      case 6: x = lds_form<6>(par, es); break;
+      case 7: x = lds_form<7>(par, es); break;
+      case 8: x = lds_form<8>(par, es); break;
+      case 9: x = lds_form<9>(par, es); break;
+      default: break;
+    }
+    b = x > b ? x : b;
+  }
+  return b;
+}
+
 hipError_t gemm_set_attributes() { return hipSuccess; }
 
-void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s) {
+void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, size_t lds, hipStream_t s) {
   if (total_tiles <= 0 || njobs <= 0 || cfg < 0 || cfg >= GEMM_NCFG) return;
   switch (t) {
-    case GEMM_DDD: launch_cfg<double, double, double>(dev_jobs, total_tiles, njobs, cfg, s); break;
-    case GEMM_FDF: launch_cfg<float, double, float>(dev_jobs, total_tiles, njobs, cfg, s); break;
-    case GEMM_FFD: launch_cfg<float, float, double>(dev_jobs, total_tiles, njobs, cfg, s); break;
-    case GEMM_DDF: launch_cfg<double, double, float>(dev_jobs, total_tiles, njobs, cfg, s); break;
-    case GEMM_DFD: launch_cfg<double, float, double>(dev_jobs, total_tiles, njobs, cfg, s); break;
+    case GEMM_DDD: launch_cfg<double, double, double>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
+    case GEMM_FDF: launch_cfg<float, double, float>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
+    case GEMM_FFD: launch_cfg<float, float, double>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
+    case GEMM_DDF: launch_cfg<double, double, float>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
+    case GEMM_DFD: launch_cfg<double, float, double>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
     default: break;
   }
 }

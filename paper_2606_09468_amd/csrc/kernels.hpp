@@ -98,8 +98,15 @@ inline int gemm_rows(int m) { return (m + 127) & ~127; }
 int gemm_prepare(GemmJob* jobs, int njobs, int cfg);
 // Whether configuration cfg evaluates parity products (the LDS-tiled ones).
 bool gemm_cfg_parity(int cfg);
-// t: the table's precision combination; its jobs are of type t or GEMM_DDD.
-void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, hipStream_t s);
+// LDS bytes per workgroup of the LDS-tiled configuration cfg for a table of
+// precision combination t (0 for the register-direct ones): the panels of
+// the largest product form and compute precision in the table, so that a
+// table of parity products, or of FP32 products only, keeps more
+// workgroups resident per CU.
+size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg);
+// t: the table's precision combination; its jobs are of type t or GEMM_DDD;
+// lds: gemm_lds_bytes of the same table and configuration.
+void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, size_t lds, hipStream_t s);
 
 hipError_t gemm_set_attributes();
 
