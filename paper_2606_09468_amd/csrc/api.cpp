@@ -49,7 +49,9 @@ struct Carve {
 // faster form and tile configuration; h is the form in use.
 struct JobList {
   std::vector<GemmJob> h, forms[2];
+  std::vector<int> hmap;  // job index of every logical tile
   GemmJob* dev = nullptr;
+  int* tmap = nullptr;
   GemmType type = GEMM_DDD;
   int tiles = 0, cfg = 0, form = 0;
   size_t lds = 0;
@@ -118,6 +120,18 @@ struct JobList {
     cfg = c;
     tiles = gemm_prepare(h.data(), n(), cfg);
     lds = gemm_lds_bytes(type, h.data(), n(), cfg);
+    hmap.assign(tiles, 0);
+    for (int j = 0; j < n(); ++j)
+      for (int t = h[j].tile0; t < (j + 1 < n() ? h[j + 1].tile0 : tiles); ++t) hmap[t] = j;
+  }
+  // the largest tile count of any form and configuration (the tile map's size)
+  int max_tiles() const {
+    int mx = 1;
+    for (int f = 0; f < 2; ++f) {
+      std::vector<GemmJob> c = forms[f];
+      for (int g = 0; g < GEMM_NCFG; ++g) mx = std::max(mx, gemm_prepare(c.data(), (int)c.size(), g));
+    }
+    return mx;
   }
   // shape signature for the tuning cache
   std::vector<int> key() const {
@@ -129,7 +143,7 @@ struct JobList {
     }
     return k;
   }
-  void run(hipStream_t s) const { gemm_run(type, dev, tiles, n(), cfg, lds, s); }
+  void run(hipStream_t s) const { gemm_run(type, dev, tmap, tiles, cfg, lds, s); }
 };
 
 // Row-major (rows x cols) operator -> the padded row-major copy (gemm_rows
@@ -293,6 +307,12 @@ hipError_t up(T* dst, const std::vector<T>& src, hipStream_t s) {
   return hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
 }
 
+// A product table and its tile map.
+hipError_t up_list(JobList* jl, hipStream_t s) {
+  hipError_t e = up(jl->dev, jl->h, s);
+  return e != hipSuccess ? e : up(jl->tmap, jl->hmap, s);
+}
+
 // Assigns every device buffer of one member (a null base only measures).
 void carve(Member* m, Carve& c) {
   const Dims& d = m->d;
@@ -382,8 +402,6 @@ void carve(Member* m, Carve& c) {
   m->parts = c.take<DiagPart>(n1 * zrows);
   m->ring = c.take<DiagRec>(RING);
   m->sc = c.take<DevScalars>(1);
-  m->H4.dev = c.take<GemmJob>(8);
-  m->H5.dev = c.take<GemmJob>(8);
 }
 
 pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
@@ -860,8 +878,8 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
   sc0.pi = m->p.forcing == 1 ? m->p.q_or_dpdx : 2.0 / m->p.re;
   HIPCHK(hipMemcpy(m->sc, &sc0, sizeof(sc0), hipMemcpyHostToDevice));
   // the member's own product tables (homogeneous solutions at init)
-  HIPCHK(up(m->H4.dev, m->H4.h, s));
-  HIPCHK(up(m->H5.dev, m->H5.h, s));
+  HIPCHK(up_list(&m->H4, s));
+  HIPCHK(up_list(&m->H5, s));
   return PCS_OK;
 }
 
@@ -1065,7 +1083,15 @@ size_t layout(Batch* b, char* base) {
   for (Member* m : b->mem) carve(m, c);
   for (Member* m : b->mem) build_jobs(m);
   build_batch(b);
-  for (JobList* jl : b->lists()) jl->dev = c.take<GemmJob>(std::max(1, jl->n()));
+  std::vector<JobList*> all = b->lists();
+  for (Member* m : b->mem) {
+    all.push_back(&m->H4);
+    all.push_back(&m->H5);
+  }
+  for (JobList* jl : all) {
+    jl->dev = c.take<GemmJob>(std::max(1, jl->n()));
+    jl->tmap = c.take<int>(jl->max_tiles());
+  }
   const size_t n = b->mem.size();
   b->dx = c.take<XArgs>(n);
   b->dzi = c.take<ZArgs>(n);
@@ -1135,6 +1161,12 @@ std::map<std::vector<int>, int>& tune_cache() {
   return c;
 }
 
+// With PCS_DEBUG set, the autotuner reports every timing on stderr.
+bool tune_log() {
+  static const bool on = std::getenv("PCS_DEBUG") != nullptr;
+  return on;
+}
+
 pcs_status autotune(Batch* b) {
   static std::mutex mu;
   std::lock_guard<std::mutex> g(mu);
@@ -1145,6 +1177,13 @@ pcs_status autotune(Batch* b) {
     if (!std::strcmp(f, "plain")) forms = 1;
     if (!std::strcmp(f, "parity")) forms = 2;
   }
+  // PCS_GEMM_CFG=c forces tile configuration c where the form allows it
+  // (for testing every configuration; default: all are timed)
+  int only = -1;
+  if (const char* c = std::getenv("PCS_GEMM_CFG")) {
+    only = std::atoi(c);
+    if (only < 0 || only >= GEMM_NCFG) only = -1;
+  }
   hipStream_t s = b->s;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1154,6 +1193,7 @@ pcs_status autotune(Batch* b) {
     jl->use(0);
     auto key = jl->key();
     key.push_back(forms);
+    key.push_back(only);
     auto it = tune_cache().find(key);
     int best = -1, bestf = 0;
     if (it != tune_cache().end()) {
@@ -1165,9 +1205,9 @@ pcs_status autotune(Batch* b) {
         if (!(forms & (1 << f))) continue;
         jl->use(f);
         for (int cfg = 0; cfg < GEMM_NCFG; ++cfg) {
-          if (!jl->allowed(cfg)) continue;
+          if (!jl->allowed(cfg) || (only >= 0 && cfg != only && jl->allowed(only))) continue;
           jl->set_cfg(cfg);
-          HIPCHK(up(jl->dev, jl->h, s));
+          HIPCHK(up_list(jl, s));
           jl->run(s);  // warm-up
           HIPCHK(hipEventRecord(e0, s));
           for (int r = 0; r < 3; ++r) jl->run(s);
@@ -1175,6 +1215,9 @@ pcs_status autotune(Batch* b) {
           HIPCHK(hipEventSynchronize(e1));
           float ms = 0;
           HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+          if (tune_log())
+            std::fprintf(stderr, "pcs: table of %d products (type %d): form %d cfg %2d tiles %6d lds %6zu: %8.2f us\n",
+                         jl->n(), (int)jl->type, f, cfg, jl->tiles, jl->lds, ms * 1e3f / 3);
           if (ms < tbest) {
             tbest = ms;
             best = cfg;
@@ -1186,7 +1229,7 @@ pcs_status autotune(Batch* b) {
     }
     jl->use(bestf);
     jl->set_cfg(best);
-    HIPCHK(up(jl->dev, jl->h, s));
+    HIPCHK(up_list(jl, s));
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -1219,7 +1262,7 @@ pcs_status upload_tables(Batch* b) {
   hipStream_t s = b->s;
   for (size_t i = 0; i < b->mem.size(); ++i) b->hfin[i].wU1 = b->mem[i]->wU1;
   for (JobList* jl : b->lists())
-    if (jl->n()) HIPCHK(up(jl->dev, jl->h, s));
+    if (jl->n()) HIPCHK(up_list(jl, s));
   HIPCHK(up(b->dx, b->hx, s));
   if (!b->hzi.empty()) {
     HIPCHK(up(b->dzi, b->hzi, s));

@@ -118,8 +118,25 @@ template <>
 struct LCfg<9> {
   static constexpr int BM = 64, BN = 32, KC = 64, NBUF = 1, PKC = 32;
 };
-constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64};
-constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32};
+// deep parity chunks for small tables, whose time is the chain of chunk loads
+template <>
+struct LCfg<10> {
+  static constexpr int BM = 32, BN = 32, KC = 32, NBUF = 1, PKC = 64;
+};
+template <>
+struct LCfg<11> {
+  static constexpr int BM = 32, BN = 32, KC = 32, NBUF = 2, PKC = 32;
+};
+template <>
+struct LCfg<12> {
+  static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 2, PKC = 16;
+};
+template <>
+struct LCfg<13> {
+  static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 1, PKC = 32;
+};
+constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 32, 32, 64, 64};
+constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 32, 32, 64, 64};
 // LDS (in elements of the compute precision) of an LDS-tiled configuration:
 // the plain panels, the parity panels (A: BM rows of PKC, B: both halves,
 // rows of BN + 4) and the larger of the two.  The kernel takes its LDS
@@ -148,18 +165,11 @@ __device__ inline int xcd_tile(int b, int total) {
   return x < r ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
 }
 
-// Job of logical tile t: the last job whose first tile is <= t (binary
-// search; a batch of simulations puts hundreds of jobs in one table).
-__device__ inline int find_job(const GemmJob* __restrict__ jobs, int njobs, int t) {
-  int lo = 0, hi = njobs - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (jobs[mid].tile0 <= t)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
+// Job of logical tile t, from the table's tile map (one load: a search
+// through the job table would be a chain of dependent loads at the start of
+// every workgroup, from a table that is cold in a graph-replayed step).
+__device__ inline const GemmJob* tile_job(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap, int t) {
+  return jobs + gmem(tmap)[t];
 }
 
 // Inverse Helmholtz symbol of kind `kind` for eigenvalue lam and wavenumber
@@ -342,10 +352,11 @@ constexpr bool dual_type() {
 }
 
 template <typename T, typename TB, typename TC, int CFG>
-__global__ __launch_bounds__(256) void gemm_reg_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+__global__ __launch_bounds__(256) void gemm_reg_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap,
+                                                       int total) {
   __shared__ double red[RCfg<CFG>::KS > 1 ? 4 * 16 * 64 : 1];
   const int t = xcd_tile(blockIdx.x, total);
-  const GemmJob* jp = jobs + find_job(jobs, njobs, t);
+  const GemmJob* jp = tile_job(jobs, tmap, t);
   if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
     reg_body<double, double, double, CFG>(jp, t, red);
   else
@@ -711,12 +722,13 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
 }
 
 template <typename T, typename TB, typename TC, int CFG>
-__global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, int njobs, int total) {
+__global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap,
+                                                       int total) {
   constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC, NBUF = LCfg<CFG>::NBUF;
   // gemm_lds_bytes of the table: the panels of its largest form and precision
   extern __shared__ __attribute__((aligned(16))) double smem[];
   const int t = xcd_tile(blockIdx.x, total);
-  const GemmJob* jp = jobs + find_job(jobs, njobs, t);
+  const GemmJob* jp = tile_job(jobs, tmap, t);
   const bool ddd = dual_type<T, TB, TC>() && jp->type == GEMM_DDD;
   if (jp->kind != PAR_NONE) {
     if (ddd)
@@ -733,11 +745,10 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict
 namespace {
 
 template <typename T, typename TB, typename TC>
-void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, size_t lds, hipStream_t s) {
-#define PCS_GEMM_LAUNCH(KERNEL, C)                                                                            \
-  case C:                                                                                                     \
-    hipLaunchKernelGGL((KERNEL<T, TB, TC, C>), dim3(total), dim3(256), C < 4 ? 0 : lds, s, dev_jobs, njobs, \
-                       total);                                                                                \
+void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, size_t lds, hipStream_t s) {
+#define PCS_GEMM_LAUNCH(KERNEL, C)                                                                                  \
+  case C:                                                                                                           \
+    hipLaunchKernelGGL((KERNEL<T, TB, TC, C>), dim3(total), dim3(256), C < 4 ? 0 : lds, s, dev_jobs, tmap, total); \
     break;
   switch (cfg) {
     PCS_GEMM_LAUNCH(gemm_reg_kernel, 0)
@@ -750,6 +761,10 @@ void launch_cfg(const GemmJob* dev_jobs, int total, int njobs, int cfg, size_t l
     PCS_GEMM_LAUNCH(gemm_lds_kernel, 7)
     PCS_GEMM_LAUNCH(gemm_lds_kernel, 8)
     PCS_GEMM_LAUNCH(gemm_lds_kernel, 9)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 10)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 11)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 12)
+    PCS_GEMM_LAUNCH(gemm_lds_kernel, 13)
     default: break;
   }
 #undef PCS_GEMM_LAUNCH
@@ -782,6 +797,10 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
       case 7: x = lds_form<7>(par, es); break;
       case 8: x = lds_form<8>(par, es); break;
       case 9: x = lds_form<9>(par, es); break;
+      case 10: x = lds_form<10>(par, es); break;
+      case 11: x = lds_form<11>(par, es); break;
+      case 12: x = lds_form<12>(par, es); break;
+      case 13: x = lds_form<13>(par, es); break;
       default: break;
     }
     b = x > b ? x : b;
@@ -791,14 +810,15 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
 
 hipError_t gemm_set_attributes() { return hipSuccess; }
 
-void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, size_t lds, hipStream_t s) {
-  if (total_tiles <= 0 || njobs <= 0 || cfg < 0 || cfg >= GEMM_NCFG) return;
+void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_tiles, int cfg, size_t lds,
+              hipStream_t s) {
+  if (total_tiles <= 0 || cfg < 0 || cfg >= GEMM_NCFG) return;
   switch (t) {
-    case GEMM_DDD: launch_cfg<double, double, double>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
-    case GEMM_FDF: launch_cfg<float, double, float>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
-    case GEMM_FFD: launch_cfg<float, float, double>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
-    case GEMM_DDF: launch_cfg<double, double, float>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
-    case GEMM_DFD: launch_cfg<double, float, double>(dev_jobs, total_tiles, njobs, cfg, lds, s); break;
+    case GEMM_DDD: launch_cfg<double, double, double>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
+    case GEMM_FDF: launch_cfg<float, double, float>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
+    case GEMM_FFD: launch_cfg<float, float, double>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
+    case GEMM_DDF: launch_cfg<double, double, float>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
+    case GEMM_DFD: launch_cfg<double, float, double>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
     default: break;
   }
 }

@@ -88,13 +88,16 @@ constexpr int MAX_JOBS = 64;
 // the four waves, 1: 64 x 32 and 2: 32 x 64 with K split in two, 3: 64 x 64.
 // LDS-tiled kernel (operand chunks shared by the four waves through LDS):
 // 4: 32 x 32, 5: 64 x 32, 6: 64 x 64, 7: 128 x 64 (double-buffered chunks),
-// 8: 32 x 32, 9: 64 x 32 (one buffer, chunks of 64 k).
-constexpr int GEMM_NCFG = 10;
+// 8: 32 x 32, 9: 64 x 32 (one buffer, chunks of 64 k), and for small tables
+// deeper parity chunks: 10, 11: 32 x 32, 12, 13: 64 x 64.
+constexpr int GEMM_NCFG = 14;
 inline int gemm_lda(int k) { return (k + 15) & ~15; }
 inline int gemm_rows(int m) { return (m + 127) & ~127; }
 
 // Fills tiles_m / tile0 for tile configuration cfg and returns the total
-// number of workgroups.
+// number of workgroups.  Logical tile t belongs to the last job whose tile0
+// is <= t; the kernels read that job index from a tile map (one int per
+// tile) built by the caller.
 int gemm_prepare(GemmJob* jobs, int njobs, int cfg);
 // Whether configuration cfg evaluates parity products (the LDS-tiled ones).
 bool gemm_cfg_parity(int cfg);
@@ -105,8 +108,10 @@ bool gemm_cfg_parity(int cfg);
 // workgroups resident per CU.
 size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg);
 // t: the table's precision combination; its jobs are of type t or GEMM_DDD;
-// lds: gemm_lds_bytes of the same table and configuration.
-void gemm_run(GemmType t, const GemmJob* dev_jobs, int total_tiles, int njobs, int cfg, size_t lds, hipStream_t s);
+// tmap: job index of every logical tile; lds: gemm_lds_bytes of the same
+// table and configuration.
+void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_tiles, int cfg, size_t lds,
+              hipStream_t s);
 
 hipError_t gemm_set_attributes();
 

@@ -142,6 +142,63 @@ def test_both_product_forms_match_oracle(P, form, monkeypatch):
         check_diag(recs, o, o.trace_c(), case)
 
 
+_ORACLE_CACHE = {}
+
+
+def _oracle_run(name, g, prm, n):
+    if name not in _ORACLE_CACHE:
+        o = Oracle(g, Params(**prm), seed=1, amp=1e-3)
+        o.step(n)
+        _ORACLE_CACHE[name] = o
+    return _ORACLE_CACHE[name]
+
+
+# tile configurations of the product kernels: 0-3 register-direct (plain
+# form only), 4-13 LDS-tiled (plain and parity forms)
+GEMM_CFGS = list(range(14))
+
+
+@pytest.mark.parametrize("cfg", GEMM_CFGS)
+def test_every_tile_configuration_matches_oracle(P, cfg, monkeypatch):
+    """The autotuner may pick any tile configuration for any table, so each
+    one, forced through PCS_GEMM_CFG in both product forms, must reproduce
+    the oracle: FP64 2D with odd padded sizes (N = 24: M + 1 = 37) and 3D,
+    and a mixed-precision 2D run (FP32 tables mixing FP64 products)."""
+    monkeypatch.setenv("PCS_GEMM_CFG", str(cfg))
+    forms = ["plain", "parity"] if cfg >= 4 else ["plain"]
+    cases = (("2D 24x25", Grid(2, 24, 25), dict(wi=20.0, dt=1e-3), 10),
+             ("3D 16x17x16", Grid(3, 16, 17, 16), dict(wi=20.0, dt=1e-3), 5))
+    for form in forms:
+        monkeypatch.setenv("PCS_PRODUCT_FORM", form)
+        for name, g, prm, n in cases:
+            case = "cfg %d %s %s" % (cfg, form, name)
+            print("case", case, flush=True)
+            sim = P.Sim(P.make_grid(g.dim, g.nx, g.ny, g.nz, g.lx, g.lz), P.make_params(**prm), seed=1, amp=1e-3)
+            sim.step(n)
+            recs, st = sim.diagnostics()
+            assert st == P.PCS_OK and len(recs) == n
+            a = sim.get_state()
+            sim.close()
+            o = _oracle_run(name, g, prm, n)
+            N = g.ny - 1
+            check_state(a, o.get_state(), g, tol_prognostic(N), tol_history(N), case)
+            check_diag(recs, o, o.trace_c(), case)
+        # mixed precision: the fluctuation bar of the mixed-precision test
+        name, g, prm, n = "2D 32x33 mixed", Grid(2, 32, 33), dict(wi=20.0, dt=1e-3), 10
+        case = "cfg %d %s %s" % (cfg, form, name)
+        print("case", case, flush=True)
+        sim = P.Sim(P.make_grid(g.dim, g.nx, g.ny, g.nz, g.lx, g.lz), P.make_params(precision=1, **prm),
+                    seed=1, amp=1e-3)
+        sim.step(n)
+        a = sim.get_state()
+        sim.close()
+        o = _oracle_run(name, g, prm, n)
+        errs = fluct_errors(a, o.get_state(), g)
+        _, names, _ = state_layout(g)
+        for k in names[:6]:
+            assert errs[k][0] <= 2e-4 and errs[k][1] <= 2e-5, (case, k, errs[k])
+
+
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_seeded_run_matches_oracle(P, case):
     name, g, prm, n = case
