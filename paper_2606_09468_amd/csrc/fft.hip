@@ -171,14 +171,31 @@ __device__ inline void butterfly(cx<T>* v, int sign) {
   }
 }
 
+// Synchronisation around the writes of a pass: the workgroup's barrier, or,
+// when the sequences of the pass belong to one wave (WAVE), only a fence that
+// keeps the compiler from moving LDS accesses across it (a wave's LDS
+// instructions execute in order, so its reads of a pass complete before its
+// writes, and its writes before the next pass's reads).
+template <bool WAVE>
+__device__ __attribute__((always_inline)) inline void pass_sync() {
+  if constexpr (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
 // One in-place Stockham pass (pass p of the plan, radix R) over nseq
 // sequences of length L: every thread reads its butterfly inputs into
-// registers, the workgroup synchronises, and the outputs go to their sorted
-// positions.  twl[m] = exp(-2 pi i m / L).  NTH threads, at most MV complex
-// values per thread: requires nseq L <= NTH cover(MV).
-template <typename T, int R, int NTH, int MV>
-__device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl, const FftPlan& pl, int p, int nseq, const cx<T>* __restrict__ tw,
-                        int sign) {
+// registers, the threads synchronise, and the outputs go to their sorted
+// positions.  twl[m] = exp(-2 pi i m / L).  NTH threads (thread tid: the
+// workgroup's, or one wave's lanes for WAVE), at most MV complex values per
+// thread: requires nseq L <= NTH cover(MV).
+template <typename T, int R, int NTH, int MV, bool WAVE>
+__device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl, const FftPlan& pl, int p, int nseq,
+                                                              const cx<T>* __restrict__ tw, int sign, int tid) {
   constexpr int NB = MV / R;
   const int L = pl.L, LR = pl.lr[p], Ns = pl.ns[p], stride = pl.ts[p];
   const unsigned mLR = pl.mlr[p], mNs = pl.mns[p];
@@ -186,7 +203,7 @@ __device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl,
   cx<T> v[NB][R];
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int idx = threadIdx.x + q * NTH;
+    const int idx = tid + q * NTH;
     if (idx < tot) {
       const int s = fdiv(idx, mLR), j = idx - s * LR;
       const LV<T> src = buf.at(s * sl + j);
@@ -194,10 +211,10 @@ __device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl,
       for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
     }
   }
-  __syncthreads();
+  pass_sync<WAVE>();
 #pragma unroll
   for (int q = 0; q < NB; ++q) {
-    const int idx = threadIdx.x + q * NTH;
+    const int idx = tid + q * NTH;
     if (idx < tot) {
       const int s = fdiv(idx, mLR), j = idx - s * LR;
       const int k = j - fdiv(j, mNs) * Ns;
@@ -215,25 +232,134 @@ __device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl,
       for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
     }
   }
-  __syncthreads();
+  pass_sync<WAVE>();
 }
 
-// nseq sequences of length pl.L, sequence s at buf + s * sl (sl >= L).
-// Inlined at every call: as a called function its register needs add to the
-// caller's (measured: 211-228 VGPRs in the x-pencil and diagnostics kernels).
-template <typename T, int NTH = NT, int MV = maxv<T>()>
-__device__ __attribute__((always_inline)) inline void lds_fft(LV<T> buf, int sl, const FftPlan& pl, int nseq, const cx<T>* __restrict__ tw, int sign) {
+// nseq sequences of length pl.L, sequence s at buf + s * sl (sl >= L),
+// transformed by the workgroup, or for WAVE by the calling wave alone
+// (tid: its lane).  Inlined at every call: as a called function its register
+// needs add to the caller's (measured: 211-228 VGPRs in the x-pencil and
+// diagnostics kernels).
+template <typename T, int NTH = NT, int MV = maxv<T>(), bool WAVE = false>
+__device__ __attribute__((always_inline)) inline void lds_fft(LV<T> buf, int sl, const FftPlan& pl, int nseq,
+                                                              const cx<T>* __restrict__ tw, int sign,
+                                                              int tid = threadIdx.x) {
   for (int p = 0; p < pl.npass; ++p) {
     const int R = pl.radix[p];
     if (R == 8)
-      pass_ip<T, 8, NTH, MV>(buf, sl, pl, p, nseq, tw, sign);
+      pass_ip<T, 8, NTH, MV, WAVE>(buf, sl, pl, p, nseq, tw, sign, tid);
     else if (R == 4)
-      pass_ip<T, 4, NTH, MV>(buf, sl, pl, p, nseq, tw, sign);
+      pass_ip<T, 4, NTH, MV, WAVE>(buf, sl, pl, p, nseq, tw, sign, tid);
     else if (R == 2)
-      pass_ip<T, 2, NTH, MV>(buf, sl, pl, p, nseq, tw, sign);
+      pass_ip<T, 2, NTH, MV, WAVE>(buf, sl, pl, p, nseq, tw, sign, tid);
     else
-      pass_ip<T, 3, NTH, MV>(buf, sl, pl, p, nseq, tw, sign);
+      pass_ip<T, 3, NTH, MV, WAVE>(buf, sl, pl, p, nseq, tw, sign, tid);
   }
+}
+
+// ------------------------------------------------ transforms of a length fixed at compile time
+// The plan of make_plan (radix 8 passes, then 4, 2, 3) for a length L known at
+// compile time, so that a pass's divisions, strides and twiddle indices fold
+// into constants (the runtime plan spends more instructions on index
+// arithmetic and plan loads than on the butterflies).
+__host__ __device__ constexpr int crad_try(int i) { return i == 0 ? 8 : (i == 1 ? 4 : (i == 2 ? 2 : 3)); }
+__host__ __device__ constexpr int cpass_count(int L) {
+  int n = 0;
+  for (int i = 0; i < 4; ++i)
+    while (L > 1 && L % crad_try(i) == 0) {
+      L /= crad_try(i);
+      ++n;
+    }
+  return n;
+}
+__host__ __device__ constexpr int cradix(int L, int p) {
+  for (int i = 0; i < 4; ++i)
+    while (L > 1 && L % crad_try(i) == 0) {
+      if (p == 0) return crad_try(i);
+      L /= crad_try(i);
+      --p;
+    }
+  return 1;
+}
+__host__ __device__ constexpr int cns(int L, int p) {
+  int ns = 1;
+  for (int i = 0; i < p; ++i) ns *= cradix(L, i);
+  return ns;
+}
+// lengths with compiled plans (those of the x and z transforms of the
+// workloads: 3/2 of 64, 128, 256, 512)
+__host__ __device__ constexpr bool compiled_length(int L) { return L == 96 || L == 192 || L == 384 || L == 768; }
+
+// pass_ip with the plan of length L fixed (SIGN: +1 inverse, -1 forward)
+template <typename T, int L, int P, int NTH, int MV, bool WAVE, int SIGN>
+__device__ __attribute__((always_inline)) inline void pass_c(LV<T> buf, int sl, int nseq, const cx<T>* __restrict__ tw,
+                                                             int tid) {
+  constexpr int R = cradix(L, P), LR = L / R, Ns = cns(L, P), stride = L / (Ns * R);
+  constexpr int NB = MV / R;
+  static_assert(cpass_count(L) > 0 && R > 1 && NB >= 1, "plan");
+  const int tot = nseq * LR;
+  cx<T> v[NB][R];
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int idx = tid + q * NTH;
+    if (idx < tot) {
+      const int s = idx / LR, j = idx - s * LR;
+      const LV<T> src = buf.at(s * sl + j);
+#pragma unroll
+      for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
+    }
+  }
+  pass_sync<WAVE>();
+#pragma unroll
+  for (int q = 0; q < NB; ++q) {
+    const int idx = tid + q * NTH;
+    if (idx < tot) {
+      const int s = idx / LR, j = idx - s * LR;
+      const int k = j % Ns;
+      if constexpr (Ns > 1) {
+#pragma unroll
+        for (int r = 1; r < R; ++r) {
+          cx<T> w = tw[r * k * stride];
+          if constexpr (SIGN > 0) w.y = -w.y;
+          v[q][r] = cmul(v[q][r], w);
+        }
+      }
+      butterfly<T, R>(v[q], SIGN);
+      const LV<T> dst = buf.at(s * sl + (j - k) * R + k);
+#pragma unroll
+      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
+    }
+  }
+  pass_sync<WAVE>();
+}
+
+template <typename T, int L, int NTH, int MV, bool WAVE, int SIGN, int P = 0>
+__device__ __attribute__((always_inline)) inline void lds_fft_c(LV<T> buf, int sl, int nseq,
+                                                                const cx<T>* __restrict__ tw, int tid) {
+  if constexpr (P < cpass_count(L)) {
+    pass_c<T, L, P, NTH, MV, WAVE, SIGN>(buf, sl, nseq, tw, tid);
+    lds_fft_c<T, L, NTH, MV, WAVE, SIGN, P + 1>(buf, sl, nseq, tw, tid);
+  }
+}
+
+// Transform with the compiled plan of length LC, or with the runtime plan
+// (LC = 0).
+template <typename T, int LC, int NTH, int MV, bool WAVE, int SIGN>
+__device__ __attribute__((always_inline)) inline void fft_any(LV<T> buf, int sl, const FftPlan& pl, int nseq,
+                                                              const cx<T>* __restrict__ tw, int tid) {
+  if constexpr (LC > 0)
+    lds_fft_c<T, LC, NTH, MV, WAVE, SIGN>(buf, sl, nseq, tw, tid);
+  else
+    lds_fft<T, NTH, MV, WAVE>(buf, sl, pl, nseq, tw, SIGN, tid);
+}
+
+// Complex values per lane of the x pencils' wave-local transforms: 16, or 8
+// for FP64 lines of a compiled length up to 384 (whose registers would
+// otherwise cost a workgroup per CU).
+constexpr int XMVW = 16;
+template <typename T, int LC>
+__host__ __device__ constexpr int xmvw() {
+  return (sizeof(T) == 8 && LC > 0 && LC <= 384) ? 8 : XMVW;
 }
 
 // Largest batch of sequences a pass can hold in registers.
@@ -431,11 +557,11 @@ __device__ inline void pointwise_mixed(const Rd& r, const Md& m, T* o) {
 }
 
 // mean: [n_means][M+1] FP64 profiles (MIXED only); pz: padded z rows per y'.
-template <typename T, int DIM, bool MIXED, int NTH, int MV>
-__global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ args, int nmem) {
+// LC: the line length when it has a compiled plan, else 0.
+template <typename T, int DIM, bool MIXED, int NTH, int LC>
+__device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& XA) {
   constexpr int NW = NTH / 64;  // waves
   using XS = XShape<DIM>;
-  const XArgs& XA = args[member_of(args, nmem)];
   const gptr<const T> in = gmem(static_cast<const T*>(XA.in));
   const gptr<T> out = gmem(static_cast<T*>(XA.out));
   const int nrows = XA.nrows, nkx = XA.nkx, m1 = XA.m1, pz = XA.pz;
@@ -445,11 +571,13 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
   const gptr<const double> mean = gmem(XA.mean);
   const gptr<double> mcol = gmem(XA.mcol);
   cx<T>* P = reinterpret_cast<cx<T>*>(fft_lds);
-  const int L = pl.L;
+  const int L = LC > 0 ? LC : pl.L;
   const int row = blockIdx.x - XA.blk0, tid = threadIdx.x;
   const size_t fstride = (size_t)nrows * nkx * 2;
   const gptr<const T> base = in + (size_t)row * nkx * 2;
-  const int S = fft_batch<T, NTH, MV>(L);
+  // each wave transforms its own pairs (wave, wave + NW, ...), SW at a time
+  constexpr int MVW = xmvw<T, LC>();
+  const int SW = fft_batch<T, 64, MVW>(L);
   const LV<T> PV{0};
   // twiddle table in LDS (behind the data), read by every radix pass
   cx<T>* twl = P + lds_padded<T>((size_t)XS::NP * L);
@@ -466,11 +594,14 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
   // each wave packs whole field pairs, so the field tables are read once per
   // pair (wave-uniform) and the lanes stream one field's kx modes
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  for (int b0 = 0; b0 < XS::NP; b0 += S) {
-    const int nb = min(S, XS::NP - b0);
-    const LV<T> X = PV.at(b0 * L);
-    for (int e = tid; e < nb * L; e += NTH) X[e] = cx<T>{0, 0};
-    __syncthreads();
+  {
+    constexpr int b0 = 0, nb = XS::NP;
+    const LV<T> X = PV;
+    // a wave clears, fills and transforms the pairs it owns, in LDS order,
+    // so only the twiddles need a workgroup barrier before the transforms
+    for (int q = wave; q < nb; q += NW)
+      for (int e = lane; e < L; e += 64) X[q * L + e] = cx<T>{0, 0};
+    pass_sync<true>();
     // the wave's items are (pair q = wave + NW i, block of 64 kx); G items'
     // loads are issued before any of them is packed
     const int nkb = (nkx + 63) >> 6;
@@ -505,7 +636,10 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
       }
     }
     __syncthreads();
-    lds_fft<T, NTH, MV>(X, L, pl, nb, twl, +1);
+    const int own = (nb - wave + NW - 1) / NW;
+    for (int i0 = 0; i0 < own; i0 += SW)
+      fft_any<T, LC, 64, MVW, true, +1>(X.at((wave + NW * i0) * L), NW * L, pl, min(SW, own - i0), twl, lane);
+    __syncthreads();
   }
   // pointwise products; outputs overwrite the first pairs at the same point
   T mrow[16];
@@ -533,10 +667,12 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
   __syncthreads();
   const T inv = T(1.0 / L);
   const gptr<T> obase = out + (size_t)row * nkx * 2;
-  for (int q0 = 0; q0 < XS::NOP; q0 += S) {
-    const int nb = min(S, XS::NOP - q0);
-    const LV<T> Z = PV.at(q0 * L);
-    lds_fft<T, NTH, MV>(Z, L, pl, nb, twl, -1);
+  {
+    constexpr int q0 = 0, nb = XS::NOP;
+    const LV<T> Z = PV;
+    const int own = (nb - wave + NW - 1) / NW;
+    for (int i0 = 0; i0 < own; i0 += SW)
+      fft_any<T, LC, 64, MVW, true, -1>(Z.at((wave + NW * i0) * L), NW * L, pl, min(SW, own - i0), twl, lane);
     for (int q = wave; q < nb; q += NW)
       for (int k = lane; k < nkx; k += 64) {
         cx<T> A, B;
@@ -552,6 +688,20 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
           }
         }
       }
+  }
+}
+
+// (FP64 lines of 768 take the runtime plan: their compiled passes would need
+// registers for fewer waves than the LDS admits)
+template <typename T, int DIM, bool MIXED, int NTH>
+__global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ args, int nmem) {
+  const XArgs& XA = args[member_of(args, nmem)];
+  switch (XA.pl.L) {
+    case 96: xpencil_body<T, DIM, MIXED, NTH, 96>(XA); break;
+    case 192: xpencil_body<T, DIM, MIXED, NTH, 192>(XA); break;
+    case 384: xpencil_body<T, DIM, MIXED, NTH, 384>(XA); break;
+    case 768: xpencil_body<T, DIM, MIXED, NTH, sizeof(T) == 4 ? 768 : 0>(XA); break;
+    default: xpencil_body<T, DIM, MIXED, NTH, 0>(XA); break;
   }
 }
 
@@ -923,7 +1073,6 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
 // workgroups keep 16 waves per CU in flight on the same LDS.  A launch of
 // fewer lines than the CUs can hold at 256 threads (a 2D grid: one line per
 // padded y row) also takes 512 threads, which halves each line's passes.
-constexpr int XMV32 = 16;
 int xpencil_threads(int precision, size_t lds, int lines) {
   (void)precision;
   if (lds == 0) return NT;
@@ -936,27 +1085,27 @@ void launch_xpencil(int dim, int precision, int threads, const XArgs* args, int 
   if (blocks <= 0) return;
   if (precision == 0 && threads == NT) {
     if (dim == 2)
-      hipLaunchKernelGGL((xpencil_kernel<double, 2, false, NT, 16>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+      hipLaunchKernelGGL((xpencil_kernel<double, 2, false, NT>), dim3(blocks), dim3(NT), lds, s, args, nmem);
     else
-      hipLaunchKernelGGL((xpencil_kernel<double, 3, false, NT, 16>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+      hipLaunchKernelGGL((xpencil_kernel<double, 3, false, NT>), dim3(blocks), dim3(NT), lds, s, args, nmem);
   } else if (precision == 0) {
     if (dim == 2)
-      hipLaunchKernelGGL((xpencil_kernel<double, 2, false, 2 * NT, 16>), dim3(blocks), dim3(2 * NT), lds, s, args,
+      hipLaunchKernelGGL((xpencil_kernel<double, 2, false, 2 * NT>), dim3(blocks), dim3(2 * NT), lds, s, args,
                          nmem);
     else
-      hipLaunchKernelGGL((xpencil_kernel<double, 3, false, 2 * NT, 16>), dim3(blocks), dim3(2 * NT), lds, s, args,
+      hipLaunchKernelGGL((xpencil_kernel<double, 3, false, 2 * NT>), dim3(blocks), dim3(2 * NT), lds, s, args,
                          nmem);
   } else if (threads == NT) {
     if (dim == 2)
-      hipLaunchKernelGGL((xpencil_kernel<float, 2, true, NT, XMV32>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+      hipLaunchKernelGGL((xpencil_kernel<float, 2, true, NT>), dim3(blocks), dim3(NT), lds, s, args, nmem);
     else
-      hipLaunchKernelGGL((xpencil_kernel<float, 3, true, NT, XMV32>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+      hipLaunchKernelGGL((xpencil_kernel<float, 3, true, NT>), dim3(blocks), dim3(NT), lds, s, args, nmem);
   } else {
     if (dim == 2)
-      hipLaunchKernelGGL((xpencil_kernel<float, 2, true, 2 * NT, XMV32>), dim3(blocks), dim3(2 * NT), lds, s, args,
+      hipLaunchKernelGGL((xpencil_kernel<float, 2, true, 2 * NT>), dim3(blocks), dim3(2 * NT), lds, s, args,
                          nmem);
     else
-      hipLaunchKernelGGL((xpencil_kernel<float, 3, true, 2 * NT, XMV32>), dim3(blocks), dim3(2 * NT), lds, s, args,
+      hipLaunchKernelGGL((xpencil_kernel<float, 3, true, 2 * NT>), dim3(blocks), dim3(2 * NT), lds, s, args,
                          nmem);
   }
 }
@@ -993,14 +1142,14 @@ size_t diag_rows_lds_bytes(int L) { return (lds_padded<double>(2 * (size_t)L) + 
 
 hipError_t fft_set_attributes() {
   const int lim = 160 * 1024;
-  const void* k160[] = {(const void*)xpencil_kernel<double, 2, false, NT, 16>,
-                        (const void*)xpencil_kernel<double, 3, false, NT, 16>,
-                        (const void*)xpencil_kernel<double, 2, false, 2 * NT, 16>,
-                        (const void*)xpencil_kernel<double, 3, false, 2 * NT, 16>,
-                        (const void*)xpencil_kernel<float, 2, true, NT, XMV32>,
-                        (const void*)xpencil_kernel<float, 3, true, NT, XMV32>,
-                        (const void*)xpencil_kernel<float, 2, true, 2 * NT, XMV32>,
-                        (const void*)xpencil_kernel<float, 3, true, 2 * NT, XMV32>,
+  const void* k160[] = {(const void*)xpencil_kernel<double, 2, false, NT>,
+                        (const void*)xpencil_kernel<double, 3, false, NT>,
+                        (const void*)xpencil_kernel<double, 2, false, 2 * NT>,
+                        (const void*)xpencil_kernel<double, 3, false, 2 * NT>,
+                        (const void*)xpencil_kernel<float, 2, true, NT>,
+                        (const void*)xpencil_kernel<float, 3, true, NT>,
+                        (const void*)xpencil_kernel<float, 2, true, 2 * NT>,
+                        (const void*)xpencil_kernel<float, 3, true, 2 * NT>,
                         (const void*)zfft_kernel<double, ZMV>,
                         (const void*)zfft_kernel<float, ZMV>};
   for (const void* k : k160) {
@@ -1012,6 +1161,8 @@ hipError_t fft_set_attributes() {
 }
 
 size_t xpencil_lds_bytes(int dim, int L, int precision) {
+  // a wave's transform batch must hold one sequence
+  if (L > 64 * cover(XMVW)) return ~(size_t)0;
   if (precision == 0) return dim == 2 ? xpencil_lds<double, 2>(L) : xpencil_lds<double, 3>(L);
   return dim == 2 ? xpencil_lds<float, 2>(L) : xpencil_lds<float, 3>(L);
 }
