@@ -721,10 +721,10 @@ constexpr int ZG = ZFFT_GROUP;
 // the compiler also allocating fewer registers for it).
 constexpr int ZMV = 24;
 
-template <typename T, int MV>
-__global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args, int nmem) {
+// LC: the column length when it has a compiled plan, else 0.
+template <typename T, int MV, int LC>
+__device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA) {
   typedef cx<T> c2;
-  const ZArgs& ZA = args[member_of(args, nmem)];
   const gptr<const T> in = gmem(static_cast<const T*>(ZA.in));
   const gptr<T> out = gmem(static_cast<T*>(ZA.out));
   const int nkx = ZA.nkx, nzs = ZA.nzs, rows_y = ZA.rows, inverse = ZA.inverse;
@@ -735,7 +735,7 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
   const gptr<const double> mean = gmem(ZA.mean);
   const gptr<double> mcol = gmem(ZA.mcol);
   c2* A = reinterpret_cast<c2*>(fft_lds);
-  const int L = pl.L;
+  const int L = LC > 0 ? LC : pl.L;
   // sequences (one per kx column) at stride L + 1: the column-wise loads and
   // stores of neighbouring kx then fall on different LDS banks
   const int SL = L + 1;
@@ -816,9 +816,16 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
   }
   __syncthreads();
   // as many columns per batch as one pass holds in registers
-  const int S = fft_batch<T, NT, MV>(L);
-  for (int b0 = 0; b0 < ng; b0 += S)
-    lds_fft<T, NT, MV>(AV.at(b0 * SL), SL, pl, min(S, ng - b0), twl, inverse ? +1 : -1);
+  // (compiled plans: 16 values per thread, whose registers keep the
+  // occupancy of the runtime plan's 24)
+  constexpr int MVC = LC > 0 ? 16 : MV;
+  const int S = fft_batch<T, NT, MVC>(L);
+  for (int b0 = 0; b0 < ng; b0 += S) {
+    if (inverse)
+      fft_any<T, LC, NT, MVC, false, +1>(AV.at(b0 * SL), SL, pl, min(S, ng - b0), twl, tid);
+    else
+      fft_any<T, LC, NT, MVC, false, -1>(AV.at(b0 * SL), SL, pl, min(S, ng - b0), twl, tid);
+  }
   if (inverse) {
     for (int e = tid; e < L * ng; e += NT) {
       const int z = fdiv(e, mng), g = e - z * ng;
@@ -839,6 +846,16 @@ __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args
       if (mcol && s == 0 && k0 + g == 0)
         mcol[(size_t)f * rows_y + i] = double(v.x) + mean_product(3, f, mean, rows_y, i);
     }
+  }
+}
+
+template <typename T, int MV>
+__global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args, int nmem) {
+  const ZArgs& ZA = args[member_of(args, nmem)];
+  switch (ZA.pl.L) {
+    case 96: zfft_body<T, MV, 96>(ZA); break;
+    case 192: zfft_body<T, MV, 192>(ZA); break;
+    default: zfft_body<T, MV, 0>(ZA); break;
   }
 }
 
@@ -871,8 +888,9 @@ __device__ inline int wave_or(int v) {
   return v;
 }
 
-__global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restrict__ args, int nmem) {
-  const DRowArgs& DA = args[member_of(args, nmem)];
+// LC: the line length when it has a compiled plan, else 0.
+template <int LC>
+__device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowArgs& DA, DiagPart* wpart) {
   const Dims d = DA.d;
   const gptr<const double> in = gmem(DA.in);
   const int zrows = DA.zrows;
@@ -880,8 +898,7 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restric
   const gptr<const double> ydy = gmem(DA.ydy);
   DiagPart* __restrict__ parts = DA.parts;
   c2* A = reinterpret_cast<c2*>(fft_lds);
-  __shared__ DiagPart wpart[NT / 64];
-  const int L = pl.L, nkx = d.nkx;
+  const int L = LC > 0 ? LC : pl.L, nkx = d.nkx;
   const unsigned mkx = fast_div_magic((unsigned)nkx);
   const LV<double> AV{0};
   c2* twl = A + lds_padded<double>(2 * (size_t)L);  // twiddle table behind the data
@@ -910,7 +927,15 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restric
     pack_pair(AV.at(q * L), L, k, Av, Bv);
   }
   __syncthreads();
-  lds_fft(AV, L, pl, 2, twl, +1);
+  // the two pairs: one wave each (lines longer than a wave's batch: the
+  // workgroup's passes)
+  if (L <= 64 * cover(16)) {
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (wave < 2) fft_any<double, LC, 64, 16, true, +1>(AV.at(wave * L), L, pl, 1, twl, tid & 63);
+    __syncthreads();
+  } else {
+    lds_fft(AV, L, pl, 2, twl, +1);
+  }
   const double dx = d.lx / d.nx, dz = d.dim == 3 ? d.lz / d.nz : 1.0;
   const double dyj = ydy[j];
   double mn = 1.0 / 0.0, cf = 0, es = 0, ts = 0;
@@ -967,6 +992,18 @@ __global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restric
       q.big |= o.big;
     }
     parts[row] = q;
+  }
+}
+
+__global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restrict__ args, int nmem) {
+  __shared__ DiagPart wpart[NT / 64];
+  const DRowArgs& DA = args[member_of(args, nmem)];
+  switch (DA.pl.L) {
+    case 64: diag_rows_body<64>(DA, wpart); break;
+    case 128: diag_rows_body<128>(DA, wpart); break;
+    case 256: diag_rows_body<256>(DA, wpart); break;
+    case 512: diag_rows_body<512>(DA, wpart); break;
+    default: diag_rows_body<0>(DA, wpart); break;
   }
 }
 
