@@ -84,23 +84,27 @@ struct V2 {
 // accesses of the z transforms spread over all banks.  FP32 keeps the plain
 // layout: there the extra address arithmetic costs more registers (and
 // occupancy) than the conflicts it removes (measured on the 3D x pencils).
+template <bool PAD>
+__host__ __device__ constexpr size_t lds_span(size_t n) {
+  return PAD ? n + (n >> 4) + 1 : n;
+}
 template <typename T>
 __host__ __device__ constexpr size_t lds_padded(size_t n) {
-  return sizeof(T) == 4 ? n : n + (n >> 4) + 1;
+  return lds_span<sizeof(T) == 8>(n);
 }
 // dynamic LDS of the transform kernels (indexed through the symbol, so
 // every access stays an LDS instruction)
 extern __shared__ double fft_lds[];
-template <typename T>
+template <typename T, bool PAD = (sizeof(T) == 8)>
 struct LV {
   int off;
   __device__ cx<T>& operator[](int i) const {
     cx<T>* b = reinterpret_cast<cx<T>*>(fft_lds);
     const int q = off + i;
-    if constexpr (sizeof(T) == 4)
-      return b[q];
-    else
+    if constexpr (PAD)
       return b[q + (q >> 4)];
+    else
+      return b[q];
   }
   __device__ LV at(int d) const { return LV{off + d}; }
 };
@@ -193,8 +197,8 @@ __device__ __attribute__((always_inline)) inline void pass_sync() {
 // positions.  twl[m] = exp(-2 pi i m / L).  NTH threads (thread tid: the
 // workgroup's, or one wave's lanes for WAVE), at most MV complex values per
 // thread: requires nseq L <= NTH cover(MV).
-template <typename T, int R, int NTH, int MV, bool WAVE>
-__device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl, const FftPlan& pl, int p, int nseq,
+template <typename T, int R, int NTH, int MV, bool WAVE, typename V>
+__device__ __attribute__((always_inline)) inline void pass_ip(V buf, int sl, const FftPlan& pl, int p, int nseq,
                                                               const cx<T>* __restrict__ tw, int sign, int tid) {
   constexpr int NB = MV / R;
   const int L = pl.L, LR = pl.lr[p], Ns = pl.ns[p], stride = pl.ts[p];
@@ -206,7 +210,7 @@ __device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl,
     const int idx = tid + q * NTH;
     if (idx < tot) {
       const int s = fdiv(idx, mLR), j = idx - s * LR;
-      const LV<T> src = buf.at(s * sl + j);
+      const V src = buf.at(s * sl + j);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
     }
@@ -227,7 +231,7 @@ __device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl,
         }
       }
       butterfly<T, R>(v[q], sign);
-      const LV<T> dst = buf.at(s * sl + (j - k) * R + k);
+      const V dst = buf.at(s * sl + (j - k) * R + k);
 #pragma unroll
       for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
     }
@@ -240,8 +244,8 @@ __device__ __attribute__((always_inline)) inline void pass_ip(LV<T> buf, int sl,
 // (tid: its lane).  Inlined at every call: as a called function its register
 // needs add to the caller's (measured: 211-228 VGPRs in the x-pencil and
 // diagnostics kernels).
-template <typename T, int NTH = NT, int MV = maxv<T>(), bool WAVE = false>
-__device__ __attribute__((always_inline)) inline void lds_fft(LV<T> buf, int sl, const FftPlan& pl, int nseq,
+template <typename T, int NTH = NT, int MV = maxv<T>(), bool WAVE = false, typename V = LV<T>>
+__device__ __attribute__((always_inline)) inline void lds_fft(V buf, int sl, const FftPlan& pl, int nseq,
                                                               const cx<T>* __restrict__ tw, int sign,
                                                               int tid = threadIdx.x) {
   for (int p = 0; p < pl.npass; ++p) {
@@ -291,8 +295,8 @@ __host__ __device__ constexpr int cns(int L, int p) {
 __host__ __device__ constexpr bool compiled_length(int L) { return L == 96 || L == 192 || L == 384 || L == 768; }
 
 // pass_ip with the plan of length L fixed (SIGN: +1 inverse, -1 forward)
-template <typename T, int L, int P, int NTH, int MV, bool WAVE, int SIGN>
-__device__ __attribute__((always_inline)) inline void pass_c(LV<T> buf, int sl, int nseq, const cx<T>* __restrict__ tw,
+template <typename T, int L, int P, int NTH, int MV, bool WAVE, int SIGN, typename V>
+__device__ __attribute__((always_inline)) inline void pass_c(V buf, int sl, int nseq, const cx<T>* __restrict__ tw,
                                                              int tid) {
   constexpr int R = cradix(L, P), LR = L / R, Ns = cns(L, P), stride = L / (Ns * R);
   constexpr int NB = MV / R;
@@ -304,7 +308,7 @@ __device__ __attribute__((always_inline)) inline void pass_c(LV<T> buf, int sl, 
     const int idx = tid + q * NTH;
     if (idx < tot) {
       const int s = idx / LR, j = idx - s * LR;
-      const LV<T> src = buf.at(s * sl + j);
+      const V src = buf.at(s * sl + j);
 #pragma unroll
       for (int r = 0; r < R; ++r) v[q][r] = src[r * LR];
     }
@@ -325,7 +329,7 @@ __device__ __attribute__((always_inline)) inline void pass_c(LV<T> buf, int sl, 
         }
       }
       butterfly<T, R>(v[q], SIGN);
-      const LV<T> dst = buf.at(s * sl + (j - k) * R + k);
+      const V dst = buf.at(s * sl + (j - k) * R + k);
 #pragma unroll
       for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
     }
@@ -333,24 +337,24 @@ __device__ __attribute__((always_inline)) inline void pass_c(LV<T> buf, int sl, 
   pass_sync<WAVE>();
 }
 
-template <typename T, int L, int NTH, int MV, bool WAVE, int SIGN, int P = 0>
-__device__ __attribute__((always_inline)) inline void lds_fft_c(LV<T> buf, int sl, int nseq,
+template <typename T, int L, int NTH, int MV, bool WAVE, int SIGN, int P = 0, typename V = LV<T>>
+__device__ __attribute__((always_inline)) inline void lds_fft_c(V buf, int sl, int nseq,
                                                                 const cx<T>* __restrict__ tw, int tid) {
   if constexpr (P < cpass_count(L)) {
     pass_c<T, L, P, NTH, MV, WAVE, SIGN>(buf, sl, nseq, tw, tid);
-    lds_fft_c<T, L, NTH, MV, WAVE, SIGN, P + 1>(buf, sl, nseq, tw, tid);
+    lds_fft_c<T, L, NTH, MV, WAVE, SIGN, P + 1, V>(buf, sl, nseq, tw, tid);
   }
 }
 
 // Transform with the compiled plan of length LC, or with the runtime plan
 // (LC = 0).
-template <typename T, int LC, int NTH, int MV, bool WAVE, int SIGN>
-__device__ __attribute__((always_inline)) inline void fft_any(LV<T> buf, int sl, const FftPlan& pl, int nseq,
+template <typename T, int LC, int NTH, int MV, bool WAVE, int SIGN, typename V>
+__device__ __attribute__((always_inline)) inline void fft_any(V buf, int sl, const FftPlan& pl, int nseq,
                                                               const cx<T>* __restrict__ tw, int tid) {
   if constexpr (LC > 0)
-    lds_fft_c<T, LC, NTH, MV, WAVE, SIGN>(buf, sl, nseq, tw, tid);
+    lds_fft_c<T, LC, NTH, MV, WAVE, SIGN, 0, V>(buf, sl, nseq, tw, tid);
   else
-    lds_fft<T, NTH, MV, WAVE>(buf, sl, pl, nseq, tw, SIGN, tid);
+    lds_fft<T, NTH, MV, WAVE, V>(buf, sl, pl, nseq, tw, SIGN, tid);
 }
 
 // Complex values per lane of the x pencils' wave-local transforms: 16, or 8
@@ -370,8 +374,8 @@ __host__ __device__ inline int fft_batch(int L) {
 
 // Hermitian packing of two real-field spectra A_k, B_k into the complex
 // sequence whose inverse transform is a + i b.
-template <typename T>
-__device__ inline void pack_pair(LV<T> X, int L, int k, cx<T> A, cx<T> B) {
+template <typename T, typename V>
+__device__ inline void pack_pair(V X, int L, int k, cx<T> A, cx<T> B) {
   if (k == 0) {
     X[0] = cx<T>{A.x, B.x};
   } else {
@@ -381,8 +385,8 @@ __device__ inline void pack_pair(LV<T> X, int L, int k, cx<T> A, cx<T> B) {
 }
 
 // Spectra of the two real fields packed in a forward transform Z, at k.
-template <typename T>
-__device__ inline void unpack_pair(LV<T> Z, int L, int k, cx<T>& A, cx<T>& B) {
+template <typename T, typename V>
+__device__ inline void unpack_pair(V Z, int L, int k, cx<T>& A, cx<T>& B) {
   const cx<T> Zk = Z[k];
   if (k == 0) {
     A = cx<T>{Zk.x, 0};
@@ -578,9 +582,12 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   // each wave transforms its own pairs (wave, wave + NW, ...), SW at a time
   constexpr int MVW = xmvw<T, LC>();
   const int SW = fft_batch<T, 64, MVW>(L);
-  const LV<T> PV{0};
+  // padded layout in both precisions (with compiled plans the FP32 conflicts
+  // of the strided pass writes cost more than the address arithmetic)
+  typedef LV<T, true> XV;
+  const XV PV{0};
   // twiddle table in LDS (behind the data), read by every radix pass
-  cx<T>* twl = P + lds_padded<T>((size_t)XS::NP * L);
+  cx<T>* twl = P + lds_span<true>((size_t)XS::NP * L);
   typedef typename V2<T>::type T2;
   {
     const gptr<const T2> tw = gmem(static_cast<const T2*>(XA.tw));
@@ -596,7 +603,7 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   {
     constexpr int b0 = 0, nb = XS::NP;
-    const LV<T> X = PV;
+    const XV X = PV;
     // a wave clears, fills and transforms the pairs it owns, in LDS order,
     // so only the twiddles need a workgroup barrier before the transforms
     for (int q = wave; q < nb; q += NW)
@@ -669,7 +676,7 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   const gptr<T> obase = out + (size_t)row * nkx * 2;
   {
     constexpr int q0 = 0, nb = XS::NOP;
-    const LV<T> Z = PV;
+    const XV Z = PV;
     const int own = (nb - wave + NW - 1) / NW;
     for (int i0 = 0; i0 < own; i0 += SW)
       fft_any<T, LC, 64, MVW, true, -1>(Z.at((wave + NW * i0) * L), NW * L, pl, min(SW, own - i0), twl, lane);
@@ -707,7 +714,7 @@ __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ 
 
 template <typename T, int DIM>
 size_t xpencil_lds(int L) {
-  return (lds_padded<T>((size_t)XShape<DIM>::NP * L) + L) * sizeof(cx<T>);
+  return (lds_span<true>((size_t)XShape<DIM>::NP * L) + L) * sizeof(cx<T>);
 }
 
 // ---------------------------------------------------------------- z columns
