@@ -247,11 +247,17 @@ struct Batch {
   std::vector<Member*> mem;
   int dim = 2, prec = 0;
   hipStream_t s = nullptr;
-  // GS: every product of the state (padded-grid values and derivatives,
-  // mixed: the FP64 mean profiles, D2 and D of the state); GP: projections of
-  // the explicit terms (mixed: and the FP64 mean column); G4 / G5: solves.
-  // Mixed-precision tables hold FP32 and FP64 products in one launch.
-  JobList GS, GP, G4, G5;
+  // Products of the state: GS the padded-grid values and derivatives, GSm
+  // (mixed) their FP64 mean profiles, GSb the FP64 D2 and D of the state.
+  // GP: projections of the explicit terms (mixed: and the FP64 mean column);
+  // G4 / G5: solves.  Mixed-precision tables hold FP32 and FP64 products in
+  // one launch.
+  JobList GS, GSm, GSb, GP, G4, G5;
+  // side streams and fork / join events of the captured steps (branches run
+  // beside the main chain inside the graphs)
+  hipStream_t side[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> evs;
+  bool branch = false;  // captured steps take the side branches (else GSm, GSb are empty: all in GS)
   // per-member argument tables (host copies, then device) and launch sizes
   std::vector<XArgs> hx;
   std::vector<ZArgs> hzi, hzf, hzd;
@@ -271,12 +277,15 @@ struct Batch {
   // one step, and GRAPH_STEPS steps back to back (fewer launches between steps)
   hipGraph_t graph = nullptr, graphn = nullptr;
   hipGraphExec_t gexec = nullptr, gexecn = nullptr;
-  std::vector<JobList*> lists() { return {&GS, &GP, &G4, &G5}; }
+  std::vector<JobList*> lists() { return {&GS, &GSm, &GSb, &GP, &G4, &G5}; }
   ~Batch() {
     for (hipGraphExec_t e : {gexec, gexecn})
       if (e) (void)hipGraphExecDestroy(e);
     for (hipGraph_t g : {graph, graphn})
       if (g) (void)hipGraphDestroy(g);
+    for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+    for (hipStream_t t : side)
+      if (t) (void)hipStreamDestroy(t);
     for (Member* m : mem) delete m;
   }
 };
@@ -895,6 +904,18 @@ pcs_status reset_state(Member* m, uint64_t seed, double amp, hipStream_t s) {
   return PCS_OK;
 }
 
+// Whether the captured steps take side branches: cross-queue edges of a
+// graph cost several microseconds each (measured 5-12 us on the main chain),
+// which the overlap repays only for steps of enough work; here from about a
+// million padded-grid points per step (a 3D or an ensemble step, not one 2D
+// channel of 256 x 257).  PCS_GRAPH_BRANCHES=0 or 1 forces the choice.
+bool use_branches(const Batch* b) {
+  if (const char* e = std::getenv("PCS_GRAPH_BRANCHES")) return std::atoi(e) != 0;
+  double pts = 0;
+  for (const Member* m : b->mem) pts += (double)(m->d.M + 1) * m->d.px * m->d.pz;
+  return pts >= (double)(1 << 20);
+}
+
 // Merges the members' tables of the given stages into one batch table (in
 // that order; the table's type is the first non-FP64 type among them).
 void merge_list(JobList& dst, const std::vector<Member*>& mem, std::initializer_list<JobList Member::*> lps) {
@@ -914,8 +935,19 @@ void merge_list(JobList& dst, const std::vector<Member*>& mem, std::initializer_
 // stage kernels and the launch sizes (workgroups, LDS) of every stage.
 void build_batch(Batch* b) {
   const std::vector<Member*>& mem = b->mem;
-  // the single-column mean-mode products first: their short tiles start early
-  merge_list(b->GS, mem, {&Member::Gbar, &Member::G1, &Member::G1b});
+  // with side branches the mean and D2 / D products get launches of their
+  // own; else one launch holds every product of the state (the single-column
+  // mean products first: their short tiles start early)
+  b->branch = use_branches(b);
+  if (b->branch) {
+    merge_list(b->GS, mem, {&Member::G1});
+    merge_list(b->GSm, mem, {&Member::Gbar});
+    merge_list(b->GSb, mem, {&Member::G1b});
+  } else {
+    merge_list(b->GS, mem, {&Member::Gbar, &Member::G1, &Member::G1b});
+    merge_list(b->GSm, mem, {});
+    merge_list(b->GSb, mem, {});
+  }
   merge_list(b->GP, mem, {&Member::Gm, &Member::G2});
   merge_list(b->G4, mem, {&Member::G4});
   merge_list(b->G5, mem, {&Member::G5});
@@ -1128,7 +1160,11 @@ template <typename Mark>
 void explicit_stage(Batch* b, const Mark& mark) {
   hipStream_t s = b->s;
   const int nm = (int)b->mem.size();
-  for (int r = mark(ST_GEMM_STATE); r > 0; --r) b->GS.run(s);
+  for (int r = mark(ST_GEMM_STATE); r > 0; --r) {
+    b->GSm.run(s);
+    b->GS.run(s);
+    b->GSb.run(s);
+  }
   for (int r = mark(ST_ZFFT_INV); r > 0; --r)
     if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
   for (int r = mark(ST_XPENCIL); r > 0; --r) launch_xpencil(b->dim, b->prec, b->xnt, b->dx, nm, b->bx, b->lx, s);
@@ -1151,6 +1187,51 @@ void enqueue_step(Batch* b, const Mark& mark) {
   for (int r = mark(ST_DIAG_ROWS); r > 0; --r) launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, s);
   for (int r = mark(ST_DIAG_FINAL); r > 0; --r) launch_diag_final(b->ddf, nm, s);
   mark(ST_COUNT);
+}
+
+// The diagnostics of the state that the last finalize wrote, on stream t.
+void enqueue_diagnostics(Batch* b, hipStream_t t) {
+  const int nm = (int)b->mem.size();
+  if (b->dim == 3) launch_zfft(0, b->dzd, nm, b->bzd, b->lzd, t);
+  launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, t);
+  launch_diag_final(b->ddf, nm, t);
+}
+
+// One step for graph capture, with side branches beside the main chain:
+// branch 1 computes the FP64 mean profiles (read by the x pencils) and the
+// FP64 D2 / D products of the state (read by the right-hand sides) while the
+// FP32 padded-grid products, transforms and projections run; branch 2
+// (diag_prev) computes the diagnostics of the previous step's state, which
+// only have to finish before this step overwrites the state (the products
+// of the solves write c, finalize the rest and the diagnostics inputs).
+// ev: four events.  The launches and their order within each chain are those
+// of enqueue_step.
+void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
+  hipStream_t s = b->s, s1 = b->side[0], s2 = b->side[1];
+  const int nm = (int)b->mem.size();
+  (void)hipEventRecord(ev[0], s);  // the previous step's state is complete
+  (void)hipStreamWaitEvent(s1, ev[0], 0);
+  b->GSm.run(s1);
+  (void)hipEventRecord(ev[1], s1);
+  b->GSb.run(s1);
+  (void)hipEventRecord(ev[2], s1);
+  if (diag_prev) {
+    (void)hipStreamWaitEvent(s2, ev[0], 0);
+    enqueue_diagnostics(b, s2);
+    (void)hipEventRecord(ev[3], s2);
+  }
+  b->GS.run(s);
+  if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
+  (void)hipStreamWaitEvent(s, ev[1], 0);
+  launch_xpencil(b->dim, b->prec, b->xnt, b->dx, nm, b->bx, b->lx, s);
+  if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
+  b->GP.run(s);
+  (void)hipStreamWaitEvent(s, ev[2], 0);
+  launch_rhs(b->drhs, nm, b->brhs, s);
+  b->G4.run(s);
+  if (diag_prev) (void)hipStreamWaitEvent(s, ev[3], 0);
+  b->G5.run(s);
+  launch_finalize(b->dfin, nm, b->bfin, s);
 }
 
 // Tile autotuner: times each candidate tile configuration of a product table
@@ -1312,7 +1393,12 @@ void capture_steps(Batch* b, int steps, hipGraph_t* graph, hipGraphExec_t* exec)
     (void)hipGetLastError();
     return;
   }
-  for (int i = 0; i < steps; ++i) enqueue_step(b, NoMark());
+  if (b->side[0] && b->side[1] && (int)b->evs.size() >= 4 * steps) {
+    for (int i = 0; i < steps; ++i) enqueue_step_branched(b, i > 0, &b->evs[4 * i]);
+    enqueue_diagnostics(b, b->s);  // the last step's
+  } else {
+    for (int i = 0; i < steps; ++i) enqueue_step(b, NoMark());
+  }
   hipGraph_t g = nullptr;
   if (hipStreamEndCapture(b->s, &g) != hipSuccess || g == nullptr) {
     (void)hipGetLastError();
@@ -1330,6 +1416,23 @@ void capture_steps(Batch* b, int steps, hipGraph_t* graph, hipGraphExec_t* exec)
 
 pcs_status capture(Batch* b) {
   if (b->s == nullptr) return PCS_OK;  // the legacy default stream cannot be captured
+  // side streams (default priority) and events for the branches; without
+  // them the graphs hold the single chain
+  bool ok = b->branch;
+  for (hipStream_t& t : b->side)
+    if (ok && !t && hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) {
+      t = nullptr;
+      ok = false;
+    }
+  while (ok && (int)b->evs.size() < 4 * GRAPH_STEPS) {
+    hipEvent_t e = nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) {
+      ok = false;
+      break;
+    }
+    b->evs.push_back(e);
+  }
+  if (!ok) (void)hipGetLastError();
   capture_steps(b, 1, &b->graph, &b->gexec);
   if (b->gexec) capture_steps(b, GRAPH_STEPS, &b->graphn, &b->gexecn);
   return PCS_OK;

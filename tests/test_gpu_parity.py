@@ -199,6 +199,34 @@ def test_every_tile_configuration_matches_oracle(P, cfg, monkeypatch):
             assert errs[k][0] <= 2e-4 and errs[k][1] <= 2e-5, (case, k, errs[k])
 
 
+@pytest.mark.parametrize("dims,precision", [((2, 24, 25, 1), 0), ((2, 32, 33, 1), 1), ((3, 16, 17, 16), 1)])
+def test_branched_graphs_match_single_chain(P, dims, precision, monkeypatch):
+    """The captured steps may run the mean and D2 / D products and the
+    previous step's diagnostics on side branches (chosen by step size; forced
+    here through PCS_GRAPH_BRANCHES): the same launches on the same data,
+    so states and every diagnostics record must be bitwise those of the
+    single-chain graphs.  20 steps: two 8-step graphs and four 1-step ones.
+    The tile configuration and product form are forced, since the branched
+    graphs split the state-product table and the autotuner could otherwise
+    pick another shape (another summation order) for the parts."""
+    monkeypatch.setenv("PCS_GEMM_CFG", "4")
+    monkeypatch.setenv("PCS_PRODUCT_FORM", "parity")
+    out = []
+    for br in ("0", "1"):
+        monkeypatch.setenv("PCS_GRAPH_BRANCHES", br)
+        print("case branches=%s %s p%d" % (br, dims, precision), flush=True)
+        sim = P.Sim(P.make_grid(*dims), P.make_params(wi=20.0, dt=1e-3, precision=precision), seed=4, amp=1e-3)
+        sim.step(20)
+        recs, st = sim.diagnostics()
+        assert st == P.PCS_OK and len(recs) == 20
+        out.append((sim.get_state(), recs))
+        sim.close()
+    (a, ra), (b, rb) = out
+    assert np.array_equal(a, b)
+    for x, y in zip(ra, rb):
+        assert x == y, (x, y)
+
+
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
 def test_seeded_run_matches_oracle(P, case):
     name, g, prm, n = case
