@@ -257,7 +257,10 @@ struct Batch {
   // beside the main chain inside the graphs)
   hipStream_t side[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> evs;
-  bool branch = false;  // captured steps take the side branches (else GSm, GSb are empty: all in GS)
+  // side branches of the captured steps: 0 none, 1 the state products and
+  // the diagnostics (GSm, GSb hold their own products; else all are in GS),
+  // 2 the diagnostics only
+  int branch = 0;
   // per-member argument tables (host copies, then device) and launch sizes
   std::vector<XArgs> hx;
   std::vector<ZArgs> hzi, hzf, hzd;
@@ -904,16 +907,21 @@ pcs_status reset_state(Member* m, uint64_t seed, double amp, hipStream_t s) {
   return PCS_OK;
 }
 
-// Whether the captured steps take side branches: cross-queue edges of a
-// graph cost several microseconds each (measured 5-12 us on the main chain),
-// which the overlap repays only for steps of enough work; here from about a
-// million padded-grid points per step (a 3D or an ensemble step, not one 2D
-// channel of 256 x 257).  PCS_GRAPH_BRANCHES=0 or 1 forces the choice.
-bool use_branches(const Batch* b) {
-  if (const char* e = std::getenv("PCS_GRAPH_BRANCHES")) return std::atoi(e) != 0;
+// Side branches of the captured steps (0, 1 or 2, as Batch::branch):
+// cross-queue edges of a graph cost several microseconds each (measured
+// 5-12 us on the main chain), which the overlap repays only for steps of
+// enough work; here both branches from about a million padded-grid points
+// per step (a 3D or an ensemble step), none below (one 2D channel of
+// 256 x 257 measured 9240 steps/s without, 9028 with the diagnostics branch
+// alone, 8488 with both).  PCS_GRAPH_BRANCHES=0, 1 or 2 forces the choice.
+int use_branches(const Batch* b) {
+  if (const char* e = std::getenv("PCS_GRAPH_BRANCHES")) {
+    const int v = std::atoi(e);
+    return v >= 0 && v <= 2 ? v : 0;
+  }
   double pts = 0;
   for (const Member* m : b->mem) pts += (double)(m->d.M + 1) * m->d.px * m->d.pz;
-  return pts >= (double)(1 << 20);
+  return pts >= (double)(1 << 20) ? 1 : 0;
 }
 
 // Merges the members' tables of the given stages into one batch table (in
@@ -939,7 +947,7 @@ void build_batch(Batch* b) {
   // own; else one launch holds every product of the state (the single-column
   // mean products first: their short tiles start early)
   b->branch = use_branches(b);
-  if (b->branch) {
+  if (b->branch == 1) {
     merge_list(b->GS, mem, {&Member::G1});
     merge_list(b->GSm, mem, {&Member::Gbar});
     merge_list(b->GSb, mem, {&Member::G1b});
@@ -1209,12 +1217,15 @@ void enqueue_diagnostics(Batch* b, hipStream_t t) {
 void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
   hipStream_t s = b->s, s1 = b->side[0], s2 = b->side[1];
   const int nm = (int)b->mem.size();
+  const bool prod = b->branch == 1;
   (void)hipEventRecord(ev[0], s);  // the previous step's state is complete
-  (void)hipStreamWaitEvent(s1, ev[0], 0);
-  b->GSm.run(s1);
-  (void)hipEventRecord(ev[1], s1);
-  b->GSb.run(s1);
-  (void)hipEventRecord(ev[2], s1);
+  if (prod) {
+    (void)hipStreamWaitEvent(s1, ev[0], 0);
+    b->GSm.run(s1);
+    (void)hipEventRecord(ev[1], s1);
+    b->GSb.run(s1);
+    (void)hipEventRecord(ev[2], s1);
+  }
   if (diag_prev) {
     (void)hipStreamWaitEvent(s2, ev[0], 0);
     enqueue_diagnostics(b, s2);
@@ -1222,11 +1233,11 @@ void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
   }
   b->GS.run(s);
   if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
-  (void)hipStreamWaitEvent(s, ev[1], 0);
+  if (prod) (void)hipStreamWaitEvent(s, ev[1], 0);
   launch_xpencil(b->dim, b->prec, b->xnt, b->dx, nm, b->bx, b->lx, s);
   if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
   b->GP.run(s);
-  (void)hipStreamWaitEvent(s, ev[2], 0);
+  if (prod) (void)hipStreamWaitEvent(s, ev[2], 0);
   launch_rhs(b->drhs, nm, b->brhs, s);
   b->G4.run(s);
   if (diag_prev) (void)hipStreamWaitEvent(s, ev[3], 0);
@@ -1418,7 +1429,7 @@ pcs_status capture(Batch* b) {
   if (b->s == nullptr) return PCS_OK;  // the legacy default stream cannot be captured
   // side streams (default priority) and events for the branches; without
   // them the graphs hold the single chain
-  bool ok = b->branch;
+  bool ok = b->branch != 0;
   for (hipStream_t& t : b->side)
     if (ok && !t && hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) {
       t = nullptr;

@@ -295,7 +295,7 @@ size_t xpencil_lds_bytes(int dim, int L, int precision);
 int zfft_blocks(int nkx, int rows, int nfields);
 size_t zfft_lds_bytes(int L, int precision);
 size_t diag_rows_lds_bytes(int L);
-constexpr int ELEM_THREADS = 256;
+constexpr int ELEM_THREADS = 64;
 constexpr int ZFFT_GROUP = 32;  // kx columns per workgroup of the z transforms
 // Raises the dynamic-LDS limit of the transform kernels (call once, outside capture).
 hipError_t fft_set_attributes();

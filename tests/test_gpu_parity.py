@@ -202,8 +202,9 @@ def test_every_tile_configuration_matches_oracle(P, cfg, monkeypatch):
 @pytest.mark.parametrize("dims,precision", [((2, 24, 25, 1), 0), ((2, 32, 33, 1), 1), ((3, 16, 17, 16), 1)])
 def test_branched_graphs_match_single_chain(P, dims, precision, monkeypatch):
     """The captured steps may run the mean and D2 / D products and the
-    previous step's diagnostics on side branches (chosen by step size; forced
-    here through PCS_GRAPH_BRANCHES): the same launches on the same data,
+    previous step's diagnostics on side branches, or the diagnostics only
+    (chosen by step size; forced here through PCS_GRAPH_BRANCHES = 1, 2
+    against 0): the same launches on the same data,
     so states and every diagnostics record must be bitwise those of the
     single-chain graphs.  20 steps: two 8-step graphs and four 1-step ones.
     The tile configuration and product form are forced, since the branched
@@ -212,7 +213,7 @@ def test_branched_graphs_match_single_chain(P, dims, precision, monkeypatch):
     monkeypatch.setenv("PCS_GEMM_CFG", "4")
     monkeypatch.setenv("PCS_PRODUCT_FORM", "parity")
     out = []
-    for br in ("0", "1"):
+    for br in ("0", "1", "2"):
         monkeypatch.setenv("PCS_GRAPH_BRANCHES", br)
         print("case branches=%s %s p%d" % (br, dims, precision), flush=True)
         sim = P.Sim(P.make_grid(*dims), P.make_params(wi=20.0, dt=1e-3, precision=precision), seed=4, amp=1e-3)
@@ -221,10 +222,11 @@ def test_branched_graphs_match_single_chain(P, dims, precision, monkeypatch):
         assert st == P.PCS_OK and len(recs) == 20
         out.append((sim.get_state(), recs))
         sim.close()
-    (a, ra), (b, rb) = out
-    assert np.array_equal(a, b)
-    for x, y in zip(ra, rb):
-        assert x == y, (x, y)
+    a, ra = out[0]
+    for b, rb in out[1:]:
+        assert np.array_equal(a, b)
+        for x, y in zip(ra, rb):
+            assert x == y, (x, y)
 
 
 @pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
