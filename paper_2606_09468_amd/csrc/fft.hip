@@ -1034,6 +1034,12 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
   const int zrows = FA.zrows, cap = FA.cap;
   const gptr<const double> w = gmem(FA.w);
   DevScalars* __restrict__ sc = FA.sc;
+  // the previous record's scalars, loaded with the partials rather than
+  // after the reduction
+  const gptr<DevScalars> sg = gmem(sc);
+  const long long step0 = sg->step;
+  const double t0 = sg->t, pi0 = sg->pi;
+  const int blowup0 = sg->blowup;
   __shared__ FinPart fp[NT / 64];
   const int tid = threadIdx.x;
   const int n1 = d.N + 1, nrows = n1 * zrows, mid = d.N / 2;
@@ -1086,15 +1092,15 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
     t.m0 += o.m0;
     t.b |= o.b;
   }
-  const long long step = sc->step + 1;
-  const double tt = sc->t + p.dt;
+  const long long step = step0 + 1;
+  const double tt = t0 + p.dt;
   DiagRec r;
   r.step = step;
   r.t = tt;
   r.min_trc = t.mn;
   r.mid_min_trc = t.mmn;
   r.cfl = p.dt * t.cf;
-  r.dpdx = sc->pi;
+  r.dpdx = pi0;
   r.energy = t.es;
   r.mean_trc = t.ts;
   r.n_lt3 = t.n3;
@@ -1104,9 +1110,9 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
   r.blowup = t.b ? 1 : 0;
   r.reserved = 0;
   FA.ring[(step - 1) % cap] = r;
-  sc->step = step;
-  sc->t = tt;
-  sc->blowup |= r.blowup;
+  sg->step = step;
+  sg->t = tt;
+  sg->blowup = blowup0 | r.blowup;
 }
 
 }  // namespace
