@@ -146,10 +146,20 @@ constexpr int lds_plain() {
   return LCfg<CFG>::NBUF * LCfg<CFG>::BM * (LCfg<CFG>::KC + 2) +
          LCfg<CFG>::NBUF * LCfg<CFG>::KC * (LCfg<CFG>::BN + 16);
 }
-template <int CFG>
+template <int CFG, int KDIV = 1>
 constexpr int lds_par() {
-  return LCfg<CFG>::NBUF * LCfg<CFG>::BM * (LCfg<CFG>::PKC + 2) +
-         LCfg<CFG>::NBUF * 2 * LCfg<CFG>::PKC * (LCfg<CFG>::BN + 4);
+  return LCfg<CFG>::NBUF * LCfg<CFG>::BM * (LCfg<CFG>::PKC / KDIV + 2) +
+         LCfg<CFG>::NBUF * 2 * (LCfg<CFG>::PKC / KDIV) * (LCfg<CFG>::BN + 4);
+}
+// FP64 parity products inside a table of FP32 products take chunks of half
+// the depth (staged by fewer threads where a panel falls below 512
+// elements): their panels then take the bytes of the FP32 panels, and the
+// table's LDS stays that of its FP32 products.
+template <int CFG>
+constexpr bool ddd_half() {
+  constexpr int K = LCfg<CFG>::PKC / 2;
+  return K % 4 == 0 && 512 % (K * LCfg<CFG>::BM) * (K * LCfg<CFG>::BM < 512) == 0 &&
+         512 % (K * LCfg<CFG>::BN) * (K * LCfg<CFG>::BN < 512) == 0;
 }
 template <int CFG>
 constexpr int lds_doubles() {
@@ -546,20 +556,23 @@ __device__ inline void store_par(const GemmJob* __restrict__ jp, const V4 (&accE
 // the even part (Ae rows, Be panel), waves 2, 3 the odd part (Ao rows, Bo
 // panel); at the end the odd waves hand their blocks to the even waves
 // through LDS, which write both mirrored output rows.
-template <typename T, typename TB, typename TC, int CFG>
+template <typename T, typename TB, typename TC, int CFG, int KDIV = 1>
 __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob* __restrict__ jp, int t,
                                                                    double* smem) {
-  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::PKC, NBUF = LCfg<CFG>::NBUF;
+  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::PKC / KDIV, NBUF = LCfg<CFG>::NBUF;
   constexpr int HM = BM / 2, WN = BN / 2, RB = HM / 16, CB = WN / 16;
   constexpr int PA = KC + 2, PB = BN + 4;
-  constexpr int NA = KC * BM / 512, NB = KC * BN / 512;
+  // element pairs per thread and chunk; a panel smaller than 512 elements
+  // (half-depth chunks) is staged by the first threads only
+  constexpr bool AF = KC * BM >= 512, BF = KC * BN >= 512;
+  constexpr int NA = AF ? KC * BM / 512 : 1, NB = BF ? KC * BN / 512 : 1;
   constexpr int RA = 512 / KC, SB = 512 / BN;
-  static_assert(NA >= 1 && NB >= 1 && KC % 4 == 0, "tile shape");
+  static_assert(KC % 4 == 0 && (AF || 512 % (KC * BM) == 0) && (BF || 512 % (KC * BN) == 0), "tile shape");
   static_assert(lds_doubles<CFG>() * 8 <= 64 * 1024, "LDS");
   // odd -> even hand-over in rounds of XR row blocks (whatever fits the
   // parity panels' LDS)
-  constexpr int XR = (2 * RB * CB * 4 * 64 <= lds_par<CFG>()) ? RB : 1;
-  static_assert(2 * XR * CB * 4 * 64 <= lds_par<CFG>() && RB % XR == 0, "exchange area");
+  constexpr int XR = (2 * RB * CB * 4 * 64 <= lds_par<CFG, KDIV>()) ? RB : 1;
+  static_assert(2 * XR * CB * 4 * 64 <= lds_par<CFG, KDIV>() && RB % XR == 0, "exchange area");
   typedef typename Vec<T>::v4 V4;
   typedef typename Vec<T>::v2 AP;
   typedef typename Vec<TB>::v2 BP;
@@ -578,6 +591,7 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
 
   const int kp = 2 * (tid % (KC / 2)), ra = tid / (KC / 2);
   const int cb2 = 2 * (tid % (BN / 2)), kb = tid / (BN / 2);
+  const bool aon = AF || ra < BM, bon = BF || kb < KC;  // this thread stages A / B pairs
   const int gc = col0 + cb2;
   const bool bpair = (((ldb | N) & 1) == 0) && ((reinterpret_cast<uintptr_t>(B) & (2 * sizeof(TB) - 1)) == 0);
   const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
@@ -605,13 +619,13 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
     for (int u = 0; u < NA; ++u) {
       const int r = ra + u * RA, kk = k0 + kp;
       const gptr<const T> src = (r < HM ? A : A2) + (size_t)(row0 + (r < HM ? r : r - HM)) * lda + kk;
-      ar[u] = kk < K ? *reinterpret_cast<gptr<const AP>>(src) : AP{0, 0};
+      ar[u] = (aon && kk < K) ? *reinterpret_cast<gptr<const AP>>(src) : AP{0, 0};
     }
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
       const int kk = k0 + kb + u * SB;
       be[u][0] = be[u][1] = bo[u][0] = bo[u][1] = TB(0);
-      if (kk < K) {
+      if (bon && kk < K) {
         if (fold) {
           const int km = KF - 1 - kk;
           TB x[2];
@@ -636,9 +650,11 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
   };
   auto store = [&](int buf) {
 #pragma unroll
-    for (int u = 0; u < NA; ++u) *reinterpret_cast<AP*>(&As[buf][(ra + u * RA) * PA + kp]) = ar[u];
+    for (int u = 0; u < NA; ++u)
+      if (aon) *reinterpret_cast<AP*>(&As[buf][(ra + u * RA) * PA + kp]) = ar[u];
 #pragma unroll
     for (int u = 0; u < NB; ++u) {
+      if (!bon) continue;
       AP v;
       v[0] = c0ok ? T(be[u][0]) : T(0);
       v[1] = c1ok ? T(be[u][1]) : T(0);
@@ -732,7 +748,7 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict
   const bool ddd = dual_type<T, TB, TC>() && jp->type == GEMM_DDD;
   if (jp->kind != PAR_NONE) {
     if (ddd)
-      lds_par_body<double, double, double, CFG>(jp, t, smem);
+      lds_par_body<double, double, double, CFG, ddd_half<CFG>() ? 2 : 1>(jp, t, smem);
     else
       lds_par_body<T, TB, TC, CFG>(jp, t, smem);
   } else if (ddd) {
@@ -776,9 +792,10 @@ bool gemm_cfg_parity(int cfg) { return cfg >= 4 && cfg < GEMM_NCFG; }
 
 namespace {
 template <int CFG>
-size_t lds_form(bool parity, size_t esize) {
+size_t lds_form(bool parity, size_t esize, bool half) {
   // + 8: the B panel starts on a double boundary
-  return esize * (size_t)(parity ? lds_par<CFG>() : lds_plain<CFG>()) + 8;
+  const int e = parity ? (half && ddd_half<CFG>() ? lds_par<CFG, 2>() : lds_par<CFG>()) : lds_plain<CFG>();
+  return esize * (size_t)e + 8;
 }
 }  // namespace
 
@@ -789,18 +806,19 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
   for (int j = 0; j < njobs; ++j) {
     const bool par = jobs[j].kind != PAR_NONE;
     const size_t es = jobs[j].type == GEMM_DDD ? 8 : own;
+    const bool half = t != GEMM_DDD && jobs[j].type == GEMM_DDD;  // FP64 products of a mixed table
     size_t x = 0;
     switch (cfg) {
-      case 4: x = lds_form<4>(par, es); break;
-      case 5: x = lds_form<5>(par, es); break;
-      case 6: x = lds_form<6>(par, es); break;
-      case 7: x = lds_form<7>(par, es); break;
-      case 8: x = lds_form<8>(par, es); break;
-      case 9: x = lds_form<9>(par, es); break;
-      case 10: x = lds_form<10>(par, es); break;
-      case 11: x = lds_form<11>(par, es); break;
-      case 12: x = lds_form<12>(par, es); break;
-      case 13: x = lds_form<13>(par, es); break;
+      case 4: x = lds_form<4>(par, es, half); break;
+      case 5: x = lds_form<5>(par, es, half); break;
+      case 6: x = lds_form<6>(par, es, half); break;
+      case 7: x = lds_form<7>(par, es, half); break;
+      case 8: x = lds_form<8>(par, es, half); break;
+      case 9: x = lds_form<9>(par, es, half); break;
+      case 10: x = lds_form<10>(par, es, half); break;
+      case 11: x = lds_form<11>(par, es, half); break;
+      case 12: x = lds_form<12>(par, es, half); break;
+      case 13: x = lds_form<13>(par, es, half); break;
       default: break;
     }
     b = x > b ? x : b;
