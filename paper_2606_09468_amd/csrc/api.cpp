@@ -55,6 +55,7 @@ struct JobList {
   GemmType type = GEMM_DDD;
   int tiles = 0, cfg = 0, form = 0;
   size_t lds = 0;
+  // a plain product in both forms; addp then makes the form-1 copy a parity product
   void add(const void* A, const void* B, int ldb, void* C, int ldc, int m, int n, int k, int flags = 0,
            int scale = SCALE_NONE, const EigScale* es = nullptr, void* C2 = nullptr, int scale2 = SCALE_NONE) {
     GemmJob j{};
@@ -143,7 +144,9 @@ struct JobList {
     }
     return k;
   }
-  void run(hipStream_t s) const { gemm_run(type, dev, tmap, tiles, cfg, lds, s); }
+  // every job of forms[1] is a parity product and every job of forms[0] a
+  // plain one (add is only called through addp)
+  void run(hipStream_t s) const { gemm_run(type, dev, tmap, tiles, cfg, form == 1, lds, s); }
 };
 
 // Row-major (rows x cols) operator -> the padded row-major copy (gemm_rows

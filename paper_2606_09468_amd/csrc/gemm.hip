@@ -737,53 +737,66 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
   store_par<T, TC, RB, CB>(jp, acc, accO, row0, col0 + wc, lk, l16);
 }
 
-template <typename T, typename TB, typename TC, int CFG>
+// PAR: the table holds parity products only (else plain ones only): one
+// body per kernel, so neither pays for the other's registers.
+template <typename T, typename TB, typename TC, int CFG, bool PAR>
 __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap,
                                                        int total) {
-  constexpr int BM = LCfg<CFG>::BM, BN = LCfg<CFG>::BN, KC = LCfg<CFG>::KC, NBUF = LCfg<CFG>::NBUF;
   // gemm_lds_bytes of the table: the panels of its largest form and precision
   extern __shared__ __attribute__((aligned(16))) double smem[];
   const int t = xcd_tile(blockIdx.x, total);
   const GemmJob* jp = tile_job(jobs, tmap, t);
   const bool ddd = dual_type<T, TB, TC>() && jp->type == GEMM_DDD;
-  if (jp->kind != PAR_NONE) {
+  if constexpr (PAR) {
     if (ddd)
       lds_par_body<double, double, double, CFG, ddd_half<CFG>() ? 2 : 1>(jp, t, smem);
     else
       lds_par_body<T, TB, TC, CFG>(jp, t, smem);
-  } else if (ddd) {
-    lds_body<double, double, double, CFG>(jp, t, smem);
   } else {
-    lds_body<T, TB, TC, CFG>(jp, t, smem);
+    if (ddd)
+      lds_body<double, double, double, CFG>(jp, t, smem);
+    else
+      lds_body<T, TB, TC, CFG>(jp, t, smem);
   }
 }
 
 namespace {
 
 template <typename T, typename TB, typename TC>
-void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, size_t lds, hipStream_t s) {
-#define PCS_GEMM_LAUNCH(KERNEL, C)                                                                                  \
-  case C:                                                                                                           \
-    hipLaunchKernelGGL((KERNEL<T, TB, TC, C>), dim3(total), dim3(256), C < 4 ? 0 : lds, s, dev_jobs, tmap, total); \
+void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, bool parity, size_t lds,
+                hipStream_t s) {
+#define PCS_GEMM_REG(C)                                                                                   \
+  case C:                                                                                                 \
+    hipLaunchKernelGGL((gemm_reg_kernel<T, TB, TC, C>), dim3(total), dim3(256), 0, s, dev_jobs, tmap, total); \
+    break;
+#define PCS_GEMM_LDS(C)                                                                                       \
+  case C:                                                                                                     \
+    if (parity)                                                                                               \
+      hipLaunchKernelGGL((gemm_lds_kernel<T, TB, TC, C, true>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, \
+                         total);                                                                              \
+    else                                                                                                      \
+      hipLaunchKernelGGL((gemm_lds_kernel<T, TB, TC, C, false>), dim3(total), dim3(256), lds, s, dev_jobs,     \
+                         tmap, total);                                                                        \
     break;
   switch (cfg) {
-    PCS_GEMM_LAUNCH(gemm_reg_kernel, 0)
-    PCS_GEMM_LAUNCH(gemm_reg_kernel, 1)
-    PCS_GEMM_LAUNCH(gemm_reg_kernel, 2)
-    PCS_GEMM_LAUNCH(gemm_reg_kernel, 3)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 4)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 5)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 6)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 7)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 8)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 9)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 10)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 11)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 12)
-    PCS_GEMM_LAUNCH(gemm_lds_kernel, 13)
+    PCS_GEMM_REG(0)
+    PCS_GEMM_REG(1)
+    PCS_GEMM_REG(2)
+    PCS_GEMM_REG(3)
+    PCS_GEMM_LDS(4)
+    PCS_GEMM_LDS(5)
+    PCS_GEMM_LDS(6)
+    PCS_GEMM_LDS(7)
+    PCS_GEMM_LDS(8)
+    PCS_GEMM_LDS(9)
+    PCS_GEMM_LDS(10)
+    PCS_GEMM_LDS(11)
+    PCS_GEMM_LDS(12)
+    PCS_GEMM_LDS(13)
     default: break;
   }
-#undef PCS_GEMM_LAUNCH
+#undef PCS_GEMM_REG
+#undef PCS_GEMM_LDS
 }
 
 }  // namespace
@@ -828,15 +841,15 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
 
 hipError_t gemm_set_attributes() { return hipSuccess; }
 
-void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_tiles, int cfg, size_t lds,
-              hipStream_t s) {
-  if (total_tiles <= 0 || cfg < 0 || cfg >= GEMM_NCFG) return;
+void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_tiles, int cfg, bool parity,
+              size_t lds, hipStream_t s) {
+  if (total_tiles <= 0 || cfg < 0 || cfg >= GEMM_NCFG || (parity && !gemm_cfg_parity(cfg))) return;
   switch (t) {
-    case GEMM_DDD: launch_cfg<double, double, double>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
-    case GEMM_FDF: launch_cfg<float, double, float>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
-    case GEMM_FFD: launch_cfg<float, float, double>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
-    case GEMM_DDF: launch_cfg<double, double, float>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
-    case GEMM_DFD: launch_cfg<double, float, double>(dev_jobs, tmap, total_tiles, cfg, lds, s); break;
+    case GEMM_DDD: launch_cfg<double, double, double>(dev_jobs, tmap, total_tiles, cfg, parity, lds, s); break;
+    case GEMM_FDF: launch_cfg<float, double, float>(dev_jobs, tmap, total_tiles, cfg, parity, lds, s); break;
+    case GEMM_FFD: launch_cfg<float, float, double>(dev_jobs, tmap, total_tiles, cfg, parity, lds, s); break;
+    case GEMM_DDF: launch_cfg<double, double, float>(dev_jobs, tmap, total_tiles, cfg, parity, lds, s); break;
+    case GEMM_DFD: launch_cfg<double, float, double>(dev_jobs, tmap, total_tiles, cfg, parity, lds, s); break;
     default: break;
   }
 }

@@ -108,10 +108,11 @@ bool gemm_cfg_parity(int cfg);
 // workgroups resident per CU.
 size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg);
 // t: the table's precision combination; its jobs are of type t or GEMM_DDD;
-// tmap: job index of every logical tile; lds: gemm_lds_bytes of the same
-// table and configuration.
-void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_tiles, int cfg, size_t lds,
-              hipStream_t s);
+// tmap: job index of every logical tile; parity: every job is a parity
+// product (else none is; a table holds one form); lds: gemm_lds_bytes of the
+// same table and configuration.
+void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_tiles, int cfg, bool parity,
+              size_t lds, hipStream_t s);
 
 hipError_t gemm_set_attributes();
 
