@@ -895,6 +895,10 @@ __device__ inline int wave_or(int v) {
   return v;
 }
 
+// Two waves per line: one transform pair each (so no wave idles during the
+// transforms), and small workgroups pack eight lines per CU.
+constexpr int DNT = 128;
+
 // LC: the line length when it has a compiled plan, else 0.
 template <int LC>
 __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowArgs& DA, DiagPart* wpart) {
@@ -912,7 +916,7 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
   {
     typedef V2<double>::type D2;
     const gptr<const D2> tw = gmem(reinterpret_cast<const D2*>(DA.tw));
-    for (int e = threadIdx.x; e < L; e += NT) {
+    for (int e = threadIdx.x; e < L; e += DNT) {
       const D2 t = tw[e];
       twl[e] = c2{t[0], t[1]};
     }
@@ -922,10 +926,10 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
   const int j = row / zrows;
   const size_t fstride = (size_t)nrows * nkx * 2;
   const gptr<const double> base = in + (size_t)row * nkx * 2;
-  for (int e = tid; e < 2 * L; e += NT) AV[e] = c2{0, 0};
+  for (int e = tid; e < 2 * L; e += DNT) AV[e] = c2{0, 0};
   __syncthreads();
   const int nf = d.dim == 2 ? 3 : 4;
-  for (int e = tid; e < 2 * nkx; e += NT) {
+  for (int e = tid; e < 2 * nkx; e += DNT) {
     const int q = fdiv(e, mkx), k = e - q * nkx;
     const int fa = 2 * q, fb = fa + 1;
     c2 Av{0, 0}, Bv{0, 0};
@@ -941,14 +945,14 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
     if (wave < 2) fft_any<double, LC, 64, 16, true, +1>(AV.at(wave * L), L, pl, 1, twl, tid & 63);
     __syncthreads();
   } else {
-    lds_fft(AV, L, pl, 2, twl, +1);
+    lds_fft<double, DNT, 16>(AV, L, pl, 2, twl, +1);
   }
   const double dx = d.lx / d.nx, dz = d.dim == 3 ? d.lz / d.nz : 1.0;
   const double dyj = ydy[j];
   double mn = 1.0 / 0.0, cf = 0, es = 0, ts = 0;
   unsigned long long n3 = 0, n0 = 0;
   int flag = 0, big = 0;
-  for (int n = tid; n < L; n += NT) {
+  for (int n = tid; n < L; n += DNT) {
     const c2 z0 = AV[n], z1 = AV[L + n];
     const double trc = z0.x + (d.dim == 2 ? 1.0 : 0.0);
     const double u = z0.y, v = z1.x, w = d.dim == 3 ? z1.y : 0.0;
@@ -987,7 +991,7 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
   __syncthreads();
   if (tid == 0) {
     DiagPart q = wpart[0];
-    for (int w2 = 1; w2 < NT / 64; ++w2) {
+    for (int w2 = 1; w2 < DNT / 64; ++w2) {
       const DiagPart& o = wpart[w2];
       q.min_trc = fmin(q.min_trc, o.min_trc);
       q.cfl = fmax(q.cfl, o.cfl);
@@ -1002,8 +1006,8 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
   }
 }
 
-__global__ __launch_bounds__(NT) void diag_rows_kernel(const DRowArgs* __restrict__ args, int nmem) {
-  __shared__ DiagPart wpart[NT / 64];
+__global__ __launch_bounds__(DNT) void diag_rows_kernel(const DRowArgs* __restrict__ args, int nmem) {
+  __shared__ DiagPart wpart[DNT / 64];
   const DRowArgs& DA = args[member_of(args, nmem)];
   switch (DA.pl.L) {
     case 64: diag_rows_body<64>(DA, wpart); break;
@@ -1179,7 +1183,7 @@ size_t zfft_lds_bytes(int L, int precision) {
 
 void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
   if (blocks <= 0) return;
-  hipLaunchKernelGGL(diag_rows_kernel, dim3(blocks), dim3(NT), lds, s, args, nmem);
+  hipLaunchKernelGGL(diag_rows_kernel, dim3(blocks), dim3(DNT), lds, s, args, nmem);
 }
 
 void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s) {
