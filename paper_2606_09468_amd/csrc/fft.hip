@@ -290,9 +290,6 @@ __host__ __device__ constexpr int cns(int L, int p) {
   for (int i = 0; i < p; ++i) ns *= cradix(L, i);
   return ns;
 }
-// lengths with compiled plans (those of the x and z transforms of the
-// workloads: 3/2 of 64, 128, 256, 512)
-__host__ __device__ constexpr bool compiled_length(int L) { return L == 96 || L == 192 || L == 384 || L == 768; }
 
 // pass_ip with the plan of length L fixed (SIGN: +1 inverse, -1 forward)
 template <typename T, int L, int P, int NTH, int MV, bool WAVE, int SIGN, typename V>
@@ -860,7 +857,9 @@ template <typename T, int MV>
 __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args, int nmem) {
   const ZArgs& ZA = args[member_of(args, nmem)];
   switch (ZA.pl.L) {
+    case 64: zfft_body<T, MV, 64>(ZA); break;  // the diagnostics' base-grid z transforms
     case 96: zfft_body<T, MV, 96>(ZA); break;
+    case 128: zfft_body<T, MV, 128>(ZA); break;
     case 192: zfft_body<T, MV, 192>(ZA); break;
     default: zfft_body<T, MV, 0>(ZA); break;
   }
