@@ -4,11 +4,14 @@
 // Fourier in x and z with full 3/2-rule dealiasing (paper, Section 2): every
 // retained mode is placed at its own frequency in a transform of 3/2 the base
 // size, products are formed pointwise, and the forward transform is
-// truncated back to the retained modes.  Transforms are mixed-radix (4, 2, 3)
-// Stockham FFTs done in place in LDS: each pass reads its butterfly inputs
+// truncated back to the retained modes.  Transforms are mixed-radix (8, 4, 2,
+// 3) Stockham FFTs done in place in LDS: each pass reads its butterfly inputs
 // into registers, synchronises, and writes the outputs to their sorted
-// positions, so one buffer suffices.  Two real fields share one complex
-// transform (z = a + i b).
+// positions, so one buffer suffices.  The lengths of the workloads run plans
+// fixed at compile time (constant strides and twiddle indices); where the
+// sequences of a pass belong to one wave (x pencils, row diagnostics) the
+// synchronisation is that of the wave alone.  Two real fields share one
+// complex transform (z = a + i b).
 //
 // x pencil: one workgroup per padded (y', z') line.  It reads the needed
 // spectral fields of that line (kx modes), generates the d/dx variants by

@@ -28,11 +28,15 @@
 // rows are padded so that the fragment reads of one MFMA hit distinct banks.
 //
 // Both deal workgroups to the eight XCDs in contiguous ranges of tiles, so
-// the row tiles of one column panel share an L2, and both share the
-// epilogue, which can scale each output element by the inverse Helmholtz
-// symbol of its eigen index (row) and Fourier mode (column) and write a
-// second, differently scaled copy.  All sums run in a fixed order, so results
-// are bitwise reproducible.
+// the row tiles of one column panel share an L2, and a workgroup finds its
+// product through a per-tile job map; both share the epilogue, which can
+// scale each output element by the inverse Helmholtz symbol of its eigen
+// index (row) and Fourier mode (column) and write a second, differently
+// scaled copy.  The LDS-tiled kernel is instantiated once per product form
+// (plain or parity) and takes the LDS its table needs (dynamic); the FP64
+// products of a mixed-precision table stage half-depth parity chunks so that
+// they fit the FP32 panels.  All sums run in a fixed order, so results are
+// bitwise reproducible.
 #include "kernels.hpp"
 
 #include <type_traits>
