@@ -159,11 +159,14 @@ constexpr int lds_par() {
 // the depth (staged by fewer threads where a panel falls below 512
 // elements): their panels then take the bytes of the FP32 panels, and the
 // table's LDS stays that of its FP32 products.
+// a panel of p elements is staged by 256 threads in element pairs: whole
+// pairs for every thread (p >= 512, a multiple of 512) or one pair for the
+// first p / 2 threads (p < 512, a divisor of 512)
+constexpr bool stageable(int p) { return p >= 512 ? p % 512 == 0 : 512 % p == 0; }
 template <int CFG>
 constexpr bool ddd_half() {
   constexpr int K = LCfg<CFG>::PKC / 2;
-  return K % 4 == 0 && 512 % (K * LCfg<CFG>::BM) * (K * LCfg<CFG>::BM < 512) == 0 &&
-         512 % (K * LCfg<CFG>::BN) * (K * LCfg<CFG>::BN < 512) == 0;
+  return K % 4 == 0 && stageable(K * LCfg<CFG>::BM) && stageable(K * LCfg<CFG>::BN);
 }
 template <int CFG>
 constexpr int lds_doubles() {
@@ -571,7 +574,7 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
   constexpr bool AF = KC * BM >= 512, BF = KC * BN >= 512;
   constexpr int NA = AF ? KC * BM / 512 : 1, NB = BF ? KC * BN / 512 : 1;
   constexpr int RA = 512 / KC, SB = 512 / BN;
-  static_assert(KC % 4 == 0 && (AF || 512 % (KC * BM) == 0) && (BF || 512 % (KC * BN) == 0), "tile shape");
+  static_assert(KC % 4 == 0 && stageable(KC * BM) && stageable(KC * BN), "tile shape");
   static_assert(lds_doubles<CFG>() * 8 <= 64 * 1024, "LDS");
   // odd -> even hand-over in rounds of XR row blocks (whatever fits the
   // parity panels' LDS)
