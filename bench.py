@@ -182,6 +182,9 @@ def main():
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy kernel of known traffic, the "
                          "reference for HBM counter runs)")
+    ap.add_argument("--midplane-bins", type=int, default=0, metavar="N",
+                    help="accumulate the on-device midplane Tr c histogram (N bins over [0, 6)) during the timed "
+                         "steps; its counts are checked and reported")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (each run, or each ensemble "
@@ -213,6 +216,8 @@ def main():
         print("bench: %s precision %d, warmup %d" % (args.workload, prec, args.warmup), file=sys.stderr, flush=True)
         sim.step(args.warmup)
         sim.diagnostics()
+        if args.midplane_bins > 0:
+            sim.midplane_histogram_setup(0.0, 6.0, args.midplane_bins)
         torch.cuda.synchronize()
         ev0 = torch.cuda.Event(enable_timing=True)
         ev1 = torch.cuda.Event(enable_timing=True)
@@ -227,11 +232,17 @@ def main():
         ms = ev0.elapsed_time(ev1)
         recs, st = sim.diagnostics()
         assert st == P.PCS_OK and len(recs) == min(args.steps, 4096) and recs[-1]["blowup"] == 0
+        hist = None
+        if args.midplane_bins > 0:
+            counts = sim.midplane_histogram()
+            assert int(counts.sum()) == args.steps * w["nx"] * (w["nz"] if w["dim"] == 3 else 1)
+            hist = dict(bins=args.midplane_bins, lo=0.0, hi=6.0, samples=int(counts.sum()),
+                        below_lo=int(counts[0]), at_or_above_hi=int(counts[-1]))
         print("bench: timed %d steps in %.3f ms (wall %.3f s)" % (args.steps, ms, wall), file=sys.stderr, flush=True)
         # per-stage durations (eager launches, HIP events on the run's stream)
         stages = sim.stage_times(args.stage_steps, reps=args.stage_reps)
         sim.close()
-        timed[prec] = dict(ms=ms, sps=args.steps / (ms / 1e3), stages=stages, prm=prm)
+        timed[prec] = dict(ms=ms, sps=args.steps / (ms / 1e3), stages=stages, prm=prm, hist=hist)
     head = precs[0]
     ms, sps, stages, prm = timed[head]["ms"], timed[head]["sps"], timed[head]["stages"], timed[head]["prm"]
     table = roofline_table(stages, stage_work(w, head))
@@ -277,6 +288,8 @@ def main():
                 "min_trc_abs": abs(d["min_trc"] - e["min_trc"]),
                 "counts_equal": all(d[k] == e[k] for k in ("n_lt3", "n_lt0", "mid_n_lt3", "mid_n_lt0")),
             }
+    if timed[head]["hist"] is not None:
+        line["midplane_histogram"] = timed[head]["hist"]
     print(json.dumps(line), flush=True)
 
 

@@ -148,6 +148,24 @@ pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
 pcs_status pcs_stage_times(struct pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage);
 const char* pcs_stage_name(int32_t i);
 
+/* Midplane statistics (paper, Section 3, eqs. (4)-(5)).  While enabled,
+ * every step adds the base-grid values of Tr c on the midplane y = 0 (the
+ * Nx Nz points of Lobatto row N/2, where y = 0 exactly) to a histogram kept
+ * on the device: with w = (hi - lo) / nbins, counts[b] (1 <= b <= nbins)
+ * counts values in [lo + (b-1) w, lo + b w) (bin 1 + floor((v - lo) nbins /
+ * (hi - lo)), evaluated in FP64), counts[0] values below lo and
+ * counts[nbins + 1] values at or above hi and non-finite ones.  These are the
+ * samples of the PDF P_c of eq. (4); P(Tr c < 3) is the fraction of samples
+ * below 3 and chi of eq. (5) that number of samples divided by Nx Nz (the
+ * per-step counts of the same events are also in pcs_diag.mid_n_lt3).
+ * Setup clears the counts (nbins = 0 turns the histogram off, the default;
+ * PCS_ERR_ARG for nbins > PCS_HIST_MAX, non-finite lo or hi, or lo >= hi) and
+ * synchronises the stream.  pcs_midplane_histogram synchronises and copies
+ * the nbins + 2 counts (n must be nbins + 2; PCS_ERR_ARG while off). */
+#define PCS_HIST_MAX 4096
+pcs_status pcs_midplane_histogram_setup(struct pcs_sim* sim, double lo, double hi, int32_t nbins);
+pcs_status pcs_midplane_histogram(struct pcs_sim* sim, uint64_t* counts, int32_t n);
+
 pcs_status pcs_destroy(struct pcs_sim* sim);
 const char* pcs_status_string(pcs_status s);
 
@@ -176,6 +194,11 @@ pcs_status pcs_ensemble_step(struct pcs_ens* ens, int32_t nsteps);
 pcs_status pcs_ensemble_diagnostics(struct pcs_ens* ens, int32_t run, pcs_diag* out, int32_t max, int32_t* n_out);
 pcs_status pcs_ensemble_state_size(struct pcs_ens* ens, int32_t run, size_t* n);
 pcs_status pcs_ensemble_get_state(struct pcs_ens* ens, int32_t run, double* host, size_t n);
+/* Midplane histogram of run `run`, as pcs_midplane_histogram_setup and
+ * pcs_midplane_histogram. */
+pcs_status pcs_ensemble_midplane_histogram_setup(struct pcs_ens* ens, int32_t run, double lo, double hi,
+                                                 int32_t nbins);
+pcs_status pcs_ensemble_midplane_histogram(struct pcs_ens* ens, int32_t run, uint64_t* counts, int32_t n);
 pcs_status pcs_ensemble_destroy(struct pcs_ens* ens);
 
 #ifdef __cplusplus

@@ -32,6 +32,8 @@ Modules:
   fourier   padded Fourier transforms in x and z (numpy.fft, float64)
   initial   laminar Poiseuille base state and the seeded perturbation
   channel   the Oracle class: state, explicit terms, CNAB2 step, diagnostics
+  stats     midplane statistics: histogram of the samples, P(Tr c < 3), chi
 """
 
 from .channel import Oracle, Grid, Params, state_layout  # noqa: F401
+from . import stats  # noqa: F401

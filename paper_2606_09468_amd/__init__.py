@@ -29,8 +29,10 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_get_state", "pcs_set_state", "pcs_stage_times", "pcs_destroy", "pcs_status_string",
            "pcs_stage_name", "pcs_ensemble_workspace_bytes", "pcs_ensemble_init", "pcs_ensemble_step",
            "pcs_ensemble_diagnostics", "pcs_ensemble_state_size", "pcs_ensemble_get_state",
-           "pcs_ensemble_destroy")
+           "pcs_ensemble_destroy", "pcs_midplane_histogram_setup", "pcs_midplane_histogram",
+           "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram")
 PCS_NSTAGE = 12
+PCS_HIST_MAX = 4096
 
 
 class pcs_grid(ctypes.Structure):
@@ -88,6 +90,11 @@ def lib():
     L.pcs_ensemble_state_size.argtypes = [vp, st, ctypes.POINTER(sz)]
     L.pcs_ensemble_get_state.argtypes = [vp, st, ctypes.POINTER(ctypes.c_double), sz]
     L.pcs_ensemble_destroy.argtypes = [vp]
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    L.pcs_midplane_histogram_setup.argtypes = [vp, ctypes.c_double, ctypes.c_double, st]
+    L.pcs_midplane_histogram.argtypes = [vp, u64p, st]
+    L.pcs_ensemble_midplane_histogram_setup.argtypes = [vp, st, ctypes.c_double, ctypes.c_double, st]
+    L.pcs_ensemble_midplane_histogram.argtypes = [vp, st, u64p, st]
     for name in EXPORTS:
         if name not in ("pcs_status_string", "pcs_stage_name"):
             getattr(L, name).restype = st
@@ -186,6 +193,20 @@ class Sim:
         _check(lib().pcs_set_state(self.handle, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), flat.size),
                "pcs_set_state")
 
+    def midplane_histogram_setup(self, lo, hi, nbins):
+        """Starts (nbins > 0, clearing the counts) or stops (nbins = 0) the
+        on-device histogram of midplane Tr c (see pcs_midplane_histogram_setup)."""
+        _check(lib().pcs_midplane_histogram_setup(self.handle, float(lo), float(hi), int(nbins)),
+               "pcs_midplane_histogram_setup")
+        self.hist_bins = int(nbins)
+
+    def midplane_histogram(self):
+        """The nbins + 2 counts: below lo, the nbins bins, at or above hi (and non-finite)."""
+        out = np.zeros(getattr(self, "hist_bins", 0) + 2, dtype=np.uint64)
+        _check(lib().pcs_midplane_histogram(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                            out.size), "pcs_midplane_histogram")
+        return out
+
     def stage_times(self, nsteps, reps=1):
         """Mean milliseconds per launch of each stage over nsteps real steps
         (eager launch, every stage but the last repeated reps times back to
@@ -246,6 +267,20 @@ class Ensemble:
         n = ctypes.c_size_t(0)
         _check(lib().pcs_ensemble_state_size(self.handle, int(run), ctypes.byref(n)), "pcs_ensemble_state_size")
         return n.value
+
+    def midplane_histogram_setup(self, run, lo, hi, nbins):
+        _check(lib().pcs_ensemble_midplane_histogram_setup(self.handle, int(run), float(lo), float(hi), int(nbins)),
+               "pcs_ensemble_midplane_histogram_setup")
+        if not hasattr(self, "hist_bins"):
+            self.hist_bins = {}
+        self.hist_bins[int(run)] = int(nbins)
+
+    def midplane_histogram(self, run):
+        out = np.zeros(getattr(self, "hist_bins", {}).get(int(run), 0) + 2, dtype=np.uint64)
+        _check(lib().pcs_ensemble_midplane_histogram(self.handle, int(run),
+                                                     out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.size),
+               "pcs_ensemble_midplane_histogram")
+        return out
 
     def get_state(self, run):
         out = np.zeros(self.state_size(run))

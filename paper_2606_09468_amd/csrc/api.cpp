@@ -226,6 +226,7 @@ struct Member {
   double *Ybar, *mcol, *smean;
   int *zsrc, *zder;
   DiagPart* parts;
+  unsigned long long* hist;  // midplane histogram counts (HIST_MAX + 2)
   DiagRec* ring;
   DevScalars* sc;
   // G1: state -> padded grid; Gbar: FP64 mean profiles there (mixed);
@@ -238,6 +239,8 @@ struct Member {
   double wU1 = 0;
   long long drained = 0;
   int blowup = 0;
+  double hlo = 0, hhi = 0;  // midplane histogram range and bins (0: off)
+  int hbins = 0;
   size_t nstate = 0;
   std::vector<JobList*> stage_lists() { return {&G1, &Gbar, &G1b, &G2, &Gm, &G4, &G5}; }
 };
@@ -415,6 +418,7 @@ void carve(Member* m, Carve& c) {
   m->zder = c.take<int>(32);
   const size_t zrows = d.dim == 3 ? d.nz : 1;
   m->parts = c.take<DiagPart>(n1 * zrows);
+  m->hist = c.take<unsigned long long>(HIST_MAX + 2);
   m->ring = c.take<DiagRec>(RING);
   m->sc = c.take<DevScalars>(1);
 }
@@ -1056,6 +1060,10 @@ void build_batch(Batch* b) {
     r.tw = m->twbx;
     r.ydy = m->ydy;
     r.parts = m->parts;
+    r.hist = m->hist;
+    r.hbins = m->hbins;
+    r.hlo = m->hlo;
+    r.hscale = m->hbins > 0 ? m->hbins / (m->hhi - m->hlo) : 0.0;
     r.blk0 = b->bdr;
     b->bdr += n1 * r.zrows;
     b->ldr = std::max(b->ldr, diag_rows_lds_bytes(d.nx));
@@ -1552,6 +1560,37 @@ pcs_status member_diagnostics(Member* m, hipStream_t s, pcs_diag* outp, int32_t 
   return m->blowup ? PCS_BLOWUP : PCS_OK;
 }
 
+// Midplane histogram of Tr c (Section 3, eqs. (4)-(5)): sets the range and
+// bins of run `idx` (nbins = 0: off), clears its counts and updates the
+// argument table the captured steps read.
+static_assert(HIST_MAX == PCS_HIST_MAX, "histogram capacity");
+pcs_status member_hist_setup(Batch* b, int idx, double lo, double hi, int32_t nbins) {
+  if (nbins < 0 || nbins > HIST_MAX) return PCS_ERR_ARG;
+  if (nbins > 0 && !(std::isfinite(lo) && std::isfinite(hi) && lo < hi && std::isfinite(nbins / (hi - lo))))
+    return PCS_ERR_ARG;
+  Member* m = b->mem[idx];
+  hipStream_t s = b->s;
+  HIPCHK(hipStreamSynchronize(s));
+  m->hlo = lo;
+  m->hhi = hi;
+  m->hbins = nbins;
+  DRowArgs& r = b->hdr[idx];
+  r.hbins = nbins;
+  r.hlo = lo;
+  r.hscale = nbins > 0 ? nbins / (hi - lo) : 0.0;
+  HIPCHK(hipMemcpy(b->ddr + idx, &r, sizeof(r), hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(m->hist, 0, (HIST_MAX + 2) * sizeof(unsigned long long)));
+  return PCS_OK;
+}
+
+pcs_status member_hist_get(Member* m, hipStream_t s, uint64_t* counts, int32_t n) {
+  if (!counts || m->hbins <= 0 || n != m->hbins + 2) return PCS_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(s));
+  static_assert(sizeof(uint64_t) == sizeof(unsigned long long), "count type");
+  HIPCHK(hipMemcpy(counts, m->hist, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  return PCS_OK;
+}
+
 pcs_status member_get_state(Member* m, hipStream_t s, double* host, size_t n) {
   if (!host || n != m->nstate) return PCS_ERR_ARG;
   DevScalars sc;
@@ -1640,6 +1679,16 @@ pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
   return PCS_OK;
 }
 
+pcs_status pcs_midplane_histogram_setup(pcs_sim* sim, double lo, double hi, int32_t nbins) {
+  if (!sim) return PCS_ERR_ARG;
+  return member_hist_setup(&sim->b, 0, lo, hi, nbins);
+}
+
+pcs_status pcs_midplane_histogram(pcs_sim* sim, uint64_t* counts, int32_t n) {
+  if (!sim) return PCS_ERR_ARG;
+  return member_hist_get(sim->m(), sim->b.s, counts, n);
+}
+
 pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
   if (!sim || nsteps <= 0 || reps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
   if (sim->m()->blowup) return PCS_ERR_STATE;
@@ -1721,6 +1770,16 @@ pcs_status pcs_ensemble_state_size(pcs_ens* e, int32_t run, size_t* n) {
 pcs_status pcs_ensemble_get_state(pcs_ens* e, int32_t run, double* host, size_t n) {
   if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
   return member_get_state(e->b.mem[run], e->b.s, host, n);
+}
+
+pcs_status pcs_ensemble_midplane_histogram_setup(pcs_ens* e, int32_t run, double lo, double hi, int32_t nbins) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  return member_hist_setup(&e->b, run, lo, hi, nbins);
+}
+
+pcs_status pcs_ensemble_midplane_histogram(pcs_ens* e, int32_t run, uint64_t* counts, int32_t n) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  return member_hist_get(e->b.mem[run], e->b.s, counts, n);
 }
 
 pcs_status pcs_ensemble_destroy(pcs_ens* e) {

@@ -954,9 +954,25 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
   double mn = 1.0 / 0.0, cf = 0, es = 0, ts = 0;
   unsigned long long n3 = 0, n0 = 0;
   int flag = 0, big = 0;
+  // the midplane row (y = 0 exactly at j = N/2) feeds the histogram
+  const int hb = (j == d.N / 2) ? DA.hbins : 0;
   for (int n = tid; n < L; n += DNT) {
     const c2 z0 = AV[n], z1 = AV[L + n];
     const double trc = z0.x + (d.dim == 2 ? 1.0 : 0.0);
+    if (hb > 0) {
+      const double u = (trc - DA.hlo) * DA.hscale;
+      const int bin = !(u < (double)hb) ? hb + 1 : (u < 0.0 ? 0 : (int)u + 1);
+      // one atomic per distinct bin of the wave (a narrow distribution would
+      // otherwise send every sample to the same counter)
+      unsigned long long todo = __ballot(1);
+      while (todo) {
+        const int leader = __ffsll((long long)todo) - 1;
+        const int b = __shfl(bin, leader);
+        const unsigned long long same = __ballot(bin == b);
+        if ((tid & 63) == leader) atomicAdd(&DA.hist[b], (unsigned long long)__popcll(same));
+        todo &= ~same;
+      }
+    }
     const double u = z0.y, v = z1.x, w = d.dim == 3 ? z1.y : 0.0;
     mn = fmin(mn, trc);
     n3 += (trc < 3.0);

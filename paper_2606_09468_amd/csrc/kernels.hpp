@@ -228,8 +228,15 @@ struct DRowArgs {
   const double* tw;
   const double* ydy;
   DiagPart* parts;
+  // midplane histogram of Tr c (hbins = 0: off): counts[0] below hlo,
+  // counts[1 + floor((v - hlo) hscale)] inside, counts[hbins + 1] at or above
+  // the top and non-finite values
+  unsigned long long* hist;
+  double hlo, hscale;
+  int hbins;
   int blk0;
 };
+constexpr int HIST_MAX = 4096;  // largest number of histogram bins
 struct DFinArgs {
   Dims d;
   Phys p;
