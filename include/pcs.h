@@ -166,6 +166,22 @@ const char* pcs_stage_name(int32_t i);
 pcs_status pcs_midplane_histogram_setup(struct pcs_sim* sim, double lo, double hi, int32_t nbins);
 pcs_status pcs_midplane_histogram(struct pcs_sim* sim, uint64_t* counts, int32_t n);
 
+/* Resampling between resolutions (Section 2 starts every run of Table 1 from one
+ * snapshot re-interpolated onto its grid; host only, no GPU work): fills dst_state
+ * (the flat layout of pcs_get_state for grid dst, nd doubles) from src_state
+ * (grid src, ns doubles) of the same dimension and box (lx, lz).  Per field
+ * and Fourier mode, the Chebyshev series interpolating the source Lobatto
+ * values is truncated or zero-padded to the target degree and evaluated on
+ * the target points (exact for polynomials of degree up to min(Ny, Ny') - 1);
+ * Fourier amplitudes of modes retained at both resolutions are copied, the
+ * others are zero; the header [step, t, Pi, 0] is copied.  Truncation can
+ * leave wall values slightly off their boundary conditions; the next step's
+ * solves restore them.  The result goes to a run with pcs_set_state.
+ * PCS_ERR_ARG for null pointers, invalid or mismatched grids (as pcs_grid,
+ * ny >= 5) or wrong sizes. */
+pcs_status pcs_resample_state(const pcs_grid* src, const double* src_state, size_t ns, const pcs_grid* dst,
+                              double* dst_state, size_t nd);
+
 pcs_status pcs_destroy(struct pcs_sim* sim);
 const char* pcs_status_string(pcs_status s);
 

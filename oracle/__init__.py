@@ -33,7 +33,9 @@ Modules:
   initial   laminar Poiseuille base state and the seeded perturbation
   channel   the Oracle class: state, explicit terms, CNAB2 step, diagnostics
   stats     midplane statistics: histogram of the samples, P(Tr c < 3), chi
+  resample  a state carried to another resolution (spectral pad/truncate)
 """
 
 from .channel import Oracle, Grid, Params, state_layout  # noqa: F401
 from . import stats  # noqa: F401
+from . import resample  # noqa: F401

@@ -30,7 +30,7 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_stage_name", "pcs_ensemble_workspace_bytes", "pcs_ensemble_init", "pcs_ensemble_step",
            "pcs_ensemble_diagnostics", "pcs_ensemble_state_size", "pcs_ensemble_get_state",
            "pcs_ensemble_destroy", "pcs_midplane_histogram_setup", "pcs_midplane_histogram",
-           "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram")
+           "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state")
 PCS_NSTAGE = 12
 PCS_HIST_MAX = 4096
 
@@ -95,6 +95,8 @@ def lib():
     L.pcs_midplane_histogram.argtypes = [vp, u64p, st]
     L.pcs_ensemble_midplane_histogram_setup.argtypes = [vp, st, ctypes.c_double, ctypes.c_double, st]
     L.pcs_ensemble_midplane_histogram.argtypes = [vp, st, u64p, st]
+    dp = ctypes.POINTER(ctypes.c_double)
+    L.pcs_resample_state.argtypes = [ctypes.POINTER(pcs_grid), dp, sz, ctypes.POINTER(pcs_grid), dp, sz]
     for name in EXPORTS:
         if name not in ("pcs_status_string", "pcs_stage_name"):
             getattr(L, name).restype = st
@@ -122,6 +124,22 @@ def make_grid(dim, nx, ny, nz=1, lx=10.0, lz=5.0):
 def make_params(re=0.01, wi=20.0, beta=0.8, kappa=5e-5, eps=0.0, dt=1e-3, forcing=0, q_or_dpdx=4.0 / 3.0,
                 precision=0):
     return pcs_params(re, wi, beta, kappa, eps, dt, forcing, q_or_dpdx, precision)
+
+
+def state_size(grid):
+    """Doubles in the flat state of a run on grid (the layout of pcs_get_state)."""
+    nf = 10 if grid.dim == 2 else 19
+    return 4 + nf * grid.ny * (1 if grid.dim == 2 else grid.nz) * (grid.nx // 2) * 2
+
+
+def resample_state(src_grid, state, dst_grid):
+    """The flat state of another resolution (see pcs_resample_state)."""
+    state = np.ascontiguousarray(state, dtype=np.float64)
+    out = np.zeros(state_size(dst_grid))
+    dp = ctypes.POINTER(ctypes.c_double)
+    _check(lib().pcs_resample_state(ctypes.byref(src_grid), state.ctypes.data_as(dp), state.size,
+                                    ctypes.byref(dst_grid), out.ctypes.data_as(dp), out.size), "pcs_resample_state")
+    return out
 
 
 def pcs_workspace_bytes(grid, params):

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libpcs.so")
 BUILD = os.path.join(ROOT, "_build")
-SOURCES = ["host_ops.cpp", "api.cpp", "gemm.hip", "elem.hip", "fft.hip"]
+SOURCES = ["host_ops.cpp", "api.cpp", "resample.cpp", "gemm.hip", "elem.hip", "fft.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-fPIC", "-std=c++17", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -442,3 +442,31 @@ def test_mixed_rejects_eps(P):
     p = P.make_params(eps=1e-3, precision=1)
     n = ctypes.c_size_t(0)
     assert P.lib().pcs_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(n)) == P.PCS_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("a,b", [((2, 16, 17, 1), (2, 32, 33, 1)), ((2, 32, 33, 1), (2, 16, 17, 1)),
+                                 ((3, 16, 17, 16), (3, 8, 33, 8))])
+def test_restart_at_another_resolution(P, a, b):
+    """Steps on one grid, pcs_resample_state to another, steps there: the
+    library end to end against the oracle doing the same with its own
+    resampling."""
+    print("case restart", a, "->", b, flush=True)
+    prm = dict(wi=20.0, dt=1e-3)
+    ga, gb = Grid(*a), Grid(*b)
+    s1 = P.Sim(P.make_grid(*a), P.make_params(**prm), seed=3, amp=1e-3)
+    s1.step(4)
+    mid = P.resample_state(P.make_grid(*a), s1.get_state(), P.make_grid(*b))
+    s1.close()
+    s2 = P.Sim(P.make_grid(*b), P.make_params(**prm), seed=0, amp=0.0)
+    s2.set_state(mid)
+    s2.step(3)
+    got = s2.get_state()
+    s2.close()
+    from oracle.resample import resample_state
+    o1 = Oracle(ga, Params(**prm), seed=3, amp=1e-3)
+    o1.step(4)
+    o2 = Oracle(gb, Params(**prm), seed=None)
+    o2.set_state(resample_state(ga, o1.get_state(), gb))
+    o2.step(3)
+    N = b[2] - 1
+    check_state(got, o2.get_state(), gb, tol_prognostic(N), tol_history(N), "restart %s->%s" % (a, b))

@@ -6,6 +6,7 @@ import ctypes
 import os
 import re
 
+import numpy as np
 import pytest
 
 import paper_2606_09468_amd as P
@@ -100,3 +101,35 @@ def test_ensemble_draw_recipe():
     assert all(ny in ENSEMBLE_NY and nx in ENSEMBLE_NX and 20 <= wi <= 100 and s == 4000 + r
                for r, (ny, nx, wi, s) in enumerate(a))
     assert len({(ny, nx) for ny, nx, _, _ in a}) > 10   # genuinely uneven
+
+
+@pytest.mark.parametrize("a,b", [
+    ((2, 12, 17, 1), (2, 20, 33, 1)),
+    ((2, 20, 33, 1), (2, 12, 17, 1)),
+    ((3, 8, 13, 8), (3, 12, 21, 16)),
+    ((3, 12, 21, 16), (3, 8, 13, 8)),
+    ((3, 16, 17, 12), (3, 8, 25, 20)),
+])
+def test_resample_state_matches_oracle(L, a, b):
+    """pcs_resample_state (host code of the library) against the oracle's
+    resampling on random states, refining and coarsening each direction."""
+    from oracle import Grid
+    from oracle.resample import resample_state
+    from tests.inputs import random_state
+    ga, gb = Grid(*a), Grid(*b)
+    s = random_state(a[0], a[1], a[2], a[3], seed=21, amp=1.0)
+    s[:4] = [17.0, 0.017, 2.5, 0.0]
+    want = resample_state(ga, s, gb)
+    got = P.resample_state(P.make_grid(*a), s, P.make_grid(*b))
+    assert got.size == want.size == P.state_size(P.make_grid(*b))
+    assert np.array_equal(got[:4], want[:4])
+    assert np.abs(got - want).max() <= 1e-13 * np.abs(want).max()
+
+
+def test_resample_state_rejects_bad_arguments(L):
+    g, s = P.make_grid(2, 8, 9), np.zeros(P.state_size(P.make_grid(2, 8, 9)))
+    for dst in (P.make_grid(2, 8, 9, lx=5.0), P.make_grid(3, 8, 9, 8), P.make_grid(2, 7, 9), P.make_grid(2, 8, 10)):
+        with pytest.raises(P.PcsError):
+            P.resample_state(g, s, dst)
+    with pytest.raises(P.PcsError):
+        P.resample_state(g, s[:-1], P.make_grid(2, 8, 9))
