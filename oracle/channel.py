@@ -1,4 +1,5 @@
-"""The oracle: one CNAB2 step of the polymer channel-flow problem, in float64.
+"""The oracle: one CNAB2 or SBDF4 step of the polymer channel-flow problem, in
+float64.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -36,6 +37,15 @@ dealiased.  The discrete problem solved here, step by step:
                     condition).
    nu = beta/Re, lap = D^2 - k^2.  Then u, w follow from continuity and
    omega_y:  u = (i kx Dv - i kz g)/k^2,  w = (i kz Dv + i kx g)/k^2.
+3'. SBDF4 (scheme 1; the paper's time integrator, Section 2: the 4th-order
+   semi-implicit BDF of Wang and Ruuth 2008), with L the implicit linear part
+   of each equation above and X the explicit terms:
+      (25/12 q^{n+1} - 4 q^n + 3 q^{n-1} - 4/3 q^{n-2} + 1/4 q^{n-3}) / dt
+          = 4 X^n - 6 X^{n-1} + 4 X^{n-2} - X^{n-3} + L q^{n+1},
+   i.e. every Helmholtz operator above with 1/dt -> 25/(12 dt) and the
+   implicit weight 1/2 -> 1 (no explicit half of L).  The state then also
+   carries q^{n-1..n-3} and X^{n-2}, X^{n-3}; a fresh initial condition
+   fills them with a constant past (q^{n-k} := q^n, X^{n-k} := X^n).
 4. Diagnostics on the base grid (Section 3 observables): min Tr c and counts
    of Tr c < 3 and Tr c < 0 over the volume and on the midplane y = 0
    (eqs. 4-5 use the midplane counts), CFL number, blow-up flag, kinetic
@@ -79,26 +89,43 @@ class Params:
     dt: float = 1.0e-3
     forcing: int = 0          # 0: constant flux Q, 1: constant drive dp/dx
     q_or_dpdx: float = 4.0 / 3.0
+    scheme: int = 0           # 0: CNAB2, 1: SBDF4
+
+# SBDF4 (Wang and Ruuth 2008, constant step): leading coefficient, weights of
+# q^{n-k} and of the explicit terms X^{n-k}, k = 0..3
+SBDF4_A0 = 25.0 / 12.0
+SBDF4_ALPHA = (4.0, -3.0, 4.0 / 3.0, -0.25)
+SBDF4_BETA = (4.0, -6.0, 4.0, -1.0)
 
 
-def state_fields(dim):
-    """Names of the state fields in the order of the flat state vector."""
+def q_h_fields(dim):
     if dim == 2:
         q = ["u", "v", "phi"] + ["c" + c for c in COMPS[2]]
         h = ["hv"] + ["F" + c for c in COMPS[2]]
     else:
         q = ["u", "v", "w", "phi", "g"] + ["c" + c for c in COMPS[3]]
         h = ["hv", "hg"] + ["F" + c for c in COMPS[3]]
-    return q + h
+    return q, h
 
 
-def state_layout(grid):
+def state_fields(dim, scheme=0):
+    """Names of the state fields in the order of the flat state vector: the
+    state q^n and the explicit terms X^{n-1} (h); SBDF4 adds q^{n-1..n-3}
+    ("name@k") and X^{n-2}, X^{n-3}."""
+    q, h = q_h_fields(dim)
+    out = q + h
+    if scheme == 1:
+        out += [f"{n}@{k}" for k in (1, 2, 3) for n in q] + [f"{n}@{k}" for k in (2, 3) for n in h]
+    return out
+
+
+def state_layout(grid, scheme=0):
     """(header length, field names, complex values per field) of the flat
     float64 state vector: header [step, t, Pi, 0] then each field as
     [y (N+1)][kz slot][kx (Nx/2)] complex, real/imag interleaved."""
     nzs = 1 if grid.dim == 2 else grid.nz
     per = (grid.ny) * nzs * (grid.nx // 2)
-    return 4, state_fields(grid.dim), per
+    return 4, state_fields(grid.dim, scheme), per
 
 
 def _sym(a, b):
@@ -121,6 +148,12 @@ class Oracle:
         if g.dim == 2:
             g.nz = 1
         self.g, self.p = g, params
+        if params.scheme not in (0, 1):
+            raise ValueError("scheme must be 0 (CNAB2) or 1 (SBDF4)")
+        # Helmholtz coefficients: 1/dt and implicit weight 1/2 (CNAB2) or
+        # 25/(12 dt) and 1 (SBDF4)
+        self.ia = 1.0 / params.dt if params.scheme == 0 else SBDF4_A0 / params.dt
+        self.th = 0.5 if params.scheme == 0 else 1.0
         self.N = g.ny - 1
         self.op = operators(self.N)
         self.M = self.op.M
@@ -141,7 +174,7 @@ class Oracle:
         self._infl = {}
         self._build_mean_solver()
         shape = (self.N + 1, self.nzs, self.nkx)
-        self.q = {name: np.zeros(shape, dtype=np.complex128) for name in state_fields(g.dim)}
+        self.q = {name: np.zeros(shape, dtype=np.complex128) for name in state_fields(g.dim, params.scheme)}
         self.step_count = 0
         self.t = 0.0
         self.pi = 2.0 / params.re if params.forcing == 1 else 0.0
@@ -206,7 +239,8 @@ class Oracle:
         self.init_history()
 
     def init_history(self):
-        """History := explicit terms of the current state (CNAB1 first step)."""
+        """History := explicit terms of the current state (CNAB1 first step);
+        SBDF4: a constant past, q^{n-k} := q^n and X^{n-k} := X^n."""
         Nh, Fh = self.explicit()
         hv, hg = self.assemble(Nh)
         self.q["hv"][:] = hv
@@ -214,12 +248,20 @@ class Oracle:
             self.q["hg"][:] = hg
         for c in self.comps:
             self.q["F" + c][:] = Fh[c]
+        if self.p.scheme == 1:
+            qn, hn = q_h_fields(self.g.dim)
+            for k in (1, 2, 3):
+                for n in qn:
+                    self.q[f"{n}@{k}"] = self.q[n].copy()
+            for k in (2, 3):
+                for n in hn:
+                    self.q[f"{n}@{k}"] = self.q[n].copy()
 
     def _build_mean_solver(self):
         p, op, N = self.p, self.op, self.N
         nu = p.beta / p.re
         D2 = op.D2
-        A = np.eye(N - 1) / p.dt - 0.5 * nu * D2[1:N, 1:N]
+        A = self.ia * np.eye(N - 1) - self.th * nu * D2[1:N, 1:N]
         self._lu_mean = sla.lu_factor(A)
         U1 = np.zeros(N + 1)
         U1[1:N] = sla.lu_solve(self._lu_mean, np.ones(N - 1))
@@ -236,7 +278,7 @@ class Oracle:
         D2 = op.D2
         D2ii = D2[1:N, 1:N]
         I = np.eye(N - 1)
-        Hphi = (1.0 / p.dt + 0.5 * nu * k2) * I - 0.5 * nu * D2ii
+        Hphi = (self.ia + self.th * nu * k2) * I - self.th * nu * D2ii
         Lv = D2ii - k2 * I
         lu_phi = sla.lu_factor(Hphi)
         lu_v = sla.lu_factor(Lv)
@@ -245,7 +287,7 @@ class Oracle:
         for jb in (0, N):
             phi = np.zeros(N + 1)
             phi[jb] = 1.0
-            phi[1:N] = sla.lu_solve(lu_phi, 0.5 * nu * D2[1:N, jb])
+            phi[1:N] = sla.lu_solve(lu_phi, self.th * nu * D2[1:N, jb])
             v = np.zeros(N + 1)
             v[1:N] = sla.lu_solve(lu_v, phi[1:N])
             homo.append((phi, v))
@@ -254,7 +296,7 @@ class Oracle:
         A = np.array([[Dm[0] @ v1, Dm[0] @ v2], [Dm[N] @ v1, Dm[N] @ v2]])
         lu_c = None
         if p.kappa > 0:
-            Hc = (1.0 / p.dt + 0.5 / p.wi + 0.5 * p.kappa * k2) * I - 0.5 * p.kappa * D2ii
+            Hc = (self.ia + self.th / p.wi + self.th * p.kappa * k2) * I - self.th * p.kappa * D2ii
             lu_c = sla.lu_factor(Hc)
         out = dict(phi=lu_phi, v=lu_v, c=lu_c, phi1=phi1, phi2=phi2, v1=v1, v2=v2, A=A)
         if self.cache_lu:
@@ -283,7 +325,7 @@ class Oracle:
         if key not in self._lu:
             p, N = self.p, self.N
             D2ii = self.op.D2[1:N, 1:N]
-            Hc = (1.0 / p.dt + 0.5 / p.wi) * np.eye(N - 1) - 0.5 * p.kappa * D2ii
+            Hc = (self.ia + self.th / p.wi) * np.eye(N - 1) - self.th * p.kappa * D2ii
             self._lu[key] = sla.lu_factor(Hc)
         return self._lu[key]
 
@@ -419,20 +461,43 @@ class Oracle:
         def d2(a):
             return np.tensordot(op.D2, a, axes=(1, 0))
 
+        sb = p.scheme == 1
+
+        def past(name):
+            """SBDF4 history of the state: sum_k alpha_k q^{n-k} / dt."""
+            a = SBDF4_ALPHA
+            return (a[0] * q[name] + a[1] * q[name + "@1"] + a[2] * q[name + "@2"] + a[3] * q[name + "@3"]) / dt
+
+        def extrap(new_x, name):
+            """Explicit terms at n+1: AB2 (CNAB2) or the SBDF4 extrapolation."""
+            if not sb:
+                return 1.5 * new_x - 0.5 * q[name]
+            b = SBDF4_BETA
+            return b[0] * new_x + b[1] * q[name] + b[2] * q[name + "@2"] + b[3] * q[name + "@3"]
+
         # right-hand sides of every mode at once
-        r_phi = (1.0 / dt - 0.5 * nu * k2) * q["phi"] + 0.5 * nu * d2(q["phi"]) \
-            + 1.5 * hv - 0.5 * q["hv"]
-        if g.dim == 3:
-            r_g = (1.0 / dt - 0.5 * nu * k2) * q["g"] + 0.5 * nu * d2(q["g"]) \
-                + 1.5 * hg - 0.5 * q["hg"]
+        if sb:
+            r_phi = past("phi") + extrap(hv, "hv")
+            if g.dim == 3:
+                r_g = past("g") + extrap(hg, "hg")
+        else:
+            r_phi = (1.0 / dt - 0.5 * nu * k2) * q["phi"] + 0.5 * nu * d2(q["phi"]) \
+                + 1.5 * hv - 0.5 * q["hv"]
+            if g.dim == 3:
+                r_g = (1.0 / dt - 0.5 * nu * k2) * q["g"] + 0.5 * nu * d2(q["g"]) \
+                    + 1.5 * hg - 0.5 * q["hg"]
         a_int = 1.0 / dt - 0.5 / p.wi
-        a_new = 1.0 / dt + 0.5 / p.wi
+        a_new = self.ia + self.th / p.wi
         r_c, r_cw = {}, {}
         for ab in self.comps:
             c = q["c" + ab]
-            expl = 1.5 * Fh[ab] - 0.5 * q["F" + ab]
-            r_c[ab] = (a_int - 0.5 * p.kappa * k2) * c + 0.5 * p.kappa * d2(c) + expl
-            r_cw[ab] = a_int * c + expl
+            expl = extrap(Fh[ab], "F" + ab)
+            if sb:
+                r_c[ab] = past("c" + ab) + expl
+                r_cw[ab] = r_c[ab].copy()
+            else:
+                r_c[ab] = (a_int - 0.5 * p.kappa * k2) * c + 0.5 * p.kappa * d2(c) + expl
+                r_cw[ab] = a_int * c + expl
             if ab[0] == ab[1]:
                 r_c[ab][:, 0, 0] += 1.0 / p.wi
                 r_cw[ab][:, 0, 0] += 1.0 / p.wi
@@ -456,7 +521,10 @@ class Oracle:
 
             # mean flow (kx = kz = 0): constant flux or constant drive
             U = q["u"][:, 0, 0].real
-            r = U / dt + 0.5 * nu * (op.D2 @ U) + 1.5 * hv[:, 0, 0].real - 0.5 * q["hv"][:, 0, 0].real
+            if sb:
+                r = past("u")[:, 0, 0].real + extrap(hv, "hv")[:, 0, 0].real
+            else:
+                r = U / dt + 0.5 * nu * (op.D2 @ U) + 1.5 * hv[:, 0, 0].real - 0.5 * q["hv"][:, 0, 0].real
             Up = np.zeros(N + 1)
             Up[1:N] = sla.lu_solve(self._lu_mean, r[1:N], check_finite=False)
             if p.forcing == 0:
@@ -467,7 +535,10 @@ class Oracle:
             self.pi = float(pi)
             if g.dim == 3:
                 W = q["w"][:, 0, 0].real
-                r = W / dt + 0.5 * nu * (op.D2 @ W) + 1.5 * hg[:, 0, 0].real - 0.5 * q["hg"][:, 0, 0].real
+                if sb:
+                    r = past("w")[:, 0, 0].real + extrap(hg, "hg")[:, 0, 0].real
+                else:
+                    r = W / dt + 0.5 * nu * (op.D2 @ W) + 1.5 * hg[:, 0, 0].real - 0.5 * q["hg"][:, 0, 0].real
                 Wn = np.zeros(N + 1)
                 Wn[1:N] = sla.lu_solve(self._lu_mean, r[1:N], check_finite=False)
                 new["w"][:, 0, 0] = Wn
@@ -478,7 +549,7 @@ class Oracle:
                 cn[0] = r_cw[ab][0] / a_new
                 cn[N] = r_cw[ab][N] / a_new
                 if p.kappa > 0:
-                    rin = r_c[ab][1:N] + 0.5 * p.kappa * (
+                    rin = r_c[ab][1:N] + self.th * p.kappa * (
                         op.D2[1:N, 0][:, None, None] * cn[0][None] + op.D2[1:N, N][:, None, None] * cn[N][None])
                     for iz in range(self.nzs):
                         for ix in range(self.nkx):
@@ -511,6 +582,12 @@ class Oracle:
         new["u"] = np.where(nz, un, new["u"])
 
         # history
+        if sb:
+            qn, hn = q_h_fields(g.dim)
+            for n in qn:
+                new[n + "@3"], new[n + "@2"], new[n + "@1"] = q[n + "@2"], q[n + "@1"], q[n]
+            for n in hn:
+                new[n + "@3"], new[n + "@2"] = q[n + "@2"], q[n]
         new["hv"] = hv
         if g.dim == 3:
             new["hg"] = hg
@@ -566,7 +643,7 @@ class Oracle:
 
     # ----------------------------------------------------------- state I/O
     def get_state(self):
-        hdr, names, per = state_layout(self.g)
+        hdr, names, per = state_layout(self.g, self.p.scheme)
         out = np.zeros(hdr + len(names) * per * 2)
         out[0], out[1], out[2] = self.step_count, self.t, self.pi
         o = hdr
@@ -576,7 +653,7 @@ class Oracle:
         return out
 
     def set_state(self, flat):
-        hdr, names, per = state_layout(self.g)
+        hdr, names, per = state_layout(self.g, self.p.scheme)
         flat = np.asarray(flat, dtype=np.float64)
         if flat.size != hdr + len(names) * per * 2:
             raise ValueError("state vector has the wrong length")
