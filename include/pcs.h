@@ -69,12 +69,21 @@ typedef struct {
  *               eps must be 0.
  *  precision = 2: as 1, but the wall-normal transforms of the fluctuation
  *               (to and from the padded grid) are computed in FP64 and
- *               only the periodic transforms and products in FP32. */
+ *               only the periodic transforms and products in FP32.
+ *  scheme = 0:  CNAB2 (Crank-Nicolson on the linear terms, 2nd-order
+ *               Adams-Bashforth on the rest).
+ *  scheme = 1:  SBDF4, the 4th-order semi-implicit BDF that Section 2 names
+ *               (Wang and Ruuth 2008, constant step):
+ *               (25/12 q^{n+1} - 4 q^n + 3 q^{n-1} - 4/3 q^{n-2} + 1/4 q^{n-3})/dt
+ *                 = 4 X^n - 6 X^{n-1} + 4 X^{n-2} - X^{n-3} + L q^{n+1}
+ *               with X the explicit and L the implicit linear terms; a fresh
+ *               initial condition starts from a constant past. */
 typedef struct {
   double re, wi, beta, kappa, eps, dt;
   int32_t forcing;
   double q_or_dpdx;
   int32_t precision;
+  int32_t scheme;
 } pcs_params;
 
 /* One record per step, computed on the base grid (nx x ny x nz points):
@@ -127,7 +136,10 @@ pcs_status pcs_state_size(struct pcs_sim* sim, size_t* n);
  *          3D: u v w phi g cxx cxy cxz cyy cyz czz | hv hg Fxx Fxy Fxz Fyy Fyz Fzz
  *   phi = lap v, g = omega_y; hv, hg, F are the previous step's explicit
  *   terms (AB2 history); the kx = kz = 0 slot of u and w holds the mean
- *   profiles U, W, that of hv and hg the mean-flow forcing history.  */
+ *   profiles U, W, that of hv and hg the mean-flow forcing history.
+ *   SBDF4 (scheme 1) appends the three previous states (every field of the
+ *   first group, for q^{n-1}, q^{n-2}, q^{n-3} in turn) and the explicit
+ *   terms of steps n-2 and n-3 (every field of the second group, twice).  */
 pcs_status pcs_get_state(struct pcs_sim* sim, double* host, size_t n);
 /* Replaces the state (same layout) and clears the blow-up flag. */
 pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
@@ -168,7 +180,7 @@ pcs_status pcs_midplane_histogram(struct pcs_sim* sim, uint64_t* counts, int32_t
 
 /* Resampling between resolutions (Section 2 starts every run of Table 1 from one
  * snapshot re-interpolated onto its grid; host only, no GPU work): fills dst_state
- * (the flat layout of pcs_get_state for grid dst, nd doubles) from src_state
+ * (the flat CNAB2 layout of pcs_get_state for grid dst, nd doubles) from src_state
  * (grid src, ns doubles) of the same dimension and box (lx, lz).  Per field
  * and Fourier mode, the Chebyshev series interpolating the source Lobatto
  * values is truncated or zero-padded to the target degree and evaluated on

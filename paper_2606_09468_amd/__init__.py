@@ -43,7 +43,8 @@ class pcs_grid(ctypes.Structure):
 class pcs_params(ctypes.Structure):
     _fields_ = [("re", ctypes.c_double), ("wi", ctypes.c_double), ("beta", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("eps", ctypes.c_double), ("dt", ctypes.c_double),
-                ("forcing", ctypes.c_int32), ("q_or_dpdx", ctypes.c_double), ("precision", ctypes.c_int32)]
+                ("forcing", ctypes.c_int32), ("q_or_dpdx", ctypes.c_double), ("precision", ctypes.c_int32),
+                ("scheme", ctypes.c_int32)]
 
 
 class pcs_diag(ctypes.Structure):
@@ -122,12 +123,12 @@ def make_grid(dim, nx, ny, nz=1, lx=10.0, lz=5.0):
 
 
 def make_params(re=0.01, wi=20.0, beta=0.8, kappa=5e-5, eps=0.0, dt=1e-3, forcing=0, q_or_dpdx=4.0 / 3.0,
-                precision=0):
-    return pcs_params(re, wi, beta, kappa, eps, dt, forcing, q_or_dpdx, precision)
+                precision=0, scheme=0):
+    return pcs_params(re, wi, beta, kappa, eps, dt, forcing, q_or_dpdx, precision, scheme)
 
 
 def state_size(grid):
-    """Doubles in the flat state of a run on grid (the layout of pcs_get_state)."""
+    """Doubles in the flat CNAB2 state of a run on grid (the layout of pcs_get_state)."""
     nf = 10 if grid.dim == 2 else 19
     return 4 + nf * grid.ny * (1 if grid.dim == 2 else grid.nz) * (grid.nx // 2) * 2
 

@@ -217,6 +217,9 @@ struct Member {
   float *IMN32p[2], *DMN32p[2], *PNM32p[2], *DP32p[2];
   double *twx, *twz, *twbx, *twbz;
   double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *DN, *Dc, *D2buf, *hgn, *hvn;
+  // SBDF4 history: state fields and explicit terms of step k in slot k mod 4
+  // of their ring (null for CNAB2)
+  double *qring, *hring;
   double *R, *Xs, *Zphi, *Zv, *Zg, *ZDv, *flux, *CB, *prep, *zbuf;
   EigScale* es;
   // mixed precision: FP32 operators, twiddles and padded-grid buffers, FP64
@@ -378,6 +381,8 @@ void carve(Member* m, Carve& c) {
   m->twbz = c.take<double>(2 * (size_t)d.nz);
   m->infl = c.take<double>(6 * n1 * d.nm + 4 * (size_t)d.nm);
   m->state = c.take<double>((size_t)(m->nq + m->nh) * n1 * cw);
+  m->qring = m->p.scheme == 1 ? c.take<double>((size_t)4 * m->nq * n1 * cw) : nullptr;
+  m->hring = m->p.scheme == 1 ? c.take<double>((size_t)4 * m->nh * n1 * cw) : nullptr;
   const size_t zrow = (size_t)m1 * d.pz * d.nkx * 2;
   const bool mixed = m->prec != 0;
   m->Yin = !mixed ? c.take<double>((size_t)m->nyin * m1 * cw) : nullptr;
@@ -434,6 +439,7 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
     return PCS_ERR_ARG;
   if (p->forcing != 0 && p->forcing != 1) return PCS_ERR_ARG;
   if (p->precision < 0 || p->precision > 2) return PCS_ERR_ARG;
+  if (p->scheme != 0 && p->scheme != 1) return PCS_ERR_ARG;
   if (p->precision != 0 && p->eps != 0.0) return PCS_ERR_UNSUPPORTED;  // the mixed split is for bilinear products
   if (!valid_fft(3 * g->nx / 2) || !valid_fft(g->nx)) return PCS_ERR_UNSUPPORTED;
   if (g->dim == 3 && (!valid_fft(3 * g->nz / 2) || !valid_fft(g->nz))) return PCS_ERR_UNSUPPORTED;
@@ -472,6 +478,9 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   q.q_or_dpdx = p->q_or_dpdx;
   q.coef = (1.0 - p->beta) / (p->re * p->wi);
   q.nu = p->beta / p->re;
+  q.scheme = p->scheme;
+  q.ia = p->scheme == 0 ? 1.0 / p->dt : (25.0 / 12.0) / p->dt;
+  q.th = p->scheme == 0 ? 0.5 : 1.0;
   m->nq = d.dim == 2 ? 6 : 11;
   m->nh = d.dim == 2 ? 4 : 8;
   m->nyin = d.dim == 2 ? 9 : 17;
@@ -479,7 +488,7 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   m->nout = d.dim == 2 ? 5 : 9;
   m->nsv = d.dim == 2 ? 1 : 2;
   m->nsolve = m->nsv + d.nc;
-  m->nstate = 4 + (size_t)(m->nq + m->nh) * (d.N + 1) * d.cw;
+  m->nstate = 4 + (size_t)(m->nq + m->nh + (p->scheme == 1 ? 3 * m->nq + 2 * m->nh : 0)) * (d.N + 1) * d.cw;
   make_plan(d.px, &m->plx);
   make_plan(d.nx, &m->pbx);
   if (d.dim == 3) {
@@ -857,7 +866,8 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
   es.kz = m->kz;
   es.nkx = d.nkx;
   es.dim = d.dim;
-  es.dt = m->p.dt;
+  es.ia = m->p.ia;
+  es.th = m->p.th;
   es.nu = m->p.nu;
   es.wi = m->p.wi;
   es.kappa = m->p.kappa;
@@ -1096,6 +1106,9 @@ void build_batch(Batch* b) {
     h.hvn = m->hvn;
     h.hgn = m->hgn;
     h.CB = m->CB;
+    h.qring = m->qring;
+    h.hring = m->hring;
+    h.sc = m->sc;
     h.blk0 = b->brhs;
     b->brhs += eblocks;
     b->hrhs.push_back(h);
@@ -1478,6 +1491,8 @@ pcs_status setup_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_par
   return PCS_OK;
 }
 
+pcs_status sbdf4_cold_start(Member* m, hipStream_t s);
+
 pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_params* params, const uint64_t* seeds,
                       double amp, void* workspace, size_t bytes, void* stream) {
   if (!workspace || !seeds || !std::isfinite(amp)) return PCS_ERR_ARG;
@@ -1507,6 +1522,8 @@ pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_para
         (st = homogeneous_solutions(b->mem[i], b->s)) != PCS_OK)
       return st;
   if ((st = upload_tables(b)) != PCS_OK || (st = history_from_state(b)) != PCS_OK) return st;
+  for (Member* m : b->mem)
+    if ((st = sbdf4_cold_start(m, b->s)) != PCS_OK) return st;
   hipError_t e1 = hipStreamSynchronize(b->s), e2 = hipGetLastError();
   if (e1 != hipSuccess || e2 != hipSuccess) {
     report(e1 != hipSuccess ? e1 : e2, "init synchronise", __LINE__);
@@ -1591,11 +1608,44 @@ pcs_status member_hist_get(Member* m, hipStream_t s, uint64_t* counts, int32_t n
   return PCS_OK;
 }
 
+// SBDF4 history in the order of the flat state after (q, h): q^{n-1}, q^{n-2},
+// q^{n-3}, then X^{n-2}, X^{n-3}, each as its ring slot for state index n.
+struct HistBlock {
+  double* dev;
+  size_t doubles;
+};
+std::vector<HistBlock> history_blocks(const Member* m, long long n) {
+  std::vector<HistBlock> out;
+  if (m->p.scheme != 1) return out;
+  const size_t fs = (size_t)(m->d.N + 1) * m->d.cw, qs = (size_t)m->nq * fs, hs = (size_t)m->nh * fs;
+  for (int k = 1; k <= 3; ++k) out.push_back({m->qring + (size_t)((n - k) & 3) * qs, qs});
+  for (int k = 2; k <= 3; ++k) out.push_back({m->hring + (size_t)((n - k) & 3) * hs, hs});
+  return out;
+}
+
+// SBDF4 start from a single state at step 0: a constant past, q^{-k} := q^0
+// and X^{-k} := X^0 (the explicit terms the state's history already holds).
+pcs_status sbdf4_cold_start(Member* m, hipStream_t s) {
+  const size_t qs = (size_t)m->nq * (m->d.N + 1) * m->d.cw;
+  const std::vector<HistBlock> hb = history_blocks(m, 0);
+  for (size_t i = 0; i < hb.size(); ++i)  // three state blocks, then two explicit ones
+    HIPCHK(hipMemcpyAsync(hb[i].dev, i < 3 ? m->state : m->state + qs, hb[i].doubles * sizeof(double),
+                          hipMemcpyDeviceToDevice, s));
+  return PCS_OK;
+}
+
 pcs_status member_get_state(Member* m, hipStream_t s, double* host, size_t n) {
   if (!host || n != m->nstate) return PCS_ERR_ARG;
   DevScalars sc;
   HIPCHK(hipMemcpyAsync(&sc, m->sc, sizeof(sc), hipMemcpyDeviceToHost, s));
-  HIPCHK(hipMemcpyAsync(host + 4, m->state, (n - 4) * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const size_t base = (size_t)(m->nq + m->nh) * (m->d.N + 1) * m->d.cw;
+  HIPCHK(hipMemcpyAsync(host + 4, m->state, base * sizeof(double), hipMemcpyDeviceToHost, s));
+  size_t o = 4 + base;
+  for (const HistBlock& hb : history_blocks(m, sc.step)) {
+    HIPCHK(hipMemcpyAsync(host + o, hb.dev, hb.doubles * sizeof(double), hipMemcpyDeviceToHost, s));
+    o += hb.doubles;
+  }
   HIPCHK(hipStreamSynchronize(s));
   host[0] = (double)sc.step;
   host[1] = sc.t;
@@ -1671,7 +1721,13 @@ pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
   sc.step = (long long)host[0];
   sc.t = host[1];
   sc.pi = host[2];
-  HIPCHK(hipMemcpyAsync(m->state, host + 4, (n - 4) * sizeof(double), hipMemcpyHostToDevice, s));
+  const size_t base = (size_t)(m->nq + m->nh) * (m->d.N + 1) * m->d.cw;
+  HIPCHK(hipMemcpyAsync(m->state, host + 4, base * sizeof(double), hipMemcpyHostToDevice, s));
+  size_t o = 4 + base;
+  for (const HistBlock& hb : history_blocks(m, sc.step)) {
+    HIPCHK(hipMemcpyAsync(hb.dev, host + o, hb.doubles * sizeof(double), hipMemcpyHostToDevice, s));
+    o += hb.doubles;
+  }
   HIPCHK(hipMemcpyAsync(m->sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));
   m->drained = sc.step;

@@ -68,13 +68,13 @@ __device__ inline int cidx(int dim, int a, int b) {
 }
 
 struct Layout {
-  int nq, F_U, F_V, F_W, F_PHI, F_G, F_C, H_HV, H_HG, H_F, nsv, nsolve, S_F;
+  int nq, nh, F_U, F_V, F_W, F_PHI, F_G, F_C, H_HV, H_HG, H_F, nsv, nsolve, S_F;
   __device__ Layout(int dim, int nc) {
     if (dim == 2) {
-      nq = 6; F_U = 0; F_V = 1; F_W = -1; F_PHI = 2; F_G = -1; F_C = 3;
+      nq = 6; nh = 4; F_U = 0; F_V = 1; F_W = -1; F_PHI = 2; F_G = -1; F_C = 3;
       H_HV = 6; H_HG = -1; H_F = 7; nsv = 1; S_F = 2;
     } else {
-      nq = 11; F_U = 0; F_V = 1; F_W = 2; F_PHI = 3; F_G = 4; F_C = 5;
+      nq = 11; nh = 8; F_U = 0; F_V = 1; F_W = 2; F_PHI = 3; F_G = 4; F_C = 5;
       H_HV = 11; H_HG = 12; H_F = 13; nsv = 2; S_F = 3;
     }
     nsolve = nsv + nc;
@@ -100,7 +100,18 @@ struct Layout {
 // and the new wall rows of c (kappa = 0 there):
 //   c_B^new = ((1/dt - 1/(2Wi)) c_B + 3/2 F_B - 1/2 F_B^old + delta/Wi) / (1/dt + 1/(2Wi)).
 // Each thread recomputes the two wall values of its mode, so no thread
-// writes anything another thread reads.  D2buf = [D2 phi, (D2 g), D2 c...]
+// writes anything another thread reads.
+// SBDF4 (p.scheme == 1) replaces the CNAB2 combinations by
+//   sum_k alpha_k q^{n-k} / dt + sum_k beta_k X^{n-k},
+//   alpha = (4, -3, 4/3, -1/4), beta = (4, -6, 4, -1),
+// with no explicit half of the linear terms, wall rows divided by
+// 25/(12 dt) + 1/Wi and the interior c rows coupled to the new wall values
+// by kappa (D2_i0 c_0 + D2_iN c_N).  q^{n-k} comes from ring slot (n-k) mod 4,
+// X^{n-1} from the state and X^{n-2}, X^{n-3} from the explicit ring's slots
+// (n-k) mod 4.  The thread then stores its element of q^n into slot n mod 4
+// and of X^{n-1} into slot (n-1) mod 4 of the two rings: slots no thread of
+// this step reads, and the stores repeat the same values if the kernel is
+// launched again on the same state.  D2buf = [D2 phi, (D2 g), D2 c...]
 // then D2U (N+1) and D2W (N+1); Dc = [D c...].  smean (mixed precision
 // only) replaces S in the mean column.  Outputs: R [nsolve][N-1 rows], hvn,
 // hgn (3D), CB [nc][2 walls][cw].
@@ -137,6 +148,13 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
   if (m.nyq) {
     st2(hvn, off, cd{0, 0});
     if (d.dim == 3) st2(hgn, off, cd{0, 0});
+    if (p.scheme == 1) {  // the history rings hold zeros in the Nyquist slot, like the state
+      const long long n = A.sc->step;
+      const auto qn = gmem(A.qring) + (size_t)(n & 3) * L.nq * fs;
+      const auto h1 = gmem(A.hring) + (size_t)((n - 1) & 3) * L.nh * fs;
+      for (int f = 0; f < L.nq; ++f) st2(qn, (size_t)f * fs + off, cd{0, 0});
+      for (int f = 0; f < L.nh; ++f) st2(h1, (size_t)f * fs + off, cd{0, 0});
+    }
     if (inter)
       for (int f = 0; f < L.nsolve; ++f) st2(R, f * fsi + offi, cd{0, 0});
     if (!inter)
@@ -169,6 +187,54 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
     st2(hgn, off, hg);
   }
   st2(hvn, off, hv);
+  if (p.scheme == 1) {
+    const long long n = A.sc->step;
+    const size_t qs = (size_t)L.nq * fs, hs = (size_t)L.nh * fs;
+    const auto qr = gmem(A.qring);
+    const auto hr = gmem(A.hring);
+    const auto q1 = qr + (size_t)((n - 1) & 3) * qs, q2 = qr + (size_t)((n - 2) & 3) * qs;
+    const auto q3 = qr + (size_t)((n - 3) & 3) * qs;
+    const auto h2 = hr + (size_t)((n - 2) & 3) * hs, h3 = hr + (size_t)((n - 3) & 3) * hs;
+    const double idt = 1.0 / dt;
+    // field f of the state at element offset o: sum_k alpha_k q^{n-k} / dt
+    auto past = [&](int f, size_t o) -> cd {
+      const size_t x = (size_t)f * fs + o;
+      return idt * (4.0 * ld2(st, x) - 3.0 * ld2(q1, x) + (4.0 / 3.0) * ld2(q2, x) - 0.25 * ld2(q3, x));
+    };
+    // explicit field f (state index, >= nq) extrapolated from X^n = x0
+    auto ext = [&](cd x0, int f, size_t o) -> cd {
+      const size_t x = (size_t)(f - L.nq) * fs + o;
+      return 4.0 * x0 - 6.0 * ld2(st, (size_t)f * fs + o) + 4.0 * ld2(h2, x) - ld2(h3, x);
+    };
+    if (inter) {
+      cd r = m.mean ? cd{past(L.F_U, off).r + ext(hv, L.H_HV, off).r, 0} : past(L.F_PHI, off) + ext(hv, L.H_HV, off);
+      st2(R, 0 * fsi + offi, r);
+      if (d.dim == 3) {
+        r = m.mean ? cd{past(L.F_W, off).r + ext(hg, L.H_HG, off).r, 0} : past(L.F_G, off) + ext(hg, L.H_HG, off);
+        st2(R, 1 * fsi + offi, r);
+      }
+    }
+    const double a_new = p.ia + p.th / p.wi;
+    for (int a = 0; a < d.nc; ++a) {
+      const bool diag = (d.dim == 2) ? (a == 0 || a == 2) : (a == 0 || a == 3 || a == 5);
+      const cd src = cd{(m.mean && diag) ? 1.0 / p.wi : 0.0, 0};
+      const int o = L.S_F + a, fc = L.F_C + a, fh = L.H_F + a;
+      const cd cb0 = (1.0 / a_new) * (past(fc, off0) + ext(Sx(o, 0), fh, off0) + src);
+      const cd cbN = (1.0 / a_new) * (past(fc, offN) + ext(Sx(o, N), fh, offN) + src);
+      if (inter) {
+        cd r = past(fc, off) + ext(Sx(o, j), fh, off) + src;
+        if (p.kappa > 0) r = r + (p.th * p.kappa) * (d2i0[j - 1] * cb0 + d2in[j - 1] * cbN);
+        st2(R, (size_t)(L.nsv + a) * fsi + offi, r);
+      } else {
+        st2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode, j == 0 ? cb0 : cbN);
+      }
+    }
+    const auto qn = qr + (size_t)(n & 3) * qs;
+    for (int f = 0; f < L.nq; ++f) st2(qn, (size_t)f * fs + off, ld2(st, (size_t)f * fs + off));
+    const auto h1 = hr + (size_t)((n - 1) & 3) * hs;
+    for (int f = 0; f < L.nh; ++f) st2(h1, (size_t)f * fs + off, ld2(st, (size_t)(L.nq + f) * fs + off));
+    return;
+  }
   const auto D2U = D2buf + (size_t)L.nsolve * fs;
   const auto D2W = D2U + n1;
   if (inter) {
@@ -345,9 +411,9 @@ void launch_finalize(const FinArgs* args, int nmem, int blocks, hipStream_t s) {
 
 // ---------------------------------------------------------------- init: homogeneous solutions
 // Right-hand side whose solve yields phi_1 + i phi_2 in every mode's phi slot:
-// interior rows of (alpha - nu/2 D2) phi = 0 with phi(+1) = 1 (real part) or
+// interior rows of (ia - th nu D2) phi = 0 with phi(+1) = 1 (real part) or
 // phi(-1) = 1 (imaginary part) move the wall column to the right:
-//   R = nu/2 (D2_i0 + i D2_iN).   Mean slot: R = 1 (gives U_1).
+//   R = th nu (D2_i0 + i D2_iN).   Mean slot: R = 1 (gives U_1).
 __global__ void homog_rhs_kernel(Dims d, Phys p, const double* __restrict__ d2i0, const double* __restrict__ d2in,
                                  double* __restrict__ R) {
   const int ni = d.N - 1;
@@ -359,8 +425,8 @@ __global__ void homog_rhs_kernel(Dims d, Phys p, const double* __restrict__ d2i0
     R[off] = 1.0;
     R[off + 1] = 0.0;
   } else {
-    R[off] = 0.5 * p.nu * d2i0[j];
-    R[off + 1] = 0.5 * p.nu * d2in[j];
+    R[off] = p.th * p.nu * d2i0[j];
+    R[off + 1] = p.th * p.nu * d2in[j];
   }
 }
 

@@ -190,10 +190,11 @@ __device__ inline const GemmJob* tile_job(const GemmJob* __restrict__ jobs, cons
 }
 
 // Inverse Helmholtz symbol of kind `kind` for eigenvalue lam and wavenumber
-// magnitude k2 (mode 0 is the mean slot).
+// magnitude k2 (mode 0 is the mean slot); ia is the scheme's leading
+// coefficient over dt and th its implicit weight.
 __device__ inline double eig_factor(const EigScale& es, int kind, double lam, double k2, bool mean) {
-  if (kind == SCALE_C) return 1.0 / (1.0 / es.dt + 0.5 / es.wi + 0.5 * es.kappa * (k2 - lam));
-  const double f = 1.0 / (1.0 / es.dt + 0.5 * es.nu * (k2 - lam));
+  if (kind == SCALE_C) return 1.0 / (es.ia + es.th / es.wi + es.th * es.kappa * (k2 - lam));
+  const double f = 1.0 / (es.ia + es.th * es.nu * (k2 - lam));
   if (kind == SCALE_V) return mean ? 0.0 : f / (lam - k2);
   return f;
 }

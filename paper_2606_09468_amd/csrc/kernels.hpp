@@ -76,7 +76,8 @@ struct EigScale {
   const double* kx;
   const double* kz;
   int nkx, dim;
-  double dt, nu, wi, kappa;
+  double ia, th;  // Helmholtz coefficients: 1/dt and 1/2 (CNAB2), 25/(12 dt) and 1 (SBDF4)
+  double nu, wi, kappa;
 };
 
 // compute / B / C precisions: D = double, F = float
@@ -154,6 +155,8 @@ struct Phys {
   double q_or_dpdx;
   double coef;      // (1 - beta)/(Re Wi)
   double nu;        // beta / Re
+  int scheme;       // 0: CNAB2, 1: SBDF4
+  double ia, th;    // leading coefficient / dt and implicit weight of the scheme
 };
 
 // Device-resident scalars advanced by the step itself.
@@ -255,6 +258,9 @@ struct RhsArgs {
   Phys p;
   const double *st, *D2buf, *Dc, *S, *smean, *DN, *kx, *kz, *d2i0, *d2in;
   double *R, *hvn, *hgn, *CB;
+  double* qring;         // SBDF4: four slots of the state fields, q^k in slot k mod 4
+  double* hring;         // SBDF4: four slots of the explicit terms, X^k in slot k mod 4
+  const DevScalars* sc;  // step index n of the current state
   int blk0;
 };
 // influence correction, flux, velocities, wall rows, history, diagnostics
