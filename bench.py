@@ -132,12 +132,12 @@ def traffic_for(kernel, workload, precision):
     return None
 
 
-def cpu_baseline(w, sample_steps):
+def cpu_baseline(w, sample_steps, scheme=0):
     from threadpoolctl import threadpool_info
 
     from oracle import Grid, Oracle, Params
     g = Grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
-    prm = Params(wi=w["wi"], dt=w["dt"])
+    prm = Params(wi=w["wi"], dt=w["dt"], scheme=scheme)
     t0 = time.perf_counter()
     o = Oracle(g, prm, seed=w["seed"], amp=1e-3)
     o.step(1)           # builds the per-wavenumber LU factors
@@ -185,7 +185,10 @@ def main():
     ap.add_argument("--midplane-bins", type=int, default=0, metavar="N",
                     help="accumulate the on-device midplane Tr c histogram (N bins over [0, 6)) during the timed "
                          "steps; its counts are checked and reported")
+    ap.add_argument("--scheme", default="cnab2", choices=["cnab2", "sbdf4"],
+                    help="time scheme: CNAB2 (the workloads' scheme) or the paper's SBDF4")
     args = ap.parse_args()
+    args.scheme_id = 1 if args.scheme == "sbdf4" else 0
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (each run, or each ensemble "
               "member, would be sharded across GPUs without communication); run with --gpus 1.",
@@ -211,7 +214,7 @@ def main():
     precs = {"both": [1, 0], "fp64": [0], "mixed": [1], "mixed64y": [2]}[args.precision]
     timed = {}
     for prec in precs:
-        prm = P.make_params(wi=w["wi"], dt=w["dt"], precision=prec)
+        prm = P.make_params(wi=w["wi"], dt=w["dt"], precision=prec, scheme=args.scheme_id)
         sim = P.Sim(grid, prm, seed=w["seed"], amp=1e-3)
         print("bench: %s precision %d, warmup %d" % (args.workload, prec, args.warmup), file=sys.stderr, flush=True)
         sim.step(args.warmup)
@@ -254,7 +257,8 @@ def main():
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64"}[head], "data": "synthetic",
-        "config": {"workload": w["desc"], "grid": [w["nx"], w["ny"], w["nz"]],
+        "config": {"workload": w["desc"] if args.scheme_id == 0 else w["desc"].replace("CNAB2", "SBDF4"),
+                   "grid": [w["nx"], w["ny"], w["nz"]],
                    "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms"}[head],
                    "parallelism": "single GPU"},
         "grid_point_updates_per_s": sps * points,
@@ -269,7 +273,7 @@ def main():
         line["speedup_mixed_vs_fp64"] = timed[1]["sps"] / timed[0]["sps"]
     if not args.no_cpu_baseline:
         print("bench: oracle sample of %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
-        o, cb = cpu_baseline(w, args.cpu_steps)
+        o, cb = cpu_baseline(w, args.cpu_steps, args.scheme_id)
         line["cpu_baseline"] = cb
         # error of each timed precision against the oracle over the same sample
         line["error_vs_oracle"] = {}
@@ -293,7 +297,7 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def ensemble_cpu_baseline(members, dt, steps=2):
+def ensemble_cpu_baseline(members, dt, steps=2, scheme=0):
     """Oracle seconds per ensemble step: each distinct member size is timed
     over `steps` steps after one warm-up step, and the members are summed."""
     from threadpoolctl import threadpool_info
@@ -304,7 +308,7 @@ def ensemble_cpu_baseline(members, dt, steps=2):
     for ny, nx, wi, seed in members:
         if (ny, nx) in per:
             continue
-        o = Oracle(Grid(2, nx, ny), Params(wi=wi, dt=dt), seed=seed, amp=1e-3)
+        o = Oracle(Grid(2, nx, ny), Params(wi=wi, dt=dt, scheme=scheme), seed=seed, amp=1e-3)
         o.step(1)
         t0 = time.perf_counter()
         o.step(steps)
@@ -324,7 +328,8 @@ def bench_ensemble(args, P):
     members = ensemble_members(ENSEMBLE["count"], ENSEMBLE["seed"])
     prec = {"both": 1, "fp64": 0, "mixed": 1, "mixed64y": 2}[args.precision]
     grids = [P.make_grid(2, nx, ny) for ny, nx, _, _ in members]
-    params = [P.make_params(wi=wi, dt=ENSEMBLE["dt"], precision=prec) for _, _, wi, _ in members]
+    params = [P.make_params(wi=wi, dt=ENSEMBLE["dt"], precision=prec, scheme=args.scheme_id)
+              for _, _, wi, _ in members]
     ens = P.Ensemble(grids, params, [s for _, _, _, s in members], amp=1e-3)
     print("bench: ensemble of %d, precision %d, warmup %d" % (len(members), prec, args.warmup),
           file=sys.stderr, flush=True)
@@ -348,14 +353,15 @@ def bench_ensemble(args, P):
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64"}[prec], "data": "synthetic",
-        "config": {"workload": ENSEMBLE["desc"], "members": len(members), "base_points": points,
+        "config": {"workload": ENSEMBLE["desc"] if args.scheme_id == 0 else ENSEMBLE["desc"].replace("CNAB2", "SBDF4"),
+                   "members": len(members), "base_points": points,
                    "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms"}[prec],
                    "parallelism": "single GPU, one graph launch per ensemble step"},
         "grid_point_updates_per_s": sps * points,
         "roofline": None,
     }
     if not args.no_cpu_baseline:
-        line["cpu_baseline"] = ensemble_cpu_baseline(members, ENSEMBLE["dt"])
+        line["cpu_baseline"] = ensemble_cpu_baseline(members, ENSEMBLE["dt"], scheme=args.scheme_id)
     print(json.dumps(line), flush=True)
 
 

@@ -141,7 +141,10 @@ pcs_status pcs_state_size(struct pcs_sim* sim, size_t* n);
  *   first group, for q^{n-1}, q^{n-2}, q^{n-3} in turn) and the explicit
  *   terms of steps n-2 and n-3 (every field of the second group, twice).  */
 pcs_status pcs_get_state(struct pcs_sim* sim, double* host, size_t n);
-/* Replaces the state (same layout) and clears the blow-up flag. */
+/* Replaces the state (same layout) and clears the blow-up flag.  An SBDF4
+ * run also takes the CNAB2 layout (n of a CNAB2 run on the same grid): the
+ * earlier states and explicit terms are then a constant past, q^{n-k} := q^n
+ * and X^{n-k} := X^{n-1} (for instance after pcs_resample_state). */
 pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
 
 /* Profiling: runs nsteps real time steps (the state advances exactly as with

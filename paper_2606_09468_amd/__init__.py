@@ -206,9 +206,9 @@ class Sim:
         return out
 
     def set_state(self, flat):
+        """Full state of this run, or (SBDF4 runs) the CNAB2 layout, which
+        restarts from a constant past; other sizes raise PcsError."""
         flat = np.ascontiguousarray(flat, dtype=np.float64)
-        if flat.size != self.state_size:
-            raise ValueError("state has %d values, expected %d" % (flat.size, self.state_size))
         _check(lib().pcs_set_state(self.handle, flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), flat.size),
                "pcs_set_state")
 

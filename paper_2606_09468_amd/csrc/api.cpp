@@ -1491,7 +1491,7 @@ pcs_status setup_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_par
   return PCS_OK;
 }
 
-pcs_status sbdf4_cold_start(Member* m, hipStream_t s);
+pcs_status sbdf4_cold_start(Member* m, hipStream_t s, long long step);
 
 pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_params* params, const uint64_t* seeds,
                       double amp, void* workspace, size_t bytes, void* stream) {
@@ -1523,7 +1523,7 @@ pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_para
       return st;
   if ((st = upload_tables(b)) != PCS_OK || (st = history_from_state(b)) != PCS_OK) return st;
   for (Member* m : b->mem)
-    if ((st = sbdf4_cold_start(m, b->s)) != PCS_OK) return st;
+    if ((st = sbdf4_cold_start(m, b->s, 0)) != PCS_OK) return st;
   hipError_t e1 = hipStreamSynchronize(b->s), e2 = hipGetLastError();
   if (e1 != hipSuccess || e2 != hipSuccess) {
     report(e1 != hipSuccess ? e1 : e2, "init synchronise", __LINE__);
@@ -1623,11 +1623,11 @@ std::vector<HistBlock> history_blocks(const Member* m, long long n) {
   return out;
 }
 
-// SBDF4 start from a single state at step 0: a constant past, q^{-k} := q^0
-// and X^{-k} := X^0 (the explicit terms the state's history already holds).
-pcs_status sbdf4_cold_start(Member* m, hipStream_t s) {
+// SBDF4 start from a single state at step n: a constant past, q^{n-k} := q^n
+// and X^{n-k} := X^{n-1} (the explicit terms the state's history holds).
+pcs_status sbdf4_cold_start(Member* m, hipStream_t s, long long step = 0) {
   const size_t qs = (size_t)m->nq * (m->d.N + 1) * m->d.cw;
-  const std::vector<HistBlock> hb = history_blocks(m, 0);
+  const std::vector<HistBlock> hb = history_blocks(m, step);
   for (size_t i = 0; i < hb.size(); ++i)  // three state blocks, then two explicit ones
     HIPCHK(hipMemcpyAsync(hb[i].dev, i < 3 ? m->state : m->state + qs, hb[i].doubles * sizeof(double),
                           hipMemcpyDeviceToDevice, s));
@@ -1712,7 +1712,11 @@ pcs_status pcs_get_state(pcs_sim* sim, double* host, size_t n) {
 }
 
 pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
-  if (!sim || !host || n != sim->m()->nstate) return PCS_ERR_ARG;
+  if (!sim || !host) return PCS_ERR_ARG;
+  const size_t base = (size_t)(sim->m()->nq + sim->m()->nh) * (sim->m()->d.N + 1) * sim->m()->d.cw;
+  // SBDF4 also takes the CNAB2 layout (no earlier states): constant past
+  const bool short_form = sim->m()->p.scheme == 1 && n == 4 + base;
+  if (n != sim->m()->nstate && !short_form) return PCS_ERR_ARG;
   for (size_t i = 0; i < 3; ++i)
     if (!std::isfinite(host[i])) return PCS_ERR_ARG;
   Member* m = sim->m();
@@ -1721,12 +1725,16 @@ pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
   sc.step = (long long)host[0];
   sc.t = host[1];
   sc.pi = host[2];
-  const size_t base = (size_t)(m->nq + m->nh) * (m->d.N + 1) * m->d.cw;
   HIPCHK(hipMemcpyAsync(m->state, host + 4, base * sizeof(double), hipMemcpyHostToDevice, s));
-  size_t o = 4 + base;
-  for (const HistBlock& hb : history_blocks(m, sc.step)) {
-    HIPCHK(hipMemcpyAsync(hb.dev, host + o, hb.doubles * sizeof(double), hipMemcpyHostToDevice, s));
-    o += hb.doubles;
+  if (short_form) {
+    pcs_status st = sbdf4_cold_start(m, s, sc.step);
+    if (st != PCS_OK) return st;
+  } else {
+    size_t o = 4 + base;
+    for (const HistBlock& hb : history_blocks(m, sc.step)) {
+      HIPCHK(hipMemcpyAsync(hb.dev, host + o, hb.doubles * sizeof(double), hipMemcpyHostToDevice, s));
+      o += hb.doubles;
+    }
   }
   HIPCHK(hipMemcpyAsync(m->sc, &sc, sizeof(sc), hipMemcpyHostToDevice, s));
   HIPCHK(hipStreamSynchronize(s));

@@ -173,3 +173,43 @@ def test_ensemble_mixes_schemes(P):
         assert a.size == b.size
         assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max(), (r, np.abs(a - b).max() / np.abs(b).max())
     ens.close()
+
+
+def test_sbdf4_takes_cnab2_state_with_constant_past(P):
+    """An SBDF4 run given a CNAB2-layout state (here a CNAB2 run's, resampled
+    to another grid) restarts from a constant past: the same as the full
+    SBDF4 state with q^{n-k} := q^n, X^{n-k} := X^{n-1}, and as the oracle."""
+    print("case sbdf4 short state", flush=True)
+    a, b = (2, 16, 17, 1), (2, 32, 33, 1)
+    prm = dict(wi=20.0, dt=1e-3)
+    s0 = P.Sim(P.make_grid(*a), P.make_params(**prm), seed=3, amp=1e-3)
+    s0.step(5)
+    short = P.resample_state(P.make_grid(*a), s0.get_state(), P.make_grid(*b))
+    s0.close()
+    gb = Grid(*b)
+    hdr, names, per = state_layout(gb, 0)
+    nq = 6
+    base = short[hdr:]
+    full = np.concatenate([short, base[:nq * 2 * per], base[:nq * 2 * per], base[:nq * 2 * per],
+                           base[nq * 2 * per:], base[nq * 2 * per:]])
+    s1 = P.Sim(P.make_grid(*b), P.make_params(scheme=1, **prm), seed=0, amp=0.0)
+    s2 = P.Sim(P.make_grid(*b), P.make_params(scheme=1, **prm), seed=0, amp=0.0)
+    s1.set_state(short)
+    s2.set_state(full)
+    assert np.array_equal(s1.get_state(), full)
+    s1.step(4)
+    s2.step(4)
+    x = s1.get_state()
+    assert np.array_equal(x, s2.get_state())
+    s1.close()
+    s2.close()
+    o = Oracle(gb, Params(scheme=1, **prm), seed=None)
+    o.set_state(full)
+    o.step(4)
+    check(x, o.get_state(), gb, "sbdf4 short state")
+    with pytest.raises(P.PcsError):
+        s3 = P.Sim(P.make_grid(*b), P.make_params(scheme=1, **prm), seed=0, amp=0.0)
+        try:
+            s3.set_state(short[:-2])
+        finally:
+            s3.close()
