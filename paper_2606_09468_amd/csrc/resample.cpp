@@ -13,9 +13,11 @@
 // field is sum_k qhat_k exp(i (kx x + kz z))): modes present at both
 // resolutions are copied, the others are zero.  All of this is host work
 // done once per restart, in extended precision, rounded once to FP64.
+#include <algorithm>
 #include <cmath>
 #include <cstddef>
 #include <cstdint>
+#include <thread>
 #include <vector>
 
 #include "../../include/pcs.h"
@@ -46,24 +48,37 @@ int slot_of_mz(int mz, int nz) {
   return mz >= 0 ? mz : mz + nz;
 }
 
+// cos(pi k / K) for k = 0 .. 2K-1 (T_n at a Lobatto point is cos(pi n j / K),
+// read at n j mod 2K)
+std::vector<long double> cos_table(int K) {
+  const long double pi = 3.141592653589793238462643383279502884L;
+  std::vector<long double> c(2 * (size_t)K);
+  for (int k = 0; k < 2 * K; ++k) c[k] = std::cos(pi * (long double)k / K);
+  return c;
+}
+
 // Q[(N'+1) x (N+1)]: values on the source points -> values of the truncated
 // series on the target points
 std::vector<double> cheb_resample_matrix(int N, int Np) {
-  const long double pi = 3.141592653589793238462643383279502884L;
   const int nmax = N < Np ? N : Np;
+  const std::vector<long double> cs = cos_table(N), ct = cos_table(Np);
   std::vector<long double> C((size_t)(nmax + 1) * (N + 1));  // a_n = sum_j C[n][j] f_j
   for (int n = 0; n <= nmax; ++n)
     for (int j = 0; j <= N; ++j) {
       const long double cn = (n == 0 || n == N) ? 2.0L : 1.0L, cj = (j == 0 || j == N) ? 2.0L : 1.0L;
-      C[(size_t)n * (N + 1) + j] = 2.0L / (N * cn * cj) * std::cos(pi * (long double)n * j / N);
+      C[(size_t)n * (N + 1) + j] = 2.0L / (N * cn * cj) * cs[((size_t)n * j) % (2 * (size_t)N)];
     }
   std::vector<double> Q((size_t)(Np + 1) * (N + 1));
-  for (int i = 0; i <= Np; ++i)
-    for (int j = 0; j <= N; ++j) {
-      long double acc = 0;
-      for (int n = 0; n <= nmax; ++n) acc += std::cos(pi * (long double)n * i / Np) * C[(size_t)n * (N + 1) + j];
-      Q[(size_t)i * (N + 1) + j] = (double)acc;
+  std::vector<long double> acc(N + 1);
+  for (int i = 0; i <= Np; ++i) {
+    std::fill(acc.begin(), acc.end(), 0.0L);
+    for (int n = 0; n <= nmax; ++n) {
+      const long double e = ct[((size_t)n * i) % (2 * (size_t)Np)];
+      const long double* cr = &C[(size_t)n * (N + 1)];
+      for (int j = 0; j <= N; ++j) acc[j] += e * cr[j];
     }
+    for (int j = 0; j <= N; ++j) Q[(size_t)i * (N + 1) + j] = (double)acc[j];
+  }
   return Q;
 }
 
@@ -81,8 +96,9 @@ extern "C" pcs_status pcs_resample_state(const pcs_grid* src, const double* ssta
   const int nkxs = src->nx / 2, nkxd = dst->nx / 2;
   const std::vector<double> Q = cheb_resample_matrix(N, Np);
   for (int h = 0; h < 4; ++h) dstate[h] = sstate[h];
-  std::vector<double> col(2 * (size_t)(N + 1));
-  for (int f = 0; f < nf; ++f) {
+  // one field per task on a few host threads (fields are independent)
+  auto field = [&](int f) {
+    std::vector<double> col(2 * (size_t)(N + 1));
     const double* sf = sstate + 4 + (size_t)f * ps * 2;
     double* df = dstate + 4 + (size_t)f * pd * 2;
     for (int sd = 0; sd < nzd; ++sd) {
@@ -109,6 +125,23 @@ extern "C" pcs_status pcs_resample_state(const pcs_grid* src, const double* ssta
         }
       }
     }
+  };
+  const unsigned hw = std::thread::hardware_concurrency();
+  const int nth = std::max(1, std::min<int>(nf, hw ? (int)std::min(hw, 16u) : 1));
+  std::vector<std::thread> pool;
+  int started = 1;  // threads 1 .. started-1 run; the calling thread covers the rest
+  for (int t = 1; t < nth; ++t) {
+    try {
+      pool.emplace_back([&, t] {
+        for (int f = t; f < nf; f += nth) field(f);
+      });
+      started = t + 1;
+    } catch (...) {
+      break;
+    }
   }
+  for (int f = 0; f < nf; ++f)
+    if (f % nth == 0 || f % nth >= started) field(f);
+  for (std::thread& th : pool) th.join();
   return PCS_OK;
 }
