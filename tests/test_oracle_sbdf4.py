@@ -177,3 +177,39 @@ def test_layout_and_cold_start():
     assert np.array_equal(o.get_state(), o2.get_state())
     with pytest.raises(ValueError):
         Oracle(g, Params(scheme=2))
+
+
+def test_wall_coupled_polymer_diffusion_matches_dense_sbdf4():
+    """A mean-mode c_xx = 1 + s(y) with no flow and kappa > 0: the interior
+    obeys ds/dt = kappa D2 s - s/Wi, the two wall values the same with
+    kappa = 0 (the Section 2 wall condition), so the interior is driven by
+    the decaying wall values through the first and last columns of D2.  The
+    oracle must equal SBDF4 applied to this linear (N+1)-point system, written
+    here as one dense solve per step."""
+    dt, nsteps, wi, kappa = 0.01, 9, 1.0, 0.05
+    g = Grid(2, 8, 17)
+    p = Params(re=1.0, wi=wi, beta=0.5, kappa=kappa, eps=0.0, dt=dt, forcing=1, q_or_dpdx=0.0, scheme=1)
+    o = Oracle(g, p, seed=None)
+    N = g.ny - 1
+    D2 = operators(N).D2
+    A = kappa * D2.copy()
+    A[0] = 0.0
+    A[N] = 0.0
+    A -= np.eye(N + 1) / wi
+    y = operators(N).y
+    rng = np.random.default_rng(5)
+    hist = [0.3 * np.cos(1.3 * y + 0.2 * k) + 0.1 * rng.standard_normal(N + 1) for k in range(4)]
+    for name in o.q:
+        o.q[name][:] = 0
+    for suf, k in (("", 0), ("@1", 1), ("@2", 2), ("@3", 3)):
+        o.q["cxx" + suf][:, 0, 0] = 1.0 + hist[k]
+        o.q["cyy" + suf][:, 0, 0] = 1.0
+    o.step(nsteps)
+    s = list(hist)
+    M = SBDF4_A0 / dt * np.eye(N + 1) - A
+    for _ in range(nsteps):
+        rhs = sum(a * v for a, v in zip(SBDF4_ALPHA, s)) / dt
+        s = [np.linalg.solve(M, rhs)] + s[:3]
+    got = o.q["cxx"][:, 0, 0].real - 1.0
+    assert np.abs(got - s[0]).max() <= 1e-13 * np.abs(s[0]).max()
+    assert np.abs(o.q["u"]).max() < 1e-14      # a mean c_xx drives no flow
