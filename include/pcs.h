@@ -181,6 +181,23 @@ const char* pcs_stage_name(int32_t i);
 pcs_status pcs_midplane_histogram_setup(struct pcs_sim* sim, double lo, double hi, int32_t nbins);
 pcs_status pcs_midplane_histogram(struct pcs_sim* sim, uint64_t* counts, int32_t n);
 
+/* Midplane PDFs of other quantities (Section 3 compares the midplane
+ * statistics of the velocity fluctuations across resolutions): the same
+ * histogram for quantity
+ *   PCS_PDF_TRC  Tr c (the histogram above),
+ *   PCS_PDF_U    u - U(0), U(0) the plane mean of u at y = 0 (its kx = kz = 0
+ *                mode) at the same step,
+ *   PCS_PDF_V    v (whose plane mean is zero),
+ *   PCS_PDF_W    w - W(0) (3D only; PCS_ERR_ARG in 2D),
+ * each with its own range, bins and counts, set up and read as above.  All
+ * four are binned by the same row-diagnostics kernel in the same step. */
+#define PCS_PDF_TRC 0
+#define PCS_PDF_U 1
+#define PCS_PDF_V 2
+#define PCS_PDF_W 3
+pcs_status pcs_midplane_pdf_setup(struct pcs_sim* sim, int32_t quantity, double lo, double hi, int32_t nbins);
+pcs_status pcs_midplane_pdf(struct pcs_sim* sim, int32_t quantity, uint64_t* counts, int32_t n);
+
 /* Resampling between resolutions (Section 2 starts every run of Table 1 from one
  * snapshot re-interpolated onto its grid; host only, no GPU work): fills dst_state
  * (the flat CNAB2 layout of pcs_get_state for grid dst, nd doubles) from src_state
@@ -230,6 +247,12 @@ pcs_status pcs_ensemble_get_state(struct pcs_ens* ens, int32_t run, double* host
 pcs_status pcs_ensemble_midplane_histogram_setup(struct pcs_ens* ens, int32_t run, double lo, double hi,
                                                  int32_t nbins);
 pcs_status pcs_ensemble_midplane_histogram(struct pcs_ens* ens, int32_t run, uint64_t* counts, int32_t n);
+/* Midplane PDF of quantity `quantity` of run `run`, as pcs_midplane_pdf_setup
+ * and pcs_midplane_pdf. */
+pcs_status pcs_ensemble_midplane_pdf_setup(struct pcs_ens* ens, int32_t run, int32_t quantity, double lo, double hi,
+                                           int32_t nbins);
+pcs_status pcs_ensemble_midplane_pdf(struct pcs_ens* ens, int32_t run, int32_t quantity, uint64_t* counts,
+                                     int32_t n);
 pcs_status pcs_ensemble_destroy(struct pcs_ens* ens);
 
 #ifdef __cplusplus

@@ -1,7 +1,7 @@
 """Midplane statistics of the polymer stretch (paper, Section 3, eqs. (4)-(5)).
 
 TEST INFRASTRUCTURE ONLY (see the package docstring): the check for the HIP
-library's on-device midplane histogram.
+library's on-device midplane histograms (Tr c and the velocity fluctuations).
 
 The paper samples Tr c on the channel midplane y = 0 over many snapshots,
 builds the PDF P_c of those samples, and reports the probability of an
@@ -42,3 +42,21 @@ def chi(values, nx, nz, threshold=3.0):
     """Eq. (5): N_events P(Tr c < 3) / (Nx Nz)."""
     v = np.asarray(values, dtype=np.float64).ravel()
     return v.size * probability_below(v, threshold) / (nx * nz)
+
+
+def midplane_quantities(oracle):
+    """The midplane samples of the current state of an Oracle, by quantity:
+    0 Tr c, 1 u - U(0), 2 v, 3 w - W(0) (3D), on the base grid of the row
+    j = N/2 (y = 0), with U(0), W(0) the plane means (the kx = kz = 0 mode)
+    of u and w there.  Section 3 compares the PDFs of these across
+    resolutions."""
+    j = oracle.N // 2
+    q = oracle.q
+    out = {0: oracle.trace_c()[j].ravel().copy()}
+    u = oracle.base_grid(q["u"])[j]
+    out[1] = (u - q["u"][j, 0, 0].real).ravel()
+    out[2] = oracle.base_grid(q["v"])[j].ravel()
+    if oracle.g.dim == 3:
+        w = oracle.base_grid(q["w"])[j]
+        out[3] = (w - q["w"][j, 0, 0].real).ravel()
+    return out

@@ -30,9 +30,12 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_stage_name", "pcs_ensemble_workspace_bytes", "pcs_ensemble_init", "pcs_ensemble_step",
            "pcs_ensemble_diagnostics", "pcs_ensemble_state_size", "pcs_ensemble_get_state",
            "pcs_ensemble_destroy", "pcs_midplane_histogram_setup", "pcs_midplane_histogram",
-           "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state")
+           "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state",
+           "pcs_midplane_pdf_setup", "pcs_midplane_pdf", "pcs_ensemble_midplane_pdf_setup", "pcs_ensemble_midplane_pdf")
 PCS_NSTAGE = 12
 PCS_HIST_MAX = 4096
+# midplane PDF quantities (pcs_midplane_pdf_setup)
+PCS_PDF_TRC, PCS_PDF_U, PCS_PDF_V, PCS_PDF_W = 0, 1, 2, 3
 
 
 class pcs_grid(ctypes.Structure):
@@ -96,6 +99,10 @@ def lib():
     L.pcs_midplane_histogram.argtypes = [vp, u64p, st]
     L.pcs_ensemble_midplane_histogram_setup.argtypes = [vp, st, ctypes.c_double, ctypes.c_double, st]
     L.pcs_ensemble_midplane_histogram.argtypes = [vp, st, u64p, st]
+    L.pcs_midplane_pdf_setup.argtypes = [vp, st, ctypes.c_double, ctypes.c_double, st]
+    L.pcs_midplane_pdf.argtypes = [vp, st, u64p, st]
+    L.pcs_ensemble_midplane_pdf_setup.argtypes = [vp, st, st, ctypes.c_double, ctypes.c_double, st]
+    L.pcs_ensemble_midplane_pdf.argtypes = [vp, st, st, u64p, st]
     dp = ctypes.POINTER(ctypes.c_double)
     L.pcs_resample_state.argtypes = [ctypes.POINTER(pcs_grid), dp, sz, ctypes.POINTER(pcs_grid), dp, sz]
     for name in EXPORTS:
@@ -217,13 +224,26 @@ class Sim:
         on-device histogram of midplane Tr c (see pcs_midplane_histogram_setup)."""
         _check(lib().pcs_midplane_histogram_setup(self.handle, float(lo), float(hi), int(nbins)),
                "pcs_midplane_histogram_setup")
-        self.hist_bins = int(nbins)
+        self.__dict__.setdefault("pdf_bins", {})[PCS_PDF_TRC] = int(nbins)
 
     def midplane_histogram(self):
         """The nbins + 2 counts: below lo, the nbins bins, at or above hi (and non-finite)."""
-        out = np.zeros(getattr(self, "hist_bins", 0) + 2, dtype=np.uint64)
+        out = np.zeros(self.__dict__.get("pdf_bins", {}).get(PCS_PDF_TRC, 0) + 2, dtype=np.uint64)
         _check(lib().pcs_midplane_histogram(self.handle, out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
                                             out.size), "pcs_midplane_histogram")
+        return out
+
+    def midplane_pdf_setup(self, quantity, lo, hi, nbins):
+        """Histogram of midplane quantity PCS_PDF_TRC / _U / _V / _W (see
+        pcs_midplane_pdf_setup)."""
+        _check(lib().pcs_midplane_pdf_setup(self.handle, int(quantity), float(lo), float(hi), int(nbins)),
+               "pcs_midplane_pdf_setup")
+        self.__dict__.setdefault("pdf_bins", {})[int(quantity)] = int(nbins)
+
+    def midplane_pdf(self, quantity):
+        out = np.zeros(self.__dict__.get("pdf_bins", {}).get(int(quantity), 0) + 2, dtype=np.uint64)
+        _check(lib().pcs_midplane_pdf(self.handle, int(quantity), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)),
+                                      out.size), "pcs_midplane_pdf")
         return out
 
     def stage_times(self, nsteps, reps=1):
@@ -290,15 +310,25 @@ class Ensemble:
     def midplane_histogram_setup(self, run, lo, hi, nbins):
         _check(lib().pcs_ensemble_midplane_histogram_setup(self.handle, int(run), float(lo), float(hi), int(nbins)),
                "pcs_ensemble_midplane_histogram_setup")
-        if not hasattr(self, "hist_bins"):
-            self.hist_bins = {}
-        self.hist_bins[int(run)] = int(nbins)
+        self.__dict__.setdefault("pdf_bins", {})[(int(run), PCS_PDF_TRC)] = int(nbins)
 
     def midplane_histogram(self, run):
-        out = np.zeros(getattr(self, "hist_bins", {}).get(int(run), 0) + 2, dtype=np.uint64)
+        out = np.zeros(self.__dict__.get("pdf_bins", {}).get((int(run), PCS_PDF_TRC), 0) + 2, dtype=np.uint64)
         _check(lib().pcs_ensemble_midplane_histogram(self.handle, int(run),
                                                      out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.size),
                "pcs_ensemble_midplane_histogram")
+        return out
+
+    def midplane_pdf_setup(self, run, quantity, lo, hi, nbins):
+        _check(lib().pcs_ensemble_midplane_pdf_setup(self.handle, int(run), int(quantity), float(lo), float(hi),
+                                                     int(nbins)), "pcs_ensemble_midplane_pdf_setup")
+        self.__dict__.setdefault("pdf_bins", {})[(int(run), int(quantity))] = int(nbins)
+
+    def midplane_pdf(self, run, quantity):
+        out = np.zeros(self.__dict__.get("pdf_bins", {}).get((int(run), int(quantity)), 0) + 2, dtype=np.uint64)
+        _check(lib().pcs_ensemble_midplane_pdf(self.handle, int(run), int(quantity),
+                                               out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.size),
+               "pcs_ensemble_midplane_pdf")
         return out
 
     def get_state(self, run):

@@ -229,7 +229,7 @@ struct Member {
   double *Ybar, *mcol, *smean;
   int *zsrc, *zder;
   DiagPart* parts;
-  unsigned long long* hist;  // midplane histogram counts (HIST_MAX + 2)
+  unsigned long long* hist;  // midplane histogram counts (HIST_Q x (HIST_MAX + 2))
   DiagRec* ring;
   DevScalars* sc;
   // G1: state -> padded grid; Gbar: FP64 mean profiles there (mixed);
@@ -242,8 +242,8 @@ struct Member {
   double wU1 = 0;
   long long drained = 0;
   int blowup = 0;
-  double hlo = 0, hhi = 0;  // midplane histogram range and bins (0: off)
-  int hbins = 0;
+  double hlo[HIST_Q] = {}, hhi[HIST_Q] = {};  // midplane histogram ranges and bins (0: off)
+  int hbins[HIST_Q] = {};
   size_t nstate = 0;
   std::vector<JobList*> stage_lists() { return {&G1, &Gbar, &G1b, &G2, &Gm, &G4, &G5}; }
 };
@@ -423,7 +423,7 @@ void carve(Member* m, Carve& c) {
   m->zder = c.take<int>(32);
   const size_t zrows = d.dim == 3 ? d.nz : 1;
   m->parts = c.take<DiagPart>(n1 * zrows);
-  m->hist = c.take<unsigned long long>(HIST_MAX + 2);
+  m->hist = c.take<unsigned long long>((size_t)HIST_Q * (HIST_MAX + 2));
   m->ring = c.take<DiagRec>(RING);
   m->sc = c.take<DevScalars>(1);
 }
@@ -1071,9 +1071,15 @@ void build_batch(Batch* b) {
     r.ydy = m->ydy;
     r.parts = m->parts;
     r.hist = m->hist;
-    r.hbins = m->hbins;
-    r.hlo = m->hlo;
-    r.hscale = m->hbins > 0 ? m->hbins / (m->hhi - m->hlo) : 0.0;
+    for (int q = 0; q < HIST_Q; ++q) {
+      r.hbins[q] = m->hbins[q];
+      r.hlo[q] = m->hlo[q];
+      r.hscale[q] = m->hbins[q] > 0 ? m->hbins[q] / (m->hhi[q] - m->hlo[q]) : 0.0;
+    }
+    // mean-mode u and w at the midplane row: the kx = kz = 0 slot of the
+    // diagnostics inputs [Tr c, u, v, w] at j = N/2
+    r.umean = m->prep + (size_t)1 * n1 * d.cw + (size_t)(d.N / 2) * d.cw;
+    r.wmean = d.dim == 3 ? m->prep + (size_t)3 * n1 * d.cw + (size_t)(d.N / 2) * d.cw : nullptr;
     r.blk0 = b->bdr;
     b->bdr += n1 * r.zrows;
     b->ldr = std::max(b->ldr, diag_rows_lds_bytes(d.nx));
@@ -1577,34 +1583,39 @@ pcs_status member_diagnostics(Member* m, hipStream_t s, pcs_diag* outp, int32_t 
   return m->blowup ? PCS_BLOWUP : PCS_OK;
 }
 
-// Midplane histogram of Tr c (Section 3, eqs. (4)-(5)): sets the range and
-// bins of run `idx` (nbins = 0: off), clears its counts and updates the
-// argument table the captured steps read.
+// Midplane histograms (Section 3: the PDF of Tr c behind eqs. (4)-(5), and
+// those of the velocity fluctuations): sets the range and bins of quantity q
+// of run `idx` (nbins = 0: off), clears its counts and updates the argument
+// table the captured steps read.
 static_assert(HIST_MAX == PCS_HIST_MAX, "histogram capacity");
-pcs_status member_hist_setup(Batch* b, int idx, double lo, double hi, int32_t nbins) {
+static_assert(HIST_Q == 4 && PCS_PDF_TRC == 0 && PCS_PDF_U == 1 && PCS_PDF_V == 2 && PCS_PDF_W == 3, "quantities");
+pcs_status member_hist_setup(Batch* b, int idx, int q, double lo, double hi, int32_t nbins) {
+  if (q < 0 || q >= HIST_Q || (q == PCS_PDF_W && b->mem[idx]->d.dim != 3)) return PCS_ERR_ARG;
   if (nbins < 0 || nbins > HIST_MAX) return PCS_ERR_ARG;
   if (nbins > 0 && !(std::isfinite(lo) && std::isfinite(hi) && lo < hi && std::isfinite(nbins / (hi - lo))))
     return PCS_ERR_ARG;
   Member* m = b->mem[idx];
   hipStream_t s = b->s;
   HIPCHK(hipStreamSynchronize(s));
-  m->hlo = lo;
-  m->hhi = hi;
-  m->hbins = nbins;
+  m->hlo[q] = lo;
+  m->hhi[q] = hi;
+  m->hbins[q] = nbins;
   DRowArgs& r = b->hdr[idx];
-  r.hbins = nbins;
-  r.hlo = lo;
-  r.hscale = nbins > 0 ? nbins / (hi - lo) : 0.0;
+  r.hbins[q] = nbins;
+  r.hlo[q] = lo;
+  r.hscale[q] = nbins > 0 ? nbins / (hi - lo) : 0.0;
   HIPCHK(hipMemcpy(b->ddr + idx, &r, sizeof(r), hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(m->hist, 0, (HIST_MAX + 2) * sizeof(unsigned long long)));
+  HIPCHK(hipMemset(m->hist + (size_t)q * (HIST_MAX + 2), 0, (HIST_MAX + 2) * sizeof(unsigned long long)));
   return PCS_OK;
 }
 
-pcs_status member_hist_get(Member* m, hipStream_t s, uint64_t* counts, int32_t n) {
-  if (!counts || m->hbins <= 0 || n != m->hbins + 2) return PCS_ERR_ARG;
+pcs_status member_hist_get(Member* m, hipStream_t s, int q, uint64_t* counts, int32_t n) {
+  if (q < 0 || q >= HIST_Q) return PCS_ERR_ARG;
+  if (!counts || m->hbins[q] <= 0 || n != m->hbins[q] + 2) return PCS_ERR_ARG;
   HIPCHK(hipStreamSynchronize(s));
   static_assert(sizeof(uint64_t) == sizeof(unsigned long long), "count type");
-  HIPCHK(hipMemcpy(counts, m->hist, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(counts, m->hist + (size_t)q * (HIST_MAX + 2), (size_t)n * sizeof(uint64_t),
+                   hipMemcpyDeviceToHost));
   return PCS_OK;
 }
 
@@ -1745,12 +1756,22 @@ pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
 
 pcs_status pcs_midplane_histogram_setup(pcs_sim* sim, double lo, double hi, int32_t nbins) {
   if (!sim) return PCS_ERR_ARG;
-  return member_hist_setup(&sim->b, 0, lo, hi, nbins);
+  return member_hist_setup(&sim->b, 0, PCS_PDF_TRC, lo, hi, nbins);
 }
 
 pcs_status pcs_midplane_histogram(pcs_sim* sim, uint64_t* counts, int32_t n) {
   if (!sim) return PCS_ERR_ARG;
-  return member_hist_get(sim->m(), sim->b.s, counts, n);
+  return member_hist_get(sim->m(), sim->b.s, PCS_PDF_TRC, counts, n);
+}
+
+pcs_status pcs_midplane_pdf_setup(pcs_sim* sim, int32_t quantity, double lo, double hi, int32_t nbins) {
+  if (!sim) return PCS_ERR_ARG;
+  return member_hist_setup(&sim->b, 0, quantity, lo, hi, nbins);
+}
+
+pcs_status pcs_midplane_pdf(pcs_sim* sim, int32_t quantity, uint64_t* counts, int32_t n) {
+  if (!sim) return PCS_ERR_ARG;
+  return member_hist_get(sim->m(), sim->b.s, quantity, counts, n);
 }
 
 pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
@@ -1838,12 +1859,23 @@ pcs_status pcs_ensemble_get_state(pcs_ens* e, int32_t run, double* host, size_t 
 
 pcs_status pcs_ensemble_midplane_histogram_setup(pcs_ens* e, int32_t run, double lo, double hi, int32_t nbins) {
   if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
-  return member_hist_setup(&e->b, run, lo, hi, nbins);
+  return member_hist_setup(&e->b, run, PCS_PDF_TRC, lo, hi, nbins);
 }
 
 pcs_status pcs_ensemble_midplane_histogram(pcs_ens* e, int32_t run, uint64_t* counts, int32_t n) {
   if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
-  return member_hist_get(e->b.mem[run], e->b.s, counts, n);
+  return member_hist_get(e->b.mem[run], e->b.s, PCS_PDF_TRC, counts, n);
+}
+
+pcs_status pcs_ensemble_midplane_pdf_setup(pcs_ens* e, int32_t run, int32_t quantity, double lo, double hi,
+                                           int32_t nbins) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  return member_hist_setup(&e->b, run, quantity, lo, hi, nbins);
+}
+
+pcs_status pcs_ensemble_midplane_pdf(pcs_ens* e, int32_t run, int32_t quantity, uint64_t* counts, int32_t n) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  return member_hist_get(e->b.mem[run], e->b.s, quantity, counts, n);
 }
 
 pcs_status pcs_ensemble_destroy(pcs_ens* e) {

@@ -954,26 +954,37 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
   double mn = 1.0 / 0.0, cf = 0, es = 0, ts = 0;
   unsigned long long n3 = 0, n0 = 0;
   int flag = 0, big = 0;
-  // the midplane row (y = 0 exactly at j = N/2) feeds the histogram
-  const int hb = (j == d.N / 2) ? DA.hbins : 0;
+  // the midplane row (y = 0 exactly at j = N/2) feeds the histograms
+  const bool midrow = (j == d.N / 2);
+  const double um = (midrow && DA.hbins[1] > 0) ? gmem(DA.umean)[0] : 0.0;
+  const double wm = (midrow && DA.hbins[3] > 0 && DA.wmean) ? gmem(DA.wmean)[0] : 0.0;
+  auto bin_sample = [&](int qh, double val) {
+    const int hb = DA.hbins[qh];
+    if (hb <= 0) return;
+    const double x = (val - DA.hlo[qh]) * DA.hscale[qh];
+    const int bin = !(x < (double)hb) ? hb + 1 : (x < 0.0 ? 0 : (int)x + 1);
+    unsigned long long* h = DA.hist + (size_t)qh * (HIST_MAX + 2);
+    // one atomic per distinct bin of the wave (a narrow distribution would
+    // otherwise send every sample to the same counter)
+    unsigned long long todo = __ballot(1);
+    while (todo) {
+      const int leader = __ffsll((long long)todo) - 1;
+      const int b = __shfl(bin, leader);
+      const unsigned long long same = __ballot(bin == b);
+      if ((tid & 63) == leader) atomicAdd(&h[b], (unsigned long long)__popcll(same));
+      todo &= ~same;
+    }
+  };
   for (int n = tid; n < L; n += DNT) {
     const c2 z0 = AV[n], z1 = AV[L + n];
     const double trc = z0.x + (d.dim == 2 ? 1.0 : 0.0);
-    if (hb > 0) {
-      const double u = (trc - DA.hlo) * DA.hscale;
-      const int bin = !(u < (double)hb) ? hb + 1 : (u < 0.0 ? 0 : (int)u + 1);
-      // one atomic per distinct bin of the wave (a narrow distribution would
-      // otherwise send every sample to the same counter)
-      unsigned long long todo = __ballot(1);
-      while (todo) {
-        const int leader = __ffsll((long long)todo) - 1;
-        const int b = __shfl(bin, leader);
-        const unsigned long long same = __ballot(bin == b);
-        if ((tid & 63) == leader) atomicAdd(&DA.hist[b], (unsigned long long)__popcll(same));
-        todo &= ~same;
-      }
-    }
     const double u = z0.y, v = z1.x, w = d.dim == 3 ? z1.y : 0.0;
+    if (midrow) {
+      bin_sample(0, trc);
+      bin_sample(1, u - um);
+      bin_sample(2, v);
+      bin_sample(3, w - wm);
+    }
     mn = fmin(mn, trc);
     n3 += (trc < 3.0);
     n0 += (trc < 0.0);

@@ -231,15 +231,18 @@ struct DRowArgs {
   const double* tw;
   const double* ydy;
   DiagPart* parts;
-  // midplane histogram of Tr c (hbins = 0: off): counts[0] below hlo,
-  // counts[1 + floor((v - hlo) hscale)] inside, counts[hbins + 1] at or above
-  // the top and non-finite values
+  // midplane histograms of quantity q = Tr c, u - U(0), v, w - W(0)
+  // (hbins[q] = 0: off), counts at hist + q (HIST_MAX + 2): [0] below hlo,
+  // [1 + floor((v - hlo) hscale)] inside, [hbins + 1] at or above the top and
+  // non-finite values; umean / wmean: the mean-mode u and w at the midplane
   unsigned long long* hist;
-  double hlo, hscale;
-  int hbins;
+  double hlo[4], hscale[4];
+  int hbins[4];
+  const double *umean, *wmean;
   int blk0;
 };
 constexpr int HIST_MAX = 4096;  // largest number of histogram bins
+constexpr int HIST_Q = 4;       // histogrammed midplane quantities
 struct DFinArgs {
   Dims d;
   Phys p;

@@ -115,3 +115,81 @@ def test_ensemble_member_histogram_equals_single_run(P):
     ref = sim.midplane_histogram()
     sim.close()
     assert np.array_equal(got, ref) and int(got.sum()) == 6 * 32
+
+
+@pytest.mark.parametrize("dims,precision,rel", [((2, 32, 33, 1), 0, 1e-11), ((3, 16, 17, 16), 0, 1e-11),
+                                                ((2, 32, 33, 1), 1, 2e-5)])
+def test_midplane_velocity_pdfs_match_oracle(P, dims, precision, rel):
+    """All four midplane histograms (Tr c, u - U(0), v, w - W(0)) in one run
+    against the oracle's samples, bin by bin up to samples within the two
+    sides' field difference of an edge (rel: the path's field tolerance
+    relative to each field's largest magnitude)."""
+    dim, nx, ny, nz = dims
+    g = Grid(dim, nx, ny, nz)
+    prm = dict(wi=20.0, dt=1e-3)
+    nsteps, seed, amp = 10, 7, 1e-2
+    o = Oracle(g, Params(**prm), seed=seed, amp=amp)
+    ref = {}
+    top = {}
+    for _ in range(nsteps):
+        o.step(1)
+        for k, v in stats.midplane_quantities(o).items():
+            ref.setdefault(k, []).append(v)
+        top[0] = max(top.get(0, 0.0), float(np.abs(o.trace_c()).max()))
+        top[1] = max(top.get(1, 0.0), float(np.abs(o.base_grid(o.q["u"])).max()))
+        top[2] = max(top.get(2, 0.0), float(np.abs(o.base_grid(o.q["v"])).max()))
+        if dim == 3:
+            top[3] = max(top.get(3, 0.0), float(np.abs(o.base_grid(o.q["w"])).max()))
+    ref = {k: np.concatenate(v) for k, v in ref.items()}
+    nb = 32
+    sim = P.Sim(P.make_grid(dim, nx, ny, nz), P.make_params(precision=precision, **prm), seed=seed, amp=amp)
+    ranges = {}
+    for k, v in ref.items():
+        vmin, vmax = float(v.min()), float(v.max())   # samples outside on both sides
+        ranges[k] = (vmin + 0.15 * (vmax - vmin), vmax - 0.15 * (vmax - vmin))
+        sim.midplane_pdf_setup(k, ranges[k][0], ranges[k][1], nb)
+    print("case midplane pdfs %s p%d" % (dims, precision), flush=True)
+    sim.step(nsteps)
+    got = {k: sim.midplane_pdf(k) for k in ref}
+    tr = sim.midplane_histogram()
+    sim.close()
+    assert np.array_equal(tr, got[0])
+    for k, v in ref.items():
+        lo, hi = ranges[k]
+        want = stats.histogram(v, lo, hi, nb)
+        assert int(got[k].sum()) == int(want.sum()) == nsteps * nx * (nz if dim == 3 else 1)
+        assert got[k][0] > 0 and got[k][nb + 1] > 0
+        u = (v - lo) * (nb / (hi - lo))
+        ties = int(np.count_nonzero(np.abs(u - np.round(u)) < rel * top[k] * nb / (hi - lo) + 1e-12))
+        diff = int(np.abs(got[k].astype(np.int64) - want.astype(np.int64)).sum())
+        print("quantity %d: L1 difference %d, samples near an edge %d" % (k, diff, ties), flush=True)
+        assert diff <= 2 * ties, (k, diff, ties)
+
+
+def test_midplane_pdf_arguments(P):
+    print("case midplane pdf arguments", flush=True)
+    sim = P.Sim(P.make_grid(2, 16, 17), P.make_params(), seed=1, amp=1e-3)
+    for q, lo, hi, nb in ((3, -1.0, 1.0, 8), (4, -1.0, 1.0, 8), (-1, -1.0, 1.0, 8), (1, 1.0, -1.0, 8),
+                          (2, -1.0, 1.0, P.PCS_HIST_MAX + 1)):
+        with pytest.raises(P.PcsError):
+            sim.midplane_pdf_setup(q, lo, hi, nb)
+    sim.midplane_pdf_setup(1, -1.0, 1.0, 8)
+    sim.step(3)
+    a = sim.midplane_pdf(1)
+    assert int(a.sum()) == 3 * 16
+    with pytest.raises(P.PcsError):       # quantity 2 is off
+        sim.midplane_pdf(2)
+    sim.midplane_pdf_setup(1, -1.0, 1.0, 8)   # setup clears the counts
+    assert int(sim.midplane_pdf(1).sum()) == 0
+    sim.close()
+    ens = P.Ensemble([P.make_grid(3, 16, 17, 16), P.make_grid(3, 16, 17, 16)], [P.make_params(), P.make_params()],
+                     [5, 6], amp=1e-2)
+    ens.midplane_pdf_setup(1, 3, -0.05, 0.05, 16)
+    single = P.Sim(P.make_grid(3, 16, 17, 16), P.make_params(), seed=6, amp=1e-2)
+    single.midplane_pdf_setup(3, -0.05, 0.05, 16)
+    ens.step(4)
+    single.step(4)
+    assert int(ens.midplane_pdf(1, 3).sum()) == 4 * 16 * 16
+    assert np.abs(ens.midplane_pdf(1, 3).astype(np.int64) - single.midplane_pdf(3).astype(np.int64)).sum() <= 2
+    ens.close()
+    single.close()
