@@ -698,12 +698,17 @@ void build_jobs(Member* m) {
   auto d2 = [&](const double* src, double* dst) {
     g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], src, cw, dst, cw, nh, cw, nh, n1, n1, +1);
   };
-  d2(st + FPHI * fs, m->D2buf + 0 * fs);
-  if (d.dim == 3) d2(st + 4 * fs, m->D2buf + 1 * fs);
-  for (int a = 0; a < d.nc; ++a) d2(st + (FC + a) * fs, m->D2buf + (m->nsv + a) * fs);
+  // SBDF4 has no explicit half of the linear terms: of these it reads only
+  // D2 c_xy (and D2 c_yz in 3D), inside the stress divergence
+  const bool cn = m->p.scheme == 0;
+  auto stress_d2 = [&](int a) { return a == 1 || (d.dim == 3 && a == 4); };
+  if (cn) d2(st + FPHI * fs, m->D2buf + 0 * fs);
+  if (cn && d.dim == 3) d2(st + 4 * fs, m->D2buf + 1 * fs);
+  for (int a = 0; a < d.nc; ++a)
+    if (cn || stress_d2(a)) d2(st + (FC + a) * fs, m->D2buf + (m->nsv + a) * fs);
   double* D2U = m->D2buf + (size_t)m->nsolve * fs;
-  g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], st + 0 * fs, cw, D2U, 1, nh, 1, nh, n1, n1, +1);
-  if (d.dim == 3)
+  if (cn) g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], st + 0 * fs, cw, D2U, 1, nh, 1, nh, n1, n1, +1);
+  if (cn && d.dim == 3)
     g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], st + 2 * fs, cw, D2U + n1, 1, nh, 1, nh, n1, n1, +1);
   for (int a = 0; a < d.nc; ++a)
     g1b.addp(PAR_FOLD_UNFOLD, m->D, m->Dp[0], m->Dp[1], st + (FC + a) * fs, cw, m->Dc + a * fs, cw, nh, cw, nh, n1, n1,
