@@ -1,0 +1,75 @@
+"""The 3D workloads at their full sizes, in the launch configuration the
+benchmark times (an 8-step graph replay):
+  * 3D 128 x 129 x 64 (Wi = 50, dt = 5e-4, seed 3): eight steps against the
+    FP64 oracle, element by element, in FP64 (step tolerances) and in mixed
+    precision (the mixed bar);
+  * 3D 256 x 257 x 128 (Wi = 100, dt = 2.5e-4, seed 5), too large for the
+    oracle within a test: properties that hold at any size.  The laminar
+    state stays steady to FP64 roundoff in both precisions, and the mixed
+    path agrees with the FP64 path (itself held to the oracle at every
+    smaller size) to the mixed bar after eight steps."""
+
+import numpy as np
+import pytest
+
+from oracle import Grid, Oracle, Params, state_layout
+from paper_2606_09468_amd.workloads import WORKLOADS
+from tests.test_gpu_parity import P, check_state, fluct_errors, tol_history, tol_prognostic  # noqa: F401
+
+pytestmark = pytest.mark.gpu
+
+
+def run(P, w, precision, seed, amp, nsteps):
+    sim = P.Sim(P.make_grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"]),
+                P.make_params(wi=w["wi"], dt=w["dt"], precision=precision), seed=seed, amp=amp)
+    s0 = sim.get_state()
+    sim.step(nsteps)
+    recs, st = sim.diagnostics()
+    s1 = sim.get_state()
+    sim.close()
+    assert st == P.PCS_OK and len(recs) == nsteps and recs[-1]["blowup"] == 0
+    return s0, s1, recs
+
+
+def test_3d_128x129x64_matches_oracle(P):
+    w = WORKLOADS["c3"]
+    g = Grid(3, w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
+    n = 8
+    print("case full size 3D 128x129x64: oracle %d steps" % n, flush=True)
+    o = Oracle(g, Params(wi=w["wi"], dt=w["dt"]), seed=w["seed"], amp=1e-3)
+    o.step(n)
+    ref = o.get_state()
+    print("oracle done", flush=True)
+    _, a, recs = run(P, w, 0, w["seed"], 1e-3, n)
+    N = g.ny - 1
+    check_state(a, ref, g, tol_prognostic(N), tol_history(N), "full size 3D 128x129x64 FP64")
+    d, e = recs[-1], o.diag[-1]
+    for k in ("energy", "mean_trc", "dpdx"):
+        assert abs(d[k] - e[k]) <= 1e-11 * max(1.0, abs(e[k])), (k, d[k], e[k])
+    _, b, _ = run(P, w, 1, w["seed"], 1e-3, n)
+    errs = fluct_errors(b, ref, g)
+    names = state_layout(g)[1][:11]
+    print("mixed", " ".join("%s=%.1e/%.1e" % (k, v[0], v[1]) for k, v in errs.items() if k in names), flush=True)
+    for k in names:
+        assert errs[k][0] <= 2e-4 and errs[k][1] <= 2e-5, (k, errs[k])
+
+
+def test_3d_256x257x128_properties(P):
+    w = WORKLOADS["c5"]
+    g = Grid(3, w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
+    n = 8
+    for precision in (0, 1):
+        print("case full size 3D 256x257x128 laminar p%d" % precision, flush=True)
+        s0, s1, _ = run(P, w, precision, w["seed"], 0.0, n)
+        assert np.abs(s1[4:] - s0[4:]).max() / np.abs(s0[4:]).max() < 1e-11
+    print("case full size 3D 256x257x128 mixed vs FP64", flush=True)
+    _, a, ra = run(P, w, 0, w["seed"], 1e-3, n)
+    _, b, rb = run(P, w, 1, w["seed"], 1e-3, n)
+    errs = fluct_errors(b, a, g)
+    names = state_layout(g)[1][:11]
+    print("mixed vs fp64", " ".join("%s=%.1e/%.1e" % (k, v[0], v[1]) for k, v in errs.items() if k in names),
+          flush=True)
+    for k in names:
+        assert errs[k][0] <= 2e-4 and errs[k][1] <= 2e-5, (k, errs[k])
+    for k in ("energy", "mean_trc", "dpdx"):
+        assert abs(ra[-1][k] - rb[-1][k]) <= 1e-8 * max(1.0, abs(ra[-1][k])), (k, ra[-1][k], rb[-1][k])
