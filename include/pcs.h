@@ -65,8 +65,9 @@ typedef struct {
  *  precision = 0: every stage in FP64.
  *  precision = 1: mixed: transforms and pointwise products of the
  *               fluctuation (all modes except kx = kz = 0) in FP32, the
- *               mean-mode profiles and every boundary-value solve in FP64;
- *               eps must be 0.
+ *               mean-mode profiles and every boundary-value solve in FP64
+ *               (the sPTT eps term is split the same way: fluctuation part
+ *               in FP32, product of the mean profiles in FP64).
  *  precision = 2: as 1, but the wall-normal transforms of the fluctuation
  *               (to and from the padded grid) are computed in FP64 and
  *               only the periodic transforms and products in FP32.

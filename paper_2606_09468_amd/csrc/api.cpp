@@ -440,7 +440,6 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   if (p->forcing != 0 && p->forcing != 1) return PCS_ERR_ARG;
   if (p->precision < 0 || p->precision > 2) return PCS_ERR_ARG;
   if (p->scheme != 0 && p->scheme != 1) return PCS_ERR_ARG;
-  if (p->precision != 0 && p->eps != 0.0) return PCS_ERR_UNSUPPORTED;  // the mixed split is for bilinear products
   if (!valid_fft(3 * g->nx / 2) || !valid_fft(g->nx)) return PCS_ERR_UNSUPPORTED;
   if (g->dim == 3 && (!valid_fft(3 * g->nz / 2) || !valid_fft(g->nz))) return PCS_ERR_UNSUPPORTED;
   m->g = *g;
@@ -1047,6 +1046,7 @@ void build_batch(Batch* b) {
       zf.deriv = nullptr;
       zf.mean = m->Ybar;
       zf.mcol = m->mcol;
+      zf.eps_wi = m->p.eps / m->p.wi;
       zf.blk0 = b->bzf;
       b->bzf += zfft_blocks(d.nkx, m1, m->nout);
       b->lzf = std::max(b->lzf, zfft_lds_bytes(d.pz, m->prec));

@@ -488,23 +488,31 @@ __host__ __device__ constexpr int n_means(int dim) { return dim == 2 ? 8 : 16; }
 // Product of the mean profiles in explicit term o at padded row i, FP64.  For
 // profiles only the y-derivatives of the mean velocity (U', W') survive
 // (v = 0, d/dx = d/dz = 0), so N = 0 and F_ab = U'_a c_yb + c_ay U'_b with
-// U'_x = U', U'_z = W'.
-__device__ inline double mean_product(int dim, int o, gptr<const double> mean, int m1, int i) {
+// U'_x = U', U'_z = W', less the sPTT term (eps/Wi) Tr(c - I)(c_ab - delta_ab)
+// of the mean profiles.
+__device__ inline double mean_product(int dim, int o, gptr<const double> mean, int m1, int i, double eps_wi) {
   auto M = [&](int k) { return mean[(size_t)k * m1 + i]; };
   if (dim == 2) {
-    // means: U U' cxx cxy cyy ...; outputs: Nx Ny Fxx Fxy Fyy
-    if (o == 2) return 2.0 * M(1) * M(3);
-    if (o == 3) return M(1) * M(4);
-    return 0.0;
+    // means: U U' cxx cxy cyy ...; outputs: Nx Ny Fxx Fxy Fyy (c_zz = 1)
+    if (o < 2) return 0.0;
+    const double tr = M(2) + M(4) - 2.0, cab = o == 3 ? M(3) : M(o) - 1.0;
+    const double s = eps_wi != 0.0 ? eps_wi * tr * cab : 0.0;
+    if (o == 2) return 2.0 * M(1) * M(3) - s;
+    if (o == 3) return M(1) * M(4) - s;
+    return -s;
   }
   // means: U W U' W' cxx cxy cxz cyy cyz czz ...; outputs: Nx Ny Nz Fxx Fxy Fxz Fyy Fyz Fzz
+  if (o < 3) return 0.0;
   const double Up = M(2), Wp = M(3);
-  if (o == 3) return 2.0 * Up * M(5);
-  if (o == 4) return Up * M(7);
-  if (o == 5) return Up * M(8) + M(5) * Wp;
-  if (o == 7) return Wp * M(7);
-  if (o == 8) return 2.0 * Wp * M(8);
-  return 0.0;
+  const double tr = M(4) + M(7) + M(9) - 3.0;
+  const double cab = M(o + 1) - ((o == 3 || o == 6 || o == 8) ? 1.0 : 0.0);
+  const double s = eps_wi != 0.0 ? eps_wi * tr * cab : 0.0;
+  if (o == 3) return 2.0 * Up * M(5) - s;
+  if (o == 4) return Up * M(7) - s;
+  if (o == 5) return Up * M(8) + M(5) * Wp - s;
+  if (o == 7) return Wp * M(7) - s;
+  if (o == 8) return 2.0 * Wp * M(8) - s;
+  return -s;
 }
 
 template <typename T>
@@ -518,10 +526,12 @@ __device__ inline T fprod(MF<T> a, MF<T> b) {
   return (a.m + a.f) * b.f + a.f * b.m;
 }
 
-// Fluctuation-containing part of the products of eqs. (1)-(2) (eps = 0);
-// r(f), m(f): fluctuation and mean of real field f at the point.
+// Fluctuation-containing part of the products of eqs. (1)-(2); r(f), m(f):
+// fluctuation and mean of real field f at the point.  The sPTT term is
+// bilinear in c - I: with T = Tr(c - I) and C = c_ab - delta_ab split the same
+// way, its fluctuation part is (eps/Wi) [(Tbar + T') C' + T' Cbar].
 template <int DIM, typename T, typename Rd, typename Md>
-__device__ inline void pointwise_mixed(const Rd& r, const Md& m, T* o) {
+__device__ inline void pointwise_mixed(const Rd& r, const Md& m, T* o, T eps_wi) {
   auto F = [&](int f) -> MF<T> { return MF<T>{m(f), r(f)}; };
   auto neg = [](MF<T> a) -> MF<T> { return MF<T>{-a.m, -a.f}; };
   auto du = [&](int k, int a) -> MF<T> {
@@ -555,6 +565,16 @@ __device__ inline void pointwise_mixed(const Rd& r, const Md& m, T* o) {
       T f = 0;
 #pragma unroll
       for (int k = 0; k < DIM; ++k) f += -fprod(F(k), dc(k, q)) + fprod(du(k, a), c(k, b)) + fprod(c(a, k), du(k, b));
+      if (eps_wi != T(0)) {
+        T tm = T(DIM == 2 ? -2 : -3), tf = 0;  // Tr(c - I) (2D: c_zz = 1)
+#pragma unroll
+        for (int e = 0; e < DIM; ++e) {
+          tm += c(e, e).m;
+          tf += c(e, e).f;
+        }
+        const MF<T> cab = c(a, b);
+        f -= eps_wi * fprod(MF<T>{tm, tf}, MF<T>{cab.m - T(a == b ? 1 : 0), cab.f});
+      }
       o[DIM + q] = f;
       ++q;
     }
@@ -663,7 +683,7 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
     };
     if constexpr (MIXED) {
       auto md = [&](int f) -> T { return mean_of(DIM, f) >= 0 ? mrow[mean_of(DIM, f)] : T(0); };
-      pointwise_mixed<DIM, T>(rd, md, o);
+      pointwise_mixed<DIM, T>(rd, md, o, T(eps_wi));
     } else {
       pointwise<DIM>(rd, o, eps_wi);
     }
@@ -690,8 +710,9 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
         if constexpr (MIXED && DIM == 2) {
           // the kx = 0 column is the whole mean (2D has no z): complete it in FP64
           if (k == 0) {
-            mcol[(size_t)fa * m1 + row] = double(A.x * inv) + mean_product(2, fa, mean, m1, row);
-            if (fb < XS::NOUT) mcol[(size_t)fb * m1 + row] = double(B.x * inv) + mean_product(2, fb, mean, m1, row);
+            mcol[(size_t)fa * m1 + row] = double(A.x * inv) + mean_product(2, fa, mean, m1, row, eps_wi);
+            if (fb < XS::NOUT)
+              mcol[(size_t)fb * m1 + row] = double(B.x * inv) + mean_product(2, fb, mean, m1, row, eps_wi);
           }
         }
       }
@@ -851,7 +872,7 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
       *reinterpret_cast<gptr<T2>>(ob + ((size_t)s * nkx + k0 + g) * 2) = T2{v.x, v.y};
       // mixed forward transform: the kx = kz = 0 value completed in FP64
       if (mcol && s == 0 && k0 + g == 0)
-        mcol[(size_t)f * rows_y + i] = double(v.x) + mean_product(3, f, mean, rows_y, i);
+        mcol[(size_t)f * rows_y + i] = double(v.x) + mean_product(3, f, mean, rows_y, i, ZA.eps_wi);
     }
   }
 }

@@ -218,6 +218,7 @@ struct ZArgs {
   const void* tw;
   const double* mean;
   double* mcol;
+  double eps_wi;  // sPTT eps / Wi: its mean product enters the FP64 mean column
   int blk0;
 };
 // diagnostics (fft.hip): per (y_j, z) line of the base grid, from the

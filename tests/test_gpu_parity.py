@@ -436,12 +436,40 @@ def test_mixed_keeps_laminar_state_exact(P, precision):
         assert np.abs(s1[4:] - s0[4:]).max() / np.abs(s0[4:]).max() < 1e-11
 
 
-def test_mixed_rejects_eps(P):
-    import ctypes
-    g = P.make_grid(2, 16, 17)
-    p = P.make_params(eps=1e-3, precision=1)
-    n = ctypes.c_size_t(0)
-    assert P.lib().pcs_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(n)) == P.PCS_ERR_UNSUPPORTED
+@pytest.mark.parametrize("precision", [1, 2])
+@pytest.mark.parametrize("case", [("2D 64x65 eps 0.05 x40", Grid(2, 64, 65), 40),
+                                  ("3D 16x33x16 eps 0.05 x20", Grid(3, 16, 33, 16), 20)], ids=["2D", "3D"])
+def test_mixed_precision_sptt_against_fp64_oracle(P, case, precision):
+    """The sPTT term (eq. (1), eps > 0) in mixed precision: its fluctuation
+    part in FP32 ((Tbar + T') C' + T' Cbar with T = Tr(c - I), C = c - I) and
+    the mean-profile product in the FP64 mean column, held to the mixed bar
+    against the FP64 oracle.  eps = 0.05 makes the term a visible part of F."""
+    name, g, n = case
+    prm = dict(wi=20.0, dt=1e-3, eps=0.05)
+    print("case mixed sptt p%d %s" % (precision, name), flush=True)
+    sim = P.Sim(P.make_grid(g.dim, g.nx, g.ny, g.nz, g.lx, g.lz), P.make_params(precision=precision, **prm),
+                seed=4, amp=1e-2)
+    sim.step(n)
+    a = sim.get_state()
+    recs, st = sim.diagnostics()
+    sim.close()
+    o = Oracle(g, Params(**prm), seed=4, amp=1e-2)
+    o.step(n)
+    b = o.get_state()
+    errs = fluct_errors(a, b, g)
+    nq = 6 if g.dim == 2 else 11
+    names = state_layout(g)[1][:nq]
+    print(name, " ".join("%s=%.1e/%.1e" % (k, v[0], v[1]) for k, v in errs.items() if k in names), flush=True)
+    for k in names:
+        assert errs[k][0] <= 2e-4 and errs[k][1] <= 2e-5, (k, errs[k])
+    # the term matters: without it the laminar mean c_xx differs at the 1e-2 level
+    o0 = Oracle(g, Params(wi=20.0, dt=1e-3), seed=4, amp=1e-2)
+    o0.step(n)
+    hdr, _, per = state_layout(g)
+    ic = names.index("cxx")
+    x = b[hdr + ic * 2 * per: hdr + (ic + 1) * 2 * per]
+    y = o0.get_state()[hdr + ic * 2 * per: hdr + (ic + 1) * 2 * per]
+    assert np.abs(x - y).max() / np.abs(y).max() > 1e3 * errs["cxx"][1]
 
 
 @pytest.mark.parametrize("a,b", [((2, 16, 17, 1), (2, 32, 33, 1)), ((2, 32, 33, 1), (2, 16, 17, 1)),
