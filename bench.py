@@ -190,7 +190,7 @@ def main():
     args = ap.parse_args()
     args.scheme_id = 1 if args.scheme == "sbdf4" else 0
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path (each run, or each ensemble "
+        print("bench.py measures one GPU only: the library has no multi-GPU path (each run, or each ensemble "
               "member, would be sharded across GPUs without communication); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
