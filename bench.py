@@ -125,7 +125,8 @@ def traffic_for(kernel, workload, precision):
     digest = hashlib.sha256(src).hexdigest()[:16]
     for line in open(path):
         parts = [x.strip() for x in line.strip().strip("|").split("|")]
-        if len(parts) >= 6 and parts[0] == kernel and parts[1] == workload and parts[2] == str(precision):
+        pname = {0: "fp64", 1: "mixed", 2: "mixed64y"}.get(precision, str(precision))
+        if len(parts) >= 6 and parts[0] == kernel and parts[1] == workload and parts[2] == pname:
             if parts[5] != digest:
                 return None
             return float(parts[3]) + float(parts[4])
