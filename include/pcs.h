@@ -142,7 +142,9 @@ pcs_status pcs_state_size(struct pcs_sim* sim, size_t* n);
  *   first group, for q^{n-1}, q^{n-2}, q^{n-3} in turn) and the explicit
  *   terms of steps n-2 and n-3 (every field of the second group, twice).  */
 pcs_status pcs_get_state(struct pcs_sim* sim, double* host, size_t n);
-/* Replaces the state (same layout) and clears the blow-up flag.  An SBDF4
+/* Replaces the state (same layout) and clears the blow-up flag.  The header's
+ * step must be a whole number in [0, 2^53] and t, Pi finite (PCS_ERR_ARG
+ * otherwise, the run unchanged).  An SBDF4
  * run also takes the CNAB2 layout (n of a CNAB2 run on the same grid): the
  * earlier states and explicit terms are then a constant past, q^{n-k} := q^n
  * and X^{n-k} := X^{n-1} (for instance after pcs_resample_state). */
@@ -153,8 +155,9 @@ pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
  * handle's stream between stages, and returns in ms[i] the mean duration of
  * one launch of stage i.  Every stage is one kernel launch: the products
  * (gemm_*), the z and x transforms, the RHS, finalize and diagnostics
- * kernels.  Each stage except the last (the step record) is launched reps
- * times back to back between its two events (these stages recompute the
+ * kernels.  Each stage except the row diagnostics (which also add the
+ * step's midplane samples to the histograms) and the step record is launched
+ * reps times back to back between its two events (these stages recompute the
  * same outputs from unchanged inputs), so that with reps > 1 the GPU does
  * not wait for the host between launches and ms[i] approaches the kernel's
  * own duration.  nstage must be at least PCS_NSTAGE; stages that do not

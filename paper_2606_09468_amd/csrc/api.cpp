@@ -1248,11 +1248,17 @@ void enqueue_diagnostics(Batch* b, hipStream_t t) {
 // only have to finish before this step overwrites the state (the products
 // of the solves write c, finalize the rest and the diagnostics inputs).
 // ev: four events.  The launches and their order within each chain are those
-// of enqueue_step.
+// of enqueue_step.  The step record (diag_final) advances the device step
+// counter, and the SBDF4 right-hand sides index the history rings with it:
+// with any SBDF4 run in the batch, the right-hand sides therefore wait for
+// the previous step's diagnostics branch (CNAB2 reads no counter there and
+// waits only before the state is overwritten).
 void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
   hipStream_t s = b->s, s1 = b->side[0], s2 = b->side[1];
   const int nm = (int)b->mem.size();
   const bool prod = b->branch == 1;
+  bool ring = false;
+  for (const Member* m : b->mem) ring |= m->p.scheme == 1;
   (void)hipEventRecord(ev[0], s);  // the previous step's state is complete
   if (prod) {
     (void)hipStreamWaitEvent(s1, ev[0], 0);
@@ -1273,9 +1279,10 @@ void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
   if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
   b->GP.run(s);
   if (prod) (void)hipStreamWaitEvent(s, ev[2], 0);
+  if (diag_prev && ring) (void)hipStreamWaitEvent(s, ev[3], 0);
   launch_rhs(b->drhs, nm, b->brhs, s);
   b->G4.run(s);
-  if (diag_prev) (void)hipStreamWaitEvent(s, ev[3], 0);
+  if (diag_prev && !ring) (void)hipStreamWaitEvent(s, ev[3], 0);
   b->G5.run(s);
   launch_finalize(b->dfin, nm, b->bfin, s);
 }
@@ -1735,6 +1742,8 @@ pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
   if (n != sim->m()->nstate && !short_form) return PCS_ERR_ARG;
   for (size_t i = 0; i < 3; ++i)
     if (!std::isfinite(host[i])) return PCS_ERR_ARG;
+  // the step index selects ring slots on the device: a whole number in [0, 2^53]
+  if (!(host[0] >= 0.0 && host[0] <= 9007199254740992.0) || host[0] != std::floor(host[0])) return PCS_ERR_ARG;
   Member* m = sim->m();
   hipStream_t s = sim->b.s;
   DevScalars sc{};
@@ -1788,9 +1797,11 @@ pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* m
   std::vector<double> acc(ST_COUNT, 0.0);
   pcs_status st = PCS_OK;
   for (int k = 0; k < nsteps && st == PCS_OK; ++k) {
+    // the row diagnostics also add the step's midplane samples to the
+    // histograms, so they run once per step like the step record
     enqueue_step(b, [&](int i) {
       (void)hipEventRecord(ev[i], b->s);
-      return i == ST_DIAG_FINAL ? 1 : (int)reps;
+      return (i == ST_DIAG_FINAL || i == ST_DIAG_ROWS) ? 1 : (int)reps;
     });
     if (hipEventSynchronize(ev[ST_COUNT]) != hipSuccess) {
       st = PCS_ERR_DEVICE;
@@ -1799,7 +1810,7 @@ pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* m
     for (int i = 0; i < ST_COUNT; ++i) {
       float t = 0;
       if (hipEventElapsedTime(&t, ev[i], ev[i + 1]) != hipSuccess) st = PCS_ERR_DEVICE;
-      acc[i] += t / (i == ST_DIAG_FINAL ? 1 : reps);
+      acc[i] += t / ((i == ST_DIAG_FINAL || i == ST_DIAG_ROWS) ? 1 : reps);
     }
   }
   for (int i = 0; i <= ST_COUNT; ++i) (void)hipEventDestroy(ev[i]);

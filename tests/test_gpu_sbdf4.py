@@ -213,3 +213,30 @@ def test_sbdf4_takes_cnab2_state_with_constant_past(P):
             s3.set_state(short[:-2])
         finally:
             s3.close()
+
+
+@pytest.mark.parametrize("dims,precision", [((2, 24, 25, 1), 0), ((3, 16, 17, 16), 0), ((3, 16, 17, 16), 1)])
+def test_sbdf4_branched_graphs_match_single_chain(P, dims, precision, monkeypatch):
+    """SBDF4 indexes its history rings with the device step counter that the
+    step record advances; in the branched graphs that record runs on a side
+    branch beside the next step.  States and records over 20 steps (two
+    8-step graphs, four 1-step ones) must be bitwise those of the single
+    chain, with the product tiles forced so the tables agree."""
+    monkeypatch.setenv("PCS_GEMM_CFG", "4")
+    monkeypatch.setenv("PCS_PRODUCT_FORM", "parity")
+    out = []
+    for br in ("0", "1", "2"):
+        monkeypatch.setenv("PCS_GRAPH_BRANCHES", br)
+        print("case sbdf4 branches=%s %s p%d" % (br, dims, precision), flush=True)
+        sim = P.Sim(P.make_grid(*dims), P.make_params(wi=20.0, dt=1e-3, precision=precision, scheme=1),
+                    seed=4, amp=1e-3)
+        sim.step(20)
+        recs, st = sim.diagnostics()
+        assert st == P.PCS_OK and len(recs) == 20
+        out.append((sim.get_state(), recs))
+        sim.close()
+    a, ra = out[0]
+    for b, rb in out[1:]:
+        assert np.array_equal(a, b)
+        for x, y in zip(ra, rb):
+            assert x == y, (x, y)
