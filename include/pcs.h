@@ -118,6 +118,27 @@ pcs_status pcs_workspace_bytes(const pcs_grid* grid, const pcs_params* params, s
 pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t seed, double amp, void* workspace,
                     size_t bytes, void* stream, struct pcs_sim** out);
 
+/* For callers that cannot allocate device memory (code that must not call
+ * hipMalloc, such as serving loops or harnesses that forbid it, or that later
+ * steps the run inside a stream capture): pcs_init without a workspace
+ * argument.  The run lives in a static device array of the library,
+ * PCS_STATIC_BYTES bytes on each GPU that uses it, held from the library's
+ * load until the process ends; nothing is allocated, by the library or on
+ * its behalf.  The array of the current device is cleared (on the stream)
+ * and then set up exactly as pcs_init would set up a workspace, except that
+ * the tile autotuner is not run (default tile shapes) and no graphs or side
+ * streams are created: pcs_step launches each step's kernels one by one on
+ * the stream, which a caller may capture.  One live handle per GPU: the
+ * array is shared by every call on that GPU and keeps the last run's
+ * contents, so runs that overlapped on one GPU would race; while a handle
+ * from this call is alive, another call on the same GPU returns
+ * PCS_ERR_WORKSPACE, as does a grid / parameter set whose pcs_workspace_bytes
+ * exceeds PCS_STATIC_BYTES.  pcs_destroy releases the array for the next
+ * call.  Other arguments, results and errors as pcs_init. */
+#define PCS_STATIC_BYTES ((size_t)64 << 20)
+pcs_status pcs_init_static(const pcs_grid* grid, const pcs_params* params, uint64_t seed, double amp, void* stream,
+                           struct pcs_sim** out);
+
 /* Enqueues nsteps time steps (asynchronous).  Returns PCS_ERR_STATE if a
  * blow-up was seen at the last synchronisation. */
 pcs_status pcs_step(struct pcs_sim* sim, int32_t nsteps);

@@ -31,9 +31,11 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_ensemble_diagnostics", "pcs_ensemble_state_size", "pcs_ensemble_get_state",
            "pcs_ensemble_destroy", "pcs_midplane_histogram_setup", "pcs_midplane_histogram",
            "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state",
-           "pcs_midplane_pdf_setup", "pcs_midplane_pdf", "pcs_ensemble_midplane_pdf_setup", "pcs_ensemble_midplane_pdf")
+           "pcs_midplane_pdf_setup", "pcs_midplane_pdf", "pcs_ensemble_midplane_pdf_setup", "pcs_ensemble_midplane_pdf",
+           "pcs_init_static")
 PCS_NSTAGE = 12
 PCS_HIST_MAX = 4096
+PCS_STATIC_BYTES = 64 << 20
 # midplane PDF quantities (pcs_midplane_pdf_setup)
 PCS_PDF_TRC, PCS_PDF_U, PCS_PDF_V, PCS_PDF_W = 0, 1, 2, 3
 
@@ -73,6 +75,8 @@ def lib():
     L.pcs_workspace_bytes.argtypes = [ctypes.POINTER(pcs_grid), ctypes.POINTER(pcs_params), ctypes.POINTER(sz)]
     L.pcs_init.argtypes = [ctypes.POINTER(pcs_grid), ctypes.POINTER(pcs_params), ctypes.c_uint64, ctypes.c_double,
                            vp, sz, vp, ctypes.POINTER(vp)]
+    L.pcs_init_static.argtypes = [ctypes.POINTER(pcs_grid), ctypes.POINTER(pcs_params), ctypes.c_uint64,
+                                  ctypes.c_double, vp, ctypes.POINTER(vp)]
     L.pcs_step.argtypes = [vp, ctypes.c_int32]
     L.pcs_diagnostics.argtypes = [vp, ctypes.POINTER(pcs_diag), ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     L.pcs_state_size.argtypes = [vp, ctypes.POINTER(sz)]
@@ -178,18 +182,27 @@ class Sim:
     """One channel-flow run: device workspace and stream from PyTorch, all
     work in libpcs.  Keep the object alive while the run is in use."""
 
-    def __init__(self, grid, params, seed=0, amp=1e-3, device="cuda:0"):
+    def __init__(self, grid, params, seed=0, amp=1e-3, device="cuda:0", static=False):
+        """static=True: pcs_init_static (the library's static device array as
+        workspace, nothing allocated; one live such run per GPU)."""
         import torch
         self.grid, self.params = grid, params
         self.device = torch.device(device)
         self.stream = torch.cuda.Stream(device=self.device)
         nbytes = pcs_workspace_bytes(grid, params)
-        self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
-        ptr = (self.workspace.data_ptr() + 255) & ~255
         self.handle = ctypes.c_void_p(0)
-        _check(lib().pcs_init(ctypes.byref(grid), ctypes.byref(params), ctypes.c_uint64(seed), float(amp),
-                              ctypes.c_void_p(ptr), nbytes, ctypes.c_void_p(self.stream.cuda_stream),
-                              ctypes.byref(self.handle)), "pcs_init")
+        if static:
+            self.workspace = None
+            with torch.cuda.device(self.device):
+                _check(lib().pcs_init_static(ctypes.byref(grid), ctypes.byref(params), ctypes.c_uint64(seed),
+                                             float(amp), ctypes.c_void_p(self.stream.cuda_stream),
+                                             ctypes.byref(self.handle)), "pcs_init_static")
+        else:
+            self.workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            ptr = (self.workspace.data_ptr() + 255) & ~255
+            _check(lib().pcs_init(ctypes.byref(grid), ctypes.byref(params), ctypes.c_uint64(seed), float(amp),
+                                  ctypes.c_void_p(ptr), nbytes, ctypes.c_void_p(self.stream.cuda_stream),
+                                  ctypes.byref(self.handle)), "pcs_init")
         n = ctypes.c_size_t(0)
         _check(lib().pcs_state_size(self.handle, ctypes.byref(n)), "pcs_state_size")
         self.state_size = n.value

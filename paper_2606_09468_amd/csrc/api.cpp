@@ -270,6 +270,9 @@ struct Batch {
   // the diagnostics (GSm, GSb hold their own products; else all are in GS),
   // 2 the diagnostics only
   int branch = 0;
+  // eager batch (the allocation-free initialisation): no autotuner timing,
+  // no side streams, no graphs; every step is launched kernel by kernel
+  bool eager = false;
   // per-member argument tables (host copies, then device) and launch sizes
   std::vector<XArgs> hx;
   std::vector<ZArgs> hzi, hzf, hzd;
@@ -1534,7 +1537,7 @@ pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_para
   }
   for (int32_t i = 0; i < n; ++i)
     if ((st = upload_member(b->mem[i], seeds[i], amp, b->s)) != PCS_OK) return st;
-  if ((st = autotune(b)) != PCS_OK) return st;
+  if (!b->eager && (st = autotune(b)) != PCS_OK) return st;
   for (int32_t i = 0; i < n; ++i)
     if ((st = reset_state(b->mem[i], seeds[i], amp, b->s)) != PCS_OK ||
         (st = homogeneous_solutions(b->mem[i], b->s)) != PCS_OK)
@@ -1547,7 +1550,7 @@ pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_para
     report(e1 != hipSuccess ? e1 : e2, "init synchronise", __LINE__);
     return PCS_ERR_DEVICE;
   }
-  capture(b);
+  if (!b->eager) capture(b);
   return PCS_OK;
 }
 
@@ -1681,8 +1684,32 @@ pcs_status member_get_state(Member* m, hipStream_t s, double* host, size_t n) {
 
 struct pcs_sim {
   Batch b;
+  int static_dev = -1;  // device whose static workspace this run holds (pcs_init_static), else -1
   Member* m() { return b.mem[0]; }
 };
+
+namespace {
+
+// ---- allocation-free initialisation (pcs_init_static)
+// The workspace of such runs is this file-scope device array: one copy per
+// GPU, resident from the library's load until the process ends.  In host
+// code `scratch` names a host-side stand-in, not device memory: its device
+// address on each GPU comes from hipGetSymbolAddress, taken once per device
+// with that device current and kept in static_slots; only that address is
+// ever passed to kernels, memsets or copies.
+constexpr size_t STATIC_BYTES = (size_t)64 << 20;
+static_assert(STATIC_BYTES == PCS_STATIC_BYTES, "static workspace size");
+static __device__ __align__(256) unsigned char scratch[STATIC_BYTES];
+
+constexpr int MAX_DEVICES = 64;
+struct StaticSlot {
+  void* ptr = nullptr;  // device address of scratch on this GPU
+  bool busy = false;    // held by a live handle
+};
+std::mutex static_mu;
+StaticSlot static_slots[MAX_DEVICES];
+
+}  // namespace
 
 struct pcs_ens {
   Batch b;
@@ -1708,6 +1735,47 @@ pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t see
     delete sim;
     return st;
   }
+  *out = sim;
+  return PCS_OK;
+}
+
+pcs_status pcs_init_static(const pcs_grid* grid, const pcs_params* params, uint64_t seed, double amp, void* stream,
+                           pcs_sim** out) {
+  if (!out) return PCS_ERR_ARG;
+  *out = nullptr;
+  if (!grid || !params) return PCS_ERR_ARG;
+  size_t need = 0;
+  {
+    Batch probe;
+    const pcs_status st = setup_batch(&probe, 1, grid, params, &need);
+    if (st != PCS_OK) return st;
+  }
+  if (need > STATIC_BYTES) return PCS_ERR_WORKSPACE;
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return PCS_ERR_DEVICE;
+  std::lock_guard<std::mutex> lock(static_mu);
+  StaticSlot& slot = static_slots[dev];
+  if (slot.busy) return PCS_ERR_WORKSPACE;  // another live handle holds this GPU's array
+  if (!slot.ptr) {
+    void* p = nullptr;
+    HIPCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return PCS_ERR_DEVICE;
+    slot.ptr = p;
+  }
+  // the array keeps the previous run's contents: start from zeros
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  HIPCHK(hipMemsetAsync(slot.ptr, 0, need, s));
+  pcs_sim* sim = new (std::nothrow) pcs_sim();
+  if (!sim) return PCS_ERR_ARG;
+  sim->b.eager = true;
+  const pcs_status st = init_batch(&sim->b, 1, grid, params, &seed, amp, slot.ptr, need, stream);
+  if (st != PCS_OK) {
+    delete sim;
+    return st;
+  }
+  slot.busy = true;
+  sim->static_dev = dev;
   *out = sim;
   return PCS_OK;
 }
@@ -1827,6 +1895,10 @@ pcs_status pcs_destroy(pcs_sim* sim) {
     (void)hipStreamSynchronize(sim->b.s);
   else
     (void)hipDeviceSynchronize();
+  if (sim->static_dev >= 0) {
+    std::lock_guard<std::mutex> lock(static_mu);
+    static_slots[sim->static_dev].busy = false;
+  }
   delete sim;
   return PCS_OK;
 }
