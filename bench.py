@@ -1,12 +1,19 @@
 #!/usr/bin/env python3
 """Throughput of the polymer channel-flow step on one MI355X.
 
-Workload (default): 2D channel, Oldroyd-B, Lx = 10, Nx = 256 Fourier points,
-Ny = 257 Chebyshev points, Re = 0.01, Wi = 50, beta = 0.8, kappa = 5e-5,
-constant flux, CNAB2 with dt = 5e-4; laminar state plus the seeded
-perturbation (seed 2, amplitude 1e-3).  A step is one full time step
-(explicit products, solves and the per-step diagnostics), replayed as one
-HIP graph.  Prints one JSON line.
+Workload (default): the largest single-GPU workload, a 3D channel, Oldroyd-B,
+Lx = 10, Lz = 5, Nx = 256, Ny = 257 Chebyshev points, Nz = 128, Re = 0.01,
+Wi = 100, beta = 0.8, kappa = 5e-5, constant flux, CNAB2 with dt = 2.5e-4;
+laminar state plus the seeded perturbation (seed 5, amplitude 1e-3), all
+state resident in HBM.  A step is one full time step (explicit products,
+solves and the per-step diagnostics), replayed from HIP graphs.  The mixed
+precision step is the headline value, the FP64 step is timed beside it.
+
+The FP64 oracle is timed on one host thread in a child process started
+before anything touches the GPU (it runs while the GPU is timed): one
+warm-up step, then the timed sample; the GPU runs of both precisions are
+then compared with the oracle's state after those steps.  Prints one JSON
+line.
 """
 
 import argparse
@@ -26,7 +33,7 @@ MFMA_F32_TFS = 157.3
 from paper_2606_09468_amd.workloads import ENSEMBLE, WORKLOADS, ensemble_members  # noqa: E402
 
 
-def stage_work(w, precision):
+def stage_work(w, precision, split):
     """Algorithmic work of one launch of each stage kernel at this workload:
     {stage: (bound, amount, peak)}.  Products: ('mfma', flops summed over
     the table, peak of the compute precision), each wall-normal product in its
@@ -35,7 +42,9 @@ def stage_work(w, precision):
     2 (ne^2 + no^2) n with ne, no the even and odd eigenvector counts.  Transform and elementwise
     kernels: ('hbm', bytes), every input field read once and every output
     written once, complex values of the kernel's precision (FP32 in the mixed
-    transforms, FP64 elsewhere); small per-mode tables are not counted."""
+    transforms, FP64 elsewhere); small per-mode tables are not counted.
+    split: the products of the state run as three launches (mean profiles,
+    padded grid, D2 / D) rather than one."""
     dim, nx, ny, nz = w["dim"], w["nx"], w["ny"], w["nz"]
     N = ny - 1
     n1, m1, ni = N + 1, 3 * N // 2 + 1, N - 1
@@ -67,13 +76,20 @@ def stage_work(w, precision):
     half = lambda r: (r + 1) // 2
     ne, no = half(ni), ni // 2
     eig = 2 * (ne * ne + no * no) * cw      # one product in the eigenbasis (either direction)
-    state = [((dim + nc + nderiv + nc) * 2 * half(m1) * cw * n1, pk(f32_state)),                  # to the padded grid
-             ((nsolve + nc) * 2 * half(n1) * cw * n1 + (dim - 1) * 2 * n1 * n1, MFMA_F64_TFS)]  # D2, D of the state
+    padded = ((dim + nc + nderiv + nc) * 2 * half(m1) * cw * n1, pk(f32_state))                    # to the padded grid
+    d2 = ((nsolve + nc) * 2 * half(n1) * cw * n1 + (dim - 1) * 2 * half(n1) * n1, MFMA_F64_TFS)   # D2, D of the state
+    mean = ((2 * (dim - 1) + 2 * nc) * 2 * half(m1) * n1, MFMA_F64_TFS)                         # mean profiles (mixed)
     proj = [((nout + dim - 1) * 2 * half(n1) * cw * m1, pk(f32_proj))]                           # P N, (D P) N
     if mixed:
-        state.append(((2 * (dim - 1) + 2 * nc) * 2 * m1 * n1, MFMA_F64_TFS))               # mean profiles
-        proj.append((nout * 2 * n1 * m1, MFMA_F64_TFS))                                    # mean column
-    out["gemm_state"] = mixed_table(state)
+        proj.append((nout * 2 * half(n1) * m1, MFMA_F64_TFS))                              # mean column
+    if split:
+        # three launches: mean profiles, padded-grid products, D2 / D of the state
+        out["gemm_state"] = mixed_table([padded])
+        out["gemm_d2"] = mixed_table([d2])
+        if mixed:
+            out["gemm_mean"] = mixed_table([mean])
+    else:
+        out["gemm_state"] = mixed_table([padded, d2] + ([mean] if mixed else []))
     if dim == 3:
         out["zfft_inv"] = ("hbm", (nyin * m1 * nzs * nkx + 26 * m1 * pz * nkx) * tb, HBM_PEAK_GBS)
         out["xpencil"] = ("hbm", (26 + nout) * m1 * pz * nkx * tb, HBM_PEAK_GBS)
@@ -133,22 +149,82 @@ def traffic_for(kernel, workload, precision):
     return None
 
 
-def cpu_baseline(w, sample_steps, scheme=0):
-    from threadpoolctl import threadpool_info
+# timed oracle steps after the warm-up step, per workload (one C5 oracle step
+# is about 80 s on one host thread)
+CPU_STEPS = {"c1": 60, "c2": 60, "c3": 4, "c5": 1}
+
+
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def oracle_job(workload, sample_steps, scheme, out):
+    """Child process: the FP64 oracle of the workload on one host thread
+    (BLAS limited to one thread; numpy.fft is single-threaded), one warm-up
+    step (it builds the per-wavenumber LU factors) then sample_steps timed
+    steps; writes the state, the last record and the timings to out."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
 
     from oracle import Grid, Oracle, Params
+    w = WORKLOADS[workload]
     g = Grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
     prm = Params(wi=w["wi"], dt=w["dt"], scheme=scheme)
-    t0 = time.perf_counter()
-    o = Oracle(g, prm, seed=w["seed"], amp=1e-3)
-    o.step(1)           # builds the per-wavenumber LU factors
-    t1 = time.perf_counter()
-    o.step(sample_steps)
-    t2 = time.perf_counter()
-    threads = max([p.get("num_threads", 1) for p in threadpool_info()] + [1])
-    return o, dict(value=sample_steps / (t2 - t1), unit="steps/s", cores=threads, kind="oracle",
-                   sample="%d steps of the same workload after 1 warm-up step (setup %.1f s excluded), "
-                          "NumPy/SciPy FP64 on the host CPU" % (sample_steps, t1 - t0))
+    with threadpool_limits(limits=1):
+        t0 = time.perf_counter()
+        o = Oracle(g, prm, seed=w["seed"], amp=1e-3)
+        t1 = time.perf_counter()
+        print("bench oracle: set up in %.1f s" % (t1 - t0), file=sys.stderr, flush=True)
+        o.step(1)
+        t2 = time.perf_counter()
+        print("bench oracle: warm-up step in %.1f s" % (t2 - t1), file=sys.stderr, flush=True)
+        for k in range(sample_steps):
+            o.step(1)
+            print("bench oracle: timed step %d of %d done" % (k + 1, sample_steps), file=sys.stderr, flush=True)
+        t3 = time.perf_counter()
+    np.savez(out, state=o.get_state(), diag=json.dumps(o.diag[-1]),
+             times=np.array([t1 - t0, t2 - t1, t3 - t2]), steps=sample_steps)
+
+
+def start_oracle(workload, sample_steps, scheme):
+    """Starts oracle_job in a child interpreter (before this process uses the
+    GPU; it reports its progress on the shared stderr); returns (process,
+    output path)."""
+    import subprocess
+    import tempfile
+    fd, out = tempfile.mkstemp(suffix=".npz", prefix="pcs_oracle_")
+    os.close(fd)
+    cmd = [sys.executable, os.path.abspath(__file__), "--oracle-job", workload, str(sample_steps), str(scheme), out]
+    proc = subprocess.Popen(cmd, stdout=subprocess.DEVNULL)
+    return proc, out
+
+
+def finish_oracle(job, sample_steps):
+    """Waits for the oracle child; returns (state, last record, cpu_baseline)."""
+    import numpy as np
+    proc, out = job
+    rc = proc.wait()
+    if rc != 0:
+        raise RuntimeError("oracle child failed with status %d (its messages are on stderr)" % rc)
+    z = np.load(out)
+    setup, warm, timed = (float(x) for x in z["times"])
+    state, diag = z["state"].copy(), json.loads(str(z["diag"]))
+    try:
+        os.remove(out)
+    except OSError:
+        pass
+    cb = dict(value=sample_steps / timed, unit="steps/s", cores=1, kind="oracle",
+              cpu_model=cpu_model(), host_threads=os.cpu_count(),
+              sample="%d FP64 oracle step(s) of the same workload on one host thread (BLAS limited to one thread, "
+                     "single-threaded numpy.fft), timed after one warm-up step (%.1f s) and setup (%.1f s), in a "
+                     "child process running beside the GPU timing" % (sample_steps, warm, setup))
+    return state, diag, cb
 
 
 def state_errors(a, b, w):
@@ -167,18 +243,24 @@ def state_errors(a, b, w):
 
 
 def main():
+    if len(sys.argv) == 6 and sys.argv[1] == "--oracle-job":
+        oracle_job(sys.argv[2], int(sys.argv[3]), int(sys.argv[4]), sys.argv[5])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=50)
-    ap.add_argument("--workload", default="c2", choices=sorted(WORKLOADS) + ["c4"],
-                    help="c4: the 64-member uneven 2D ensemble, one graph launch per step")
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["c4"],
+                    help="c5 (default): 3D 256x257x128, the largest single-GPU workload; "
+                         "c4: the 64-member uneven 2D ensemble, one graph launch per step")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed", "mixed64y"],
                     help="both: time mixed (value) and FP64 (reported beside it)")
-    ap.add_argument("--stage-steps", type=int, default=20)
-    ap.add_argument("--stage-reps", type=int, default=5,
-                    help="back-to-back launches of each stage per profiled step (per-launch kernel times)")
-    ap.add_argument("--cpu-steps", type=int, default=60)
+    ap.add_argument("--stage-steps", type=int, default=10)
+    ap.add_argument("--stage-reps", type=int, default=1,
+                    help="launches of each stage per profiled step (1: every kernel runs once per step, on the "
+                         "inputs the previous stage just wrote, as inside a step)")
+    ap.add_argument("--cpu-steps", type=int, default=None,
+                    help="timed oracle steps after the warm-up step (default per workload: %s)" % CPU_STEPS)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first copy MIB MiB device to device (a plain copy kernel of known traffic, the "
@@ -195,6 +277,18 @@ def main():
               "member, would be sharded across GPUs without communication); run with --gpus 1.",
               file=sys.stderr)
         sys.exit(2)
+    if args.cpu_steps is None:
+        args.cpu_steps = CPU_STEPS.get(args.workload, 1)
+    # the oracle child starts before this process touches the GPU
+    job = None
+    if not args.no_cpu_baseline and args.workload != "c4":
+        job = start_oracle(args.workload, args.cpu_steps, args.scheme_id)
+        print("bench: oracle child started (1 warm-up + %d timed steps)" % args.cpu_steps, file=sys.stderr,
+              flush=True)
+    # tile choices of the product tables from the committed tuning file (new
+    # table shapes are timed and appended), so that the timed kernels are the
+    # ones the committed profiles describe
+    os.environ.setdefault("PCS_TUNE_CACHE", os.path.join(ROOT, "paper_2606_09468_amd", "tune_gfx950.txt"))
     import numpy as np
     import torch
 
@@ -249,7 +343,8 @@ def main():
         timed[prec] = dict(ms=ms, sps=args.steps / (ms / 1e3), stages=stages, prm=prm, hist=hist)
     head = precs[0]
     ms, sps, stages, prm = timed[head]["ms"], timed[head]["sps"], timed[head]["stages"], timed[head]["prm"]
-    table = roofline_table(stages, stage_work(w, head))
+    split = stages.get("gemm_d2", 0.0) > 0.0
+    table = roofline_table(stages, stage_work(w, head, split))
     dom = max(table, key=lambda k: table[k]["avg_ms"])
     roof = dict(kernel=dom, **table[dom])
     roof["traffic"] = traffic_for(dom, args.workload, head)
@@ -272,20 +367,24 @@ def main():
         line["fp64"] = {"value": timed[0]["sps"], "ms_per_step": timed[0]["ms"] / args.steps,
                         "grid_point_updates_per_s": timed[0]["sps"] * points}
         line["speedup_mixed_vs_fp64"] = timed[1]["sps"] / timed[0]["sps"]
-    if not args.no_cpu_baseline:
-        print("bench: oracle sample of %d steps" % args.cpu_steps, file=sys.stderr, flush=True)
-        o, cb = cpu_baseline(w, args.cpu_steps, args.scheme_id)
+    if job is not None:
+        # the GPU state of each timed precision after the oracle's steps
+        gstates = {}
+        for prec in precs:
+            sim2 = P.Sim(grid, timed[prec]["prm"], seed=w["seed"], amp=1e-3)
+            sim2.step(args.cpu_steps + 1)
+            recs2, _ = sim2.diagnostics()
+            gstates[prec] = (sim2.get_state(), recs2[-1])
+            sim2.close()
+        print("bench: waiting for the oracle child", file=sys.stderr, flush=True)
+        ostate, odiag, cb = finish_oracle(job, args.cpu_steps)
         line["cpu_baseline"] = cb
         # error of each timed precision against the oracle over the same sample
         line["error_vs_oracle"] = {}
         for prec in precs:
-            sim2 = P.Sim(grid, timed[prec]["prm"], seed=w["seed"], amp=1e-3)
-            sim2.step(args.cpu_steps + 1)
-            a = sim2.get_state()
-            recs2, _ = sim2.diagnostics()
-            sim2.close()
-            errs = state_errors(a, o.get_state(), w)
-            d, e = recs2[-1], o.diag[-1]
+            a, d = gstates[prec]
+            errs = state_errors(a, ostate, w)
+            e = odiag
             line["error_vs_oracle"][{0: "fp64", 1: "mixed", 2: "mixed64y"}[prec]] = {
                 "steps": args.cpu_steps + 1,
                 "max_rel_velocity": max(errs[k] for k in errs if k in ("u", "v", "w", "phi", "g")),

@@ -114,7 +114,13 @@ pcs_status pcs_workspace_bytes(const pcs_grid* grid, const pcs_params* params, s
  * of amplitude amp drawn from SplitMix64(seed) (amp = 0: laminar), and the
  * history from the explicit terms of that state.  Synchronises the stream.
  * workspace: device pointer of at least pcs_workspace_bytes bytes.
- * stream: hipStream_t or NULL.  *out receives the handle. */
+ * stream: hipStream_t or NULL.  *out receives the handle.
+ * Tile shapes of the wall-normal products are chosen by timing the
+ * candidates on the device (once per table shape and process).  If the
+ * environment variable PCS_TUNE_CACHE names a file, choices recorded there for
+ * this GPU architecture and table shape are used without timing, and new
+ * choices are appended to it, so that runs in different processes use the
+ * same tiles and the same summation order. */
 pcs_status pcs_init(const pcs_grid* grid, const pcs_params* params, uint64_t seed, double amp, void* workspace,
                     size_t bytes, void* stream, struct pcs_sim** out);
 
@@ -175,8 +181,12 @@ pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
  * pcs_step) launched stage by stage, with a HIP event recorded on the
  * handle's stream between stages, and returns in ms[i] the mean duration of
  * one launch of stage i.  Every stage is one kernel launch: the products
- * (gemm_*), the z and x transforms, the RHS, finalize and diagnostics
- * kernels.  Each stage except the row diagnostics (which also add the
+ * (gemm_*: the FP64 mean profiles, the padded-grid values and derivatives,
+ * the FP64 D2 / D of the state, the projections, the two eigenbasis
+ * products), the z and x transforms, the RHS, finalize and diagnostics
+ * kernels.  Where one launch holds all products of the state (steps of less
+ * than about a million padded-grid points), gemm_state times it and
+ * gemm_mean and gemm_d2 report empty intervals.  Each stage except the row diagnostics (which also add the
  * step's midplane samples to the histograms) and the step record is launched
  * reps times back to back between its two events (these stages recompute the
  * same outputs from unchanged inputs), so that with reps > 1 the GPU does
@@ -184,7 +194,7 @@ pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
  * own duration.  nstage must be at least PCS_NSTAGE; stages that do not
  * apply (the z transforms in 2D) report their empty interval.  Stage names
  * come from pcs_stage_name.  Synchronises the stream. */
-#define PCS_NSTAGE 12
+#define PCS_NSTAGE 14
 pcs_status pcs_stage_times(struct pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage);
 const char* pcs_stage_name(int32_t i);
 

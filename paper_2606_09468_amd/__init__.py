@@ -33,7 +33,7 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state",
            "pcs_midplane_pdf_setup", "pcs_midplane_pdf", "pcs_ensemble_midplane_pdf_setup", "pcs_ensemble_midplane_pdf",
            "pcs_init_static")
-PCS_NSTAGE = 12
+PCS_NSTAGE = 14
 PCS_HIST_MAX = 4096
 PCS_STATIC_BYTES = 64 << 20
 # midplane PDF quantities (pcs_midplane_pdf_setup)

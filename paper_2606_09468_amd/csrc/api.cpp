@@ -14,9 +14,12 @@
 #include <cstdlib>
 #include <complex>
 #include <cstring>
+#include <fstream>
 #include <map>
 #include <mutex>
 #include <new>
+#include <sstream>
+#include <string>
 #include <vector>
 
 #include "../../include/pcs.h"
@@ -1187,13 +1190,13 @@ size_t layout(Batch* b, char* base) {
 // one kernel launch (or none where it does not apply), all on the caller's
 // stream.
 enum Stage {
-  ST_GEMM_STATE, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_RHS, ST_GEMM_VINV, ST_GEMM_V, ST_FINALIZE,
-  ST_DIAG_ZFFT, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
+  ST_GEMM_MEAN, ST_GEMM_STATE, ST_GEMM_D2, ST_ZFFT_INV, ST_XPENCIL, ST_ZFFT_FWD, ST_GEMM_PROJ, ST_RHS, ST_GEMM_VINV,
+  ST_GEMM_V, ST_FINALIZE, ST_DIAG_ZFFT, ST_DIAG_ROWS, ST_DIAG_FINAL, ST_COUNT
 };
 static_assert(ST_COUNT == PCS_NSTAGE, "stage table");
-const char* const STAGE_NAMES[ST_COUNT] = {"gemm_state", "zfft_inv",  "xpencil",   "zfft_fwd",
-                                            "gemm_proj",  "rhs",       "gemm_vinv", "gemm_v",
-                                            "finalize",   "diag_zfft", "diag_rows", "diag_final"};
+const char* const STAGE_NAMES[ST_COUNT] = {"gemm_mean", "gemm_state", "gemm_d2",   "zfft_inv",  "xpencil",
+                                            "zfft_fwd",  "gemm_proj",  "rhs",       "gemm_vinv", "gemm_v",
+                                            "finalize",  "diag_zfft",  "diag_rows", "diag_final"};
 
 // mark(i) returns how many times stage i is launched back to back (1 in a
 // normal step; the profiling path repeats every stage whose outputs do not
@@ -1206,11 +1209,9 @@ template <typename Mark>
 void explicit_stage(Batch* b, const Mark& mark) {
   hipStream_t s = b->s;
   const int nm = (int)b->mem.size();
-  for (int r = mark(ST_GEMM_STATE); r > 0; --r) {
-    b->GSm.run(s);
-    b->GS.run(s);
-    b->GSb.run(s);
-  }
+  for (int r = mark(ST_GEMM_MEAN); r > 0; --r) b->GSm.run(s);
+  for (int r = mark(ST_GEMM_STATE); r > 0; --r) b->GS.run(s);
+  for (int r = mark(ST_GEMM_D2); r > 0; --r) b->GSb.run(s);
   for (int r = mark(ST_ZFFT_INV); r > 0; --r)
     if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
   for (int r = mark(ST_XPENCIL); r > 0; --r) launch_xpencil(b->dim, b->prec, b->xnt, b->dx, nm, b->bx, b->lx, s);
@@ -1292,10 +1293,48 @@ void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
 
 // Tile autotuner: times each candidate tile configuration of a product table
 // on the device (results of the timing launches are discarded) and keeps the
-// fastest.  Choices are cached per table shape for the process lifetime.
+// fastest.  Choices are cached per table shape for the process lifetime, and
+// across processes in the file named by PCS_TUNE_CACHE (if set): one line per
+// choice, "<arch> <choice> <key...>" (arch as the device reports it, up to the
+// first ':'; key: the table's shape signature); lines of this device's arch are
+// loaded before tuning, and every new choice is appended, so a table shape
+// keeps its tiles (and its summation order) from one process to the next.
 std::map<std::vector<int>, int>& tune_cache() {
   static std::map<std::vector<int>, int> c;
   return c;
+}
+
+std::string device_arch() {
+  int dev = 0;
+  hipDeviceProp_t prop{};
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+    (void)hipGetLastError();
+    return "unknown";
+  }
+  std::string a(prop.gcnArchName);
+  const size_t c = a.find(':');
+  return c == std::string::npos ? a : a.substr(0, c);
+}
+
+void load_tune_file(const char* path, const std::string& arch) {
+  std::ifstream in(path);
+  std::string line;
+  while (std::getline(in, line)) {
+    std::istringstream ls(line);
+    std::string a;
+    int choice = -1;
+    if (!(ls >> a >> choice) || a != arch || choice < 0 || choice >= 2 * GEMM_NCFG) continue;
+    std::vector<int> key;
+    for (int v; ls >> v;) key.push_back(v);
+    if (!key.empty()) tune_cache()[key] = choice;
+  }
+}
+
+void append_tune_file(const char* path, const std::string& arch, const std::vector<int>& key, int choice) {
+  std::ofstream out(path, std::ios::app);
+  out << arch << ' ' << choice;
+  for (int v : key) out << ' ' << v;
+  out << '\n';
 }
 
 // With PCS_DEBUG set, the autotuner reports every timing on stderr.
@@ -1321,6 +1360,9 @@ pcs_status autotune(Batch* b) {
     only = std::atoi(c);
     if (only < 0 || only >= GEMM_NCFG) only = -1;
   }
+  const char* tune_path = std::getenv("PCS_TUNE_CACHE");
+  const std::string arch = tune_path ? device_arch() : std::string();
+  if (tune_path) load_tune_file(tune_path, arch);
   hipStream_t s = b->s;
   hipEvent_t e0, e1;
   HIPCHK(hipEventCreate(&e0));
@@ -1363,6 +1405,7 @@ pcs_status autotune(Batch* b) {
         }
       }
       tune_cache()[key] = bestf * GEMM_NCFG + best;
+      if (tune_path) append_tune_file(tune_path, arch, key, bestf * GEMM_NCFG + best);
     }
     jl->use(bestf);
     jl->set_cfg(best);
