@@ -146,7 +146,11 @@ pcs_status pcs_init_static(const pcs_grid* grid, const pcs_params* params, uint6
                            struct pcs_sim** out);
 
 /* Enqueues nsteps time steps (asynchronous).  Returns PCS_ERR_STATE if a
- * blow-up was seen at the last synchronisation. */
+ * blow-up was seen at the last synchronisation.  A run blowing up inside the
+ * enqueued steps stops on the device: once a step record flags blow-up, every
+ * kernel of the following steps skips the run's work and no further records
+ * are written (finite-time blow-up, Section 2, is a property of the run, not
+ * a device fault); pcs_set_state restarts it. */
 pcs_status pcs_step(struct pcs_sim* sim, int32_t nsteps);
 
 /* Synchronises the stream and copies the diagnostic records produced since
@@ -263,9 +267,13 @@ const char* pcs_status_string(pcs_status s);
  * state pcs_init would build with grids[r], params[r], seeds[r], amp).
  * Errors: PCS_ERR_ARG for n <= 0 or null arrays, PCS_ERR_UNSUPPORTED if
  * the runs mix dimensions or precisions (or any run's grid is unsupported),
- * PCS_ERR_WORKSPACE as for pcs_init.  A run that blows up keeps being
- * stepped with the others (its values are then meaningless); its own
- * diagnostics report PCS_BLOWUP. */
+ * PCS_ERR_WORKSPACE as for pcs_init.  A run that blows up (Section 2
+ * discusses finite-time blow-up of the unregularised equations) is masked
+ * from the step after the record that flags it: its kernels skip their work
+ * items, its step count and records stop, and the other runs advance exactly
+ * as they would without it (no run reads another's data).  Its diagnostics
+ * report PCS_BLOWUP, pcs_ensemble_run_status reports PCS_ERR_STATE, and
+ * pcs_ensemble_set_state gives it a new state and unmasks it. */
 struct pcs_ens;
 pcs_status pcs_ensemble_workspace_bytes(int32_t n, const pcs_grid* grids, const pcs_params* params, size_t* bytes);
 pcs_status pcs_ensemble_init(int32_t n, const pcs_grid* grids, const pcs_params* params, const uint64_t* seeds,
@@ -277,6 +285,13 @@ pcs_status pcs_ensemble_step(struct pcs_ens* ens, int32_t nsteps);
 pcs_status pcs_ensemble_diagnostics(struct pcs_ens* ens, int32_t run, pcs_diag* out, int32_t max, int32_t* n_out);
 pcs_status pcs_ensemble_state_size(struct pcs_ens* ens, int32_t run, size_t* n);
 pcs_status pcs_ensemble_get_state(struct pcs_ens* ens, int32_t run, double* host, size_t n);
+/* Replaces the state of run `run` (the semantics and layout of pcs_set_state:
+ * synchronises the stream, clears the run's blow-up flag and so unmasks it;
+ * the other runs are untouched). */
+pcs_status pcs_ensemble_set_state(struct pcs_ens* ens, int32_t run, const double* host, size_t n);
+/* Synchronises the stream; PCS_OK if run `run` is being stepped, PCS_ERR_STATE
+ * if it is masked after a blow-up (until pcs_ensemble_set_state). */
+pcs_status pcs_ensemble_run_status(struct pcs_ens* ens, int32_t run);
 /* Midplane histogram of run `run`, as pcs_midplane_histogram_setup and
  * pcs_midplane_histogram. */
 pcs_status pcs_ensemble_midplane_histogram_setup(struct pcs_ens* ens, int32_t run, double lo, double hi,

@@ -32,7 +32,7 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_ensemble_destroy", "pcs_midplane_histogram_setup", "pcs_midplane_histogram",
            "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state",
            "pcs_midplane_pdf_setup", "pcs_midplane_pdf", "pcs_ensemble_midplane_pdf_setup", "pcs_ensemble_midplane_pdf",
-           "pcs_init_static")
+           "pcs_init_static", "pcs_ensemble_set_state", "pcs_ensemble_run_status")
 PCS_NSTAGE = 14
 PCS_HIST_MAX = 4096
 PCS_STATIC_BYTES = 64 << 20
@@ -98,6 +98,8 @@ def lib():
     L.pcs_ensemble_state_size.argtypes = [vp, st, ctypes.POINTER(sz)]
     L.pcs_ensemble_get_state.argtypes = [vp, st, ctypes.POINTER(ctypes.c_double), sz]
     L.pcs_ensemble_destroy.argtypes = [vp]
+    L.pcs_ensemble_set_state.argtypes = [vp, st, ctypes.POINTER(ctypes.c_double), sz]
+    L.pcs_ensemble_run_status.argtypes = [vp, st]
     u64p = ctypes.POINTER(ctypes.c_uint64)
     L.pcs_midplane_histogram_setup.argtypes = [vp, ctypes.c_double, ctypes.c_double, st]
     L.pcs_midplane_histogram.argtypes = [vp, u64p, st]
@@ -343,6 +345,17 @@ class Ensemble:
                                                out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), out.size),
                "pcs_ensemble_midplane_pdf")
         return out
+
+    def set_state(self, run, flat):
+        """New state of run `run` (pcs_ensemble_set_state; unmasks a blown-up run)."""
+        flat = np.ascontiguousarray(flat, dtype=np.float64)
+        _check(lib().pcs_ensemble_set_state(self.handle, int(run), flat.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                            flat.size), "pcs_ensemble_set_state")
+
+    def run_status(self, run):
+        """PCS_OK if run `run` is being stepped, PCS_ERR_STATE if it is masked after a blow-up."""
+        return _check(lib().pcs_ensemble_run_status(self.handle, int(run)), "pcs_ensemble_run_status",
+                      allow=(PCS_OK, PCS_ERR_STATE))
 
     def get_state(self, run):
         out = np.zeros(self.state_size(run))

@@ -766,6 +766,11 @@ void build_jobs(Member* m) {
   for (int a = 0; a < d.nc; ++a) vmul(m->G5, Xs + (xo + a) * fsi, st + (FC + a) * fs + cw);
   // w . U_p for the flux constraint: the mean column only (w V split like V)
   m->G5.addp(PAR_SPLIT_UNFOLD, m->wV, m->wVp[0], m->wVp[1], Xs, cw, m->flux, cw, 1, 2, ne, 1, ni, +1);
+  // a run whose blow-up flag is set is masked: its products are skipped
+  const int* skip = m->sc ? &m->sc->blowup : nullptr;
+  for (JobList* jl : m->stage_lists())
+    for (int f = 0; f < 2; ++f)
+      for (GemmJob& j : jl->forms[f]) j.skip = skip;
   for (JobList* jl : {&m->H4, &m->H5}) jl->prepare();
 }
 
@@ -1019,6 +1024,8 @@ void build_batch(Batch* b) {
     x.eps_wi = m->p.eps / m->p.wi;
     x.mean = m->Ybar;
     x.mcol = d.dim == 2 ? m->mcol : nullptr;
+    const int* skip = m->sc ? &m->sc->blowup : nullptr;  // the run's blow-up flag masks its work
+    x.skip = skip;
     x.blk0 = b->bx;
     b->bx += x.nrows;
     b->lx = std::max(b->lx, xpencil_lds_bytes(d.dim, d.px, m->prec));
@@ -1039,6 +1046,7 @@ void build_batch(Batch* b) {
       zi.deriv = m->zder;
       zi.kz = m->kz;
       zi.tw = twz;
+      zi.skip = skip;
       zi.blk0 = b->bzi;
       b->bzi += zfft_blocks(d.nkx, m1, m->nzin);
       b->lzi = std::max(b->lzi, zfft_lds_bytes(d.pz, m->prec));
@@ -1068,6 +1076,7 @@ void build_batch(Batch* b) {
       zd.inverse = 1;
       zd.pl = m->pbz;
       zd.tw = m->twbz;
+      zd.skip = skip;
       zd.blk0 = b->bzd;
       b->bzd += zfft_blocks(d.nkx, n1, 4);
       b->lzd = std::max(b->lzd, zfft_lds_bytes(d.nz, 0));
@@ -1091,6 +1100,7 @@ void build_batch(Batch* b) {
     // diagnostics inputs [Tr c, u, v, w] at j = N/2
     r.umean = m->prep + (size_t)1 * n1 * d.cw + (size_t)(d.N / 2) * d.cw;
     r.wmean = d.dim == 3 ? m->prep + (size_t)3 * n1 * d.cw + (size_t)(d.N / 2) * d.cw : nullptr;
+    r.skip = skip;
     r.blk0 = b->bdr;
     b->bdr += n1 * r.zrows;
     b->ldr = std::max(b->ldr, diag_rows_lds_bytes(d.nx));
@@ -1556,6 +1566,7 @@ pcs_status setup_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_par
 }
 
 pcs_status sbdf4_cold_start(Member* m, hipStream_t s, long long step);
+pcs_status member_set_state(Member* m, hipStream_t s, const double* host, size_t n);
 
 pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_params* params, const uint64_t* seeds,
                       double amp, void* workspace, size_t bytes, void* stream) {
@@ -1847,16 +1858,26 @@ pcs_status pcs_get_state(pcs_sim* sim, double* host, size_t n) {
 
 pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
   if (!sim || !host) return PCS_ERR_ARG;
-  const size_t base = (size_t)(sim->m()->nq + sim->m()->nh) * (sim->m()->d.N + 1) * sim->m()->d.cw;
+  return member_set_state(sim->m(), sim->b.s, host, n);
+}
+
+}  // extern "C"
+
+namespace {
+
+pcs_status member_set_state(Member* m, hipStream_t s, const double* host, size_t n) {
+  if (!host) return PCS_ERR_ARG;
+  const size_t base = (size_t)(m->nq + m->nh) * (m->d.N + 1) * m->d.cw;
   // SBDF4 also takes the CNAB2 layout (no earlier states): constant past
-  const bool short_form = sim->m()->p.scheme == 1 && n == 4 + base;
-  if (n != sim->m()->nstate && !short_form) return PCS_ERR_ARG;
+  const bool short_form = m->p.scheme == 1 && n == 4 + base;
+  if (n != m->nstate && !short_form) return PCS_ERR_ARG;
   for (size_t i = 0; i < 3; ++i)
     if (!std::isfinite(host[i])) return PCS_ERR_ARG;
   // the step index selects ring slots on the device: a whole number in [0, 2^53]
   if (!(host[0] >= 0.0 && host[0] <= 9007199254740992.0) || host[0] != std::floor(host[0])) return PCS_ERR_ARG;
-  Member* m = sim->m();
-  hipStream_t s = sim->b.s;
+  // the run may still be in use by steps enqueued earlier (an ensemble's other
+  // runs, or this run's own steps): finish them first
+  HIPCHK(hipStreamSynchronize(s));
   DevScalars sc{};
   sc.step = (long long)host[0];
   sc.t = host[1];
@@ -1878,6 +1899,10 @@ pcs_status pcs_set_state(pcs_sim* sim, const double* host, size_t n) {
   m->blowup = 0;
   return PCS_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 pcs_status pcs_midplane_histogram_setup(pcs_sim* sim, double lo, double hi, int32_t nbins) {
   if (!sim) return PCS_ERR_ARG;
@@ -1986,6 +2011,21 @@ pcs_status pcs_ensemble_state_size(pcs_ens* e, int32_t run, size_t* n) {
 pcs_status pcs_ensemble_get_state(pcs_ens* e, int32_t run, double* host, size_t n) {
   if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
   return member_get_state(e->b.mem[run], e->b.s, host, n);
+}
+
+pcs_status pcs_ensemble_set_state(pcs_ens* e, int32_t run, const double* host, size_t n) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  return member_set_state(e->b.mem[run], e->b.s, host, n);
+}
+
+pcs_status pcs_ensemble_run_status(pcs_ens* e, int32_t run) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  Member* m = e->b.mem[run];
+  DevScalars sc;
+  HIPCHK(hipMemcpyAsync(&sc, m->sc, sizeof(sc), hipMemcpyDeviceToHost, e->b.s));
+  HIPCHK(hipStreamSynchronize(e->b.s));
+  if (sc.blowup) m->blowup = 1;
+  return sc.blowup ? PCS_ERR_STATE : PCS_OK;
 }
 
 pcs_status pcs_ensemble_midplane_histogram_setup(pcs_ens* e, int32_t run, double lo, double hi, int32_t nbins) {

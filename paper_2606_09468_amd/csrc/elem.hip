@@ -117,6 +117,7 @@ struct Layout {
 // hgn (3D), CB [nc][2 walls][cw].
 __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __restrict__ args, int nmem) {
   const RhsArgs& A = args[member_of(args, nmem)];
+  if (masked(&A.sc->blowup)) return;
   const Dims d = A.d;
   const Phys p = A.p;
   const auto st = gmem(A.st);
@@ -297,6 +298,7 @@ void launch_rhs(const RhsArgs* args, int nmem, int blocks, hipStream_t s) {
 // infl layout: [phi1 phi2 v1 v2 Dv1 Dv2][N+1][nm], then Ainv [4][nm].
 __global__ __launch_bounds__(ELEM_THREADS) void finalize_kernel(const FinArgs* __restrict__ args, int nmem) {
   const FinArgs& A = args[member_of(args, nmem)];
+  if (masked(&A.sc->blowup)) return;
   const Dims d = A.d;
   const Phys p = A.p;
   const auto Zphi = gmem(A.Zphi);

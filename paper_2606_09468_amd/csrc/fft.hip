@@ -724,6 +724,7 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
 template <typename T, int DIM, bool MIXED, int NTH>
 __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ args, int nmem) {
   const XArgs& XA = args[member_of(args, nmem)];
+  if (masked(XA.skip)) return;
   switch (XA.pl.L) {
     case 96: xpencil_body<T, DIM, MIXED, NTH, 96>(XA); break;
     case 192: xpencil_body<T, DIM, MIXED, NTH, 192>(XA); break;
@@ -880,6 +881,7 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
 template <typename T, int MV>
 __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args, int nmem) {
   const ZArgs& ZA = args[member_of(args, nmem)];
+  if (masked(ZA.skip)) return;
   switch (ZA.pl.L) {
     case 64: zfft_body<T, MV, 64>(ZA); break;  // the diagnostics' base-grid z transforms
     case 96: zfft_body<T, MV, 96>(ZA); break;
@@ -1059,6 +1061,7 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
 __global__ __launch_bounds__(DNT) void diag_rows_kernel(const DRowArgs* __restrict__ args, int nmem) {
   __shared__ DiagPart wpart[DNT / 64];
   const DRowArgs& DA = args[member_of(args, nmem)];
+  if (masked(DA.skip)) return;
   switch (DA.pl.L) {
     case 64: diag_rows_body<64>(DA, wpart); break;
     case 128: diag_rows_body<128>(DA, wpart); break;
@@ -1094,6 +1097,7 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
   const long long step0 = sg->step;
   const double t0 = sg->t, pi0 = sg->pi;
   const int blowup0 = sg->blowup;
+  if (blowup0) return;  // masked run: no record, the step count stays
   __shared__ FinPart fp[NT / 64];
   const int tid = threadIdx.x;
   const int n1 = d.N + 1, nrows = n1 * zrows, mid = d.N / 2;

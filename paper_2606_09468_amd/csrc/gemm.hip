@@ -375,6 +375,7 @@ __global__ __launch_bounds__(256) void gemm_reg_kernel(const GemmJob* __restrict
   __shared__ double red[RCfg<CFG>::KS > 1 ? 4 * 16 * 64 : 1];
   const int t = xcd_tile(blockIdx.x, total);
   const GemmJob* jp = tile_job(jobs, tmap, t);
+  if (masked(jp->skip)) return;
   if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
     reg_body<double, double, double, CFG>(jp, t, red);
   else
@@ -754,6 +755,7 @@ __global__ __launch_bounds__(256) void gemm_lds_kernel(const GemmJob* __restrict
   extern __shared__ __attribute__((aligned(16))) double smem[];
   const int t = xcd_tile(blockIdx.x, total);
   const GemmJob* jp = tile_job(jobs, tmap, t);
+  if (masked(jp->skip)) return;
   const bool ddd = dual_type<T, TB, TC>() && jp->type == GEMM_DDD;
   if constexpr (PAR) {
     if (ddd)

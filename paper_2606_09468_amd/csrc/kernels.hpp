@@ -61,6 +61,7 @@ struct GemmJob {
   int flags;           // GEMM_ZERO_MEAN: B columns 0 and 1 (the kx = kz = 0 mode) read as zero
   int scale, scale2;   // SCALE_*: output row i is eigen coefficient i, scaled per mode
   const EigScale* es;  // per-solve constants for the scaling
+  const int* skip;     // the run's blow-up flag (device): nonzero skips the product; null: never
   int tiles_m, tile0;  // filled by gemm_prepare
 };
 constexpr int GEMM_ZERO_MEAN = 1;
@@ -159,7 +160,10 @@ struct Phys {
   double ia, th;    // leading coefficient / dt and implicit weight of the scheme
 };
 
-// Device-resident scalars advanced by the step itself.
+// Device-resident scalars advanced by the step itself.  blowup is sticky:
+// once a step record flags it, every stage kernel skips the run's work and
+// the step record is no longer written (the run is masked until the host
+// sets a new state).
 struct DevScalars {
   long long step;
   double t;
@@ -167,6 +171,8 @@ struct DevScalars {
   int blowup;
   int pad;
 };
+// the masking test at the start of a stage kernel
+__device__ inline bool masked(const int* skip) { return skip != nullptr && *gmem(skip) != 0; }
 
 struct DiagRec {
   long long step;
@@ -202,6 +208,7 @@ struct XArgs {
   double eps_wi;
   const double* mean;
   double* mcol;
+  const int* skip;  // the run's blow-up flag: nonzero skips its work (as in every stage kernel)
   int blk0;
 };
 // z columns (fft.hip): workgroups (kx group, row, field) flattened; the
@@ -219,6 +226,7 @@ struct ZArgs {
   const double* mean;
   double* mcol;
   double eps_wi;  // sPTT eps / Wi: its mean product enters the FP64 mean column
+  const int* skip;
   int blk0;
 };
 // diagnostics (fft.hip): per (y_j, z) line of the base grid, from the
@@ -240,6 +248,7 @@ struct DRowArgs {
   double hlo[4], hscale[4];
   int hbins[4];
   const double *umean, *wmean;
+  const int* skip;
   int blk0;
 };
 constexpr int HIST_MAX = 4096;  // largest number of histogram bins

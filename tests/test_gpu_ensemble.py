@@ -124,3 +124,86 @@ def test_full_size_ensemble_sampled_members(P):
             fl, full = errs[name]
             assert fl < 2e-4 and full < 2e-5, (r, name, fl, full)
     ens.close()
+
+
+def test_blown_up_member_is_masked_and_isolated(P, monkeypatch):
+    """One member of an ensemble runs with an absurd time step (dt = 2,
+    CFL far above 1) and blows up numerically within a few steps.  It must be
+    flagged (PCS_BLOWUP, then PCS_ERR_STATE from its run status), masked (no
+    record or step after the flagged one, its state left where it stopped
+    while the others advance), and every other member must stay bitwise
+    equal to the same ensemble without the bad time step.  A new state
+    through pcs_ensemble_set_state unmasks it, and it then advances as the
+    same run on its own does.  Tile shape and product form are forced so
+    that both ensembles and the single run evaluate identical products."""
+    monkeypatch.setenv("PCS_GEMM_CFG", "4")
+    monkeypatch.setenv("PCS_PRODUCT_FORM", "parity")
+    members = SMALL[:4]
+    bad, nsteps = 1, 16
+
+    def make(dt_bad):
+        grids = [P.make_grid(2, nx, ny) for ny, nx, _, _ in members]
+        params = [P.make_params(wi=wi, dt=(dt_bad if r == bad else 1e-3)) for r, (_, _, wi, _) in enumerate(members)]
+        return P.Ensemble(grids, params, [s for _, _, _, s in members], amp=1e-3)
+
+    print("case ensemble blow-up masking", members, flush=True)
+    ref = make(1e-3)
+    ens = make(2.0)
+    ref.step(nsteps)
+    ens.step(nsteps)
+    recs, st = ens.diagnostics(bad)
+    assert st == P.PCS_BLOWUP and 1 <= len(recs) < nsteps
+    assert recs[-1]["blowup"] == 1 and all(r["blowup"] == 0 for r in recs[:-1])
+    assert recs[-1]["step"] == len(recs)
+    assert ens.run_status(bad) == P.PCS_ERR_STATE
+    for r in range(len(members)):
+        if r == bad:
+            continue
+        assert ens.run_status(r) == P.PCS_OK
+        assert np.array_equal(ens.get_state(r), ref.get_state(r)), r
+        ra, sa = ens.diagnostics(r)
+        rb, sb = ref.diagnostics(r)
+        assert sa == sb == P.PCS_OK and ra == rb and len(ra) == nsteps
+    # the masked run stays where it stopped
+    frozen = ens.get_state(bad)
+    ens.step(3)
+    ref.step(3)
+    assert np.array_equal(ens.get_state(bad), frozen, equal_nan=True)
+    recs, st = ens.diagnostics(bad)
+    assert recs == [] and st == P.PCS_BLOWUP
+    for r in range(len(members)):
+        if r != bad:
+            assert np.array_equal(ens.get_state(r), ref.get_state(r)), r
+    # recovery: a fresh state for the bad run (its own seeded initial state)
+    ny, nx, wi, seed = members[bad]
+    sim = P.Sim(P.make_grid(2, nx, ny), P.make_params(wi=wi, dt=2.0), seed=seed, amp=1e-3)
+    fresh = sim.get_state()
+    ens.set_state(bad, fresh)
+    assert ens.run_status(bad) == P.PCS_OK
+    ens.step(2)
+    sim.step(2)
+    recs, st = ens.diagnostics(bad)
+    assert st == P.PCS_OK and [x["step"] for x in recs] == [1, 2] and recs[-1]["blowup"] == 0
+    a, b = ens.get_state(bad), sim.get_state()
+    assert np.abs(a - b).max() <= 1e-12 * np.abs(b).max()
+    sim.close()
+    ens.close()
+    ref.close()
+
+
+def test_single_run_stops_at_its_blowup_step(P):
+    """A single run with dt = 2 stepped 16 steps in one call: the device
+    stops it at the step whose record flags the blow-up (no later records,
+    step count frozen), and the host then refuses further steps."""
+    print("case single-run blow-up stop", flush=True)
+    ny, nx, wi, seed = SMALL[1]
+    sim = P.Sim(P.make_grid(2, nx, ny), P.make_params(wi=wi, dt=2.0), seed=seed, amp=1e-3)
+    sim.step(16)
+    recs, st = sim.diagnostics()
+    assert st == P.PCS_BLOWUP and 1 <= len(recs) < 16 and recs[-1]["blowup"] == 1
+    state = sim.get_state()
+    assert state[0] == recs[-1]["step"]
+    with pytest.raises(P.PcsError) as e:
+        sim.step(1)
+    assert e.value.status == P.PCS_ERR_STATE
+    sim.close()
