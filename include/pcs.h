@@ -221,21 +221,40 @@ pcs_status pcs_midplane_histogram_setup(struct pcs_sim* sim, double lo, double h
 pcs_status pcs_midplane_histogram(struct pcs_sim* sim, uint64_t* counts, int32_t n);
 
 /* Midplane PDFs of other quantities (Section 3 compares the midplane
- * statistics of the velocity fluctuations across resolutions): the same
- * histogram for quantity
- *   PCS_PDF_TRC  Tr c (the histogram above),
- *   PCS_PDF_U    u - U(0), U(0) the plane mean of u at y = 0 (its kx = kz = 0
- *                mode) at the same step,
- *   PCS_PDF_V    v (whose plane mean is zero),
- *   PCS_PDF_W    w - W(0) (3D only; PCS_ERR_ARG in 2D),
- * each with its own range, bins and counts, set up and read as above.  All
- * four are binned by the same row-diagnostics kernel in the same step. */
+ * statistics of the velocity fluctuations and of the longitudinal and
+ * transverse velocity gradients across resolutions): the same histogram for
+ * quantity
+ *   PCS_PDF_TRC   Tr c (the histogram above),
+ *   PCS_PDF_U     u - U(0), U(0) the plane mean of u at y = 0 (its kx = kz = 0
+ *                 mode) at the same step,
+ *   PCS_PDF_V     v (whose plane mean is zero),
+ *   PCS_PDF_W     w - W(0),
+ *   PCS_PDF_DUDX  d u / d x (longitudinal gradient of u),
+ *   PCS_PDF_DUDZ  d u / d z (transverse gradient of u),
+ *   PCS_PDF_DWDX  d w / d x (transverse gradient of w),
+ *   PCS_PDF_DWDZ  d w / d z (longitudinal gradient of w),
+ * (the quantities with w or d/dz are 3D only: PCS_ERR_ARG in 2D), each with
+ * its own range, bins and counts, set up and read as above.  All are binned
+ * by the same row-diagnostics kernel in the same step; the gradients are
+ * spectral derivatives of the base-grid fields. */
 #define PCS_PDF_TRC 0
 #define PCS_PDF_U 1
 #define PCS_PDF_V 2
 #define PCS_PDF_W 3
+#define PCS_PDF_DUDX 4
+#define PCS_PDF_DUDZ 5
+#define PCS_PDF_DWDX 6
+#define PCS_PDF_DWDZ 7
 pcs_status pcs_midplane_pdf_setup(struct pcs_sim* sim, int32_t quantity, double lo, double hi, int32_t nbins);
 pcs_status pcs_midplane_pdf(struct pcs_sim* sim, int32_t quantity, uint64_t* counts, int32_t n);
+/* Running moments of the samples of an enabled quantity (the paper's PDFs
+ * are standardised by their own mean and standard deviation): out[0] the
+ * number of finite samples, out[1] their sum, out[2] the sum of their
+ * squares, accumulated on the device since the quantity's setup (which clears
+ * them) in a fixed order, so repeated runs give identical sums; mean =
+ * out[1] / out[0], variance = out[2] / out[0] - mean^2.  Synchronises;
+ * PCS_ERR_ARG while the quantity is off or for a null out. */
+pcs_status pcs_midplane_moments(struct pcs_sim* sim, int32_t quantity, double* out);
 
 /* Resampling between resolutions (Section 2 starts every run of Table 1 from one
  * snapshot re-interpolated onto its grid; host only, no GPU work): fills dst_state
@@ -303,6 +322,8 @@ pcs_status pcs_ensemble_midplane_pdf_setup(struct pcs_ens* ens, int32_t run, int
                                            int32_t nbins);
 pcs_status pcs_ensemble_midplane_pdf(struct pcs_ens* ens, int32_t run, int32_t quantity, uint64_t* counts,
                                      int32_t n);
+/* Running moments of run `run`, as pcs_midplane_moments. */
+pcs_status pcs_ensemble_midplane_moments(struct pcs_ens* ens, int32_t run, int32_t quantity, double* out);
 pcs_status pcs_ensemble_destroy(struct pcs_ens* ens);
 
 #ifdef __cplusplus

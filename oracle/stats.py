@@ -46,17 +46,35 @@ def chi(values, nx, nz, threshold=3.0):
 
 def midplane_quantities(oracle):
     """The midplane samples of the current state of an Oracle, by quantity:
-    0 Tr c, 1 u - U(0), 2 v, 3 w - W(0) (3D), on the base grid of the row
-    j = N/2 (y = 0), with U(0), W(0) the plane means (the kx = kz = 0 mode)
-    of u and w there.  Section 3 compares the PDFs of these across
-    resolutions."""
+    0 Tr c, 1 u - U(0), 2 v, 3 w - W(0) (3D), 4 du/dx, 5 du/dz (3D),
+    6 dw/dx (3D), 7 dw/dz (3D), on the base grid of the row j = N/2 (y = 0),
+    with U(0), W(0) the plane means (the kx = kz = 0 mode) of u and w there
+    and the gradients as spectral derivatives (i kx, i kz times each mode).
+    Section 3 compares the PDFs of the velocity fluctuations and of the
+    longitudinal (du/dx, dw/dz) and transverse (du/dz, dw/dx) gradients
+    across resolutions."""
     j = oracle.N // 2
     q = oracle.q
+    ikx = 1j * oracle.kx[None, None, :]
+    ikz = 1j * oracle.kz[None, :, None]
     out = {0: oracle.trace_c()[j].ravel().copy()}
     u = oracle.base_grid(q["u"])[j]
     out[1] = (u - q["u"][j, 0, 0].real).ravel()
     out[2] = oracle.base_grid(q["v"])[j].ravel()
+    out[4] = oracle.base_grid(ikx * q["u"])[j].ravel()
     if oracle.g.dim == 3:
         w = oracle.base_grid(q["w"])[j]
         out[3] = (w - q["w"][j, 0, 0].real).ravel()
+        out[5] = oracle.base_grid(ikz * q["u"])[j].ravel()
+        out[6] = oracle.base_grid(ikx * q["w"])[j].ravel()
+        out[7] = oracle.base_grid(ikz * q["w"])[j].ravel()
     return out
+
+
+def moments(values):
+    """(count, sum, sum of squares) of the finite samples: the standardised
+    PDFs of Section 3 use mean = sum / count and the standard deviation
+    sqrt(sum of squares / count - mean^2)."""
+    v = np.asarray(values, dtype=np.float64).ravel()
+    v = v[np.isfinite(v)]
+    return float(v.size), float(v.sum()), float((v * v).sum())

@@ -32,12 +32,14 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_ensemble_destroy", "pcs_midplane_histogram_setup", "pcs_midplane_histogram",
            "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state",
            "pcs_midplane_pdf_setup", "pcs_midplane_pdf", "pcs_ensemble_midplane_pdf_setup", "pcs_ensemble_midplane_pdf",
-           "pcs_init_static", "pcs_ensemble_set_state", "pcs_ensemble_run_status")
+           "pcs_init_static", "pcs_ensemble_set_state", "pcs_ensemble_run_status", "pcs_midplane_moments",
+           "pcs_ensemble_midplane_moments")
 PCS_NSTAGE = 14
 PCS_HIST_MAX = 4096
 PCS_STATIC_BYTES = 64 << 20
 # midplane PDF quantities (pcs_midplane_pdf_setup)
 PCS_PDF_TRC, PCS_PDF_U, PCS_PDF_V, PCS_PDF_W = 0, 1, 2, 3
+PCS_PDF_DUDX, PCS_PDF_DUDZ, PCS_PDF_DWDX, PCS_PDF_DWDZ = 4, 5, 6, 7
 
 
 class pcs_grid(ctypes.Structure):
@@ -109,6 +111,8 @@ def lib():
     L.pcs_midplane_pdf.argtypes = [vp, st, u64p, st]
     L.pcs_ensemble_midplane_pdf_setup.argtypes = [vp, st, st, ctypes.c_double, ctypes.c_double, st]
     L.pcs_ensemble_midplane_pdf.argtypes = [vp, st, st, u64p, st]
+    L.pcs_midplane_moments.argtypes = [vp, st, ctypes.POINTER(ctypes.c_double)]
+    L.pcs_ensemble_midplane_moments.argtypes = [vp, st, st, ctypes.POINTER(ctypes.c_double)]
     dp = ctypes.POINTER(ctypes.c_double)
     L.pcs_resample_state.argtypes = [ctypes.POINTER(pcs_grid), dp, sz, ctypes.POINTER(pcs_grid), dp, sz]
     for name in EXPORTS:
@@ -164,6 +168,15 @@ def pcs_workspace_bytes(grid, params):
 
 
 DIAG_FIELDS = [f[0] for f in pcs_diag._fields_ if f[0] != "reserved"]
+
+
+def _moments(out):
+    """(samples, mean, standard deviation) from the device's count, sum and sum of squares."""
+    n, s1, s2 = out[0], out[1], out[2]
+    if n <= 0:
+        return 0, float("nan"), float("nan")
+    mean = s1 / n
+    return int(n), mean, float(np.sqrt(max(s2 / n - mean * mean, 0.0)))
 
 
 def _arrays(grids, params):
@@ -261,6 +274,13 @@ class Sim:
                                       out.size), "pcs_midplane_pdf")
         return out
 
+    def midplane_moments(self, quantity):
+        """(samples, mean, standard deviation) of an enabled midplane quantity
+        since its setup (pcs_midplane_moments)."""
+        out = (ctypes.c_double * 3)()
+        _check(lib().pcs_midplane_moments(self.handle, int(quantity), out), "pcs_midplane_moments")
+        return _moments(out)
+
     def stage_times(self, nsteps, reps=1):
         """Mean milliseconds per launch of each stage over nsteps real steps
         (eager launch, every stage but the last repeated reps times back to
@@ -356,6 +376,12 @@ class Ensemble:
         """PCS_OK if run `run` is being stepped, PCS_ERR_STATE if it is masked after a blow-up."""
         return _check(lib().pcs_ensemble_run_status(self.handle, int(run)), "pcs_ensemble_run_status",
                       allow=(PCS_OK, PCS_ERR_STATE))
+
+    def midplane_moments(self, run, quantity):
+        out = (ctypes.c_double * 3)()
+        _check(lib().pcs_ensemble_midplane_moments(self.handle, int(run), int(quantity), out),
+               "pcs_ensemble_midplane_moments")
+        return _moments(out)
 
     def get_state(self, run):
         out = np.zeros(self.state_size(run))

@@ -233,6 +233,11 @@ struct Member {
   int *zsrc, *zder;
   DiagPart* parts;
   unsigned long long* hist;  // midplane histogram counts (HIST_Q x (HIST_MAX + 2))
+  // midplane moments: per line z [HIST_Q][3] partials, running [HIST_Q][3];
+  // zgrad (3D): d/dz of u and w on the midplane row, [2][nz][nkx] complex;
+  // zgsrc / zgder: the field table of that z transform
+  double *mparts, *msum, *zgrad;
+  int *zgsrc, *zgder;
   DiagRec* ring;
   DevScalars* sc;
   // G1: state -> padded grid; Gbar: FP64 mean profiles there (mixed);
@@ -430,6 +435,11 @@ void carve(Member* m, Carve& c) {
   const size_t zrows = d.dim == 3 ? d.nz : 1;
   m->parts = c.take<DiagPart>(n1 * zrows);
   m->hist = c.take<unsigned long long>((size_t)HIST_Q * (HIST_MAX + 2));
+  m->mparts = c.take<double>(zrows * HIST_Q * 3);
+  m->msum = c.take<double>(HIST_Q * 3);
+  m->zgrad = d.dim == 3 ? c.take<double>(2 * (size_t)d.nz * d.nkx * 2) : nullptr;
+  m->zgsrc = c.take<int>(2);
+  m->zgder = c.take<int>(2);
   m->ring = c.take<DiagRec>(RING);
   m->sc = c.take<DevScalars>(1);
 }
@@ -913,6 +923,9 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
     }
     HIPCHK(up(m->zsrc, src, s));
     HIPCHK(up(m->zder, der, s));
+    // midplane d/dz of u (field 1 of the diagnostics inputs) and w (field 3)
+    HIPCHK(up(m->zgsrc, std::vector<int>{1 * (d.N + 1), 3 * (d.N + 1)}, s));
+    HIPCHK(up(m->zgder, std::vector<int>{1, 1}, s));
   }
   // initial state
   std::vector<double> st;
@@ -1081,6 +1094,19 @@ void build_batch(Batch* b) {
       b->bzd += zfft_blocks(d.nkx, n1, 4);
       b->lzd = std::max(b->lzd, zfft_lds_bytes(d.nz, 0));
       b->hzd.push_back(zd);
+      // d/dz of u and w on the midplane row (the velocity-gradient PDFs): the
+      // same launch, one row, fields picked by whole-field offsets from that row
+      ZArgs zg = zd;
+      zg.in = m->prep + (size_t)(d.N / 2) * d.cw;
+      zg.out = m->zgrad;
+      zg.rows = 1;
+      zg.nfields = 2;
+      zg.src_field = m->zgsrc;
+      zg.deriv = m->zgder;
+      zg.kz = m->kz;
+      zg.blk0 = b->bzd;
+      b->bzd += zfft_blocks(d.nkx, 1, 2);
+      b->hzd.push_back(zg);
     }
     DRowArgs r{};
     r.d = d;
@@ -1089,8 +1115,11 @@ void build_batch(Batch* b) {
     r.pl = m->pbx;
     r.tw = m->twbx;
     r.ydy = m->ydy;
+    r.kx = m->kx;
     r.parts = m->parts;
     r.hist = m->hist;
+    r.zgrad = m->zgrad;
+    r.mparts = m->mparts;
     for (int q = 0; q < HIST_Q; ++q) {
       r.hbins[q] = m->hbins[q];
       r.hlo[q] = m->hlo[q];
@@ -1114,6 +1143,11 @@ void build_batch(Batch* b) {
     f.sc = m->sc;
     f.ring = m->ring;
     f.cap = RING;
+    f.mparts = m->mparts;
+    f.msum = m->msum;
+    f.mom_mask = 0;
+    for (int q = 0; q < HIST_Q; ++q)
+      if (m->hbins[q] > 0) f.mom_mask |= 1 << q;
     b->hdf.push_back(f);
     const int eblocks = (n1 * d.nm + ELEM_THREADS - 1) / ELEM_THREADS;
     RhsArgs h{};
@@ -1187,7 +1221,7 @@ size_t layout(Batch* b, char* base) {
   b->dx = c.take<XArgs>(n);
   b->dzi = c.take<ZArgs>(n);
   b->dzf = c.take<ZArgs>(n);
-  b->dzd = c.take<ZArgs>(n);
+  b->dzd = c.take<ZArgs>(2 * n);
   b->ddr = c.take<DRowArgs>(n);
   b->ddf = c.take<DFinArgs>(n);
   b->drhs = c.take<RhsArgs>(n);
@@ -1240,7 +1274,7 @@ void enqueue_step(Batch* b, const Mark& mark) {
   for (int r = mark(ST_GEMM_V); r > 0; --r) b->G5.run(s);
   for (int r = mark(ST_FINALIZE); r > 0; --r) launch_finalize(b->dfin, nm, b->bfin, s);
   for (int r = mark(ST_DIAG_ZFFT); r > 0; --r)
-    if (b->dim == 3) launch_zfft(0, b->dzd, nm, b->bzd, b->lzd, s);
+    if (b->dim == 3) launch_zfft(0, b->dzd, (int)b->hzd.size(), b->bzd, b->lzd, s);
   for (int r = mark(ST_DIAG_ROWS); r > 0; --r) launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, s);
   for (int r = mark(ST_DIAG_FINAL); r > 0; --r) launch_diag_final(b->ddf, nm, s);
   mark(ST_COUNT);
@@ -1249,7 +1283,7 @@ void enqueue_step(Batch* b, const Mark& mark) {
 // The diagnostics of the state that the last finalize wrote, on stream t.
 void enqueue_diagnostics(Batch* b, hipStream_t t) {
   const int nm = (int)b->mem.size();
-  if (b->dim == 3) launch_zfft(0, b->dzd, nm, b->bzd, b->lzd, t);
+  if (b->dim == 3) launch_zfft(0, b->dzd, (int)b->hzd.size(), b->bzd, b->lzd, t);
   launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, t);
   launch_diag_final(b->ddf, nm, t);
 }
@@ -1657,9 +1691,13 @@ pcs_status member_diagnostics(Member* m, hipStream_t s, pcs_diag* outp, int32_t 
 // of run `idx` (nbins = 0: off), clears its counts and updates the argument
 // table the captured steps read.
 static_assert(HIST_MAX == PCS_HIST_MAX, "histogram capacity");
-static_assert(HIST_Q == 4 && PCS_PDF_TRC == 0 && PCS_PDF_U == 1 && PCS_PDF_V == 2 && PCS_PDF_W == 3, "quantities");
+static_assert(HIST_Q == 8 && PCS_PDF_TRC == 0 && PCS_PDF_U == 1 && PCS_PDF_V == 2 && PCS_PDF_W == 3 &&
+                  PCS_PDF_DUDX == 4 && PCS_PDF_DUDZ == 5 && PCS_PDF_DWDX == 6 && PCS_PDF_DWDZ == 7,
+              "quantities");
+// quantities that need the spanwise direction (w or d/dz)
+bool needs_3d(int q) { return q == PCS_PDF_W || q == PCS_PDF_DUDZ || q == PCS_PDF_DWDX || q == PCS_PDF_DWDZ; }
 pcs_status member_hist_setup(Batch* b, int idx, int q, double lo, double hi, int32_t nbins) {
-  if (q < 0 || q >= HIST_Q || (q == PCS_PDF_W && b->mem[idx]->d.dim != 3)) return PCS_ERR_ARG;
+  if (q < 0 || q >= HIST_Q || (needs_3d(q) && b->mem[idx]->d.dim != 3)) return PCS_ERR_ARG;
   if (nbins < 0 || nbins > HIST_MAX) return PCS_ERR_ARG;
   if (nbins > 0 && !(std::isfinite(lo) && std::isfinite(hi) && lo < hi && std::isfinite(nbins / (hi - lo))))
     return PCS_ERR_ARG;
@@ -1674,7 +1712,19 @@ pcs_status member_hist_setup(Batch* b, int idx, int q, double lo, double hi, int
   r.hlo[q] = lo;
   r.hscale[q] = nbins > 0 ? nbins / (hi - lo) : 0.0;
   HIPCHK(hipMemcpy(b->ddr + idx, &r, sizeof(r), hipMemcpyHostToDevice));
+  DFinArgs& f = b->hdf[idx];
+  f.mom_mask = nbins > 0 ? (f.mom_mask | (1 << q)) : (f.mom_mask & ~(1 << q));
+  HIPCHK(hipMemcpy(b->ddf + idx, &f, sizeof(f), hipMemcpyHostToDevice));
   HIPCHK(hipMemset(m->hist + (size_t)q * (HIST_MAX + 2), 0, (HIST_MAX + 2) * sizeof(unsigned long long)));
+  HIPCHK(hipMemset(m->msum + (size_t)q * 3, 0, 3 * sizeof(double)));
+  return PCS_OK;
+}
+
+// Running moments of quantity q: [samples, sum, sum of squares].
+pcs_status member_moments(Member* m, hipStream_t s, int q, double* out) {
+  if (q < 0 || q >= HIST_Q || !out || m->hbins[q] <= 0) return PCS_ERR_ARG;
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(out, m->msum + (size_t)q * 3, 3 * sizeof(double), hipMemcpyDeviceToHost));
   return PCS_OK;
 }
 
@@ -1924,6 +1974,11 @@ pcs_status pcs_midplane_pdf(pcs_sim* sim, int32_t quantity, uint64_t* counts, in
   return member_hist_get(sim->m(), sim->b.s, quantity, counts, n);
 }
 
+pcs_status pcs_midplane_moments(pcs_sim* sim, int32_t quantity, double* out) {
+  if (!sim) return PCS_ERR_ARG;
+  return member_moments(sim->m(), sim->b.s, quantity, out);
+}
+
 pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
   if (!sim || nsteps <= 0 || reps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
   if (sim->m()->blowup) return PCS_ERR_STATE;
@@ -2047,6 +2102,11 @@ pcs_status pcs_ensemble_midplane_pdf_setup(pcs_ens* e, int32_t run, int32_t quan
 pcs_status pcs_ensemble_midplane_pdf(pcs_ens* e, int32_t run, int32_t quantity, uint64_t* counts, int32_t n) {
   if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
   return member_hist_get(e->b.mem[run], e->b.s, quantity, counts, n);
+}
+
+pcs_status pcs_ensemble_midplane_moments(pcs_ens* e, int32_t run, int32_t quantity, double* out) {
+  if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
+  return member_moments(e->b.mem[run], e->b.s, quantity, out);
 }
 
 pcs_status pcs_ensemble_destroy(pcs_ens* e) {

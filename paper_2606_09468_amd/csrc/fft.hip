@@ -926,7 +926,8 @@ constexpr int DNT = 128;
 
 // LC: the line length when it has a compiled plan, else 0.
 template <int LC>
-__device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowArgs& DA, DiagPart* wpart) {
+__device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowArgs& DA, DiagPart* wpart,
+                                                                     double* wred) {
   const Dims d = DA.d;
   const gptr<const double> in = gmem(DA.in);
   const int zrows = DA.zrows;
@@ -1056,18 +1057,105 @@ __device__ __attribute__((always_inline)) inline void diag_rows_body(const DRowA
     }
     parts[row] = q;
   }
+  if (!midrow) return;
+  // ---- midplane line z: running moments of every histogrammed quantity (the
+  // count, sum and sum of squares of its finite samples, reduced in a fixed
+  // order), then the velocity gradients d_x u, d_z u, d_x w, d_z w
+  const int z = row - j * zrows;
+  double* mp = DA.mparts + (size_t)z * HIST_Q * 3;
+  auto moments = [&](int qh, auto value) {
+    if (DA.hbins[qh] <= 0) return;
+    double c = 0, s1 = 0, s2 = 0;
+    for (int n = tid; n < L; n += DNT) {
+      const double x = value(n);
+      if (isfinite(x)) {
+        c += 1.0;
+        s1 += x;
+        s2 += x * x;
+      }
+    }
+    c = wave_sum(c);
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    __syncthreads();
+    if ((tid & 63) == 0) {
+      wred[3 * wv] = c;
+      wred[3 * wv + 1] = s1;
+      wred[3 * wv + 2] = s2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double a = 0, b = 0, e2 = 0;
+      for (int w2 = 0; w2 < DNT / 64; ++w2) {
+        a += wred[3 * w2];
+        b += wred[3 * w2 + 1];
+        e2 += wred[3 * w2 + 2];
+      }
+      mp[3 * qh] = a;
+      mp[3 * qh + 1] = b;
+      mp[3 * qh + 2] = e2;
+    }
+  };
+  const double trc_add = d.dim == 2 ? 1.0 : 0.0;
+  moments(0, [&](int n) { return AV[n].x + trc_add; });
+  moments(1, [&](int n) { return AV[n].y - um; });
+  moments(2, [&](int n) { return AV[L + n].x; });
+  if (d.dim == 3) moments(3, [&](int n) { return AV[L + n].y - wm; });
+  const bool grads = DA.hbins[4] > 0 || DA.hbins[5] > 0 || DA.hbins[6] > 0 || DA.hbins[7] > 0;
+  if (!grads) return;
+  // pairs (d_x u, d_z u) and (d_x w, d_z w): d_x by i kx on the line's
+  // spectra, d_z from the midplane row's z transform with i kz (3D)
+  __syncthreads();
+  for (int e = tid; e < 2 * L; e += DNT) AV[e] = c2{0, 0};
+  __syncthreads();
+  const gptr<const double> kxv = gmem(DA.kx);
+  for (int e = tid; e < 2 * nkx; e += DNT) {
+    const int q = fdiv(e, mkx), k = e - q * nkx;
+    c2 Av{0, 0}, Bv{0, 0};
+    if (q == 0 || d.dim == 3) {
+      const int fsrc = q == 0 ? 1 : 3;  // u and w among the inputs [Tr c, u, v, w]
+      const double fr = base[fsrc * fstride + 2 * k], fi = base[fsrc * fstride + 2 * k + 1];
+      const double kk = kxv[k];
+      Av = c2{-kk * fi, kk * fr};
+      if (d.dim == 3) {
+        const gptr<const double> zg = gmem(DA.zgrad) + ((size_t)q * zrows + z) * nkx * 2;
+        Bv = c2{zg[2 * k], zg[2 * k + 1]};
+      }
+    }
+    pack_pair(AV.at(q * L), L, k, Av, Bv);
+  }
+  __syncthreads();
+  if (L <= 64 * cover(16)) {
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+    if (wave < 2) fft_any<double, LC, 64, 16, true, +1>(AV.at(wave * L), L, pl, 1, twl, tid & 63);
+    __syncthreads();
+  } else {
+    lds_fft<double, DNT, 16>(AV, L, pl, 2, twl, +1);
+  }
+  for (int n = tid; n < L; n += DNT) {
+    const c2 g0 = AV[n], g1 = AV[L + n];
+    bin_sample(4, g0.x);
+    bin_sample(5, g0.y);
+    bin_sample(6, g1.x);
+    bin_sample(7, g1.y);
+  }
+  moments(4, [&](int n) { return AV[n].x; });
+  moments(5, [&](int n) { return AV[n].y; });
+  moments(6, [&](int n) { return AV[L + n].x; });
+  moments(7, [&](int n) { return AV[L + n].y; });
 }
 
 __global__ __launch_bounds__(DNT) void diag_rows_kernel(const DRowArgs* __restrict__ args, int nmem) {
   __shared__ DiagPart wpart[DNT / 64];
+  __shared__ double wred[3 * (DNT / 64)];
   const DRowArgs& DA = args[member_of(args, nmem)];
   if (masked(DA.skip)) return;
   switch (DA.pl.L) {
-    case 64: diag_rows_body<64>(DA, wpart); break;
-    case 128: diag_rows_body<128>(DA, wpart); break;
-    case 256: diag_rows_body<256>(DA, wpart); break;
-    case 512: diag_rows_body<512>(DA, wpart); break;
-    default: diag_rows_body<0>(DA, wpart); break;
+    case 64: diag_rows_body<64>(DA, wpart, wred); break;
+    case 128: diag_rows_body<128>(DA, wpart, wred); break;
+    case 256: diag_rows_body<256>(DA, wpart, wred); break;
+    case 512: diag_rows_body<512>(DA, wpart, wred); break;
+    default: diag_rows_body<0>(DA, wpart, wred); break;
   }
 }
 
@@ -1135,6 +1223,21 @@ __global__ __launch_bounds__(NT) void diag_final_kernel(const DFinArgs* __restri
   v.b = wave_or(b);
   if ((tid & 63) == 0) fp[tid >> 6] = v;
   __syncthreads();
+  // running midplane moments: quantity q summed over the midplane lines in order
+  if (tid < HIST_Q && ((FA.mom_mask >> tid) & 1)) {
+    const gptr<const double> mp = gmem(FA.mparts);
+    double c = 0, s1 = 0, s2 = 0;
+    for (int zz = 0; zz < zrows; ++zz) {
+      const size_t o = ((size_t)zz * HIST_Q + tid) * 3;
+      c += mp[o];
+      s1 += mp[o + 1];
+      s2 += mp[o + 2];
+    }
+    const gptr<double> ms = gmem(FA.msum) + (size_t)tid * 3;
+    ms[0] += c;
+    ms[1] += s1;
+    ms[2] += s2;
+  }
   if (tid != 0) return;
   FinPart t = fp[0];
   for (int w2 = 1; w2 < NT / 64; ++w2) {

@@ -232,6 +232,8 @@ struct ZArgs {
 // diagnostics (fft.hip): per (y_j, z) line of the base grid, from the
 // spectral Tr c, u, v, w (in: [4][N+1][zrows][kx]), then one workgroup per
 // member for the step record.
+constexpr int HIST_MAX = 4096;  // largest number of histogram bins
+constexpr int HIST_Q = 8;       // histogrammed midplane quantities
 struct DRowArgs {
   Dims d;
   const double* in;
@@ -239,20 +241,23 @@ struct DRowArgs {
   FftPlan pl;
   const double* tw;
   const double* ydy;
+  const double* kx;
   DiagPart* parts;
-  // midplane histograms of quantity q = Tr c, u - U(0), v, w - W(0)
-  // (hbins[q] = 0: off), counts at hist + q (HIST_MAX + 2): [0] below hlo,
-  // [1 + floor((v - hlo) hscale)] inside, [hbins + 1] at or above the top and
-  // non-finite values; umean / wmean: the mean-mode u and w at the midplane
+  // midplane histograms of quantity q = Tr c, u - U(0), v, w - W(0), d_x u,
+  // d_z u, d_x w, d_z w (hbins[q] = 0: off), counts at hist + q (HIST_MAX + 2):
+  // [0] below hlo, [1 + floor((v - hlo) hscale)] inside, [hbins + 1] at or
+  // above the top and non-finite values; umean / wmean: the mean-mode u and w
+  // at the midplane; zgrad (3D): d_z u and d_z w of the midplane row,
+  // [2][z][kx] (physical in z, spectral in x); mparts: per midplane line z
+  // and quantity, the count, sum and sum of squares of its finite samples
   unsigned long long* hist;
-  double hlo[4], hscale[4];
-  int hbins[4];
-  const double *umean, *wmean;
+  double hlo[HIST_Q], hscale[HIST_Q];
+  int hbins[HIST_Q];
+  const double *umean, *wmean, *zgrad;
+  double* mparts;  // [zrows][HIST_Q][3]
   const int* skip;
   int blk0;
 };
-constexpr int HIST_MAX = 4096;  // largest number of histogram bins
-constexpr int HIST_Q = 4;       // histogrammed midplane quantities
 struct DFinArgs {
   Dims d;
   Phys p;
@@ -262,6 +267,11 @@ struct DFinArgs {
   DevScalars* sc;
   DiagRec* ring;
   int cap;
+  // running moments of the histogrammed midplane quantities: msum[q] +=
+  // the sums of mparts over the midplane lines, for q with bit q of mom_mask
+  const double* mparts;
+  double* msum;  // [HIST_Q][3]: samples, sum, sum of squares
+  int mom_mask;
 };
 // explicit assembly and CNAB2 right-hand sides (elem.hip); smean: mixed
 // path only, [nout][N+1] FP64 projection of the kx = kz = 0 column of the

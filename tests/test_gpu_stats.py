@@ -120,10 +120,12 @@ def test_ensemble_member_histogram_equals_single_run(P):
 @pytest.mark.parametrize("dims,precision,rel", [((2, 32, 33, 1), 0, 1e-11), ((3, 16, 17, 16), 0, 1e-11),
                                                 ((2, 32, 33, 1), 1, 2e-5)])
 def test_midplane_velocity_pdfs_match_oracle(P, dims, precision, rel):
-    """All four midplane histograms (Tr c, u - U(0), v, w - W(0)) in one run
-    against the oracle's samples, bin by bin up to samples within the two
-    sides' field difference of an edge (rel: the path's field tolerance
-    relative to each field's largest magnitude)."""
+    """All midplane histograms (Tr c, u - U(0), v, w - W(0), du/dx, du/dz,
+    dw/dx, dw/dz; 2D: those without w or d/dz) in one run against the
+    oracle's samples, bin by bin up to samples within the two sides' field
+    difference of an edge (rel: the path's field tolerance relative to each
+    field's largest magnitude), and the running moments (count exactly, sum
+    and sum of squares to the field tolerance) that standardise the PDFs."""
     dim, nx, ny, nz = dims
     g = Grid(dim, nx, ny, nz)
     prm = dict(wi=20.0, dt=1e-3)
@@ -140,6 +142,11 @@ def test_midplane_velocity_pdfs_match_oracle(P, dims, precision, rel):
         top[2] = max(top.get(2, 0.0), float(np.abs(o.base_grid(o.q["v"])).max()))
         if dim == 3:
             top[3] = max(top.get(3, 0.0), float(np.abs(o.base_grid(o.q["w"])).max()))
+        # the gradients carry the error of u and w times at most the largest wavenumber
+        kmax = max(float(o.kx.max()), float(np.abs(o.kz).max()))
+        for k in (4, 5, 6, 7):
+            if k in ref:
+                top[k] = max(top.get(k, 0.0), kmax * top[1 if k in (4, 5) else 3] + float(np.abs(ref[k][-1]).max()))
     ref = {k: np.concatenate(v) for k, v in ref.items()}
     nb = 32
     sim = P.Sim(P.make_grid(dim, nx, ny, nz), P.make_params(precision=precision, **prm), seed=seed, amp=amp)
@@ -151,6 +158,7 @@ def test_midplane_velocity_pdfs_match_oracle(P, dims, precision, rel):
     print("case midplane pdfs %s p%d" % (dims, precision), flush=True)
     sim.step(nsteps)
     got = {k: sim.midplane_pdf(k) for k in ref}
+    mom = {k: sim.midplane_moments(k) for k in ref}
     tr = sim.midplane_histogram()
     sim.close()
     assert np.array_equal(tr, got[0])
@@ -164,12 +172,19 @@ def test_midplane_velocity_pdfs_match_oracle(P, dims, precision, rel):
         diff = int(np.abs(got[k].astype(np.int64) - want.astype(np.int64)).sum())
         print("quantity %d: L1 difference %d, samples near an edge %d" % (k, diff, ties), flush=True)
         assert diff <= 2 * ties, (k, diff, ties)
+        n, s1, s2 = stats.moments(v)
+        gn, gmean, gstd = mom[k]
+        assert gn == n
+        mean, std = s1 / n, np.sqrt(max(s2 / n - (s1 / n) ** 2, 0.0))
+        assert abs(gmean - mean) <= 4 * rel * top[k] + 1e-14, (k, gmean, mean)
+        assert abs(gstd - std) <= 4 * rel * top[k] + 1e-14, (k, gstd, std)
 
 
 def test_midplane_pdf_arguments(P):
     print("case midplane pdf arguments", flush=True)
     sim = P.Sim(P.make_grid(2, 16, 17), P.make_params(), seed=1, amp=1e-3)
-    for q, lo, hi, nb in ((3, -1.0, 1.0, 8), (4, -1.0, 1.0, 8), (-1, -1.0, 1.0, 8), (1, 1.0, -1.0, 8),
+    for q, lo, hi, nb in ((3, -1.0, 1.0, 8), (5, -1.0, 1.0, 8), (6, -1.0, 1.0, 8), (7, -1.0, 1.0, 8),
+                          (8, -1.0, 1.0, 8), (-1, -1.0, 1.0, 8), (1, 1.0, -1.0, 8),
                           (2, -1.0, 1.0, P.PCS_HIST_MAX + 1)):
         with pytest.raises(P.PcsError):
             sim.midplane_pdf_setup(q, lo, hi, nb)
@@ -179,6 +194,10 @@ def test_midplane_pdf_arguments(P):
     assert int(a.sum()) == 3 * 16
     with pytest.raises(P.PcsError):       # quantity 2 is off
         sim.midplane_pdf(2)
+    with pytest.raises(P.PcsError):
+        sim.midplane_moments(2)
+    sim.midplane_pdf_setup(4, -1.0, 1.0, 8)  # du/dx exists in 2D
+    assert sim.midplane_moments(4)[0] == 0
     sim.midplane_pdf_setup(1, -1.0, 1.0, 8)   # setup clears the counts
     assert int(sim.midplane_pdf(1).sum()) == 0
     sim.close()

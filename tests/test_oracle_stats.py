@@ -47,3 +47,40 @@ def test_histogram_below_three_matches_midplane_count():
         n3 += o.diagnostics()["mid_n_lt3"]
     assert int(tot[:nb // 2 + 1].sum()) == n3
     assert int(tot.sum()) == 4 * g.nx
+
+
+def test_midplane_gradients_by_direct_sums():
+    """The midplane velocity gradients of oracle.stats (spectral derivatives
+    through the oracle's base-grid transform) against direct Fourier sums of
+    i kx u-hat and i kz u-hat (and of w) at every base-grid point of the
+    midplane, from the Chebyshev series of each mode evaluated at y = 0 with
+    numpy.polynomial; the fluctuations u - U(0), w - W(0) likewise."""
+    from tests.inputs import random_state
+    from tests.test_oracle_assembly_pins import SField
+    for dims in ((3, 12, 17, 8), (2, 16, 17, 1)):
+        dim, nx, ny, nz = dims
+        o = Oracle(Grid(dim, nx, ny, nz), Params(), seed=None)
+        o.set_state(random_state(dim, nx, ny, nz, seed=12, amp=1.0))
+        got = stats.midplane_quantities(o)
+        xs = np.arange(nx) * o.g.lx / nx
+        zs = np.arange(nz) * o.g.lz / nz if dim == 3 else np.zeros(1)
+        y0 = np.zeros(1)
+        u = SField.from_lobatto(o.q["u"], o.kx, o.kz)
+        want = {4: u.dx().eval(xs, y0, zs)[0]}
+        mean_u = u.coef[:, 0, 0].real
+        import numpy.polynomial.chebyshev as npc
+        want[1] = u.eval(xs, y0, zs)[0] - npc.chebval(0.0, mean_u)
+        if dim == 3:
+            w = SField.from_lobatto(o.q["w"], o.kx, o.kz)
+            want[5] = u.dz().eval(xs, y0, zs)[0]
+            want[6] = w.dx().eval(xs, y0, zs)[0]
+            want[7] = w.dz().eval(xs, y0, zs)[0]
+            want[3] = w.eval(xs, y0, zs)[0] - npc.chebval(0.0, w.coef[:, 0, 0].real)
+        for k, v in want.items():
+            g = got[k].reshape(v.shape)
+            sc = np.abs(v).max()
+            assert sc > 1e-3, (dims, k)
+            assert np.abs(g - v).max() <= 1e-12 * sc, (dims, k, np.abs(g - v).max() / sc)
+        # moments are the plain sums of the finite samples
+        n, s1, s2 = stats.moments(np.array([1.0, 2.0, np.nan, 4.0]))
+        assert (n, s1, s2) == (3.0, 7.0, 21.0)
