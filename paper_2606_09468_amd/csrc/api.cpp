@@ -110,7 +110,12 @@ struct JobList {
     form = f;
     h = forms[f];
   }
-  bool allowed(int c) const { return form == 0 || gemm_cfg_parity(c); }
+  // a configuration the table's form can use (the B-stationary ones: parity
+  // products only, and only while the whole K range of a panel fits the LDS)
+  bool allowed(int c) const {
+    if (gemm_cfg_bst(c)) return form == 1 && gemm_lds_bytes(type, h.data(), n(), c) <= GEMM_LDS_MAX;
+    return form == 0 || gemm_cfg_parity(c);
+  }
   // Tile configuration before tuning: the largest tile that still gives
   // every CU a workgroup.
   void prepare() {
@@ -1417,6 +1422,7 @@ pcs_status autotune(Batch* b) {
     auto key = jl->key();
     key.push_back(forms);
     key.push_back(only);
+    key.push_back(GEMM_NCFG);  // the candidate set: choices made among fewer configurations do not apply
     auto it = tune_cache().find(key);
     int best = -1, bestf = 0;
     if (it != tune_cache().end()) {

@@ -609,13 +609,6 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   // twiddle table in LDS (behind the data), read by every radix pass
   cx<T>* twl = P + lds_span<true>((size_t)XS::NP * L);
   typedef typename V2<T>::type T2;
-  {
-    const gptr<const T2> tw = gmem(static_cast<const T2*>(XA.tw));
-    for (int i = tid; i < L; i += NTH) {
-      const T2 t = tw[i];
-      twl[i] = cx<T>{t[0], t[1]};
-    }
-  }
   const short* src = XSRC[DIM - 2];
   const short* dxf = XDX[DIM - 2];
   // each wave packs whole field pairs, so the field tables are read once per
@@ -624,18 +617,13 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   {
     constexpr int b0 = 0, nb = XS::NP;
     const XV X = PV;
-    // a wave clears, fills and transforms the pairs it owns, in LDS order,
-    // so only the twiddles need a workgroup barrier before the transforms
-    for (int q = wave; q < nb; q += NW)
-      for (int e = lane; e < L; e += 64) X[q * L + e] = cx<T>{0, 0};
-    pass_sync<true>();
     // the wave's items are (pair q = wave + NW i, block of 64 kx); G items'
     // loads are issued before any of them is packed
     const int nkb = (nkx + 63) >> 6;
     const int items = max(0, (nb - wave + NW - 1) / NW) * nkb;
     constexpr int G = (sizeof(T) == 4 && DIM == 3) ? 8 : 4;  // measured: 8 costs FP64 and 2D more registers than it saves
-    for (int i0 = 0; i0 < items; i0 += G) {
-      T2 va[G], vb[G];
+    T2 va[G], vb[G];
+    auto load_items = [&](int i0) {
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int it = i0 + u, qi = it / nkb, k = lane + 64 * (it - qi * nkb);
@@ -646,6 +634,28 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
           if (fb < XS::NREAL) vb[u] = *reinterpret_cast<gptr<const T2>>(base + src[fb] * fstride + 2 * k);
         }
       }
+    };
+    // loads in issue order: the twiddles (a few per thread), then the first
+    // items, whose latency the twiddle stores and the clearing of the pairs
+    // then overlap (loads complete in order, so the twiddles come first)
+    constexpr int TWN = (64 * cover(XMVW) + NTH - 1) / NTH;  // the longest line xpencil_lds_bytes admits
+    T2 tv[TWN];
+    {
+      const gptr<const T2> tw = gmem(static_cast<const T2*>(XA.tw));
+#pragma unroll
+      for (int r = 0; r < TWN; ++r) tv[r] = tid + r * NTH < L ? tw[tid + r * NTH] : T2{0, 0};
+    }
+    load_items(0);
+#pragma unroll
+    for (int r = 0; r < TWN; ++r)
+      if (tid + r * NTH < L) twl[tid + r * NTH] = cx<T>{tv[r][0], tv[r][1]};
+    // a wave clears, fills and transforms the pairs it owns, in LDS order,
+    // so only the twiddles need a workgroup barrier before the transforms
+    for (int q = wave; q < nb; q += NW)
+      for (int e = lane; e < L; e += 64) X[q * L + e] = cx<T>{0, 0};
+    pass_sync<true>();
+    for (int i0 = 0; i0 < items; i0 += G) {
+      if (i0 > 0) load_items(i0);
 #pragma unroll
       for (int u = 0; u < G; ++u) {
         const int it = i0 + u, qi = it / nkb, k = lane + 64 * (it - qi * nkb);

@@ -139,8 +139,8 @@ template <>
 struct LCfg<13> {
   static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 1, PKC = 32;
 };
-constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 32, 32, 64, 64};
-constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 32, 32, 64, 64};
+constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 32, 32, 64, 64, 0, 0};
+constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 32, 32, 64, 64, 32, 64};
 // LDS (in elements of the compute precision) of an LDS-tiled configuration:
 // the plain panels, the parity panels (A: BM rows of PKC, B: both halves,
 // rows of BN + 4) and the larger of the two.  The kernel takes its LDS
@@ -263,7 +263,8 @@ int gemm_prepare(GemmJob* jobs, int njobs, int cfg) {
   int t = 0;
   for (int j = 0; j < njobs; ++j) {
     const int rows = jobs[j].kind != PAR_NONE ? bm / 2 : bm;  // a parity tile: BM/2 rows of E and of O
-    jobs[j].tiles_m = (jobs[j].m + rows - 1) / rows;
+    // the B-stationary configurations cover every row of a product per tile
+    jobs[j].tiles_m = gemm_cfg_bst(cfg) ? 1 : (jobs[j].m + rows - 1) / rows;
     const int tn = (jobs[j].n + bn - 1) / bn;
     jobs[j].tile0 = t;
     t += jobs[j].tiles_m * tn;
@@ -746,6 +747,115 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
   store_par<T, TC, RB, CB>(jp, acc, accO, row0, col0 + wc, lk, l16);
 }
 
+// ------------------------------------------------------------ B-stationary parity kernel
+// One workgroup per (product, panel of BN output columns).  The folded (or
+// split) B panel of the whole K range is staged into LDS once, converted to
+// the compute precision (K padded with zero rows to a multiple of 16); the
+// four waves then sweep the product's 16-row blocks of E and O (block r by
+// wave r mod 4), each over all BN columns, with the A fragments streamed from
+// global memory (the operators are small and stay in L2) one 16-wide k block
+// ahead of the multiply.  Lane group g takes k = 16 b + 4 g + s at MFMA step
+// s of block b, so a lane's A fragment of a block is one vector load.  Every
+// element of B is read from HBM once per product, where the LDS-tiled kernel
+// reads it once per row tile.
+template <int BN>
+constexpr int bst_pitch() {
+  return BN + 4;
+}
+template <typename T, typename TB, typename TC, int BN>
+__device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __restrict__ jp, int t, double* smem) {
+  constexpr int CB = BN / 16, PB = bst_pitch<BN>();
+  typedef typename Vec<T>::v4 V4;
+  const int col0 = (t - jp->tile0) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int M = jp->m, N = jp->n, K = jp->k, KF = jp->kf, lda = jp->lda, ldb = jp->ldb;
+  const int K16 = (K + 15) & ~15;
+  const bool fold = jp->kind != PAR_SPLIT_UNFOLD;
+  const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
+  T* Be = reinterpret_cast<T*>(smem);
+  T* Bo = Be + (size_t)K16 * PB;
+  const gptr<const TB> B = gmem(static_cast<const TB*>(jp->B));
+  // stage the panel, columns fastest (coalesced rows of B), four elements'
+  // loads in flight per thread before their LDS stores
+  constexpr int U = 4;
+  const int tot = K16 * BN;
+  for (int e0 = 0; e0 < tot; e0 += U * 256) {
+    TB x[U], y[U];
+    int kk[U], c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * 256 + tid;
+      kk[u] = e / BN;
+      c[u] = e - kk[u] * BN;
+      const int gc = col0 + c[u];
+      x[u] = y[u] = TB(0);
+      if (e < tot && kk[u] < K && gc < N && !(zm && gc < 2)) {
+        x[u] = B[(size_t)kk[u] * ldb + gc];
+        const int kr = fold ? KF - 1 - kk[u] : K + kk[u];
+        if (fold ? kr > kk[u] : kr < KF) y[u] = B[(size_t)kr * ldb + gc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + u * 256 + tid >= tot) continue;
+      const int o = kk[u] * PB + c[u];
+      if (fold) {
+        Be[o] = T(x[u] + y[u]);
+        Bo[o] = T(x[u] - y[u]);
+      } else {
+        Be[o] = T(x[u]);
+        Bo[o] = T(y[u]);
+      }
+    }
+  }
+  __syncthreads();
+  const gptr<const T> A = gmem(static_cast<const T*>(jp->A));
+  const gptr<const T> A2 = gmem(static_cast<const T*>(jp->A2));
+  const int nrb = (M + 15) >> 4, nkb = K16 >> 4;
+  const T* be = Be + (size_t)(4 * lk) * PB + l16;
+  const T* bo = Bo + (size_t)(4 * lk) * PB + l16;
+  for (int rb = wave; rb < nrb; rb += 4) {
+    V4 E[1][CB], O[1][CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) E[0][cb] = O[0][cb] = V4{0, 0, 0, 0};
+    // A rows are allocated (zero) up to gemm_rows(m) and lda = K16
+    const gptr<const V4> ae = reinterpret_cast<gptr<const V4>>(A + (size_t)(rb * 16 + l16) * lda + 4 * lk);
+    const gptr<const V4> ao = reinterpret_cast<gptr<const V4>>(A2 + (size_t)(rb * 16 + l16) * lda + 4 * lk);
+    V4 xe = ae[0], xo = ao[0];
+    for (int b = 0; b < nkb; ++b) {
+      const V4 ce = xe, co = xo;
+      if (b + 1 < nkb) {
+        xe = ae[4 * (b + 1)];
+        xo = ao[4 * (b + 1)];
+      }
+      const T* pe = be + (size_t)(16 * b) * PB;
+      const T* po = bo + (size_t)(16 * b) * PB;
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          E[0][cb] = mfma(ce[s2], pe[s2 * PB + cb * 16], E[0][cb]);
+          O[0][cb] = mfma(co[s2], po[s2 * PB + cb * 16], O[0][cb]);
+        }
+    }
+    store_par<T, TC, 1, CB>(jp, E, O, rb * 16, col0, lk, l16);
+  }
+}
+
+template <typename T, typename TB, typename TC, int BN>
+__global__ __launch_bounds__(256) void gemm_bst_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap,
+                                                       int total) {
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  const int t = xcd_tile(blockIdx.x, total);
+  const GemmJob* jp = tile_job(jobs, tmap, t);
+  if (masked(jp->skip)) return;
+  if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
+    bst_body<double, double, double, BN>(jp, t, smem);
+  else
+    bst_body<T, TB, TC, BN>(jp, t, smem);
+}
+
 // PAR: the table holds parity products only (else plain ones only): one
 // body per kernel, so neither pays for the other's registers.
 template <typename T, typename TB, typename TC, int CFG, bool PAR>
@@ -803,6 +913,14 @@ void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, bo
     PCS_GEMM_LDS(11)
     PCS_GEMM_LDS(12)
     PCS_GEMM_LDS(13)
+    case 14:
+      if (parity)
+        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 32>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
+      break;
+    case 15:
+      if (parity)
+        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 64>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
+      break;
     default: break;
   }
 #undef PCS_GEMM_REG
@@ -812,6 +930,7 @@ void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, bo
 }  // namespace
 
 bool gemm_cfg_parity(int cfg) { return cfg >= 4 && cfg < GEMM_NCFG; }
+bool gemm_cfg_bst(int cfg) { return cfg == 14 || cfg == 15; }
 
 namespace {
 template <int CFG>
@@ -842,6 +961,13 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
       case 11: x = lds_form<11>(par, es, half); break;
       case 12: x = lds_form<12>(par, es, half); break;
       case 13: x = lds_form<13>(par, es, half); break;
+      case 14:
+      case 15: {
+        // the whole K range of the folded panel: two halves of K16 rows
+        const size_t pitch = cfg == 14 ? bst_pitch<32>() : bst_pitch<64>();
+        x = par ? 2 * (size_t)((jobs[j].k + 15) & ~15) * pitch * es + 16 : ~(size_t)0 >> 1;
+        break;
+      }
       default: break;
     }
     b = x > b ? x : b;
@@ -849,7 +975,20 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
   return b;
 }
 
-hipError_t gemm_set_attributes() { return hipSuccess; }
+hipError_t gemm_set_attributes() {
+  // the B-stationary kernels stage a whole K range: up to the CU's 160 KB
+  const void* k[] = {
+      (const void*)gemm_bst_kernel<double, double, double, 32>, (const void*)gemm_bst_kernel<double, double, double, 64>,
+      (const void*)gemm_bst_kernel<float, double, float, 32>,   (const void*)gemm_bst_kernel<float, double, float, 64>,
+      (const void*)gemm_bst_kernel<float, float, double, 32>,   (const void*)gemm_bst_kernel<float, float, double, 64>,
+      (const void*)gemm_bst_kernel<double, double, float, 32>,  (const void*)gemm_bst_kernel<double, double, float, 64>,
+      (const void*)gemm_bst_kernel<double, float, double, 32>,  (const void*)gemm_bst_kernel<double, float, double, 64>};
+  for (const void* f : k) {
+    const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LDS_MAX);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
 
 void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_tiles, int cfg, bool parity,
               size_t lds, hipStream_t s) {

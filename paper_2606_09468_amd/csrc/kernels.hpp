@@ -91,8 +91,12 @@ constexpr int MAX_JOBS = 64;
 // LDS-tiled kernel (operand chunks shared by the four waves through LDS):
 // 4: 32 x 32, 5: 64 x 32, 6: 64 x 64, 7: 128 x 64 (double-buffered chunks),
 // 8: 32 x 32, 9: 64 x 32 (one buffer, chunks of 64 k), and for small tables
-// deeper parity chunks: 10, 11: 32 x 32, 12, 13: 64 x 64.
-constexpr int GEMM_NCFG = 14;
+// deeper parity chunks: 10, 11: 32 x 32, 12, 13: 64 x 64.  B-stationary
+// kernel (parity products only; a workgroup stages the whole K range of a
+// panel of B once and computes every output row of it): 14: 32 and 15: 64
+// columns per panel.
+constexpr int GEMM_NCFG = 16;
+constexpr size_t GEMM_LDS_MAX = 160 * 1024;  // LDS a workgroup may take
 inline int gemm_lda(int k) { return (k + 15) & ~15; }
 inline int gemm_rows(int m) { return (m + 127) & ~127; }
 
@@ -101,8 +105,11 @@ inline int gemm_rows(int m) { return (m + 127) & ~127; }
 // is <= t; the kernels read that job index from a tile map (one int per
 // tile) built by the caller.
 int gemm_prepare(GemmJob* jobs, int njobs, int cfg);
-// Whether configuration cfg evaluates parity products (the LDS-tiled ones).
+// Whether configuration cfg evaluates parity products (the LDS-tiled and
+// B-stationary ones), and whether it is B-stationary (one tile per column
+// panel of a product, every row; its LDS grows with K).
 bool gemm_cfg_parity(int cfg);
+bool gemm_cfg_bst(int cfg);
 // LDS bytes per workgroup of the LDS-tiled configuration cfg for a table of
 // precision combination t (0 for the register-direct ones): the panels of
 // the largest product form and compute precision in the table, so that a

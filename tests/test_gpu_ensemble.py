@@ -207,3 +207,68 @@ def test_single_run_stops_at_its_blowup_step(P):
         sim.step(1)
     assert e.value.status == P.PCS_ERR_STATE
     sim.close()
+
+
+def test_full_ensemble_every_size_class_against_oracle(P):
+    """The 64-member uneven ensemble (mixed precision, dt = 5e-4) over 5
+    steps: the first member of each of its 19 (Ny, Nx) size classes against
+    its own FP64 oracle run with the mixed bar, and every member's records
+    finite and advanced.  The Nx = 512 members run the 768-point x
+    transforms, the Ny = 97 and 193 members padded wall-normal grids of 145
+    and 289 points."""
+    members = ensemble_members()
+    nsteps = 5
+    print("case full ensemble, one member per size class", flush=True)
+    grids = [P.make_grid(2, nx, ny) for ny, nx, _, _ in members]
+    params = [P.make_params(wi=wi, dt=5e-4, precision=1) for _, _, wi, _ in members]
+    ens = P.Ensemble(grids, params, [s for _, _, _, s in members], amp=1e-3)
+    ens.step(nsteps)
+    firsts = {}
+    for r, (ny, nx, _, _) in enumerate(members):
+        firsts.setdefault((ny, nx), r)
+        recs, st = ens.diagnostics(r)
+        assert st == P.PCS_OK and len(recs) == nsteps and recs[-1]["blowup"] == 0
+    assert len(firsts) == 19
+    for (ny, nx), r in sorted(firsts.items()):
+        _, _, wi, seed = members[r]
+        g = Grid(2, nx, ny)
+        o = Oracle(g, Params(wi=wi, dt=5e-4), seed=seed, amp=1e-3)
+        o.step(nsteps)
+        errs = fluct_errors(ens.get_state(r), o.get_state(), g)
+        print("member %d %dx%d: worst fluctuation %.1e, full %.1e" % (
+            r, nx, ny, max(v[0] for v in list(errs.values())[:6]), max(v[1] for v in list(errs.values())[:6])),
+            flush=True)
+        for name in ("u", "v", "phi", "cxx", "cxy", "cyy"):
+            fl, full = errs[name]
+            assert fl < 2e-4 and full < 2e-5, (r, nx, ny, name, fl, full)
+    ens.close()
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_member_512x193_fifty_steps_against_oracle(P, precision):
+    """Member 12 of the ensemble draw (Nx = 512, Ny = 193, Wi = 87.15, seed
+    4012) over 50 steps, the full state against its oracle run: FP64 with
+    the single-run tolerances (N = 192), mixed with the mixed bar."""
+    members = ensemble_members()
+    ny, nx, wi, seed = members[12]
+    assert (ny, nx) == (193, 512)
+    nsteps = 50
+    print("case member 12 512x193 p%d x%d" % (precision, nsteps), flush=True)
+    g = Grid(2, nx, ny)
+    o = Oracle(g, Params(wi=wi, dt=5e-4), seed=seed, amp=1e-3)
+    o.step(nsteps)
+    sim = P.Sim(P.make_grid(2, nx, ny), P.make_params(wi=wi, dt=5e-4, precision=precision), seed=seed, amp=1e-3)
+    sim.step(nsteps)
+    recs, st = sim.diagnostics()
+    a = sim.get_state()
+    sim.close()
+    assert st == P.PCS_OK and len(recs) == nsteps
+    N = ny - 1
+    if precision == 0:
+        check_state(a, o.get_state(), g, tol_prognostic(N), tol_history(N), "member 12 FP64")
+        check_diag(recs, o, o.trace_c(), "member 12 FP64")
+    else:
+        errs = fluct_errors(a, o.get_state(), g)
+        for name in ("u", "v", "phi", "cxx", "cxy", "cyy"):
+            fl, full = errs[name]
+            assert fl < 2e-4 and full < 2e-5, (name, fl, full)

@@ -177,8 +177,9 @@ def _oracle_run(name, g, prm, n):
 
 
 # tile configurations of the product kernels: 0-3 register-direct (plain
-# form only), 4-13 LDS-tiled (plain and parity forms)
-GEMM_CFGS = list(range(14))
+# form only), 4-13 LDS-tiled (plain and parity forms), 14-15 B-stationary
+# (parity form only)
+GEMM_CFGS = list(range(16))
 
 
 @pytest.mark.parametrize("cfg", GEMM_CFGS)
@@ -188,7 +189,7 @@ def test_every_tile_configuration_matches_oracle(P, cfg, monkeypatch):
     the oracle: FP64 2D with odd padded sizes (N = 24: M + 1 = 37) and 3D,
     and a mixed-precision 2D run (FP32 tables mixing FP64 products)."""
     monkeypatch.setenv("PCS_GEMM_CFG", str(cfg))
-    forms = ["plain", "parity"] if cfg >= 4 else ["plain"]
+    forms = ["parity"] if cfg >= 14 else (["plain", "parity"] if cfg >= 4 else ["plain"])
     cases = (("2D 24x25", Grid(2, 24, 25), dict(wi=20.0, dt=1e-3), 10),
              ("3D 16x17x16", Grid(3, 16, 17, 16), dict(wi=20.0, dt=1e-3), 5))
     for form in forms:
