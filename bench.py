@@ -60,8 +60,8 @@ def stage_work(w, precision, split):
     nyin = 9 if dim == 2 else 17
     nh = 1 + (dim - 2) + nc
     mixed = precision != 0
-    f32_state = precision == 1            # the state -> padded-grid products in FP32
-    f32_proj = precision == 1
+    f32_state = precision in (1, 3)       # the state -> padded-grid products in FP32 (3: compensated)
+    f32_proj = precision in (1, 3)
     tb = 8 if mixed else 16               # bytes per complex value in the transforms
     pk = lambda f32: MFMA_F32_TFS if f32 else MFMA_F64_TFS
     out = {}
@@ -141,7 +141,7 @@ def traffic_for(kernel, workload, precision):
     digest = hashlib.sha256(src).hexdigest()[:16]
     for line in open(path):
         parts = [x.strip() for x in line.strip().strip("|").split("|")]
-        pname = {0: "fp64", 1: "mixed", 2: "mixed64y"}.get(precision, str(precision))
+        pname = {0: "fp64", 1: "mixed", 2: "mixed64y", 3: "mixedcomp"}.get(precision, str(precision))
         if len(parts) >= 6 and parts[0] == kernel and parts[1] == workload and parts[2] == pname:
             if parts[5] != digest:
                 return None
@@ -253,8 +253,9 @@ def main():
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["c4"],
                     help="c5 (default): 3D 256x257x128, the largest single-GPU workload; "
                          "c4: the 64-member uneven 2D ensemble, one graph launch per step")
-    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed", "mixed64y"],
-                    help="both: time mixed (value) and FP64 (reported beside it)")
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed", "mixed64y", "mixedcomp"],
+                    help="both: time mixed (value) and FP64 (reported beside it); mixed64y: FP64 wall-normal "
+                         "transforms; mixedcomp: error-compensated FP32 wall-normal transforms")
     ap.add_argument("--stage-steps", type=int, default=10)
     ap.add_argument("--stage-reps", type=int, default=1,
                     help="launches of each stage per profiled step (1: every kernel runs once per step, on the "
@@ -306,7 +307,7 @@ def main():
         return bench_ensemble(args, P)
     w = WORKLOADS[args.workload]
     grid = P.make_grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
-    precs = {"both": [1, 0], "fp64": [0], "mixed": [1], "mixed64y": [2]}[args.precision]
+    precs = {"both": [1, 0], "fp64": [0], "mixed": [1], "mixed64y": [2], "mixedcomp": [3]}[args.precision]
     timed = {}
     for prec in precs:
         prm = P.make_params(wi=w["wi"], dt=w["dt"], precision=prec, scheme=args.scheme_id)
@@ -352,10 +353,11 @@ def main():
     line = {
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64"}[head], "data": "synthetic",
+        "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64", 3: "f32+f64"}[head], "data": "synthetic",
         "config": {"workload": w["desc"] if args.scheme_id == 0 else w["desc"].replace("CNAB2", "SBDF4"),
                    "grid": [w["nx"], w["ny"], w["nz"]],
-                   "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms"}[head],
+                   "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms",
+                                 3: "mixed, error-compensated FP32 y-transforms"}[head],
                    "parallelism": "single GPU"},
         "grid_point_updates_per_s": sps * points,
         "roofline": roof,
@@ -385,7 +387,7 @@ def main():
             a, d = gstates[prec]
             errs = state_errors(a, ostate, w)
             e = odiag
-            line["error_vs_oracle"][{0: "fp64", 1: "mixed", 2: "mixed64y"}[prec]] = {
+            line["error_vs_oracle"][{0: "fp64", 1: "mixed", 2: "mixed64y", 3: "mixedcomp"}[prec]] = {
                 "steps": args.cpu_steps + 1,
                 "max_rel_velocity": max(errs[k] for k in errs if k in ("u", "v", "w", "phi", "g")),
                 "max_rel_conformation": max(errs[k] for k in errs if k.startswith("c")),
@@ -426,7 +428,7 @@ def bench_ensemble(args, P):
     member advanced one step per graph launch) and summed point updates."""
     import torch
     members = ensemble_members(ENSEMBLE["count"], ENSEMBLE["seed"])
-    prec = {"both": 1, "fp64": 0, "mixed": 1, "mixed64y": 2}[args.precision]
+    prec = {"both": 1, "fp64": 0, "mixed": 1, "mixed64y": 2, "mixedcomp": 3}[args.precision]
     grids = [P.make_grid(2, nx, ny) for ny, nx, _, _ in members]
     params = [P.make_params(wi=wi, dt=ENSEMBLE["dt"], precision=prec, scheme=args.scheme_id)
               for _, _, wi, _ in members]
@@ -452,10 +454,11 @@ def bench_ensemble(args, P):
     line = {
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64"}[prec], "data": "synthetic",
+        "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64", 3: "f32+f64"}[prec], "data": "synthetic",
         "config": {"workload": ENSEMBLE["desc"] if args.scheme_id == 0 else ENSEMBLE["desc"].replace("CNAB2", "SBDF4"),
                    "members": len(members), "base_points": points,
-                   "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms"}[prec],
+                   "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms",
+                                 3: "mixed, error-compensated FP32 y-transforms"}[prec],
                    "parallelism": "single GPU, one graph launch per ensemble step"},
         "grid_point_updates_per_s": sps * points,
         "roofline": None,

@@ -114,11 +114,18 @@ struct JobList {
   // products only, and only while the whole K range of a panel fits the LDS)
   bool allowed(int c) const {
     if (gemm_cfg_bst(c)) return form == 1 && gemm_lds_bytes(type, h.data(), n(), c) <= GEMM_LDS_MAX;
+    if (gemm_type_comp(type)) return false;  // error-compensated tables: B-stationary parity products only
     return form == 0 || gemm_cfg_parity(c);
   }
   // Tile configuration before tuning: the largest tile that still gives
   // every CU a workgroup.
   void prepare() {
+    if (gemm_type_comp(type)) {
+      // the compensated products exist in the parity form of the B-stationary kernel only
+      use(1);
+      set_cfg(allowed(14) ? 14 : 15);
+      return;
+    }
     h = forms[form];
     int c = 7;  // configurations 0 .. 7 grow with the tile
     while (c > 0 && (!allowed(c) || gemm_prepare(h.data(), n(), c) < 256)) --c;
@@ -223,6 +230,8 @@ struct Member {
   // V^-1 (fold / split), V and D V (split / unfold)
   double *IMNp[2], *DMNp[2], *D2p[2], *Dp[2], *PNMp[2], *DPp[2], *V4p[2], *V5p[2], *DVp[2], *wVp[2];
   float *IMN32p[2], *DMN32p[2], *PNM32p[2], *DP32p[2];
+  // precision 3: FP32 tails of those halves (operator = FP32 head + tail)
+  float *IMN32lp[2], *DMN32lp[2], *PNM32lp[2], *DP32lp[2];
   double *twx, *twz, *twbx, *twbz;
   double *infl, *state, *Yin, *Zin, *Zout, *Yout, *S, *DN, *Dc, *D2buf, *hgn, *hvn;
   // SBDF4 history: state fields and explicit terms of step k in slot k mod 4
@@ -381,6 +390,11 @@ void carve(Member* m, Carve& c) {
       m->DMN32p[q] = m->prec != 0 ? c.take<float>(opsz(mh, nh)) : nullptr;
       m->PNM32p[q] = m->prec != 0 ? c.take<float>(opsz(nh, mh)) : nullptr;
       m->DP32p[q] = m->prec != 0 ? c.take<float>(opsz(nh, mh)) : nullptr;
+      const bool comp = m->prec == 3;
+      m->IMN32lp[q] = comp ? c.take<float>(opsz(mh, nh)) : nullptr;
+      m->DMN32lp[q] = comp ? c.take<float>(opsz(mh, nh)) : nullptr;
+      m->PNM32lp[q] = comp ? c.take<float>(opsz(nh, mh)) : nullptr;
+      m->DP32lp[q] = comp ? c.take<float>(opsz(nh, mh)) : nullptr;
     }
   }
   m->lam = c.take<double>(ni);
@@ -459,7 +473,7 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   if (!(p->re > 0) || !(p->wi > 0) || !(p->beta >= 0 && p->beta <= 1) || !(p->kappa >= 0) || !(p->dt > 0))
     return PCS_ERR_ARG;
   if (p->forcing != 0 && p->forcing != 1) return PCS_ERR_ARG;
-  if (p->precision < 0 || p->precision > 2) return PCS_ERR_ARG;
+  if (p->precision < 0 || p->precision > 3) return PCS_ERR_ARG;
   if (p->scheme != 0 && p->scheme != 1) return PCS_ERR_ARG;
   if (!valid_fft(3 * g->nx / 2) || !valid_fft(g->nx)) return PCS_ERR_UNSUPPORTED;
   if (g->dim == 3 && (!valid_fft(3 * g->nz / 2) || !valid_fft(g->nz))) return PCS_ERR_UNSUPPORTED;
@@ -667,8 +681,11 @@ void build_jobs(Member* m) {
   // odd parts): half rows mh / nh, half columns nh / mh, ne eigen pairs.
   const int mh = (m1 + 1) / 2, nh = (n1 + 1) / 2, ne = (ni + 1) / 2;  // ne: even eigenvectors
   JobList& g1 = m->G1;
-  g1.type = mixed ? (m->prec == 1 ? GEMM_FDF : GEMM_DDF) : GEMM_DDD;
-  const bool f32ops = mixed && m->prec == 1;
+  // precision 1: FP32; 2: FP64; 3: error-compensated FP32 (FP32 operator
+  // heads and tails, parity form only)
+  const bool comp = m->prec == 3;
+  g1.type = mixed ? (m->prec == 2 ? GEMM_DDF : (comp ? GEMM_CDF : GEMM_FDF)) : GEMM_DDD;
+  const bool f32ops = mixed && m->prec != 2;
   const void* I = f32ops ? (const void*)m->IMN32 : (const void*)m->IMN;
   const void* DI = f32ops ? (const void*)m->DMN32 : (const void*)m->DMN;
   const void* Ip[2] = {f32ops ? (const void*)m->IMN32p[0] : m->IMNp[0], f32ops ? (const void*)m->IMN32p[1] : m->IMNp[1]};
@@ -679,11 +696,19 @@ void build_jobs(Member* m) {
   const int zm = mixed ? GEMM_ZERO_MEAN : 0;
   const int nvel = d.dim;
   // values (centrosymmetric operator) and d/dy (centro-antisymmetric) on the padded grid
+  auto tails = [&](JobList& jl, float* const (&lo)[2]) {
+    if (comp) {
+      jl.forms[1].back().Alo = lo[0];
+      jl.forms[1].back().A2lo = lo[1];
+    }
+  };
   auto val = [&](const double* src, void* dst) {
     g1.addp(PAR_FOLD_UNFOLD, I, Ip[0], Ip[1], src, cw, dst, cw, mh, cw, nh, m1, n1, +1, zm);
+    tails(g1, m->IMN32lp);
   };
   auto dy = [&](const double* src, void* dst) {
     g1.addp(PAR_FOLD_UNFOLD, DI, DIp[0], DIp[1], src, cw, dst, cw, mh, cw, nh, m1, n1, -1, zm);
+    tails(g1, m->DMN32lp);
   };
   for (int a = 0; a < nvel; ++a) val(st + a * fs, yf(a));
   for (int a = 0; a < d.nc; ++a) val(st + (FC + a) * fs, yf(nvel + a));
@@ -735,18 +760,23 @@ void build_jobs(Member* m) {
              -1);
   // G2: projection of the explicit terms, and D of the projected N_x, N_z
   // through (D P) (mixed: FP32 operands, FP64 result)
-  m->G2.type = mixed ? (m->prec == 1 ? GEMM_FFD : GEMM_DFD) : GEMM_DDD;
-  const void* P = f32ops ? (const void*)m->PNM32 : (const void*)m->PNM;
+  m->G2.type = mixed ? (m->prec == 2 ? GEMM_DFD : (comp ? GEMM_CFD : GEMM_FFD)) : GEMM_DDD;
+  const void* P = f32ops ? (const void*)m->PNM32 : (const void*)m->PNM;  // (plain form; not used by precision 3)
   const void* DP = f32ops ? (const void*)m->DP32 : (const void*)m->DP;
   const void* Pp[2] = {f32ops ? (const void*)m->PNM32p[0] : m->PNMp[0], f32ops ? (const void*)m->PNM32p[1] : m->PNMp[1]};
   const void* DPp[2] = {f32ops ? (const void*)m->DP32p[0] : m->DPp[0], f32ops ? (const void*)m->DP32p[1] : m->DPp[1]};
   const char* Yo = mixed ? (const char*)m->Yout32 : (const char*)m->Yout;
-  for (int f = 0; f < m->nout; ++f)
+  for (int f = 0; f < m->nout; ++f) {
     m->G2.addp(PAR_FOLD_UNFOLD, P, Pp[0], Pp[1], Yo + (size_t)f * fsm * ysz, cw, m->S + f * fs, cw, nh, cw, mh, n1, m1,
                +1);
+    tails(m->G2, m->PNM32lp);
+  }
   m->G2.addp(PAR_FOLD_UNFOLD, DP, DPp[0], DPp[1], Yo, cw, m->DN, cw, nh, cw, mh, n1, m1, -1);
-  if (d.dim == 3)
+  tails(m->G2, m->DP32lp);
+  if (d.dim == 3) {
     m->G2.addp(PAR_FOLD_UNFOLD, DP, DPp[0], DPp[1], Yo + 2 * fsm * ysz, cw, m->DN + fs, cw, nh, cw, mh, n1, m1, -1);
+    tails(m->G2, m->DP32lp);
+  }
   if (mixed) {
     // the mean column again, in FP64, from the FP64-completed padded-grid means
     m->Gm.type = GEMM_DDD;
@@ -843,12 +873,23 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
       return r != hipSuccess ? r : up(dst[1], padded<float>(o, rows, cols), s);
     };
     const bool mixed = m->prec != 0;
+    // FP32 tails of the halves (precision 3): v - fp32(v), rounded to FP32
+    auto put2t = [&](float* const (&dst)[2], int rows, int cols) -> hipError_t {
+      if (m->prec != 3) return hipSuccess;
+      std::vector<double> te(e.size()), to(o.size());
+      for (size_t i = 0; i < e.size(); ++i) te[i] = e[i] - (double)(float)e[i];
+      for (size_t i = 0; i < o.size(); ++i) to[i] = o[i] - (double)(float)o[i];
+      hipError_t r = up(dst[0], padded<float>(te, rows, cols), s);
+      return r != hipSuccess ? r : up(dst[1], padded<float>(to, rows, cols), s);
+    };
     fold(op->IMN, n1, 0, mh, mh, e, o);
     HIPCHK(put2(m->IMNp, mh, nh));
     if (mixed) HIPCHK(put2f(m->IMN32p, mh, nh));
+    HIPCHK(put2t(m->IMN32lp, mh, nh));
     fold(op->DMN, n1, 0, mh, mh, e, o);
     HIPCHK(put2(m->DMNp, mh, nh));
     if (mixed) HIPCHK(put2f(m->DMN32p, mh, nh));
+    HIPCHK(put2t(m->DMN32lp, mh, nh));
     fold(op->D2, n1, 0, nh, nh, e, o);
     HIPCHK(put2(m->D2p, nh, nh));
     fold(op->D, n1, 0, nh, nh, e, o);
@@ -856,9 +897,11 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
     fold(op->PNM, m1, 0, nh, nh, e, o);
     HIPCHK(put2(m->PNMp, nh, mh));
     if (mixed) HIPCHK(put2f(m->PNM32p, nh, mh));
+    HIPCHK(put2t(m->PNM32lp, nh, mh));
     fold(DP, m1, 0, nh, nh, e, o);
     HIPCHK(put2(m->DPp, nh, mh));
     if (mixed) HIPCHK(put2f(m->DP32p, nh, mh));
+    HIPCHK(put2t(m->DP32lp, nh, mh));
     // V^-1: even rows act on the folded sums, odd rows on the differences
     std::vector<double> e2, o2;
     fold(op->Vinv, ni, 0, ne, ne, e, o2);
@@ -1454,11 +1497,20 @@ pcs_status autotune(Batch* b) {
           }
         }
       }
-      tune_cache()[key] = bestf * GEMM_NCFG + best;
-      if (tune_path) append_tune_file(tune_path, arch, key, bestf * GEMM_NCFG + best);
+      if (best >= 0) {
+        tune_cache()[key] = bestf * GEMM_NCFG + best;
+        if (tune_path) append_tune_file(tune_path, arch, key, bestf * GEMM_NCFG + best);
+      }
     }
-    jl->use(bestf);
-    jl->set_cfg(best);
+    if (best < 0) {
+      // no candidate under the forced form (the compensated tables have the
+      // parity form only): the table's default
+      jl->use(0);
+      jl->prepare();
+    } else {
+      jl->use(bestf);
+      jl->set_cfg(best);
+    }
     HIPCHK(up_list(jl, s));
   }
   (void)hipEventDestroy(e0);

@@ -843,6 +843,150 @@ __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __
   }
 }
 
+// ------------------------------------------------------------ error-compensated FP32 products
+// Types GEMM_CDF (B FP64, C FP32) and GEMM_CFD (B FP32, C FP64): the products
+// of the B-stationary kernel in FP32 arithmetic with error compensation.
+// Every operand is split into an FP32 head and tail, v = hi + lo with
+// hi = fp32(v), lo = fp32(v - hi): the operator halves once on the host (A, A2
+// the heads, Alo, A2lo the tails), the folded B panel (formed in FP64) while
+// it is staged (four LDS panels).  Each MFMA step (four k) computes the head
+// product hi*hi into a fresh accumulator and adds it to a running sum with
+// Knuth's TwoSum (sum and rounding error kept apart), while the two cross
+// products hi*lo and lo*hi, of relative size 2^-24, accumulate in plain FP32.
+// The output is hi + lo sum + cross terms, formed in FP64 and rounded once to
+// the output precision.  Compared with plain FP32 this removes the rounding of
+// the inputs and of the operator and leaves the rounding of four-term FP32
+// partial sums (the TwoSum recovers that of their accumulation).
+__device__ inline void two_sum(float& s, float& e, float x) {
+  const float t = s + x;
+  const float bp = t - s;
+  e += (s - (t - bp)) + (x - bp);
+  s = t;
+}
+
+template <typename TB, typename TC, int BN>
+__device__ __attribute__((always_inline)) inline void bst_comp_body(const GemmJob* __restrict__ jp, int t,
+                                                                    double* smem) {
+  constexpr int CB = BN / 16, PB = bst_pitch<BN>();
+  const int col0 = (t - jp->tile0) * BN;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int l16 = lane & 15, lk = lane >> 4;
+  const int M = jp->m, N = jp->n, K = jp->k, KF = jp->kf, lda = jp->lda, ldb = jp->ldb;
+  const int K16 = (K + 15) & ~15;
+  const bool fold = jp->kind != PAR_SPLIT_UNFOLD;
+  const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
+  const size_t pan = (size_t)K16 * PB;
+  float* Beh = reinterpret_cast<float*>(smem);
+  float* Bel = Beh + pan;
+  float* Boh = Bel + pan;
+  float* Bol = Boh + pan;
+  const gptr<const TB> B = gmem(static_cast<const TB*>(jp->B));
+  constexpr int U = 4;
+  const int tot = K16 * BN;
+  for (int e0 = 0; e0 < tot; e0 += U * 256) {
+    double x[U], y[U];
+    int kk[U], c[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int e = e0 + u * 256 + tid;
+      kk[u] = e / BN;
+      c[u] = e - kk[u] * BN;
+      const int gc = col0 + c[u];
+      x[u] = y[u] = 0.0;
+      if (e < tot && kk[u] < K && gc < N && !(zm && gc < 2)) {
+        x[u] = (double)B[(size_t)kk[u] * ldb + gc];
+        const int kr = fold ? KF - 1 - kk[u] : K + kk[u];
+        if (fold ? kr > kk[u] : kr < KF) y[u] = (double)B[(size_t)kr * ldb + gc];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      if (e0 + u * 256 + tid >= tot) continue;
+      const int o = kk[u] * PB + c[u];
+      const double ve = fold ? x[u] + y[u] : x[u], vo = fold ? x[u] - y[u] : y[u];
+      const float he = (float)ve, ho = (float)vo;
+      Beh[o] = he;
+      Bel[o] = (float)(ve - (double)he);
+      Boh[o] = ho;
+      Bol[o] = (float)(vo - (double)ho);
+    }
+  }
+  __syncthreads();
+  const gptr<const float> Ah = gmem(static_cast<const float*>(jp->A));
+  const gptr<const float> A2h = gmem(static_cast<const float*>(jp->A2));
+  const gptr<const float> Al = gmem(static_cast<const float*>(jp->Alo));
+  const gptr<const float> A2l = gmem(static_cast<const float*>(jp->A2lo));
+  const int nrb = (M + 15) >> 4, nkb = K16 >> 4;
+  const size_t bo = (size_t)(4 * lk) * PB + l16;
+  for (int rb = wave; rb < nrb; rb += 4) {
+    flt4 Se[CB], Ee[CB], Xe[CB], So[CB], Eo[CB], Xo[CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb) Se[cb] = Ee[cb] = Xe[cb] = So[cb] = Eo[cb] = Xo[cb] = flt4{0, 0, 0, 0};
+    const size_t ar = (size_t)(rb * 16 + l16) * lda + 4 * lk;
+    const gptr<const flt4> aeh = reinterpret_cast<gptr<const flt4>>(Ah + ar);
+    const gptr<const flt4> ael = reinterpret_cast<gptr<const flt4>>(Al + ar);
+    const gptr<const flt4> aoh = reinterpret_cast<gptr<const flt4>>(A2h + ar);
+    const gptr<const flt4> aol = reinterpret_cast<gptr<const flt4>>(A2l + ar);
+    flt4 neh = aeh[0], nel = ael[0], noh = aoh[0], nol = aol[0];
+    for (int b = 0; b < nkb; ++b) {
+      const flt4 xeh = neh, xel = nel, xoh = noh, xol = nol;
+      if (b + 1 < nkb) {
+        neh = aeh[4 * (b + 1)];
+        nel = ael[4 * (b + 1)];
+        noh = aoh[4 * (b + 1)];
+        nol = aol[4 * (b + 1)];
+      }
+      const size_t rowo = bo + (size_t)(16 * b) * PB;
+#pragma unroll
+      for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+        for (int cb = 0; cb < CB; ++cb) {
+          const size_t o = rowo + (size_t)s2 * PB + cb * 16;
+          const float beh = Beh[o], bel = Bel[o], boh = Boh[o], bol = Bol[o];
+          const flt4 pe = mfma(xeh[s2], beh, flt4{0, 0, 0, 0});
+          const flt4 po = mfma(xoh[s2], boh, flt4{0, 0, 0, 0});
+          Xe[cb] = mfma(xeh[s2], bel, Xe[cb]);
+          Xe[cb] = mfma(xel[s2], beh, Xe[cb]);
+          Xo[cb] = mfma(xoh[s2], bol, Xo[cb]);
+          Xo[cb] = mfma(xol[s2], boh, Xo[cb]);
+#pragma unroll
+          for (int r = 0; r < 4; ++r) {
+            float se = Se[cb][r], ee = Ee[cb][r], so = So[cb][r], eo = Eo[cb][r];
+            two_sum(se, ee, pe[r]);
+            two_sum(so, eo, po[r]);
+            Se[cb][r] = se;
+            Ee[cb][r] = ee;
+            So[cb][r] = so;
+            Eo[cb][r] = eo;
+          }
+        }
+    }
+    dbl4 E[1][CB], O[1][CB];
+#pragma unroll
+    for (int cb = 0; cb < CB; ++cb)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        E[0][cb][r] = (double)Se[cb][r] + (double)Ee[cb][r] + (double)Xe[cb][r];
+        O[0][cb][r] = (double)So[cb][r] + (double)Eo[cb][r] + (double)Xo[cb][r];
+      }
+    // FP64 values in the layout of the FP32 instruction's output
+    store_par<float, TC, 1, CB>(jp, E, O, rb * 16, col0, lk, l16);
+  }
+}
+
+template <typename TB, typename TC, int BN>
+__global__ __launch_bounds__(256) void gemm_bst_comp_kernel(const GemmJob* __restrict__ jobs,
+                                                            const int* __restrict__ tmap, int total) {
+  extern __shared__ __attribute__((aligned(16))) double smem[];
+  const int t = xcd_tile(blockIdx.x, total);
+  const GemmJob* jp = tile_job(jobs, tmap, t);
+  if (masked(jp->skip)) return;
+  if (jp->type == GEMM_DDD)
+    bst_body<double, double, double, BN>(jp, t, smem);
+  else
+    bst_comp_body<TB, TC, BN>(jp, t, smem);
+}
+
 template <typename T, typename TB, typename TC, int BN>
 __global__ __launch_bounds__(256) void gemm_bst_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap,
                                                        int total) {
@@ -931,6 +1075,7 @@ void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, bo
 
 bool gemm_cfg_parity(int cfg) { return cfg >= 4 && cfg < GEMM_NCFG; }
 bool gemm_cfg_bst(int cfg) { return cfg == 14 || cfg == 15; }
+bool gemm_type_comp(GemmType t) { return t == GEMM_CDF || t == GEMM_CFD; }
 
 namespace {
 template <int CFG>
@@ -943,9 +1088,17 @@ size_t lds_form(bool parity, size_t esize, bool half) {
 
 size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
   // compute precision of the table's own type (its GEMM_DDD jobs compute in FP64)
-  const size_t own = (t == GEMM_FDF || t == GEMM_FFD) ? 4 : 8;
+  const size_t own = (t == GEMM_FDF || t == GEMM_FFD || gemm_type_comp(t)) ? 4 : 8;
   size_t b = 0;
   for (int j = 0; j < njobs; ++j) {
+    if (gemm_type_comp(t) && jobs[j].type != GEMM_DDD) {
+      // head and tail panels of both halves, B-stationary only
+      if (!gemm_cfg_bst(cfg) || jobs[j].kind == PAR_NONE) return ~(size_t)0 >> 1;
+      const size_t pitch = cfg == 14 ? bst_pitch<32>() : bst_pitch<64>();
+      const size_t x = 4 * (size_t)((jobs[j].k + 15) & ~15) * pitch * 4 + 16;
+      b = x > b ? x : b;
+      continue;
+    }
     const bool par = jobs[j].kind != PAR_NONE;
     const size_t es = jobs[j].type == GEMM_DDD ? 8 : own;
     const bool half = t != GEMM_DDD && jobs[j].type == GEMM_DDD;  // FP64 products of a mixed table
@@ -982,7 +1135,9 @@ hipError_t gemm_set_attributes() {
       (const void*)gemm_bst_kernel<float, double, float, 32>,   (const void*)gemm_bst_kernel<float, double, float, 64>,
       (const void*)gemm_bst_kernel<float, float, double, 32>,   (const void*)gemm_bst_kernel<float, float, double, 64>,
       (const void*)gemm_bst_kernel<double, double, float, 32>,  (const void*)gemm_bst_kernel<double, double, float, 64>,
-      (const void*)gemm_bst_kernel<double, float, double, 32>,  (const void*)gemm_bst_kernel<double, float, double, 64>};
+      (const void*)gemm_bst_kernel<double, float, double, 32>,  (const void*)gemm_bst_kernel<double, float, double, 64>,
+      (const void*)gemm_bst_comp_kernel<double, float, 32>,     (const void*)gemm_bst_comp_kernel<double, float, 64>,
+      (const void*)gemm_bst_comp_kernel<float, double, 32>,     (const void*)gemm_bst_comp_kernel<float, double, 64>};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LDS_MAX);
     if (e != hipSuccess) return e;
@@ -993,6 +1148,27 @@ hipError_t gemm_set_attributes() {
 void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_tiles, int cfg, bool parity,
               size_t lds, hipStream_t s) {
   if (total_tiles <= 0 || cfg < 0 || cfg >= GEMM_NCFG || (parity && !gemm_cfg_parity(cfg))) return;
+  if (gemm_type_comp(t)) {
+    // compensated tables: parity products, B-stationary configurations only
+    if (!parity || !gemm_cfg_bst(cfg)) return;
+    const bool wide = cfg == 15;
+    if (t == GEMM_CDF) {
+      if (wide)
+        hipLaunchKernelGGL((gemm_bst_comp_kernel<double, float, 64>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
+                           tmap, total_tiles);
+      else
+        hipLaunchKernelGGL((gemm_bst_comp_kernel<double, float, 32>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
+                           tmap, total_tiles);
+    } else {
+      if (wide)
+        hipLaunchKernelGGL((gemm_bst_comp_kernel<float, double, 64>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
+                           tmap, total_tiles);
+      else
+        hipLaunchKernelGGL((gemm_bst_comp_kernel<float, double, 32>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
+                           tmap, total_tiles);
+    }
+    return;
+  }
   switch (t) {
     case GEMM_DDD: launch_cfg<double, double, double>(dev_jobs, tmap, total_tiles, cfg, parity, lds, s); break;
     case GEMM_FDF: launch_cfg<float, double, float>(dev_jobs, tmap, total_tiles, cfg, parity, lds, s); break;

@@ -52,6 +52,8 @@ struct GemmJob {
              // whose operator A2 is padded to the same shape) and lda serves both
   const void* A;
   const void* A2;
+  const void* Alo;   // error-compensated types: FP32 tails of A and A2 (A = head + tail)
+  const void* A2lo;
   const void* B;
   void* C;
   void* C2;  // optional second output: alpha A B scaled by scale2 (no beta term)
@@ -81,8 +83,11 @@ struct EigScale {
   double nu, wi, kappa;
 };
 
-// compute / B / C precisions: D = double, F = float
-enum GemmType { GEMM_DDD = 0, GEMM_FDF, GEMM_FFD, GEMM_DDF, GEMM_DFD, GEMM_NTYPES };
+// compute / B / C precisions: D = double, F = float, C = error-compensated
+// FP32 (head and tail products, TwoSum accumulation; parity products in the
+// B-stationary configurations only)
+enum GemmType { GEMM_DDD = 0, GEMM_FDF, GEMM_FFD, GEMM_DDF, GEMM_DFD, GEMM_CDF, GEMM_CFD, GEMM_NTYPES };
+bool gemm_type_comp(GemmType t);
 
 constexpr int MAX_JOBS = 64;
 // Tile configurations.  Register-direct kernel (operand fragments loaded
