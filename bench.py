@@ -27,13 +27,17 @@ sys.path.insert(0, ROOT)
 
 METRIC = "time steps/s and grid-point-updates/s, mixed vs FP64 at stated error, 1 GPU"
 HBM_PEAK_GBS = 8000.0
+# names of the precision settings (pcs_params.precision)
+PNAME = {0: "fp64", 1: "mixed", 2: "mixed64y", 3: "mixedcomp", 4: "auto"}
+PDESC = {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms", 3: "mixed, error-compensated FP32 y-transforms",
+         4: "mixed, each y-transform table the fastest variant within the error budget"}
 MFMA_F64_TFS = 78.6
 MFMA_F32_TFS = 157.3
 
 from paper_2606_09468_amd.workloads import ENSEMBLE, WORKLOADS, ensemble_members  # noqa: E402
 
 
-def stage_work(w, precision, split):
+def stage_work(w, precision, split, yvar=None):
     """Algorithmic work of one launch of each stage kernel at this workload:
     {stage: (bound, amount, peak)}.  Products: ('mfma', flops summed over
     the table, peak of the compute precision), each wall-normal product in its
@@ -44,7 +48,9 @@ def stage_work(w, precision, split):
     written once, complex values of the kernel's precision (FP32 in the mixed
     transforms, FP64 elsewhere); small per-mode tables are not counted.
     split: the products of the state run as three launches (mean profiles,
-    padded grid, D2 / D) rather than one."""
+    padded grid, D2 / D) rather than one.  yvar: the wall-normal product
+    variants in use (1 FP32, 2 FP64 operators, 3 compensated FP32; for the
+    state products and the projections), by default those of the precision."""
     dim, nx, ny, nz = w["dim"], w["nx"], w["ny"], w["nz"]
     N = ny - 1
     n1, m1, ni = N + 1, 3 * N // 2 + 1, N - 1
@@ -60,8 +66,10 @@ def stage_work(w, precision, split):
     nyin = 9 if dim == 2 else 17
     nh = 1 + (dim - 2) + nc
     mixed = precision != 0
-    f32_state = precision in (1, 3)       # the state -> padded-grid products in FP32 (3: compensated)
-    f32_proj = precision in (1, 3)
+    if yvar is None:
+        yvar = [precision, precision]
+    f32_state = yvar[0] in (1, 3)         # the state -> padded-grid products in FP32 (3: compensated)
+    f32_proj = yvar[1] in (1, 3)
     tb = 8 if mixed else 16               # bytes per complex value in the transforms
     pk = lambda f32: MFMA_F32_TFS if f32 else MFMA_F64_TFS
     out = {}
@@ -141,7 +149,7 @@ def traffic_for(kernel, workload, precision):
     digest = hashlib.sha256(src).hexdigest()[:16]
     for line in open(path):
         parts = [x.strip() for x in line.strip().strip("|").split("|")]
-        pname = {0: "fp64", 1: "mixed", 2: "mixed64y", 3: "mixedcomp"}.get(precision, str(precision))
+        pname = PNAME.get(precision, str(precision))
         if len(parts) >= 6 and parts[0] == kernel and parts[1] == workload and parts[2] == pname:
             if parts[5] != digest:
                 return None
@@ -253,7 +261,7 @@ def main():
     ap.add_argument("--workload", default="c5", choices=sorted(WORKLOADS) + ["c4"],
                     help="c5 (default): 3D 256x257x128, the largest single-GPU workload; "
                          "c4: the 64-member uneven 2D ensemble, one graph launch per step")
-    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed", "mixed64y", "mixedcomp"],
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed", "mixed64y", "mixedcomp", "auto"],
                     help="both: time mixed (value) and FP64 (reported beside it); mixed64y: FP64 wall-normal "
                          "transforms; mixedcomp: error-compensated FP32 wall-normal transforms")
     ap.add_argument("--stage-steps", type=int, default=10)
@@ -307,7 +315,7 @@ def main():
         return bench_ensemble(args, P)
     w = WORKLOADS[args.workload]
     grid = P.make_grid(w["dim"], w["nx"], w["ny"], w["nz"], 10.0, w["lz"])
-    precs = {"both": [1, 0], "fp64": [0], "mixed": [1], "mixed64y": [2], "mixedcomp": [3]}[args.precision]
+    precs = {"both": [1, 0], "fp64": [0], "mixed": [1], "mixed64y": [2], "mixedcomp": [3], "auto": [4]}[args.precision]
     timed = {}
     for prec in precs:
         prm = P.make_params(wi=w["wi"], dt=w["dt"], precision=prec, scheme=args.scheme_id)
@@ -340,12 +348,13 @@ def main():
         print("bench: timed %d steps in %.3f ms (wall %.3f s)" % (args.steps, ms, wall), file=sys.stderr, flush=True)
         # per-stage durations (eager launches, HIP events on the run's stream)
         stages = sim.stage_times(args.stage_steps, reps=args.stage_reps)
+        ych = sim.y_choice()
         sim.close()
-        timed[prec] = dict(ms=ms, sps=args.steps / (ms / 1e3), stages=stages, prm=prm, hist=hist)
+        timed[prec] = dict(ms=ms, sps=args.steps / (ms / 1e3), stages=stages, prm=prm, hist=hist, ych=ych)
     head = precs[0]
     ms, sps, stages, prm = timed[head]["ms"], timed[head]["sps"], timed[head]["stages"], timed[head]["prm"]
     split = stages.get("gemm_d2", 0.0) > 0.0
-    table = roofline_table(stages, stage_work(w, head, split))
+    table = roofline_table(stages, stage_work(w, head, split, timed[head]["ych"]["variant"]))
     dom = max(table, key=lambda k: table[k]["avg_ms"])
     roof = dict(kernel=dom, **table[dom])
     roof["traffic"] = traffic_for(dom, args.workload, head)
@@ -353,11 +362,10 @@ def main():
     line = {
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64", 3: "f32+f64"}[head], "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if head == 0 else "f32+f64", "data": "synthetic",
         "config": {"workload": w["desc"] if args.scheme_id == 0 else w["desc"].replace("CNAB2", "SBDF4"),
                    "grid": [w["nx"], w["ny"], w["nz"]],
-                   "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms",
-                                 3: "mixed, error-compensated FP32 y-transforms"}[head],
+                   "precision": PDESC[head],
                    "parallelism": "single GPU"},
         "grid_point_updates_per_s": sps * points,
         "roofline": roof,
@@ -387,13 +395,15 @@ def main():
             a, d = gstates[prec]
             errs = state_errors(a, ostate, w)
             e = odiag
-            line["error_vs_oracle"][{0: "fp64", 1: "mixed", 2: "mixed64y", 3: "mixedcomp"}[prec]] = {
+            line["error_vs_oracle"][PNAME[prec]] = {
                 "steps": args.cpu_steps + 1,
                 "max_rel_velocity": max(errs[k] for k in errs if k in ("u", "v", "w", "phi", "g")),
                 "max_rel_conformation": max(errs[k] for k in errs if k.startswith("c")),
                 "min_trc_abs": abs(d["min_trc"] - e["min_trc"]),
                 "counts_equal": all(d[k] == e[k] for k in ("n_lt3", "n_lt0", "mid_n_lt3", "mid_n_lt0")),
             }
+    if head == 4:
+        line["y_choice"] = timed[head]["ych"]
     if timed[head]["hist"] is not None:
         line["midplane_histogram"] = timed[head]["hist"]
     print(json.dumps(line), flush=True)
@@ -428,7 +438,7 @@ def bench_ensemble(args, P):
     member advanced one step per graph launch) and summed point updates."""
     import torch
     members = ensemble_members(ENSEMBLE["count"], ENSEMBLE["seed"])
-    prec = {"both": 1, "fp64": 0, "mixed": 1, "mixed64y": 2, "mixedcomp": 3}[args.precision]
+    prec = {"both": 1, "fp64": 0, "mixed": 1, "mixed64y": 2, "mixedcomp": 3, "auto": 4}[args.precision]
     grids = [P.make_grid(2, nx, ny) for ny, nx, _, _ in members]
     params = [P.make_params(wi=wi, dt=ENSEMBLE["dt"], precision=prec, scheme=args.scheme_id)
               for _, _, wi, _ in members]
@@ -454,11 +464,10 @@ def bench_ensemble(args, P):
     line = {
         "metric": METRIC, "value": sps, "unit": "steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": {0: "f64", 1: "f32+f64", 2: "f32+f64", 3: "f32+f64"}[prec], "data": "synthetic",
+        "vs_baseline": None, "dtype": "f64" if prec == 0 else "f32+f64", "data": "synthetic",
         "config": {"workload": ENSEMBLE["desc"] if args.scheme_id == 0 else ENSEMBLE["desc"].replace("CNAB2", "SBDF4"),
                    "members": len(members), "base_points": points,
-                   "precision": {0: "fp64", 1: "mixed", 2: "mixed, FP64 y-transforms",
-                                 3: "mixed, error-compensated FP32 y-transforms"}[prec],
+                   "precision": PDESC[prec],
                    "parallelism": "single GPU, one graph launch per ensemble step"},
         "grid_point_updates_per_s": sps * points,
         "roofline": None,

@@ -71,6 +71,30 @@ typedef struct {
  *  precision = 2: as 1, but the wall-normal transforms of the fluctuation
  *               (to and from the padded grid) are computed in FP64 and
  *               only the periodic transforms and products in FP32.
+ *  precision = 3: as 1, but the wall-normal transforms of the fluctuation
+ *               are error-compensated FP32 products: every operator is an
+ *               FP32 head plus an FP32 tail, every state value is split the
+ *               same way, and the results of the FP32 matrix instructions
+ *               are accumulated as unevaluated FP32 pairs (exact two-term
+ *               sums).  This removes the rounding of the operands and of
+ *               the accumulation across instructions, but not the rounding
+ *               inside each instruction (a chain of four fused multiply-adds
+ *               on this hardware), so the measured error stays of the order
+ *               of plain FP32 at two to five times its cost (pcs_y_choice
+ *               reports both).
+ *  precision = 4: as 1, but each of the two wall-normal product tables
+ *               (values and d/dy of the state on the padded grid; the
+ *               projections of the explicit terms) takes, at pcs_init, the
+ *               fastest of the three variants above (PCS_Y_FP32,
+ *               PCS_Y_FP64, PCS_Y_COMP) whose measured error is within the
+ *               budget: the error of a variant is the largest difference of
+ *               its outputs from those of the FP64-operator variant on the
+ *               run's initial state, relative to the largest magnitude of
+ *               the same output field (mean mode excluded), over all fields
+ *               of the table; the budget is PCS_Y_ERROR_BUDGET from the
+ *               environment if set (a non-negative number), else 1e-5.  The
+ *               choice is made for the whole ensemble; pcs_y_choice reports
+ *               it with the errors and times measured.
  *  scheme = 0:  CNAB2 (Crank-Nicolson on the linear terms, 2nd-order
  *               Adams-Bashforth on the rest).
  *  scheme = 1:  SBDF4, the 4th-order semi-implicit BDF that Section 2 names
@@ -216,6 +240,28 @@ const char* pcs_stage_name(int32_t i);
  * PCS_ERR_ARG for nbins > PCS_HIST_MAX, non-finite lo or hi, or lo >= hi) and
  * synchronises the stream.  pcs_midplane_histogram synchronises and copies
  * the nbins + 2 counts (n must be nbins + 2; PCS_ERR_ARG while off). */
+/* The wall-normal product variants of the mixed precisions (see
+ * pcs_params.precision) and the choice made for precision 4:
+ * variant[0] is that of the padded-grid values and d/dy of the state,
+ * variant[1] that of the projections of the explicit terms (0 for the FP64
+ * path of precision 0); budget the error budget in force; error[t][v - 1]
+ * and time_us[t][v - 1] the measured error and launch time of table t in
+ * variant v (-1 where not measured: every precision other than 4, and time
+ * in runs initialised by pcs_init_static, which are not timed and then
+ * prefer PCS_Y_FP32, then PCS_Y_FP64, among the variants within the
+ * budget).  The time of table t is that of the launch holding it, which
+ * may hold other FP64 products of the same stage. */
+#define PCS_Y_FP32 1
+#define PCS_Y_FP64 2
+#define PCS_Y_COMP 3
+typedef struct {
+  int32_t variant[2];
+  double budget;
+  double error[2][3];
+  double time_us[2][3];
+} pcs_ychoice;
+pcs_status pcs_y_choice(struct pcs_sim* sim, pcs_ychoice* out);
+
 #define PCS_HIST_MAX 4096
 pcs_status pcs_midplane_histogram_setup(struct pcs_sim* sim, double lo, double hi, int32_t nbins);
 pcs_status pcs_midplane_histogram(struct pcs_sim* sim, uint64_t* counts, int32_t n);
@@ -324,6 +370,7 @@ pcs_status pcs_ensemble_midplane_pdf(struct pcs_ens* ens, int32_t run, int32_t q
                                      int32_t n);
 /* Running moments of run `run`, as pcs_midplane_moments. */
 pcs_status pcs_ensemble_midplane_moments(struct pcs_ens* ens, int32_t run, int32_t quantity, double* out);
+pcs_status pcs_ensemble_y_choice(struct pcs_ens* ens, pcs_ychoice* out);
 pcs_status pcs_ensemble_destroy(struct pcs_ens* ens);
 
 #ifdef __cplusplus

@@ -33,13 +33,15 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state",
            "pcs_midplane_pdf_setup", "pcs_midplane_pdf", "pcs_ensemble_midplane_pdf_setup", "pcs_ensemble_midplane_pdf",
            "pcs_init_static", "pcs_ensemble_set_state", "pcs_ensemble_run_status", "pcs_midplane_moments",
-           "pcs_ensemble_midplane_moments")
+           "pcs_ensemble_midplane_moments", "pcs_y_choice", "pcs_ensemble_y_choice")
 PCS_NSTAGE = 14
 PCS_HIST_MAX = 4096
 PCS_STATIC_BYTES = 64 << 20
 # midplane PDF quantities (pcs_midplane_pdf_setup)
 PCS_PDF_TRC, PCS_PDF_U, PCS_PDF_V, PCS_PDF_W = 0, 1, 2, 3
 PCS_PDF_DUDX, PCS_PDF_DUDZ, PCS_PDF_DWDX, PCS_PDF_DWDZ = 4, 5, 6, 7
+# wall-normal product variants of the mixed precisions (pcs_y_choice)
+PCS_Y_FP32, PCS_Y_FP64, PCS_Y_COMP = 1, 2, 3
 
 
 class pcs_grid(ctypes.Structure):
@@ -60,6 +62,11 @@ class pcs_diag(ctypes.Structure):
                 ("energy", ctypes.c_double), ("mean_trc", ctypes.c_double), ("n_lt3", ctypes.c_uint64),
                 ("n_lt0", ctypes.c_uint64), ("mid_n_lt3", ctypes.c_uint64), ("mid_n_lt0", ctypes.c_uint64),
                 ("blowup", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class pcs_ychoice(ctypes.Structure):
+    _fields_ = [("variant", ctypes.c_int32 * 2), ("budget", ctypes.c_double),
+                ("error", (ctypes.c_double * 3) * 2), ("time_us", (ctypes.c_double * 3) * 2)]
 
 
 _lib = None
@@ -114,6 +121,8 @@ def lib():
     L.pcs_midplane_moments.argtypes = [vp, st, ctypes.POINTER(ctypes.c_double)]
     L.pcs_ensemble_midplane_moments.argtypes = [vp, st, st, ctypes.POINTER(ctypes.c_double)]
     dp = ctypes.POINTER(ctypes.c_double)
+    L.pcs_y_choice.argtypes = [vp, ctypes.POINTER(pcs_ychoice)]
+    L.pcs_ensemble_y_choice.argtypes = [vp, ctypes.POINTER(pcs_ychoice)]
     L.pcs_resample_state.argtypes = [ctypes.POINTER(pcs_grid), dp, sz, ctypes.POINTER(pcs_grid), dp, sz]
     for name in EXPORTS:
         if name not in ("pcs_status_string", "pcs_stage_name"):
@@ -177,6 +186,17 @@ def _moments(out):
         return 0, float("nan"), float("nan")
     mean = s1 / n
     return int(n), mean, float(np.sqrt(max(s2 / n - mean * mean, 0.0)))
+
+
+def _ychoice(out):
+    """{"variant": [state products, projections], "budget": b, "error": [[per
+    variant FP32, FP64, compensated] per table], "time_us": likewise}, with
+    None where not measured."""
+    def val(x):
+        return None if x < 0 else float(x)
+    return {"variant": [int(out.variant[0]), int(out.variant[1])], "budget": val(out.budget),
+            "error": [[val(out.error[t][v]) for v in range(3)] for t in range(2)],
+            "time_us": [[val(out.time_us[t][v]) for v in range(3)] for t in range(2)]}
 
 
 def _arrays(grids, params):
@@ -281,6 +301,13 @@ class Sim:
         _check(lib().pcs_midplane_moments(self.handle, int(quantity), out), "pcs_midplane_moments")
         return _moments(out)
 
+    def y_choice(self):
+        """The wall-normal product variants in use and, for precision 4, the
+        errors and times they were chosen by (pcs_y_choice)."""
+        out = pcs_ychoice()
+        _check(lib().pcs_y_choice(self.handle, ctypes.byref(out)), "pcs_y_choice")
+        return _ychoice(out)
+
     def stage_times(self, nsteps, reps=1):
         """Mean milliseconds per launch of each stage over nsteps real steps
         (eager launch, every stage but the last repeated reps times back to
@@ -377,10 +404,16 @@ class Ensemble:
         return _check(lib().pcs_ensemble_run_status(self.handle, int(run)), "pcs_ensemble_run_status",
                       allow=(PCS_OK, PCS_ERR_STATE))
 
+    def y_choice(self):
+        """As Sim.y_choice, for the whole ensemble (pcs_ensemble_y_choice)."""
+        out = pcs_ychoice()
+        _check(lib().pcs_ensemble_y_choice(self.handle, ctypes.byref(out)), "pcs_ensemble_y_choice")
+        return _ychoice(out)
+
     def midplane_moments(self, run, quantity):
         out = (ctypes.c_double * 3)()
         _check(lib().pcs_ensemble_midplane_moments(self.handle, int(run), int(quantity), out),
-               "pcs_ensemble_midplane_moments")
+               "pcs_ensemble_midplane_moments", "pcs_y_choice", "pcs_ensemble_y_choice")
         return _moments(out)
 
     def get_state(self, run):

@@ -32,6 +32,7 @@ namespace {
 
 constexpr int RING = 4096;
 constexpr size_t ALIGN = 256;
+constexpr int Y_FP32 = PCS_Y_FP32, Y_FP64 = PCS_Y_FP64, Y_COMP = PCS_Y_COMP;
 
 struct Carve {
   char* base;
@@ -261,6 +262,12 @@ struct Member {
   // solutions at init (own device tables)
   JobList G1, Gbar, G1b, G2, Gm, G4, G5, H4, H5;
   int prec = 0;
+  // arithmetic of the mixed-precision wall-normal products: yv1 for the
+  // padded-grid values and d/dy of the state (G1), yv2 for the projections
+  // of the explicit terms (G2); Y_FP32, Y_FP64 (FP64 operators, FP32 grid
+  // values) or Y_COMP (error-compensated FP32); fixed by precision 1-3,
+  // chosen at initialisation for precision 4
+  int yv1 = 0, yv2 = 0;
   double wU1 = 0;
   long long drained = 0;
   int blowup = 0;
@@ -295,6 +302,11 @@ struct Batch {
   // eager batch (the allocation-free initialisation): no autotuner timing,
   // no side streams, no graphs; every step is launched kernel by kernel
   bool eager = false;
+  // precision 4: the error budget, and per table (state products,
+  // projections) and variant the measured error and time (-1: not measured)
+  double ybudget = -1;
+  double yerr[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
+  double yus[2][3] = {{-1, -1, -1}, {-1, -1, -1}};
   // per-member argument tables (host copies, then device) and launch sizes
   std::vector<XArgs> hx;
   std::vector<ZArgs> hzi, hzf, hzd;
@@ -390,7 +402,7 @@ void carve(Member* m, Carve& c) {
       m->DMN32p[q] = m->prec != 0 ? c.take<float>(opsz(mh, nh)) : nullptr;
       m->PNM32p[q] = m->prec != 0 ? c.take<float>(opsz(nh, mh)) : nullptr;
       m->DP32p[q] = m->prec != 0 ? c.take<float>(opsz(nh, mh)) : nullptr;
-      const bool comp = m->prec == 3;
+      const bool comp = m->prec == 3 || m->prec == 4;
       m->IMN32lp[q] = comp ? c.take<float>(opsz(mh, nh)) : nullptr;
       m->DMN32lp[q] = comp ? c.take<float>(opsz(mh, nh)) : nullptr;
       m->PNM32lp[q] = comp ? c.take<float>(opsz(nh, mh)) : nullptr;
@@ -473,7 +485,7 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   if (!(p->re > 0) || !(p->wi > 0) || !(p->beta >= 0 && p->beta <= 1) || !(p->kappa >= 0) || !(p->dt > 0))
     return PCS_ERR_ARG;
   if (p->forcing != 0 && p->forcing != 1) return PCS_ERR_ARG;
-  if (p->precision < 0 || p->precision > 3) return PCS_ERR_ARG;
+  if (p->precision < 0 || p->precision > 4) return PCS_ERR_ARG;
   if (p->scheme != 0 && p->scheme != 1) return PCS_ERR_ARG;
   if (!valid_fft(3 * g->nx / 2) || !valid_fft(g->nx)) return PCS_ERR_UNSUPPORTED;
   if (g->dim == 3 && (!valid_fft(3 * g->nz / 2) || !valid_fft(g->nz))) return PCS_ERR_UNSUPPORTED;
@@ -495,6 +507,7 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   d.lx = g->lx;
   d.lz = g->dim == 2 ? 1.0 : g->lz;
   m->prec = p->precision;
+  m->yv1 = m->yv2 = m->prec == 4 ? Y_FP64 : m->prec;
   // every transform's working set must fit one workgroup's LDS
   const size_t lds_max = 160 * 1024;
   if (xpencil_lds_bytes(d.dim, d.px, m->prec) > lds_max) return PCS_ERR_UNSUPPORTED;
@@ -681,11 +694,10 @@ void build_jobs(Member* m) {
   // odd parts): half rows mh / nh, half columns nh / mh, ne eigen pairs.
   const int mh = (m1 + 1) / 2, nh = (n1 + 1) / 2, ne = (ni + 1) / 2;  // ne: even eigenvectors
   JobList& g1 = m->G1;
-  // precision 1: FP32; 2: FP64; 3: error-compensated FP32 (FP32 operator
+  // variant yv1: FP32, FP64, or error-compensated FP32 (FP32 operator
   // heads and tails, parity form only)
-  const bool comp = m->prec == 3;
-  g1.type = mixed ? (m->prec == 2 ? GEMM_DDF : (comp ? GEMM_CDF : GEMM_FDF)) : GEMM_DDD;
-  const bool f32ops = mixed && m->prec != 2;
+  g1.type = mixed ? (m->yv1 == Y_FP64 ? GEMM_DDF : (m->yv1 == Y_COMP ? GEMM_CDF : GEMM_FDF)) : GEMM_DDD;
+  const bool f32ops = mixed && m->yv1 != Y_FP64;
   const void* I = f32ops ? (const void*)m->IMN32 : (const void*)m->IMN;
   const void* DI = f32ops ? (const void*)m->DMN32 : (const void*)m->DMN;
   const void* Ip[2] = {f32ops ? (const void*)m->IMN32p[0] : m->IMNp[0], f32ops ? (const void*)m->IMN32p[1] : m->IMNp[1]};
@@ -697,7 +709,7 @@ void build_jobs(Member* m) {
   const int nvel = d.dim;
   // values (centrosymmetric operator) and d/dy (centro-antisymmetric) on the padded grid
   auto tails = [&](JobList& jl, float* const (&lo)[2]) {
-    if (comp) {
+    if (gemm_type_comp(jl.type)) {
       jl.forms[1].back().Alo = lo[0];
       jl.forms[1].back().A2lo = lo[1];
     }
@@ -760,11 +772,13 @@ void build_jobs(Member* m) {
              -1);
   // G2: projection of the explicit terms, and D of the projected N_x, N_z
   // through (D P) (mixed: FP32 operands, FP64 result)
-  m->G2.type = mixed ? (m->prec == 2 ? GEMM_DFD : (comp ? GEMM_CFD : GEMM_FFD)) : GEMM_DDD;
-  const void* P = f32ops ? (const void*)m->PNM32 : (const void*)m->PNM;  // (plain form; not used by precision 3)
-  const void* DP = f32ops ? (const void*)m->DP32 : (const void*)m->DP;
-  const void* Pp[2] = {f32ops ? (const void*)m->PNM32p[0] : m->PNMp[0], f32ops ? (const void*)m->PNM32p[1] : m->PNMp[1]};
-  const void* DPp[2] = {f32ops ? (const void*)m->DP32p[0] : m->DPp[0], f32ops ? (const void*)m->DP32p[1] : m->DPp[1]};
+  m->G2.type = mixed ? (m->yv2 == Y_FP64 ? GEMM_DFD : (m->yv2 == Y_COMP ? GEMM_CFD : GEMM_FFD)) : GEMM_DDD;
+  const bool f32ops2 = mixed && m->yv2 != Y_FP64;
+  const void* P = f32ops2 ? (const void*)m->PNM32 : (const void*)m->PNM;  // (plain form; not used by Y_COMP)
+  const void* DP = f32ops2 ? (const void*)m->DP32 : (const void*)m->DP;
+  const void* Pp[2] = {f32ops2 ? (const void*)m->PNM32p[0] : m->PNMp[0],
+                       f32ops2 ? (const void*)m->PNM32p[1] : m->PNMp[1]};
+  const void* DPp[2] = {f32ops2 ? (const void*)m->DP32p[0] : m->DPp[0], f32ops2 ? (const void*)m->DP32p[1] : m->DPp[1]};
   const char* Yo = mixed ? (const char*)m->Yout32 : (const char*)m->Yout;
   for (int f = 0; f < m->nout; ++f) {
     m->G2.addp(PAR_FOLD_UNFOLD, P, Pp[0], Pp[1], Yo + (size_t)f * fsm * ysz, cw, m->S + f * fs, cw, nh, cw, mh, n1, m1,
@@ -873,9 +887,9 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
       return r != hipSuccess ? r : up(dst[1], padded<float>(o, rows, cols), s);
     };
     const bool mixed = m->prec != 0;
-    // FP32 tails of the halves (precision 3): v - fp32(v), rounded to FP32
+    // FP32 tails of the halves (precisions 3 and 4): v - fp32(v), rounded to FP32
     auto put2t = [&](float* const (&dst)[2], int rows, int cols) -> hipError_t {
-      if (m->prec != 3) return hipSuccess;
+      if (m->prec != 3 && m->prec != 4) return hipSuccess;
       std::vector<double> te(e.size()), to(o.size());
       for (size_t i = 0; i < e.size(); ++i) te[i] = e[i] - (double)(float)e[i];
       for (size_t i = 0; i < o.size(); ++i) to[i] = o[i] - (double)(float)o[i];
@@ -1660,6 +1674,164 @@ pcs_status setup_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_par
 pcs_status sbdf4_cold_start(Member* m, hipStream_t s, long long step);
 pcs_status member_set_state(Member* m, hipStream_t s, const double* host, size_t n);
 
+// Largest difference of `got` from `ref` relative to the largest magnitude
+// of `ref`, per field of rows x cw values (columns 0 and 1, the mean mode,
+// excluded: the mixed path carries that mode in FP64 elsewhere), maximised
+// over the fields; infinite for a non-finite difference.
+template <typename T>
+double field_error(const T* got, const T* ref, size_t nf, size_t rows, size_t cw) {
+  double worst = 0;
+  for (size_t f = 0; f < nf; ++f) {
+    double dmax = 0, rmax = 0;
+    for (size_t r = 0; r < rows; ++r)
+      for (size_t c = 2; c < cw; ++c) {
+        const size_t i = (f * rows + r) * cw + c;
+        const double d = std::fabs((double)got[i] - (double)ref[i]);
+        if (!(d <= dmax)) dmax = d;  // also NaN
+        rmax = std::max(rmax, std::fabs((double)ref[i]));
+      }
+    if (!std::isfinite(dmax)) return INFINITY;
+    if (dmax > 0) worst = std::max(worst, rmax > 0 ? dmax / rmax : INFINITY);
+  }
+  return worst;
+}
+
+// Precision 4: the variant of each wall-normal product table, chosen under
+// the error budget (see pcs_params.precision).  Every variant runs the
+// explicit half of a step on the initial state; the FP64-operator variant
+// is the reference.  A variant of the state products is judged by its own
+// outputs (the padded-grid values and d/dy), a variant of the projections
+// by its outputs under the reference state products, so that each error
+// belongs to one table.  Times are those of the table's launch after
+// tuning; an eager batch is not timed and prefers FP32, then FP64.  Leaves
+// the batch built with the choice, tuned, and the tables of the homogeneous
+// solutions uploaded; the state is reset by the caller.
+pcs_status choose_y_variants(Batch* b, const uint64_t* seeds, double amp) {
+  double budget = 1e-5;
+  if (const char* e = std::getenv("PCS_Y_ERROR_BUDGET")) {
+    char* end = nullptr;
+    const double v = std::strtod(e, &end);
+    if (end == e || !(v >= 0) || !std::isfinite(v)) return PCS_ERR_ARG;
+    budget = v;
+  }
+  b->ybudget = budget;
+  hipStream_t s = b->s;
+  struct Events {
+    hipEvent_t e[2] = {nullptr, nullptr};
+    ~Events() {
+      for (hipEvent_t x : e)
+        if (x) (void)hipEventDestroy(x);
+    }
+  } ev;
+  if (!b->eager) {
+    HIPCHK(hipEventCreate(&ev.e[0]));
+    HIPCHK(hipEventCreate(&ev.e[1]));
+  }
+  auto time_us = [&](const JobList& jl, double* out) -> pcs_status {
+    jl.run(s);  // warm-up
+    HIPCHK(hipEventRecord(ev.e[0], s));
+    for (int r = 0; r < 5; ++r) jl.run(s);
+    HIPCHK(hipEventRecord(ev.e[1], s));
+    HIPCHK(hipEventSynchronize(ev.e[1]));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, ev.e[0], ev.e[1]));
+    *out = ms * 1e3 / 5;
+    return PCS_OK;
+  };
+  auto rebuild = [&](int v1, int v2) -> pcs_status {
+    for (Member* m : b->mem) {
+      m->yv1 = v1;
+      m->yv2 = v2;
+      build_jobs(m);
+    }
+    build_batch(b);
+    pcs_status st = PCS_OK;
+    if (!b->eager && (st = autotune(b)) != PCS_OK) return st;
+    return PCS_OK;
+  };
+  const size_t nm = b->mem.size();
+  // per member: reference padded-grid values (FP32) and projections (FP64)
+  std::vector<std::vector<float>> yref(nm);
+  std::vector<std::vector<double>> sref(nm);
+  std::vector<float> ybuf;
+  std::vector<double> sbuf;
+  // runs the explicit half of a step in variants (v1, v2) and measures the
+  // state products (t1, e1) and / or the projections (t2, e2)
+  auto trial = [&](int v1, int v2, int t1, int t2) -> pcs_status {
+    pcs_status st = rebuild(v1, v2);
+    if (st != PCS_OK) return st;
+    for (size_t i = 0; i < nm; ++i)
+      if ((st = reset_state(b->mem[i], seeds[i], amp, s)) != PCS_OK) return st;
+    if ((st = upload_tables(b)) != PCS_OK) return st;
+    explicit_stage(b, NoMark());
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(s));
+    const bool ref = v1 == Y_FP64 && v2 == Y_FP64;
+    for (size_t i = 0; i < nm; ++i) {
+      const Member* m = b->mem[i];
+      const size_t cw = m->d.cw, m1 = m->d.M + 1, n1 = m->d.N + 1;
+      if (ref || t1 > 0) {
+        std::vector<float>& y = ref ? yref[i] : ybuf;
+        y.resize((size_t)m->nyin * m1 * cw);
+        HIPCHK(hipMemcpy(y.data(), m->Yin32, y.size() * sizeof(float), hipMemcpyDeviceToHost));
+        if (!ref)
+          b->yerr[0][t1 - 1] = std::max(std::max(b->yerr[0][t1 - 1], 0.0),
+                                        field_error(y.data(), yref[i].data(), m->nyin, m1, cw));
+      }
+      if (ref || t2 > 0) {
+        // the projections S (nout fields), then D N (1 or 2 fields)
+        std::vector<double>& q = ref ? sref[i] : sbuf;
+        const size_t ns = (size_t)m->nout * n1 * cw, nd = (size_t)(m->d.dim == 2 ? 1 : 2) * n1 * cw;
+        q.resize(ns + nd);
+        HIPCHK(hipMemcpy(q.data(), m->S, ns * sizeof(double), hipMemcpyDeviceToHost));
+        HIPCHK(hipMemcpy(q.data() + ns, m->DN, nd * sizeof(double), hipMemcpyDeviceToHost));
+        if (!ref)
+          b->yerr[1][t2 - 1] =
+              std::max(std::max(b->yerr[1][t2 - 1], 0.0),
+                       field_error(q.data(), sref[i].data(), m->nout + (m->d.dim == 2 ? 1 : 2), n1, cw));
+      }
+    }
+    if (!b->eager) {
+      if (t1 > 0 || ref) {
+        double us = 0;
+        if ((st = time_us(b->GS, &us)) != PCS_OK) return st;
+        b->yus[0][(ref ? Y_FP64 : t1) - 1] = us;
+      }
+      if (t2 > 0 || ref) {
+        double us = 0;
+        if ((st = time_us(b->GP, &us)) != PCS_OK) return st;
+        b->yus[1][(ref ? Y_FP64 : t2) - 1] = us;
+      }
+    }
+    return PCS_OK;
+  };
+  pcs_status st = trial(Y_FP64, Y_FP64, 0, 0);
+  if (st != PCS_OK) return st;
+  b->yerr[0][Y_FP64 - 1] = b->yerr[1][Y_FP64 - 1] = 0.0;
+  std::vector<int> cand{Y_FP32};
+  if (!b->eager) cand.push_back(Y_COMP);
+  for (int v : cand) {
+    if ((st = trial(v, Y_FP64, v, 0)) != PCS_OK || (st = trial(Y_FP64, v, 0, v)) != PCS_OK) return st;
+  }
+  // the fastest variant within the budget (eager: the first of FP32, FP64)
+  int pick[2];
+  for (int t = 0; t < 2; ++t) {
+    pick[t] = Y_FP64;
+    if (b->eager) {
+      if (b->yerr[t][Y_FP32 - 1] <= budget) pick[t] = Y_FP32;
+      continue;
+    }
+    for (int v : cand)
+      if (b->yerr[t][v - 1] <= budget && b->yus[t][v - 1] < b->yus[t][pick[t] - 1]) pick[t] = v;
+  }
+  if ((st = rebuild(pick[0], pick[1])) != PCS_OK) return st;
+  for (Member* m : b->mem) {
+    HIPCHK(up_list(&m->H4, s));
+    HIPCHK(up_list(&m->H5, s));
+  }
+  return PCS_OK;
+}
+
 pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_params* params, const uint64_t* seeds,
                       double amp, void* workspace, size_t bytes, void* stream) {
   if (!workspace || !seeds || !std::isfinite(amp)) return PCS_ERR_ARG;
@@ -1683,7 +1855,11 @@ pcs_status init_batch(Batch* b, int32_t n, const pcs_grid* grids, const pcs_para
   }
   for (int32_t i = 0; i < n; ++i)
     if ((st = upload_member(b->mem[i], seeds[i], amp, b->s)) != PCS_OK) return st;
-  if (!b->eager && (st = autotune(b)) != PCS_OK) return st;
+  if (b->prec == 4) {
+    if ((st = choose_y_variants(b, seeds, amp)) != PCS_OK) return st;
+  } else if (!b->eager && (st = autotune(b)) != PCS_OK) {
+    return st;
+  }
   for (int32_t i = 0; i < n; ++i)
     if ((st = reset_state(b->mem[i], seeds[i], amp, b->s)) != PCS_OK ||
         (st = homogeneous_solutions(b->mem[i], b->s)) != PCS_OK)
@@ -1779,6 +1955,19 @@ pcs_status member_hist_setup(Batch* b, int idx, int q, double lo, double hi, int
 }
 
 // Running moments of quantity q: [samples, sum, sum of squares].
+pcs_status batch_y_choice(const Batch* b, pcs_ychoice* out) {
+  if (!out) return PCS_ERR_ARG;
+  out->variant[0] = b->mem[0]->yv1;
+  out->variant[1] = b->mem[0]->yv2;
+  out->budget = b->ybudget;
+  for (int t = 0; t < 2; ++t)
+    for (int v = 0; v < 3; ++v) {
+      out->error[t][v] = b->yerr[t][v];
+      out->time_us[t][v] = b->yus[t][v];
+    }
+  return PCS_OK;
+}
+
 pcs_status member_moments(Member* m, hipStream_t s, int q, double* out) {
   if (q < 0 || q >= HIST_Q || !out || m->hbins[q] <= 0) return PCS_ERR_ARG;
   HIPCHK(hipStreamSynchronize(s));
@@ -2037,6 +2226,11 @@ pcs_status pcs_midplane_moments(pcs_sim* sim, int32_t quantity, double* out) {
   return member_moments(sim->m(), sim->b.s, quantity, out);
 }
 
+pcs_status pcs_y_choice(pcs_sim* sim, pcs_ychoice* out) {
+  if (!sim) return PCS_ERR_ARG;
+  return batch_y_choice(&sim->b, out);
+}
+
 pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
   if (!sim || nsteps <= 0 || reps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
   if (sim->m()->blowup) return PCS_ERR_STATE;
@@ -2165,6 +2359,11 @@ pcs_status pcs_ensemble_midplane_pdf(pcs_ens* e, int32_t run, int32_t quantity, 
 pcs_status pcs_ensemble_midplane_moments(pcs_ens* e, int32_t run, int32_t quantity, double* out) {
   if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
   return member_moments(e->b.mem[run], e->b.s, quantity, out);
+}
+
+pcs_status pcs_ensemble_y_choice(pcs_ens* e, pcs_ychoice* out) {
+  if (!e) return PCS_ERR_ARG;
+  return batch_y_choice(&e->b, out);
 }
 
 pcs_status pcs_ensemble_destroy(pcs_ens* e) {

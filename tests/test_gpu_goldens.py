@@ -26,7 +26,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
 CASES = [("c5", "c5_oracle_8steps.npz"), ("c3", "c3_oracle_100steps.npz")]
 
 
-@pytest.mark.parametrize("precision", [0, 1, 3])
+@pytest.mark.parametrize("precision", [0, 1, 3, 4])
 @pytest.mark.parametrize("name,fname", CASES, ids=[c[0] for c in CASES])
 def test_full_size_against_golden(P, name, fname, precision):
     z = np.load(os.path.join(GOLDEN, fname), allow_pickle=False)

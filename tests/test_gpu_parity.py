@@ -497,7 +497,7 @@ MIXED_CASES = [
 ]
 
 
-@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("precision", [1, 2, 3, 4])
 @pytest.mark.parametrize("case", MIXED_CASES, ids=[c[0] for c in MIXED_CASES])
 def test_mixed_precision_against_fp64_oracle(P, case, precision):
     """Mixed path (FP32 transforms and products of the fluctuation, FP64 mean
@@ -526,7 +526,7 @@ def test_mixed_precision_against_fp64_oracle(P, case, precision):
         assert abs(d[k] - e[k]) <= 1e-8 * max(1.0, abs(e[k])), (k, d[k], e[k])
 
 
-@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("precision", [1, 2, 3, 4])
 def test_mixed_keeps_laminar_state_exact(P, precision):
     """With no fluctuation the FP32 part contributes nothing: the laminar state
     stays fixed to FP64 roundoff in mixed precision too (measured 5e-13 after
@@ -541,7 +541,7 @@ def test_mixed_keeps_laminar_state_exact(P, precision):
         assert np.abs(s1[4:] - s0[4:]).max() / np.abs(s0[4:]).max() < 1e-11
 
 
-@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("precision", [1, 2, 3, 4])
 @pytest.mark.parametrize("case", [("2D 64x65 eps 0.05 x40", Grid(2, 64, 65), 40),
                                   ("3D 16x33x16 eps 0.05 x20", Grid(3, 16, 33, 16), 20)], ids=["2D", "3D"])
 def test_mixed_precision_sptt_against_fp64_oracle(P, case, precision):

@@ -133,7 +133,7 @@ def test_sbdf4_resume_and_stage_path(P):
         s.close()
 
 
-@pytest.mark.parametrize("precision", [1, 2, 3])
+@pytest.mark.parametrize("precision", [1, 2, 3, 4])
 def test_sbdf4_mixed_precision(P, precision):
     """Mixed precision with SBDF4 against the FP64 oracle, to the bar of the
     CNAB2 mixed path: prognostic fluctuation within 2e-4 of its own max,
