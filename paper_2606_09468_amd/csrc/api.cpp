@@ -101,6 +101,31 @@ struct JobList {
     j.kf = kf;
     j.sigma = sigma;
   }
+  // Marks consecutive parity products that fold the same B panel (see
+  // GemmJob::pair) so that the B-stationary tiles stage it once for both;
+  // error-compensated products are never paired (their kernel stages four
+  // panels and computes one product per tile).
+  // PCS_PAIR_PANELS=0 in the environment leaves every product unpaired (for
+  // comparison).
+  void mark_pairs() {
+    if (const char* e = std::getenv("PCS_PAIR_PANELS"))
+      if (std::atoi(e) == 0) return;
+    std::vector<GemmJob>& f = forms[1];
+    auto plain_parity = [](const GemmJob& a) {
+      return a.kind == PAR_FOLD_UNFOLD && a.scale == SCALE_NONE && a.C2 == nullptr && !gemm_type_comp((GemmType)a.type);
+    };
+    for (size_t j = 0; j + 1 < f.size();) {
+      const GemmJob &a = f[j], &b = f[j + 1];
+      if (plain_parity(a) && plain_parity(b) && a.B == b.B && a.k == b.k && a.kf == b.kf && a.ldb == b.ldb &&
+          a.n == b.n && a.flags == b.flags && a.type == b.type) {
+        f[j].pair = 1;
+        f[j + 1].pair = 2;
+        j += 2;
+      } else {
+        ++j;
+      }
+    }
+  }
   int n() const { return (int)forms[0].size(); }
   void clear() {
     h.clear();
@@ -322,7 +347,8 @@ struct Batch {
   FinArgs* dfin = nullptr;
   int bx = 0, bzi = 0, bzf = 0, bzd = 0, bdr = 0, brhs = 0, bfin = 0;
   size_t lx = 0, lzi = 0, lzf = 0, lzd = 0, ldr = 0;
-  int xnt = 0;  // threads per x-pencil workgroup
+  int xnt = 0;          // threads per x-pencil workgroup
+  int xchunk = 0;       // 3D lines in field chunks: their common length (xpencil_chunked), else 0
   // one step, and GRAPH_STEPS steps back to back (fewer launches between steps)
   hipGraph_t graph = nullptr, graphn = nullptr;
   hipGraphExec_t gexec = nullptr, gexecn = nullptr;
@@ -722,13 +748,23 @@ void build_jobs(Member* m) {
     g1.addp(PAR_FOLD_UNFOLD, DI, DIp[0], DIp[1], src, cw, dst, cw, mh, cw, nh, m1, n1, -1, zm);
     tails(g1, m->DMN32lp);
   };
-  for (int a = 0; a < nvel; ++a) val(st + a * fs, yf(a));
-  for (int a = 0; a < d.nc; ++a) val(st + (FC + a) * fs, yf(nvel + a));
+  // padded-grid inputs: values of u v (w) c, then d/dy of u (w) c; the
+  // products are listed with the values and d/dy of one field adjacent, so
+  // that they share a staged panel (mark_pairs)
   const int yd0 = nvel + d.nc;  // first d/dy field in the padded-grid input
+  val(st + 0 * fs, yf(0));
   dy(st + 0 * fs, yf(yd0));
-  int o = yd0 + 1;
-  if (d.dim == 3) dy(st + 2 * fs, yf(o++));
-  for (int a = 0; a < d.nc; ++a) dy(st + (FC + a) * fs, yf(o++));
+  val(st + 1 * fs, yf(1));
+  if (d.dim == 3) {
+    val(st + 2 * fs, yf(2));
+    dy(st + 2 * fs, yf(yd0 + 1));
+  }
+  const int ydc = yd0 + (d.dim == 3 ? 2 : 1);  // first d/dy of c
+  for (int a = 0; a < d.nc; ++a) {
+    val(st + (FC + a) * fs, yf(nvel + a));
+    dy(st + (FC + a) * fs, yf(ydc + a));
+  }
+  g1.mark_pairs();
   if (mixed) {
     // FP64 mean profiles on the padded grid (real part of the kx = kz = 0 column)
     // 2D: U U' c (3) c' (3); 3D: U W U' W' c (6) c' (6)
@@ -761,15 +797,17 @@ void build_jobs(Member* m) {
   auto stress_d2 = [&](int a) { return a == 1 || (d.dim == 3 && a == 4); };
   if (cn) d2(st + FPHI * fs, m->D2buf + 0 * fs);
   if (cn && d.dim == 3) d2(st + 4 * fs, m->D2buf + 1 * fs);
-  for (int a = 0; a < d.nc; ++a)
+  // D2 and D of each c adjacent (one staged panel, mark_pairs)
+  for (int a = 0; a < d.nc; ++a) {
     if (cn || stress_d2(a)) d2(st + (FC + a) * fs, m->D2buf + (m->nsv + a) * fs);
+    g1b.addp(PAR_FOLD_UNFOLD, m->D, m->Dp[0], m->Dp[1], st + (FC + a) * fs, cw, m->Dc + a * fs, cw, nh, cw, nh, n1, n1,
+             -1);
+  }
   double* D2U = m->D2buf + (size_t)m->nsolve * fs;
   if (cn) g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], st + 0 * fs, cw, D2U, 1, nh, 1, nh, n1, n1, +1);
   if (cn && d.dim == 3)
     g1b.addp(PAR_FOLD_UNFOLD, m->D2, m->D2p[0], m->D2p[1], st + 2 * fs, cw, D2U + n1, 1, nh, 1, nh, n1, n1, +1);
-  for (int a = 0; a < d.nc; ++a)
-    g1b.addp(PAR_FOLD_UNFOLD, m->D, m->Dp[0], m->Dp[1], st + (FC + a) * fs, cw, m->Dc + a * fs, cw, nh, cw, nh, n1, n1,
-             -1);
+  g1b.mark_pairs();
   // G2: projection of the explicit terms, and D of the projected N_x, N_z
   // through (D P) (mixed: FP32 operands, FP64 result)
   m->G2.type = mixed ? (m->yv2 == Y_FP64 ? GEMM_DFD : (m->yv2 == Y_COMP ? GEMM_CFD : GEMM_FFD)) : GEMM_DDD;
@@ -1076,6 +1114,9 @@ void build_batch(Batch* b) {
   b->hfin.clear();
   b->bx = b->bzi = b->bzf = b->bzd = b->bdr = b->brhs = b->bfin = 0;
   b->lx = b->lzi = b->lzf = b->lzd = b->ldr = 0;
+  b->xchunk = mem[0]->d.px;
+  for (Member* m : mem)
+    if (!xpencil_chunked(m->d.dim, m->d.px, m->prec) || m->d.px != mem[0]->d.px) b->xchunk = 0;
   for (Member* m : mem) {
     const Dims& d = m->d;
     const bool mixed = m->prec != 0;
@@ -1103,7 +1144,7 @@ void build_batch(Batch* b) {
     x.skip = skip;
     x.blk0 = b->bx;
     b->bx += x.nrows;
-    b->lx = std::max(b->lx, xpencil_lds_bytes(d.dim, d.px, m->prec));
+    b->lx = std::max(b->lx, xpencil_lds_bytes(d.dim, d.px, m->prec, b->xchunk > 0));
     b->hx.push_back(x);
     if (d.dim == 3) {
       const int ngx = (d.nkx + ZFFT_GROUP - 1) / ZFFT_GROUP;
@@ -1260,7 +1301,7 @@ void build_batch(Batch* b) {
     b->bfin += eblocks;
     b->hfin.push_back(q);
   }
-  b->xnt = xpencil_threads(b->prec, b->lx, b->bx);
+  b->xnt = b->xchunk > 0 ? xpencil_chunk_threads() : xpencil_threads(b->prec, b->lx, b->bx);
 }
 
 // Carves every member, builds all tables, and carves the batch's device
@@ -1320,7 +1361,8 @@ void explicit_stage(Batch* b, const Mark& mark) {
   for (int r = mark(ST_GEMM_D2); r > 0; --r) b->GSb.run(s);
   for (int r = mark(ST_ZFFT_INV); r > 0; --r)
     if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
-  for (int r = mark(ST_XPENCIL); r > 0; --r) launch_xpencil(b->dim, b->prec, b->xnt, b->dx, nm, b->bx, b->lx, s);
+  for (int r = mark(ST_XPENCIL); r > 0; --r)
+    launch_xpencil(b->dim, b->prec, b->xnt, b->xchunk, b->dx, nm, b->bx, b->lx, s);
   for (int r = mark(ST_ZFFT_FWD); r > 0; --r)
     if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
   for (int r = mark(ST_GEMM_PROJ); r > 0; --r) b->GP.run(s);
@@ -1385,7 +1427,7 @@ void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
   b->GS.run(s);
   if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
   if (prod) (void)hipStreamWaitEvent(s, ev[1], 0);
-  launch_xpencil(b->dim, b->prec, b->xnt, b->dx, nm, b->bx, b->lx, s);
+  launch_xpencil(b->dim, b->prec, b->xnt, b->xchunk, b->dx, nm, b->bx, b->lx, s);
   if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
   b->GP.run(s);
   if (prod) (void)hipStreamWaitEvent(s, ev[2], 0);

@@ -21,6 +21,10 @@
 //          - (eps/Wi) Tr(c - I)(c_ab - delta_ab)                (eq. 1)
 // at every point, and writes the forward transforms of the outputs,
 // truncated to the retained modes.  d_y v comes from continuity (eq. 3).
+#include <cstdlib>
+#include <cstring>
+#include <type_traits>
+
 #include "kernels.hpp"
 
 namespace pcs {
@@ -749,6 +753,297 @@ size_t xpencil_lds(int L) {
   return (lds_span<true>((size_t)XShape<DIM>::NP * L) + L) * sizeof(cx<T>);
 }
 
+// ------------------------------------------------ 3D x pencils in field chunks
+// Of the 35 real fields of a 3D line only the nine values u, v, w, c enter
+// products with each other (the sPTT term); each of the 26 gradients enters
+// the explicit terms of eqs. (1)-(2) linearly, with coefficients made of the
+// nine values: -u_k d_k u_a in N_a, -u_k d_k c_ab in F_ab, and d_k u_a in
+// F_ab through (d_k u_a) c_kb and c_ak (d_k u_b) (d_y v = -(d_x u + d_z w)
+// by eq. (3) adds through both of its terms).  The chunked pencil keeps the
+// nine values and the nine explicit terms of its points in registers and
+// passes the fields through LDS a chunk of CP pairs at a time (one pair per
+// wave): the chunk's spectra are packed and inverse transformed, every point
+// adds the chunk's contributions, and the LDS takes the next chunk, whose
+// global loads are issued before the current chunk's transforms.  A line
+// then needs CP pairs of LDS instead of 18, and several lines share a CU.
+
+// kind of real field f of the 3D line: 0 a value (u v w c), 1 a velocity
+// gradient d_k u_a, 2 a conformation gradient d_k c_q, 3 the zero pad
+__host__ __device__ constexpr int x3_kind(int f) {
+  return f < 9 ? 0 : f < 12 ? 1 : f < 18 ? 2 : f < 20 ? 1 : f < 26 ? 2 : f < 29 ? 1 : f < 35 ? 2 : 3;
+}
+// derivative direction k of gradient f
+__host__ __device__ constexpr int x3_dir(int f) { return f < 18 ? 0 : f < 26 ? 1 : 2; }
+// component of gradient f: a of d_k u_a, or the stored index q of d_k c_q
+__host__ __device__ constexpr int x3_comp(int f) {
+  return f < 12 ? f - 9 : f < 18 ? f - 12 : f == 18 ? 0 : f == 19 ? 2 : f < 26 ? f - 20 : f < 29 ? f - 26 : f - 29;
+}
+
+// product of two split factors (mean m, fluctuation f): the part containing
+// a fluctuation, (am + af) bf + af bm, as fprod, with the terms of a mean part
+// that does not exist (HA, HB false: the factor has no mean) left out; FP64
+// path: the plain product of the values
+template <bool MIXED, bool HA, bool HB, typename T>
+__device__ __attribute__((always_inline)) inline T xprod(T am, T af, T bm, T bf) {
+  if constexpr (!MIXED)
+    return af * bf;
+  else if constexpr (HA && HB)
+    return (am + af) * bf + af * bm;
+  else if constexpr (HA)
+    return (am + af) * bf;
+  else if constexpr (HB)
+    return af * bf + af * bm;
+  else
+    return af * bf;
+}
+
+// Per point of the chunked pencil: the values v = u v w c (mixed: their
+// fluctuations; the means are the line's profile values mr = the mean
+// profiles at its y row, in the order of mean_of) and the explicit terms
+// o = N_x N_y N_z F (6).
+template <bool MIXED, typename T>
+__device__ __attribute__((always_inline)) inline T x3_umean(const T (&mr)[16], int k) {
+  if constexpr (MIXED) return k == 0 ? mr[0] : (k == 2 ? mr[1] : T(0));
+  else return T(0);
+}
+template <bool MIXED, typename T>
+__device__ __attribute__((always_inline)) inline T x3_cmean(const T (&mr)[16], int q) {
+  if constexpr (MIXED) return mr[4 + q];
+  else return T(0);
+}
+
+// contributions of G = d_K u_A = (gm, gf) (HG: G has a mean part)
+template <int K, int A, bool HG, bool MIXED, typename T>
+__device__ __attribute__((always_inline)) inline void x3_vgrad(T gm, T gf, const T (&mr)[16], const T (&v)[9],
+                                                               T (&o)[9]) {
+  o[A] -= xprod<MIXED, K != 1, HG>(x3_umean<MIXED>(mr, K), v[K], gm, gf);
+  int q = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b, ++q) {
+      if (a == A) {
+        const int kb = cidx(3, K, b);
+        o[3 + q] += xprod<MIXED, HG, true>(gm, gf, x3_cmean<MIXED>(mr, kb), v[3 + kb]);
+      }
+      if (b == A) {
+        const int ak = cidx(3, a, K);
+        o[3 + q] += xprod<MIXED, true, HG>(x3_cmean<MIXED>(mr, ak), v[3 + ak], gm, gf);
+      }
+    }
+}
+
+// real field F of the line at the point, value s
+template <int F, bool MIXED, typename T>
+__device__ __attribute__((always_inline)) inline void x3_field(T s, const T (&mr)[16], T (&v)[9], T (&o)[9]) {
+  constexpr int kind = x3_kind(F);
+  if constexpr (kind == 0) {
+    v[F] = s;
+  } else if constexpr (kind == 1 || kind == 2) {
+    constexpr int K = x3_dir(F), E = x3_comp(F), MI = mean_of(3, F);
+    T sm = T(0);
+    if constexpr (MIXED && MI >= 0) sm = mr[MI];
+    if constexpr (kind == 2) {
+      o[3 + E] -= xprod<MIXED, K != 1, (MI >= 0)>(x3_umean<MIXED>(mr, K), v[K], sm, s);
+    } else {
+      x3_vgrad<K, E, (MI >= 0), MIXED>(sm, s, mr, v, o);
+      // d_y v = -(d_x u + d_z w) (d_x u and d_z w have no mean part)
+      if constexpr (F == 9 || F == 28) x3_vgrad<1, 1, false, MIXED>(T(0), -s, mr, v, o);
+    }
+  }
+}
+
+// the sPTT term of eq. (1), from the values alone
+template <bool MIXED, typename T>
+__device__ __attribute__((always_inline)) inline void x3_sptt(T eps_wi, const T (&mr)[16], const T (&v)[9],
+                                                              T (&o)[9]) {
+  if (eps_wi == T(0)) return;
+  T tm = T(-3), tf = T(0);  // Tr(c - I): mean part and fluctuation
+#pragma unroll
+  for (int e = 0; e < 3; ++e) {
+    const int q = cidx(3, e, e);
+    if constexpr (MIXED) {
+      tm += mr[4 + q];
+      tf += v[3 + q];
+    } else {
+      tf += v[3 + q] - T(1);
+    }
+  }
+  int q = 0;
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = a; b < 3; ++b, ++q) {
+      const T d = T(a == b ? 1 : 0);
+      if constexpr (MIXED)
+        o[3 + q] -= eps_wi * xprod<true, true, true>(tm, tf, mr[4 + q] - d, v[3 + q]);
+      else
+        o[3 + q] -= eps_wi * tf * (v[3 + q] - d);
+    }
+}
+
+// fields F .. FE - 1 of a chunk that starts at field F0, read from LDS at
+// point n (pair j of the chunk at j L)
+template <int F, int FE, int F0, bool MIXED, typename T, typename V>
+__device__ __attribute__((always_inline)) inline void x3_chunk_fields(V X, int L, int n, const T (&mr)[16], T (&v)[9],
+                                                                      T (&o)[9]) {
+  if constexpr (F < FE) {
+    const cx<T> z = X[((F - F0) >> 1) * L + n];
+    x3_field<F, MIXED>(z.x, mr, v, o);
+    if constexpr (F + 1 < FE) x3_field<F + 1, MIXED>(z.y, mr, v, o);
+    x3_chunk_fields<F + 2, FE, F0, MIXED>(X, L, n, mr, v, o);
+  }
+}
+
+// calls f(integral_constant<int, I>) for I = I0 .. I1 - 1 in order
+template <int I, int I1, typename Fn>
+__device__ __attribute__((always_inline)) inline void static_for(Fn&& f) {
+  if constexpr (I < I1) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, I1>(f);
+  }
+}
+
+// threads of a chunked pencil: six waves, one field pair each per chunk,
+// and one point per thread for lines up to 384 (measured: 256 threads, two
+// points each, need 180 registers)
+constexpr int X3C_NTH = 384;
+
+template <typename T, bool MIXED, int NTH, int LC>
+__device__ __attribute__((always_inline)) inline void xpencil3c_body(const XArgs& XA) {
+  constexpr int CP = NTH / 64;                // field pairs per chunk
+  constexpr int NCH = (18 + CP - 1) / CP;    // chunks over the 18 pairs
+  constexpr int PPT = (LC + NTH - 1) / NTH;  // points per thread
+  constexpr int NKB = (LC / 3 + 63) / 64;    // blocks of 64 kx (nkx = L / 3)
+  // one sequence per wave: L / 64 values per lane in every pass
+  constexpr int MVW = LC <= 384 ? 8 : 16;
+  static_assert(64 * cover(MVW) >= LC, "a wave's pass must cover its sequence");
+  typedef typename V2<T>::type T2;
+  typedef LV<T, true> XV;
+  const XV PV{0};
+  const int nkx = XA.nkx, row = blockIdx.x - XA.blk0, tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const size_t fstride = (size_t)XA.nrows * nkx * 2;
+  const gptr<const T> base = gmem(static_cast<const T*>(XA.in)) + (size_t)row * nkx * 2;
+  const gptr<const double> kx = gmem(XA.kx);
+  cx<T>* twl = reinterpret_cast<cx<T>*>(fft_lds) + lds_span<true>((size_t)CP * LC);
+  T2 va[NKB], vb[NKB];
+  // global loads of this wave's pair of chunk c (fields 2p, 2p + 1; none from 35)
+  auto load = [&](int c) {
+    const int fa = 2 * (c * CP + wave), fb = fa + 1;
+#pragma unroll
+    for (int u = 0; u < NKB; ++u) {
+      const int k = lane + 64 * u;
+      va[u] = vb[u] = T2{0, 0};
+      if (k < nkx && fa < 35) {
+        va[u] = *reinterpret_cast<gptr<const T2>>(base + XSRC[1][fa] * fstride + 2 * k);
+        if (fb < 35) vb[u] = *reinterpret_cast<gptr<const T2>>(base + XSRC[1][fb] * fstride + 2 * k);
+      }
+    }
+  };
+  // packs the loaded pair (d/dx applied where the table says) into this
+  // wave's sequence, zero between the retained modes
+  auto pack = [&](int c) {
+    const XV X = PV.at(wave * LC);
+    for (int e = nkx + lane; e <= LC - nkx; e += 64) X[e] = cx<T>{0, 0};
+    const int fa = 2 * (c * CP + wave), fb = fa + 1;
+    const bool da = fa < 35 && XDX[1][fa] != 0, db = fb < 35 && XDX[1][fb] != 0;
+#pragma unroll
+    for (int u = 0; u < NKB; ++u) {
+      const int k = lane + 64 * u;
+      if (k < nkx) {
+        cx<T> A{va[u][0], va[u][1]}, B{vb[u][0], vb[u][1]};
+        if (da || db) {
+          const T kk = T(kx[k]);
+          if (da) A = cx<T>{-kk * A.y, kk * A.x};
+          if (db) B = cx<T>{-kk * B.y, kk * B.x};
+        }
+        pack_pair(X, LC, k, A, B);
+      }
+    }
+    pass_sync<true>();  // the wave's transform reads what its lanes wrote
+  };
+  // twiddles (loads issued first), then chunk 0's loads
+  constexpr int TWN = (LC + NTH - 1) / NTH;
+  T2 tv[TWN];
+  {
+    const gptr<const T2> g = gmem(static_cast<const T2*>(XA.tw));
+#pragma unroll
+    for (int r = 0; r < TWN; ++r) tv[r] = tid + r * NTH < LC ? g[tid + r * NTH] : T2{0, 0};
+  }
+  load(0);
+#pragma unroll
+  for (int r = 0; r < TWN; ++r)
+    if (tid + r * NTH < LC) twl[tid + r * NTH] = cx<T>{tv[r][0], tv[r][1]};
+  T mr[16];
+  if constexpr (MIXED) {
+    const gptr<const double> mean = gmem(XA.mean);
+    const int yrow = row / XA.pz;
+    // one value per workgroup: kept in scalar registers
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      mr[i] = __builtin_bit_cast(T, __builtin_amdgcn_readfirstlane(
+                                        __builtin_bit_cast(int, T(mean[(size_t)i * XA.m1 + yrow]))));
+  } else {
+#pragma unroll
+    for (int i = 0; i < 16; ++i) mr[i] = T(0);
+  }
+  T pv[PPT][9], po[PPT][9];
+#pragma unroll
+  for (int i = 0; i < PPT; ++i)
+#pragma unroll
+    for (int q = 0; q < 9; ++q) pv[i][q] = po[i][q] = T(0);
+  __syncthreads();  // the twiddles
+  static_for<0, NCH>([&](auto cc) {
+    constexpr int C = decltype(cc)::value;
+    pack(C);
+    if constexpr (C + 1 < NCH) load(C + 1);
+    fft_any<T, LC, 64, MVW, true, +1>(PV.at(wave * LC), LC, XA.pl, 1, twl, lane);
+    __syncthreads();
+    constexpr int F0 = 2 * CP * C, FE = (2 * CP * (C + 1) < 35) ? 2 * CP * (C + 1) : 35;
+#pragma unroll
+    for (int i = 0; i < PPT; ++i) {
+      const int n = tid + i * NTH;
+      if (n < LC) x3_chunk_fields<F0, FE, F0, MIXED>(PV, LC, n, mr, pv[i], po[i]);
+    }
+    __syncthreads();
+  });
+  // the explicit terms to LDS as five pairs (the last half zero), forward
+  // transforms (a wave per pair), truncation to the retained modes
+  const T eps_wi = T(XA.eps_wi);
+#pragma unroll
+  for (int i = 0; i < PPT; ++i) {
+    const int n = tid + i * NTH;
+    if (n < LC) {
+      x3_sptt<MIXED>(eps_wi, mr, pv[i], po[i]);
+#pragma unroll
+      for (int q = 0; q < 5; ++q) PV[q * LC + n] = cx<T>{po[i][2 * q], q < 4 ? po[i][2 * q + 1] : T(0)};
+    }
+  }
+  __syncthreads();
+  const T inv = T(1.0 / LC);
+  const gptr<T> obase = gmem(static_cast<T*>(XA.out)) + (size_t)row * nkx * 2;
+  for (int q = wave; q < 5; q += CP) {
+    fft_any<T, LC, 64, MVW, true, -1>(PV.at(q * LC), LC, XA.pl, 1, twl, lane);
+    for (int k = lane; k < nkx; k += 64) {
+      cx<T> A, B;
+      unpack_pair(PV.at(q * LC), LC, k, A, B);
+      const int fa = 2 * q, fb = fa + 1;
+      *reinterpret_cast<gptr<T2>>(obase + (size_t)fa * fstride + 2 * k) = T2{A.x * inv, A.y * inv};
+      if (fb < 9) *reinterpret_cast<gptr<T2>>(obase + (size_t)fb * fstride + 2 * k) = T2{B.x * inv, B.y * inv};
+    }
+  }
+}
+
+// One compiled line length per kernel (its registers are those of that
+// length alone); xpencil_chunked admits a launch whose lines all have it.
+template <typename T, bool MIXED, int NTH, int LC>
+__global__ __launch_bounds__(NTH) void xpencil3c_kernel(const XArgs* __restrict__ args, int nmem) {
+  const XArgs& XA = args[member_of(args, nmem)];
+  if (masked(XA.skip)) return;
+  xpencil3c_body<T, MIXED, NTH, LC>(XA);
+}
+
 // ---------------------------------------------------------------- z columns
 // Complex transforms along the spanwise index of [field][y][z row][kx] data.
 // inverse: kz slots (Nyquist slot skipped, optional i kz factor) are placed at
@@ -1301,9 +1596,45 @@ int xpencil_threads(int precision, size_t lds, int lines) {
   return (160 * 1024) / lds < 4 ? 2 * NT : NT;
 }
 
-void launch_xpencil(int dim, int precision, int threads, const XArgs* args, int nmem, int blocks, size_t lds,
-                    hipStream_t s) {
+// The chunked pencil where it was measured faster than the whole line (in
+// LDS-limited FP64 lines of 384: 5.07 against 5.31 ms per launch of
+// 256 x 257 x 128; slower in FP32 of that size, 2.11 against 2.11 ms, and in
+// lines of 192, 0.38 / 0.61 against 0.24 / 0.48 ms for 128 x 129 x 64 in
+// FP32 / FP64, where its barriers lengthen each line's chain).
+// PCS_XPENCIL_FORM=chunked or =whole in the environment forces a form for
+// every length it supports.
+bool xpencil_chunked(int dim, int L, int precision) {
+  if (dim != 3 || !(L == 96 || L == 192 || L == 384)) return false;
+  if (const char* e = std::getenv("PCS_XPENCIL_FORM")) {
+    if (!std::strcmp(e, "whole")) return false;
+    if (!std::strcmp(e, "chunked")) return true;
+  }
+  return precision == 0 && L == 384;
+}
+
+int xpencil_chunk_threads() { return X3C_NTH; }
+
+template <typename T, bool MIXED>
+void launch_x3c(int L, const XArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
+  if (L == 96)
+    hipLaunchKernelGGL((xpencil3c_kernel<T, MIXED, X3C_NTH, 96>), dim3(blocks), dim3(X3C_NTH), lds, s, args, nmem);
+  else if (L == 192)
+    hipLaunchKernelGGL((xpencil3c_kernel<T, MIXED, X3C_NTH, 192>), dim3(blocks), dim3(X3C_NTH), lds, s, args, nmem);
+  else if (L == 384)
+    hipLaunchKernelGGL((xpencil3c_kernel<T, MIXED, X3C_NTH, 384>), dim3(blocks), dim3(X3C_NTH), lds, s, args, nmem);
+}
+
+void launch_xpencil(int dim, int precision, int threads, int chunk_len, const XArgs* args, int nmem, int blocks,
+                    size_t lds, hipStream_t s) {
   if (blocks <= 0) return;
+  if (chunk_len > 0) {
+    (void)threads;
+    if (precision == 0)
+      launch_x3c<double, false>(chunk_len, args, nmem, blocks, lds, s);
+    else
+      launch_x3c<float, true>(chunk_len, args, nmem, blocks, lds, s);
+    return;
+  }
   if (precision == 0 && threads == NT) {
     if (dim == 2)
       hipLaunchKernelGGL((xpencil_kernel<double, 2, false, NT>), dim3(blocks), dim3(NT), lds, s, args, nmem);
@@ -1371,6 +1702,12 @@ hipError_t fft_set_attributes() {
                         (const void*)xpencil_kernel<float, 3, true, NT>,
                         (const void*)xpencil_kernel<float, 2, true, 2 * NT>,
                         (const void*)xpencil_kernel<float, 3, true, 2 * NT>,
+                        (const void*)xpencil3c_kernel<double, false, X3C_NTH, 96>,
+                        (const void*)xpencil3c_kernel<double, false, X3C_NTH, 192>,
+                        (const void*)xpencil3c_kernel<double, false, X3C_NTH, 384>,
+                        (const void*)xpencil3c_kernel<float, true, X3C_NTH, 96>,
+                        (const void*)xpencil3c_kernel<float, true, X3C_NTH, 192>,
+                        (const void*)xpencil3c_kernel<float, true, X3C_NTH, 384>,
                         (const void*)zfft_kernel<double, ZMV>,
                         (const void*)zfft_kernel<float, ZMV>};
   for (const void* k : k160) {
@@ -1381,9 +1718,13 @@ hipError_t fft_set_attributes() {
   return hipFuncSetAttribute((const void*)diag_rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, 128 * 1024);
 }
 
-size_t xpencil_lds_bytes(int dim, int L, int precision) {
+size_t xpencil_lds_bytes(int dim, int L, int precision, bool chunked) {
   // a wave's transform batch must hold one sequence
   if (L > 64 * cover(XMVW)) return ~(size_t)0;
+  if (chunked) {
+    const size_t cp = X3C_NTH / 64;
+    return (lds_span<true>(cp * L) + L) * (precision == 0 ? sizeof(cx<double>) : sizeof(cx<float>));
+  }
   if (precision == 0) return dim == 2 ? xpencil_lds<double, 2>(L) : xpencil_lds<double, 3>(L);
   return dim == 2 ? xpencil_lds<float, 2>(L) : xpencil_lds<float, 3>(L);
 }

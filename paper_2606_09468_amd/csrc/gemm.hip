@@ -264,8 +264,9 @@ int gemm_prepare(GemmJob* jobs, int njobs, int cfg) {
   for (int j = 0; j < njobs; ++j) {
     const int rows = jobs[j].kind != PAR_NONE ? bm / 2 : bm;  // a parity tile: BM/2 rows of E and of O
     // the B-stationary configurations cover every row of a product per tile
+    // (and the paired next product's rows: see GemmJob::pair)
     jobs[j].tiles_m = gemm_cfg_bst(cfg) ? 1 : (jobs[j].m + rows - 1) / rows;
-    const int tn = (jobs[j].n + bn - 1) / bn;
+    const int tn = (gemm_cfg_bst(cfg) && jobs[j].pair == 2) ? 0 : (jobs[j].n + bn - 1) / bn;
     jobs[j].tile0 = t;
     t += jobs[j].tiles_m * tn;
   }
@@ -769,7 +770,7 @@ __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __
   const int col0 = (t - jp->tile0) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
-  const int M = jp->m, N = jp->n, K = jp->k, KF = jp->kf, lda = jp->lda, ldb = jp->ldb;
+  const int N = jp->n, K = jp->k, KF = jp->kf, ldb = jp->ldb;
   const int K16 = (K + 15) & ~15;
   const bool fold = jp->kind != PAR_SPLIT_UNFOLD;
   const bool zm = (jp->flags & GEMM_ZERO_MEAN) != 0;
@@ -810,36 +811,42 @@ __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __
     }
   }
   __syncthreads();
-  const gptr<const T> A = gmem(static_cast<const T*>(jp->A));
-  const gptr<const T> A2 = gmem(static_cast<const T*>(jp->A2));
-  const int nrb = (M + 15) >> 4, nkb = K16 >> 4;
+  const int nkb = K16 >> 4;
   const T* be = Be + (size_t)(4 * lk) * PB + l16;
   const T* bo = Bo + (size_t)(4 * lk) * PB + l16;
-  for (int rb = wave; rb < nrb; rb += 4) {
-    V4 E[1][CB], O[1][CB];
+  // the row sweep of one product over the staged panel: this job's, then
+  // the paired next job's (same panel, its own operator and output)
+  for (const GemmJob* q = jp;; ++q) {
+    const gptr<const T> A = gmem(static_cast<const T*>(q->A));
+    const gptr<const T> A2 = gmem(static_cast<const T*>(q->A2));
+    const int nrb = (q->m + 15) >> 4, qlda = q->lda;
+    for (int rb = wave; rb < nrb; rb += 4) {
+      V4 E[1][CB], O[1][CB];
 #pragma unroll
-    for (int cb = 0; cb < CB; ++cb) E[0][cb] = O[0][cb] = V4{0, 0, 0, 0};
-    // A rows are allocated (zero) up to gemm_rows(m) and lda = K16
-    const gptr<const V4> ae = reinterpret_cast<gptr<const V4>>(A + (size_t)(rb * 16 + l16) * lda + 4 * lk);
-    const gptr<const V4> ao = reinterpret_cast<gptr<const V4>>(A2 + (size_t)(rb * 16 + l16) * lda + 4 * lk);
-    V4 xe = ae[0], xo = ao[0];
-    for (int b = 0; b < nkb; ++b) {
-      const V4 ce = xe, co = xo;
-      if (b + 1 < nkb) {
-        xe = ae[4 * (b + 1)];
-        xo = ao[4 * (b + 1)];
-      }
-      const T* pe = be + (size_t)(16 * b) * PB;
-      const T* po = bo + (size_t)(16 * b) * PB;
-#pragma unroll
-      for (int s2 = 0; s2 < 4; ++s2)
-#pragma unroll
-        for (int cb = 0; cb < CB; ++cb) {
-          E[0][cb] = mfma(ce[s2], pe[s2 * PB + cb * 16], E[0][cb]);
-          O[0][cb] = mfma(co[s2], po[s2 * PB + cb * 16], O[0][cb]);
+      for (int cb = 0; cb < CB; ++cb) E[0][cb] = O[0][cb] = V4{0, 0, 0, 0};
+      // A rows are allocated (zero) up to gemm_rows(m) and lda = K16
+      const gptr<const V4> ae = reinterpret_cast<gptr<const V4>>(A + (size_t)(rb * 16 + l16) * qlda + 4 * lk);
+      const gptr<const V4> ao = reinterpret_cast<gptr<const V4>>(A2 + (size_t)(rb * 16 + l16) * qlda + 4 * lk);
+      V4 xe = ae[0], xo = ao[0];
+      for (int b = 0; b < nkb; ++b) {
+        const V4 ce = xe, co = xo;
+        if (b + 1 < nkb) {
+          xe = ae[4 * (b + 1)];
+          xo = ao[4 * (b + 1)];
         }
+        const T* pe = be + (size_t)(16 * b) * PB;
+        const T* po = bo + (size_t)(16 * b) * PB;
+#pragma unroll
+        for (int s2 = 0; s2 < 4; ++s2)
+#pragma unroll
+          for (int cb = 0; cb < CB; ++cb) {
+            E[0][cb] = mfma(ce[s2], pe[s2 * PB + cb * 16], E[0][cb]);
+            O[0][cb] = mfma(co[s2], po[s2 * PB + cb * 16], O[0][cb]);
+          }
+      }
+      store_par<T, TC, 1, CB>(q, E, O, rb * 16, col0, lk, l16);
     }
-    store_par<T, TC, 1, CB>(jp, E, O, rb * 16, col0, lk, l16);
+    if (q != jp || jp->pair != 1) break;
   }
 }
 

@@ -64,6 +64,12 @@ struct GemmJob {
   int scale, scale2;   // SCALE_*: output row i is eigen coefficient i, scaled per mode
   const EigScale* es;  // per-solve constants for the scaling
   const int* skip;     // the run's blow-up flag (device): nonzero skips the product; null: never
+  // B-stationary configurations: 1 when the next job of the table stages the
+  // same folded panel (same B, kind, k, kf, ldb, n and flags: the values and
+  // d/dy, or D2 and D, of one field), whose product this job's tiles then
+  // also compute from the staged panel; 2 for that next job (no tiles of
+  // its own there); 0 otherwise.  Other configurations ignore it.
+  int pair;
   int tiles_m, tile0;  // filled by gemm_prepare
 };
 constexpr int GEMM_ZERO_MEAN = 1;
@@ -331,8 +337,16 @@ __device__ inline int member_of(const Args* __restrict__ a, int nmem) {
 // launch from its largest member: threads per x-pencil workgroup
 // (xpencil_threads of that LDS size and the launch's line count).
 int xpencil_threads(int precision, size_t lds, int lines);
-void launch_xpencil(int dim, int precision, int threads, const XArgs* args, int nmem, int blocks, size_t lds,
-                    hipStream_t s);
+// 3D lines of the lengths 96, 192 and 384 can take the chunked pencil (the
+// nine values and nine explicit terms of each point in registers, the other
+// fields through LDS a chunk of field pairs at a time; xpencil_chunked says
+// where it is used), with xpencil_chunk_threads() threads per workgroup,
+// when every line of the launch has the same such length (chunk_len; 0: the
+// whole-line pencil).
+bool xpencil_chunked(int dim, int L, int precision);
+int xpencil_chunk_threads();
+void launch_xpencil(int dim, int precision, int threads, int chunk_len, const XArgs* args, int nmem, int blocks,
+                    size_t lds, hipStream_t s);
 void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
 void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
 void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s);
@@ -340,7 +354,7 @@ void launch_rhs(const RhsArgs* args, int nmem, int blocks, hipStream_t s);
 void launch_finalize(const FinArgs* args, int nmem, int blocks, hipStream_t s);
 // workgroups and dynamic LDS of one member's launch
 int xpencil_blocks(const Dims& d);
-size_t xpencil_lds_bytes(int dim, int L, int precision);
+size_t xpencil_lds_bytes(int dim, int L, int precision, bool chunked = false);
 int zfft_blocks(int nkx, int rows, int nfields);
 size_t zfft_lds_bytes(int L, int precision);
 size_t diag_rows_lds_bytes(int L);

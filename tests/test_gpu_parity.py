@@ -526,6 +526,48 @@ def test_mixed_precision_against_fp64_oracle(P, case, precision):
         assert abs(d[k] - e[k]) <= 1e-8 * max(1.0, abs(e[k])), (k, d[k], e[k])
 
 
+XFORM_CASES = [
+    ("3D 64x33x16 x6", Grid(3, 64, 33, 16), dict(wi=50.0, dt=5e-4, eps=1e-3), 6),     # lines of 96
+    ("3D 128x33x8 x6", Grid(3, 128, 33, 8), dict(wi=50.0, dt=5e-4), 6),               # lines of 192
+    ("3D 256x17x4 x4", Grid(3, 256, 17, 4), dict(wi=20.0, dt=1e-3, eps=1e-3), 4),     # lines of 384
+]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", XFORM_CASES, ids=[c[0] for c in XFORM_CASES])
+def test_xpencil_forms_match_oracle(P, case, precision, monkeypatch):
+    """Both forms of the 3D x pencil (the whole line in LDS, and the chunked
+    one that streams the gradients through LDS in field chunks), forced with
+    PCS_XPENCIL_FORM, against the FP64 oracle (the FP64 tolerances, or the
+    mixed bar), and in FP64 against each other (the same products summed in
+    another order) to the same tolerances."""
+    name, g, prm, n = case
+    o = Oracle(g, Params(**prm), seed=3, amp=1e-3)
+    o.step(n)
+    b = o.get_state()
+    N = g.ny - 1
+    got = {}
+    for form in ("whole", "chunked"):
+        monkeypatch.setenv("PCS_XPENCIL_FORM", form)
+        print("case xpencil %s %s p%d" % (form, name, precision), flush=True)
+        sim = P.Sim(P.make_grid(g.dim, g.nx, g.ny, g.nz, g.lx, g.lz), P.make_params(precision=precision, **prm),
+                    seed=3, amp=1e-3)
+        sim.step(n)
+        a = sim.get_state()
+        recs, st = sim.diagnostics()
+        sim.close()
+        assert st == P.PCS_OK and len(recs) == n
+        if precision == 0:
+            check_state(a, b, g, tol_prognostic(N), tol_history(N), name + " " + form)
+        else:
+            errs = fluct_errors(a, b, g)
+            for k in state_layout(g)[1][:11]:
+                assert errs[k][0] <= 2e-4 and errs[k][1] <= 2e-5, (form, k, errs[k])
+        got[form] = a
+    if precision == 0:
+        check_state(got["chunked"], got["whole"], g, tol_prognostic(N), tol_history(N), name + " forms")
+
+
 @pytest.mark.parametrize("precision", [1, 2, 3, 4])
 def test_mixed_keeps_laminar_state_exact(P, precision):
     """With no fluctuation the FP32 part contributes nothing: the laminar state
