@@ -818,17 +818,19 @@ void build_jobs(Member* m) {
                        f32ops2 ? (const void*)m->PNM32p[1] : m->PNMp[1]};
   const void* DPp[2] = {f32ops2 ? (const void*)m->DP32p[0] : m->DPp[0], f32ops2 ? (const void*)m->DP32p[1] : m->DPp[1]};
   const char* Yo = mixed ? (const char*)m->Yout32 : (const char*)m->Yout;
+  // P N of every explicit term, with D P N_x (and D P N_z) beside the P N
+  // of the same term (one staged panel, mark_pairs)
   for (int f = 0; f < m->nout; ++f) {
     m->G2.addp(PAR_FOLD_UNFOLD, P, Pp[0], Pp[1], Yo + (size_t)f * fsm * ysz, cw, m->S + f * fs, cw, nh, cw, mh, n1, m1,
                +1);
     tails(m->G2, m->PNM32lp);
+    if (f == 0 || (f == 2 && d.dim == 3)) {
+      m->G2.addp(PAR_FOLD_UNFOLD, DP, DPp[0], DPp[1], Yo + (size_t)f * fsm * ysz, cw, m->DN + (f / 2) * fs, cw, nh, cw,
+                 mh, n1, m1, -1);
+      tails(m->G2, m->DP32lp);
+    }
   }
-  m->G2.addp(PAR_FOLD_UNFOLD, DP, DPp[0], DPp[1], Yo, cw, m->DN, cw, nh, cw, mh, n1, m1, -1);
-  tails(m->G2, m->DP32lp);
-  if (d.dim == 3) {
-    m->G2.addp(PAR_FOLD_UNFOLD, DP, DPp[0], DPp[1], Yo + 2 * fsm * ysz, cw, m->DN + fs, cw, nh, cw, mh, n1, m1, -1);
-    tails(m->G2, m->DP32lp);
-  }
+  m->G2.mark_pairs();
   if (mixed) {
     // the mean column again, in FP64, from the FP64-completed padded-grid means
     m->Gm.type = GEMM_DDD;
@@ -1147,7 +1149,9 @@ void build_batch(Batch* b) {
     b->lx = std::max(b->lx, xpencil_lds_bytes(d.dim, d.px, m->prec, b->xchunk > 0));
     b->hx.push_back(x);
     if (d.dim == 3) {
-      const int ngx = (d.nkx + ZFFT_GROUP - 1) / ZFFT_GROUP;
+      // the state transforms run in the member's precision, the diagnostics' in FP64
+      const int ngx = (d.nkx + zfft_group(m->prec) - 1) / zfft_group(m->prec);
+      const int ngd = (d.nkx + zfft_group(0) - 1) / zfft_group(0);
       ZArgs zi{};
       zi.in = yin;
       zi.out = zin;
@@ -1164,7 +1168,7 @@ void build_batch(Batch* b) {
       zi.tw = twz;
       zi.skip = skip;
       zi.blk0 = b->bzi;
-      b->bzi += zfft_blocks(d.nkx, m1, m->nzin);
+      b->bzi += zfft_blocks(d.nkx, m1, m->nzin, m->prec);
       b->lzi = std::max(b->lzi, zfft_lds_bytes(d.pz, m->prec));
       b->hzi.push_back(zi);
       ZArgs zf = zi;
@@ -1178,7 +1182,7 @@ void build_batch(Batch* b) {
       zf.mcol = m->mcol;
       zf.eps_wi = m->p.eps / m->p.wi;
       zf.blk0 = b->bzf;
-      b->bzf += zfft_blocks(d.nkx, m1, m->nout);
+      b->bzf += zfft_blocks(d.nkx, m1, m->nout, m->prec);
       b->lzf = std::max(b->lzf, zfft_lds_bytes(d.pz, m->prec));
       b->hzf.push_back(zf);
       ZArgs zd{};
@@ -1188,13 +1192,13 @@ void build_batch(Batch* b) {
       zd.nzs = d.nzs;
       zd.rows = n1;
       zd.nfields = 4;
-      zd.ngx = ngx;
+      zd.ngx = ngd;
       zd.inverse = 1;
       zd.pl = m->pbz;
       zd.tw = m->twbz;
       zd.skip = skip;
       zd.blk0 = b->bzd;
-      b->bzd += zfft_blocks(d.nkx, n1, 4);
+      b->bzd += zfft_blocks(d.nkx, n1, 4, 0);
       b->lzd = std::max(b->lzd, zfft_lds_bytes(d.nz, 0));
       b->hzd.push_back(zd);
       // d/dz of u and w on the midplane row (the velocity-gradient PDFs): the
@@ -1208,7 +1212,7 @@ void build_batch(Batch* b) {
       zg.deriv = m->zgder;
       zg.kz = m->kz;
       zg.blk0 = b->bzd;
-      b->bzd += zfft_blocks(d.nkx, 1, 2);
+      b->bzd += zfft_blocks(d.nkx, 1, 2, 0);
       b->hzd.push_back(zg);
     }
     DRowArgs r{};

@@ -654,9 +654,11 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
     for (int r = 0; r < TWN; ++r)
       if (tid + r * NTH < L) twl[tid + r * NTH] = cx<T>{tv[r][0], tv[r][1]};
     // a wave clears, fills and transforms the pairs it owns, in LDS order,
-    // so only the twiddles need a workgroup barrier before the transforms
+    // so only the twiddles need a workgroup barrier before the transforms;
+    // the packing writes every position but the band between the retained
+    // modes, which alone is cleared
     for (int q = wave; q < nb; q += NW)
-      for (int e = lane; e < L; e += 64) X[q * L + e] = cx<T>{0, 0};
+      for (int e = nkx + lane; e <= L - nkx; e += 64) X[q * L + e] = cx<T>{0, 0};
     pass_sync<true>();
     for (int i0 = 0; i0 < items; i0 += G) {
       if (i0 > 0) load_items(i0);
@@ -1049,7 +1051,13 @@ __global__ __launch_bounds__(NTH) void xpencil3c_kernel(const XArgs* __restrict_
 // inverse: kz slots (Nyquist slot skipped, optional i kz factor) are placed at
 // their own frequency in a length-Lz transform; forward: length-Lz data is
 // transformed, divided by Lz and truncated to the retained slots.
-constexpr int ZG = ZFFT_GROUP;
+// kx columns per workgroup: 32 in FP32, 16 in FP64 (the FP64 columns of
+// 32 x 193 took 99 KB of LDS, one workgroup per CU: 3.74 ms for the inverse
+// transforms of 256 x 257 x 128)
+template <typename T>
+__host__ __device__ constexpr int zgroup() {
+  return sizeof(T) == 8 ? 16 : 32;
+}
 // Complex values per thread of the z columns: 24 (one register batch holds
 // all 32 columns up to length 192; measured faster than 16 in both precisions,
 // the compiler also allocating fewer registers for it).
@@ -1058,6 +1066,7 @@ constexpr int ZMV = 24;
 // LC: the column length when it has a compiled plan, else 0.
 template <typename T, int MV, int LC>
 __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA) {
+  constexpr int ZG = zgroup<T>();
   typedef cx<T> c2;
   const gptr<const T> in = gmem(static_cast<const T*>(ZA.in));
   const gptr<T> out = gmem(static_cast<T*>(ZA.out));
@@ -1099,8 +1108,16 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
   // loads are in flight at once
   constexpr int PER = 8;
   if (inverse) {
-    for (int e = tid; e < ZG * SL; e += NT) AV[e] = c2{0, 0};
-    __syncthreads();
+    // zero the band between the retained slots (the Nyquist slot's position
+    // included); the scatter below writes every other position of a column,
+    // at addresses disjoint from the band
+    {
+      const int h = nzs / 2, nb = L - nzs + 1;
+      for (int e = tid; e < ng * nb; e += NT) {
+        const int g = e / nb;
+        AV[g * SL + h + (e - g * nb)] = c2{0, 0};
+      }
+    }
     const int tot = nzs * ng;
     for (int e0 = 0; e0 < tot; e0 += PER * NT) {
       c2 v[PER];
@@ -1672,11 +1689,16 @@ void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t 
     hipLaunchKernelGGL((zfft_kernel<float, ZMV>), dim3(blocks), dim3(NT), lds, s, args, nmem);
 }
 
-int zfft_blocks(int nkx, int rows, int nfields) { return ((nkx + ZG - 1) / ZG) * rows * nfields; }
+int zfft_group(int precision) { return precision == 0 ? zgroup<double>() : zgroup<float>(); }
+
+int zfft_blocks(int nkx, int rows, int nfields, int precision) {
+  const int g = zfft_group(precision);
+  return ((nkx + g - 1) / g) * rows * nfields;
+}
 
 size_t zfft_lds_bytes(int L, int precision) {
-  return precision == 0 ? (lds_padded<double>((size_t)ZG * (L + 1)) + L) * sizeof(cx<double>)
-                        : (lds_padded<float>((size_t)ZG * (L + 1)) + L) * sizeof(cx<float>);
+  return precision == 0 ? (lds_padded<double>((size_t)zgroup<double>() * (L + 1)) + L) * sizeof(cx<double>)
+                        : (lds_padded<float>((size_t)zgroup<float>() * (L + 1)) + L) * sizeof(cx<float>);
 }
 
 void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {

@@ -355,11 +355,13 @@ void launch_finalize(const FinArgs* args, int nmem, int blocks, hipStream_t s);
 // workgroups and dynamic LDS of one member's launch
 int xpencil_blocks(const Dims& d);
 size_t xpencil_lds_bytes(int dim, int L, int precision, bool chunked = false);
-int zfft_blocks(int nkx, int rows, int nfields);
+// kx columns per workgroup of the z transforms of a precision (0: FP64),
+// and the workgroups of one member's launch
+int zfft_group(int precision);
+int zfft_blocks(int nkx, int rows, int nfields, int precision);
 size_t zfft_lds_bytes(int L, int precision);
 size_t diag_rows_lds_bytes(int L);
 constexpr int ELEM_THREADS = 64;
-constexpr int ZFFT_GROUP = 32;  // kx columns per workgroup of the z transforms
 // Raises the dynamic-LDS limit of the transform kernels (call once, outside capture).
 hipError_t fft_set_attributes();
 
