@@ -348,6 +348,7 @@ struct Batch {
   int bx = 0, bzi = 0, bzf = 0, bzd = 0, bdr = 0, brhs = 0, bfin = 0;
   size_t lx = 0, lzi = 0, lzf = 0, lzd = 0, ldr = 0;
   int xnt = 0;          // threads per x-pencil workgroup
+  int zgi = 32, zgd = 32;  // kx columns per workgroup of the state's and the diagnostics' z transforms
   int xchunk = 0;       // 3D lines in field chunks: their common length (xpencil_chunked), else 0
   // one step, and GRAPH_STEPS steps back to back (fewer launches between steps)
   hipGraph_t graph = nullptr, graphn = nullptr;
@@ -538,7 +539,8 @@ pcs_status setup_dims(Member* m, const pcs_grid* g, const pcs_params* p) {
   const size_t lds_max = 160 * 1024;
   if (xpencil_lds_bytes(d.dim, d.px, m->prec) > lds_max) return PCS_ERR_UNSUPPORTED;
   if (diag_rows_lds_bytes(d.nx) > 128 * 1024) return PCS_ERR_UNSUPPORTED;
-  if (d.dim == 3 && (zfft_lds_bytes(d.pz, m->prec) > lds_max || zfft_lds_bytes(d.nz, 0) > lds_max))
+  if (d.dim == 3 && (zfft_lds_bytes(d.pz, m->prec, zfft_group(d.pz, m->prec)) > lds_max ||
+                     zfft_lds_bytes(d.nz, 0, zfft_group(d.nz, 0)) > lds_max))
     return PCS_ERR_UNSUPPORTED;
   Phys& q = m->p;
   q.re = p->re;
@@ -1116,6 +1118,13 @@ void build_batch(Batch* b) {
   b->hfin.clear();
   b->bx = b->bzi = b->bzf = b->bzd = b->bdr = b->brhs = b->bfin = 0;
   b->lx = b->lzi = b->lzf = b->lzd = b->ldr = 0;
+  // one column group per z-transform launch: the smallest any member's length asks for
+  b->zgi = b->zgd = 32;
+  for (Member* m : mem)
+    if (m->d.dim == 3) {
+      b->zgi = std::min(b->zgi, zfft_group(m->d.pz, m->prec));
+      b->zgd = std::min(b->zgd, zfft_group(m->d.nz, 0));
+    }
   b->xchunk = mem[0]->d.px;
   for (Member* m : mem)
     if (!xpencil_chunked(m->d.dim, m->d.px, m->prec) || m->d.px != mem[0]->d.px) b->xchunk = 0;
@@ -1150,8 +1159,8 @@ void build_batch(Batch* b) {
     b->hx.push_back(x);
     if (d.dim == 3) {
       // the state transforms run in the member's precision, the diagnostics' in FP64
-      const int ngx = (d.nkx + zfft_group(m->prec) - 1) / zfft_group(m->prec);
-      const int ngd = (d.nkx + zfft_group(0) - 1) / zfft_group(0);
+      const int ngx = (d.nkx + b->zgi - 1) / b->zgi;
+      const int ngd = (d.nkx + b->zgd - 1) / b->zgd;
       ZArgs zi{};
       zi.in = yin;
       zi.out = zin;
@@ -1168,8 +1177,8 @@ void build_batch(Batch* b) {
       zi.tw = twz;
       zi.skip = skip;
       zi.blk0 = b->bzi;
-      b->bzi += zfft_blocks(d.nkx, m1, m->nzin, m->prec);
-      b->lzi = std::max(b->lzi, zfft_lds_bytes(d.pz, m->prec));
+      b->bzi += zfft_blocks(d.nkx, m1, m->nzin, b->zgi);
+      b->lzi = std::max(b->lzi, zfft_lds_bytes(d.pz, m->prec, b->zgi));
       b->hzi.push_back(zi);
       ZArgs zf = zi;
       zf.in = zout;
@@ -1182,8 +1191,8 @@ void build_batch(Batch* b) {
       zf.mcol = m->mcol;
       zf.eps_wi = m->p.eps / m->p.wi;
       zf.blk0 = b->bzf;
-      b->bzf += zfft_blocks(d.nkx, m1, m->nout, m->prec);
-      b->lzf = std::max(b->lzf, zfft_lds_bytes(d.pz, m->prec));
+      b->bzf += zfft_blocks(d.nkx, m1, m->nout, b->zgi);
+      b->lzf = std::max(b->lzf, zfft_lds_bytes(d.pz, m->prec, b->zgi));
       b->hzf.push_back(zf);
       ZArgs zd{};
       zd.in = m->prep;
@@ -1198,8 +1207,8 @@ void build_batch(Batch* b) {
       zd.tw = m->twbz;
       zd.skip = skip;
       zd.blk0 = b->bzd;
-      b->bzd += zfft_blocks(d.nkx, n1, 4, 0);
-      b->lzd = std::max(b->lzd, zfft_lds_bytes(d.nz, 0));
+      b->bzd += zfft_blocks(d.nkx, n1, 4, b->zgd);
+      b->lzd = std::max(b->lzd, zfft_lds_bytes(d.nz, 0, b->zgd));
       b->hzd.push_back(zd);
       // d/dz of u and w on the midplane row (the velocity-gradient PDFs): the
       // same launch, one row, fields picked by whole-field offsets from that row
@@ -1212,7 +1221,7 @@ void build_batch(Batch* b) {
       zg.deriv = m->zgder;
       zg.kz = m->kz;
       zg.blk0 = b->bzd;
-      b->bzd += zfft_blocks(d.nkx, 1, 2, 0);
+      b->bzd += zfft_blocks(d.nkx, 1, 2, b->zgd);
       b->hzd.push_back(zg);
     }
     DRowArgs r{};
@@ -1364,11 +1373,11 @@ void explicit_stage(Batch* b, const Mark& mark) {
   for (int r = mark(ST_GEMM_STATE); r > 0; --r) b->GS.run(s);
   for (int r = mark(ST_GEMM_D2); r > 0; --r) b->GSb.run(s);
   for (int r = mark(ST_ZFFT_INV); r > 0; --r)
-    if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
+    if (b->dim == 3) launch_zfft(b->prec, b->zgi, b->dzi, nm, b->bzi, b->lzi, s);
   for (int r = mark(ST_XPENCIL); r > 0; --r)
     launch_xpencil(b->dim, b->prec, b->xnt, b->xchunk, b->dx, nm, b->bx, b->lx, s);
   for (int r = mark(ST_ZFFT_FWD); r > 0; --r)
-    if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
+    if (b->dim == 3) launch_zfft(b->prec, b->zgi, b->dzf, nm, b->bzf, b->lzf, s);
   for (int r = mark(ST_GEMM_PROJ); r > 0; --r) b->GP.run(s);
   for (int r = mark(ST_RHS); r > 0; --r) launch_rhs(b->drhs, nm, b->brhs, s);
 }
@@ -1382,7 +1391,7 @@ void enqueue_step(Batch* b, const Mark& mark) {
   for (int r = mark(ST_GEMM_V); r > 0; --r) b->G5.run(s);
   for (int r = mark(ST_FINALIZE); r > 0; --r) launch_finalize(b->dfin, nm, b->bfin, s);
   for (int r = mark(ST_DIAG_ZFFT); r > 0; --r)
-    if (b->dim == 3) launch_zfft(0, b->dzd, (int)b->hzd.size(), b->bzd, b->lzd, s);
+    if (b->dim == 3) launch_zfft(0, b->zgd, b->dzd, (int)b->hzd.size(), b->bzd, b->lzd, s);
   for (int r = mark(ST_DIAG_ROWS); r > 0; --r) launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, s);
   for (int r = mark(ST_DIAG_FINAL); r > 0; --r) launch_diag_final(b->ddf, nm, s);
   mark(ST_COUNT);
@@ -1391,7 +1400,7 @@ void enqueue_step(Batch* b, const Mark& mark) {
 // The diagnostics of the state that the last finalize wrote, on stream t.
 void enqueue_diagnostics(Batch* b, hipStream_t t) {
   const int nm = (int)b->mem.size();
-  if (b->dim == 3) launch_zfft(0, b->dzd, (int)b->hzd.size(), b->bzd, b->lzd, t);
+  if (b->dim == 3) launch_zfft(0, b->zgd, b->dzd, (int)b->hzd.size(), b->bzd, b->lzd, t);
   launch_diag_rows(b->ddr, nm, b->bdr, b->ldr, t);
   launch_diag_final(b->ddf, nm, t);
 }
@@ -1429,10 +1438,10 @@ void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
     (void)hipEventRecord(ev[3], s2);
   }
   b->GS.run(s);
-  if (b->dim == 3) launch_zfft(b->prec, b->dzi, nm, b->bzi, b->lzi, s);
+  if (b->dim == 3) launch_zfft(b->prec, b->zgi, b->dzi, nm, b->bzi, b->lzi, s);
   if (prod) (void)hipStreamWaitEvent(s, ev[1], 0);
   launch_xpencil(b->dim, b->prec, b->xnt, b->xchunk, b->dx, nm, b->bx, b->lx, s);
-  if (b->dim == 3) launch_zfft(b->prec, b->dzf, nm, b->bzf, b->lzf, s);
+  if (b->dim == 3) launch_zfft(b->prec, b->zgi, b->dzf, nm, b->bzf, b->lzf, s);
   b->GP.run(s);
   if (prod) (void)hipStreamWaitEvent(s, ev[2], 0);
   if (diag_prev && ring) (void)hipStreamWaitEvent(s, ev[3], 0);

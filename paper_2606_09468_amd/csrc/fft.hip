@@ -1051,22 +1051,22 @@ __global__ __launch_bounds__(NTH) void xpencil3c_kernel(const XArgs* __restrict_
 // inverse: kz slots (Nyquist slot skipped, optional i kz factor) are placed at
 // their own frequency in a length-Lz transform; forward: length-Lz data is
 // transformed, divided by Lz and truncated to the retained slots.
-// kx columns per workgroup: 32 in FP32, 16 in FP64 (the FP64 columns of
-// 32 x 193 took 99 KB of LDS, one workgroup per CU: 3.74 ms for the inverse
-// transforms of 256 x 257 x 128)
-template <typename T>
-__host__ __device__ constexpr int zgroup() {
-  return sizeof(T) == 8 ? 16 : 32;
-}
+// kx columns per workgroup: G of 32, 16 or 8, the largest whose columns fit
+// ZLDS_TARGET bytes of LDS (zfft_group), so that several workgroups share a
+// CU.  Measured (inverse transforms, ms per launch): 256 x 257 x 128 FP32
+// 1.22 with 32 columns of 192 (49 KB) against 0.84 with 16, FP64 2.42 with 16
+// (52 KB) against 2.03 with 8; 128 x 129 x 64 FP32 0.100 with 32 columns of
+// 96 (25 KB) against 0.105 with 16, FP64 0.251 with 16 against 0.309 with 8.
+constexpr size_t ZLDS_TARGET = 40 * 1024;
 // Complex values per thread of the z columns: 24 (one register batch holds
 // all 32 columns up to length 192; measured faster than 16 in both precisions,
 // the compiler also allocating fewer registers for it).
 constexpr int ZMV = 24;
 
-// LC: the column length when it has a compiled plan, else 0.
-template <typename T, int MV, int LC>
+// LC: the column length when it has a compiled plan, else 0; ZG: columns
+// per workgroup.
+template <typename T, int MV, int LC, int ZG>
 __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA) {
-  constexpr int ZG = zgroup<T>();
   typedef cx<T> c2;
   const gptr<const T> in = gmem(static_cast<const T*>(ZA.in));
   const gptr<T> out = gmem(static_cast<T*>(ZA.out));
@@ -1200,16 +1200,16 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
   }
 }
 
-template <typename T, int MV>
+template <typename T, int MV, int ZG>
 __global__ __launch_bounds__(NT) void zfft_kernel(const ZArgs* __restrict__ args, int nmem) {
   const ZArgs& ZA = args[member_of(args, nmem)];
   if (masked(ZA.skip)) return;
   switch (ZA.pl.L) {
-    case 64: zfft_body<T, MV, 64>(ZA); break;  // the diagnostics' base-grid z transforms
-    case 96: zfft_body<T, MV, 96>(ZA); break;
-    case 128: zfft_body<T, MV, 128>(ZA); break;
-    case 192: zfft_body<T, MV, 192>(ZA); break;
-    default: zfft_body<T, MV, 0>(ZA); break;
+    case 64: zfft_body<T, MV, 64, ZG>(ZA); break;  // the diagnostics' base-grid z transforms
+    case 96: zfft_body<T, MV, 96, ZG>(ZA); break;
+    case 128: zfft_body<T, MV, 128, ZG>(ZA); break;
+    case 192: zfft_body<T, MV, 192, ZG>(ZA); break;
+    default: zfft_body<T, MV, 0, ZG>(ZA); break;
   }
 }
 
@@ -1681,24 +1681,35 @@ void launch_xpencil(int dim, int precision, int threads, int chunk_len, const XA
 
 int xpencil_blocks(const Dims& d) { return (d.M + 1) * d.pz; }
 
-void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
+template <typename T>
+void launch_zfft_t(int group, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
+  if (group == 32)
+    hipLaunchKernelGGL((zfft_kernel<T, ZMV, 32>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+  else if (group == 16)
+    hipLaunchKernelGGL((zfft_kernel<T, ZMV, 16>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+  else
+    hipLaunchKernelGGL((zfft_kernel<T, ZMV, 8>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+}
+
+void launch_zfft(int precision, int group, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
   if (blocks <= 0) return;
   if (precision == 0)
-    hipLaunchKernelGGL((zfft_kernel<double, ZMV>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+    launch_zfft_t<double>(group, args, nmem, blocks, lds, s);
   else
-    hipLaunchKernelGGL((zfft_kernel<float, ZMV>), dim3(blocks), dim3(NT), lds, s, args, nmem);
+    launch_zfft_t<float>(group, args, nmem, blocks, lds, s);
 }
 
-int zfft_group(int precision) { return precision == 0 ? zgroup<double>() : zgroup<float>(); }
-
-int zfft_blocks(int nkx, int rows, int nfields, int precision) {
-  const int g = zfft_group(precision);
-  return ((nkx + g - 1) / g) * rows * nfields;
+int zfft_group(int L, int precision) {
+  for (int g : {32, 16})
+    if (zfft_lds_bytes(L, precision, g) <= ZLDS_TARGET) return g;
+  return 8;
 }
 
-size_t zfft_lds_bytes(int L, int precision) {
-  return precision == 0 ? (lds_padded<double>((size_t)zgroup<double>() * (L + 1)) + L) * sizeof(cx<double>)
-                        : (lds_padded<float>((size_t)zgroup<float>() * (L + 1)) + L) * sizeof(cx<float>);
+int zfft_blocks(int nkx, int rows, int nfields, int group) { return ((nkx + group - 1) / group) * rows * nfields; }
+
+size_t zfft_lds_bytes(int L, int precision, int group) {
+  return precision == 0 ? (lds_padded<double>((size_t)group * (L + 1)) + L) * sizeof(cx<double>)
+                        : (lds_padded<float>((size_t)group * (L + 1)) + L) * sizeof(cx<float>);
 }
 
 void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s) {
@@ -1730,8 +1741,12 @@ hipError_t fft_set_attributes() {
                         (const void*)xpencil3c_kernel<float, true, X3C_NTH, 96>,
                         (const void*)xpencil3c_kernel<float, true, X3C_NTH, 192>,
                         (const void*)xpencil3c_kernel<float, true, X3C_NTH, 384>,
-                        (const void*)zfft_kernel<double, ZMV>,
-                        (const void*)zfft_kernel<float, ZMV>};
+                        (const void*)zfft_kernel<double, ZMV, 32>,
+                        (const void*)zfft_kernel<double, ZMV, 16>,
+                        (const void*)zfft_kernel<double, ZMV, 8>,
+                        (const void*)zfft_kernel<float, ZMV, 32>,
+                        (const void*)zfft_kernel<float, ZMV, 16>,
+                        (const void*)zfft_kernel<float, ZMV, 8>};
   for (const void* k : k160) {
     hipError_t e = hipFuncSetAttribute(k, hipFuncAttributeMaxDynamicSharedMemorySize, lim);
     if (e != hipSuccess) return e;

@@ -347,7 +347,8 @@ bool xpencil_chunked(int dim, int L, int precision);
 int xpencil_chunk_threads();
 void launch_xpencil(int dim, int precision, int threads, int chunk_len, const XArgs* args, int nmem, int blocks,
                     size_t lds, hipStream_t s);
-void launch_zfft(int precision, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
+// group: kx columns per workgroup (zfft_group), the same for every member of the launch
+void launch_zfft(int precision, int group, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
 void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
 void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s);
 void launch_rhs(const RhsArgs* args, int nmem, int blocks, hipStream_t s);
@@ -355,11 +356,11 @@ void launch_finalize(const FinArgs* args, int nmem, int blocks, hipStream_t s);
 // workgroups and dynamic LDS of one member's launch
 int xpencil_blocks(const Dims& d);
 size_t xpencil_lds_bytes(int dim, int L, int precision, bool chunked = false);
-// kx columns per workgroup of the z transforms of a precision (0: FP64),
-// and the workgroups of one member's launch
-int zfft_group(int precision);
-int zfft_blocks(int nkx, int rows, int nfields, int precision);
-size_t zfft_lds_bytes(int L, int precision);
+// kx columns per workgroup of z transforms of length L in a precision (0:
+// FP64), the workgroups of one member's launch and their LDS
+int zfft_group(int L, int precision);
+int zfft_blocks(int nkx, int rows, int nfields, int group);
+size_t zfft_lds_bytes(int L, int precision, int group);
 size_t diag_rows_lds_bytes(int L);
 constexpr int ELEM_THREADS = 64;
 // Raises the dynamic-LDS limit of the transform kernels (call once, outside capture).

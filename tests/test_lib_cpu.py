@@ -41,15 +41,15 @@ def test_workspace_bytes_and_validation(L):
     assert 1e9 < n3 < 40e9      # resident on one 288 GB device
     sz = ctypes.c_size_t(0)
     bad = [P.make_grid(2, 30, 33), P.make_grid(2, 16, 32), P.make_grid(2, 16, 7), P.make_grid(3, 16, 17, 10),
-           P.make_grid(3, 16, 17, 384)]
-    # 3*30/2 = 45 (radix 5), even Ny, Ny < 9, 3*10/2 = 15, FP64 z columns of 576 beyond one workgroup's LDS
-    # (16 columns: 166 KB)
+           P.make_grid(3, 16, 17, 1024)]
+    # 3*30/2 = 45 (radix 5), even Ny, Ny < 9, 3*10/2 = 15, FP64 z columns of 1536 beyond one workgroup's LDS
+    # (even 8 columns: 209 KB)
     for gb in bad:
         st = L.pcs_workspace_bytes(ctypes.byref(gb), ctypes.byref(p), ctypes.byref(sz))
         assert st == P.PCS_ERR_UNSUPPORTED, (gb.nx, gb.ny, gb.nz)
-    # the same z size fits in FP32 (mixed precision: 32 columns, 152 KB), and FP64 columns of 384 fit
-    assert P.pcs_workspace_bytes(P.make_grid(3, 16, 17, 384), P.make_params(precision=1)) > 0
-    assert P.pcs_workspace_bytes(P.make_grid(3, 16, 17, 256), p) > 0
+    # the same z size fits in FP32 (mixed precision: 8 columns, 98 KB), and FP64 columns of 576 fit
+    assert P.pcs_workspace_bytes(P.make_grid(3, 16, 17, 1024), P.make_params(precision=1)) > 0
+    assert P.pcs_workspace_bytes(P.make_grid(3, 16, 17, 384), p) > 0
     pb = P.make_params(wi=-1.0)
     assert L.pcs_workspace_bytes(ctypes.byref(g), ctypes.byref(pb), ctypes.byref(sz)) == P.PCS_ERR_ARG
     assert L.pcs_workspace_bytes(None, ctypes.byref(p), ctypes.byref(sz)) == P.PCS_ERR_ARG
