@@ -139,8 +139,8 @@ template <>
 struct LCfg<13> {
   static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 1, PKC = 32;
 };
-constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 32, 32, 64, 64, 0, 0};
-constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 32, 32, 64, 64, 32, 64};
+constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 32, 32, 64, 64, 0, 0, 0};
+constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 32, 32, 64, 64, 32, 64, 16};
 // LDS (in elements of the compute precision) of an LDS-tiled configuration:
 // the plain panels, the parity panels (A: BM rows of PKC, B: both halves,
 // rows of BN + 4) and the larger of the two.  The kernel takes its LDS
@@ -1078,6 +1078,10 @@ void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, bo
       if (parity)
         hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 64>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
       break;
+    case 16:
+      if (parity)
+        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 16>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
+      break;
     default: break;
   }
 #undef PCS_GEMM_REG
@@ -1087,7 +1091,7 @@ void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, bo
 }  // namespace
 
 bool gemm_cfg_parity(int cfg) { return cfg >= 4 && cfg < GEMM_NCFG; }
-bool gemm_cfg_bst(int cfg) { return cfg == 14 || cfg == 15; }
+bool gemm_cfg_bst(int cfg) { return cfg >= 14 && cfg < GEMM_NCFG; }
 bool gemm_type_comp(GemmType t) { return t == GEMM_CDF || t == GEMM_CFD; }
 
 namespace {
@@ -1107,7 +1111,7 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
     if (gemm_type_comp(t) && jobs[j].type != GEMM_DDD) {
       // head and tail panels of both halves, B-stationary only
       if (!gemm_cfg_bst(cfg) || jobs[j].kind == PAR_NONE) return ~(size_t)0 >> 1;
-      const size_t pitch = cfg == 14 ? bst_pitch<32>() : bst_pitch<64>();
+      const size_t pitch = CFG_BN[cfg] + 4;  // bst_pitch
       const size_t x = 4 * (size_t)((jobs[j].k + 15) & ~15) * pitch * 4 + 16;
       b = x > b ? x : b;
       continue;
@@ -1128,9 +1132,10 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
       case 12: x = lds_form<12>(par, es, half); break;
       case 13: x = lds_form<13>(par, es, half); break;
       case 14:
-      case 15: {
+      case 15:
+      case 16: {
         // the whole K range of the folded panel: two halves of K16 rows
-        const size_t pitch = cfg == 14 ? bst_pitch<32>() : bst_pitch<64>();
+        const size_t pitch = CFG_BN[cfg] + 4;  // bst_pitch
         x = par ? 2 * (size_t)((jobs[j].k + 15) & ~15) * pitch * es + 16 : ~(size_t)0 >> 1;
         break;
       }
@@ -1150,7 +1155,11 @@ hipError_t gemm_set_attributes() {
       (const void*)gemm_bst_kernel<double, double, float, 32>,  (const void*)gemm_bst_kernel<double, double, float, 64>,
       (const void*)gemm_bst_kernel<double, float, double, 32>,  (const void*)gemm_bst_kernel<double, float, double, 64>,
       (const void*)gemm_bst_comp_kernel<double, float, 32>,     (const void*)gemm_bst_comp_kernel<double, float, 64>,
-      (const void*)gemm_bst_comp_kernel<float, double, 32>,     (const void*)gemm_bst_comp_kernel<float, double, 64>};
+      (const void*)gemm_bst_comp_kernel<float, double, 32>,     (const void*)gemm_bst_comp_kernel<float, double, 64>,
+      (const void*)gemm_bst_kernel<double, double, double, 16>, (const void*)gemm_bst_kernel<float, double, float, 16>,
+      (const void*)gemm_bst_kernel<float, float, double, 16>,   (const void*)gemm_bst_kernel<double, double, float, 16>,
+      (const void*)gemm_bst_kernel<double, float, double, 16>,  (const void*)gemm_bst_comp_kernel<double, float, 16>,
+      (const void*)gemm_bst_comp_kernel<float, double, 16>};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LDS_MAX);
     if (e != hipSuccess) return e;
@@ -1164,20 +1173,26 @@ void gemm_run(GemmType t, const GemmJob* dev_jobs, const int* tmap, int total_ti
   if (gemm_type_comp(t)) {
     // compensated tables: parity products, B-stationary configurations only
     if (!parity || !gemm_cfg_bst(cfg)) return;
-    const bool wide = cfg == 15;
+    const int bn = CFG_BN[cfg];
     if (t == GEMM_CDF) {
-      if (wide)
+      if (bn == 64)
         hipLaunchKernelGGL((gemm_bst_comp_kernel<double, float, 64>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
                            tmap, total_tiles);
-      else
+      else if (bn == 32)
         hipLaunchKernelGGL((gemm_bst_comp_kernel<double, float, 32>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
                            tmap, total_tiles);
+      else
+        hipLaunchKernelGGL((gemm_bst_comp_kernel<double, float, 16>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
+                           tmap, total_tiles);
     } else {
-      if (wide)
+      if (bn == 64)
         hipLaunchKernelGGL((gemm_bst_comp_kernel<float, double, 64>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
                            tmap, total_tiles);
-      else
+      else if (bn == 32)
         hipLaunchKernelGGL((gemm_bst_comp_kernel<float, double, 32>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
+                           tmap, total_tiles);
+      else
+        hipLaunchKernelGGL((gemm_bst_comp_kernel<float, double, 16>), dim3(total_tiles), dim3(256), lds, s, dev_jobs,
                            tmap, total_tiles);
     }
     return;
