@@ -119,6 +119,19 @@ def stage_work(w, precision, split, yvar=None):
     return out
 
 
+def ensemble_work(ws, precision, split, yvar=None):
+    """stage_work summed over the members of an ensemble (every stage is one
+    launch over all of them): bytes and flops add; the peak of a product
+    stage is that of its whole flop mix (total flops over the summed time
+    each member's flops would take at its own mix's peak)."""
+    out = {}
+    for w in ws:
+        for k, (bound, amount, peak) in stage_work(w, precision, split, yvar).items():
+            b, a, t = out.get(k, (bound, 0.0, 0.0))
+            out[k] = (bound, a + amount, t + amount / peak)
+    return {k: (b, a, a / t if t > 0 else 0.0) for k, (b, a, t) in out.items()}
+
+
 def roofline_table(stages, work):
     """Per-kernel roofline from the measured per-launch durations."""
     table = {}
@@ -458,7 +471,13 @@ def bench_ensemble(args, P):
     for r in range(len(members)):
         recs, st = ens.diagnostics(r)
         assert st == P.PCS_OK and recs[-1]["step"] == args.warmup + args.steps and recs[-1]["blowup"] == 0
+    # per-stage durations (eager launches over all members, HIP events on the ensemble's stream)
+    stages = ens.stage_times(args.stage_steps, reps=args.stage_reps)
+    ych = ens.y_choice()
     ens.close()
+    split = stages.get("gemm_d2", 0.0) > 0.0
+    work = ensemble_work([dict(dim=2, nx=nx, ny=ny, nz=1) for ny, nx, _, _ in members], prec, split, ych["variant"])
+    table = roofline_table(stages, work)
     sps = args.steps / (ms / 1e3)
     points = sum(nx * ny for ny, nx, _, _ in members)
     line = {
@@ -471,7 +490,13 @@ def bench_ensemble(args, P):
                    "parallelism": "single GPU, one graph launch per ensemble step"},
         "grid_point_updates_per_s": sps * points,
         "roofline": None,
+        "stage_ms": stages,
+        "stage_roofline": {k: {"frac": round(v["frac"], 4), "achieved": round(v["achieved"], 2),
+                               "unit": v["unit"], "avg_ms": round(v["avg_ms"], 5)} for k, v in table.items()},
     }
+    if table:
+        dom = max(table, key=lambda k: table[k]["avg_ms"])
+        line["roofline"] = dict(kernel=dom, **table[dom], traffic=None)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = ensemble_cpu_baseline(members, ENSEMBLE["dt"], scheme=args.scheme_id)
     print(json.dumps(line), flush=True)

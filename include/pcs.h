@@ -214,14 +214,15 @@ pcs_status pcs_set_state(struct pcs_sim* sim, const double* host, size_t n);
  * products), the z and x transforms, the RHS, finalize and diagnostics
  * kernels.  Where one launch holds all products of the state (steps of less
  * than about a million padded-grid points), gemm_state times it and
- * gemm_mean and gemm_d2 report empty intervals.  Each stage except the row diagnostics (which also add the
+ * gemm_mean and gemm_d2 report 0.  Each stage except the row diagnostics (which also add the
  * step's midplane samples to the histograms) and the step record is launched
  * reps times back to back between its two events (these stages recompute the
  * same outputs from unchanged inputs), so that with reps > 1 the GPU does
  * not wait for the host between launches and ms[i] approaches the kernel's
  * own duration.  nstage must be at least PCS_NSTAGE; stages that do not
- * apply (the z transforms in 2D) report their empty interval.  Stage names
- * come from pcs_stage_name.  Synchronises the stream. */
+ * apply (the z transforms in 2D) report 0, as do entries beyond
+ * PCS_NSTAGE.  Stage names come from pcs_stage_name.  Synchronises the
+ * stream. */
 #define PCS_NSTAGE 14
 pcs_status pcs_stage_times(struct pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage);
 const char* pcs_stage_name(int32_t i);
@@ -371,6 +372,9 @@ pcs_status pcs_ensemble_midplane_pdf(struct pcs_ens* ens, int32_t run, int32_t q
 /* Running moments of run `run`, as pcs_midplane_moments. */
 pcs_status pcs_ensemble_midplane_moments(struct pcs_ens* ens, int32_t run, int32_t quantity, double* out);
 pcs_status pcs_ensemble_y_choice(struct pcs_ens* ens, pcs_ychoice* out);
+/* pcs_stage_times for the whole ensemble (every stage is one launch over all
+ * runs); runs masked after a blow-up cost nothing in it. */
+pcs_status pcs_ensemble_stage_times(struct pcs_ens* ens, int32_t nsteps, int32_t reps, double* ms, int32_t nstage);
 pcs_status pcs_ensemble_destroy(struct pcs_ens* ens);
 
 #ifdef __cplusplus

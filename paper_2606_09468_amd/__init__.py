@@ -33,7 +33,7 @@ EXPORTS = ("pcs_workspace_bytes", "pcs_init", "pcs_step", "pcs_diagnostics", "pc
            "pcs_ensemble_midplane_histogram_setup", "pcs_ensemble_midplane_histogram", "pcs_resample_state",
            "pcs_midplane_pdf_setup", "pcs_midplane_pdf", "pcs_ensemble_midplane_pdf_setup", "pcs_ensemble_midplane_pdf",
            "pcs_init_static", "pcs_ensemble_set_state", "pcs_ensemble_run_status", "pcs_midplane_moments",
-           "pcs_ensemble_midplane_moments", "pcs_y_choice", "pcs_ensemble_y_choice")
+           "pcs_ensemble_midplane_moments", "pcs_y_choice", "pcs_ensemble_y_choice", "pcs_ensemble_stage_times")
 PCS_NSTAGE = 14
 PCS_HIST_MAX = 4096
 PCS_STATIC_BYTES = 64 << 20
@@ -123,6 +123,8 @@ def lib():
     dp = ctypes.POINTER(ctypes.c_double)
     L.pcs_y_choice.argtypes = [vp, ctypes.POINTER(pcs_ychoice)]
     L.pcs_ensemble_y_choice.argtypes = [vp, ctypes.POINTER(pcs_ychoice)]
+    L.pcs_ensemble_stage_times.argtypes = [vp, ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_double),
+                                           ctypes.c_int32]
     L.pcs_resample_state.argtypes = [ctypes.POINTER(pcs_grid), dp, sz, ctypes.POINTER(pcs_grid), dp, sz]
     for name in EXPORTS:
         if name not in ("pcs_status_string", "pcs_stage_name"):
@@ -404,6 +406,13 @@ class Ensemble:
         return _check(lib().pcs_ensemble_run_status(self.handle, int(run)), "pcs_ensemble_run_status",
                       allow=(PCS_OK, PCS_ERR_STATE))
 
+    def stage_times(self, nsteps, reps=1):
+        """As Sim.stage_times, for the whole ensemble (pcs_ensemble_stage_times)."""
+        ms = (ctypes.c_double * PCS_NSTAGE)()
+        _check(lib().pcs_ensemble_stage_times(self.handle, int(nsteps), int(reps), ms, PCS_NSTAGE),
+               "pcs_ensemble_stage_times")
+        return {lib().pcs_stage_name(i).decode(): ms[i] for i in range(PCS_NSTAGE)}
+
     def y_choice(self):
         """As Sim.y_choice, for the whole ensemble (pcs_ensemble_y_choice)."""
         out = pcs_ychoice()
@@ -413,7 +422,7 @@ class Ensemble:
     def midplane_moments(self, run, quantity):
         out = (ctypes.c_double * 3)()
         _check(lib().pcs_ensemble_midplane_moments(self.handle, int(run), int(quantity), out),
-               "pcs_ensemble_midplane_moments", "pcs_y_choice", "pcs_ensemble_y_choice")
+               "pcs_ensemble_midplane_moments", "pcs_y_choice", "pcs_ensemble_y_choice", "pcs_ensemble_stage_times")
         return _moments(out)
 
     def get_state(self, run):

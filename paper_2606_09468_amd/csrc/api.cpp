@@ -2286,10 +2286,7 @@ pcs_status pcs_y_choice(pcs_sim* sim, pcs_ychoice* out) {
   return batch_y_choice(&sim->b, out);
 }
 
-pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
-  if (!sim || nsteps <= 0 || reps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
-  if (sim->m()->blowup) return PCS_ERR_STATE;
-  Batch* b = &sim->b;
+pcs_status batch_stage_times(Batch* b, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
   hipEvent_t ev[ST_COUNT + 1];
   for (int i = 0; i <= ST_COUNT; ++i) HIPCHK(hipEventCreate(&ev[i]));
   std::vector<double> acc(ST_COUNT, 0.0);
@@ -2312,9 +2309,22 @@ pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* m
     }
   }
   for (int i = 0; i <= ST_COUNT; ++i) (void)hipEventDestroy(ev[i]);
-  for (int i = 0; i < ST_COUNT; ++i) ms[i] = acc[i] / nsteps;
+  // stages with no launch in this batch report 0
+  bool present[ST_COUNT];
+  for (bool& x : present) x = true;
+  present[ST_GEMM_MEAN] = b->GSm.n() > 0;
+  present[ST_GEMM_STATE] = b->GS.n() > 0;
+  present[ST_GEMM_D2] = b->GSb.n() > 0;
+  present[ST_ZFFT_INV] = present[ST_ZFFT_FWD] = present[ST_DIAG_ZFFT] = b->dim == 3;
+  for (int i = 0; i < ST_COUNT; ++i) ms[i] = present[i] ? acc[i] / nsteps : 0.0;
   for (int i = ST_COUNT; i < nstage; ++i) ms[i] = 0.0;
   return st;
+}
+
+pcs_status pcs_stage_times(pcs_sim* sim, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
+  if (!sim || nsteps <= 0 || reps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
+  if (sim->m()->blowup) return PCS_ERR_STATE;
+  return batch_stage_times(&sim->b, nsteps, reps, ms, nstage);
 }
 
 const char* pcs_stage_name(int32_t i) { return (i >= 0 && i < ST_COUNT) ? STAGE_NAMES[i] : nullptr; }
@@ -2414,6 +2424,11 @@ pcs_status pcs_ensemble_midplane_pdf(pcs_ens* e, int32_t run, int32_t quantity, 
 pcs_status pcs_ensemble_midplane_moments(pcs_ens* e, int32_t run, int32_t quantity, double* out) {
   if (!e || run < 0 || run >= (int32_t)e->b.mem.size()) return PCS_ERR_ARG;
   return member_moments(e->b.mem[run], e->b.s, quantity, out);
+}
+
+pcs_status pcs_ensemble_stage_times(pcs_ens* e, int32_t nsteps, int32_t reps, double* ms, int32_t nstage) {
+  if (!e || nsteps <= 0 || reps <= 0 || !ms || nstage < ST_COUNT) return PCS_ERR_ARG;
+  return batch_stage_times(&e->b, nsteps, reps, ms, nstage);
 }
 
 pcs_status pcs_ensemble_y_choice(pcs_ens* e, pcs_ychoice* out) {

@@ -445,9 +445,35 @@ def test_stage_times_advance_state_like_step(P, dims):
     # they recompute the same outputs, so the state must still match
     t = s2.stage_times(3, reps=3)
     assert set(t) >= {"xpencil", "gemm_state", "finalize"} and all(v >= 0 for v in t.values())
+    # stages with no launch report 0: the z transforms in 2D, and the separate
+    # mean and D2 / D product launches of small steps (one product launch)
+    for k in ("xpencil", "gemm_state", "gemm_proj", "rhs", "gemm_vinv", "gemm_v", "finalize", "diag_rows",
+              "diag_final"):
+        assert t[k] > 0, (k, t)
+    for k in ("gemm_mean", "gemm_d2") + (("zfft_inv", "zfft_fwd", "diag_zfft") if dims[0] == 2 else ()):
+        assert t[k] == 0, (k, t)
+    if dims[0] == 3:
+        assert t["zfft_inv"] > 0 and t["zfft_fwd"] > 0 and t["diag_zfft"] > 0
     assert np.array_equal(s1.get_state(), s2.get_state())
     s1.close()
     s2.close()
+
+
+def test_ensemble_stage_times(P):
+    """pcs_ensemble_stage_times: every stage of a small 2D ensemble timed,
+    the state advanced as by pcs_ensemble_step."""
+    print("case ensemble stage timing", flush=True)
+    grids = [P.make_grid(2, 32, 33), P.make_grid(2, 64, 65)]
+    params = [P.make_params(wi=20.0, dt=1e-3) for _ in grids]
+    e1 = P.Ensemble(grids, params, [1, 2], amp=1e-3)
+    e2 = P.Ensemble(grids, params, [1, 2], amp=1e-3)
+    e1.step(3)
+    t = e2.stage_times(3, reps=2)
+    assert t["gemm_state"] > 0 and t["xpencil"] > 0 and t["zfft_inv"] == 0
+    for r in range(2):
+        assert np.array_equal(e1.get_state(r), e2.get_state(r))
+    e1.close()
+    e2.close()
 
 
 def test_stage_times_bin_each_step_once(P):
