@@ -12,7 +12,7 @@ import pytest
 
 from oracle import Grid, Oracle, Params
 from paper_2606_09468_amd.workloads import ensemble_members
-from tests.test_gpu_parity import check_diag, check_state, fluct_errors, tol_history, tol_prognostic
+from tests.test_gpu_parity import check_diag, check_state, fluct_errors, mixed_ok, tol_history, tol_prognostic
 
 pytestmark = pytest.mark.gpu
 
@@ -62,7 +62,8 @@ def test_fp64_ensemble_members_match_oracle(P):
 
 def test_mixed_ensemble_members_match_oracle(P):
     """Mixed-precision members against the FP64 oracle with the single-run
-    mixed bar (fluctuation 2e-4 of its max, full fields 2e-5)."""
+    mixed bar (mixed_ok: fluctuation 2e-4 of its max, fields with a mean part
+    2e-5 of theirs)."""
     nsteps = 20
     members = SMALL[:4]
     print("case mixed ensemble", members, flush=True)
@@ -75,8 +76,7 @@ def test_mixed_ensemble_members_match_oracle(P):
         errs = fluct_errors(ens.get_state(r), o.get_state(), g)
         print("member", r, {k: "%.1e/%.1e" % v for k, v in errs.items()}, flush=True)
         for name in ("u", "v", "phi", "cxx", "cxy", "cyy"):
-            fl, full = errs[name]
-            assert fl < 2e-4 and full < 2e-5, (r, name, fl, full)
+            assert mixed_ok(errs[name]), (r, name, errs[name])
     ens.close()
 
 
@@ -121,8 +121,7 @@ def test_full_size_ensemble_sampled_members(P):
         errs = fluct_errors(ens.get_state(r), o.get_state(), g)
         print("member", r, nx, ny, {k: "%.1e/%.1e" % v for k, v in errs.items()}, flush=True)
         for name in ("u", "v", "phi", "cxx", "cxy", "cyy"):
-            fl, full = errs[name]
-            assert fl < 2e-4 and full < 2e-5, (r, name, fl, full)
+            assert mixed_ok(errs[name]), (r, name, errs[name])
     ens.close()
 
 
@@ -239,8 +238,7 @@ def test_full_ensemble_every_size_class_against_oracle(P):
             r, nx, ny, max(v[0] for v in list(errs.values())[:6]), max(v[1] for v in list(errs.values())[:6])),
             flush=True)
         for name in ("u", "v", "phi", "cxx", "cxy", "cyy"):
-            fl, full = errs[name]
-            assert fl < 2e-4 and full < 2e-5, (r, nx, ny, name, fl, full)
+            assert mixed_ok(errs[name]), (r, nx, ny, name, errs[name])
     ens.close()
 
 
@@ -270,5 +268,4 @@ def test_member_512x193_fifty_steps_against_oracle(P, precision):
     else:
         errs = fluct_errors(a, o.get_state(), g)
         for name in ("u", "v", "phi", "cxx", "cxy", "cyy"):
-            fl, full = errs[name]
-            assert fl < 2e-4 and full < 2e-5, (name, fl, full)
+            assert mixed_ok(errs[name]), (name, errs[name])

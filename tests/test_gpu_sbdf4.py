@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import Grid, Oracle, Params, state_layout
-from tests.test_gpu_parity import P, tol_history, tol_prognostic  # noqa: F401
+from tests.test_gpu_parity import P, FieldErr, mixed_ok, tol_history, tol_prognostic  # noqa: F401
 from tests.test_oracle_sbdf4 import recursion
 
 pytestmark = pytest.mark.gpu
@@ -136,8 +136,9 @@ def test_sbdf4_resume_and_stage_path(P):
 @pytest.mark.parametrize("precision", [1, 2, 3, 4])
 def test_sbdf4_mixed_precision(P, precision):
     """Mixed precision with SBDF4 against the FP64 oracle, to the bar of the
-    CNAB2 mixed path: prognostic fluctuation within 2e-4 of its own max,
-    every prognostic field within 2e-5 of its full max."""
+    CNAB2 mixed path (mixed_ok): prognostic fluctuation within 2e-4 of its
+    own max, every prognostic field with a mean part within 2e-5 of its full
+    max."""
     print("case sbdf4 mixed p%d" % precision, flush=True)
     g, prm, n = Grid(2, 64, 65), dict(wi=20.0, dt=1e-3), 40
     sim = P.Sim(P.make_grid(2, 64, 65), P.make_params(precision=precision, scheme=1, **prm), seed=1, amp=1e-3)
@@ -152,10 +153,11 @@ def test_sbdf4_mixed_precision(P, precision):
         x = a[hdr + i * 2 * per: hdr + (i + 1) * 2 * per].reshape(g.ny, -1, 2).copy()
         y = b[hdr + i * 2 * per: hdr + (i + 1) * 2 * per].reshape(g.ny, -1, 2).copy()
         full = np.abs(x - y).max() / np.abs(y).max()
+        zero_mean = not np.any(y[:, 0, :])
         x[:, 0, :] = 0
         y[:, 0, :] = 0
         fl = np.abs(x - y).max() / np.abs(y).max()
-        assert fl <= 2e-4 and full <= 2e-5, (name, fl, full)
+        assert mixed_ok(FieldErr(fl, full, zero_mean)), (name, fl, full)
 
 
 def test_ensemble_mixes_schemes(P):

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 
 from oracle import Grid, state_layout
-from tests.test_gpu_parity import P, check_counts, fluct_errors, tol_history, tol_prognostic  # noqa: F401
+from tests.test_gpu_parity import P, check_counts, fluct_errors, mixed_ok, tol_history, tol_prognostic  # noqa: F401
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def test_static_init_matches_workspace_init(P):
         else:
             errs = fluct_errors(a, b, g)
             for name in names[:nq]:
-                assert errs[name][0] <= 2e-4 and errs[name][1] <= 2e-5, (case, name, errs[name])
+                assert mixed_ok(errs[name]), (case, name, errs[name])
         for x, y in zip(ra, rb):
             assert x["step"] == y["step"] and x["blowup"] == y["blowup"] == 0
             assert abs(x["min_trc"] - y["min_trc"]) <= 2e-5 * abs(y["min_trc"]), (case, x["min_trc"], y["min_trc"])
