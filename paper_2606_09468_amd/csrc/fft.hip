@@ -11,7 +11,11 @@
 // fixed at compile time (constant strides and twiddle indices); where the
 // sequences of a pass belong to one wave (x pencils, row diagnostics) the
 // synchronisation is that of the wave alone.  Two real fields share one
-// complex transform (z = a + i b).
+// complex transform (z = a + i b).  The x lines of those lengths (L = 3 nkx)
+// put the radix-3 pass first in the inverse and last in the forward
+// transform, so that the spectra enter and leave through registers and the
+// zero band of the 3/2 rule is never stored; their power-of-two passes take
+// radices up to 16.
 //
 // x pencil: one workgroup per padded (y', z') line.  It reads the needed
 // spectral fields of that line (kx modes), generates the d/dx variants by
@@ -170,6 +174,29 @@ __device__ inline void butterfly(cx<T>* v, int sign) {
       v[2 * m] = a[m];
       v[2 * m + 1] = b[m];
     }
+  } else if constexpr (R == 16) {
+    // 4 x 4: inputs n = 4 n1 + n2, outputs k = k1 + 4 k2; DFT4 over n1,
+    // twiddle w16^(n2 k1) (w16 = exp(sign 2 pi i / 16)), DFT4 over n2
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173), h = T(0.70710678118654752440);
+    const T sg = T(sign);
+    // w16^m for m = 0 .. 9 (cos, sign * sin)
+    const cx<T> w[10] = {{1, 0},   {c1, sg * s1},      {h, sg * h},         {s1, sg * c1},  {0, sg},
+                         {-s1, sg * c1}, {-h, sg * h}, {-c1, sg * s1},      {-1, 0},        {-c1, -sg * s1}};
+    cx<T> a[4][4];
+#pragma unroll
+    for (int n2 = 0; n2 < 4; ++n2) {
+      cx<T> t[4] = {v[n2], v[4 + n2], v[8 + n2], v[12 + n2]};
+      butterfly<T, 4>(t, sign);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) a[n2][k1] = (n2 && k1) ? cmul(t[k1], w[n2 * k1]) : t[k1];
+    }
+#pragma unroll
+    for (int k1 = 0; k1 < 4; ++k1) {
+      cx<T> t[4] = {a[0][k1], a[1][k1], a[2][k1], a[3][k1]};
+      butterfly<T, 4>(t, sign);
+#pragma unroll
+      for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = t[k2];
+    }
   } else {
     const T h = T(0.86602540378443864676) * T(sign);  // sign * sqrt(3)/2
     cx<T> t1 = v[1] + v[2];
@@ -298,13 +325,15 @@ __host__ __device__ constexpr int cns(int L, int p) {
   return ns;
 }
 
-// pass_ip with the plan of length L fixed (SIGN: +1 inverse, -1 forward)
-template <typename T, int L, int P, int NTH, int MV, bool WAVE, int SIGN, typename V>
-__device__ __attribute__((always_inline)) inline void pass_c(V buf, int sl, int nseq, const cx<T>* __restrict__ tw,
-                                                             int tid) {
-  constexpr int R = cradix(L, P), LR = L / R, Ns = cns(L, P), stride = L / (Ns * R);
+// One Stockham pass of radix R over sequences of a length L fixed at compile
+// time, NS the product of the radices before it (SIGN: +1 inverse, -1
+// forward); as pass_ip otherwise.
+template <typename T, int L, int R, int NS, int NTH, int MV, bool WAVE, int SIGN, typename V>
+__device__ __attribute__((always_inline)) inline void pass_rn(V buf, int sl, int nseq, const cx<T>* __restrict__ tw,
+                                                              int tid) {
+  constexpr int LR = L / R, stride = L / (NS * R);
   constexpr int NB = MV / R;
-  static_assert(cpass_count(L) > 0 && R > 1 && NB >= 1, "plan");
+  static_assert(R > 1 && NB >= 1 && L % (NS * R) == 0, "plan");
   const int tot = nseq * LR;
   cx<T> v[NB][R];
 #pragma unroll
@@ -323,8 +352,8 @@ __device__ __attribute__((always_inline)) inline void pass_c(V buf, int sl, int 
     const int idx = tid + q * NTH;
     if (idx < tot) {
       const int s = idx / LR, j = idx - s * LR;
-      const int k = j % Ns;
-      if constexpr (Ns > 1) {
+      const int k = j % NS;
+      if constexpr (NS > 1) {
 #pragma unroll
         for (int r = 1; r < R; ++r) {
           cx<T> w = tw[r * k * stride];
@@ -335,10 +364,18 @@ __device__ __attribute__((always_inline)) inline void pass_c(V buf, int sl, int 
       butterfly<T, R>(v[q], SIGN);
       const V dst = buf.at(s * sl + (j - k) * R + k);
 #pragma unroll
-      for (int r = 0; r < R; ++r) dst[r * Ns] = v[q][r];
+      for (int r = 0; r < R; ++r) dst[r * NS] = v[q][r];
     }
   }
   pass_sync<WAVE>();
+}
+
+// pass_ip with the plan of length L fixed
+template <typename T, int L, int P, int NTH, int MV, bool WAVE, int SIGN, typename V>
+__device__ __attribute__((always_inline)) inline void pass_c(V buf, int sl, int nseq, const cx<T>* __restrict__ tw,
+                                                             int tid) {
+  static_assert(cpass_count(L) > 0, "plan");
+  pass_rn<T, L, cradix(L, P), cns(L, P), NTH, MV, WAVE, SIGN>(buf, sl, nseq, tw, tid);
 }
 
 template <typename T, int L, int NTH, int MV, bool WAVE, int SIGN, int P = 0, typename V = LV<T>>
@@ -368,6 +405,97 @@ constexpr int XMVW = 16;
 template <typename T, int LC>
 __host__ __device__ constexpr int xmvw() {
   return (sizeof(T) == 8 && LC > 0 && LC <= 384) ? 8 : XMVW;
+}
+
+// ------------------------------------------------ x lines of a compiled length L = 3 nkx
+// The 3/2-rule line of an x pencil carries nonzero spectrum at k < nkx and
+// k > 2 nkx only (nkx = L / 3 retained modes).  Its inverse transform takes
+// the radix-3 pass first, over the stride nkx: butterfly j then reads X_j and
+// X_(j + 2 nkx) and nothing of the zero band, and is formed straight from the
+// spectra in registers (no packing into LDS, no clearing of the band).  The
+// forward transform takes the radix-3 pass last and computes only the
+// outputs k < nkx and k > 2 nkx, which the unpacking of the two real fields
+// reads, straight from registers.  In both, one lane takes butterflies j and
+// nkx - j (j = 0 with nkx / 2), which read and write the same modes.  The
+// power-of-two part L / 3 goes in as few passes as radices of at most RM allow,
+// bits spread evenly (128: 16 x 8; 64: 8 x 8; 256: 16 x 16).
+__host__ __device__ constexpr int clog2(int n) {
+  int a = 0;
+  while ((1 << a) < n) ++a;
+  return a;
+}
+__host__ __device__ constexpr int xp_count(int L, int RM) { return (clog2(L / 3) + clog2(RM) - 1) / clog2(RM); }
+// radix of power-of-two pass i, in the inverse transform's order
+__host__ __device__ constexpr int xp_radix(int L, int RM, int i) {
+  return 1 << (clog2(L / 3) / xp_count(L, RM) + (i < clog2(L / 3) % xp_count(L, RM) ? 1 : 0));
+}
+// sequences of length L a wave's passes hold at MV complex values per lane
+template <int L, int MV>
+__host__ __device__ constexpr int xp_batch() {
+  return 64 * MV / L;
+}
+template <typename T, int L, int RM, int MV, int I = 0, int NS = 3, typename V>
+__device__ __attribute__((always_inline)) inline void xfft_inv_tail(V buf, int sl, int nseq,
+                                                                    const cx<T>* __restrict__ tw, int lane) {
+  if constexpr (I < xp_count(L, RM)) {
+    constexpr int R = xp_radix(L, RM, I);
+    pass_rn<T, L, R, NS, 64, MV, true, +1>(buf, sl, nseq, tw, lane);
+    xfft_inv_tail<T, L, RM, MV, I + 1, NS * R, V>(buf, sl, nseq, tw, lane);
+  }
+}
+template <typename T, int L, int RM, int MV, int I = 0, int NS = 1, typename V>
+__device__ __attribute__((always_inline)) inline void xfft_fwd_head(V buf, int sl, int nseq,
+                                                                    const cx<T>* __restrict__ tw, int lane) {
+  if constexpr (I < xp_count(L, RM)) {
+    constexpr int R = xp_radix(L, RM, xp_count(L, RM) - 1 - I);
+    pass_rn<T, L, R, NS, 64, MV, true, -1>(buf, sl, nseq, tw, lane);
+    xfft_fwd_head<T, L, RM, MV, I + 1, NS * R, V>(buf, sl, nseq, tw, lane);
+  }
+}
+// Radix-3 inverse butterfly with a zero middle input: outputs of (x, 0, c).
+template <typename T, typename V>
+__device__ __attribute__((always_inline)) inline void xp_first3(V dst, cx<T> x, cx<T> c) {
+  const T h = T(0.86602540378443864676);
+  const cx<T> t2{x.x - T(0.5) * c.x, x.y - T(0.5) * c.y};
+  // i * (sqrt(3)/2) * (0 - c)
+  const cx<T> it3{h * c.y, -h * c.x};
+  dst[0] = x + c;
+  dst[1] = t2 + it3;
+  dst[2] = t2 - it3;
+}
+// First inverse pass of unit u of a line Xq (the butterflies j1 = u and
+// j2 = nkx - u, or 0 and nkx / 2 for u = 0) from the modes (A1, B1) at j1 and
+// (A2, B2) at j2 of the two real fields a, b of the pair: X_k = A_k + i B_k,
+// X_(L-k) = conj(A_k) + i conj(B_k), X_0 = Re A_0 + i Re B_0.
+template <typename T, typename V>
+__device__ __attribute__((always_inline)) inline void xp_first(V Xq, int nkx, int u, cx<T> A1, cx<T> B1, cx<T> A2,
+                                                               cx<T> B2) {
+  const int j2 = u ? nkx - u : nkx >> 1;
+  const cx<T> p1 = u ? cx<T>{A1.x - B1.y, A1.y + B1.x} : cx<T>{A1.x, B1.x};
+  const cx<T> p2{A2.x - B2.y, A2.y + B2.x};
+  const cx<T> q1{A1.x + B1.y, B1.x - A1.y}, q2{A2.x + B2.y, B2.x - A2.y};
+  // X_(j + 2 nkx) = X_(L - (nkx - j)): of mode j2 for j1, of mode j1 for j2
+  // (u = 0: zero for j1 = 0, mode nkx / 2 itself for j2)
+  xp_first3<T>(Xq.at(3 * u), p1, u ? q2 : cx<T>{0, 0});
+  xp_first3<T>(Xq.at(3 * j2), p2, u ? q1 : q2);
+}
+// Last forward pass (radix 3, stride nkx) at butterfly j of a line Zq:
+// outputs Z_j (y0) and Z_(j + 2 nkx) (y2).
+template <typename T, typename V>
+__device__ __attribute__((always_inline)) inline void xp_last(V Zq, int nkx, int j, const cx<T>* __restrict__ tw,
+                                                              cx<T>& y0, cx<T>& y2) {
+  const T h = T(0.86602540378443864676);
+  const cx<T> v0 = Zq[j], v1 = cmul(Zq[j + nkx], tw[j]), v2 = cmul(Zq[j + 2 * nkx], tw[2 * j]);
+  const cx<T> t1 = v1 + v2, d = v1 - v2;
+  y0 = v0 + t1;
+  // v0 - t1 / 2 + i (sqrt(3)/2) (v1 - v2)
+  y2 = cx<T>{v0.x - T(0.5) * t1.x - h * d.y, v0.y - T(0.5) * t1.y + h * d.x};
+}
+// Spectra of the two real fields at mode k from Z_k and Z_(L-k) (k > 0).
+template <typename T>
+__device__ __attribute__((always_inline)) inline void xp_unpack(cx<T> Zk, cx<T> Zc, cx<T>& A, cx<T>& B) {
+  A = cx<T>{T(0.5) * (Zk.x + Zc.x), T(0.5) * (Zk.y - Zc.y)};
+  B = cx<T>{T(0.5) * (Zk.y + Zc.y), T(-0.5) * (Zk.x - Zc.x)};
 }
 
 // Largest batch of sequences a pass can hold in registers.
@@ -618,7 +746,84 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   // each wave packs whole field pairs, so the field tables are read once per
   // pair (wave-uniform) and the lanes stream one field's kx modes
   const int lane = tid & 63, wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  {
+  // loads in issue order: the twiddles (a few per thread), then the first
+  // items, whose latency the twiddle stores then overlap (loads complete in
+  // order, so the twiddles come first)
+  constexpr int TWN = (64 * cover(XMVW) + NTH - 1) / NTH;  // the longest line xpencil_lds_bytes admits
+  if constexpr (LC > 0) {
+    // compiled lengths (L = 3 nkx): radix-3 first pass from the spectra
+    constexpr int NKX = LC / 3, NU = NKX / 2, NUB = (NU + 63) / 64;
+    constexpr int RM = MVW < 16 ? MVW : 16, SWX = xp_batch<LC, MVW>();
+    static_assert(SWX >= 1 && NKX * 3 == LC, "x line");
+    constexpr int nb = XS::NP;
+    const XV X = PV;
+    // the wave's items: (pair q = wave + NW i, block of 64 units); the loads
+    // of GI items (four modes each) are issued before any is transformed
+    const int items = max(0, (nb - wave + NW - 1) / NW) * NUB;
+    constexpr int GI = (sizeof(T) == 4 && DIM == 3) ? 4 : 2;
+    T2 va1[GI], vb1[GI], va2[GI], vb2[GI];
+    auto load_units = [&](int i0) {
+#pragma unroll
+      for (int g = 0; g < GI; ++g) {
+        const int it = i0 + g, qi = it / NUB, u = lane + 64 * (it - qi * NUB);
+        const int fa = 2 * (wave + NW * qi), fb = fa + 1;
+        va1[g] = vb1[g] = va2[g] = vb2[g] = T2{0, 0};
+        if (it < items && u < NU) {
+          const int j2 = u ? NKX - u : NKX / 2;
+          const gptr<const T> pa = base + src[fa] * fstride;
+          va1[g] = *reinterpret_cast<gptr<const T2>>(pa + 2 * u);
+          va2[g] = *reinterpret_cast<gptr<const T2>>(pa + 2 * j2);
+          if (fb < XS::NREAL) {
+            const gptr<const T> pb = base + src[fb] * fstride;
+            vb1[g] = *reinterpret_cast<gptr<const T2>>(pb + 2 * u);
+            vb2[g] = *reinterpret_cast<gptr<const T2>>(pb + 2 * j2);
+          }
+        }
+      }
+    };
+    T2 tv[TWN];
+    {
+      const gptr<const T2> tw = gmem(static_cast<const T2*>(XA.tw));
+#pragma unroll
+      for (int r = 0; r < TWN; ++r) tv[r] = tid + r * NTH < L ? tw[tid + r * NTH] : T2{0, 0};
+    }
+    load_units(0);
+#pragma unroll
+    for (int r = 0; r < TWN; ++r)
+      if (tid + r * NTH < L) twl[tid + r * NTH] = cx<T>{tv[r][0], tv[r][1]};
+    for (int i0 = 0; i0 < items; i0 += GI) {
+      if (i0 > 0) load_units(i0);
+#pragma unroll
+      for (int g = 0; g < GI; ++g) {
+        const int it = i0 + g, qi = it / NUB, u = lane + 64 * (it - qi * NUB);
+        const int q = wave + NW * qi, fa = 2 * q, fb = fa + 1;
+        if (it < items && u < NU) {
+          const int j2 = u ? NKX - u : NKX / 2;
+          cx<T> A1{va1[g][0], va1[g][1]}, B1{vb1[g][0], vb1[g][1]};
+          cx<T> A2{va2[g][0], va2[g][1]}, B2{vb2[g][0], vb2[g][1]};
+          const bool da = dxf[fa] != 0, db = fb < XS::NREAL && dxf[fb] != 0;
+          if (da || db) {
+            const T k1 = T(kx[u]), k2 = T(kx[j2]);
+            if (da) {
+              A1 = cx<T>{-k1 * A1.y, k1 * A1.x};
+              A2 = cx<T>{-k2 * A2.y, k2 * A2.x};
+            }
+            if (db) {
+              B1 = cx<T>{-k1 * B1.y, k1 * B1.x};
+              B2 = cx<T>{-k2 * B2.y, k2 * B2.x};
+            }
+          }
+          xp_first<T>(X.at(q * L), NKX, u, A1, B1, A2, B2);
+        }
+      }
+    }
+    // every wave's twiddles (each wave's first pass wrote its own pairs)
+    __syncthreads();
+    const int own = (nb - wave + NW - 1) / NW;
+    for (int i0 = 0; i0 < own; i0 += SWX)
+      xfft_inv_tail<T, LC, RM, MVW>(X.at((wave + NW * i0) * L), NW * L, min(SWX, own - i0), twl, lane);
+    __syncthreads();
+  } else {
     constexpr int b0 = 0, nb = XS::NP;
     const XV X = PV;
     // the wave's items are (pair q = wave + NW i, block of 64 kx); G items'
@@ -639,10 +844,6 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
         }
       }
     };
-    // loads in issue order: the twiddles (a few per thread), then the first
-    // items, whose latency the twiddle stores and the clearing of the pairs
-    // then overlap (loads complete in order, so the twiddles come first)
-    constexpr int TWN = (64 * cover(XMVW) + NTH - 1) / NTH;  // the longest line xpencil_lds_bytes admits
     T2 tv[TWN];
     {
       const gptr<const T2> tw = gmem(static_cast<const T2*>(XA.tw));
@@ -710,7 +911,49 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   __syncthreads();
   const T inv = T(1.0 / L);
   const gptr<T> obase = out + (size_t)row * nkx * 2;
-  {
+  if constexpr (LC > 0) {
+    // compiled lengths: the radix-3 last pass unpacked and stored from registers
+    constexpr int NKX = LC / 3, NU = NKX / 2;
+    constexpr int RM = MVW < 16 ? MVW : 16, SWX = xp_batch<LC, MVW>();
+    constexpr int nb = XS::NOP;
+    const XV Z = PV;
+    const int own = (nb - wave + NW - 1) / NW;
+    for (int i0 = 0; i0 < own; i0 += SWX)
+      xfft_fwd_head<T, LC, RM, MVW>(Z.at((wave + NW * i0) * L), NW * L, min(SWX, own - i0), twl, lane);
+    for (int q = wave; q < nb; q += NW)
+      for (int u = lane; u < NU; u += 64) {
+        const int j2 = u ? NKX - u : NKX / 2;
+        cx<T> y0a, y2a, y0b, y2b, A1, B1, A2, B2;
+        xp_last<T>(Z.at(q * L), NKX, u, twl, y0a, y2a);
+        xp_last<T>(Z.at(q * L), NKX, j2, twl, y0b, y2b);
+        // mode u pairs Z_u with Z_(L-u) = Z_(2 nkx + j2); mode j2 with Z_(2 nkx + u)
+        // (u = 0: mode 0 alone, mode nkx / 2 with its own butterfly's y2)
+        if (u) {
+          xp_unpack<T>(y0a, y2b, A1, B1);
+        } else {
+          A1 = cx<T>{y0a.x, 0};
+          B1 = cx<T>{y0a.y, 0};
+        }
+        xp_unpack<T>(y0b, u ? y2a : y2b, A2, B2);
+        const int fa = 2 * q, fb = fa + 1;
+        const gptr<T> oa = obase + (size_t)fa * fstride;
+        *reinterpret_cast<gptr<T2>>(oa + 2 * u) = T2{A1.x * inv, A1.y * inv};
+        *reinterpret_cast<gptr<T2>>(oa + 2 * j2) = T2{A2.x * inv, A2.y * inv};
+        if (fb < XS::NOUT) {
+          const gptr<T> ob = obase + (size_t)fb * fstride;
+          *reinterpret_cast<gptr<T2>>(ob + 2 * u) = T2{B1.x * inv, B1.y * inv};
+          *reinterpret_cast<gptr<T2>>(ob + 2 * j2) = T2{B2.x * inv, B2.y * inv};
+        }
+        if constexpr (MIXED && DIM == 2) {
+          // the kx = 0 column is the whole mean (2D has no z): complete it in FP64
+          if (u == 0) {
+            mcol[(size_t)fa * m1 + row] = double(A1.x * inv) + mean_product(2, fa, mean, m1, row, eps_wi);
+            if (fb < XS::NOUT)
+              mcol[(size_t)fb * m1 + row] = double(B1.x * inv) + mean_product(2, fb, mean, m1, row, eps_wi);
+          }
+        }
+      }
+  } else {
     constexpr int q0 = 0, nb = XS::NOP;
     const XV Z = PV;
     const int own = (nb - wave + NW - 1) / NW;
@@ -735,24 +978,34 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   }
 }
 
-// (FP64 lines of 768 take the runtime plan: their compiled passes would need
-// registers for fewer waves than the LDS admits)
+template <typename T, int DIM>
+__host__ __device__ constexpr size_t xpencil_lds(int L) {
+  return (lds_span<true>((size_t)XShape<DIM>::NP * L) + L) * sizeof(cx<T>);
+}
+
+// Compiled plan of a line length in a kernel of NTH threads: the host takes
+// 256-thread workgroups only where four fit a CU's LDS, so a length whose
+// LDS does not allow that never runs there and takes the runtime plan (its
+// compiled passes would only raise the kernel's registers); FP64 lines of 768
+// take the runtime plan too (their compiled passes would need registers for
+// fewer waves than the LDS admits).
+template <typename T, int DIM, int NTH, int L>
+__host__ __device__ constexpr int xpencil_lc() {
+  if (sizeof(T) == 8 && L == 768) return 0;
+  return (NTH > 256 || 4 * xpencil_lds<T, DIM>(L) <= 160 * 1024) ? L : 0;
+}
+
 template <typename T, int DIM, bool MIXED, int NTH>
 __global__ __launch_bounds__(NTH) void xpencil_kernel(const XArgs* __restrict__ args, int nmem) {
   const XArgs& XA = args[member_of(args, nmem)];
   if (masked(XA.skip)) return;
   switch (XA.pl.L) {
-    case 96: xpencil_body<T, DIM, MIXED, NTH, 96>(XA); break;
-    case 192: xpencil_body<T, DIM, MIXED, NTH, 192>(XA); break;
-    case 384: xpencil_body<T, DIM, MIXED, NTH, 384>(XA); break;
-    case 768: xpencil_body<T, DIM, MIXED, NTH, sizeof(T) == 4 ? 768 : 0>(XA); break;
+    case 96: xpencil_body<T, DIM, MIXED, NTH, xpencil_lc<T, DIM, NTH, 96>()>(XA); break;
+    case 192: xpencil_body<T, DIM, MIXED, NTH, xpencil_lc<T, DIM, NTH, 192>()>(XA); break;
+    case 384: xpencil_body<T, DIM, MIXED, NTH, xpencil_lc<T, DIM, NTH, 384>()>(XA); break;
+    case 768: xpencil_body<T, DIM, MIXED, NTH, xpencil_lc<T, DIM, NTH, 768>()>(XA); break;
     default: xpencil_body<T, DIM, MIXED, NTH, 0>(XA); break;
   }
-}
-
-template <typename T, int DIM>
-size_t xpencil_lds(int L) {
-  return (lds_span<true>((size_t)XShape<DIM>::NP * L) + L) * sizeof(cx<T>);
 }
 
 // ------------------------------------------------ 3D x pencils in field chunks
