@@ -582,6 +582,10 @@ XFORM_CASES = [
     ("3D 64x33x16 x6", Grid(3, 64, 33, 16), dict(wi=50.0, dt=5e-4, eps=1e-3), 6),     # lines of 96
     ("3D 128x33x8 x6", Grid(3, 128, 33, 8), dict(wi=50.0, dt=5e-4), 6),               # lines of 192
     ("3D 256x17x4 x4", Grid(3, 256, 17, 4), dict(wi=20.0, dt=1e-3, eps=1e-3), 4),     # lines of 384
+    # enough lines (25 x 72) for the launch shapes of the large grids (lines
+    # of 192 in FP64 and of 384 in both precisions: two workgroups per CU)
+    ("3D 128x17x48 x4", Grid(3, 128, 17, 48), dict(wi=50.0, dt=5e-4), 4),             # lines of 192
+    ("3D 256x17x48 x3", Grid(3, 256, 17, 48), dict(wi=20.0, dt=1e-3, eps=1e-3), 3),   # lines of 384
 ]
 
 
