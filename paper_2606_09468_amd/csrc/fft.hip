@@ -434,22 +434,24 @@ template <int L, int MV>
 __host__ __device__ constexpr int xp_batch() {
   return 64 * MV / L;
 }
-template <typename T, int L, int RM, int MV, int I = 0, int NS = 3, typename V>
+// the passes after the radix-3 one (inverse) and before it (forward), by NTH
+// threads (one wave's lanes for WAVE)
+template <typename T, int L, int RM, int MV, int NTH = 64, bool WAVE = true, int I = 0, int NS = 3, typename V>
 __device__ __attribute__((always_inline)) inline void xfft_inv_tail(V buf, int sl, int nseq,
-                                                                    const cx<T>* __restrict__ tw, int lane) {
+                                                                    const cx<T>* __restrict__ tw, int tid) {
   if constexpr (I < xp_count(L, RM)) {
     constexpr int R = xp_radix(L, RM, I);
-    pass_rn<T, L, R, NS, 64, MV, true, +1>(buf, sl, nseq, tw, lane);
-    xfft_inv_tail<T, L, RM, MV, I + 1, NS * R, V>(buf, sl, nseq, tw, lane);
+    pass_rn<T, L, R, NS, NTH, MV, WAVE, +1>(buf, sl, nseq, tw, tid);
+    xfft_inv_tail<T, L, RM, MV, NTH, WAVE, I + 1, NS * R, V>(buf, sl, nseq, tw, tid);
   }
 }
-template <typename T, int L, int RM, int MV, int I = 0, int NS = 1, typename V>
+template <typename T, int L, int RM, int MV, int NTH = 64, bool WAVE = true, int I = 0, int NS = 1, typename V>
 __device__ __attribute__((always_inline)) inline void xfft_fwd_head(V buf, int sl, int nseq,
-                                                                    const cx<T>* __restrict__ tw, int lane) {
+                                                                    const cx<T>* __restrict__ tw, int tid) {
   if constexpr (I < xp_count(L, RM)) {
     constexpr int R = xp_radix(L, RM, xp_count(L, RM) - 1 - I);
-    pass_rn<T, L, R, NS, 64, MV, true, -1>(buf, sl, nseq, tw, lane);
-    xfft_fwd_head<T, L, RM, MV, I + 1, NS * R, V>(buf, sl, nseq, tw, lane);
+    pass_rn<T, L, R, NS, NTH, MV, WAVE, -1>(buf, sl, nseq, tw, tid);
+    xfft_fwd_head<T, L, RM, MV, NTH, WAVE, I + 1, NS * R, V>(buf, sl, nseq, tw, tid);
   }
 }
 // Radix-3 inverse butterfly with a zero middle input: outputs of (x, 0, c).
@@ -1357,6 +1359,97 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
   const int dz = deriv ? deriv[f] : 0;
   const gptr<const T> ib = in + ((size_t)sf * rows_y + i) * rin * nkx * 2;
   const gptr<T> ob = out + ((size_t)f * rows_y + i) * rout * nkx * 2;
+  // as many columns per batch as one pass holds in registers
+  // (compiled plans: 16 values per thread, whose registers keep the
+  // occupancy of the runtime plan's 24)
+  constexpr int MVC = LC > 0 ? 16 : MV;
+  if constexpr (LC > 0 && LC % 3 == 0) {
+    // padded columns (L = 3 nzs / 2): radix-3 pass first (inverse) or last
+    // (forward) over the 3/2-rule band, fed from and stored to HBM through
+    // registers (see the x lines); butterfly j holds the stored modes j and
+    // nzs / 2 + j (the Nyquist slot, j = 0, is zero)
+    if (2 * L == 3 * nzs) {
+      constexpr int NZH = LC / 3, S = NT * MVC / LC;
+      if (inverse) {
+        constexpr int PB = 4;
+        const int tot = NZH * ng;
+        for (int e0 = 0; e0 < tot; e0 += PB * NT) {
+          T2 xa[PB], xc[PB];
+#pragma unroll
+          for (int u = 0; u < PB; ++u) {
+            const int e = e0 + tid + u * NT;
+            xa[u] = xc[u] = T2{0, 0};
+            if (e < tot) {
+              const int j = fdiv(e, mng), g = e - j * ng;
+              xa[u] = *reinterpret_cast<gptr<const T2>>(ib + ((size_t)j * nkx + k0 + g) * 2);
+              if (j > 0) xc[u] = *reinterpret_cast<gptr<const T2>>(ib + ((size_t)(NZH + j) * nkx + k0 + g) * 2);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < PB; ++u) {
+            const int e = e0 + tid + u * NT;
+            if (e < tot) {
+              const int j = fdiv(e, mng), g = e - j * ng;
+              c2 a{xa[u][0], xa[u][1]}, c{xc[u][0], xc[u][1]};
+              if (dz) {
+                const T ka = T(kz[j]), kc = T(kz[NZH + j]);
+                a = c2{-ka * a.y, ka * a.x};
+                c = c2{-kc * c.y, kc * c.x};
+              }
+              xp_first3<T>(AV.at(g * SL + 3 * j), a, c);
+            }
+          }
+        }
+        __syncthreads();
+        for (int b0 = 0; b0 < ng; b0 += S)
+          xfft_inv_tail<T, LC, 16, MVC, NT, false>(AV.at(b0 * SL), SL, min(S, ng - b0), twl, tid);
+        for (int e = tid; e < L * ng; e += NT) {
+          const int z = fdiv(e, mng), g = e - z * ng;
+          const c2 v = AV[g * SL + z];
+          *reinterpret_cast<gptr<T2>>(ob + ((size_t)z * nkx + k0 + g) * 2) = T2{v.x, v.y};
+        }
+      } else {
+        constexpr int PER = 8;
+        const int tot = L * ng;
+        for (int e0 = 0; e0 < tot; e0 += PER * NT) {
+          T2 v[PER];
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int e = e0 + tid + u * NT;
+            if (e < tot) {
+              const int z = fdiv(e, mng), g = e - z * ng;
+              v[u] = *reinterpret_cast<gptr<const T2>>(ib + ((size_t)z * nkx + k0 + g) * 2);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int e = e0 + tid + u * NT;
+            if (e < tot) {
+              const int z = fdiv(e, mng), g = e - z * ng;
+              AV[g * SL + z] = c2{v[u][0], v[u][1]};
+            }
+          }
+        }
+        __syncthreads();
+        for (int b0 = 0; b0 < ng; b0 += S)
+          xfft_fwd_head<T, LC, 16, MVC, NT, false>(AV.at(b0 * SL), SL, min(S, ng - b0), twl, tid);
+        const T inv = T(1.0 / L);
+        for (int e = tid; e < NZH * ng; e += NT) {
+          const int j = fdiv(e, mng), g = e - j * ng;
+          c2 y0, y2;
+          xp_last<T>(AV.at(g * SL), NZH, j, twl, y0, y2);
+          y0 = scal(inv, y0);
+          y2 = j ? scal(inv, y2) : c2{0, 0};
+          *reinterpret_cast<gptr<T2>>(ob + ((size_t)j * nkx + k0 + g) * 2) = T2{y0.x, y0.y};
+          *reinterpret_cast<gptr<T2>>(ob + ((size_t)(NZH + j) * nkx + k0 + g) * 2) = T2{y2.x, y2.y};
+          // mixed forward transform: the kx = kz = 0 value completed in FP64
+          if (mcol && j == 0 && k0 + g == 0)
+            mcol[(size_t)f * rows_y + i] = double(y0.x) + mean_product(3, f, mean, rows_y, i, ZA.eps_wi);
+        }
+      }
+      return;
+    }
+  }
   // gather PER elements per thread before writing LDS, so that many global
   // loads are in flight at once
   constexpr int PER = 8;
@@ -1419,10 +1512,6 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
     }
   }
   __syncthreads();
-  // as many columns per batch as one pass holds in registers
-  // (compiled plans: 16 values per thread, whose registers keep the
-  // occupancy of the runtime plan's 24)
-  constexpr int MVC = LC > 0 ? 16 : MV;
   const int S = fft_batch<T, NT, MVC>(L);
   for (int b0 = 0; b0 < ng; b0 += S) {
     if (inverse)
