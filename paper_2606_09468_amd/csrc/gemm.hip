@@ -777,36 +777,58 @@ __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __
   T* Be = reinterpret_cast<T*>(smem);
   T* Bo = Be + (size_t)K16 * PB;
   const gptr<const TB> B = gmem(static_cast<const TB*>(jp->B));
-  // stage the panel, columns fastest (coalesced rows of B), four elements'
-  // loads in flight per thread before their LDS stores
-  constexpr int U = 4;
-  const int tot = K16 * BN;
-  for (int e0 = 0; e0 < tot; e0 += U * 256) {
-    TB x[U], y[U];
+  // stage the panel, columns fastest (coalesced rows of B): each thread
+  // loads runs of VW consecutive columns (16 bytes) of a row and of its
+  // mirror row, U runs in flight before their LDS stores (one vector load
+  // per run where the row stride and the base keep it aligned)
+  constexpr int VW = 16 / sizeof(TB), U = 4;
+  typedef TB TBv __attribute__((ext_vector_type(VW)));
+  const bool vec = (ldb % VW) == 0 && (reinterpret_cast<uintptr_t>(jp->B) & 15) == 0;
+  const int totv = K16 * (BN / VW);
+  for (int e0 = 0; e0 < totv; e0 += U * 256) {
+    TBv x[U], y[U];
     int kk[U], c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = e0 + u * 256 + tid;
+      const int e = (e0 + u * 256 + tid) * VW;
       kk[u] = e / BN;
       c[u] = e - kk[u] * BN;
       const int gc = col0 + c[u];
-      x[u] = y[u] = TB(0);
-      if (e < tot && kk[u] < K && gc < N && !(zm && gc < 2)) {
-        x[u] = B[(size_t)kk[u] * ldb + gc];
+      x[u] = y[u] = TBv{};
+      if (e0 + u * 256 + tid < totv && kk[u] < K && gc < N) {
         const int kr = fold ? KF - 1 - kk[u] : K + kk[u];
-        if (fold ? kr > kk[u] : kr < KF) y[u] = B[(size_t)kr * ldb + gc];
+        const bool hy = fold ? kr > kk[u] : kr < KF;
+        if (vec && gc + VW <= N) {
+          x[u] = *reinterpret_cast<gptr<const TBv>>(B + (size_t)kk[u] * ldb + gc);
+          if (hy) y[u] = *reinterpret_cast<gptr<const TBv>>(B + (size_t)kr * ldb + gc);
+        } else {
+#pragma unroll
+          for (int i = 0; i < VW; ++i)
+            if (gc + i < N) {
+              x[u][i] = B[(size_t)kk[u] * ldb + gc + i];
+              if (hy) y[u][i] = B[(size_t)kr * ldb + gc + i];
+            }
+        }
+        if (zm && gc < 2) {
+#pragma unroll
+          for (int i = 0; i < VW; ++i)
+            if (gc + i < 2) x[u][i] = y[u][i] = TB(0);
+        }
       }
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (e0 + u * 256 + tid >= tot) continue;
+      if (e0 + u * 256 + tid >= totv) continue;
       const int o = kk[u] * PB + c[u];
-      if (fold) {
-        Be[o] = T(x[u] + y[u]);
-        Bo[o] = T(x[u] - y[u]);
-      } else {
-        Be[o] = T(x[u]);
-        Bo[o] = T(y[u]);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        if (fold) {
+          Be[o + i] = T(x[u][i] + y[u][i]);
+          Bo[o + i] = T(x[u][i] - y[u][i]);
+        } else {
+          Be[o + i] = T(x[u][i]);
+          Bo[o + i] = T(y[u][i]);
+        }
       }
     }
   }
