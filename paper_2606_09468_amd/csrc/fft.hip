@@ -105,17 +105,22 @@ __host__ __device__ constexpr size_t lds_padded(size_t n) {
 }
 // dynamic LDS of the transform kernels (indexed through the symbol, so
 // every access stays an LDS instruction)
+// An access at a constant offset that is a multiple of 16 adds a constant
+// to the padded base, so the strided accesses of a pass share one address
+// computation (immediate offsets).
 extern __shared__ double fft_lds[];
 template <typename T, bool PAD = (sizeof(T) == 8)>
 struct LV {
   int off;
   __device__ cx<T>& operator[](int i) const {
     cx<T>* b = reinterpret_cast<cx<T>*>(fft_lds);
-    const int q = off + i;
-    if constexpr (PAD)
+    if constexpr (PAD) {
+      if (__builtin_constant_p(i) && i >= 0 && (i & 15) == 0) return b[off + (off >> 4) + i + (i >> 4)];
+      const int q = off + i;
       return b[q + (q >> 4)];
-    else
-      return b[q];
+    } else {
+      return b[off + i];
+    }
   }
   __device__ LV at(int d) const { return LV{off + d}; }
 };
@@ -737,7 +742,8 @@ __device__ __attribute__((always_inline)) inline void xpencil_body(const XArgs& 
   constexpr int MVW = xmvw<T, LC>();
   const int SW = fft_batch<T, 64, MVW>(L);
   // padded layout in both precisions (with compiled plans the FP32 conflicts
-  // of the strided pass writes cost more than the address arithmetic)
+  // of the strided pass writes cost more than the address arithmetic; the
+  // strides that are multiples of 16 take immediate offsets)
   typedef LV<T, true> XV;
   const XV PV{0};
   // twiddle table in LDS (behind the data), read by every radix pass
