@@ -759,13 +759,13 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
 // s of block b, so a lane's A fragment of a block is one vector load.  Every
 // element of B is read from HBM once per product, where the LDS-tiled kernel
 // reads it once per row tile.
-template <int BN>
+template <typename T, int BN>
 constexpr int bst_pitch() {
-  return BN + 4;
+  return BN + (sizeof(T) == 8 ? 2 : 4);
 }
 template <typename T, typename TB, typename TC, int BN>
 __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __restrict__ jp, int t, double* smem) {
-  constexpr int CB = BN / 16, PB = bst_pitch<BN>();
+  constexpr int CB = BN / 16, PB = bst_pitch<T, BN>();
   typedef typename Vec<T>::v4 V4;
   const int col0 = (t - jp->tile0) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -902,7 +902,7 @@ __device__ inline void two_sum(float& s, float& e, float x) {
 template <typename TB, typename TC, int BN>
 __device__ __attribute__((always_inline)) inline void bst_comp_body(const GemmJob* __restrict__ jp, int t,
                                                                     double* smem) {
-  constexpr int CB = BN / 16, PB = bst_pitch<BN>();
+  constexpr int CB = BN / 16, PB = bst_pitch<float, BN>();
   const int col0 = (t - jp->tile0) * BN;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int l16 = lane & 15, lk = lane >> 4;
@@ -1157,7 +1157,7 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
       case 15:
       case 16: {
         // the whole K range of the folded panel: two halves of K16 rows
-        const size_t pitch = CFG_BN[cfg] + 4;  // bst_pitch
+        const size_t pitch = CFG_BN[cfg] + (es == 8 ? 2 : 4);  // bst_pitch
         x = par ? 2 * (size_t)((jobs[j].k + 15) & ~15) * pitch * es + 16 : ~(size_t)0 >> 1;
         break;
       }
