@@ -758,7 +758,10 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
 // ahead of the multiply.  Lane group g takes k = 16 b + 4 g + s at MFMA step
 // s of block b, so a lane's A fragment of a block is one vector load.  Every
 // element of B is read from HBM once per product, where the LDS-tiled kernel
-// reads it once per row tile.
+// reads it once per row tile.  Row pitch of the staged panel: BN + 4
+// elements in FP32 (the four lane groups' rows of a step fall on disjoint
+// banks), BN + 2 in FP64, where both pitches leave two-way conflicts and the
+// narrower one lets two 32-column panels of 257-point products share a CU.
 template <typename T, int BN>
 constexpr int bst_pitch() {
   return BN + (sizeof(T) == 8 ? 2 : 4);
