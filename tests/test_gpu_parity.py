@@ -145,6 +145,10 @@ CASES = [
     ("3D 32x65x32 Wi50 x8", Grid(3, 32, 65, 32), dict(wi=50.0, dt=5e-4), 8),
     # 32 kx columns of length 144 exceed one register pass: z columns in two batches
     ("3D wide-z 64x17x96 x3", Grid(3, 64, 17, 96), dict(wi=50.0, dt=5e-4), 3),
+    # padded z columns of the compiled lengths 96 and 192 (the band-folded
+    # outer passes) at a small x-y size
+    ("3D z columns of 96 16x17x64 x4", Grid(3, 16, 17, 64), dict(wi=20.0, dt=1e-3), 4),
+    ("3D z columns of 192 8x17x128 x3", Grid(3, 8, 17, 128), dict(wi=20.0, dt=1e-3), 3),
 ]
 
 
@@ -545,6 +549,8 @@ MIXED_CASES = [
     ("3D 32x33x32 x20", Grid(3, 32, 33, 32), dict(wi=50.0, dt=5e-4), 20),
     # FP32 z columns: 32 of length 288 exceed one register pass (two batches)
     ("3D wide-z 64x17x192 x3", Grid(3, 64, 17, 192), dict(wi=50.0, dt=5e-4), 3),
+    # padded z columns of 96 (compiled, band-folded) in FP32
+    ("3D z columns of 96 16x17x64 x4", Grid(3, 16, 17, 64), dict(wi=20.0, dt=1e-3), 4),
 ]
 
 
