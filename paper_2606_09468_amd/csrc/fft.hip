@@ -1376,7 +1376,54 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
     // nzs / 2 + j (the Nyquist slot, j = 0, is zero)
     if (2 * L == 3 * nzs) {
       constexpr int NZH = LC / 3, S = NT * MVC / LC;
-      if (inverse) {
+      // FP32 with an even column count: each thread takes two adjacent kx
+      // columns (contiguous in HBM) with 16-byte loads and stores
+      typedef T T4 __attribute__((ext_vector_type(4)));
+      const bool two = sizeof(T) == 4 && ((ng | nkx | k0) & 1) == 0;
+      const int nh = ng >> 1;
+      const unsigned mnh = fast_div_magic((unsigned)max(nh, 1));
+      if (inverse && two) {
+        constexpr int PB = 4;
+        const int tot = NZH * nh;
+        for (int e0 = 0; e0 < tot; e0 += PB * NT) {
+          T4 xa[PB], xc[PB];
+#pragma unroll
+          for (int u = 0; u < PB; ++u) {
+            const int e = e0 + tid + u * NT;
+            xa[u] = xc[u] = T4{0, 0, 0, 0};
+            if (e < tot) {
+              const int j = fdiv(e, mnh), g = 2 * (e - j * nh);
+              xa[u] = *reinterpret_cast<gptr<const T4>>(ib + ((size_t)j * nkx + k0 + g) * 2);
+              if (j > 0) xc[u] = *reinterpret_cast<gptr<const T4>>(ib + ((size_t)(NZH + j) * nkx + k0 + g) * 2);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < PB; ++u) {
+            const int e = e0 + tid + u * NT;
+            if (e < tot) {
+              const int j = fdiv(e, mnh), g = 2 * (e - j * nh);
+              c2 a0{xa[u][0], xa[u][1]}, c0{xc[u][0], xc[u][1]}, a1{xa[u][2], xa[u][3]}, c1{xc[u][2], xc[u][3]};
+              if (dz) {
+                const T ka = T(kz[j]), kc = T(kz[NZH + j]);
+                a0 = c2{-ka * a0.y, ka * a0.x};
+                c0 = c2{-kc * c0.y, kc * c0.x};
+                a1 = c2{-ka * a1.y, ka * a1.x};
+                c1 = c2{-kc * c1.y, kc * c1.x};
+              }
+              xp_first3<T>(AV.at(g * SL + 3 * j), a0, c0);
+              xp_first3<T>(AV.at((g + 1) * SL + 3 * j), a1, c1);
+            }
+          }
+        }
+        __syncthreads();
+        for (int b0 = 0; b0 < ng; b0 += S)
+          xfft_inv_tail<T, LC, 16, MVC, NT, false>(AV.at(b0 * SL), SL, min(S, ng - b0), twl, tid);
+        for (int e = tid; e < L * nh; e += NT) {
+          const int z = fdiv(e, mnh), g = 2 * (e - z * nh);
+          const c2 v0 = AV[g * SL + z], v1 = AV[(g + 1) * SL + z];
+          *reinterpret_cast<gptr<T4>>(ob + ((size_t)z * nkx + k0 + g) * 2) = T4{v0.x, v0.y, v1.x, v1.y};
+        }
+      } else if (inverse) {
         constexpr int PB = 4;
         const int tot = NZH * ng;
         for (int e0 = 0; e0 < tot; e0 += PB * NT) {
@@ -1413,6 +1460,48 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
           const int z = fdiv(e, mng), g = e - z * ng;
           const c2 v = AV[g * SL + z];
           *reinterpret_cast<gptr<T2>>(ob + ((size_t)z * nkx + k0 + g) * 2) = T2{v.x, v.y};
+        }
+      } else if (two) {
+        constexpr int PER = 8;
+        const int tot = L * nh;
+        for (int e0 = 0; e0 < tot; e0 += PER * NT) {
+          T4 v[PER];
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int e = e0 + tid + u * NT;
+            if (e < tot) {
+              const int z = fdiv(e, mnh), g = 2 * (e - z * nh);
+              v[u] = *reinterpret_cast<gptr<const T4>>(ib + ((size_t)z * nkx + k0 + g) * 2);
+            }
+          }
+#pragma unroll
+          for (int u = 0; u < PER; ++u) {
+            const int e = e0 + tid + u * NT;
+            if (e < tot) {
+              const int z = fdiv(e, mnh), g = 2 * (e - z * nh);
+              AV[g * SL + z] = c2{v[u][0], v[u][1]};
+              AV[(g + 1) * SL + z] = c2{v[u][2], v[u][3]};
+            }
+          }
+        }
+        __syncthreads();
+        for (int b0 = 0; b0 < ng; b0 += S)
+          xfft_fwd_head<T, LC, 16, MVC, NT, false>(AV.at(b0 * SL), SL, min(S, ng - b0), twl, tid);
+        const T inv = T(1.0 / L);
+        for (int e = tid; e < NZH * nh; e += NT) {
+          const int j = fdiv(e, mnh), g = 2 * (e - j * nh);
+          c2 y0, y2, w0, w2;
+          xp_last<T>(AV.at(g * SL), NZH, j, twl, y0, y2);
+          xp_last<T>(AV.at((g + 1) * SL), NZH, j, twl, w0, w2);
+          y0 = scal(inv, y0);
+          w0 = scal(inv, w0);
+          y2 = j ? scal(inv, y2) : c2{0, 0};
+          w2 = j ? scal(inv, w2) : c2{0, 0};
+          *reinterpret_cast<gptr<T4>>(ob + ((size_t)j * nkx + k0 + g) * 2) = T4{y0.x, y0.y, w0.x, w0.y};
+          *reinterpret_cast<gptr<T4>>(ob + ((size_t)(NZH + j) * nkx + k0 + g) * 2) = T4{y2.x, y2.y, w2.x, w2.y};
+          // mixed forward transform: the kx = kz = 0 value completed in FP64
+          if (mcol && j == 0 && k0 + g == 0)
+            mcol[(size_t)f * rows_y + i] = double(y0.x) + mean_product(3, f, mean, rows_y, i, ZA.eps_wi);
         }
       } else {
         constexpr int PER = 8;
