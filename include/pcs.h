@@ -87,7 +87,8 @@ typedef struct {
  *               projections of the explicit terms) takes, at pcs_init, the
  *               fastest of the three variants above (PCS_Y_FP32,
  *               PCS_Y_FP64, PCS_Y_COMP) whose measured error is within the
- *               budget: the error of a variant is the largest difference of
+ *               budget (equal times keep the FP64 operators): the error of
+ *               a variant is the largest difference of
  *               its outputs from those of the FP64-operator variant on the
  *               run's initial state, relative to the largest magnitude of
  *               the same output field (mean mode excluded), over all fields

@@ -1868,7 +1868,8 @@ pcs_status choose_y_variants(Batch* b, const uint64_t* seeds, double amp) {
   for (int v : cand) {
     if ((st = trial(v, Y_FP64, v, 0)) != PCS_OK || (st = trial(Y_FP64, v, 0, v)) != PCS_OK) return st;
   }
-  // the fastest variant within the budget (eager: the first of FP32, FP64)
+  // the fastest variant within the budget, FP64 unless another is strictly
+  // faster (eager: the first of FP32, FP64)
   int pick[2];
   for (int t = 0; t < 2; ++t) {
     pick[t] = Y_FP64;
