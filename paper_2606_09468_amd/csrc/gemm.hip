@@ -752,8 +752,9 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
 // One workgroup per (product, panel of BN output columns).  The folded (or
 // split) B panel of the whole K range is staged into LDS once, converted to
 // the compute precision (K padded with zero rows to a multiple of 16); the
-// four waves then sweep the product's 16-row blocks of E and O (block r by
-// wave r mod 4), each over all BN columns, with the A fragments streamed from
+// NW waves (four; eight for 16-column panels, whose staging is then shared
+// by twice the waves) sweep the product's 16-row blocks of E and O (block r
+// by wave r mod NW), each over all BN columns, with the A fragments streamed from
 // global memory (the operators are small and stay in L2) one 16-wide k block
 // ahead of the multiply.  Lane group g takes k = 16 b + 4 g + s at MFMA step
 // s of block b, so a lane's A fragment of a block is one vector load.  Every
@@ -766,7 +767,7 @@ template <typename T, int BN>
 constexpr int bst_pitch() {
   return BN + (sizeof(T) == 8 ? 2 : 4);
 }
-template <typename T, typename TB, typename TC, int BN>
+template <typename T, typename TB, typename TC, int BN, int NW = 4>
 __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __restrict__ jp, int t, double* smem) {
   constexpr int CB = BN / 16, PB = bst_pitch<T, BN>();
   typedef typename Vec<T>::v4 V4;
@@ -788,17 +789,17 @@ __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __
   typedef TB TBv __attribute__((ext_vector_type(VW)));
   const bool vec = (ldb % VW) == 0 && (reinterpret_cast<uintptr_t>(jp->B) & 15) == 0;
   const int totv = K16 * (BN / VW);
-  for (int e0 = 0; e0 < totv; e0 += U * 256) {
+  for (int e0 = 0; e0 < totv; e0 += U * (64 * NW)) {
     TBv x[U], y[U];
     int kk[U], c[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const int e = (e0 + u * 256 + tid) * VW;
+      const int e = (e0 + u * (64 * NW) + tid) * VW;
       kk[u] = e / BN;
       c[u] = e - kk[u] * BN;
       const int gc = col0 + c[u];
       x[u] = y[u] = TBv{};
-      if (e0 + u * 256 + tid < totv && kk[u] < K && gc < N) {
+      if (e0 + u * (64 * NW) + tid < totv && kk[u] < K && gc < N) {
         const int kr = fold ? KF - 1 - kk[u] : K + kk[u];
         const bool hy = fold ? kr > kk[u] : kr < KF;
         if (vec && gc + VW <= N) {
@@ -821,7 +822,7 @@ __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      if (e0 + u * 256 + tid >= totv) continue;
+      if (e0 + u * (64 * NW) + tid >= totv) continue;
       const int o = kk[u] * PB + c[u];
 #pragma unroll
       for (int i = 0; i < VW; ++i) {
@@ -845,7 +846,7 @@ __device__ __attribute__((always_inline)) inline void bst_body(const GemmJob* __
     const gptr<const T> A = gmem(static_cast<const T*>(q->A));
     const gptr<const T> A2 = gmem(static_cast<const T*>(q->A2));
     const int nrb = (q->m + 15) >> 4, qlda = q->lda;
-    for (int rb = wave; rb < nrb; rb += 4) {
+    for (int rb = wave; rb < nrb; rb += NW) {
       V4 E[1][CB], O[1][CB];
 #pragma unroll
       for (int cb = 0; cb < CB; ++cb) E[0][cb] = O[0][cb] = V4{0, 0, 0, 0};
@@ -1026,16 +1027,17 @@ __global__ __launch_bounds__(256) void gemm_bst_comp_kernel(const GemmJob* __res
 }
 
 template <typename T, typename TB, typename TC, int BN>
-__global__ __launch_bounds__(256) void gemm_bst_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap,
+__global__ __launch_bounds__(BN == 16 ? 512 : 256) void gemm_bst_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap,
                                                        int total) {
   extern __shared__ __attribute__((aligned(16))) double smem[];
   const int t = xcd_tile(blockIdx.x, total);
   const GemmJob* jp = tile_job(jobs, tmap, t);
   if (masked(jp->skip)) return;
+  constexpr int NW = BN == 16 ? 8 : 4;
   if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
-    bst_body<double, double, double, BN>(jp, t, smem);
+    bst_body<double, double, double, BN, NW>(jp, t, smem);
   else
-    bst_body<T, TB, TC, BN>(jp, t, smem);
+    bst_body<T, TB, TC, BN, NW>(jp, t, smem);
 }
 
 // PAR: the table holds parity products only (else plain ones only): one
@@ -1105,7 +1107,7 @@ void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, bo
       break;
     case 16:
       if (parity)
-        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 16>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
+        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 16>), dim3(total), dim3(512), lds, s, dev_jobs, tmap, total);
       break;
     default: break;
   }
