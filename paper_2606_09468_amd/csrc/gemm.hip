@@ -139,8 +139,8 @@ template <>
 struct LCfg<13> {
   static constexpr int BM = 64, BN = 64, KC = 16, NBUF = 1, PKC = 32;
 };
-constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 32, 32, 64, 64, 0, 0, 0};
-constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 32, 32, 64, 64, 32, 64, 16};
+constexpr int CFG_BM[GEMM_NCFG] = {32, 64, 32, 64, 32, 64, 64, 128, 32, 64, 32, 32, 64, 64, 0, 0, 0, 0};
+constexpr int CFG_BN[GEMM_NCFG] = {32, 32, 64, 64, 32, 32, 64, 64, 32, 32, 32, 32, 64, 64, 32, 64, 16, 32};
 // LDS (in elements of the compute precision) of an LDS-tiled configuration:
 // the plain panels, the parity panels (A: BM rows of PKC, B: both halves,
 // rows of BN + 4) and the larger of the two.  The kernel takes its LDS
@@ -752,8 +752,10 @@ __device__ __attribute__((always_inline)) inline void lds_par_body(const GemmJob
 // One workgroup per (product, panel of BN output columns).  The folded (or
 // split) B panel of the whole K range is staged into LDS once, converted to
 // the compute precision (K padded with zero rows to a multiple of 16); the
-// NW waves (four; eight for 16-column panels, whose staging is then shared
-// by twice the waves) sweep the product's 16-row blocks of E and O (block r
+// NW waves (four or eight: configurations 14, 15 and 17 are the 32- and
+// 64-column panels in four waves and the 32-column ones in eight, 16 the
+// 16-column ones in eight; eight waves share one staging among twice the
+// waves) sweep the product's 16-row blocks of E and O (block r
 // by wave r mod NW), each over all BN columns, with the A fragments streamed from
 // global memory (the operators are small and stay in L2) one 16-wide k block
 // ahead of the multiply.  Lane group g takes k = 16 b + 4 g + s at MFMA step
@@ -1026,14 +1028,14 @@ __global__ __launch_bounds__(256) void gemm_bst_comp_kernel(const GemmJob* __res
     bst_comp_body<TB, TC, BN>(jp, t, smem);
 }
 
-template <typename T, typename TB, typename TC, int BN>
-__global__ __launch_bounds__(BN == 16 ? 512 : 256) void gemm_bst_kernel(const GemmJob* __restrict__ jobs, const int* __restrict__ tmap,
-                                                       int total) {
+// NW waves per workgroup (configurations 14, 15: four; 16, 17: eight)
+template <typename T, typename TB, typename TC, int BN, int NW>
+__global__ __launch_bounds__(64 * NW) void gemm_bst_kernel(const GemmJob* __restrict__ jobs,
+                                                           const int* __restrict__ tmap, int total) {
   extern __shared__ __attribute__((aligned(16))) double smem[];
   const int t = xcd_tile(blockIdx.x, total);
   const GemmJob* jp = tile_job(jobs, tmap, t);
   if (masked(jp->skip)) return;
-  constexpr int NW = BN == 16 ? 8 : 4;
   if (dual_type<T, TB, TC>() && jp->type == GEMM_DDD)
     bst_body<double, double, double, BN, NW>(jp, t, smem);
   else
@@ -1099,15 +1101,19 @@ void launch_cfg(const GemmJob* dev_jobs, const int* tmap, int total, int cfg, bo
     PCS_GEMM_LDS(13)
     case 14:
       if (parity)
-        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 32>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
+        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 32, 4>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
       break;
     case 15:
       if (parity)
-        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 64>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
+        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 64, 4>), dim3(total), dim3(256), lds, s, dev_jobs, tmap, total);
       break;
     case 16:
       if (parity)
-        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 16>), dim3(total), dim3(512), lds, s, dev_jobs, tmap, total);
+        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 16, 8>), dim3(total), dim3(512), lds, s, dev_jobs, tmap, total);
+      break;
+    case 17:
+      if (parity)
+        hipLaunchKernelGGL((gemm_bst_kernel<T, TB, TC, 32, 8>), dim3(total), dim3(512), lds, s, dev_jobs, tmap, total);
       break;
     default: break;
   }
@@ -1136,8 +1142,9 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
   size_t b = 0;
   for (int j = 0; j < njobs; ++j) {
     if (gemm_type_comp(t) && jobs[j].type != GEMM_DDD) {
-      // head and tail panels of both halves, B-stationary only
-      if (!gemm_cfg_bst(cfg) || jobs[j].kind == PAR_NONE) return ~(size_t)0 >> 1;
+      // head and tail panels of both halves, B-stationary only; the compensated kernel has one wave count per
+      // panel width, so configuration 17 would repeat 14
+      if (!gemm_cfg_bst(cfg) || cfg == 17 || jobs[j].kind == PAR_NONE) return ~(size_t)0 >> 1;
       const size_t pitch = CFG_BN[cfg] + 4;  // bst_pitch
       const size_t x = 4 * (size_t)((jobs[j].k + 15) & ~15) * pitch * 4 + 16;
       b = x > b ? x : b;
@@ -1160,7 +1167,8 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
       case 13: x = lds_form<13>(par, es, half); break;
       case 14:
       case 15:
-      case 16: {
+      case 16:
+      case 17: {
         // the whole K range of the folded panel: two halves of K16 rows
         const size_t pitch = CFG_BN[cfg] + (es == 8 ? 2 : 4);  // bst_pitch
         x = par ? 2 * (size_t)((jobs[j].k + 15) & ~15) * pitch * es + 16 : ~(size_t)0 >> 1;
@@ -1176,17 +1184,20 @@ size_t gemm_lds_bytes(GemmType t, const GemmJob* jobs, int njobs, int cfg) {
 hipError_t gemm_set_attributes() {
   // the B-stationary kernels stage a whole K range: up to the CU's 160 KB
   const void* k[] = {
-      (const void*)gemm_bst_kernel<double, double, double, 32>, (const void*)gemm_bst_kernel<double, double, double, 64>,
-      (const void*)gemm_bst_kernel<float, double, float, 32>,   (const void*)gemm_bst_kernel<float, double, float, 64>,
-      (const void*)gemm_bst_kernel<float, float, double, 32>,   (const void*)gemm_bst_kernel<float, float, double, 64>,
-      (const void*)gemm_bst_kernel<double, double, float, 32>,  (const void*)gemm_bst_kernel<double, double, float, 64>,
-      (const void*)gemm_bst_kernel<double, float, double, 32>,  (const void*)gemm_bst_kernel<double, float, double, 64>,
+      (const void*)gemm_bst_kernel<double, double, double, 32, 4>, (const void*)gemm_bst_kernel<double, double, double, 64, 4>,
+      (const void*)gemm_bst_kernel<float, double, float, 32, 4>,   (const void*)gemm_bst_kernel<float, double, float, 64, 4>,
+      (const void*)gemm_bst_kernel<float, float, double, 32, 4>,   (const void*)gemm_bst_kernel<float, float, double, 64, 4>,
+      (const void*)gemm_bst_kernel<double, double, float, 32, 4>,  (const void*)gemm_bst_kernel<double, double, float, 64, 4>,
+      (const void*)gemm_bst_kernel<double, float, double, 32, 4>,  (const void*)gemm_bst_kernel<double, float, double, 64, 4>,
       (const void*)gemm_bst_comp_kernel<double, float, 32>,     (const void*)gemm_bst_comp_kernel<double, float, 64>,
       (const void*)gemm_bst_comp_kernel<float, double, 32>,     (const void*)gemm_bst_comp_kernel<float, double, 64>,
-      (const void*)gemm_bst_kernel<double, double, double, 16>, (const void*)gemm_bst_kernel<float, double, float, 16>,
-      (const void*)gemm_bst_kernel<float, float, double, 16>,   (const void*)gemm_bst_kernel<double, double, float, 16>,
-      (const void*)gemm_bst_kernel<double, float, double, 16>,  (const void*)gemm_bst_comp_kernel<double, float, 16>,
-      (const void*)gemm_bst_comp_kernel<float, double, 16>};
+      (const void*)gemm_bst_kernel<double, double, double, 16, 8>, (const void*)gemm_bst_kernel<float, double, float, 16, 8>,
+      (const void*)gemm_bst_kernel<float, float, double, 16, 8>,   (const void*)gemm_bst_kernel<double, double, float, 16, 8>,
+      (const void*)gemm_bst_kernel<double, float, double, 16, 8>,  (const void*)gemm_bst_comp_kernel<double, float, 16>,
+      (const void*)gemm_bst_comp_kernel<float, double, 16>,
+      (const void*)gemm_bst_kernel<double, double, double, 32, 8>, (const void*)gemm_bst_kernel<float, double, float, 32, 8>,
+      (const void*)gemm_bst_kernel<float, float, double, 32, 8>,   (const void*)gemm_bst_kernel<double, double, float, 32, 8>,
+      (const void*)gemm_bst_kernel<double, float, double, 32, 8>};
   for (const void* f : k) {
     const hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, GEMM_LDS_MAX);
     if (e != hipSuccess) return e;

@@ -104,9 +104,9 @@ constexpr int MAX_JOBS = 64;
 // 8: 32 x 32, 9: 64 x 32 (one buffer, chunks of 64 k), and for small tables
 // deeper parity chunks: 10, 11: 32 x 32, 12, 13: 64 x 64.  B-stationary
 // kernel (parity products only; a workgroup stages the whole K range of a
-// panel of B once and computes every output row of it): 14: 32, 15: 64 and
-// 16: 16 columns per panel.
-constexpr int GEMM_NCFG = 17;
+// panel of B once and computes every output row of it): 14: 32, 15: 64
+// columns per panel in four waves, 16: 16 and 17: 32 columns in eight.
+constexpr int GEMM_NCFG = 18;
 constexpr size_t GEMM_LDS_MAX = 160 * 1024;  // LDS a workgroup may take
 inline int gemm_lda(int k) { return (k + 15) & ~15; }
 inline int gemm_rows(int m) { return (m + 127) & ~127; }
