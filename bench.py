@@ -171,7 +171,7 @@ def traffic_for(kernel, workload, precision):
 
 
 # timed oracle steps after the warm-up step, per workload (one C5 oracle step
-# is about 80 s on one host thread)
+# is about 30 s on one host thread)
 CPU_STEPS = {"c1": 60, "c2": 60, "c3": 4, "c5": 1}
 
 

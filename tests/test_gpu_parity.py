@@ -181,7 +181,7 @@ def _oracle_run(name, g, prm, n):
 
 
 # tile configurations of the product kernels: 0-3 register-direct (plain
-# form only), 4-13 LDS-tiled (plain and parity forms), 14-16 B-stationary
+# form only), 4-13 LDS-tiled (plain and parity forms), 14-17 B-stationary
 # (parity form only)
 GEMM_CFGS = list(range(18))
 
