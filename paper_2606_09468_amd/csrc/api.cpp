@@ -32,6 +32,7 @@ namespace {
 
 constexpr int RING = 4096;
 constexpr size_t ALIGN = 256;
+constexpr int ZPAIRS = 9;  // d/dz fields of the 3D inverse z-transform table (u, v, w, c)
 constexpr int Y_FP32 = PCS_Y_FP32, Y_FP64 = PCS_Y_FP64, Y_COMP = PCS_Y_COMP;
 
 struct Carve {
@@ -1016,12 +1017,13 @@ pcs_status upload_member(Member* m, uint64_t seed, double amp, hipStream_t s) {
     HIPCHK(up(m->twz, twiddles(d.pz, -1), s));
     HIPCHK(up(m->twbz, twiddles(d.nz, -1), s));
     // z-transform input table: the 17 y-transformed fields, then d/dz of u v w c6
+    // (fields 17 + k = d/dz of field k < ZPAIRS, the pairing the kernel's block order takes)
     std::vector<int> src(26), der(26);
     for (int f = 0; f < 17; ++f) {
       src[f] = f;
       der[f] = 0;
     }
-    for (int f = 0; f < 9; ++f) {
+    for (int f = 0; f < ZPAIRS; ++f) {
       src[17 + f] = f;
       der[17 + f] = 1;
     }
@@ -1173,6 +1175,7 @@ void build_batch(Batch* b) {
       zi.pl = m->plz;
       zi.src_field = m->zsrc;
       zi.deriv = m->zder;
+      zi.npair = ZPAIRS;
       zi.kz = m->kz;
       zi.tw = twz;
       zi.skip = skip;
@@ -1187,6 +1190,7 @@ void build_batch(Batch* b) {
       zf.inverse = 0;
       zf.src_field = nullptr;
       zf.deriv = nullptr;
+      zf.npair = 0;
       zf.mean = m->Ybar;
       zf.mcol = m->mcol;
       zf.eps_wi = m->p.eps / m->p.wi;

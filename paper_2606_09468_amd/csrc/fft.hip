@@ -1353,9 +1353,27 @@ __device__ __attribute__((always_inline)) inline void zfft_body(const ZArgs& ZA)
       twl[e] = c2{t[0], t[1]};
     }
   }
-  // local workgroup -> (kx group, row, field)
+  // local workgroup -> (kx group, row, field).  Pairs (field k, its d/dz)
+  // first, in groups of 16 blocks: 8 units of a source field, then the same
+  // 8 units of its derivative (a last group of rem < 8 units likewise with
+  // rem), then the unpaired fields one after the other
   const int lb = blockIdx.x - ZA.blk0;
-  const int gx = lb % ZA.ngx, i = (lb / ZA.ngx) % rows_y, f = lb / (ZA.ngx * rows_y);
+  const int U = ZA.ngx * rows_y, np = ZA.npair;
+  int f, w;
+  if (np > 0 && lb < 2 * np * U) {
+    const int q = lb >> 4, r = lb & 15, rem = min(8, np * U - 8 * q);
+    const bool second = r >= rem;
+    const int unit = 8 * q + (second ? r - rem : r);
+    const int k = unit / U;
+    w = unit - k * U;
+    f = second ? ZA.nfields - np + k : k;
+  } else {
+    const int lr = lb - 2 * np * U;
+    const int k = lr / U;
+    w = lr - k * U;
+    f = np + k;
+  }
+  const int gx = w % ZA.ngx, i = w / ZA.ngx;
   const int k0 = gx * ZG;
   const int ng = min(ZG, nkx - k0);
   const unsigned mng = fast_div_magic((unsigned)ng);

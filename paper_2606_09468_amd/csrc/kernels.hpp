@@ -239,6 +239,11 @@ struct ZArgs {
   FftPlan pl;
   const int* src_field;
   const int* deriv;
+  // npair > 0: output fields nfields - npair + k are d/dz of fields k < npair;
+  // the two workgroups of a (field, row, kx group) of such a pair are block
+  // indices 8 apart (one XCD, dispatched together), so the second reads the
+  // shared input from that XCD's L2
+  int npair;
   const double* kz;
   const void* tw;
   const double* mean;
