@@ -33,6 +33,7 @@ namespace {
 constexpr int RING = 4096;
 constexpr size_t ALIGN = 256;
 constexpr int ZPAIRS = 9;  // d/dz fields of the 3D inverse z-transform table (u, v, w, c)
+constexpr size_t RHS_SPLIT_ELEMS = 256 * 1024;  // (row, mode) elements of a launch for separate wall rows
 constexpr int Y_FP32 = PCS_Y_FP32, Y_FP64 = PCS_Y_FP64, Y_COMP = PCS_Y_COMP;
 
 struct Carve {
@@ -338,15 +339,15 @@ struct Batch {
   std::vector<ZArgs> hzi, hzf, hzd;
   std::vector<DRowArgs> hdr;
   std::vector<DFinArgs> hdf;
-  std::vector<RhsArgs> hrhs;
+  std::vector<RhsArgs> hrhs, hrhsw;  // interior rows; wall rows (launched first)
   std::vector<FinArgs> hfin;
   XArgs* dx = nullptr;
   ZArgs *dzi = nullptr, *dzf = nullptr, *dzd = nullptr;
   DRowArgs* ddr = nullptr;
   DFinArgs* ddf = nullptr;
-  RhsArgs* drhs = nullptr;
+  RhsArgs *drhs = nullptr, *drhsw = nullptr;
   FinArgs* dfin = nullptr;
-  int bx = 0, bzi = 0, bzf = 0, bzd = 0, bdr = 0, brhs = 0, bfin = 0;
+  int bx = 0, bzi = 0, bzf = 0, bzd = 0, bdr = 0, brhs = 0, brhsw = 0, bfin = 0;
   size_t lx = 0, lzi = 0, lzf = 0, lzd = 0, ldr = 0;
   int xnt = 0;          // threads per x-pencil workgroup
   int zgi = 32, zgd = 32;  // kx columns per workgroup of the state's and the diagnostics' z transforms
@@ -1117,8 +1118,9 @@ void build_batch(Batch* b) {
   b->hdr.clear();
   b->hdf.clear();
   b->hrhs.clear();
+  b->hrhsw.clear();
   b->hfin.clear();
-  b->bx = b->bzi = b->bzf = b->bzd = b->bdr = b->brhs = b->bfin = 0;
+  b->bx = b->bzi = b->bzf = b->bzd = b->bdr = b->brhs = b->brhsw = b->bfin = 0;
   b->lx = b->lzi = b->lzf = b->lzd = b->ldr = 0;
   // one column group per z-transform launch: the smallest any member's length asks for
   b->zgi = b->zgd = 32;
@@ -1130,6 +1132,14 @@ void build_batch(Batch* b) {
   b->xchunk = mem[0]->d.px;
   for (Member* m : mem)
     if (!xpencil_chunked(m->d.dim, m->d.px, m->prec) || m->d.px != mem[0]->d.px) b->xchunk = 0;
+  // right-hand sides: wall rows first, then the interior rows reading their
+  // new wall values, where the launch is large enough for the re-read wall rows
+  // to cost more than the second launch's latency (measured: 3D 256 x 257 x 128
+  // 0.79 -> 0.72 ms, 128 x 129 x 64 0.117 -> 0.106 ms; 2D 256 x 257, 33K
+  // elements, 13 -> 17 us); else one launch whose threads recompute them
+  size_t rhs_elems = 0;
+  for (Member* m : mem) rhs_elems += (size_t)(m->d.N + 1) * m->d.nm;
+  const bool rhs_split = rhs_elems >= RHS_SPLIT_ELEMS;
   for (Member* m : mem) {
     const Dims& d = m->d;
     const bool mixed = m->prec != 0;
@@ -1290,8 +1300,17 @@ void build_batch(Batch* b) {
     h.qring = m->qring;
     h.hring = m->hring;
     h.sc = m->sc;
+    if (rhs_split) {
+      h.rows = RHS_WALLS;
+      h.blk0 = b->brhsw;
+      b->brhsw += (2 * d.nm + ELEM_THREADS - 1) / ELEM_THREADS;
+      b->hrhsw.push_back(h);
+      h.rows = RHS_INTERIOR;
+    } else {
+      h.rows = RHS_ALL;
+    }
     h.blk0 = b->brhs;
-    b->brhs += eblocks;
+    b->brhs += ((rhs_split ? n1 - 2 : n1) * d.nm + ELEM_THREADS - 1) / ELEM_THREADS;
     b->hrhs.push_back(h);
     FinArgs q{};
     q.d = d;
@@ -1345,6 +1364,7 @@ size_t layout(Batch* b, char* base) {
   b->ddr = c.take<DRowArgs>(n);
   b->ddf = c.take<DFinArgs>(n);
   b->drhs = c.take<RhsArgs>(n);
+  b->drhsw = c.take<RhsArgs>(n);
   b->dfin = c.take<FinArgs>(n);
   return c.off;
 }
@@ -1383,7 +1403,7 @@ void explicit_stage(Batch* b, const Mark& mark) {
   for (int r = mark(ST_ZFFT_FWD); r > 0; --r)
     if (b->dim == 3) launch_zfft(b->prec, b->zgi, b->dzf, nm, b->bzf, b->lzf, s);
   for (int r = mark(ST_GEMM_PROJ); r > 0; --r) b->GP.run(s);
-  for (int r = mark(ST_RHS); r > 0; --r) launch_rhs(b->drhs, nm, b->brhs, s);
+  for (int r = mark(ST_RHS); r > 0; --r) launch_rhs(b->drhsw, b->brhsw, b->drhs, b->brhs, nm, s);
 }
 
 template <typename Mark>
@@ -1449,7 +1469,7 @@ void enqueue_step_branched(Batch* b, bool diag_prev, hipEvent_t* ev) {
   b->GP.run(s);
   if (prod) (void)hipStreamWaitEvent(s, ev[2], 0);
   if (diag_prev && ring) (void)hipStreamWaitEvent(s, ev[3], 0);
-  launch_rhs(b->drhs, nm, b->brhs, s);
+  launch_rhs(b->drhsw, b->brhsw, b->drhs, b->brhs, nm, s);
   b->G4.run(s);
   if (diag_prev && !ring) (void)hipStreamWaitEvent(s, ev[3], 0);
   b->G5.run(s);
@@ -1627,6 +1647,7 @@ pcs_status upload_tables(Batch* b) {
   HIPCHK(up(b->ddr, b->hdr, s));
   HIPCHK(up(b->ddf, b->hdf, s));
   HIPCHK(up(b->drhs, b->hrhs, s));
+  HIPCHK(up(b->drhsw, b->hrhsw, s));
   HIPCHK(up(b->dfin, b->hfin, s));
   return PCS_OK;
 }

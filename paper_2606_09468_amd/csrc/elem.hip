@@ -99,8 +99,10 @@ struct Layout {
 //        + delta/Wi (mean slot) + kappa/2 (D2_i0 c_0^new + D2_iN c_N^new)
 // and the new wall rows of c (kappa = 0 there):
 //   c_B^new = ((1/dt - 1/(2Wi)) c_B + 3/2 F_B - 1/2 F_B^old + delta/Wi) / (1/dt + 1/(2Wi)).
-// Each thread recomputes the two wall values of its mode, so no thread
-// writes anything another thread reads.
+// A.rows: RHS_ALL, one launch in which each thread computes the two wall
+// values of its mode; or RHS_WALLS (rows 0 and N, storing c_B^new into CB)
+// and then RHS_INTERIOR (rows 1..N-1, reading them from CB).  Within a
+// launch no thread reads what another writes.
 // SBDF4 (p.scheme == 1) replaces the CNAB2 combinations by
 //   sum_k alpha_k q^{n-k} / dt + sum_k beta_k X^{n-k},
 //   alpha = (4, -3, 4/3, -1/4), beta = (4, -6, 4, -1),
@@ -136,9 +138,12 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
   const auto CB = gmem(A.CB);
   const int n1 = d.N + 1, N = d.N, ni = d.N - 1;
   const int e = (blockIdx.x - A.blk0) * blockDim.x + threadIdx.x;
-  if (e >= n1 * d.nm) return;
+  const int rows = A.rows;
+  if (e >= (rows == RHS_WALLS ? 2 : rows == RHS_INTERIOR ? ni : n1) * d.nm) return;
   const Layout L(d.dim, d.nc);
-  Mode m = decode(d, e, kx, kz);
+  // element (row, mode) of this thread among the launch's rows
+  const int el = rows == RHS_WALLS ? (e < d.nm ? e : e + (N - 1) * d.nm) : rows == RHS_INTERIOR ? e + d.nm : e;
+  Mode m = decode(d, el, kx, kz);
   const int j = m.j;
   const bool inter = (j > 0 && j < N);
   const size_t fs = (size_t)n1 * d.cw, fsi = (size_t)ni * d.cw;
@@ -220,14 +225,18 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
       const bool diag = (d.dim == 2) ? (a == 0 || a == 2) : (a == 0 || a == 3 || a == 5);
       const cd src = cd{(m.mean && diag) ? 1.0 / p.wi : 0.0, 0};
       const int o = L.S_F + a, fc = L.F_C + a, fh = L.H_F + a;
-      const cd cb0 = (1.0 / a_new) * (past(fc, off0) + ext(Sx(o, 0), fh, off0) + src);
-      const cd cbN = (1.0 / a_new) * (past(fc, offN) + ext(Sx(o, N), fh, offN) + src);
+      // new value of component a at wall w (0: row 0, 1: row N)
+      auto wall = [&](int w) -> cd {
+        if (rows == RHS_INTERIOR) return ld2(CB, (size_t)(2 * a + w) * d.cw + 2 * m.mode);
+        const size_t ow = w ? offN : off0;
+        return (1.0 / a_new) * (past(fc, ow) + ext(Sx(o, w ? N : 0), fh, ow) + src);
+      };
       if (inter) {
         cd r = past(fc, off) + ext(Sx(o, j), fh, off) + src;
-        if (p.kappa > 0) r = r + (p.th * p.kappa) * (d2i0[j - 1] * cb0 + d2in[j - 1] * cbN);
+        if (p.kappa > 0) r = r + (p.th * p.kappa) * (d2i0[j - 1] * wall(0) + d2in[j - 1] * wall(1));
         st2(R, (size_t)(L.nsv + a) * fsi + offi, r);
       } else {
-        st2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode, j == 0 ? cb0 : cbN);
+        st2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode, wall(j == 0 ? 0 : 1));
       }
     }
     const auto qn = qr + (size_t)(n & 3) * qs;
@@ -268,21 +277,26 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
     const bool diag = (d.dim == 2) ? (a == 0 || a == 2) : (a == 0 || a == 3 || a == 5);
     const cd src = cd{(m.mean && diag) ? 1.0 / p.wi : 0.0, 0};
     const int o = L.S_F + a;
-    const cd cb0 = (1.0 / a_new) * (a_int * ld2(cf, off0) + 1.5 * Sx(o, 0) - 0.5 * ld2(Fo, off0) + src);
-    const cd cbN = (1.0 / a_new) * (a_int * ld2(cf, offN) + 1.5 * Sx(o, N) - 0.5 * ld2(Fo, offN) + src);
+    // new value of component a at wall w (0: row 0, 1: row N)
+    auto wall = [&](int w) -> cd {
+      if (rows == RHS_INTERIOR) return ld2(CB, (size_t)(2 * a + w) * d.cw + 2 * m.mode);
+      const size_t ow = w ? offN : off0;
+      return (1.0 / a_new) * (a_int * ld2(cf, ow) + 1.5 * Sx(o, w ? N : 0) - 0.5 * ld2(Fo, ow) + src);
+    };
     if (inter) {
       cd r = (a_int - 0.5 * p.kappa * m.k2) * ld2(cf, off) + (0.5 * p.kappa) * ld2(D2buf, (L.nsv + a) * fs + off) +
              1.5 * Sx(o, j) - 0.5 * ld2(Fo, off) + src;
-      if (p.kappa > 0) r = r + (0.5 * p.kappa) * (d2i0[j - 1] * cb0 + d2in[j - 1] * cbN);
+      if (p.kappa > 0) r = r + (0.5 * p.kappa) * (d2i0[j - 1] * wall(0) + d2in[j - 1] * wall(1));
       st2(R, (size_t)(L.nsv + a) * fsi + offi, r);
     } else {
-      st2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode, j == 0 ? cb0 : cbN);
+      st2(CB, (size_t)(2 * a + (j == 0 ? 0 : 1)) * d.cw + 2 * m.mode, wall(j == 0 ? 0 : 1));
     }
   }
 }
 
-void launch_rhs(const RhsArgs* args, int nmem, int blocks, hipStream_t s) {
-  hipLaunchKernelGGL(rhs_kernel, dim3(blocks), dim3(ELEM_THREADS), 0, s, args, nmem);
+void launch_rhs(const RhsArgs* walls, int wblocks, const RhsArgs* inner, int iblocks, int nmem, hipStream_t s) {
+  if (wblocks > 0) hipLaunchKernelGGL(rhs_kernel, dim3(wblocks), dim3(ELEM_THREADS), 0, s, walls, nmem);
+  if (iblocks > 0) hipLaunchKernelGGL(rhs_kernel, dim3(iblocks), dim3(ELEM_THREADS), 0, s, inner, nmem);
 }
 
 // ---------------------------------------------------------------- finalize
