@@ -1301,13 +1301,9 @@ void build_batch(Batch* b) {
     h.hring = m->hring;
     h.sc = m->sc;
     if (rhs_split) {
-      h.rows = RHS_WALLS;
       h.blk0 = b->brhsw;
       b->brhsw += (2 * d.nm + ELEM_THREADS - 1) / ELEM_THREADS;
       b->hrhsw.push_back(h);
-      h.rows = RHS_INTERIOR;
-    } else {
-      h.rows = RHS_ALL;
     }
     h.blk0 = b->brhs;
     b->brhs += ((rhs_split ? n1 - 2 : n1) * d.nm + ELEM_THREADS - 1) / ELEM_THREADS;

@@ -99,7 +99,7 @@ struct Layout {
 //        + delta/Wi (mean slot) + kappa/2 (D2_i0 c_0^new + D2_iN c_N^new)
 // and the new wall rows of c (kappa = 0 there):
 //   c_B^new = ((1/dt - 1/(2Wi)) c_B + 3/2 F_B - 1/2 F_B^old + delta/Wi) / (1/dt + 1/(2Wi)).
-// A.rows: RHS_ALL, one launch in which each thread computes the two wall
+// ROWS: RHS_ALL, one launch in which each thread computes the two wall
 // values of its mode; or RHS_WALLS (rows 0 and N, storing c_B^new into CB)
 // and then RHS_INTERIOR (rows 1..N-1, reading them from CB).  Within a
 // launch no thread reads what another writes.
@@ -117,6 +117,7 @@ struct Layout {
 // then D2U (N+1) and D2W (N+1); Dc = [D c...].  smean (mixed precision
 // only) replaces S in the mean column.  Outputs: R [nsolve][N-1 rows], hvn,
 // hgn (3D), CB [nc][2 walls][cw].
+template <int ROWS>
 __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __restrict__ args, int nmem) {
   const RhsArgs& A = args[member_of(args, nmem)];
   if (masked(&A.sc->blowup)) return;
@@ -138,7 +139,7 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
   const auto CB = gmem(A.CB);
   const int n1 = d.N + 1, N = d.N, ni = d.N - 1;
   const int e = (blockIdx.x - A.blk0) * blockDim.x + threadIdx.x;
-  const int rows = A.rows;
+  constexpr int rows = ROWS;
   if (e >= (rows == RHS_WALLS ? 2 : rows == RHS_INTERIOR ? ni : n1) * d.nm) return;
   const Layout L(d.dim, d.nc);
   // element (row, mode) of this thread among the launch's rows
@@ -295,8 +296,13 @@ __global__ __launch_bounds__(ELEM_THREADS) void rhs_kernel(const RhsArgs* __rest
 }
 
 void launch_rhs(const RhsArgs* walls, int wblocks, const RhsArgs* inner, int iblocks, int nmem, hipStream_t s) {
-  if (wblocks > 0) hipLaunchKernelGGL(rhs_kernel, dim3(wblocks), dim3(ELEM_THREADS), 0, s, walls, nmem);
-  if (iblocks > 0) hipLaunchKernelGGL(rhs_kernel, dim3(iblocks), dim3(ELEM_THREADS), 0, s, inner, nmem);
+  if (wblocks > 0) {
+    hipLaunchKernelGGL(rhs_kernel<RHS_WALLS>, dim3(wblocks), dim3(ELEM_THREADS), 0, s, walls, nmem);
+    if (iblocks > 0)
+      hipLaunchKernelGGL(rhs_kernel<RHS_INTERIOR>, dim3(iblocks), dim3(ELEM_THREADS), 0, s, inner, nmem);
+  } else if (iblocks > 0) {
+    hipLaunchKernelGGL(rhs_kernel<RHS_ALL>, dim3(iblocks), dim3(ELEM_THREADS), 0, s, inner, nmem);
+  }
 }
 
 // ---------------------------------------------------------------- finalize

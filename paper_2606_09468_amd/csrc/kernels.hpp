@@ -307,12 +307,12 @@ struct RhsArgs {
   double* qring;         // SBDF4: four slots of the state fields, q^k in slot k mod 4
   double* hring;         // SBDF4: four slots of the explicit terms, X^k in slot k mod 4
   const DevScalars* sc;  // step index n of the current state
-  int rows;              // RHS_ALL, RHS_WALLS or RHS_INTERIOR: the rows the launch covers
   int blk0;
 };
-// rows of a right-hand-side launch: all (each thread computes the new wall
-// values of c its row needs), the two wall rows (stored into CB), or the
-// interior rows (reading them from CB after the wall launch)
+// rows of a right-hand-side launch (rhs_kernel's template argument): all
+// (each thread computes the new wall values of c its row needs), the two
+// wall rows (stored into CB), or the interior rows (reading them from CB
+// after the wall launch)
 enum { RHS_ALL = 0, RHS_WALLS = 1, RHS_INTERIOR = 2 };
 // influence correction, flux, velocities, wall rows, history, diagnostics
 // inputs (elem.hip)
@@ -361,8 +361,8 @@ void launch_xpencil(int dim, int precision, int threads, int chunk_len, const XA
 void launch_zfft(int precision, int group, const ZArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
 void launch_diag_rows(const DRowArgs* args, int nmem, int blocks, size_t lds, hipStream_t s);
 void launch_diag_final(const DFinArgs* args, int nmem, hipStream_t s);
-// the wall rows of every member (walls, wblocks; none when the launch covers
-// all rows), then the other rows (inner, iblocks)
+// the wall rows of every member (walls, wblocks), then the interior rows
+// (inner, iblocks); with wblocks == 0, inner covers all rows in one launch
 void launch_rhs(const RhsArgs* walls, int wblocks, const RhsArgs* inner, int iblocks, int nmem, hipStream_t s);
 void launch_finalize(const FinArgs* args, int nmem, int blocks, hipStream_t s);
 // workgroups and dynamic LDS of one member's launch
