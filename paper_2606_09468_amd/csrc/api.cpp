@@ -1139,7 +1139,12 @@ void build_batch(Batch* b) {
   // elements, 13 -> 17 us); else one launch whose threads recompute them
   size_t rhs_elems = 0;
   for (Member* m : mem) rhs_elems += (size_t)(m->d.N + 1) * m->d.nm;
-  const bool rhs_split = rhs_elems >= RHS_SPLIT_ELEMS;
+  bool rhs_split = rhs_elems >= RHS_SPLIT_ELEMS;
+  // PCS_RHS_FORM=split or =fused forces a form (both give the same arithmetic)
+  if (const char* e = std::getenv("PCS_RHS_FORM")) {
+    if (!std::strcmp(e, "split")) rhs_split = true;
+    if (!std::strcmp(e, "fused")) rhs_split = false;
+  }
   for (Member* m : mem) {
     const Dims& d = m->d;
     const bool mixed = m->prec != 0;
